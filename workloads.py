@@ -1,0 +1,170 @@
+"""Seeded synthetic inputs shaped like the paper's TSV-array workloads.
+
+This module holds input generation only: cell geometry and materials, the
+cell-type map of an array, thermal load, boundary-condition choice, a smooth
+background displacement field (a stand-in for the coarse chiplet solution the
+paper uses for sub-modelling, Sec. 4.4 and 5.2, which is not available), and
+a Poisson request stream.  It holds none of the method's arithmetic and is
+the only module imported by both the oracle-side and the GPU-side code of
+the tests and of the benchmark.
+
+Units: micrometres, MPa, 1/K, K.  Material triples are (E, nu, alpha).
+"""
+from dataclasses import dataclass, field, replace
+from typing import Optional
+
+import numpy as np
+
+SI = (130.0e3, 0.28, 2.6e-6)      # silicon matrix
+CU = (110.0e3, 0.35, 17.0e-6)     # copper via
+SIO2 = (71.0e3, 0.16, 0.5e-6)     # dielectric liner
+
+
+@dataclass(frozen=True)
+class CellSpec:
+    pitch_x: float = 15.0
+    pitch_y: float = 15.0
+    height: float = 50.0
+    mesh: tuple = (16, 16, 32)            # hexes along x, y, z
+    tsv_diameter: float = 5.0             # 0 => dummy (pure matrix) block
+    liner_thickness: float = 0.0
+    matrix: tuple = SI
+    via: tuple = CU
+    liner: tuple = SIO2
+    interp: tuple = (4, 4, 4)             # Lagrange nodes per axis
+
+    def dummy(self):
+        return replace(self, tsv_diameter=0.0, liner_thickness=0.0)
+
+
+@dataclass
+class FourierField:
+    """u(r) = sum_m w_m e_m cos(2 pi (a_m x/Lx + b_m y/Ly + c_m z/Lz) + phi_m).
+
+    The weights sum to ``amplitude`` so |u| <= amplitude everywhere."""
+    L: tuple
+    k: np.ndarray          # (M, 3) integer wave numbers
+    e: np.ndarray          # (M, 3) unit directions
+    w: np.ndarray          # (M,) weights
+    phi: np.ndarray        # (M,) phases
+
+    def __call__(self, xyz):
+        xyz = np.asarray(xyz, dtype=float)
+        arg = 2.0 * np.pi * (xyz / np.asarray(self.L)[None, :]) @ self.k.T.astype(float)
+        arg = arg + self.phi[None, :]
+        return (np.cos(arg) * self.w[None, :]) @ self.e
+
+
+def fourier_field(rng, L, modes=8, amplitude=0.1):
+    ks = [(a, b, c) for a in range(3) for b in range(3) for c in range(3) if (a, b, c) != (0, 0, 0)]
+    idx = rng.choice(len(ks), size=modes, replace=True)
+    k = np.array([ks[i] for i in idx], dtype=np.int64)
+    e = rng.normal(size=(modes, 3))
+    e /= np.linalg.norm(e, axis=1, keepdims=True)
+    w = rng.uniform(0.5, 1.0, size=modes)
+    w *= amplitude / w.sum()
+    phi = rng.uniform(0.0, 2.0 * np.pi, size=modes)
+    return FourierField(tuple(float(v) for v in L), k, e, w, phi)
+
+
+@dataclass
+class ArrayCase:
+    """One global-stage problem: an N_x x N_y array of blocks of the given
+    types (cell_type[cy * N_x + cx] indexes ``specs``)."""
+    name: str
+    specs: list
+    nx_cells: int
+    ny_cells: int
+    cell_type: np.ndarray
+    delta_T: float = -250.0
+    clamp_bottom: bool = True
+    clamp_top: bool = False
+    field: Optional[FourierField] = None
+    mixed: bool = False
+
+    @property
+    def n_cells(self):
+        return self.nx_cells * self.ny_cells
+
+
+def dummy_map(rng, n_cells, fraction):
+    t = np.zeros(n_cells, dtype=np.uint8)
+    k = int(round(fraction * n_cells))
+    if k:
+        t[rng.choice(n_cells, size=k, replace=False)] = 1
+    return t
+
+
+def case_c1():
+    """2x2 array, 10x10x20 hexes, quadratic faces, bottom clamped."""
+    spec = CellSpec(mesh=(10, 10, 20), interp=(3, 3, 3))
+    return ArrayCase("2x2 TSV, 10x10x20 hex, quadratic", [spec], 2, 2,
+                     np.zeros(4, dtype=np.uint8))
+
+
+def case_c2(seed=0):
+    """16x16 array, 16x16x32 hexes, cubic faces, diameter drawn from {4,5,6}."""
+    rng = np.random.default_rng(seed)
+    d = float(rng.choice([4.0, 5.0, 6.0]))
+    spec = CellSpec(tsv_diameter=d)
+    return ArrayCase(f"16x16 TSV d={d:g}, 16x16x32 hex, cubic", [spec], 16, 16,
+                     np.zeros(256, dtype=np.uint8))
+
+
+def case_c3(seed=0):
+    """64x64 array with 10% dummy blocks, mixed precision."""
+    rng = np.random.default_rng(seed)
+    spec = CellSpec()
+    return ArrayCase("64x64 TSV + 10% dummy, 16x16x32 hex, cubic", [spec, spec.dummy()], 64, 64,
+                     dummy_map(rng, 4096, 0.10), mixed=True)
+
+
+def case_c5(seed=0):
+    """200x200 array, 20x20x40 hexes with a 0.5 um liner, Fourier field on all
+    outer faces."""
+    rng = np.random.default_rng(seed)
+    spec = CellSpec(mesh=(20, 20, 40), liner_thickness=0.5)
+    L = (200 * spec.pitch_x, 200 * spec.pitch_y, spec.height)
+    return ArrayCase("200x200 TSV+liner, 20x20x40 hex, cubic, Fourier boundary", [spec], 200, 200,
+                     np.zeros(40000, dtype=np.uint8), clamp_bottom=False,
+                     field=fourier_field(rng, L), mixed=True)
+
+
+def small_case(nx=3, ny=2, mesh=(4, 4, 6), interp=(3, 3, 3), dummies=True, seed=0, **kw):
+    """A few-block array with a small cell mesh, for fast parity tests."""
+    rng = np.random.default_rng(seed)
+    spec = CellSpec(mesh=mesh, interp=interp, **kw)
+    specs = [spec, spec.dummy()] if dummies else [spec]
+    t = dummy_map(rng, nx * ny, 0.34) if dummies else np.zeros(nx * ny, dtype=np.uint8)
+    return ArrayCase(f"{nx}x{ny} small", specs, nx, ny, t)
+
+
+@dataclass
+class Request:
+    arrival_s: float
+    N: int
+    pitch: float
+    delta_T: float
+    seed: int
+
+
+def request_stream(seed=0, n_requests=2000, rate_hz=200.0, n_min=4, n_max=48,
+                   pitches=(10.0, 15.0, 20.0), dT_range=(-300.0, -150.0)):
+    """Poisson arrivals; per request N ~ U{n_min..n_max}, pitch ~ U(pitches),
+    dT ~ U[dT_range]; each request seeds its own 10% dummy placement."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate_hz, size=n_requests)
+    t = np.cumsum(gaps) - gaps[0]
+    out = []
+    for i in range(n_requests):
+        out.append(Request(float(t[i]), int(rng.integers(n_min, n_max + 1)),
+                           float(rng.choice(pitches)), float(rng.uniform(*dT_range)),
+                           int(rng.integers(0, 2 ** 31 - 1))))
+    return out
+
+
+def request_case(req, mesh=(16, 16, 32), interp=(4, 4, 4)):
+    rng = np.random.default_rng(req.seed)
+    spec = CellSpec(pitch_x=req.pitch, pitch_y=req.pitch, mesh=mesh, interp=interp)
+    return ArrayCase(f"{req.N}x{req.N} p={req.pitch:g}", [spec, spec.dummy()], req.N, req.N,
+                     dummy_map(rng, req.N * req.N, 0.10), delta_T=req.delta_T, mixed=True)
