@@ -1,0 +1,197 @@
+/*
+ * mos.h - C ABI of the MI355X library for MORE-Stress, the model-order-reduced
+ * thermal-stress solve of periodic TSV arrays (arXiv 2411.12690).
+ *
+ * The four stage calls follow the paper's problem statement:
+ *   mos_build_cell   unit block -> fine FE system          (Sec. 3.2, 4.2; eq. 1-7, 11-12)
+ *   mos_reduce       FE system -> reduced order model      (Sec. 4.2-4.3; eq. 8-19)
+ *   mos_solve_array  ROMs + array layout -> reduced u      (Sec. 4.3-4.4; eq. 20)
+ *   mos_reconstruct  reduced u -> per-cell stress          (Sec. 4.3, last paragraph; eq. 1, 15)
+ *
+ * Conventions
+ *   Units: micrometres, MPa, 1/K, K.  Stress in MPa, displacement in um.
+ *   Every call returns mos_status; on failure *out is set to NULL, nothing is
+ *   written to caller buffers, and mos_last_error() (thread-local) describes
+ *   the failure.  No C++ exception crosses this boundary.
+ *   Handles are owned by the library and released with the matching *_free.
+ *   Host input arrays are read during the call only (copied if kept).
+ *   "device" pointers are HIP device addresses on the context's device;
+ *   device work is enqueued on the context's stream.  Calls that return
+ *   host data or status synchronise that stream.
+ *   A context and its handles must be used from one host thread at a time.
+ *
+ * Numbering contracts (shared with any independent implementation)
+ *   Cell FE node (a,b,c), 0<=a<=m_x etc., has id (c*(m_y+1)+b)*(m_x+1)+a and
+ *   DoF 3*id+component.  Cell element (ea,eb,ec) has id (ec*m_y+eb)*m_x+ea.
+ *   Lagrange surface node (i,j,k) of a cell (i in {0,n_x-1} or j in {0,n_y-1}
+ *   or k in {0,n_z-1}) has local index s = its rank in (k,j,i) lexicographic
+ *   order, i fastest; the reduced cell DoF is 3*s+component (eq. 14-16).
+ *   The abstract array mesh has lattice X = N_x(n_x-1)+1, Y = N_y(n_y-1)+1,
+ *   Z = n_z; lattice point (I,J,K) is a node iff I%(n_x-1)==0 or
+ *   J%(n_y-1)==0 or K in {0, n_z-1}; node id = rank in (K,J,I) order, I
+ *   fastest; global DoF 3*id+component.  Cell (cx,cy) has id cy*N_x+cx and its
+ *   surface node (i,j,k) is lattice point (cx(n_x-1)+i, cy(n_y-1)+j, k).
+ */
+#ifndef MOS_H
+#define MOS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MOS_OK = 0,
+    MOS_EINVAL = -1,      /* invalid argument or incompatible handles */
+    MOS_ENOMEM = -2,      /* device or host allocation failed */
+    MOS_ENOCONV = -3,     /* iterative solve did not reach the tolerance */
+    MOS_ESINGULAR = -4,   /* matrix not positive definite / no constraints */
+    MOS_EHIP = -5,        /* HIP runtime error */
+    MOS_EBUSY = -6        /* resource temporarily unavailable (serving) */
+} mos_status;
+
+typedef enum { MOS_FP64 = 0, MOS_MIXED = 1 } mos_precision;
+
+typedef struct mos_ctx_s *mos_ctx;
+typedef struct mos_cell_s *mos_cell;
+typedef struct mos_rom_s *mos_rom;
+typedef struct mos_sol_s *mos_sol;
+
+/* Isotropic linear thermo-elastic material (eq. 1-2): E [MPa], nu [-], alpha [1/K]. */
+typedef struct { double E, nu, alpha; } mos_material;
+
+/* Unit block of Sec. 4.2 / Fig. 2: a pitch_x x pitch_y x height cuboid of
+ * `matrix` with a centred via of diameter tsv_diameter (0 = dummy block,
+ * Sec. 4.4) and a liner of liner_thickness around it, meshed as a structured
+ * mesh[0] x mesh[1] x mesh[2] grid of trilinear hexahedra; an element takes
+ * the via material if its centroid's distance r to the via axis satisfies
+ * r < d/2, the liner if r < d/2 + t, else the matrix.  interp[] is the number
+ * of equally spaced Lagrange nodes per axis (n_x, n_y, n_z) >= 2 (eq. 8-10). */
+typedef struct {
+    double pitch_x, pitch_y, height;
+    int32_t mesh[3];
+    double tsv_diameter, liner_thickness;
+    mos_material matrix, via, liner;
+    int32_t interp[3];
+} mos_cell_desc;
+
+enum { MOS_BC_CLAMP_BOTTOM = 1, MOS_BC_CLAMP_TOP = 2 };
+
+/* One global-stage problem (Sec. 4.3-4.4).  cell_type[cy*nx_cells+cx] indexes
+ * the roms[] array passed with it (host memory).  Constrained DoFs: the
+ * clamped faces (value 0) and then the prescribed (global DoF, value) list,
+ * a later entry overriding an earlier one; the system is lifted
+ * symmetrically (Sec. 4.2 eq. 13 form, same solution).  rtol bounds the
+ * FP64 true residual ||b - A u||_2 / ||b||_2 (0 selects 1e-12 for MOS_FP64,
+ * 1e-10 for MOS_MIXED); max_iters bounds the total PCG iterations (0 selects
+ * 20000). */
+typedef struct {
+    int32_t nx_cells, ny_cells;
+    const uint8_t *cell_type;
+    double delta_T;
+    uint32_t bc_flags;
+    int64_t n_prescribed;
+    const int64_t *prescribed_dof;
+    const double *prescribed_value;
+    mos_precision precision;
+    double rtol;
+    int32_t max_iters;
+} mos_array_desc;
+
+/* Optional device allocator (e.g. a framework's caching allocator).  NULL
+ * members select hipMalloc / hipFree. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *user;
+} mos_allocator;
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  `alloc` may be NULL. */
+mos_status mos_ctx_create(int device, void *hip_stream, const mos_allocator *alloc, mos_ctx *out);
+void mos_ctx_destroy(mos_ctx ctx);
+
+/* Sec. 3.2 and 4.2 (eq. 1-7, 11-12): mesh the unit block, assign materials,
+ * and assemble on the device the FE stiffness K (CSR, 27-node stencil) and the
+ * unit-dT thermal load b of the whole block, plus K_ff of the interior DoFs
+ * in band form.  Errors: MOS_EINVAL for a non-positive size, a mesh axis
+ * outside [2, 128], interp outside [2, 8], nu outside (-1, 0.5), E <= 0. */
+mos_status mos_build_cell(mos_ctx ctx, const mos_cell_desc *desc, mos_cell *out);
+
+/* Sec. 4.2-4.3 (eq. 8-19): Lagrange weights L of the boundary FE nodes, one
+ * Cholesky factorisation of K_ff and n+1 solves giving Phi = [f_0..f_{n-1}]
+ * and f_T, then A_element = K_r = sym(Phi^T K Phi), b_element = b_r =
+ * Phi^T b, and the centroid stress basis used by mos_reconstruct.  The ROM
+ * stays resident in device memory.  Errors: MOS_ESINGULAR if K_ff is not
+ * positive definite.  The cell may be freed afterwards. */
+mos_status mos_reduce(mos_ctx ctx, mos_cell cell, mos_rom *out);
+
+/* Sec. 4.3-4.4 (eq. 20): assemble the reduced global system of the array
+ * element by element, lift the constraints, and solve with Jacobi-PCG
+ * (MOS_FP64: FP64 throughout; MOS_MIXED: FP32 PCG corrections inside FP64
+ * iterative refinement on the true residual).  All roms must share pitch,
+ * height, mesh and interp (MOS_EINVAL otherwise).  An array with no
+ * constrained DoF is MOS_ESINGULAR; PCG breakdown or max_iters is
+ * MOS_ENOCONV (the handle is still returned NULL). */
+mos_status mos_solve_array(mos_ctx ctx, const mos_array_desc *desc, const mos_rom *roms,
+                           int32_t n_roms, mos_sol *out);
+
+enum { MOS_OUT_VM = 1, MOS_OUT_SIGMA6 = 2 };
+/* Sec. 4.3 last paragraph with eq. 1 and 15: per cell c and fine element e,
+ * sigma = dT sigma_T(e) + Psi(e) u_c with Psi = D B0 Phi at the element
+ * centroid; von Mises from sigma.  vm: device array [n_cells][n_elem],
+ * sigma6: device array [n_cells][n_elem][6] (xx,yy,zz,xy,yz,zx); element
+ * order as in the numbering contract.  Element type is double for a
+ * MOS_FP64 solution and float for MOS_MIXED.  Either pointer may be NULL
+ * when its flag is not set. */
+mos_status mos_reconstruct(mos_ctx ctx, mos_sol sol, uint32_t outputs, void *vm, void *sigma6);
+
+/* Copy the reduced solution (n_global_dofs doubles) to host memory and report
+ * the final relative true residual and total PCG iterations (any may be NULL). */
+mos_status mos_get_solution(mos_sol sol, double *u_host, double *rel_residual, int32_t *iters);
+
+enum {
+    MOS_Q_N = 1,            /* rom/cell: reduced DoFs per cell, n (eq. 16) */
+    MOS_Q_CELL_DOFS = 2,    /* rom/cell: FE DoFs of the block */
+    MOS_Q_CELL_ELEMS = 3,   /* rom/cell: fine elements of the block */
+    MOS_Q_CELL_NNZ = 4,     /* cell: nonzeros of K */
+    MOS_Q_FREE_DOFS = 5,    /* cell: interior DoFs */
+    MOS_Q_BANDWIDTH = 6,    /* cell: half bandwidth of K_ff */
+    MOS_Q_GLOBAL_DOFS = 7,  /* sol: reduced global DoFs */
+    MOS_Q_ITERS = 8,        /* sol: total PCG iterations */
+    MOS_Q_REFINES = 9,      /* sol: FP64 refinement sweeps */
+    MOS_Q_DEVICE_BYTES = 10 /* any handle: device bytes it holds */
+};
+mos_status mos_query(const void *handle, int what, int64_t *value);
+
+/* Parity exports (host buffers, caller-owned).  Cell: K as CSR over all FE
+ * DoFs (row_ptr[n_dofs+1], col[nnz], val[nnz]), b[n_dofs], material code per
+ * element (0 matrix, 1 via, 2 liner).  Any pointer may be NULL. */
+mos_status mos_cell_export(mos_cell cell, int64_t *row_ptr, int32_t *col, double *val, double *b,
+                           uint8_t *material);
+/* ROM: Phi row-major [n_dofs][n], f_T[n_dofs], K_r row-major [n][n], b_r[n]. */
+mos_status mos_rom_export(mos_rom rom, double *phi, double *f_T, double *K_r, double *b_r);
+
+/* Abstract array mesh of nx_cells x ny_cells blocks shaped like `rom`
+ * (numbering contract above).  n_nodes receives the node count; when the
+ * arrays are non-NULL: coords[n_nodes][3] (um), conn[n_cells][n/3] node ids,
+ * and the sparsity pattern of the assembled global matrix over DoFs
+ * (union of per-cell dense blocks, columns ascending): row_ptr[3 n_nodes + 1]
+ * and col[row_ptr[3 n_nodes]].  Call with col == NULL first to size it. */
+mos_status mos_array_layout(mos_ctx ctx, int32_t nx_cells, int32_t ny_cells, mos_rom rom,
+                            int64_t *n_nodes, double *coords, int32_t *conn, int64_t *row_ptr,
+                            int32_t *col);
+
+void mos_cell_free(mos_cell cell);
+void mos_rom_free(mos_rom rom);
+void mos_sol_free(mos_sol sol);
+
+/* Thread-local description of the last failure on this thread. */
+const char *mos_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MOS_H */

@@ -1,0 +1,555 @@
+// C ABI entry points: argument checking, handle lifetime, host-side
+// numbering of the abstract array mesh (Sec. 4.3), and dispatch to the
+// device stages.  No exception crosses the ABI.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "mos_internal.h"
+#include "mesh.h"
+
+namespace mos {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+mos_status DeviceArena::alloc(size_t n, void **out) {
+    *out = nullptr;
+    if (n == 0) n = 16;
+    n = (size_t)round_up((int64_t)n, 256);
+    void *p = nullptr;
+    if (ctx->user_alloc) {
+        p = ctx->alloc.alloc(n, ctx->alloc.user);
+        if (!p) {
+            set_error("device allocation of %zu bytes failed (user allocator)", n);
+            return MOS_ENOMEM;
+        }
+    } else {
+        hipError_t e = hipMalloc(&p, n);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("hipMalloc(%zu) failed: %s", n, hipGetErrorString(e));
+            return MOS_ENOMEM;
+        }
+    }
+    ptrs.push_back(p);
+    bytes += n;
+    *out = p;
+    return MOS_OK;
+}
+
+void DeviceArena::release() {
+    if (!ctx) return;
+    if (!ptrs.empty()) (void)hipStreamSynchronize(ctx->stream);
+    for (void *p : ptrs) {
+        if (ctx->user_alloc) ctx->alloc.free(p, ctx->alloc.user);
+        else (void)hipFree(p);
+    }
+    ptrs.clear();
+    bytes = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Abstract array mesh (numbering contract in mos.h)
+// ---------------------------------------------------------------------------
+void surface_nodes(int nx, int ny, int nz, std::vector<int> &ijk) {
+    ijk.clear();
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i)
+                if (i == 0 || i == nx - 1 || j == 0 || j == ny - 1 || k == 0 || k == nz - 1) {
+                    ijk.push_back(i);
+                    ijk.push_back(j);
+                    ijk.push_back(k);
+                }
+}
+
+void ArrayMesh::build(int Nx_, int Ny_, int nx_, int ny_, int nz_) {
+    Nx = Nx_;
+    Ny = Ny_;
+    nx = nx_;
+    ny = ny_;
+    nz = nz_;
+    X = (int64_t)Nx * (nx - 1) + 1;
+    Y = (int64_t)Ny * (ny - 1) + 1;
+    Z = nz;
+    node_of.assign((size_t)(X * Y * Z), -1);
+    int64_t cnt = 0;
+    for (int64_t K = 0; K < Z; ++K)
+        for (int64_t J = 0; J < Y; ++J)
+            for (int64_t I = 0; I < X; ++I)
+                if (I % (nx - 1) == 0 || J % (ny - 1) == 0 || K == 0 || K == nz - 1)
+                    node_of[(size_t)((K * Y + J) * X + I)] = (int32_t)cnt++;
+    n_nodes = cnt;
+    surface_nodes(nx, ny, nz, surf);
+    S = (int)surf.size() / 3;
+    conn.resize((size_t)Nx * Ny * S);
+    for (int cy = 0; cy < Ny; ++cy)
+        for (int cx = 0; cx < Nx; ++cx) {
+            size_t c = (size_t)cy * Nx + cx;
+            for (int s = 0; s < S; ++s) {
+                int64_t I = (int64_t)cx * (nx - 1) + surf[3 * s];
+                int64_t J = (int64_t)cy * (ny - 1) + surf[3 * s + 1];
+                int64_t K = surf[3 * s + 2];
+                conn[c * S + s] = node_of[(size_t)((K * Y + J) * X + I)];
+            }
+        }
+}
+
+}  // namespace mos
+
+using namespace mos;
+
+static bool valid_material(const mos_material &m) {
+    return std::isfinite(m.E) && m.E > 0.0 && std::isfinite(m.nu) && m.nu > -1.0 && m.nu < 0.5 &&
+           std::isfinite(m.alpha);
+}
+
+static mos_status check_cell_desc(const mos_cell_desc *d) {
+    if (!d) {
+        set_error("descriptor is NULL");
+        return MOS_EINVAL;
+    }
+    if (!(d->pitch_x > 0 && d->pitch_y > 0 && d->height > 0) || !std::isfinite(d->pitch_x) ||
+        !std::isfinite(d->pitch_y) || !std::isfinite(d->height)) {
+        set_error("pitch and height must be positive and finite");
+        return MOS_EINVAL;
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (d->mesh[a] < 2 || d->mesh[a] > 128) {
+            set_error("mesh[%d] = %d outside [2, 128]", a, d->mesh[a]);
+            return MOS_EINVAL;
+        }
+        if (d->interp[a] < 2 || d->interp[a] > 8) {
+            set_error("interp[%d] = %d outside [2, 8]", a, d->interp[a]);
+            return MOS_EINVAL;
+        }
+    }
+    {
+        int nx = d->interp[0], ny = d->interp[1], nz = d->interp[2];
+        int S = nx * ny * nz - (nx - 2) * (ny - 2) * (nz - 2);
+        if (S > MAX_SURF) {
+            set_error("interp (%d,%d,%d) has %d surface nodes, more than %d", nx, ny, nz, S, MAX_SURF);
+            return MOS_EINVAL;
+        }
+    }
+    if (!(d->tsv_diameter >= 0) || !(d->liner_thickness >= 0) || !std::isfinite(d->tsv_diameter) ||
+        !std::isfinite(d->liner_thickness)) {
+        set_error("tsv_diameter and liner_thickness must be finite and >= 0");
+        return MOS_EINVAL;
+    }
+    if (!valid_material(d->matrix) || !valid_material(d->via) || !valid_material(d->liner)) {
+        set_error("material needs E > 0, -1 < nu < 0.5 and finite alpha");
+        return MOS_EINVAL;
+    }
+    int64_t dofs = 3LL * (d->mesh[0] + 1) * (d->mesh[1] + 1) * (d->mesh[2] + 1);
+    if (dofs * 81 > (int64_t)INT32_MAX) {
+        set_error("cell mesh too large for 32-bit sparse indices");
+        return MOS_EINVAL;
+    }
+    return MOS_OK;
+}
+
+extern "C" {
+
+const char *mos_last_error(void) { return g_err; }
+
+mos_status mos_ctx_create(int device, void *hip_stream, const mos_allocator *alloc, mos_ctx *out) {
+    if (!out) {
+        set_error("out is NULL");
+        return MOS_EINVAL;
+    }
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) {
+        (void)hipGetLastError();
+        set_error("no HIP device available (%s)", hipGetErrorString(e));
+        return MOS_EHIP;
+    }
+    if (device < 0 || device >= n) {
+        set_error("device %d out of range [0, %d)", device, n);
+        return MOS_EINVAL;
+    }
+    if (alloc && ((alloc->alloc == nullptr) != (alloc->free == nullptr))) {
+        set_error("allocator needs both alloc and free");
+        return MOS_EINVAL;
+    }
+    MOS_HIP(hipSetDevice(device));
+    mos_ctx c = new (std::nothrow) mos_ctx_s();
+    if (!c) {
+        set_error("out of host memory");
+        return MOS_ENOMEM;
+    }
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    if (alloc && alloc->alloc) {
+        c->alloc = *alloc;
+        c->user_alloc = true;
+    }
+    e = hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        set_error("hipHostMalloc failed: %s", hipGetErrorString(e));
+        return MOS_ENOMEM;
+    }
+    *out = c;
+    return MOS_OK;
+}
+
+void mos_ctx_destroy(mos_ctx ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    delete ctx;
+}
+
+mos_status mos_build_cell(mos_ctx ctx, const mos_cell_desc *desc, mos_cell *out) {
+    if (!out) {
+        set_error("out is NULL");
+        return MOS_EINVAL;
+    }
+    *out = nullptr;
+    if (!ctx) {
+        set_error("ctx is NULL");
+        return MOS_EINVAL;
+    }
+    MOS_TRY(check_cell_desc(desc));
+    MOS_HIP(hipSetDevice(ctx->device));
+    mos_cell c = new (std::nothrow) mos_cell_s();
+    if (!c) {
+        set_error("out of host memory");
+        return MOS_ENOMEM;
+    }
+    c->ctx = ctx;
+    c->mem.ctx = ctx;
+    c->desc = *desc;
+    c->mx = desc->mesh[0];
+    c->my = desc->mesh[1];
+    c->mz = desc->mesh[2];
+    mos_status s = launch_cell_assembly(c);
+    if (s == MOS_OK) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) {
+            set_error("cell assembly failed: %s", hipGetErrorString(e));
+            s = MOS_EHIP;
+        }
+    }
+    if (s != MOS_OK) {
+        mos_cell_free(c);
+        return s;
+    }
+    *out = c;
+    return MOS_OK;
+}
+
+mos_status mos_reduce(mos_ctx ctx, mos_cell cell, mos_rom *out) {
+    if (!out) {
+        set_error("out is NULL");
+        return MOS_EINVAL;
+    }
+    *out = nullptr;
+    if (!ctx || !cell || cell->kind != KIND_CELL || cell->ctx != ctx) {
+        set_error("invalid context or cell handle");
+        return MOS_EINVAL;
+    }
+    if (cell->n_free == 0) {
+        set_error("cell has no interior DoFs");
+        return MOS_EINVAL;
+    }
+    MOS_HIP(hipSetDevice(ctx->device));
+    mos_rom r = new (std::nothrow) mos_rom_s();
+    if (!r) {
+        set_error("out of host memory");
+        return MOS_ENOMEM;
+    }
+    r->ctx = ctx;
+    r->mem.ctx = ctx;
+    mos_status s = reduce_cell(cell, r);
+    if (s == MOS_OK) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) {
+            set_error("reduction failed: %s", hipGetErrorString(e));
+            s = MOS_EHIP;
+        }
+    }
+    if (s != MOS_OK) {
+        mos_rom_free(r);
+        return s;
+    }
+    *out = r;
+    return MOS_OK;
+}
+
+static mos_status check_roms(const mos_rom *roms, int32_t n_roms) {
+    if (!roms || n_roms < 1 || n_roms > MAX_TYPES) {
+        set_error("need 1..%d ROMs", MAX_TYPES);
+        return MOS_EINVAL;
+    }
+    for (int t = 0; t < n_roms; ++t)
+        if (!roms[t] || roms[t]->kind != KIND_ROM) {
+            set_error("roms[%d] is not a ROM handle", t);
+            return MOS_EINVAL;
+        }
+    const mos_cell_desc &a = roms[0]->desc;
+    for (int t = 1; t < n_roms; ++t) {
+        const mos_cell_desc &b = roms[t]->desc;
+        bool same = a.pitch_x == b.pitch_x && a.pitch_y == b.pitch_y && a.height == b.height;
+        for (int k = 0; k < 3; ++k) same = same && a.mesh[k] == b.mesh[k] && a.interp[k] == b.interp[k];
+        if (!same) {
+            set_error("roms[%d] differs from roms[0] in pitch, height, mesh or interp", t);
+            return MOS_EINVAL;
+        }
+    }
+    return MOS_OK;
+}
+
+mos_status mos_solve_array(mos_ctx ctx, const mos_array_desc *d, const mos_rom *roms, int32_t n_roms,
+                           mos_sol *out) {
+    if (!out) {
+        set_error("out is NULL");
+        return MOS_EINVAL;
+    }
+    *out = nullptr;
+    if (!ctx || !d) {
+        set_error("ctx or descriptor is NULL");
+        return MOS_EINVAL;
+    }
+    MOS_TRY(check_roms(roms, n_roms));
+    for (int t = 0; t < n_roms; ++t)
+        if (roms[t]->ctx != ctx) {
+            set_error("roms[%d] belongs to another context", t);
+            return MOS_EINVAL;
+        }
+    if (d->nx_cells < 1 || d->ny_cells < 1 || (int64_t)d->nx_cells * d->ny_cells > (1 << 22) || !d->cell_type) {
+        set_error("array size must be >= 1x1 and <= 4M cells, with a cell_type map");
+        return MOS_EINVAL;
+    }
+    if (!std::isfinite(d->delta_T) || d->n_prescribed < 0 ||
+        (d->n_prescribed > 0 && (!d->prescribed_dof || !d->prescribed_value)) ||
+        (d->bc_flags & ~(uint32_t)(MOS_BC_CLAMP_BOTTOM | MOS_BC_CLAMP_TOP)) ||
+        (d->precision != MOS_FP64 && d->precision != MOS_MIXED) || d->rtol < 0 || d->max_iters < 0) {
+        set_error("invalid delta_T, constraints, precision, rtol or max_iters");
+        return MOS_EINVAL;
+    }
+    const int64_t n_cells = (int64_t)d->nx_cells * d->ny_cells;
+    for (int64_t c = 0; c < n_cells; ++c)
+        if (d->cell_type[c] >= n_roms) {
+            set_error("cell_type[%lld] = %d but only %d ROMs", (long long)c, d->cell_type[c], n_roms);
+            return MOS_EINVAL;
+        }
+    MOS_HIP(hipSetDevice(ctx->device));
+    mos_sol s = new (std::nothrow) mos_sol_s();
+    if (!s) {
+        set_error("out of host memory");
+        return MOS_ENOMEM;
+    }
+    s->ctx = ctx;
+    s->mem.ctx = ctx;
+    mos_status st = solve_array(ctx, d, roms, n_roms, s);
+    if (st != MOS_OK) {
+        mos_sol_free(s);
+        return st;
+    }
+    *out = s;
+    return MOS_OK;
+}
+
+mos_status mos_reconstruct(mos_ctx ctx, mos_sol sol, uint32_t outputs, void *vm, void *sigma6) {
+    if (!ctx || !sol || sol->kind != KIND_SOL || sol->ctx != ctx) {
+        set_error("invalid context or solution handle");
+        return MOS_EINVAL;
+    }
+    if ((outputs & ~(uint32_t)(MOS_OUT_VM | MOS_OUT_SIGMA6)) || outputs == 0 ||
+        ((outputs & MOS_OUT_VM) && !vm) || ((outputs & MOS_OUT_SIGMA6) && !sigma6)) {
+        set_error("outputs must select VM and/or SIGMA6 with non-NULL buffers");
+        return MOS_EINVAL;
+    }
+    MOS_HIP(hipSetDevice(ctx->device));
+    return reconstruct(ctx, sol, outputs, vm, sigma6);
+}
+
+mos_status mos_get_solution(mos_sol sol, double *u_host, double *rel_residual, int32_t *iters) {
+    if (!sol || sol->kind != KIND_SOL) {
+        set_error("invalid solution handle");
+        return MOS_EINVAL;
+    }
+    if (u_host) {
+        MOS_HIP(hipSetDevice(sol->ctx->device));
+        MOS_HIP(hipMemcpyAsync(u_host, sol->u, sol->n_dofs * sizeof(double), hipMemcpyDeviceToHost,
+                               sol->ctx->stream));
+        MOS_HIP(hipStreamSynchronize(sol->ctx->stream));
+    }
+    if (rel_residual) *rel_residual = sol->rel_residual;
+    if (iters) *iters = sol->iters;
+    return MOS_OK;
+}
+
+mos_status mos_query(const void *handle, int what, int64_t *value) {
+    if (!handle || !value) {
+        set_error("handle or value is NULL");
+        return MOS_EINVAL;
+    }
+    uint32_t kind = *static_cast<const uint32_t *>(handle);
+    if (kind == KIND_CELL) {
+        const mos_cell_s *c = static_cast<const mos_cell_s *>(handle);
+        int nx = c->desc.interp[0], ny = c->desc.interp[1], nz = c->desc.interp[2];
+        switch (what) {
+            case MOS_Q_N: *value = 3LL * (nx * ny * nz - (nx - 2) * (ny - 2) * (nz - 2)); return MOS_OK;
+            case MOS_Q_CELL_DOFS: *value = c->n_dofs; return MOS_OK;
+            case MOS_Q_CELL_ELEMS: *value = c->n_elem; return MOS_OK;
+            case MOS_Q_CELL_NNZ: *value = c->nnz; return MOS_OK;
+            case MOS_Q_FREE_DOFS: *value = c->n_free; return MOS_OK;
+            case MOS_Q_BANDWIDTH: *value = c->bw; return MOS_OK;
+            case MOS_Q_DEVICE_BYTES: *value = (int64_t)c->mem.bytes; return MOS_OK;
+        }
+    } else if (kind == KIND_ROM) {
+        const mos_rom_s *r = static_cast<const mos_rom_s *>(handle);
+        switch (what) {
+            case MOS_Q_N: *value = r->n; return MOS_OK;
+            case MOS_Q_CELL_DOFS: *value = r->n_dofs; return MOS_OK;
+            case MOS_Q_CELL_ELEMS: *value = r->n_elem; return MOS_OK;
+            case MOS_Q_DEVICE_BYTES: *value = (int64_t)r->mem.bytes; return MOS_OK;
+        }
+    } else if (kind == KIND_SOL) {
+        const mos_sol_s *s = static_cast<const mos_sol_s *>(handle);
+        switch (what) {
+            case MOS_Q_GLOBAL_DOFS: *value = s->n_dofs; return MOS_OK;
+            case MOS_Q_ITERS: *value = s->iters; return MOS_OK;
+            case MOS_Q_REFINES: *value = s->refines; return MOS_OK;
+            case MOS_Q_DEVICE_BYTES: *value = (int64_t)s->mem.bytes; return MOS_OK;
+        }
+    } else {
+        set_error("unknown handle");
+        return MOS_EINVAL;
+    }
+    set_error("query %d not defined for this handle", what);
+    return MOS_EINVAL;
+}
+
+mos_status mos_cell_export(mos_cell c, int64_t *row_ptr, int32_t *col, double *val, double *b,
+                           uint8_t *material) {
+    if (!c || c->kind != KIND_CELL) {
+        set_error("invalid cell handle");
+        return MOS_EINVAL;
+    }
+    hipStream_t st = c->ctx->stream;
+    MOS_HIP(hipSetDevice(c->ctx->device));
+    if (row_ptr) {
+        std::vector<int32_t> rp(c->n_dofs + 1);
+        MOS_HIP(hipMemcpyAsync(rp.data(), c->row_ptr, rp.size() * 4, hipMemcpyDeviceToHost, st));
+        MOS_HIP(hipStreamSynchronize(st));
+        for (size_t i = 0; i < rp.size(); ++i) row_ptr[i] = rp[i];
+    }
+    if (col) MOS_HIP(hipMemcpyAsync(col, c->col, c->nnz * 4, hipMemcpyDeviceToHost, st));
+    if (val) MOS_HIP(hipMemcpyAsync(val, c->val, c->nnz * 8, hipMemcpyDeviceToHost, st));
+    if (b) MOS_HIP(hipMemcpyAsync(b, c->b, c->n_dofs * 8, hipMemcpyDeviceToHost, st));
+    if (material) MOS_HIP(hipMemcpyAsync(material, c->mat, c->n_elem, hipMemcpyDeviceToHost, st));
+    MOS_HIP(hipStreamSynchronize(st));
+    return MOS_OK;
+}
+
+mos_status mos_rom_export(mos_rom r, double *phi, double *f_T, double *K_r, double *b_r) {
+    if (!r || r->kind != KIND_ROM) {
+        set_error("invalid ROM handle");
+        return MOS_EINVAL;
+    }
+    hipStream_t st = r->ctx->stream;
+    MOS_HIP(hipSetDevice(r->ctx->device));
+    if (phi || f_T) {
+        std::vector<double> h((size_t)r->n_dofs * r->ldp);
+        MOS_HIP(hipMemcpyAsync(h.data(), r->phi, h.size() * 8, hipMemcpyDeviceToHost, st));
+        MOS_HIP(hipStreamSynchronize(st));
+        for (int i = 0; i < r->n_dofs; ++i) {
+            if (phi) std::memcpy(phi + (size_t)i * r->n, h.data() + (size_t)i * r->ldp, r->n * 8);
+            if (f_T) f_T[i] = h[(size_t)i * r->ldp + r->n];
+        }
+    }
+    if (K_r) MOS_HIP(hipMemcpyAsync(K_r, r->kr, (size_t)r->n * r->n * 8, hipMemcpyDeviceToHost, st));
+    if (b_r) MOS_HIP(hipMemcpyAsync(b_r, r->br, r->n * 8, hipMemcpyDeviceToHost, st));
+    MOS_HIP(hipStreamSynchronize(st));
+    return MOS_OK;
+}
+
+mos_status mos_array_layout(mos_ctx ctx, int32_t nx_cells, int32_t ny_cells, mos_rom rom, int64_t *n_nodes,
+                            double *coords, int32_t *conn, int64_t *row_ptr, int32_t *col) {
+    if (!ctx || !rom || rom->kind != KIND_ROM || !n_nodes || nx_cells < 1 || ny_cells < 1 ||
+        (int64_t)nx_cells * ny_cells > (1 << 22)) {
+        set_error("invalid arguments to mos_array_layout");
+        return MOS_EINVAL;
+    }
+    const mos_cell_desc &d = rom->desc;
+    ArrayMesh m;
+    m.build(nx_cells, ny_cells, d.interp[0], d.interp[1], d.interp[2]);
+    *n_nodes = m.n_nodes;
+    if (coords) {
+        for (int64_t K = 0; K < m.Z; ++K)
+            for (int64_t J = 0; J < m.Y; ++J)
+                for (int64_t I = 0; I < m.X; ++I) {
+                    int32_t id = m.node_of[(size_t)((K * m.Y + J) * m.X + I)];
+                    if (id < 0) continue;
+                    coords[3 * (size_t)id + 0] = d.pitch_x * I / (m.nx - 1);
+                    coords[3 * (size_t)id + 1] = d.pitch_y * J / (m.ny - 1);
+                    coords[3 * (size_t)id + 2] = d.height * K / (m.nz - 1);
+                }
+    }
+    if (conn) std::memcpy(conn, m.conn.data(), m.conn.size() * sizeof(int32_t));
+    if (row_ptr) {
+        // Node-level pattern: union of the node sets of the cells around each node.
+        std::vector<std::vector<int32_t>> cells_of((size_t)m.n_nodes);
+        const int64_t nc = (int64_t)nx_cells * ny_cells;
+        for (int64_t c = 0; c < nc; ++c)
+            for (int s = 0; s < m.S; ++s) cells_of[m.conn[(size_t)c * m.S + s]].push_back((int32_t)c);
+        row_ptr[0] = 0;
+        std::vector<int32_t> nb;
+        for (int64_t node = 0; node < m.n_nodes; ++node) {
+            nb.clear();
+            for (int32_t c : cells_of[node])
+                nb.insert(nb.end(), m.conn.begin() + (size_t)c * m.S, m.conn.begin() + (size_t)(c + 1) * m.S);
+            std::sort(nb.begin(), nb.end());
+            nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+            for (int ci = 0; ci < 3; ++ci) {
+                int64_t r = 3 * node + ci;
+                row_ptr[r + 1] = row_ptr[r] + 3 * (int64_t)nb.size();
+                if (col) {
+                    int64_t k = row_ptr[r];
+                    for (int32_t v : nb)
+                        for (int cj = 0; cj < 3; ++cj) col[k++] = 3 * v + cj;
+                }
+            }
+        }
+    }
+    return MOS_OK;
+}
+
+void mos_cell_free(mos_cell c) {
+    if (!c || c->kind != KIND_CELL) return;
+    c->mem.release();
+    c->kind = 0;
+    delete c;
+}
+
+void mos_rom_free(mos_rom r) {
+    if (!r || r->kind != KIND_ROM) return;
+    r->mem.release();
+    r->kind = 0;
+    delete r;
+}
+
+void mos_sol_free(mos_sol s) {
+    if (!s || s->kind != KIND_SOL) return;
+    s->mem.release();
+    s->kind = 0;
+    delete s;
+}
+
+}  // extern "C"

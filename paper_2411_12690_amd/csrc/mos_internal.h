@@ -1,0 +1,155 @@
+// Internal declarations of the MI355X MORE-Stress library: handle layouts,
+// device-memory helpers, error reporting and the kernel launchers each
+// translation unit provides.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "mos.h"
+
+namespace mos {
+
+void set_error(const char *fmt, ...);
+
+#define MOS_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            ::mos::set_error("%s: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__,  \
+                             __LINE__);                                                 \
+            return MOS_EHIP;                                                            \
+        }                                                                               \
+    } while (0)
+
+#define MOS_LAUNCH_CHECK() MOS_HIP(hipGetLastError())
+
+#define MOS_TRY(expr)                       \
+    do {                                    \
+        mos_status s_ = (expr);             \
+        if (s_ != MOS_OK) return s_;        \
+    } while (0)
+
+enum : uint32_t { KIND_CELL = 0x4c4c4543u, KIND_ROM = 0x214d4f52u, KIND_SOL = 0x214c4f53u };
+
+// Tile edge of the banded Cholesky factor (64 x 64 FP64 tiles).
+constexpr int NB = 64;
+
+// A set of device allocations released together.
+struct DeviceArena {
+    mos_ctx ctx = nullptr;
+    std::vector<void *> ptrs;
+    size_t bytes = 0;
+    mos_status alloc(size_t n, void **out);
+    template <class T>
+    mos_status alloc_n(size_t count, T **out) {
+        return alloc(count * sizeof(T), reinterpret_cast<void **>(out));
+    }
+    void release();
+};
+
+}  // namespace mos
+
+struct mos_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    mos_allocator alloc{};
+    bool user_alloc = false;
+    // Small pinned host buffer for status words read back from the device.
+    void *pinned = nullptr;
+};
+
+struct mos_cell_s {
+    uint32_t kind = mos::KIND_CELL;
+    mos_ctx ctx = nullptr;
+    mos_cell_desc desc{};
+    int mx = 0, my = 0, mz = 0;
+    int n_nodes = 0, n_dofs = 0, n_elem = 0;
+    int64_t nnz = 0;
+    int n_free = 0, bw = 0;       // interior DoFs and half bandwidth of K_ff
+    int NT = 0, W = 0;            // tiles along the band and sub-diagonal tile count
+    int n_bnodes = 0;             // boundary FE nodes
+    mos::DeviceArena mem;
+    // device arrays
+    uint8_t *mat = nullptr;       // [n_elem] material code
+    double *ke = nullptr;         // [3][24][24] element stiffness per material
+    double *fe = nullptr;         // [3][24] unit-dT element load per material
+    double *mprop = nullptr;      // [3][3] (lambda, mu, beta) per material
+    int32_t *row_ptr = nullptr;   // [n_dofs+1]
+    int32_t *col = nullptr;       // [nnz]
+    double *val = nullptr;        // [nnz]
+    double *b = nullptr;          // [n_dofs]
+    int32_t *free_dof = nullptr;  // [n_free] FE DoF of each interior DoF
+    int32_t *bnode = nullptr;     // [n_bnodes] FE node id of each boundary node
+    double *tiles = nullptr;      // [NT][W+1][NB*NB] band of K_ff, column-major tiles
+};
+
+struct mos_rom_s {
+    uint32_t kind = mos::KIND_ROM;
+    mos_ctx ctx = nullptr;
+    mos_cell_desc desc{};
+    int mx = 0, my = 0, mz = 0, n_dofs = 0, n_elem = 0;
+    int n = 0, n_surf = 0;
+    int ldp = 0;                  // row stride of phi (>= n+1, multiple of 8)
+    int ldk = 0;                  // n rounded up to 16 (padded K_r edge)
+    int n_eblk = 0;               // element blocks of 16
+    double orth = 0.0;            // max |f_T^T K Phi| / max |K_r|, a health check
+    mos::DeviceArena mem;
+    double *phi = nullptr;        // [n_dofs][ldp]; column n holds f_T
+    double *kr = nullptr;         // [n][n]
+    double *br = nullptr;         // [n]
+    double *kr_pad = nullptr;     // [ldk][ldk] zero padded
+    float *kr32_pad = nullptr;    // FP32 copy of kr_pad
+    double *psi = nullptr;        // [n_eblk][6][ldk][16] centroid stress basis
+    double *sig_t = nullptr;      // [n_elem][6] unit-dT thermal stress at centroids
+    uint16_t *psi_hi = nullptr;   // bf16 split of psi, MFMA operand layout
+    uint16_t *psi_lo = nullptr;
+};
+
+struct mos_sol_s {
+    uint32_t kind = mos::KIND_SOL;
+    mos_ctx ctx = nullptr;
+    mos_precision precision = MOS_FP64;
+    int Nx = 0, Ny = 0, n_cells = 0;
+    int n = 0, n_surf = 0, n_elem = 0, ldk = 0, n_eblk = 0;
+    int64_t n_nodes = 0, n_dofs = 0;
+    double delta_T = 0.0;
+    double rel_residual = 0.0;
+    int iters = 0, refines = 0;
+    int n_types = 0;
+    int n_pc = 0;                            // padded permuted cell slots
+    std::vector<int> seg;                    // [n_types+1] slot ranges per type (multiples of 16)
+    std::vector<mos_rom> roms;               // per type, borrowed
+    mos::DeviceArena mem;
+    int32_t *perm = nullptr;                 // [n_pc] cell id per slot or -1
+    int32_t *conn = nullptr;                 // [n_cells][n_surf] node ids
+    int32_t *gidx = nullptr;                 // [ldk][n_pc] global DoF of cell DoF k in slot, -1 pad
+    double *u = nullptr;                     // [n_dofs] solution
+};
+
+namespace mos {
+
+// ---- kernel launchers (defined in the .hip files) ----
+// cell.hip
+mos_status launch_cell_assembly(mos_cell c);
+mos_status fill(mos_ctx ctx, double *p, size_t n, double v);
+// dense.hip
+mos_status band_cholesky(mos_cell c, double *dinv, int *status_dev, int *not_spd);
+mos_status band_solve(mos_cell c, const double *dinv, double *rhs, int ldr, int ncols);
+// reduce.hip
+mos_status reduce_cell(mos_cell c, mos_rom r);
+// solve.hip
+mos_status solve_array(mos_ctx ctx, const mos_array_desc *d, const mos_rom *roms, int n_roms, mos_sol s);
+// recon.hip
+mos_status reconstruct(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void *sigma6);
+
+// ---- host helpers (api.cpp) ----
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+inline int ceil_div(int64_t a, int64_t b) { return int((a + b - 1) / b); }
+
+}  // namespace mos

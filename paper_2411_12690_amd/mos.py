@@ -1,0 +1,315 @@
+"""ctypes binding of the C ABI in include/mos.h (argument marshalling only).
+
+Every stage runs in the HIP library ``libmos.so``; this module converts
+Python descriptors to the C structs, passes device pointers of torch tensors,
+routes device allocations through torch's caching allocator and turns status
+codes into exceptions.  Importing it fails loudly when the library is absent.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmos.so")
+
+MOS_OK, MOS_EINVAL, MOS_ENOMEM, MOS_ENOCONV, MOS_ESINGULAR, MOS_EHIP, MOS_EBUSY = 0, -1, -2, -3, -4, -5, -6
+MOS_FP64, MOS_MIXED = 0, 1
+MOS_BC_CLAMP_BOTTOM, MOS_BC_CLAMP_TOP = 1, 2
+MOS_OUT_VM, MOS_OUT_SIGMA6 = 1, 2
+(MOS_Q_N, MOS_Q_CELL_DOFS, MOS_Q_CELL_ELEMS, MOS_Q_CELL_NNZ, MOS_Q_FREE_DOFS, MOS_Q_BANDWIDTH,
+ MOS_Q_GLOBAL_DOFS, MOS_Q_ITERS, MOS_Q_REFINES, MOS_Q_DEVICE_BYTES) = range(1, 11)
+
+EXPORTED = ("mos_ctx_create", "mos_ctx_destroy", "mos_build_cell", "mos_reduce", "mos_solve_array",
+            "mos_reconstruct", "mos_get_solution", "mos_query", "mos_cell_export", "mos_rom_export",
+            "mos_array_layout", "mos_cell_free", "mos_rom_free", "mos_sol_free", "mos_last_error")
+
+
+class MosError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class Material(ctypes.Structure):
+    _fields_ = [("E", ctypes.c_double), ("nu", ctypes.c_double), ("alpha", ctypes.c_double)]
+
+
+class CellDesc(ctypes.Structure):
+    _fields_ = [("pitch_x", ctypes.c_double), ("pitch_y", ctypes.c_double), ("height", ctypes.c_double),
+                ("mesh", ctypes.c_int32 * 3), ("tsv_diameter", ctypes.c_double),
+                ("liner_thickness", ctypes.c_double), ("matrix", Material), ("via", Material),
+                ("liner", Material), ("interp", ctypes.c_int32 * 3)]
+
+
+class ArrayDesc(ctypes.Structure):
+    _fields_ = [("nx_cells", ctypes.c_int32), ("ny_cells", ctypes.c_int32),
+                ("cell_type", ctypes.POINTER(ctypes.c_uint8)), ("delta_T", ctypes.c_double),
+                ("bc_flags", ctypes.c_uint32), ("n_prescribed", ctypes.c_int64),
+                ("prescribed_dof", ctypes.POINTER(ctypes.c_int64)),
+                ("prescribed_value", ctypes.POINTER(ctypes.c_double)), ("precision", ctypes.c_int),
+                ("rtol", ctypes.c_double), ("max_iters", ctypes.c_int32)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, vp = ctypes.POINTER, ctypes.c_void_p
+    sig = {
+        "mos_ctx_create": (ctypes.c_int, [ctypes.c_int, vp, P(Allocator), P(vp)]),
+        "mos_ctx_destroy": (None, [vp]),
+        "mos_build_cell": (ctypes.c_int, [vp, P(CellDesc), P(vp)]),
+        "mos_reduce": (ctypes.c_int, [vp, vp, P(vp)]),
+        "mos_solve_array": (ctypes.c_int, [vp, P(ArrayDesc), P(vp), ctypes.c_int32, P(vp)]),
+        "mos_reconstruct": (ctypes.c_int, [vp, vp, ctypes.c_uint32, vp, vp]),
+        "mos_get_solution": (ctypes.c_int, [vp, vp, P(ctypes.c_double), P(ctypes.c_int32)]),
+        "mos_query": (ctypes.c_int, [vp, ctypes.c_int, P(ctypes.c_int64)]),
+        "mos_cell_export": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
+        "mos_rom_export": (ctypes.c_int, [vp, vp, vp, vp, vp]),
+        "mos_array_layout": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, vp, P(ctypes.c_int64), vp, vp,
+                                            vp, vp]),
+        "mos_cell_free": (None, [vp]),
+        "mos_rom_free": (None, [vp]),
+        "mos_sol_free": (None, [vp]),
+        "mos_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = _load()
+    return _lib
+
+
+def _check(status, what):
+    if status != MOS_OK:
+        msg = lib().mos_last_error().decode(errors="replace")
+        raise MosError(status, f"{what}: {msg}")
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def cell_desc(spec):
+    d = CellDesc()
+    d.pitch_x, d.pitch_y, d.height = float(spec.pitch_x), float(spec.pitch_y), float(spec.height)
+    d.mesh[:] = [int(v) for v in spec.mesh]
+    d.tsv_diameter, d.liner_thickness = float(spec.tsv_diameter), float(spec.liner_thickness)
+    d.matrix, d.via, d.liner = (Material(*map(float, m)) for m in (spec.matrix, spec.via, spec.liner))
+    d.interp[:] = [int(v) for v in spec.interp]
+    return d
+
+
+class _Handle:
+    _free = None
+
+    def __init__(self, ptr, ctx):
+        self.ptr = ptr
+        self.ctx = ctx
+
+    def query(self, what):
+        v = ctypes.c_int64()
+        _check(lib().mos_query(self.ptr, what, ctypes.byref(v)), "mos_query")
+        return v.value
+
+    def close(self):
+        if self.ptr:
+            getattr(lib(), self._free)(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Cell(_Handle):
+    _free = "mos_cell_free"
+
+
+class Rom(_Handle):
+    _free = "mos_rom_free"
+
+
+class Solution(_Handle):
+    _free = "mos_sol_free"
+    precision = MOS_FP64
+
+
+class Context:
+    """A library context on one device and torch stream.  Device memory goes
+    through torch's caching allocator unless ``torch_allocator`` is False."""
+
+    def __init__(self, device=0, stream=None, torch_allocator=True):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self._alloc = None
+        alloc_p = None
+        if torch_allocator:
+            dev, st = device, self.stream
+
+            def _a(size, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(size, dev, st)
+                except Exception:
+                    return None
+
+            def _f(ptr, user):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._alloc = Allocator(ALLOC_FN(_a), FREE_FN(_f), None)
+            alloc_p = ctypes.byref(self._alloc)
+        h = ctypes.c_void_p()
+        _check(lib().mos_ctx_create(device, ctypes.c_void_p(self.stream.cuda_stream), alloc_p, ctypes.byref(h)),
+               "mos_ctx_create")
+        self.ptr = h
+
+    def close(self):
+        if self.ptr:
+            lib().mos_ctx_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mos_build_cell(ctx, spec):
+    d = cell_desc(spec)
+    h = ctypes.c_void_p()
+    _check(lib().mos_build_cell(ctx.ptr, ctypes.byref(d), ctypes.byref(h)), "mos_build_cell")
+    return Cell(h, ctx)
+
+
+def mos_reduce(ctx, cell):
+    h = ctypes.c_void_p()
+    _check(lib().mos_reduce(ctx.ptr, cell.ptr, ctypes.byref(h)), "mos_reduce")
+    return Rom(h, ctx)
+
+
+def mos_solve_array(ctx, roms, nx_cells, ny_cells, cell_type, delta_T, clamp_bottom=True, clamp_top=False,
+                    prescribed_dofs=None, prescribed_values=None, mixed=False, rtol=0.0, max_iters=0):
+    ct = np.ascontiguousarray(cell_type, dtype=np.uint8)
+    if ct.size != nx_cells * ny_cells:
+        raise ValueError("cell_type must have nx_cells * ny_cells entries")
+    d = ArrayDesc()
+    d.nx_cells, d.ny_cells = int(nx_cells), int(ny_cells)
+    d.cell_type = ct.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    d.delta_T = float(delta_T)
+    d.bc_flags = (MOS_BC_CLAMP_BOTTOM if clamp_bottom else 0) | (MOS_BC_CLAMP_TOP if clamp_top else 0)
+    pd = pv = None
+    if prescribed_dofs is not None and len(prescribed_dofs):
+        pd = np.ascontiguousarray(prescribed_dofs, dtype=np.int64)
+        pv = np.ascontiguousarray(prescribed_values, dtype=np.float64)
+        if pd.shape != pv.shape:
+            raise ValueError("prescribed dofs and values differ in length")
+        d.n_prescribed = pd.size
+        d.prescribed_dof = pd.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        d.prescribed_value = pv.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.precision = MOS_MIXED if mixed else MOS_FP64
+    d.rtol, d.max_iters = float(rtol), int(max_iters)
+    arr = (ctypes.c_void_p * len(roms))(*[r.ptr.value for r in roms])
+    h = ctypes.c_void_p()
+    _check(lib().mos_solve_array(ctx.ptr, ctypes.byref(d), arr, len(roms), ctypes.byref(h)), "mos_solve_array")
+    s = Solution(h, ctx)
+    s.precision = d.precision
+    s.n_cells = nx_cells * ny_cells
+    s.n_elem = roms[0].query(MOS_Q_CELL_ELEMS)
+    s.roms = list(roms)
+    return s
+
+
+def mos_reconstruct(ctx, sol, vm=None, sigma6=None):
+    """Write von Mises and/or the six stress components into caller-owned
+    device tensors ([n_cells, n_elem] and [n_cells, n_elem, 6]); float64 for
+    an FP64 solution, float32 for a mixed one."""
+    torch = ctx.torch
+    want = torch.float32 if sol.precision == MOS_MIXED else torch.float64
+    flags = 0
+    for t, shape, flag in ((vm, (sol.n_cells, sol.n_elem), MOS_OUT_VM),
+                           (sigma6, (sol.n_cells, sol.n_elem, 6), MOS_OUT_SIGMA6)):
+        if t is None:
+            continue
+        if t.dtype != want or tuple(t.shape) != shape or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError(f"output must be a contiguous {want} device tensor of shape {shape}")
+        flags |= flag
+    _check(lib().mos_reconstruct(ctx.ptr, sol.ptr, flags, ctypes.c_void_p(vm.data_ptr() if vm is not None else 0),
+                                 ctypes.c_void_p(sigma6.data_ptr() if sigma6 is not None else 0)),
+           "mos_reconstruct")
+
+
+def mos_get_solution(sol):
+    n = sol.query(MOS_Q_GLOBAL_DOFS)
+    u = np.empty(n)
+    res = ctypes.c_double()
+    it = ctypes.c_int32()
+    _check(lib().mos_get_solution(sol.ptr, _ptr(u), ctypes.byref(res), ctypes.byref(it)), "mos_get_solution")
+    return u, res.value, it.value
+
+
+def mos_cell_export(cell):
+    n_dofs = cell.query(MOS_Q_CELL_DOFS)
+    nnz = cell.query(MOS_Q_CELL_NNZ)
+    n_elem = cell.query(MOS_Q_CELL_ELEMS)
+    indptr = np.empty(n_dofs + 1, dtype=np.int64)
+    indices = np.empty(nnz, dtype=np.int32)
+    data = np.empty(nnz)
+    b = np.empty(n_dofs)
+    mat = np.empty(n_elem, dtype=np.uint8)
+    _check(lib().mos_cell_export(cell.ptr, _ptr(indptr), _ptr(indices), _ptr(data), _ptr(b), _ptr(mat)),
+           "mos_cell_export")
+    return indptr, indices, data, b, mat
+
+
+def mos_rom_export(rom):
+    n = rom.query(MOS_Q_N)
+    n_dofs = rom.query(MOS_Q_CELL_DOFS)
+    phi = np.empty((n_dofs, n))
+    fT = np.empty(n_dofs)
+    Kr = np.empty((n, n))
+    br = np.empty(n)
+    _check(lib().mos_rom_export(rom.ptr, _ptr(phi), _ptr(fT), _ptr(Kr), _ptr(br)), "mos_rom_export")
+    return phi, fT, Kr, br
+
+
+def mos_array_layout(ctx, nx_cells, ny_cells, rom, pattern=False):
+    n_nodes = ctypes.c_int64()
+    _check(lib().mos_array_layout(ctx.ptr, nx_cells, ny_cells, rom.ptr, ctypes.byref(n_nodes), None, None, None,
+                                  None), "mos_array_layout")
+    nn = n_nodes.value
+    S = rom.query(MOS_Q_N) // 3
+    coords = np.empty((nn, 3))
+    conn = np.empty((nx_cells * ny_cells, S), dtype=np.int32)
+    indptr = indices = None
+    if pattern:
+        indptr = np.empty(3 * nn + 1, dtype=np.int64)
+        _check(lib().mos_array_layout(ctx.ptr, nx_cells, ny_cells, rom.ptr, ctypes.byref(n_nodes), None, None,
+                                      _ptr(indptr), None), "mos_array_layout")
+        indices = np.empty(int(indptr[-1]), dtype=np.int32)
+    _check(lib().mos_array_layout(ctx.ptr, nx_cells, ny_cells, rom.ptr, ctypes.byref(n_nodes), _ptr(coords),
+                                  _ptr(conn), _ptr(indptr), _ptr(indices)), "mos_array_layout")
+    return coords, conn, indptr, indices
