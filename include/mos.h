@@ -184,6 +184,21 @@ mos_status mos_array_layout(mos_ctx ctx, int32_t nx_cells, int32_t ny_cells, mos
                             int64_t *n_nodes, double *coords, int32_t *conn, int64_t *row_ptr,
                             int32_t *col);
 
+/* Kernel timing for measurement tools.  After mos_timing_start(ctx, k, every)
+ * every `every`-th launch (every >= 1) of kernel k by this context is
+ * bracketed by a pair of HIP events on the context stream; mos_timing_stop
+ * synchronises the stream and returns the number of timed launches and their
+ * summed duration in milliseconds, then stops timing.  One kernel at a time. */
+enum {
+    MOS_K_CELL_GEMM = 1,    /* element-by-element K_r GEMM of the PCG matvec */
+    MOS_K_ASSEMBLE = 2,     /* node-centric sum of cell products (+ p.Ap) */
+    MOS_K_PCG_UPDATE = 3,   /* PCG vector updates and reductions */
+    MOS_K_RECON = 4,        /* stress reconstruction GEMM + von Mises */
+    MOS_K_COUNT = 5
+};
+mos_status mos_timing_start(mos_ctx ctx, int kernel, int every);
+mos_status mos_timing_stop(mos_ctx ctx, int64_t *launches, double *total_ms);
+
 void mos_cell_free(mos_cell cell);
 void mos_rom_free(mos_rom rom);
 void mos_sol_free(mos_sol sol);

@@ -57,6 +57,25 @@ void DeviceArena::release() {
     bytes = 0;
 }
 
+bool timer_take(mos_ctx ctx, int id, hipEvent_t *e0, hipEvent_t *e1) {
+    *e0 = *e1 = nullptr;
+    if (!ctx || ctx->timed_kernel != id) return false;
+    if (ctx->timed_seen++ % ctx->timed_every) return false;
+    if (ctx->ev_used + 2 > ctx->ev.size()) {
+        hipEvent_t a = nullptr, b = nullptr;
+        if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        ctx->ev.push_back(a);
+        ctx->ev.push_back(b);
+    }
+    *e0 = ctx->ev[ctx->ev_used];
+    *e1 = ctx->ev[ctx->ev_used + 1];
+    ctx->ev_used += 2;
+    return true;
+}
+
 // ---------------------------------------------------------------------------
 // Abstract array mesh (numbering contract in mos.h)
 // ---------------------------------------------------------------------------
@@ -210,7 +229,39 @@ void mos_ctx_destroy(mos_ctx ctx) {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
     delete ctx;
+}
+
+mos_status mos_timing_start(mos_ctx ctx, int kernel, int every) {
+    if (!ctx || kernel < 1 || kernel >= MOS_K_COUNT || every < 1) {
+        set_error("invalid context, kernel id or sampling interval");
+        return MOS_EINVAL;
+    }
+    ctx->timed_kernel = kernel;
+    ctx->timed_every = every;
+    ctx->timed_seen = 0;
+    ctx->ev_used = 0;
+    return MOS_OK;
+}
+
+mos_status mos_timing_stop(mos_ctx ctx, int64_t *launches, double *total_ms) {
+    if (!ctx) {
+        set_error("invalid context");
+        return MOS_EINVAL;
+    }
+    MOS_HIP(hipStreamSynchronize(ctx->stream));
+    double total = 0.0;
+    for (size_t i = 0; i + 1 < ctx->ev_used; i += 2) {
+        float ms = 0.0f;
+        MOS_HIP(hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]));
+        total += ms;
+    }
+    if (launches) *launches = (int64_t)(ctx->ev_used / 2);
+    if (total_ms) *total_ms = total;
+    ctx->timed_kernel = 0;
+    ctx->ev_used = 0;
+    return MOS_OK;
 }
 
 mos_status mos_build_cell(mos_ctx ctx, const mos_cell_desc *desc, mos_cell *out) {

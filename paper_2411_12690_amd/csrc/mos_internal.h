@@ -3,6 +3,7 @@
 // translation unit provides.  Nothing here is part of the C ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
@@ -62,7 +63,29 @@ struct mos_ctx_s {
     bool user_alloc = false;
     // Small pinned host buffer for status words read back from the device.
     void *pinned = nullptr;
+    // Kernel timing (mos_timing_start / mos_timing_stop).
+    int timed_kernel = 0;
+    int timed_every = 1;          // time one launch in this many
+    int64_t timed_seen = 0;       // launches of the timed kernel so far
+    std::vector<hipEvent_t> ev;   // pairs (start, stop), reused
+    size_t ev_used = 0;
 };
+
+namespace mos {
+// When this launch of kernel `id` is sampled for timing, returns true and the
+// event pair the dispatch itself stamps (start and end of its execution).
+bool timer_take(mos_ctx ctx, int id, hipEvent_t *e0, hipEvent_t *e1);
+
+// Launch through hipExtLaunchKernelGGL so that sampled launches carry their
+// own execution timestamps; unsampled launches pass null events.
+template <typename F, typename... Args>
+inline void launch_timed(mos_ctx ctx, int id, F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t stream,
+                         Args... args) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    timer_take(ctx, id, &e0, &e1);
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, e0, e1, 0, args...);
+}
+}  // namespace mos
 
 struct mos_cell_s {
     uint32_t kind = mos::KIND_CELL;

@@ -110,11 +110,11 @@ mos_status reconstruct(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void 
     void *v = (outputs & MOS_OUT_VM) ? vm : nullptr;
     void *g = (outputs & MOS_OUT_SIGMA6) ? sigma6 : nullptr;
     if (s->precision == MOS_FP64)
-        hipLaunchKernelGGL(k_recon_f64<double>, grid, dim3(256), 0, st, tt, U, s->perm, s->n_pc, s->ldk, s->n_elem,
-                           s->delta_T, (double *)v, (double *)g);
+        launch_timed(ctx, MOS_K_RECON, k_recon_f64<double>, grid, dim3(256), 0, st, tt, (const double *)U,
+                     (const int32_t *)s->perm, s->n_pc, s->ldk, s->n_elem, s->delta_T, (double *)v, (double *)g);
     else
-        hipLaunchKernelGGL(k_recon_f64<float>, grid, dim3(256), 0, st, tt, U, s->perm, s->n_pc, s->ldk, s->n_elem,
-                           s->delta_T, (float *)v, (float *)g);
+        launch_timed(ctx, MOS_K_RECON, k_recon_f64<float>, grid, dim3(256), 0, st, tt, (const double *)U,
+                     (const int32_t *)s->perm, s->n_pc, s->ldk, s->n_elem, s->delta_T, (float *)v, (float *)g);
     MOS_LAUNCH_CHECK();
     MOS_HIP(hipStreamSynchronize(st));
     return MOS_OK;

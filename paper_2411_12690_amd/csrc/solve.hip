@@ -29,12 +29,15 @@ struct TypeTable {
     int n_types;
 };
 
+// Scalars of the pipelined PCG.  The GEMM kernel of iteration i (block 0)
+// reduces the dot-product partials, decides whether to stop, and publishes
+// the step (alpha, beta) that the update kernel of the same iteration
+// applies; gamma and alpha of iteration i are kept for iteration i+1.
 struct PcgState {
-    double rho[2];   // r.z, double-buffered by iteration parity
-    double pq;       // p.Ap of the current iteration
-    double rr;       // r.r after the last update
-    double tol2;     // stop when rr <= tol2
-    int iter, done, max_iter, pad;
+    double gamma_prev, alpha_prev;  // of the last applied iteration
+    double a_cur, b_cur;            // step of the current iteration
+    double rr;                      // ||r||^2 at the last check
+    int iter, done, pad0, pad1;
 };
 
 __device__ __forceinline__ int type_of_slot(const TypeTable &tt, int slot) {
@@ -123,14 +126,9 @@ __device__ __forceinline__ double sum_partials(const double *part, int n) {
     return sh;
 }
 
-// q[d] = sum over the cells around d's node of Y[3s+ci][slot]; in mode 0 the
-// lifted operator keeps constrained DoFs as identity (q = p there) and the
-// block partial of p.q is written; mode 1 is the raw operator.
+// Raw operator: q[d] = sum over the cells around d's node of Y[3s+ci][slot].
 template <class T>
-__global__ void k_assemble(const T *Y, const int32_t *inc, const uint8_t *cmask, const T *p, T *q, int64_t n_dofs,
-                           int n_pc, int mode, double *part, const PcgState *st) {
-    if (st && block_done(st)) return;
-    double acc = 0.0;
+__global__ void k_assemble(const T *Y, const int32_t *inc, T *q, int64_t n_dofs, int n_pc) {
     for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < n_dofs; d += (int64_t)gridDim.x * blockDim.x) {
         const int64_t node = d / 3;
         const int ci = (int)(d % 3);
@@ -140,104 +138,293 @@ __global__ void k_assemble(const T *Y, const int32_t *inc, const uint8_t *cmask,
             if (v < 0) break;
             s += Y[(size_t)(3 * (v & MAX_SURF) + ci) * n_pc + (v >> INC_SHIFT)];
         }
-        if (mode == 0) {
-            T pv = p[d];
-            T qv = cmask[d] ? pv : s;
-            q[d] = qv;
-            acc += (double)pv * (double)qv;
-        } else {
-            q[d] = s;
+        q[d] = s;
+    }
+}
+
+// Sum of the cell products around DoF d.
+template <class T>
+__device__ __forceinline__ T gather_sum(const T *Y, const int32_t *inc, int64_t d, int n_pc) {
+    const int64_t node = d / 3;
+    const int ci = (int)(d % 3);
+    T s = 0;
+    for (int e = 0; e < 4; ++e) {
+        int v = inc[node * 4 + e];
+        if (v < 0) break;
+        s += Y[(size_t)(3 * (v & MAX_SURF) + ci) * n_pc + (v >> INC_SHIFT)];
+    }
+    return s;
+}
+
+// Copy DoF d's value into every cell slot that holds it (cell-major layout
+// Mc[3s+ci][slot] read densely by the cell GEMM).
+template <class T>
+__device__ __forceinline__ void scatter_to_cells(T *Mc, const int32_t *inc, int64_t d, int n_pc, T v) {
+    const int64_t node = d / 3;
+    const int ci = (int)(d % 3);
+    for (int e = 0; e < 4; ++e) {
+        int iv = inc[node * 4 + e];
+        if (iv < 0) break;
+        Mc[(size_t)(3 * (iv & MAX_SURF) + ci) * n_pc + (iv >> INC_SHIFT)] = v;
+    }
+}
+
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c) {
+    __shared__ double sh[3][16];
+    for (int m = 32; m >= 1; m >>= 1) {
+        a += __shfl_xor(a, m);
+        b += __shfl_xor(b, m);
+        c += __shfl_xor(c, m);
+    }
+    const int w = threadIdx.x / 64, nw = blockDim.x / 64;
+    __syncthreads();
+    if (threadIdx.x % 64 == 0) {
+        sh[0][w] = a;
+        sh[1][w] = b;
+        sh[2][w] = c;
+    }
+    __syncthreads();
+    a = b = c = 0.0;
+    for (int i = 0; i < nw; ++i) {
+        a += sh[0][i];
+        b += sh[1][i];
+        c += sh[2][i];
+    }
+}
+
+// One wave: fixed-order sums of three partial arrays, result in every lane.
+__device__ __forceinline__ void wave_sum3(const double *pa, const double *pb, const double *pc, int n, double &a,
+                                          double &b, double &c) {
+    a = b = c = 0.0;
+    const int lane = threadIdx.x % 64;
+    for (int i = lane; i < n; i += 64) {
+        a += pa[i];
+        b += pb[i];
+        c += pc[i];
+    }
+    for (int m = 32; m >= 1; m >>= 1) {
+        a += __shfl_xor(a, m);
+        b += __shfl_xor(b, m);
+        c += __shfl_xor(c, m);
+    }
+}
+
+constexpr int GEMM_WAVES = 4;      // split-K ways of the cell GEMM
+constexpr int GEMM_MAX_STEPS = 16; // k-steps of 4 whose loads are issued together
+
+// Iteration `it` (it < 0: GEMM only), part 1.  Y[k][slot] = sum_j K_r(type)[k][j] Mc[j][slot] for
+// one 16 x 16 output tile per workgroup, K split over four waves and summed
+// in a fixed order through LDS; Mc is the cell-major copy of m = M^-1 w.
+// One extra block turns the partial sums of (r,u), (w,u), (r,r) into the stop
+// decision and the step (alpha, beta) of this iteration, in parallel with the
+// GEMM tiles.
+template <class T>
+__global__ __launch_bounds__(256) void k_ppcg_gemm(TypeTable tt, const T *Mc, T *Y, int ldk, int n_pc, PcgState *st,
+                                                   const double *pg, const double *pd, const double *pr, int nparts,
+                                                   double tol2, int it, int max_iter) {
+    typedef typename Mfma<T>::v4 v4;
+    __shared__ v4 red[GEMM_WAVES - 1][64];
+    __shared__ int done_flag;
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    if ((int)blockIdx.y == n_pc / 16) {
+        // The extra block row: block 0 does the scalar work of the iteration.
+        if (it < 0 || blockIdx.x != 0 || wave != 0) return;
+        const double g_prev = st->gamma_prev, a_prev = st->alpha_prev;
+        const int done = st->done;
+        double gamma, delta, rr;
+        wave_sum3(pg, pd, pr, nparts, gamma, delta, rr);
+        if (lane == 0 && !done) {
+            int stop = 0;
+            double alpha = 0.0, beta = 0.0;
+            if (rr <= tol2) {
+                stop = 1;
+            } else if (it >= max_iter) {
+                stop = 3;
+            } else {
+                if (it == 0) {
+                    alpha = gamma / delta;
+                } else {
+                    beta = gamma / g_prev;
+                    alpha = gamma / (delta - beta * gamma / a_prev);
+                }
+                if (!(alpha > 0.0) || !isfinite(alpha) || !isfinite(beta)) stop = 2;
+            }
+            st->rr = rr;
+            if (stop) {
+                st->done = stop;
+                st->iter = it;
+            } else {
+                st->a_cur = alpha;
+                st->b_cur = beta;
+                st->gamma_prev = gamma;
+                st->alpha_prev = alpha;
+                st->iter = it + 1;
+            }
         }
+        return;
     }
-    if (mode == 0) {
-        double b = block_sum(acc);
-        if (threadIdx.x == 0) part[blockIdx.x] = b;
+    const int rb = blockIdx.x, pc0 = blockIdx.y * 16;
+    const T *kr = static_cast<const T *>(tt.kr[type_of_slot(tt, pc0)]);
+    const int col = pc0 + lane % 16;
+    const int steps = ldk / (4 * GEMM_WAVES);
+    const int k_begin = wave * steps * 4;
+    const T *ap = kr + (size_t)(k_begin + lane / 16) * ldk + rb * 16 + lane % 16;
+    const T *bp = Mc + (size_t)(k_begin + lane / 16) * n_pc + col;
+    T a[GEMM_MAX_STEPS], b[GEMM_MAX_STEPS];
+    const int cnt0 = min(GEMM_MAX_STEPS, steps);
+    // First operands are requested before the stop flag is known, so both
+    // round trips overlap.
+#pragma unroll
+    for (int j = 0; j < GEMM_MAX_STEPS; ++j)
+        if (j < cnt0) {
+            a[j] = ap[(size_t)(4 * j) * ldk];
+            b[j] = bp[(size_t)(4 * j) * n_pc];
+        }
+    if (threadIdx.x == 0) done_flag = st->done;
+    __syncthreads();
+    if (done_flag) return;
+    v4 acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < GEMM_MAX_STEPS; ++j)
+        if (j < cnt0) acc = Mfma<T>::op(a[j], b[j], acc);
+    for (int s0 = GEMM_MAX_STEPS; s0 < steps; s0 += GEMM_MAX_STEPS) {
+        const int cnt = min(GEMM_MAX_STEPS, steps - s0);
+#pragma unroll
+        for (int j = 0; j < GEMM_MAX_STEPS; ++j)
+            if (j < cnt) {
+                a[j] = ap[(size_t)(4 * (s0 + j)) * ldk];
+                b[j] = bp[(size_t)(4 * (s0 + j)) * n_pc];
+            }
+#pragma unroll
+        for (int j = 0; j < GEMM_MAX_STEPS; ++j)
+            if (j < cnt) acc = Mfma<T>::op(a[j], b[j], acc);
+    }
+    if (wave > 0) red[wave - 1][lane] = acc;
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int w = 0; w < GEMM_WAVES - 1; ++w) acc += red[w][lane];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Y[(size_t)(rb * 16 + Mfma<T>::row(lane, q)) * n_pc + col] = acc[q];
     }
 }
 
+// Pipelined PCG (one fused reduction per iteration), start, part 1:
+// r = rhs, u = M^-1 r, x = z = q = s = p = 0, u copied to the cell layout.
 template <class T>
-__global__ void k_pcg_init(const T *rhs, T *x, T *r, T *z, T *p, const T *dinv, int64_t n, double *part_rz,
-                           double *part_rr) {
-    double rz = 0.0, rr = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        T rv = rhs[i];
-        T zv = dinv[i] * rv;
-        x[i] = 0;
-        r[i] = rv;
-        z[i] = zv;
-        p[i] = zv;
-        rz += (double)rv * (double)zv;
-        rr += (double)rv * (double)rv;
-    }
-    double a = block_sum(rz);
-    double b = block_sum(rr);
-    if (threadIdx.x == 0) {
-        part_rz[blockIdx.x] = a;
-        part_rr[blockIdx.x] = b;
+__global__ void k_ppcg_start(const T *rhs, const T *dinv, const int32_t *inc, T *x, T *r, T *u, T *z, T *q, T *s,
+                             T *p, T *Mc, int64_t n, int n_pc) {
+    for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x) {
+        T rv = rhs[d];
+        T uv = dinv[d] * rv;
+        x[d] = 0;
+        r[d] = rv;
+        u[d] = uv;
+        z[d] = 0;
+        q[d] = 0;
+        s[d] = 0;
+        p[d] = 0;
+        scatter_to_cells(Mc, inc, d, n_pc, uv);
     }
 }
 
-__global__ void k_pcg_init2(const double *part_rz, const double *part_rr, int nparts, PcgState *st, double tol2,
-                            int max_iter) {
-    double rz = sum_partials(part_rz, nparts);
-    double rr = sum_partials(part_rr, nparts);
-    if (threadIdx.x == 0) {
-        st->rho[0] = rz;
-        st->rho[1] = 0.0;
-        st->pq = 0.0;
-        st->rr = rr;
-        st->tol2 = tol2;
-        st->iter = 0;
-        st->max_iter = max_iter;
-        st->done = (rr <= tol2) ? 1 : 0;
-    }
-}
-
+// Start, part 2: w = A u (lifted: 0 on constrained DoFs), m = M^-1 w in the
+// cell layout, block partials of (r,u), (w,u), (r,r).
 template <class T>
-__global__ void k_pcg_update1(T *x, T *r, T *z, const T *p, const T *q, const T *dinv, int64_t n,
-                              const double *part_pq, int nparts, double *part_rz, double *part_rr, PcgState *st,
-                              int parity) {
-    if (block_done(st)) return;
-    const double pq = sum_partials(part_pq, nparts);
-    const double alpha = st->rho[parity] / pq;
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->pq = pq;
-    const T a = (T)alpha;
-    double rz = 0.0, rr = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        x[i] += a * p[i];
-        T rv = r[i] - a * q[i];
-        r[i] = rv;
-        T zv = dinv[i] * rv;
-        z[i] = zv;
-        rz += (double)rv * (double)zv;
-        rr += (double)rv * (double)rv;
+__global__ void k_ppcg_start2(const T *Y, const int32_t *inc, const uint8_t *cmask, const T *dinv, const T *r,
+                              const T *u, T *w, T *m, T *Mc, int64_t n, int n_pc, double *pg, double *pd, double *pr,
+                              PcgState *st) {
+    double g = 0.0, dl = 0.0, rr = 0.0;
+    for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < n; d += (int64_t)gridDim.x * blockDim.x) {
+        T sum = gather_sum(Y, inc, d, n_pc);
+        T wv = cmask[d] ? T(0) : sum;
+        T mv = dinv[d] * wv;
+        w[d] = wv;
+        m[d] = mv;
+        scatter_to_cells(Mc, inc, d, n_pc, mv);
+        double rv = (double)r[d], uv = (double)u[d];
+        g += rv * uv;
+        dl += (double)wv * uv;
+        rr += rv * rv;
     }
-    double s1 = block_sum(rz);
-    double s2 = block_sum(rr);
+    block_sum3(g, dl, rr);
     if (threadIdx.x == 0) {
-        part_rz[blockIdx.x] = s1;
-        part_rr[blockIdx.x] = s2;
+        pg[blockIdx.x] = g;
+        pd[blockIdx.x] = dl;
+        pr[blockIdx.x] = rr;
     }
-}
-
-template <class T>
-__global__ void k_pcg_update2(T *p, const T *z, int64_t n, const double *part_rz, const double *part_rr, int nparts,
-                              PcgState *st, int parity) {
-    if (block_done(st)) return;
-    const double rz = sum_partials(part_rz, nparts);
-    const double rr = sum_partials(part_rr, nparts);
-    const double beta = rz / st->rho[parity];
-    const T b = (T)beta;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = z[i] + b * p[i];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->rho[parity ^ 1] = rz;
-        st->rr = rr;
-        st->iter += 1;
-        if (!(st->pq > 0.0) || !isfinite(rz) || !isfinite(st->pq)) st->done = 2;
-        else if (rr <= st->tol2) st->done = 1;
-        else if (st->iter >= st->max_iter) st->done = 3;
+        st->iter = 0;
+        st->done = 0;
+        st->rr = 0.0;
     }
+}
+
+// Iteration `it`, part 2, per DoF: n = A m from the cell products, the eight
+// recurrences with the step published by part 1, m = M^-1 w copied to the
+// cell layout, and the block partials of the next (r,u), (w,u), (r,r).
+template <class T>
+__global__ void k_ppcg_step(const T *Y, const int32_t *inc, const uint8_t *cmask, const T *dinv, T *x, T *r, T *u,
+                            T *w, T *z, T *q, T *s, T *p, T *m, T *Mc, int64_t n, int n_pc, double *pg, double *pd,
+                            double *pr, const PcgState *st) {
+    __shared__ int done_flag;
+    __shared__ double step[2];
+    const int64_t d0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // The incidence of the first DoF is requested before the flag barrier.
+    int4 inc0 = make_int4(-1, -1, -1, -1);
+    if (d0 < n) inc0 = reinterpret_cast<const int4 *>(inc)[d0 / 3];
+    if (threadIdx.x == 0) {
+        done_flag = st->done;
+        step[0] = st->a_cur;
+        step[1] = st->b_cur;
+    }
+    __syncthreads();
+    if (done_flag) return;
+    const T a = (T)step[0], b = (T)step[1];
+    double g = 0.0, dl = 0.0, r2 = 0.0;
+    for (int64_t d = d0; d < n; d += (int64_t)gridDim.x * blockDim.x) {
+        const int ci = (int)(d % 3);
+        int4 iv = d == d0 ? inc0 : reinterpret_cast<const int4 *>(inc)[d / 3];
+        const int e4[4] = {iv.x, iv.y, iv.z, iv.w};
+        T sum = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (e4[e] >= 0) sum += Y[(size_t)(3 * (e4[e] & MAX_SURF) + ci) * n_pc + (e4[e] >> INC_SHIFT)];
+        T nv = cmask[d] ? T(0) : sum;
+        T zv = nv + b * z[d];
+        T qv = m[d] + b * q[d];
+        T sv = w[d] + b * s[d];
+        T pv = u[d] + b * p[d];
+        x[d] += a * pv;
+        T rv = r[d] - a * sv;
+        T uv = u[d] - a * qv;
+        T wv = w[d] - a * zv;
+        T mv = dinv[d] * wv;
+        z[d] = zv;
+        q[d] = qv;
+        s[d] = sv;
+        p[d] = pv;
+        r[d] = rv;
+        u[d] = uv;
+        w[d] = wv;
+        m[d] = mv;
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (e4[e] >= 0) Mc[(size_t)(3 * (e4[e] & MAX_SURF) + ci) * n_pc + (e4[e] >> INC_SHIFT)] = mv;
+        g += (double)rv * (double)uv;
+        dl += (double)wv * (double)uv;
+        r2 += (double)rv * (double)rv;
+    }
+    block_sum3(g, dl, r2);
+    if (threadIdx.x == 0) {
+        pg[blockIdx.x] = g;
+        pd[blockIdx.x] = dl;
+        pr[blockIdx.x] = r2;
+    }
+}
+
+__global__ void k_zero_words(uint32_t *p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
 }
 
 // b_raw[d] = dT * sum over the cells around d of b_r(type)[3s+ci].
@@ -323,19 +510,20 @@ struct Workspace {
     uint8_t *cmask = nullptr;
     double *g = nullptr, *b_raw = nullptr, *b_l = nullptr, *x = nullptr, *r64 = nullptr, *q64 = nullptr;
     double *Y64 = nullptr;
-    double *part = nullptr, *part2 = nullptr, *part3 = nullptr, *scal = nullptr;
+    double *part = nullptr, *pg = nullptr, *pd = nullptr, *pr = nullptr, *scal = nullptr;
     PcgState *st = nullptr;
-    // inner solver vectors (T = double or float)
-    void *xi = nullptr, *ri = nullptr, *zi = nullptr, *pi = nullptr, *qi = nullptr, *di = nullptr, *rhs = nullptr,
-         *Yi = nullptr;
+    // Inner solver (T = double or float): vectors and the cell-major copy.
+    void *v[11] = {};     // x r u w z q s p m dinv rhs
+    void *Mc = nullptr, *Yi = nullptr;
 };
+
+enum { VX, VR, VU, VW, VZ, VQ, VS, VP, VM, VDINV, VRHS, NVEC };
 
 template <class T>
 mos_status apply_raw(hipStream_t st, const Workspace &w, const TypeTable &tt, const T *v, T *Y, T *out) {
     hipLaunchKernelGGL(k_cell_gemm<T>, dim3(w.ldk / 16, w.n_pc / 16), dim3(64), 0, st, tt, v, w.gidx, Y, w.ldk, w.n_pc,
                        (const PcgState *)nullptr);
-    hipLaunchKernelGGL(k_assemble<T>, dim3(w.nblk), dim3(256), 0, st, Y, w.inc, w.cmask, v, out, w.n, w.n_pc, 1,
-                       (double *)nullptr, (const PcgState *)nullptr);
+    hipLaunchKernelGGL(k_assemble<T>, dim3(w.nblk), dim3(256), 0, st, Y, w.inc, out, w.n, w.n_pc);
     MOS_LAUNCH_CHECK();
     return MOS_OK;
 }
@@ -348,34 +536,42 @@ mos_status read_scalar(mos_ctx ctx, const double *dev, double *out) {
     return MOS_OK;
 }
 
-// Jacobi-PCG on the lifted operator for rhs (type T), solution in w.xi.
+// Pipelined Jacobi-PCG on the lifted operator for the rhs in w.v[VRHS]
+// (type T); the solution is left in w.v[VX].  Stops when the recursive
+// residual satisfies ||r|| <= rtol ||rhs||.
 template <class T>
 mos_status pcg(mos_ctx ctx, Workspace &w, const TypeTable &tt, double rtol, int max_iter, int *iters, int *done) {
     hipStream_t st = ctx->stream;
-    T *x = (T *)w.xi, *r = (T *)w.ri, *z = (T *)w.zi, *p = (T *)w.pi, *q = (T *)w.qi, *di = (T *)w.di,
-      *rhs = (T *)w.rhs, *Y = (T *)w.Yi;
-    hipLaunchKernelGGL(k_pcg_init<T>, dim3(w.nblk), dim3(256), 0, st, rhs, x, r, z, p, di, w.n, w.part2, w.part3);
-    // tol2 relative to the rhs norm: computed in init2 from rr of r0 = rhs.
-    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(64), 0, st, w.part3, w.nblk, w.scal);
+    T *V[NVEC];
+    for (int i = 0; i < NVEC; ++i) V[i] = static_cast<T *>(w.v[i]);
+    T *Mc = static_cast<T *>(w.Mc), *Y = static_cast<T *>(w.Yi);
+    const dim3 g_gemm(w.ldk / 16, w.n_pc / 16 + 1), g_vec(w.nblk), b_vec(256);
+    hipLaunchKernelGGL(k_ppcg_start<T>, g_vec, b_vec, 0, st, V[VRHS], V[VDINV], w.inc, V[VX], V[VR], V[VU], V[VZ],
+                       V[VQ], V[VS], V[VP], Mc, w.n, w.n_pc);
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, (uint32_t *)w.st, sizeof(PcgState) / 4);
+    // Y = K_r Mc(u) for w = A u: the GEMM alone (it = -1: no scalar work).
+    hipLaunchKernelGGL(k_ppcg_gemm<T>, g_gemm, dim3(64 * GEMM_WAVES), 0, st, tt, Mc, Y, w.ldk, w.n_pc, w.st, w.pg,
+                       w.pd, w.pr, 0, 0.0, -1, 0);
+    hipLaunchKernelGGL(k_ppcg_start2<T>, g_vec, b_vec, 0, st, Y, w.inc, w.cmask, V[VDINV], V[VR], V[VU], V[VW], V[VM],
+                       Mc, w.n, w.n_pc, w.pg, w.pd, w.pr, w.st);
+    MOS_LAUNCH_CHECK();
+    // tol2 is relative to ||rhs||^2 = the rr partials of the start kernel.
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(64), 0, st, w.pr, w.nblk, w.scal);
     MOS_LAUNCH_CHECK();
     double rr0 = 0.0;
     MOS_TRY(read_scalar(ctx, w.scal, &rr0));
-    hipLaunchKernelGGL(k_pcg_init2, dim3(1), dim3(64), 0, st, w.part2, w.part3, w.nblk, w.st, rtol * rtol * rr0,
-                       max_iter);
-    MOS_LAUNCH_CHECK();
+    const double tol2 = rtol * rtol * rr0;
     PcgState *hs = static_cast<PcgState *>(ctx->pinned);
     int it = 0, chunk = 8;
     while (true) {
         for (int j = 0; j < chunk; ++j, ++it) {
-            const int par = it & 1;
-            hipLaunchKernelGGL(k_cell_gemm<T>, dim3(w.ldk / 16, w.n_pc / 16), dim3(64), 0, st, tt, p, w.gidx, Y, w.ldk,
-                               w.n_pc, w.st);
-            hipLaunchKernelGGL(k_assemble<T>, dim3(w.nblk), dim3(256), 0, st, Y, w.inc, w.cmask, p, q, w.n, w.n_pc, 0,
-                               w.part, w.st);
-            hipLaunchKernelGGL(k_pcg_update1<T>, dim3(w.nblk), dim3(256), 0, st, x, r, z, p, q, di, w.n, w.part,
-                               w.nblk, w.part2, w.part3, w.st, par);
-            hipLaunchKernelGGL(k_pcg_update2<T>, dim3(w.nblk), dim3(256), 0, st, p, z, w.n, w.part2, w.part3, w.nblk,
-                               w.st, par);
+            launch_timed(ctx, MOS_K_CELL_GEMM, k_ppcg_gemm<T>, g_gemm, dim3(64 * GEMM_WAVES), 0, st, tt,
+                         (const T *)Mc, Y, w.ldk, w.n_pc, w.st, (const double *)w.pg, (const double *)w.pd,
+                         (const double *)w.pr, w.nblk, tol2, it, max_iter);
+            launch_timed(ctx, MOS_K_PCG_UPDATE, k_ppcg_step<T>, g_vec, b_vec, 0, st, (const T *)Y,
+                         (const int32_t *)w.inc, (const uint8_t *)w.cmask, (const T *)V[VDINV], V[VX], V[VR], V[VU],
+                         V[VW], V[VZ], V[VQ], V[VS], V[VP], V[VM], Mc, w.n, w.n_pc, w.pg, w.pd, w.pr,
+                         (const PcgState *)w.st);
         }
         MOS_LAUNCH_CHECK();
         MOS_HIP(hipMemcpyAsync(hs, w.st, sizeof(PcgState), hipMemcpyDeviceToHost, st));
@@ -512,21 +708,23 @@ mos_status solve_array(mos_ctx ctx, const mos_array_desc *d, const mos_rom *roms
     MOS_TRY(tmp.alloc_n(n_dofs, &w.q64));
     MOS_TRY(tmp.alloc_n((size_t)ldk * n_pc, &w.Y64));
     MOS_TRY(tmp.alloc_n(w.nblk, &w.part));
-    MOS_TRY(tmp.alloc_n(w.nblk, &w.part2));
-    MOS_TRY(tmp.alloc_n(w.nblk, &w.part3));
+    MOS_TRY(tmp.alloc_n(w.nblk, &w.pg));
+    MOS_TRY(tmp.alloc_n(w.nblk, &w.pd));
+    MOS_TRY(tmp.alloc_n(w.nblk, &w.pr));
     MOS_TRY(tmp.alloc_n(4, &w.scal));
     MOS_TRY(tmp.alloc(sizeof(PcgState), (void **)&w.st));
     w.x = s->u;
     const bool mixed = d->precision == MOS_MIXED;
     const size_t esz = mixed ? sizeof(float) : sizeof(double);
-    MOS_TRY(tmp.alloc(n_dofs * esz, &w.xi));
-    MOS_TRY(tmp.alloc(n_dofs * esz, &w.ri));
-    MOS_TRY(tmp.alloc(n_dofs * esz, &w.zi));
-    MOS_TRY(tmp.alloc(n_dofs * esz, &w.pi));
-    MOS_TRY(tmp.alloc(n_dofs * esz, &w.qi));
-    MOS_TRY(tmp.alloc(n_dofs * esz, &w.di));
-    MOS_TRY(tmp.alloc(n_dofs * esz, &w.rhs));
+    for (int i = 0; i < NVEC; ++i) MOS_TRY(tmp.alloc(n_dofs * esz, &w.v[i]));
+    MOS_TRY(tmp.alloc((size_t)ldk * n_pc * esz, &w.Mc));
     MOS_TRY(tmp.alloc((size_t)ldk * n_pc * esz, &w.Yi));
+    {
+        size_t words = (size_t)ldk * n_pc * esz / 4;
+        hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min<size_t>((words + 255) / 256, 4096)), dim3(256), 0, st,
+                           (uint32_t *)w.Mc, words);
+        MOS_LAUNCH_CHECK();
+    }
 
     MOS_HIP(hipMemcpyAsync(s->perm, perm.data(), perm.size() * 4, hipMemcpyHostToDevice, st));
     MOS_HIP(hipMemcpyAsync(s->conn, m.conn.data(), m.conn.size() * 4, hipMemcpyHostToDevice, st));
@@ -557,10 +755,10 @@ mos_status solve_array(mos_ctx ctx, const mos_array_desc *d, const mos_rom *roms
     MOS_TRY(read_scalar(ctx, w.scal, &bb));
     if (mixed)
         hipLaunchKernelGGL(k_diag<float>, dim3(ceil_div(n_dofs, 256)), dim3(256), 0, st, w.tt64, w.inc, w.cmask,
-                           (float *)w.di, n_dofs, ldk);
+                           (float *)w.v[VDINV], n_dofs, ldk);
     else
         hipLaunchKernelGGL(k_diag<double>, dim3(ceil_div(n_dofs, 256)), dim3(256), 0, st, w.tt64, w.inc, w.cmask,
-                           (double *)w.di, n_dofs, ldk);
+                           (double *)w.v[VDINV], n_dofs, ldk);
     MOS_LAUNCH_CHECK();
 
     const double rtol = d->rtol > 0 ? d->rtol : (mixed ? 1e-10 : 1e-12);
@@ -591,26 +789,29 @@ mos_status solve_array(mos_ctx ctx, const mos_array_desc *d, const mos_rom *roms
         const double rnorm = std::sqrt(rr);
         int iters = 0, done = 0;
         if (mixed) {
-            hipLaunchKernelGGL(k_scale_to<float>, dim3(w.nblk), dim3(256), 0, st, w.r64, (float *)w.rhs, 1.0 / rnorm,
-                               n_dofs);
+            hipLaunchKernelGGL(k_scale_to<float>, dim3(w.nblk), dim3(256), 0, st, w.r64, (float *)w.v[VRHS],
+                               1.0 / rnorm, n_dofs);
             MOS_LAUNCH_CHECK();
-            MOS_TRY(pcg<float>(ctx, w, w.tt32, 1e-5, max_iters - total_iters, &iters, &done));
-            hipLaunchKernelGGL(k_add_scaled<float>, dim3(w.nblk), dim3(256), 0, st, w.x, (const float *)w.xi, rnorm,
-                               n_dofs);
+            MOS_TRY(pcg<float>(ctx, w, w.tt32, 1e-4, max_iters - total_iters, &iters, &done));
+            hipLaunchKernelGGL(k_add_scaled<float>, dim3(w.nblk), dim3(256), 0, st, w.x, (const float *)w.v[VX],
+                               rnorm, n_dofs);
         } else {
-            hipLaunchKernelGGL(k_scale_to<double>, dim3(w.nblk), dim3(256), 0, st, w.r64, (double *)w.rhs, 1.0,
+            hipLaunchKernelGGL(k_scale_to<double>, dim3(w.nblk), dim3(256), 0, st, w.r64, (double *)w.v[VRHS], 1.0,
                                n_dofs);
             MOS_LAUNCH_CHECK();
             double tol_in = std::max(0.1 * rtol * bnorm / rnorm, 1e-15);
             MOS_TRY(pcg<double>(ctx, w, w.tt64, tol_in, max_iters - total_iters, &iters, &done));
-            hipLaunchKernelGGL(k_add_scaled<double>, dim3(w.nblk), dim3(256), 0, st, w.x, (const double *)w.xi, 1.0,
-                               n_dofs);
+            hipLaunchKernelGGL(k_add_scaled<double>, dim3(w.nblk), dim3(256), 0, st, w.x, (const double *)w.v[VX],
+                               1.0, n_dofs);
         }
         MOS_LAUNCH_CHECK();
         total_iters += iters;
         refines++;
-        if (done == 2) {
-            set_error("PCG breakdown (p.Ap <= 0 or non-finite) after %d iterations", total_iters);
+        // A breakdown after some progress only ends this correction sweep: the
+        // iterate up to the last completed step is kept and the FP64 residual
+        // of the next sweep decides.  Without progress the solve has failed.
+        if (done == 2 && iters == 0) {
+            set_error("PCG breakdown (p.Ap <= 0 or non-finite) at the start of sweep %d", refines);
             return MOS_ENOCONV;
         }
     }

@@ -22,7 +22,9 @@ MOS_OUT_VM, MOS_OUT_SIGMA6 = 1, 2
 
 EXPORTED = ("mos_ctx_create", "mos_ctx_destroy", "mos_build_cell", "mos_reduce", "mos_solve_array",
             "mos_reconstruct", "mos_get_solution", "mos_query", "mos_cell_export", "mos_rom_export",
-            "mos_array_layout", "mos_cell_free", "mos_rom_free", "mos_sol_free", "mos_last_error")
+            "mos_array_layout", "mos_timing_start", "mos_timing_stop", "mos_cell_free", "mos_rom_free",
+            "mos_sol_free", "mos_last_error")
+MOS_K_CELL_GEMM, MOS_K_ASSEMBLE, MOS_K_PCG_UPDATE, MOS_K_RECON = 1, 2, 3, 4
 
 
 class MosError(RuntimeError):
@@ -77,6 +79,8 @@ def _load():
         "mos_rom_export": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "mos_array_layout": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, vp, P(ctypes.c_int64), vp, vp,
                                             vp, vp]),
+        "mos_timing_start": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
+        "mos_timing_stop": (ctypes.c_int, [vp, P(ctypes.c_int64), P(ctypes.c_double)]),
         "mos_cell_free": (None, [vp]),
         "mos_rom_free": (None, [vp]),
         "mos_sol_free": (None, [vp]),
@@ -313,3 +317,15 @@ def mos_array_layout(ctx, nx_cells, ny_cells, rom, pattern=False):
     _check(lib().mos_array_layout(ctx.ptr, nx_cells, ny_cells, rom.ptr, ctypes.byref(n_nodes), _ptr(coords),
                                   _ptr(conn), _ptr(indptr), _ptr(indices)), "mos_array_layout")
     return coords, conn, indptr, indices
+
+
+def mos_timing_start(ctx, kernel, every=1):
+    _check(lib().mos_timing_start(ctx.ptr, kernel, every), "mos_timing_start")
+
+
+def mos_timing_stop(ctx):
+    """Returns (launches, total milliseconds) of the timed kernel."""
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(lib().mos_timing_stop(ctx.ptr, ctypes.byref(n), ctypes.byref(ms)), "mos_timing_stop")
+    return n.value, ms.value
