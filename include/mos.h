@@ -184,6 +184,45 @@ mos_status mos_array_layout(mos_ctx ctx, int32_t nx_cells, int32_t ny_cells, mos
                             int64_t *n_nodes, double *coords, int32_t *conn, int64_t *row_ptr,
                             int32_t *col);
 
+/* ---- Batched / served global stage ----------------------------------------
+ * An engine keeps device arenas for many array problems that share one set
+ * of ROMs (same pitch, height, mesh and interp) and one precision.  Problems
+ * are submitted at any time, admitted in arrival order when their DoFs and
+ * cell slots fit in the arenas (the device-memory budget), and advanced
+ * together: every mos_engine_progress call admits what fits, runs
+ * `iterations` PCG iterations of all admitted problems in shared launches,
+ * refines / retires problems whose inner solve stopped, and reconstructs
+ * retired problems into the buffers given at submission.  Per-problem
+ * reductions are segmented and in a fixed order, so a problem's result is the
+ * same alone or in any mix.  For callers that batch requests of different
+ * sizes (continuous batching). */
+typedef struct mos_engine_s *mos_engine;
+
+/* device_bytes: arena budget; a problem larger than the arenas is rejected
+ * with MOS_EINVAL at submission.  roms must outlive the engine. */
+mos_status mos_engine_create(mos_ctx ctx, const mos_rom *roms, int32_t n_roms, mos_precision precision,
+                             size_t device_bytes, mos_engine *out);
+/* Queue one problem (desc->precision must equal the engine's).  vm / sigma6:
+ * optional device outputs as for mos_reconstruct; u: optional device array of
+ * the problem's reduced DoFs for the solution.  Buffers must stay valid until
+ * the ticket completes. */
+mos_status mos_engine_submit(mos_engine e, const mos_array_desc *desc, void *vm, void *sigma6, double *u,
+                             int64_t *ticket);
+/* One round of admission, `iterations` PCG iterations and retirement.
+ * Tickets completed since the last call are written to completed[] (up to
+ * max_completed; the rest are reported by the next call). */
+mos_status mos_engine_progress(mos_engine e, int32_t iterations, int64_t *completed, int32_t max_completed,
+                               int32_t *n_completed);
+/* Outcome of a completed ticket (status MOS_OK or the failure code), its
+ * relative FP64 residual, PCG iterations and refinement sweeps; the ticket is
+ * forgotten afterwards.  MOS_EBUSY if it has not completed. */
+mos_status mos_engine_result(mos_engine e, int64_t ticket, int32_t *status, double *rel_residual, int32_t *iters,
+                             int32_t *sweeps);
+/* Problems admitted and queued, and the arena capacities. */
+mos_status mos_engine_stats(mos_engine e, int64_t *active, int64_t *queued, int64_t *capacity_dofs,
+                            int64_t *capacity_slots);
+void mos_engine_destroy(mos_engine e);
+
 /* Kernel timing for measurement tools.  After mos_timing_start(ctx, k, every)
  * every `every`-th launch (every >= 1) of kernel k by this context is
  * bracketed by a pair of HIP events on the context stream; mos_timing_stop

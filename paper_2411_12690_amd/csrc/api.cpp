@@ -7,8 +7,9 @@
 #include <new>
 #include <vector>
 
-#include "mos_internal.h"
+#include "engine.h"
 #include "mesh.h"
+#include "mos_internal.h"
 
 namespace mos {
 
@@ -364,6 +365,20 @@ static mos_status check_roms(const mos_rom *roms, int32_t n_roms) {
     return MOS_OK;
 }
 
+static mos_engine new_engine(mos_ctx ctx, const mos_rom *roms, int32_t n_roms, mos_precision precision) {
+    mos_engine e = new (std::nothrow) mos_engine_s();
+    if (!e) return nullptr;
+    e->ctx = ctx;
+    e->mem.ctx = ctx;
+    e->precision = precision;
+    e->roms.assign(roms, roms + n_roms);
+    e->ldk = roms[0]->ldk;
+    e->n = roms[0]->n;
+    e->n_elem = roms[0]->n_elem;
+    e->n_eblk = roms[0]->n_eblk;
+    return e;
+}
+
 mos_status mos_solve_array(mos_ctx ctx, const mos_array_desc *d, const mos_rom *roms, int32_t n_roms,
                            mos_sol *out) {
     if (!out) {
@@ -381,24 +396,27 @@ mos_status mos_solve_array(mos_ctx ctx, const mos_array_desc *d, const mos_rom *
             set_error("roms[%d] belongs to another context", t);
             return MOS_EINVAL;
         }
-    if (d->nx_cells < 1 || d->ny_cells < 1 || (int64_t)d->nx_cells * d->ny_cells > (1 << 22) || !d->cell_type) {
-        set_error("array size must be >= 1x1 and <= 4M cells, with a cell_type map");
+    if (d->precision != MOS_FP64 && d->precision != MOS_MIXED) {
+        set_error("invalid precision");
         return MOS_EINVAL;
     }
-    if (!std::isfinite(d->delta_T) || d->n_prescribed < 0 ||
-        (d->n_prescribed > 0 && (!d->prescribed_dof || !d->prescribed_value)) ||
-        (d->bc_flags & ~(uint32_t)(MOS_BC_CLAMP_BOTTOM | MOS_BC_CLAMP_TOP)) ||
-        (d->precision != MOS_FP64 && d->precision != MOS_MIXED) || d->rtol < 0 || d->max_iters < 0) {
-        set_error("invalid delta_T, constraints, precision, rtol or max_iters");
-        return MOS_EINVAL;
-    }
-    const int64_t n_cells = (int64_t)d->nx_cells * d->ny_cells;
-    for (int64_t c = 0; c < n_cells; ++c)
-        if (d->cell_type[c] >= n_roms) {
-            set_error("cell_type[%lld] = %d but only %d ROMs", (long long)c, d->cell_type[c], n_roms);
-            return MOS_EINVAL;
-        }
     MOS_HIP(hipSetDevice(ctx->device));
+    // A one-problem engine sized exactly for this array.
+    mos_engine e = new_engine(ctx, roms, n_roms, d->precision);
+    if (!e) {
+        set_error("out of host memory");
+        return MOS_ENOMEM;
+    }
+    struct EngineGuard {
+        mos_engine e;
+        ~EngineGuard() {
+            engine_free(e);
+            delete e;
+        }
+    } eg{e};
+    int64_t dofs = 0, slots = 0;
+    MOS_TRY(engine_problem_size(e, d, &dofs, &slots));
+    MOS_TRY(engine_alloc(e, dofs, slots));
     mos_sol s = new (std::nothrow) mos_sol_s();
     if (!s) {
         set_error("out of host memory");
@@ -406,13 +424,175 @@ mos_status mos_solve_array(mos_ctx ctx, const mos_array_desc *d, const mos_rom *
     }
     s->ctx = ctx;
     s->mem.ctx = ctx;
-    mos_status st = solve_array(ctx, d, roms, n_roms, s);
-    if (st != MOS_OK) {
-        mos_sol_free(s);
-        return st;
+    struct SolGuard {
+        mos_sol s;
+        bool keep = false;
+        ~SolGuard() {
+            if (!keep) mos_sol_free(s);
+        }
+    } sg{s};
+    const mos_cell_desc &cd = roms[0]->desc;
+    ArrayMesh m;
+    m.build(d->nx_cells, d->ny_cells, cd.interp[0], cd.interp[1], cd.interp[2]);
+    MOS_TRY(s->mem.alloc_n(3 * m.n_nodes, &s->u));
+    int64_t ticket = 0;
+    MOS_TRY(engine_submit(e, d, nullptr, nullptr, s->u, &ticket));
+    std::vector<int64_t> done;
+    while (e->finished.find(ticket) == e->finished.end()) MOS_TRY(engine_progress(e, 16, &done));
+    EngineProblem *P = e->finished[ticket];
+    if (P->status != MOS_OK) {
+        set_error("%s", P->error.c_str());
+        return P->status;
     }
+    // The solution handle keeps what mos_reconstruct needs.
+    s->precision = d->precision;
+    s->Nx = P->Nx;
+    s->Ny = P->Ny;
+    s->n_cells = (int)P->n_cells;
+    s->n = roms[0]->n;
+    s->n_surf = roms[0]->n_surf;
+    s->n_elem = roms[0]->n_elem;
+    s->ldk = roms[0]->ldk;
+    s->n_eblk = roms[0]->n_eblk;
+    s->n_nodes = P->n_nodes;
+    s->n_dofs = P->n_dofs;
+    s->delta_T = d->delta_T;
+    s->rel_residual = P->rel;
+    s->iters = P->iters;
+    s->refines = P->sweeps;
+    s->n_types = n_roms;
+    s->roms.assign(roms, roms + n_roms);
+    s->seg.resize(n_roms + 1);
+    for (int t = 0; t <= n_roms; ++t) s->seg[t] = P->seg[t] * 16;
+    s->n_pc = P->n_sb * 16;
+    const int S = s->n_surf, ldk = s->ldk, n = s->n;
+    std::vector<int32_t> gidx((size_t)ldk * s->n_pc, -1);
+    for (int sl = 0; sl < s->n_pc; ++sl) {
+        int32_t c = P->perm[sl];
+        if (c < 0) continue;
+        for (int k = 0; k < n; ++k) gidx[(size_t)k * s->n_pc + sl] = 3 * P->conn[(size_t)c * S + k / 3] + k % 3;
+    }
+    MOS_TRY(s->mem.alloc_n(s->n_pc, &s->perm));
+    MOS_TRY(s->mem.alloc_n(P->conn.size(), &s->conn));
+    MOS_TRY(s->mem.alloc_n(gidx.size(), &s->gidx));
+    hipStream_t st = ctx->stream;
+    MOS_HIP(hipMemcpyAsync(s->perm, P->perm.data(), P->perm.size() * 4, hipMemcpyHostToDevice, st));
+    MOS_HIP(hipMemcpyAsync(s->conn, P->conn.data(), P->conn.size() * 4, hipMemcpyHostToDevice, st));
+    MOS_HIP(hipMemcpyAsync(s->gidx, gidx.data(), gidx.size() * 4, hipMemcpyHostToDevice, st));
+    MOS_HIP(hipStreamSynchronize(st));
+    sg.keep = true;
     *out = s;
     return MOS_OK;
+}
+
+mos_status mos_engine_create(mos_ctx ctx, const mos_rom *roms, int32_t n_roms, mos_precision precision,
+                             size_t device_bytes, mos_engine *out) {
+    if (!out) {
+        set_error("out is NULL");
+        return MOS_EINVAL;
+    }
+    *out = nullptr;
+    if (!ctx || (precision != MOS_FP64 && precision != MOS_MIXED)) {
+        set_error("invalid context or precision");
+        return MOS_EINVAL;
+    }
+    MOS_TRY(check_roms(roms, n_roms));
+    MOS_HIP(hipSetDevice(ctx->device));
+    mos_engine e = new_engine(ctx, roms, n_roms, precision);
+    if (!e) {
+        set_error("out of host memory");
+        return MOS_ENOMEM;
+    }
+    // Split the budget between DoF arrays and cell slots (~100 DoFs per cell).
+    const double w = precision == MOS_MIXED ? 4.0 : 8.0;
+    const double per_dof = 11 * w + 5 * 8 + 1 + 16.0 / 3 + 4 * 8.0 / 256 + 4.0 / 256;
+    const double per_slot = e->ldk * (2 * w + 16) + 4 + 8.0 / 16;
+    const double units = (double)device_bytes / (100 * per_dof + per_slot);
+    const int64_t dofs = (int64_t)(units * 100), slots = (int64_t)units;
+    if (dofs < 768 || slots < 16) {
+        delete e;
+        set_error("device budget of %zu bytes is too small for an engine", device_bytes);
+        return MOS_EINVAL;
+    }
+    mos_status s = engine_alloc(e, dofs, slots);
+    if (s != MOS_OK) {
+        engine_free(e);
+        delete e;
+        return s;
+    }
+    *out = e;
+    return MOS_OK;
+}
+
+mos_status mos_engine_submit(mos_engine e, const mos_array_desc *desc, void *vm, void *sigma6, double *u,
+                             int64_t *ticket) {
+    if (!e || !desc || !ticket) {
+        set_error("engine, descriptor or ticket is NULL");
+        return MOS_EINVAL;
+    }
+    *ticket = 0;
+    return engine_submit(e, desc, vm, sigma6, u, ticket);
+}
+
+mos_status mos_engine_progress(mos_engine e, int32_t iterations, int64_t *completed, int32_t max_completed,
+                               int32_t *n_completed) {
+    if (!e || iterations < 1 || max_completed < 0 || (max_completed > 0 && !completed)) {
+        set_error("invalid engine or arguments");
+        return MOS_EINVAL;
+    }
+    MOS_HIP(hipSetDevice(e->ctx->device));
+    std::vector<int64_t> done;
+    mos_status s = engine_progress(e, iterations, &done);
+    e->completed_unreported.insert(e->completed_unreported.end(), done.begin(), done.end());
+    int32_t k = 0;
+    while (k < max_completed && k < (int32_t)e->completed_unreported.size()) {
+        completed[k] = e->completed_unreported[k];
+        ++k;
+    }
+    e->completed_unreported.erase(e->completed_unreported.begin(), e->completed_unreported.begin() + k);
+    if (n_completed) *n_completed = k;
+    return s;
+}
+
+mos_status mos_engine_result(mos_engine e, int64_t ticket, int32_t *status, double *rel_residual, int32_t *iters,
+                             int32_t *sweeps) {
+    if (!e) {
+        set_error("invalid engine");
+        return MOS_EINVAL;
+    }
+    auto it = e->finished.find(ticket);
+    if (it == e->finished.end()) {
+        set_error("ticket %lld has not completed", (long long)ticket);
+        return MOS_EBUSY;
+    }
+    EngineProblem *P = it->second;
+    if (status) *status = P->status;
+    if (rel_residual) *rel_residual = P->rel;
+    if (iters) *iters = P->iters;
+    if (sweeps) *sweeps = P->sweeps;
+    if (P->status != MOS_OK) set_error("%s", P->error.c_str());
+    delete P;
+    e->finished.erase(it);
+    return MOS_OK;
+}
+
+mos_status mos_engine_stats(mos_engine e, int64_t *active, int64_t *queued, int64_t *capacity_dofs,
+                            int64_t *capacity_slots) {
+    if (!e) {
+        set_error("invalid engine");
+        return MOS_EINVAL;
+    }
+    if (active) *active = (int64_t)e->active.size();
+    if (queued) *queued = (int64_t)e->queue.size();
+    if (capacity_dofs) *capacity_dofs = (int64_t)e->cap_blk * 256;
+    if (capacity_slots) *capacity_slots = (int64_t)e->cap_sb * 16;
+    return MOS_OK;
+}
+
+void mos_engine_destroy(mos_engine e) {
+    if (!e) return;
+    engine_free(e);
+    delete e;
 }
 
 mos_status mos_reconstruct(mos_ctx ctx, mos_sol sol, uint32_t outputs, void *vm, void *sigma6) {

@@ -1,0 +1,112 @@
+// Batched global-stage engine: types shared by engine.hip and api.cpp.
+#pragma once
+
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "mos_internal.h"
+
+namespace mos {
+
+constexpr int MAX_PROBS = 1024;  // problems resident in one engine at a time
+
+// Per-problem PCG scalars in device memory.  Written by the problem's scalar
+// wave (iteration launches) or by single-thread set-up kernels; read by the
+// batch kernels and, between chunks, by the host.
+struct ProbState {
+    double gamma_prev, alpha_prev;  // (r,u) and step of the last applied iteration
+    double a_cur, b_cur;            // step of the current iteration
+    double rr;                      // ||r||^2 at the last check
+    double tol2, rtol2;             // stop threshold and its relative form
+    int it, done, active, max_iter; // iterations of this sweep; stop code; iterating; cap
+    int blk_begin, blk_end;         // the problem's DoF blocks (partial sums)
+    int pad0, pad1;
+};
+
+enum { VX, VR, VU, VW, VZ, VQ, VS, VP, VM, VDINV, VRHS, NVEC };
+
+struct EngineProblem;
+
+// First-fit allocator of block ranges (host side).
+struct RangeAlloc {
+    int cap = 0, high = 0;
+    std::map<int, int> free_;  // begin -> length
+    void init(int c);
+    int take(int n);
+    void give(int b, int n);
+};
+
+}  // namespace mos
+
+struct mos_engine_s {
+    uint32_t kind = 0x21474e45u;
+    mos_ctx ctx = nullptr;
+    mos_precision precision = MOS_FP64;
+    std::vector<mos_rom> roms;
+    int ldk = 0, n = 0, n_elem = 0, n_eblk = 0;
+    int cap_blk = 0, cap_sb = 0, ld_slots = 0;
+    mos::DeviceArena mem;
+    // device arrays
+    void *v[mos::NVEC] = {};                  // inner vectors (double or float)
+    void *Mc = nullptr, *Yi = nullptr;        // inner cell layouts [ldk][ld_slots]
+    double *Mc64 = nullptr, *Y64 = nullptr;   // FP64 cell layouts
+    double *x64 = nullptr, *b_raw = nullptr, *g = nullptr, *r64 = nullptr, *q64 = nullptr;
+    uint8_t *cmask = nullptr;
+    int32_t *inc = nullptr;                   // [dofs/3][4]
+    int32_t *blk_prob = nullptr;              // [cap_blk]
+    double *pg = nullptr, *pd = nullptr, *pr = nullptr, *pr64 = nullptr;  // [cap_blk]
+    int32_t *sb_rom = nullptr, *sb_prob = nullptr;  // [cap_sb]
+    int32_t *perm = nullptr;                  // [ld_slots]
+    mos::ProbState *ps = nullptr;             // [MAX_PROBS]
+    double *res2 = nullptr, *bb2 = nullptr;   // [MAX_PROBS]
+    double *scale = nullptr;                  // [2*MAX_PROBS] inner rhs scale, correction scale
+    double *scale_host = nullptr;             // pinned staging of `scale`
+    void **kr64_tab = nullptr, **kr32_tab = nullptr;
+    double **br_tab = nullptr, **psi_tab = nullptr, **sigt_tab = nullptr;
+    // host state
+    mos::RangeAlloc blk, sbs, pids;
+    int64_t next_ticket = 0;
+    std::deque<mos::EngineProblem *> queue;
+    std::vector<mos::EngineProblem *> active;
+    std::map<int64_t, mos::EngineProblem *> finished;
+    std::vector<int64_t> completed_unreported;
+};
+
+namespace mos {
+
+// Host description of one problem in an engine.
+struct EngineProblem {
+    int64_t ticket = 0;
+    int pid = -1;
+    int Nx = 0, Ny = 0;
+    int64_t n_cells = 0, n_nodes = 0, n_dofs = 0;
+    int blk_begin = 0, n_blk = 0;
+    int sb_begin = 0, n_sb = 0;
+    std::vector<int> seg;         // per ROM: first slot block within the problem (n_roms+1)
+    std::vector<int32_t> perm;    // [n_sb*16] cell id per slot, -1 pad
+    std::vector<int32_t> conn;    // [n_cells][S]
+    std::vector<int32_t> inc;     // [n_blk*256/3][4], problem-local slots
+    std::vector<uint8_t> cmask;   // [n_blk*256]
+    std::vector<double> g;        // [n_blk*256]
+    double dT = 0.0, rtol = 0.0;
+    int max_iters = 0, iters = 0, sweeps = 0;
+    double rel = 1.0;
+    int state = 0;                // 0 queued, 1 iterating, 2 converged, 3 failed
+    mos_status status = MOS_OK;
+    std::string error;
+    void *vm = nullptr, *sig6 = nullptr;
+    double *u_out = nullptr;
+};
+
+mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots);
+mos_status engine_submit(mos_engine e, const mos_array_desc *d, void *vm, void *sig6, double *u_out,
+                         int64_t *ticket);
+mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *completed);
+void engine_free(mos_engine e);
+// Capacity (DoFs, slots) one problem needs, for sizing an engine exactly.
+mos_status engine_problem_size(mos_engine e, const mos_array_desc *d, int64_t *dofs, int64_t *slots);
+
+}  // namespace mos

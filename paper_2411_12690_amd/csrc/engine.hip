@@ -1,0 +1,1097 @@
+// Global stage for many arrays at once (Sec. 4.3-4.4, eq. 20).
+//
+// An engine owns capacity-sized device arenas.  Every admitted problem (one
+// array: its own size, cell types, dT and constraints) gets a block-aligned
+// range of DoFs (blocks of 256) and a range of cell slots (blocks of 16,
+// one cell type per slot block) and keeps them for its lifetime.  The reduced
+// operator is applied element by element: a per-slot-block GEMM with the
+// shared K_r of the block's cell type (MFMA), then a node-centric sum over the
+// <= 4 cells around each DoF in ascending cell order.  Pipelined Jacobi-PCG
+// (one fused reduction per iteration) advances all iterating problems with
+// two batch-wide launches per iteration; the extra blocks of the GEMM launch
+// reduce each problem's dot-product partials in a fixed order and publish its
+// step, so a problem's result does not depend on what else is in the batch.
+// Between iteration chunks the host admits queued problems, checks the FP64
+// true residual of problems whose inner solve stopped (iterative refinement:
+// FP64 inner solves for MOS_FP64, FP32 for MOS_MIXED), restarts or retires
+// them, and reconstructs finished ones.
+#include <algorithm>
+#include <cmath>
+#include <deque>
+#include <map>
+#include <vector>
+
+#include "engine.h"
+#include "mesh.h"
+#include "mos_internal.h"
+
+namespace mos {
+namespace {
+
+constexpr int DB = 256;       // DoFs per DoF block
+constexpr int DOF_ALIGN = 3 * DB;
+
+template <class T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // Output register q of lane l holds row l/16 + 4q, column l%16.
+    static __device__ __forceinline__ int row(int lane, int q) { return lane / 16 + 4 * q; }
+};
+template <>
+struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // Output register q of lane l holds row 4(l/16) + q, column l%16.
+    static __device__ __forceinline__ int row(int lane, int q) { return 4 * (lane / 16) + q; }
+};
+
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c) {
+    __shared__ double sh[3][16];
+    for (int m = 32; m >= 1; m >>= 1) {
+        a += __shfl_xor(a, m);
+        b += __shfl_xor(b, m);
+        c += __shfl_xor(c, m);
+    }
+    const int w = threadIdx.x / 64, nw = blockDim.x / 64;
+    __syncthreads();
+    if (threadIdx.x % 64 == 0) {
+        sh[0][w] = a;
+        sh[1][w] = b;
+        sh[2][w] = c;
+    }
+    __syncthreads();
+    a = b = c = 0.0;
+    for (int i = 0; i < nw; ++i) {
+        a += sh[0][i];
+        b += sh[1][i];
+        c += sh[2][i];
+    }
+}
+
+// Fixed-order sums over partial[begin, end) of up to three arrays; every lane
+// of the calling wave gets the result.
+__device__ __forceinline__ void wave_sum3(const double *pa, const double *pb, const double *pc, int begin, int end,
+                                          double &a, double &b, double &c) {
+    a = b = c = 0.0;
+    const int lane = threadIdx.x % 64;
+    for (int i = begin + lane; i < end; i += 64) {
+        a += pa[i];
+        b += pb[i];
+        c += pc[i];
+    }
+    for (int m = 32; m >= 1; m >>= 1) {
+        a += __shfl_xor(a, m);
+        b += __shfl_xor(b, m);
+        c += __shfl_xor(c, m);
+    }
+}
+
+constexpr int GEMM_WAVES = 4;       // split-K ways of the cell GEMM
+constexpr int GEMM_MAX_STEPS = 16;  // k-steps of 4 whose loads are issued together
+
+// Y[k][slot] = sum_j K_r[j][k] Mc[j][slot] for one 16 x 16 tile per workgroup
+// (K_r symmetric), K split over four waves summed in a fixed order through
+// LDS.  Slot blocks [sb_base, sb_base + n_sb); with `gate` the tile is skipped
+// unless its problem is iterating.  Extra block rows beyond n_sb (iteration
+// launches only) run one wave per problem: the step of iteration ps[p].it.
+template <class T>
+__global__ __launch_bounds__(256) void k_bgemm(const void *const *kr_tab, const int32_t *sb_rom, const int32_t *sb_prob,
+                                               const T *Mc, T *Y, int ldk, int ld_slots, int sb_base, int n_sb,
+                                               int gate, ProbState *ps, int n_probs, const double *pg,
+                                               const double *pd, const double *pr) {
+    typedef typename Mfma<T>::v4 v4;
+    __shared__ v4 red[GEMM_WAVES - 1][64];
+    __shared__ int skip;
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    if ((int)blockIdx.y >= n_sb) {
+        if (blockIdx.x != 0) return;
+        const int p = ((int)blockIdx.y - n_sb) * GEMM_WAVES + wave;
+        if (p >= n_probs) return;
+        ProbState &S = ps[p];
+        if (!S.active || S.done) return;
+        const int it = S.it;
+        const double g_prev = S.gamma_prev, a_prev = S.alpha_prev;
+        double gamma, delta, rr;
+        wave_sum3(pg, pd, pr, S.blk_begin, S.blk_end, gamma, delta, rr);
+        if (lane == 0) {
+            if (it == 0) S.tol2 = S.rtol2 * rr;
+            int stop = 0;
+            double alpha = 0.0, beta = 0.0;
+            if (rr <= S.tol2) {
+                stop = 1;
+            } else if (it >= S.max_iter) {
+                stop = 3;
+            } else {
+                if (it == 0) {
+                    alpha = gamma / delta;
+                } else {
+                    beta = gamma / g_prev;
+                    alpha = gamma / (delta - beta * gamma / a_prev);
+                }
+                if (!(alpha > 0.0) || !isfinite(alpha) || !isfinite(beta)) stop = 2;
+            }
+            S.rr = rr;
+            if (stop) {
+                S.done = stop;
+            } else {
+                S.a_cur = alpha;
+                S.b_cur = beta;
+                S.gamma_prev = gamma;
+                S.alpha_prev = alpha;
+                S.it = it + 1;
+            }
+        }
+        return;
+    }
+    const int sb = sb_base + (int)blockIdx.y;
+    const int rom = sb_rom[sb];
+    const int rb = blockIdx.x, pc0 = sb * 16;
+    const int col = pc0 + lane % 16;
+    const int steps = ldk / (4 * GEMM_WAVES);
+    const int k_begin = wave * steps * 4;
+    if (threadIdx.x == 0) {
+        int sk = rom < 0;
+        if (!sk && gate) {
+            const ProbState &S = ps[sb_prob[sb]];
+            sk = !S.active || S.done;
+        }
+        skip = sk;
+    }
+    __syncthreads();
+    if (skip) return;
+    const T *kr = static_cast<const T *>(kr_tab[rom]);
+    const T *ap = kr + (size_t)(k_begin + lane / 16) * ldk + rb * 16 + lane % 16;
+    const T *bp = Mc + (size_t)(k_begin + lane / 16) * ld_slots + col;
+    v4 acc = {0, 0, 0, 0};
+    for (int s0 = 0; s0 < steps; s0 += GEMM_MAX_STEPS) {
+        const int cnt = min(GEMM_MAX_STEPS, steps - s0);
+        T a[GEMM_MAX_STEPS], b[GEMM_MAX_STEPS];
+#pragma unroll
+        for (int j = 0; j < GEMM_MAX_STEPS; ++j)
+            if (j < cnt) {
+                a[j] = ap[(size_t)(4 * (s0 + j)) * ldk];
+                b[j] = bp[(size_t)(4 * (s0 + j)) * ld_slots];
+            }
+#pragma unroll
+        for (int j = 0; j < GEMM_MAX_STEPS; ++j)
+            if (j < cnt) acc = Mfma<T>::op(a[j], b[j], acc);
+    }
+    if (wave > 0) red[wave - 1][lane] = acc;
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int w = 0; w < GEMM_WAVES - 1; ++w) acc += red[w][lane];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Y[(size_t)(rb * 16 + Mfma<T>::row(lane, q)) * ld_slots + col] = acc[q];
+    }
+}
+
+// Incidence of DoF d: up to four packed (slot, surface node) of the cells
+// around its node, ascending cell order, -1 padded.
+__device__ __forceinline__ int4 incidence(const int32_t *inc, int64_t d) {
+    return reinterpret_cast<const int4 *>(inc)[d / 3];
+}
+
+template <class T>
+__device__ __forceinline__ T cell_sum(const T *Y, int4 iv, int ci, int ld_slots) {
+    const int e4[4] = {iv.x, iv.y, iv.z, iv.w};
+    T s = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if (e4[e] >= 0) s += Y[(size_t)(3 * (e4[e] & MAX_SURF) + ci) * ld_slots + (e4[e] >> INC_SHIFT)];
+    return s;
+}
+
+template <class T>
+__device__ __forceinline__ void cell_scatter(T *Mc, int4 iv, int ci, int ld_slots, T v) {
+    const int e4[4] = {iv.x, iv.y, iv.z, iv.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if (e4[e] >= 0) Mc[(size_t)(3 * (e4[e] & MAX_SURF) + ci) * ld_slots + (e4[e] >> INC_SHIFT)] = v;
+}
+
+// Copy a DoF vector into the cell-major layout, DoFs [d0, d1).
+template <class S, class T>
+__global__ void k_scatter(const S *v, const int32_t *inc, T *Mc, int64_t d0, int64_t d1, int ld_slots) {
+    const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= d1) return;
+    cell_scatter(Mc, incidence(inc, d), (int)(d % 3), ld_slots, (T)v[d]);
+}
+
+// out = (raw operator applied to the scattered vector), DoFs [d0, d1).
+template <class T>
+__global__ void k_assemble_raw(const T *Y, const int32_t *inc, T *out, int64_t d0, int64_t d1, int ld_slots) {
+    const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= d1) return;
+    out[d] = cell_sum(Y, incidence(inc, d), (int)(d % 3), ld_slots);
+}
+
+// b_raw[d] = dT * sum over the cells around d of b_r(type)[3s+ci].
+__global__ void k_brhs(const double *const *br_tab, const int32_t *sb_rom, const int32_t *inc, double dT, double *b,
+                       int64_t d0, int64_t d1) {
+    const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= d1) return;
+    const int4 iv = incidence(inc, d);
+    const int e4[4] = {iv.x, iv.y, iv.z, iv.w};
+    const int ci = (int)(d % 3);
+    double s = 0.0;
+    for (int e = 0; e < 4; ++e)
+        if (e4[e] >= 0) s += br_tab[sb_rom[(e4[e] >> INC_SHIFT) / 16]][3 * (e4[e] & MAX_SURF) + ci];
+    b[d] = dT * s;
+}
+
+template <class T>
+__global__ void k_bdiag(const void *const *kr64_tab, const int32_t *sb_rom, const int32_t *inc, const uint8_t *cmask,
+                        T *dinv, int64_t d0, int64_t d1, int ldk) {
+    const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= d1) return;
+    const int4 iv = incidence(inc, d);
+    const int e4[4] = {iv.x, iv.y, iv.z, iv.w};
+    const int ci = (int)(d % 3);
+    double s = 0.0;
+    for (int e = 0; e < 4; ++e)
+        if (e4[e] >= 0) {
+            const int k = 3 * (e4[e] & MAX_SURF) + ci;
+            s += static_cast<const double *>(kr64_tab[sb_rom[(e4[e] >> INC_SHIFT) / 16]])[(size_t)k * ldk + k];
+        }
+    dinv[d] = (cmask[d] || s == 0.0) ? T(1) : T(1.0 / s);
+}
+
+// Partials of ||b_l||^2 with the lifted rhs b_l = g (constrained), b - A g (free).
+__global__ void k_blift_norm(const double *b_raw, const double *ag, const double *g, const uint8_t *cmask,
+                             double *part, int64_t d0) {
+    const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double v = cmask[d] ? g[d] : b_raw[d] - ag[d];
+    double a = v * v, b = 0.0, c = 0.0;
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) part[d0 / DB + blockIdx.x] = a;
+}
+
+// True residual of the lifted system (0 on constrained DoFs), its partials.
+__global__ void k_bresidual(const double *b_raw, const double *ax, const uint8_t *cmask, double *r, double *part,
+                            int64_t d0) {
+    const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double v = cmask[d] ? 0.0 : b_raw[d] - ax[d];
+    r[d] = v;
+    double a = v * v, b = 0.0, c = 0.0;
+    block_sum3(a, b, c);
+    if (threadIdx.x == 0) part[d0 / DB + blockIdx.x] = a;
+}
+
+// dst[p] = fixed-order sum of part[begin, end).
+__global__ void k_reduce_range(const double *part, int begin, int end, double *dst) {
+    double a, b, c;
+    wave_sum3(part, part, part, begin, end, a, b, c);
+    if (threadIdx.x == 0) *dst = a;
+}
+
+template <class T>
+__global__ void k_to_inner(const double *r64, T *rhs, const double *scale_of, int64_t d0) {
+    const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    rhs[d] = (T)(r64[d] * *scale_of);
+}
+
+template <class T>
+__global__ void k_add_inner(double *x, const T *dx, const double *scale_of, int64_t d0) {
+    const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    x[d] += *scale_of * (double)dx[d];
+}
+
+__global__ void k_prob_start(ProbState *ps, int p, int blk_begin, int blk_end, double rtol2, int max_iter) {
+    ProbState &S = ps[p];
+    S.gamma_prev = S.alpha_prev = S.a_cur = S.b_cur = S.rr = S.tol2 = 0.0;
+    S.rtol2 = rtol2;
+    S.it = 0;
+    S.done = 0;
+    S.active = 1;
+    S.max_iter = max_iter;
+    S.blk_begin = blk_begin;
+    S.blk_end = blk_end;
+}
+
+__global__ void k_prob_stop(ProbState *ps, int p) { ps[p].active = 0; }
+
+// Inner solve start, part 1 (DoFs [d0, d0 + 256*gridDim)): r = rhs,
+// u = M^-1 r, x = z = q = s = p = 0, u copied to the cell layout.
+template <class T>
+__global__ void k_bstart(const T *rhs, const T *dinv, const int32_t *inc, T *x, T *r, T *u, T *z, T *q, T *s, T *p,
+                         T *Mc, int64_t d0, int ld_slots) {
+    const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const T rv = rhs[d];
+    const T uv = dinv[d] * rv;
+    x[d] = 0;
+    r[d] = rv;
+    u[d] = uv;
+    z[d] = 0;
+    q[d] = 0;
+    s[d] = 0;
+    p[d] = 0;
+    cell_scatter(Mc, incidence(inc, d), (int)(d % 3), ld_slots, uv);
+}
+
+// Part 2: w = A u (0 on constrained DoFs), m = M^-1 w to the cell layout,
+// partials of (r,u), (w,u), (r,r) for iteration 0.
+template <class T>
+__global__ void k_bstart2(const T *Y, const int32_t *inc, const uint8_t *cmask, const T *dinv, const T *r,
+                          const T *u, T *w, T *m, T *Mc, int64_t d0, int ld_slots, double *pg, double *pd,
+                          double *pr) {
+    const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int4 iv = incidence(inc, d);
+    const int ci = (int)(d % 3);
+    const T sum = cell_sum(Y, iv, ci, ld_slots);
+    const T wv = cmask[d] ? T(0) : sum;
+    const T mv = dinv[d] * wv;
+    w[d] = wv;
+    m[d] = mv;
+    cell_scatter(Mc, iv, ci, ld_slots, mv);
+    const double rv = (double)r[d], uv = (double)u[d];
+    double g = rv * uv, dl = (double)wv * uv, rr = rv * rv;
+    block_sum3(g, dl, rr);
+    if (threadIdx.x == 0) {
+        const int b = (int)(d0 / DB) + blockIdx.x;
+        pg[b] = g;
+        pd[b] = dl;
+        pr[b] = rr;
+    }
+}
+
+// One iteration, per DoF block of every iterating problem: n = A m from the
+// cell products, the eight recurrences with the published step, m = M^-1 w
+// to the cell layout, partials of the next (r,u), (w,u), (r,r).
+template <class T>
+__global__ __launch_bounds__(256) void k_bstep(const T *Y, const int32_t *inc, const uint8_t *cmask, const T *dinv,
+                                               T *x, T *r, T *u, T *w, T *z, T *q, T *s, T *p, T *m, T *Mc,
+                                               int ld_slots, const int32_t *blk_prob, const ProbState *ps, double *pg,
+                                               double *pd, double *pr) {
+    __shared__ int go;
+    __shared__ double step[2];
+    const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x;
+    const int4 iv = incidence(inc, d);  // requested before the gate is known
+    if (threadIdx.x == 0) {
+        const int pb = blk_prob[blockIdx.x];
+        int g = 0;
+        if (pb >= 0) {
+            const ProbState &S = ps[pb];
+            g = S.active && !S.done;
+            step[0] = S.a_cur;
+            step[1] = S.b_cur;
+        }
+        go = g;
+    }
+    __syncthreads();
+    if (!go) return;
+    const T a = (T)step[0], b = (T)step[1];
+    const int ci = (int)(d % 3);
+    const T sum = cell_sum(Y, iv, ci, ld_slots);
+    const T nv = cmask[d] ? T(0) : sum;
+    const T zv = nv + b * z[d];
+    const T qv = m[d] + b * q[d];
+    const T sv = w[d] + b * s[d];
+    const T pv = u[d] + b * p[d];
+    x[d] += a * pv;
+    const T rv = r[d] - a * sv;
+    const T uv = u[d] - a * qv;
+    const T wv = w[d] - a * zv;
+    const T mv = dinv[d] * wv;
+    z[d] = zv;
+    q[d] = qv;
+    s[d] = sv;
+    p[d] = pv;
+    r[d] = rv;
+    u[d] = uv;
+    w[d] = wv;
+    m[d] = mv;
+    cell_scatter(Mc, iv, ci, ld_slots, mv);
+    double g = (double)rv * (double)uv, dl = (double)wv * (double)uv, r2 = (double)rv * (double)rv;
+    block_sum3(g, dl, r2);
+    if (threadIdx.x == 0) {
+        pg[blockIdx.x] = g;
+        pd[blockIdx.x] = dl;
+        pr[blockIdx.x] = r2;
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+}  // namespace
+
+// ---- first-fit range allocator ----
+void RangeAlloc::init(int c) {
+    cap = c;
+    high = 0;
+    free_.clear();
+    if (c > 0) free_[0] = c;
+}
+
+int RangeAlloc::take(int n) {
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+        if (it->second >= n) {
+            int b = it->first, len = it->second;
+            free_.erase(it);
+            if (len > n) free_[b + n] = len - n;
+            high = std::max(high, b + n);
+            return b;
+        }
+    return -1;
+}
+
+void RangeAlloc::give(int b, int n) {
+    auto it = free_.emplace(b, n).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            free_.erase(it);
+        }
+    }
+    // Allocated space is the complement of the free ranges.
+    auto last = std::prev(free_.end());
+    high = (last->first + last->second == cap) ? last->first : cap;
+}
+
+namespace {
+
+mos_status prepare_problem(mos_engine e, const mos_array_desc *d, EngineProblem *P) {
+    const mos_rom r0 = e->roms[0];
+    const mos_cell_desc &cd = r0->desc;
+    ArrayMesh m;
+    m.build(d->nx_cells, d->ny_cells, cd.interp[0], cd.interp[1], cd.interp[2]);
+    const int S = m.S;
+    P->Nx = m.Nx;
+    P->Ny = m.Ny;
+    P->n_cells = (int64_t)m.Nx * m.Ny;
+    P->n_nodes = m.n_nodes;
+    P->n_dofs = 3 * m.n_nodes;
+    P->dT = d->delta_T;
+    const bool mixed = e->precision == MOS_MIXED;
+    P->rtol = d->rtol > 0 ? d->rtol : (mixed ? 1e-10 : 1e-12);
+    P->max_iters = d->max_iters > 0 ? d->max_iters : 20000;
+    P->n_blk = (int)(round_up(P->n_dofs, DOF_ALIGN) / DB);
+    const int64_t nd_pad = (int64_t)P->n_blk * DB;
+    P->cmask.assign(nd_pad, 1);
+    P->g.assign(nd_pad, 0.0);
+    for (int64_t i = 0; i < P->n_dofs; ++i) P->cmask[i] = 0;
+    int64_t n_con = 0;
+    for (int side = 0; side < 2; ++side) {
+        uint32_t flag = side == 0 ? MOS_BC_CLAMP_BOTTOM : MOS_BC_CLAMP_TOP;
+        if (!(d->bc_flags & flag)) continue;
+        int64_t K = side == 0 ? 0 : m.Z - 1;
+        for (int64_t J = 0; J < m.Y; ++J)
+            for (int64_t I = 0; I < m.X; ++I) {
+                int32_t id = m.node_of[(size_t)((K * m.Y + J) * m.X + I)];
+                for (int ci = 0; ci < 3; ++ci) {
+                    P->cmask[3 * (int64_t)id + ci] = 1;
+                    P->g[3 * (int64_t)id + ci] = 0.0;
+                }
+            }
+    }
+    for (int64_t i = 0; i < d->n_prescribed; ++i) {
+        int64_t dof = d->prescribed_dof[i];
+        double v = d->prescribed_value[i];
+        if (dof < 0 || dof >= P->n_dofs || !std::isfinite(v)) {
+            set_error("prescribed entry %lld: DoF %lld outside [0, %lld) or value not finite", (long long)i,
+                      (long long)dof, (long long)P->n_dofs);
+            return MOS_EINVAL;
+        }
+        P->cmask[dof] = 1;
+        P->g[dof] = v;
+    }
+    for (int64_t i = 0; i < P->n_dofs; ++i) n_con += P->cmask[i];
+    if (n_con == 0) {
+        set_error("array has no constrained DoF: the reduced stiffness is singular (rigid motions)");
+        return MOS_ESINGULAR;
+    }
+    const int n_roms = (int)e->roms.size();
+    std::vector<int> count(n_roms, 0);
+    for (int64_t c = 0; c < P->n_cells; ++c) count[d->cell_type[c]]++;
+    P->seg.assign(n_roms + 1, 0);
+    for (int t = 0; t < n_roms; ++t) P->seg[t + 1] = P->seg[t] + ceil_div(count[t], 16);
+    P->n_sb = std::max(P->seg[n_roms], 1);
+    P->perm.assign((size_t)P->n_sb * 16, -1);
+    std::vector<int32_t> slot_of((size_t)P->n_cells);
+    {
+        std::vector<int> next(n_roms);
+        for (int t = 0; t < n_roms; ++t) next[t] = P->seg[t] * 16;
+        for (int64_t c = 0; c < P->n_cells; ++c) {
+            int sl = next[d->cell_type[c]]++;
+            P->perm[sl] = (int32_t)c;
+            slot_of[c] = sl;
+        }
+    }
+    P->conn = m.conn;
+    // Incidence with problem-local slot indices; made global at placement.
+    P->inc.assign((size_t)nd_pad / 3 * 4, -1);
+    std::vector<uint8_t> cnt((size_t)m.n_nodes, 0);
+    for (int64_t c = 0; c < P->n_cells; ++c)
+        for (int s = 0; s < S; ++s) {
+            int32_t node = m.conn[(size_t)c * S + s];
+            P->inc[(size_t)node * 4 + cnt[node]++] = (slot_of[c] << INC_SHIFT) | s;
+        }
+    return MOS_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Engine internals
+// ---------------------------------------------------------------------------
+namespace {
+
+template <class T>
+mos_status start_inner(mos_engine e, EngineProblem *P, int max_iter) {
+    hipStream_t st = e->ctx->stream;
+    const int64_t d0 = (int64_t)P->blk_begin * DB;
+    T *V[NVEC];
+    for (int i = 0; i < NVEC; ++i) V[i] = static_cast<T *>(e->v[i]);
+    T *Mc = static_cast<T *>(e->Mc), *Y = static_cast<T *>(e->Yi);
+    const double rtol_in = e->precision == MOS_MIXED ? 1e-4 : std::max(0.1 * P->rtol, 1e-15);
+    hipLaunchKernelGGL(k_prob_start, dim3(1), dim3(1), 0, st, e->ps, P->pid, P->blk_begin, P->blk_begin + P->n_blk,
+                       rtol_in * rtol_in, max_iter);
+    hipLaunchKernelGGL(k_bstart<T>, dim3(P->n_blk), dim3(DB), 0, st, (const T *)V[VRHS], (const T *)V[VDINV], e->inc,
+                       V[VX], V[VR], V[VU], V[VZ], V[VQ], V[VS], V[VP], Mc, d0, e->ld_slots);
+    hipLaunchKernelGGL(k_bgemm<T>, dim3(e->ldk / 16, P->n_sb), dim3(256), 0, st,
+                       (const void *const *)(e->precision == MOS_MIXED ? e->kr32_tab : e->kr64_tab), e->sb_rom,
+                       e->sb_prob, (const T *)Mc, Y, e->ldk, e->ld_slots, P->sb_begin, P->n_sb, 0, e->ps, 0,
+                       (const double *)nullptr, (const double *)nullptr, (const double *)nullptr);
+    hipLaunchKernelGGL(k_bstart2<T>, dim3(P->n_blk), dim3(DB), 0, st, (const T *)Y, e->inc, e->cmask,
+                       (const T *)V[VDINV], (const T *)V[VR], (const T *)V[VU], V[VW], V[VM], Mc, d0, e->ld_slots,
+                       e->pg, e->pd, e->pr);
+    MOS_LAUNCH_CHECK();
+    return MOS_OK;
+}
+
+// r64 = b - A x (lifted, FP64) over the problem; its squared norm into res2[pid];
+// x is left scattered in the FP64 cell layout.
+mos_status residual(mos_engine e, EngineProblem *P) {
+    hipStream_t st = e->ctx->stream;
+    const int64_t d0 = (int64_t)P->blk_begin * DB, d1 = d0 + (int64_t)P->n_blk * DB;
+    hipLaunchKernelGGL((k_scatter<double, double>), dim3(P->n_blk), dim3(DB), 0, st, (const double *)e->x64, e->inc,
+                       e->Mc64, d0, d1, e->ld_slots);
+    hipLaunchKernelGGL(k_bgemm<double>, dim3(e->ldk / 16, P->n_sb), dim3(256), 0, st,
+                       (const void *const *)e->kr64_tab, e->sb_rom, e->sb_prob, (const double *)e->Mc64, e->Y64,
+                       e->ldk, e->ld_slots, P->sb_begin, P->n_sb, 0, e->ps, 0, (const double *)nullptr,
+                       (const double *)nullptr, (const double *)nullptr);
+    hipLaunchKernelGGL(k_assemble_raw<double>, dim3(P->n_blk), dim3(DB), 0, st, (const double *)e->Y64, e->inc, e->q64,
+                       d0, d1, e->ld_slots);
+    hipLaunchKernelGGL(k_bresidual, dim3(P->n_blk), dim3(DB), 0, st, (const double *)e->b_raw, (const double *)e->q64,
+                       e->cmask, e->r64, e->pr64, d0);
+    hipLaunchKernelGGL(k_reduce_range, dim3(1), dim3(64), 0, st, (const double *)e->pr64, P->blk_begin,
+                       P->blk_begin + P->n_blk, e->res2 + P->pid);
+    MOS_LAUNCH_CHECK();
+    return MOS_OK;
+}
+
+mos_status setup_problem(mos_engine e, EngineProblem *P) {
+    hipStream_t st = e->ctx->stream;
+    const int64_t d0 = (int64_t)P->blk_begin * DB, d1 = d0 + (int64_t)P->n_blk * DB;
+    const int64_t nd_pad = (int64_t)P->n_blk * DB;
+    // Tables: problem-local slot indices become global.
+    const int slot0 = P->sb_begin * 16;
+    std::vector<int32_t> inc(P->inc);
+    for (auto &v : inc)
+        if (v >= 0) v = (((v >> INC_SHIFT) + slot0) << INC_SHIFT) | (v & MAX_SURF);
+    std::vector<int32_t> sb_rom(P->n_sb, -1), sb_prob(P->n_sb, P->pid), blk_prob(P->n_blk, P->pid);
+    const int n_roms = (int)e->roms.size();
+    for (int t = 0; t < n_roms; ++t)
+        for (int b = P->seg[t]; b < P->seg[t + 1]; ++b) sb_rom[b] = t;
+    MOS_HIP(hipMemcpyAsync(e->inc + d0 / 3 * 4, inc.data(), inc.size() * 4, hipMemcpyHostToDevice, st));
+    MOS_HIP(hipMemcpyAsync(e->cmask + d0, P->cmask.data(), nd_pad, hipMemcpyHostToDevice, st));
+    MOS_HIP(hipMemcpyAsync(e->g + d0, P->g.data(), nd_pad * 8, hipMemcpyHostToDevice, st));
+    MOS_HIP(hipMemcpyAsync(e->x64 + d0, P->g.data(), nd_pad * 8, hipMemcpyHostToDevice, st));
+    MOS_HIP(hipMemcpyAsync(e->sb_rom + P->sb_begin, sb_rom.data(), sb_rom.size() * 4, hipMemcpyHostToDevice, st));
+    MOS_HIP(hipMemcpyAsync(e->sb_prob + P->sb_begin, sb_prob.data(), sb_prob.size() * 4, hipMemcpyHostToDevice, st));
+    MOS_HIP(hipMemcpyAsync(e->perm + slot0, P->perm.data(), P->perm.size() * 4, hipMemcpyHostToDevice, st));
+    MOS_HIP(hipStreamSynchronize(st));  // the staged host tables are locals
+    // b_raw, A g, ||b_l||^2, Jacobi diagonal.
+    hipLaunchKernelGGL(k_brhs, dim3(P->n_blk), dim3(DB), 0, st, (const double *const *)e->br_tab, e->sb_rom, e->inc,
+                       P->dT, e->b_raw, d0, d1);
+    hipLaunchKernelGGL((k_scatter<double, double>), dim3(P->n_blk), dim3(DB), 0, st, (const double *)e->g, e->inc,
+                       e->Mc64, d0, d1, e->ld_slots);
+    hipLaunchKernelGGL(k_bgemm<double>, dim3(e->ldk / 16, P->n_sb), dim3(256), 0, st,
+                       (const void *const *)e->kr64_tab, e->sb_rom, e->sb_prob, (const double *)e->Mc64, e->Y64,
+                       e->ldk, e->ld_slots, P->sb_begin, P->n_sb, 0, e->ps, 0, (const double *)nullptr,
+                       (const double *)nullptr, (const double *)nullptr);
+    hipLaunchKernelGGL(k_assemble_raw<double>, dim3(P->n_blk), dim3(DB), 0, st, (const double *)e->Y64, e->inc, e->q64,
+                       d0, d1, e->ld_slots);
+    hipLaunchKernelGGL(k_blift_norm, dim3(P->n_blk), dim3(DB), 0, st, (const double *)e->b_raw,
+                       (const double *)e->q64, (const double *)e->g, e->cmask, e->pr64, d0);
+    hipLaunchKernelGGL(k_reduce_range, dim3(1), dim3(64), 0, st, (const double *)e->pr64, P->blk_begin,
+                       P->blk_begin + P->n_blk, e->bb2 + P->pid);
+    if (e->precision == MOS_MIXED)
+        hipLaunchKernelGGL(k_bdiag<float>, dim3(P->n_blk), dim3(DB), 0, st, (const void *const *)e->kr64_tab,
+                           e->sb_rom, e->inc, e->cmask, (float *)e->v[VDINV], d0, d1, e->ldk);
+    else
+        hipLaunchKernelGGL(k_bdiag<double>, dim3(P->n_blk), dim3(DB), 0, st, (const void *const *)e->kr64_tab,
+                           e->sb_rom, e->inc, e->cmask, (double *)e->v[VDINV], d0, d1, e->ldk);
+    MOS_LAUNCH_CHECK();
+    // Inner right-hand side from the initial residual r = b_l.
+    MOS_TRY(residual(e, P));
+    return MOS_OK;
+}
+
+// After residual(): the relative residual decides; restart the inner solve or finish.
+// Returns true when the problem left the iterating set.
+mos_status after_residual(mos_engine e, EngineProblem *P, double res2, double bb2, bool *left) {
+    hipStream_t st = e->ctx->stream;
+    *left = false;
+    const double bnorm = std::sqrt(bb2), rnorm = std::sqrt(res2);
+    P->rel = bnorm > 0 ? rnorm / bnorm : rnorm;
+    if (!std::isfinite(P->rel)) {
+        P->state = 3;
+        P->status = MOS_ENOCONV;
+        P->error = "non-finite residual in the global solve";
+        *left = true;
+        return MOS_OK;
+    }
+    if (P->rel <= P->rtol || res2 == 0.0) {
+        P->state = 2;
+        *left = true;
+        return MOS_OK;
+    }
+    const int max_refine = e->precision == MOS_MIXED ? 30 : 6;
+    if (P->sweeps >= max_refine || P->iters >= P->max_iters) {
+        char buf[256];
+        snprintf(buf, sizeof(buf), "global solve stopped at relative residual %.3e > rtol %.3e after %d iterations, %d sweeps",
+                 P->rel, P->rtol, P->iters, P->sweeps);
+        P->error = buf;
+        P->state = 3;
+        P->status = MOS_ENOCONV;
+        *left = true;
+        return MOS_OK;
+    }
+    // Inner rhs = r / ||r|| (mixed) or r (FP64); scale kept on the device.
+    const int64_t d0 = (int64_t)P->blk_begin * DB;
+    double scale_in = e->precision == MOS_MIXED ? 1.0 / rnorm : 1.0;
+    double scale_out = e->precision == MOS_MIXED ? rnorm : 1.0;
+    double *sc = e->scale + 2 * P->pid;
+    double *hs = e->scale_host + 2 * P->pid;  // pinned; stable until the next sweep's sync
+    hs[0] = scale_in;
+    hs[1] = scale_out;
+    MOS_HIP(hipMemcpyAsync(sc, hs, 2 * sizeof(double), hipMemcpyHostToDevice, st));
+    if (e->precision == MOS_MIXED) {
+        hipLaunchKernelGGL(k_to_inner<float>, dim3(P->n_blk), dim3(DB), 0, st, (const double *)e->r64,
+                           (float *)e->v[VRHS], (const double *)sc, d0);
+        MOS_TRY(start_inner<float>(e, P, P->max_iters - P->iters));
+    } else {
+        hipLaunchKernelGGL(k_to_inner<double>, dim3(P->n_blk), dim3(DB), 0, st, (const double *)e->r64,
+                           (double *)e->v[VRHS], (const double *)sc, d0);
+        MOS_TRY(start_inner<double>(e, P, P->max_iters - P->iters));
+    }
+    MOS_LAUNCH_CHECK();
+    P->sweeps++;
+    P->state = 1;
+    return MOS_OK;
+}
+
+}  // namespace
+
+mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
+    mos_ctx ctx = e->ctx;
+    const bool mixed = e->precision == MOS_MIXED;
+    const size_t w = mixed ? 4 : 8;
+    const int ldk = e->ldk;
+    const int64_t dofs = std::max<int64_t>(round_up(cap_dofs, DOF_ALIGN), DOF_ALIGN);
+    const int64_t slots = std::max<int64_t>(round_up(cap_slots, 16), 16);
+    e->cap_blk = (int)(dofs / DB);
+    e->cap_sb = (int)(slots / 16);
+    e->ld_slots = (int)slots;
+    DeviceArena &m = e->mem;
+    for (int i = 0; i < NVEC; ++i) MOS_TRY(m.alloc(dofs * w, &e->v[i]));
+    MOS_TRY(m.alloc((size_t)ldk * slots * w, &e->Mc));
+    MOS_TRY(m.alloc((size_t)ldk * slots * w, &e->Yi));
+    MOS_TRY(m.alloc_n((size_t)ldk * slots, &e->Mc64));
+    MOS_TRY(m.alloc_n((size_t)ldk * slots, &e->Y64));
+    MOS_TRY(m.alloc_n(dofs, &e->x64));
+    MOS_TRY(m.alloc_n(dofs, &e->b_raw));
+    MOS_TRY(m.alloc_n(dofs, &e->g));
+    MOS_TRY(m.alloc_n(dofs, &e->r64));
+    MOS_TRY(m.alloc_n(dofs, &e->q64));
+    MOS_TRY(m.alloc_n(dofs, &e->cmask));
+    MOS_TRY(m.alloc_n(dofs / 3 * 4, &e->inc));
+    MOS_TRY(m.alloc_n(e->cap_blk, &e->blk_prob));
+    MOS_TRY(m.alloc_n(e->cap_blk, &e->pg));
+    MOS_TRY(m.alloc_n(e->cap_blk, &e->pd));
+    MOS_TRY(m.alloc_n(e->cap_blk, &e->pr));
+    MOS_TRY(m.alloc_n(e->cap_blk, &e->pr64));
+    MOS_TRY(m.alloc_n(e->cap_sb, &e->sb_rom));
+    MOS_TRY(m.alloc_n(e->cap_sb, &e->sb_prob));
+    MOS_TRY(m.alloc_n(slots, &e->perm));
+    MOS_TRY(m.alloc_n(MAX_PROBS, &e->ps));
+    MOS_TRY(m.alloc_n(MAX_PROBS, &e->res2));
+    MOS_TRY(m.alloc_n(MAX_PROBS, &e->bb2));
+    MOS_TRY(m.alloc_n(2 * MAX_PROBS, &e->scale));
+    if (hipHostMalloc((void **)&e->scale_host, 2 * MAX_PROBS * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        e->scale_host = nullptr;
+        set_error("pinned host allocation failed");
+        return MOS_ENOMEM;
+    }
+    MOS_TRY(m.alloc_n(MAX_TYPES, &e->kr64_tab));
+    MOS_TRY(m.alloc_n(MAX_TYPES, &e->kr32_tab));
+    MOS_TRY(m.alloc_n(MAX_TYPES, &e->br_tab));
+    MOS_TRY(m.alloc_n(MAX_TYPES, &e->psi_tab));
+    MOS_TRY(m.alloc_n(MAX_TYPES, &e->sigt_tab));
+    hipStream_t st = ctx->stream;
+    auto fill32 = [&](void *p, int64_t n, uint32_t v) {
+        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, st,
+                           (uint32_t *)p, n, v);
+    };
+    // Cell layouts must hold zeros in padding slots and rows.
+    fill32(e->Mc, (int64_t)ldk * slots * w / 4, 0u);
+    fill32(e->Mc64, (int64_t)ldk * slots * 2, 0u);
+    fill32(e->blk_prob, e->cap_blk, 0xffffffffu);
+    fill32(e->sb_rom, e->cap_sb, 0xffffffffu);
+    fill32(e->sb_prob, e->cap_sb, 0u);
+    fill32(e->ps, (int64_t)MAX_PROBS * sizeof(ProbState) / 4, 0u);
+    MOS_LAUNCH_CHECK();
+    std::vector<const void *> t64(MAX_TYPES, nullptr), t32(MAX_TYPES, nullptr), tb(MAX_TYPES, nullptr),
+        tp(MAX_TYPES, nullptr), ts(MAX_TYPES, nullptr);
+    for (size_t t = 0; t < e->roms.size(); ++t) {
+        t64[t] = e->roms[t]->kr_pad;
+        t32[t] = e->roms[t]->kr32_pad;
+        tb[t] = e->roms[t]->br;
+        tp[t] = e->roms[t]->psi;
+        ts[t] = e->roms[t]->sig_t;
+    }
+    MOS_HIP(hipMemcpyAsync(e->kr64_tab, t64.data(), MAX_TYPES * 8, hipMemcpyHostToDevice, st));
+    MOS_HIP(hipMemcpyAsync(e->kr32_tab, t32.data(), MAX_TYPES * 8, hipMemcpyHostToDevice, st));
+    MOS_HIP(hipMemcpyAsync(e->br_tab, tb.data(), MAX_TYPES * 8, hipMemcpyHostToDevice, st));
+    MOS_HIP(hipMemcpyAsync(e->psi_tab, tp.data(), MAX_TYPES * 8, hipMemcpyHostToDevice, st));
+    MOS_HIP(hipMemcpyAsync(e->sigt_tab, ts.data(), MAX_TYPES * 8, hipMemcpyHostToDevice, st));
+    MOS_HIP(hipStreamSynchronize(st));
+    e->blk.init(e->cap_blk);
+    e->sbs.init(e->cap_sb);
+    e->pids.init(MAX_PROBS);
+    return MOS_OK;
+}
+
+mos_status engine_check_desc(mos_engine e, const mos_array_desc *d) {
+    if (!d || d->nx_cells < 1 || d->ny_cells < 1 || (int64_t)d->nx_cells * d->ny_cells > (1 << 22) || !d->cell_type) {
+        set_error("array size must be >= 1x1 and <= 4M cells, with a cell_type map");
+        return MOS_EINVAL;
+    }
+    if (!std::isfinite(d->delta_T) || d->n_prescribed < 0 ||
+        (d->n_prescribed > 0 && (!d->prescribed_dof || !d->prescribed_value)) ||
+        (d->bc_flags & ~(uint32_t)(MOS_BC_CLAMP_BOTTOM | MOS_BC_CLAMP_TOP)) || d->precision != e->precision ||
+        d->rtol < 0 || d->max_iters < 0) {
+        set_error("invalid delta_T, constraints, precision (must match the engine), rtol or max_iters");
+        return MOS_EINVAL;
+    }
+    const int64_t n_cells = (int64_t)d->nx_cells * d->ny_cells;
+    for (int64_t c = 0; c < n_cells; ++c)
+        if (d->cell_type[c] >= e->roms.size()) {
+            set_error("cell_type[%lld] = %d but only %d ROMs", (long long)c, d->cell_type[c], (int)e->roms.size());
+            return MOS_EINVAL;
+        }
+    return MOS_OK;
+}
+
+mos_status engine_submit(mos_engine e, const mos_array_desc *d, void *vm, void *sig6, double *u_out,
+                         int64_t *ticket) {
+    MOS_TRY(engine_check_desc(e, d));
+    EngineProblem *P = new (std::nothrow) EngineProblem();
+    if (!P) {
+        set_error("out of host memory");
+        return MOS_ENOMEM;
+    }
+    mos_status s = prepare_problem(e, d, P);
+    if (s != MOS_OK) {
+        delete P;
+        return s;
+    }
+    if (P->n_blk > e->cap_blk || P->n_sb > e->cap_sb) {
+        set_error("problem needs %d DoF blocks and %d slot blocks; the engine holds %d and %d", P->n_blk, P->n_sb,
+                  e->cap_blk, e->cap_sb);
+        delete P;
+        return MOS_EINVAL;
+    }
+    P->ticket = ++e->next_ticket;
+    P->vm = vm;
+    P->sig6 = sig6;
+    P->u_out = u_out;
+    e->queue.push_back(P);
+    *ticket = P->ticket;
+    return MOS_OK;
+}
+
+namespace {
+
+mos_status reconstruct_problem(mos_engine e, EngineProblem *P);
+
+void release_problem(mos_engine e, EngineProblem *P) {
+    hipStream_t st = e->ctx->stream;
+    const int one = -1;
+    std::vector<int32_t> neg(std::max(P->n_blk, P->n_sb), one);
+    (void)hipMemcpyAsync(e->blk_prob + P->blk_begin, neg.data(), P->n_blk * 4, hipMemcpyHostToDevice, st);
+    (void)hipMemcpyAsync(e->sb_rom + P->sb_begin, neg.data(), P->n_sb * 4, hipMemcpyHostToDevice, st);
+    hipLaunchKernelGGL(k_prob_stop, dim3(1), dim3(1), 0, st, e->ps, P->pid);
+    // Copies from a host vector must finish before it goes out of scope.
+    (void)hipStreamSynchronize(st);
+    e->blk.give(P->blk_begin, P->n_blk);
+    e->sbs.give(P->sb_begin, P->n_sb);
+    e->pids.give(P->pid, 1);
+}
+
+}  // namespace
+
+// One round: admit, iterate a chunk, check stopped problems, retire finished.
+mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *completed) {
+    mos_ctx ctx = e->ctx;
+    hipStream_t st = ctx->stream;
+    // 1. Admission in arrival order while the arenas have room.
+    std::vector<EngineProblem *> admitted;
+    while (!e->queue.empty()) {
+        EngineProblem *P = e->queue.front();
+        int pid = e->pids.take(1);
+        if (pid < 0) break;
+        int b = e->blk.take(P->n_blk);
+        if (b < 0) {
+            e->pids.give(pid, 1);
+            break;
+        }
+        int sb = e->sbs.take(P->n_sb);
+        if (sb < 0) {
+            e->blk.give(b, P->n_blk);
+            e->pids.give(pid, 1);
+            break;
+        }
+        P->pid = pid;
+        P->blk_begin = b;
+        P->sb_begin = sb;
+        // blk_prob for the range (device)
+        std::vector<int32_t> bp(P->n_blk, pid);
+        MOS_HIP(hipMemcpyAsync(e->blk_prob + b, bp.data(), bp.size() * 4, hipMemcpyHostToDevice, st));
+        MOS_TRY(setup_problem(e, P));
+        MOS_HIP(hipStreamSynchronize(st));  // host-side tables must outlive their copies
+        e->queue.pop_front();
+        e->active.push_back(P);
+        admitted.push_back(P);
+    }
+    // Residual of the newly admitted problems decides their first sweep.
+    if (!admitted.empty()) {
+        std::vector<double> r2(MAX_PROBS), b2(MAX_PROBS);
+        MOS_HIP(hipMemcpyAsync(r2.data(), e->res2, MAX_PROBS * 8, hipMemcpyDeviceToHost, st));
+        MOS_HIP(hipMemcpyAsync(b2.data(), e->bb2, MAX_PROBS * 8, hipMemcpyDeviceToHost, st));
+        MOS_HIP(hipStreamSynchronize(st));
+        for (EngineProblem *P : admitted) {
+            bool left = false;
+            MOS_TRY(after_residual(e, P, r2[P->pid], b2[P->pid], &left));
+        }
+    }
+    // 2. A chunk of iterations over everything that is iterating.
+    bool any_iter = false;
+    for (EngineProblem *P : e->active) any_iter |= P->state == 1;
+    if (any_iter) {
+        const int hw_sb = e->sbs.high, hw_blk = e->blk.high, hw_p = e->pids.high;
+        const dim3 g_gemm(e->ldk / 16, hw_sb + ceil_div(hw_p, GEMM_WAVES));
+        for (int j = 0; j < chunk; ++j) {
+            if (e->precision == MOS_MIXED) {
+                float *V[NVEC];
+                for (int i = 0; i < NVEC; ++i) V[i] = static_cast<float *>(e->v[i]);
+                launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm<float>, g_gemm, dim3(256), 0, st,
+                             (const void *const *)e->kr32_tab, (const int32_t *)e->sb_rom, (const int32_t *)e->sb_prob,
+                             (const float *)e->Mc, (float *)e->Yi, e->ldk, e->ld_slots, 0, hw_sb, 1, e->ps, hw_p,
+                             (const double *)e->pg, (const double *)e->pd, (const double *)e->pr);
+                launch_timed(ctx, MOS_K_PCG_UPDATE, k_bstep<float>, dim3(hw_blk), dim3(DB), 0, st,
+                             (const float *)e->Yi, (const int32_t *)e->inc, (const uint8_t *)e->cmask,
+                             (const float *)V[VDINV], V[VX], V[VR], V[VU], V[VW], V[VZ], V[VQ], V[VS], V[VP], V[VM],
+                             (float *)e->Mc, e->ld_slots, (const int32_t *)e->blk_prob, (const ProbState *)e->ps,
+                             e->pg, e->pd, e->pr);
+            } else {
+                double *V[NVEC];
+                for (int i = 0; i < NVEC; ++i) V[i] = static_cast<double *>(e->v[i]);
+                launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm<double>, g_gemm, dim3(256), 0, st,
+                             (const void *const *)e->kr64_tab, (const int32_t *)e->sb_rom, (const int32_t *)e->sb_prob,
+                             (const double *)e->Mc, (double *)e->Yi, e->ldk, e->ld_slots, 0, hw_sb, 1, e->ps, hw_p,
+                             (const double *)e->pg, (const double *)e->pd, (const double *)e->pr);
+                launch_timed(ctx, MOS_K_PCG_UPDATE, k_bstep<double>, dim3(hw_blk), dim3(DB), 0, st,
+                             (const double *)e->Yi, (const int32_t *)e->inc, (const uint8_t *)e->cmask,
+                             (const double *)V[VDINV], V[VX], V[VR], V[VU], V[VW], V[VZ], V[VQ], V[VS], V[VP], V[VM],
+                             (double *)e->Mc, e->ld_slots, (const int32_t *)e->blk_prob, (const ProbState *)e->ps,
+                             e->pg, e->pd, e->pr);
+            }
+        }
+        MOS_LAUNCH_CHECK();
+        // 3. Problems whose inner solve stopped: fold in the correction, FP64 residual.
+        std::vector<ProbState> hs(hw_p);
+        MOS_HIP(hipMemcpyAsync(hs.data(), e->ps, hw_p * sizeof(ProbState), hipMemcpyDeviceToHost, st));
+        MOS_HIP(hipStreamSynchronize(st));
+        std::vector<EngineProblem *> stopped;
+        for (EngineProblem *P : e->active) {
+            if (P->state != 1) continue;
+            const ProbState &S = hs[P->pid];
+            if (!S.done) continue;
+            P->iters += S.it;
+            if (S.done == 2 && S.it == 0) {
+                P->state = 3;
+                P->status = MOS_ENOCONV;
+                P->error = "PCG breakdown (p.Ap <= 0 or non-finite) at the start of a sweep";
+                continue;
+            }
+            const int64_t d0 = (int64_t)P->blk_begin * DB;
+            const double *sc = e->scale + 2 * P->pid + 1;
+            if (e->precision == MOS_MIXED)
+                hipLaunchKernelGGL(k_add_inner<float>, dim3(P->n_blk), dim3(DB), 0, st, e->x64,
+                                   (const float *)e->v[VX], sc, d0);
+            else
+                hipLaunchKernelGGL(k_add_inner<double>, dim3(P->n_blk), dim3(DB), 0, st, e->x64,
+                                   (const double *)e->v[VX], sc, d0);
+            hipLaunchKernelGGL(k_prob_stop, dim3(1), dim3(1), 0, st, e->ps, P->pid);
+            MOS_TRY(residual(e, P));
+            stopped.push_back(P);
+        }
+        if (!stopped.empty()) {
+            std::vector<double> r2(hw_p), b2(hw_p);
+            MOS_HIP(hipMemcpyAsync(r2.data(), e->res2, hw_p * 8, hipMemcpyDeviceToHost, st));
+            MOS_HIP(hipMemcpyAsync(b2.data(), e->bb2, hw_p * 8, hipMemcpyDeviceToHost, st));
+            MOS_HIP(hipStreamSynchronize(st));
+            for (EngineProblem *P : stopped) {
+                bool left = false;
+                MOS_TRY(after_residual(e, P, r2[P->pid], b2[P->pid], &left));
+            }
+        }
+    }
+    // 4. Retire finished problems (reconstruct into their buffers first).
+    std::vector<EngineProblem *> keep;
+    for (EngineProblem *P : e->active) {
+        if (P->state == 2 || P->state == 3) {
+            if (P->state == 2 && (P->vm || P->sig6)) MOS_TRY(reconstruct_problem(e, P));
+            if (P->state == 2 && P->u_out)
+                MOS_HIP(hipMemcpyAsync(P->u_out, e->x64 + (int64_t)P->blk_begin * DB, P->n_dofs * 8,
+                                       hipMemcpyDeviceToDevice, st));
+            e->finished[P->ticket] = P;
+            release_problem(e, P);
+            if (completed) completed->push_back(P->ticket);
+        } else {
+            keep.push_back(P);
+        }
+    }
+    e->active.swap(keep);
+    return MOS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Reconstruction of one engine problem (outputs in its caller buffers).
+// ---------------------------------------------------------------------------
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// One wave per (element block of 16, slot block of 16) of the problem; the
+// FP64 cell layout holds the scattered solution.
+template <class OutT>
+__global__ __launch_bounds__(256) void k_brecon(const double *const *psi_tab, const double *const *sigt_tab,
+                                                const int32_t *sb_rom, const double *U, const int32_t *perm,
+                                                int sb_begin, int n_sb, int ld_slots, int ldk, int n_elem, double dT,
+                                                OutT *vm, OutT *sig6) {
+    const int eb = blockIdx.x;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int sbl = blockIdx.y * 4 + wave;
+    if (sbl >= n_sb) return;
+    const int sb = sb_begin + sbl;
+    const int rom = sb_rom[sb];
+    if (rom < 0) return;
+    const int pc0 = sb * 16;
+    const double *psi = psi_tab[rom] + (size_t)eb * 6 * ldk * 16;
+    d4 acc[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc[k] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < ldk; k0 += 4) {
+        const int kk = k0 + lane / 16;
+        const double b = U[(size_t)kk * ld_slots + pc0 + lane % 16];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double a = psi[((size_t)k * ldk + kk) * 16 + lane % 16];
+            acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[k], 0, 0, 0);
+        }
+    }
+    const int cell = perm[pc0 + lane % 16];
+    if (cell < 0) return;
+    const double *stt = sigt_tab[rom];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = eb * 16 + lane / 16 + 4 * q;  // FP64 MFMA output row
+        if (e >= n_elem) continue;
+        double s[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) s[k] = acc[k][q] + dT * stt[(size_t)e * 6 + k];
+        const size_t o = (size_t)cell * n_elem + e;
+        if (vm) {
+            double a = s[0] - s[1], b = s[1] - s[2], c = s[2] - s[0];
+            vm[o] = (OutT)sqrt(0.5 * (a * a + b * b + c * c) + 3.0 * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5]));
+        }
+        if (sig6)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sig6[o * 6 + k] = (OutT)s[k];
+    }
+}
+
+mos_status reconstruct_problem(mos_engine e, EngineProblem *P) {
+    hipStream_t st = e->ctx->stream;
+    // The last residual check left the solution scattered in the FP64 cell layout.
+    dim3 grid(e->n_eblk, ceil_div(P->n_sb, 4));
+    if (e->precision == MOS_FP64)
+        launch_timed(e->ctx, MOS_K_RECON, k_brecon<double>, grid, dim3(256), 0, st, (const double *const *)e->psi_tab,
+                     (const double *const *)e->sigt_tab, (const int32_t *)e->sb_rom, (const double *)e->Mc64,
+                     (const int32_t *)e->perm, P->sb_begin, P->n_sb, e->ld_slots, e->ldk, e->n_elem, P->dT,
+                     (double *)P->vm, (double *)P->sig6);
+    else
+        launch_timed(e->ctx, MOS_K_RECON, k_brecon<float>, grid, dim3(256), 0, st, (const double *const *)e->psi_tab,
+                     (const double *const *)e->sigt_tab, (const int32_t *)e->sb_rom, (const double *)e->Mc64,
+                     (const int32_t *)e->perm, P->sb_begin, P->n_sb, e->ld_slots, e->ldk, e->n_elem, P->dT,
+                     (float *)P->vm, (float *)P->sig6);
+    MOS_LAUNCH_CHECK();
+    return MOS_OK;
+}
+
+}  // namespace
+
+mos_status engine_problem_size(mos_engine e, const mos_array_desc *d, int64_t *dofs, int64_t *slots) {
+    MOS_TRY(engine_check_desc(e, d));
+    const mos_cell_desc &cd = e->roms[0]->desc;
+    const int nx = cd.interp[0], ny = cd.interp[1], nz = cd.interp[2];
+    const int64_t X = (int64_t)d->nx_cells * (nx - 1) + 1, Y = (int64_t)d->ny_cells * (ny - 1) + 1;
+    const int64_t nodes = X * Y * nz - (int64_t)d->nx_cells * d->ny_cells * (nx - 2) * (ny - 2) * (nz - 2);
+    *dofs = round_up(3 * nodes, DOF_ALIGN);
+    const int64_t n_cells = (int64_t)d->nx_cells * d->ny_cells;
+    std::vector<int64_t> count(e->roms.size(), 0);
+    for (int64_t c = 0; c < n_cells; ++c) count[d->cell_type[c]]++;
+    int64_t sl = 0;
+    for (int64_t cnt : count) sl += round_up(cnt, 16);
+    *slots = std::max<int64_t>(sl, 16);
+    return MOS_OK;
+}
+
+void engine_free(mos_engine e) {
+    if (!e) return;
+    for (EngineProblem *P : e->queue) delete P;
+    for (EngineProblem *P : e->active) delete P;
+    for (auto &kv : e->finished) delete kv.second;
+    e->queue.clear();
+    e->active.clear();
+    e->finished.clear();
+    e->mem.release();
+    if (e->scale_host) (void)hipHostFree(e->scale_host);
+    e->scale_host = nullptr;
+}
+
+}  // namespace mos

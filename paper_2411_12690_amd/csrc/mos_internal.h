@@ -166,8 +166,6 @@ mos_status band_cholesky(mos_cell c, double *dinv, int *status_dev, int *not_spd
 mos_status band_solve(mos_cell c, const double *dinv, double *rhs, int ldr, int ncols);
 // reduce.hip
 mos_status reduce_cell(mos_cell c, mos_rom r);
-// solve.hip
-mos_status solve_array(mos_ctx ctx, const mos_array_desc *d, const mos_rom *roms, int n_roms, mos_sol s);
 // recon.hip
 mos_status reconstruct(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void *sigma6);
 

@@ -22,8 +22,9 @@ MOS_OUT_VM, MOS_OUT_SIGMA6 = 1, 2
 
 EXPORTED = ("mos_ctx_create", "mos_ctx_destroy", "mos_build_cell", "mos_reduce", "mos_solve_array",
             "mos_reconstruct", "mos_get_solution", "mos_query", "mos_cell_export", "mos_rom_export",
-            "mos_array_layout", "mos_timing_start", "mos_timing_stop", "mos_cell_free", "mos_rom_free",
-            "mos_sol_free", "mos_last_error")
+            "mos_array_layout", "mos_engine_create", "mos_engine_submit", "mos_engine_progress",
+            "mos_engine_result", "mos_engine_stats", "mos_engine_destroy", "mos_timing_start", "mos_timing_stop",
+            "mos_cell_free", "mos_rom_free", "mos_sol_free", "mos_last_error")
 MOS_K_CELL_GEMM, MOS_K_ASSEMBLE, MOS_K_PCG_UPDATE, MOS_K_RECON = 1, 2, 3, 4
 
 
@@ -79,6 +80,14 @@ def _load():
         "mos_rom_export": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "mos_array_layout": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, vp, P(ctypes.c_int64), vp, vp,
                                             vp, vp]),
+        "mos_engine_create": (ctypes.c_int, [vp, P(vp), ctypes.c_int32, ctypes.c_int, ctypes.c_size_t, P(vp)]),
+        "mos_engine_submit": (ctypes.c_int, [vp, P(ArrayDesc), vp, vp, vp, P(ctypes.c_int64)]),
+        "mos_engine_progress": (ctypes.c_int, [vp, ctypes.c_int32, vp, ctypes.c_int32, P(ctypes.c_int32)]),
+        "mos_engine_result": (ctypes.c_int, [vp, ctypes.c_int64, P(ctypes.c_int32), P(ctypes.c_double),
+                                             P(ctypes.c_int32), P(ctypes.c_int32)]),
+        "mos_engine_stats": (ctypes.c_int, [vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64),
+                                            P(ctypes.c_int64)]),
+        "mos_engine_destroy": (None, [vp]),
         "mos_timing_start": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
         "mos_timing_stop": (ctypes.c_int, [vp, P(ctypes.c_int64), P(ctypes.c_double)]),
         "mos_cell_free": (None, [vp]),
@@ -215,8 +224,9 @@ def mos_reduce(ctx, cell):
     return Rom(h, ctx)
 
 
-def mos_solve_array(ctx, roms, nx_cells, ny_cells, cell_type, delta_T, clamp_bottom=True, clamp_top=False,
-                    prescribed_dofs=None, prescribed_values=None, mixed=False, rtol=0.0, max_iters=0):
+def array_desc(nx_cells, ny_cells, cell_type, delta_T, clamp_bottom=True, clamp_top=False,
+               prescribed_dofs=None, prescribed_values=None, mixed=False, rtol=0.0, max_iters=0):
+    """Build the C descriptor; returns (desc, keep-alive arrays)."""
     ct = np.ascontiguousarray(cell_type, dtype=np.uint8)
     if ct.size != nx_cells * ny_cells:
         raise ValueError("cell_type must have nx_cells * ny_cells entries")
@@ -225,7 +235,7 @@ def mos_solve_array(ctx, roms, nx_cells, ny_cells, cell_type, delta_T, clamp_bot
     d.cell_type = ct.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
     d.delta_T = float(delta_T)
     d.bc_flags = (MOS_BC_CLAMP_BOTTOM if clamp_bottom else 0) | (MOS_BC_CLAMP_TOP if clamp_top else 0)
-    pd = pv = None
+    keep = [ct]
     if prescribed_dofs is not None and len(prescribed_dofs):
         pd = np.ascontiguousarray(prescribed_dofs, dtype=np.int64)
         pv = np.ascontiguousarray(prescribed_values, dtype=np.float64)
@@ -234,17 +244,110 @@ def mos_solve_array(ctx, roms, nx_cells, ny_cells, cell_type, delta_T, clamp_bot
         d.n_prescribed = pd.size
         d.prescribed_dof = pd.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
         d.prescribed_value = pv.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        keep += [pd, pv]
     d.precision = MOS_MIXED if mixed else MOS_FP64
     d.rtol, d.max_iters = float(rtol), int(max_iters)
-    arr = (ctypes.c_void_p * len(roms))(*[r.ptr.value for r in roms])
+    return d, keep
+
+
+def _rom_array(roms):
+    return (ctypes.c_void_p * len(roms))(*[r.ptr.value for r in roms])
+
+
+def mos_solve_array(ctx, roms, nx_cells, ny_cells, cell_type, delta_T, clamp_bottom=True, clamp_top=False,
+                    prescribed_dofs=None, prescribed_values=None, mixed=False, rtol=0.0, max_iters=0):
+    d, keep = array_desc(nx_cells, ny_cells, cell_type, delta_T, clamp_bottom, clamp_top, prescribed_dofs,
+                         prescribed_values, mixed, rtol, max_iters)
     h = ctypes.c_void_p()
-    _check(lib().mos_solve_array(ctx.ptr, ctypes.byref(d), arr, len(roms), ctypes.byref(h)), "mos_solve_array")
+    _check(lib().mos_solve_array(ctx.ptr, ctypes.byref(d), _rom_array(roms), len(roms), ctypes.byref(h)),
+           "mos_solve_array")
     s = Solution(h, ctx)
     s.precision = d.precision
     s.n_cells = nx_cells * ny_cells
     s.n_elem = roms[0].query(MOS_Q_CELL_ELEMS)
     s.roms = list(roms)
     return s
+
+
+class Engine:
+    """Batched / served global stage (mos_engine_*): submit problems, call
+    progress() until their tickets complete."""
+
+    def __init__(self, ctx, roms, mixed=False, device_bytes=8 << 30):
+        self.ctx = ctx
+        self.roms = list(roms)
+        self.mixed = mixed
+        self.ptr = None
+        self._keep = {}
+        h = ctypes.c_void_p()
+        _check(lib().mos_engine_create(ctx.ptr, _rom_array(roms), len(roms), MOS_MIXED if mixed else MOS_FP64,
+                                       int(device_bytes), ctypes.byref(h)), "mos_engine_create")
+        self.ptr = h
+
+    def submit(self, nx_cells, ny_cells, cell_type, delta_T, vm=None, sigma6=None, u=None, **kw):
+        d, keep = array_desc(nx_cells, ny_cells, cell_type, delta_T, mixed=self.mixed, **kw)
+        t = ctypes.c_int64()
+        ptr = (lambda x: ctypes.c_void_p(x.data_ptr()) if x is not None else None)
+        _check(lib().mos_engine_submit(self.ptr, ctypes.byref(d), ptr(vm), ptr(sigma6), ptr(u), ctypes.byref(t)),
+               "mos_engine_submit")
+        self._keep[t.value] = (keep, vm, sigma6, u)
+        return t.value
+
+    def progress(self, iterations=16, max_completed=4096):
+        out = np.zeros(max_completed, dtype=np.int64)
+        n = ctypes.c_int32()
+        _check(lib().mos_engine_progress(self.ptr, iterations, _ptr(out), max_completed, ctypes.byref(n)),
+               "mos_engine_progress")
+        return [int(v) for v in out[:n.value]]
+
+    def result(self, ticket):
+        """(status, relative residual, iterations, sweeps); forgets the ticket."""
+        st, res, it, sw = ctypes.c_int32(), ctypes.c_double(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().mos_engine_result(self.ptr, ticket, ctypes.byref(st), ctypes.byref(res), ctypes.byref(it),
+                                       ctypes.byref(sw)), "mos_engine_result")
+        self._keep.pop(ticket, None)
+        return st.value, res.value, it.value, sw.value
+
+    def stats(self):
+        a, q, cd, cs = (ctypes.c_int64() for _ in range(4))
+        _check(lib().mos_engine_stats(self.ptr, ctypes.byref(a), ctypes.byref(q), ctypes.byref(cd), ctypes.byref(cs)),
+               "mos_engine_stats")
+        return dict(active=a.value, queued=q.value, capacity_dofs=cd.value, capacity_slots=cs.value)
+
+    def close(self):
+        if self.ptr:
+            lib().mos_engine_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mos_engine_create(ctx, roms, mixed=False, device_bytes=8 << 30):
+    return Engine(ctx, roms, mixed, device_bytes)
+
+
+def mos_engine_submit(engine, *args, **kw):
+    return engine.submit(*args, **kw)
+
+
+def mos_engine_progress(engine, iterations=16):
+    return engine.progress(iterations)
+
+
+def mos_engine_result(engine, ticket):
+    return engine.result(ticket)
+
+
+def mos_engine_stats(engine):
+    return engine.stats()
+
+
+def mos_engine_destroy(engine):
+    engine.close()
 
 
 def mos_reconstruct(ctx, sol, vm=None, sigma6=None):
