@@ -186,7 +186,8 @@ mos_status mos_array_layout(mos_ctx ctx, int32_t nx_cells, int32_t ny_cells, mos
 
 /* ---- Batched / served global stage ----------------------------------------
  * An engine keeps device arenas for many array problems that share one set
- * of ROMs (same pitch, height, mesh and interp) and one precision.  Problems
+ * of ROMs (same cell mesh and interp; pitch and height may differ between
+ * ROMs, but the cells of one array must agree on them) and one precision.  Problems
  * are submitted at any time, admitted in arrival order when their DoFs and
  * cell slots fit in the arenas (the device-memory budget), and advanced
  * together: every mos_engine_progress call admits what fits, runs

@@ -342,7 +342,10 @@ mos_status mos_reduce(mos_ctx ctx, mos_cell cell, mos_rom *out) {
     return MOS_OK;
 }
 
-static mos_status check_roms(const mos_rom *roms, int32_t n_roms) {
+// ROMs used together share the cell mesh and the interpolation order (same
+// reduced size and stress basis shape); with same_block they must also share
+// pitch and height (one array is made of one block geometry).
+static mos_status check_roms(const mos_rom *roms, int32_t n_roms, bool same_block = true) {
     if (!roms || n_roms < 1 || n_roms > MAX_TYPES) {
         set_error("need 1..%d ROMs", MAX_TYPES);
         return MOS_EINVAL;
@@ -355,10 +358,12 @@ static mos_status check_roms(const mos_rom *roms, int32_t n_roms) {
     const mos_cell_desc &a = roms[0]->desc;
     for (int t = 1; t < n_roms; ++t) {
         const mos_cell_desc &b = roms[t]->desc;
-        bool same = a.pitch_x == b.pitch_x && a.pitch_y == b.pitch_y && a.height == b.height;
+        bool same = true;
         for (int k = 0; k < 3; ++k) same = same && a.mesh[k] == b.mesh[k] && a.interp[k] == b.interp[k];
+        if (same_block) same = same && a.pitch_x == b.pitch_x && a.pitch_y == b.pitch_y && a.height == b.height;
         if (!same) {
-            set_error("roms[%d] differs from roms[0] in pitch, height, mesh or interp", t);
+            set_error("roms[%d] differs from roms[0] in %s", t,
+                      same_block ? "pitch, height, mesh or interp" : "mesh or interp");
             return MOS_EINVAL;
         }
     }
@@ -496,7 +501,7 @@ mos_status mos_engine_create(mos_ctx ctx, const mos_rom *roms, int32_t n_roms, m
         set_error("invalid context or precision");
         return MOS_EINVAL;
     }
-    MOS_TRY(check_roms(roms, n_roms));
+    MOS_TRY(check_roms(roms, n_roms, false));
     MOS_HIP(hipSetDevice(ctx->device));
     mos_engine e = new_engine(ctx, roms, n_roms, precision);
     if (!e) {

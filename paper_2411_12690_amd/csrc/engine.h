@@ -94,6 +94,9 @@ struct EngineProblem {
     double dT = 0.0, rtol = 0.0;
     int max_iters = 0, iters = 0, sweeps = 0;
     double rel = 1.0;
+    double last_res2 = -1.0;      // FP64 residual before the last correction
+    int sweep_cap = 0;            // inner iterations allowed per sweep
+    int undone = 0;               // corrections undone because they raised the residual
     int state = 0;                // 0 queued, 1 iterating, 2 converged, 3 failed
     mos_status status = MOS_OK;
     std::string error;

@@ -299,9 +299,9 @@ __global__ void k_to_inner(const double *r64, T *rhs, const double *scale_of, in
 }
 
 template <class T>
-__global__ void k_add_inner(double *x, const T *dx, const double *scale_of, int64_t d0) {
+__global__ void k_add_inner(double *x, const T *dx, const double *scale_of, double sign, int64_t d0) {
     const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    x[d] += *scale_of * (double)dx[d];
+    x[d] += sign * *scale_of * (double)dx[d];
 }
 
 __global__ void k_prob_start(ProbState *ps, int p, int blk_begin, int blk_end, double rtol2, int max_iter) {
@@ -557,13 +557,12 @@ mos_status prepare_problem(mos_engine e, const mos_array_desc *d, EngineProblem 
 namespace {
 
 template <class T>
-mos_status start_inner(mos_engine e, EngineProblem *P, int max_iter) {
+mos_status start_inner(mos_engine e, EngineProblem *P, int max_iter, double rtol_in) {
     hipStream_t st = e->ctx->stream;
     const int64_t d0 = (int64_t)P->blk_begin * DB;
     T *V[NVEC];
     for (int i = 0; i < NVEC; ++i) V[i] = static_cast<T *>(e->v[i]);
     T *Mc = static_cast<T *>(e->Mc), *Y = static_cast<T *>(e->Yi);
-    const double rtol_in = e->precision == MOS_MIXED ? 1e-4 : std::max(0.1 * P->rtol, 1e-15);
     hipLaunchKernelGGL(k_prob_start, dim3(1), dim3(1), 0, st, e->ps, P->pid, P->blk_begin, P->blk_begin + P->n_blk,
                        rtol_in * rtol_in, max_iter);
     hipLaunchKernelGGL(k_bstart<T>, dim3(P->n_blk), dim3(DB), 0, st, (const T *)V[VRHS], (const T *)V[VDINV], e->inc,
@@ -648,11 +647,33 @@ mos_status setup_problem(mos_engine e, EngineProblem *P) {
     return MOS_OK;
 }
 
-// After residual(): the relative residual decides; restart the inner solve or finish.
-// Returns true when the problem left the iterating set.
+// After residual(): the relative residual decides; restart the inner solve or
+// finish.  Refinement is kept monotone: a correction that raised the FP64
+// residual is undone and the next sweep gets half the iterations.
 mos_status after_residual(mos_engine e, EngineProblem *P, double res2, double bb2, bool *left) {
     hipStream_t st = e->ctx->stream;
     *left = false;
+    const bool mixed = e->precision == MOS_MIXED;
+    if (P->sweep_cap == 0) P->sweep_cap = mixed ? 256 : P->max_iters;
+    if (P->last_res2 >= 0.0 && !(res2 <= P->last_res2)) {
+        const int64_t d0 = (int64_t)P->blk_begin * DB;
+        const double *sc = e->scale + 2 * P->pid + 1;
+        if (mixed)
+            hipLaunchKernelGGL(k_add_inner<float>, dim3(P->n_blk), dim3(DB), 0, st, e->x64, (const float *)e->v[VX],
+                               sc, -1.0, d0);
+        else
+            hipLaunchKernelGGL(k_add_inner<double>, dim3(P->n_blk), dim3(DB), 0, st, e->x64,
+                               (const double *)e->v[VX], sc, -1.0, d0);
+        MOS_LAUNCH_CHECK();
+        MOS_TRY(residual(e, P));
+        MOS_HIP(hipMemcpyAsync(e->scale_host + 2 * MAX_PROBS, e->res2 + P->pid, sizeof(double),
+                               hipMemcpyDeviceToHost, st));
+        MOS_HIP(hipStreamSynchronize(st));
+        res2 = e->scale_host[2 * MAX_PROBS];  // scratch slot after the per-problem scales
+        P->sweep_cap = std::max(P->sweep_cap / 2, 8);
+        P->undone++;
+    }
+    P->last_res2 = res2;
     const double bnorm = std::sqrt(bb2), rnorm = std::sqrt(res2);
     P->rel = bnorm > 0 ? rnorm / bnorm : rnorm;
     if (!std::isfinite(P->rel)) {
@@ -667,8 +688,8 @@ mos_status after_residual(mos_engine e, EngineProblem *P, double res2, double bb
         *left = true;
         return MOS_OK;
     }
-    const int max_refine = e->precision == MOS_MIXED ? 30 : 6;
-    if (P->sweeps >= max_refine || P->iters >= P->max_iters) {
+    const int max_refine = mixed ? 40 : 8;
+    if (P->sweeps >= max_refine || P->iters >= P->max_iters || P->undone > 8) {
         char buf[256];
         snprintf(buf, sizeof(buf), "global solve stopped at relative residual %.3e > rtol %.3e after %d iterations, %d sweeps",
                  P->rel, P->rtol, P->iters, P->sweeps);
@@ -690,11 +711,14 @@ mos_status after_residual(mos_engine e, EngineProblem *P, double res2, double bb
     if (e->precision == MOS_MIXED) {
         hipLaunchKernelGGL(k_to_inner<float>, dim3(P->n_blk), dim3(DB), 0, st, (const double *)e->r64,
                            (float *)e->v[VRHS], (const double *)sc, d0);
-        MOS_TRY(start_inner<float>(e, P, P->max_iters - P->iters));
+        // FP32 inner solves reduce the residual by a fixed factor per sweep.
+        MOS_TRY(start_inner<float>(e, P, std::min(P->sweep_cap, P->max_iters - P->iters), 1e-4));
     } else {
         hipLaunchKernelGGL(k_to_inner<double>, dim3(P->n_blk), dim3(DB), 0, st, (const double *)e->r64,
                            (double *)e->v[VRHS], (const double *)sc, d0);
-        MOS_TRY(start_inner<double>(e, P, P->max_iters - P->iters));
+        // FP64 inner solves aim at a tenth of the final absolute target.
+        const double rtol_in = std::min(0.5, std::max(0.1 * P->rtol * bnorm / rnorm, 1e-15));
+        MOS_TRY(start_inner<double>(e, P, std::min(P->sweep_cap, P->max_iters - P->iters), rtol_in));
     }
     MOS_LAUNCH_CHECK();
     P->sweeps++;
@@ -739,7 +763,8 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     MOS_TRY(m.alloc_n(MAX_PROBS, &e->res2));
     MOS_TRY(m.alloc_n(MAX_PROBS, &e->bb2));
     MOS_TRY(m.alloc_n(2 * MAX_PROBS, &e->scale));
-    if (hipHostMalloc((void **)&e->scale_host, 2 * MAX_PROBS * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&e->scale_host, (2 * MAX_PROBS + 8) * sizeof(double), hipHostMallocDefault) !=
+        hipSuccess) {
         (void)hipGetLastError();
         e->scale_host = nullptr;
         set_error("pinned host allocation failed");
@@ -797,11 +822,20 @@ mos_status engine_check_desc(mos_engine e, const mos_array_desc *d) {
         return MOS_EINVAL;
     }
     const int64_t n_cells = (int64_t)d->nx_cells * d->ny_cells;
-    for (int64_t c = 0; c < n_cells; ++c)
-        if (d->cell_type[c] >= e->roms.size()) {
-            set_error("cell_type[%lld] = %d but only %d ROMs", (long long)c, d->cell_type[c], (int)e->roms.size());
+    int first = -1;
+    for (int64_t c = 0; c < n_cells; ++c) {
+        const int t = d->cell_type[c];
+        if (t >= (int)e->roms.size()) {
+            set_error("cell_type[%lld] = %d but only %d ROMs", (long long)c, t, (int)e->roms.size());
             return MOS_EINVAL;
         }
+        if (first < 0) first = t;
+        const mos_cell_desc &a = e->roms[first]->desc, &b = e->roms[t]->desc;
+        if (a.pitch_x != b.pitch_x || a.pitch_y != b.pitch_y || a.height != b.height) {
+            set_error("cells of one array use ROMs %d and %d of different pitch or height", first, t);
+            return MOS_EINVAL;
+        }
+    }
     return MOS_OK;
 }
 
@@ -951,10 +985,10 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
             const double *sc = e->scale + 2 * P->pid + 1;
             if (e->precision == MOS_MIXED)
                 hipLaunchKernelGGL(k_add_inner<float>, dim3(P->n_blk), dim3(DB), 0, st, e->x64,
-                                   (const float *)e->v[VX], sc, d0);
+                                   (const float *)e->v[VX], sc, 1.0, d0);
             else
                 hipLaunchKernelGGL(k_add_inner<double>, dim3(P->n_blk), dim3(DB), 0, st, e->x64,
-                                   (const double *)e->v[VX], sc, d0);
+                                   (const double *)e->v[VX], sc, 1.0, d0);
             hipLaunchKernelGGL(k_prob_stop, dim3(1), dim3(1), 0, st, e->ps, P->pid);
             MOS_TRY(residual(e, P));
             stopped.push_back(P);

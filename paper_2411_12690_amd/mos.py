@@ -306,6 +306,7 @@ class Engine:
         _check(lib().mos_engine_result(self.ptr, ticket, ctypes.byref(st), ctypes.byref(res), ctypes.byref(it),
                                        ctypes.byref(sw)), "mos_engine_result")
         self._keep.pop(ticket, None)
+        self.last_error = lib().mos_last_error().decode(errors="replace") if st.value != MOS_OK else ""
         return st.value, res.value, it.value, sw.value
 
     def stats(self):
