@@ -219,6 +219,18 @@ mos_status mos_engine_progress(mos_engine e, int32_t iterations, int64_t *comple
  * forgotten afterwards.  MOS_EBUSY if it has not completed. */
 mos_status mos_engine_result(mos_engine e, int64_t ticket, int32_t *status, double *rel_residual, int32_t *iters,
                              int32_t *sweeps);
+/* Engine options.  MOS_OPT_CELL_GEMM selects the cell-GEMM variant of the
+ * PCG matvec (the per-type product K_r * u_cell of eq. 20 over all cells):
+ * 1 = 16x16 output tiles with the contraction split over four waves (any
+ * basis size); 2 = K_r-stationary rows: each wave holds 16 rows of K_r in
+ * registers and streams consecutive 16-cell blocks (basis sizes padded to
+ * 32, 80 or 176, i.e. interpolation orders 2-4).  The default is 2 where it
+ * applies, else 1; asking for 2 elsewhere runs 1.  Set options before the first submission; results can
+ * differ in the last bits between variants, never between batch
+ * compositions. */
+enum { MOS_OPT_CELL_GEMM = 1 };
+mos_status mos_engine_option(mos_engine e, int option, int64_t value);
+
 /* Problems admitted and queued, and the arena capacities. */
 mos_status mos_engine_stats(mos_engine e, int64_t *active, int64_t *queued, int64_t *capacity_dofs,
                             int64_t *capacity_slots);
@@ -227,8 +239,10 @@ void mos_engine_destroy(mos_engine e);
 /* Kernel timing for measurement tools.  After mos_timing_start(ctx, k, every)
  * every `every`-th launch (every >= 1) of kernel k by this context is
  * bracketed by a pair of HIP events on the context stream; mos_timing_stop
- * synchronises the stream and returns the number of timed launches and their
- * summed duration in milliseconds, then stops timing.  One kernel at a time. */
+ * synchronises the stream and returns the number of timed launches, their
+ * summed duration in milliseconds and the number of launches of the kernel
+ * seen since the start (timed or not), then stops timing.  One kernel at a
+ * time. */
 enum {
     MOS_K_CELL_GEMM = 1,    /* element-by-element K_r GEMM of the PCG matvec */
     MOS_K_ASSEMBLE = 2,     /* node-centric sum of cell products (+ p.Ap) */
@@ -237,7 +251,7 @@ enum {
     MOS_K_COUNT = 5
 };
 mos_status mos_timing_start(mos_ctx ctx, int kernel, int every);
-mos_status mos_timing_stop(mos_ctx ctx, int64_t *launches, double *total_ms);
+mos_status mos_timing_stop(mos_ctx ctx, int64_t *launches, double *total_ms, int64_t *seen);
 
 void mos_cell_free(mos_cell cell);
 void mos_rom_free(mos_rom rom);

@@ -246,7 +246,7 @@ mos_status mos_timing_start(mos_ctx ctx, int kernel, int every) {
     return MOS_OK;
 }
 
-mos_status mos_timing_stop(mos_ctx ctx, int64_t *launches, double *total_ms) {
+mos_status mos_timing_stop(mos_ctx ctx, int64_t *launches, double *total_ms, int64_t *seen) {
     if (!ctx) {
         set_error("invalid context");
         return MOS_EINVAL;
@@ -260,6 +260,7 @@ mos_status mos_timing_stop(mos_ctx ctx, int64_t *launches, double *total_ms) {
     }
     if (launches) *launches = (int64_t)(ctx->ev_used / 2);
     if (total_ms) *total_ms = total;
+    if (seen) *seen = ctx->timed_seen;
     ctx->timed_kernel = 0;
     ctx->ev_used = 0;
     return MOS_OK;
@@ -579,6 +580,23 @@ mos_status mos_engine_result(mos_engine e, int64_t ticket, int32_t *status, doub
     delete P;
     e->finished.erase(it);
     return MOS_OK;
+}
+
+mos_status mos_engine_option(mos_engine e, int option, int64_t value) {
+    if (!e) {
+        set_error("invalid engine");
+        return MOS_EINVAL;
+    }
+    if (option == MOS_OPT_CELL_GEMM && (value == 1 || value == 2)) {
+        if (!e->active.empty() || !e->queue.empty()) {
+            set_error("engine options must be set before the first submission");
+            return MOS_EBUSY;
+        }
+        e->gemm_rows = value == 2;
+        return MOS_OK;
+    }
+    set_error("unknown option %d or value %lld", option, (long long)value);
+    return MOS_EINVAL;
 }
 
 mos_status mos_engine_stats(mos_engine e, int64_t *active, int64_t *queued, int64_t *capacity_dofs,

@@ -48,6 +48,7 @@ struct mos_engine_s {
     std::vector<mos_rom> roms;
     int ldk = 0, n = 0, n_elem = 0, n_eblk = 0;
     int cap_blk = 0, cap_sb = 0, ld_slots = 0;
+    bool gemm_rows = false;                   // cell GEMM variant (fixed per engine)
     mos::DeviceArena mem;
     // device arrays
     void *v[mos::NVEC] = {};                  // inner vectors (double or float)

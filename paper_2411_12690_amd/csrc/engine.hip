@@ -93,6 +93,44 @@ __device__ __forceinline__ void wave_sum3(const double *pa, const double *pb, co
     }
 }
 
+// Scalar step of iteration ps[p].it for one problem (one wave): fixed-order
+// sums of its dot-product partials, stop decision, and (alpha, beta).
+__device__ __forceinline__ void problem_step(ProbState &S, const double *pg, const double *pd, const double *pr) {
+    const int lane = threadIdx.x % 64;
+    if (!S.active || S.done) return;
+    const int it = S.it;
+    const double g_prev = S.gamma_prev, a_prev = S.alpha_prev;
+    double gamma, delta, rr;
+    wave_sum3(pg, pd, pr, S.blk_begin, S.blk_end, gamma, delta, rr);
+    if (lane != 0) return;
+    if (it == 0) S.tol2 = S.rtol2 * rr;
+    int stop = 0;
+    double alpha = 0.0, beta = 0.0;
+    if (rr <= S.tol2) {
+        stop = 1;
+    } else if (it >= S.max_iter) {
+        stop = 3;
+    } else {
+        if (it == 0) {
+            alpha = gamma / delta;
+        } else {
+            beta = gamma / g_prev;
+            alpha = gamma / (delta - beta * gamma / a_prev);
+        }
+        if (!(alpha > 0.0) || !isfinite(alpha) || !isfinite(beta)) stop = 2;
+    }
+    S.rr = rr;
+    if (stop) {
+        S.done = stop;
+    } else {
+        S.a_cur = alpha;
+        S.b_cur = beta;
+        S.gamma_prev = gamma;
+        S.alpha_prev = alpha;
+        S.it = it + 1;
+    }
+}
+
 constexpr int GEMM_WAVES = 4;       // split-K ways of the cell GEMM
 constexpr int GEMM_MAX_STEPS = 16;  // k-steps of 4 whose loads are issued together
 
@@ -113,41 +151,7 @@ __global__ __launch_bounds__(256) void k_bgemm(const void *const *kr_tab, const 
     if ((int)blockIdx.y >= n_sb) {
         if (blockIdx.x != 0) return;
         const int p = ((int)blockIdx.y - n_sb) * GEMM_WAVES + wave;
-        if (p >= n_probs) return;
-        ProbState &S = ps[p];
-        if (!S.active || S.done) return;
-        const int it = S.it;
-        const double g_prev = S.gamma_prev, a_prev = S.alpha_prev;
-        double gamma, delta, rr;
-        wave_sum3(pg, pd, pr, S.blk_begin, S.blk_end, gamma, delta, rr);
-        if (lane == 0) {
-            if (it == 0) S.tol2 = S.rtol2 * rr;
-            int stop = 0;
-            double alpha = 0.0, beta = 0.0;
-            if (rr <= S.tol2) {
-                stop = 1;
-            } else if (it >= S.max_iter) {
-                stop = 3;
-            } else {
-                if (it == 0) {
-                    alpha = gamma / delta;
-                } else {
-                    beta = gamma / g_prev;
-                    alpha = gamma / (delta - beta * gamma / a_prev);
-                }
-                if (!(alpha > 0.0) || !isfinite(alpha) || !isfinite(beta)) stop = 2;
-            }
-            S.rr = rr;
-            if (stop) {
-                S.done = stop;
-            } else {
-                S.a_cur = alpha;
-                S.b_cur = beta;
-                S.gamma_prev = gamma;
-                S.alpha_prev = alpha;
-                S.it = it + 1;
-            }
-        }
+        if (p < n_probs) problem_step(ps[p], pg, pd, pr);
         return;
     }
     const int sb = sb_base + (int)blockIdx.y;
@@ -188,6 +192,60 @@ __global__ __launch_bounds__(256) void k_bgemm(const void *const *kr_tab, const 
     if (wave == 0) {
 #pragma unroll
         for (int w = 0; w < GEMM_WAVES - 1; ++w) acc += red[w][lane];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Y[(size_t)(rb * 16 + Mfma<T>::row(lane, q)) * ld_slots + col] = acc[q];
+    }
+}
+
+// K_r-stationary variant: one wave per (16-row block of K_r, run of `spw`
+// consecutive slot blocks).  The wave keeps its 16 rows of K_r (KS k-steps of
+// 4) in registers, reloading them only when the cell type changes, and for
+// each slot block issues all KS operand loads before its chain of KS MFMAs.
+// Each 16x16 output is one MFMA chain in k order, so results do not depend
+// on spw.  Grid row 1 holds the per-problem scalar waves.
+template <class T, int KS>
+__global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, const int32_t *sb_rom,
+                                                    const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots,
+                                                    int sb_base, int n_sb, int spw, int gate, ProbState *ps,
+                                                    int n_probs, const double *pg, const double *pd,
+                                                    const double *pr) {
+    typedef typename Mfma<T>::v4 v4;
+    constexpr int ldk = 4 * KS;
+    constexpr int nrb = ldk / 16;
+    const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+    if (blockIdx.y == 1) {
+        const int p = (int)blockIdx.x * 4 + wave;
+        if (p < n_probs) problem_step(ps[p], pg, pd, pr);
+        return;
+    }
+    const int task = (int)blockIdx.x * 4 + wave;
+    const int rb = task % nrb, run = task / nrb;
+    const int s_begin = run * spw;
+    if (s_begin >= n_sb) return;
+    const int s_end = min(s_begin + spw, n_sb);
+    T a[KS], b[KS];
+    int cur = -1;
+    for (int sl = s_begin; sl < s_end; ++sl) {
+        const int sb = sb_base + sl;
+        const int rom = sb_rom[sb];
+        if (rom < 0) continue;
+        if (gate) {
+            const ProbState &S = ps[sb_prob[sb]];
+            if (!S.active || S.done) continue;
+        }
+        const T *bp = Mc + (size_t)(lane / 16) * ld_slots + sb * 16 + lane % 16;
+#pragma unroll
+        for (int k = 0; k < KS; ++k) b[k] = bp[(size_t)(4 * k) * ld_slots];
+        if (rom != cur) {
+            const T *ap = static_cast<const T *>(kr_tab[rom]) + (size_t)(lane / 16) * ldk + rb * 16 + lane % 16;
+#pragma unroll
+            for (int k = 0; k < KS; ++k) a[k] = ap[(size_t)(4 * k) * ldk];
+            cur = rom;
+        }
+        v4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < KS; ++k) acc = Mfma<T>::op(a[k], b[k], acc);
+        const int col = sb * 16 + lane % 16;
 #pragma unroll
         for (int q = 0; q < 4; ++q) Y[(size_t)(rb * 16 + Mfma<T>::row(lane, q)) * ld_slots + col] = acc[q];
     }
@@ -803,6 +861,9 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     MOS_HIP(hipMemcpyAsync(e->psi_tab, tp.data(), MAX_TYPES * 8, hipMemcpyHostToDevice, st));
     MOS_HIP(hipMemcpyAsync(e->sigt_tab, ts.data(), MAX_TYPES * 8, hipMemcpyHostToDevice, st));
     MOS_HIP(hipStreamSynchronize(st));
+    // The GEMM variant is fixed per engine (never per batch), so a problem's
+    // rounding does not depend on what else is in the batch.
+    e->gemm_rows = ldk / 4 == 8 || ldk / 4 == 20 || ldk / 4 == 44;
     e->blk.init(e->cap_blk);
     e->sbs.init(e->cap_sb);
     e->pids.init(MAX_PROBS);
@@ -887,6 +948,31 @@ void release_problem(mos_engine e, EngineProblem *P) {
 
 }  // namespace
 
+template <class T>
+mos_status launch_rows(mos_ctx ctx, int ks, dim3 grid, hipStream_t st, const void *const *kr_tab, const int32_t *sb_rom,
+                       const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots, int n_sb, int spw, ProbState *ps,
+                       int n_probs, const double *pg, const double *pd, const double *pr) {
+    switch (ks) {
+        case 8:
+            launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm_rows<T, 8>, grid, dim3(256), 0, st, kr_tab, sb_rom, sb_prob, Mc,
+                         Y, ld_slots, 0, n_sb, spw, 1, ps, n_probs, pg, pd, pr);
+            break;
+        case 20:
+            launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm_rows<T, 20>, grid, dim3(256), 0, st, kr_tab, sb_rom, sb_prob,
+                         Mc, Y, ld_slots, 0, n_sb, spw, 1, ps, n_probs, pg, pd, pr);
+            break;
+        case 44:
+            launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm_rows<T, 44>, grid, dim3(256), 0, st, kr_tab, sb_rom, sb_prob,
+                         Mc, Y, ld_slots, 0, n_sb, spw, 1, ps, n_probs, pg, pd, pr);
+            break;
+        default:
+            set_error("no rows GEMM for %d k-steps", ks);
+            return MOS_EINVAL;
+    }
+    MOS_LAUNCH_CHECK();
+    return MOS_OK;
+}
+
 // One round: admit, iterate a chunk, check stopped problems, retire finished.
 mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *completed) {
     mos_ctx ctx = e->ctx;
@@ -937,14 +1023,29 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
     if (any_iter) {
         const int hw_sb = e->sbs.high, hw_blk = e->blk.high, hw_p = e->pids.high;
         const dim3 g_gemm(e->ldk / 16, hw_sb + ceil_div(hw_p, GEMM_WAVES));
+        // Cell GEMM variant is fixed per engine; the rows variant picks how
+        // many slot blocks each wave streams from the batch size only (its
+        // results do not depend on that choice).
+        const int ks = e->ldk / 4;
+        const bool rows = e->gemm_rows && (ks == 8 || ks == 20 || ks == 44);
+        const int nrb = e->ldk / 16;
+        const int spw = std::max(1, (int)((int64_t)hw_sb * nrb / 2048));
+        const int64_t tasks = (int64_t)nrb * ceil_div(hw_sb, spw);
+        const dim3 g_rows((unsigned)std::max<int64_t>(ceil_div(tasks, 4), ceil_div(hw_p, 4)), 2);
         for (int j = 0; j < chunk; ++j) {
             if (e->precision == MOS_MIXED) {
                 float *V[NVEC];
                 for (int i = 0; i < NVEC; ++i) V[i] = static_cast<float *>(e->v[i]);
-                launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm<float>, g_gemm, dim3(256), 0, st,
-                             (const void *const *)e->kr32_tab, (const int32_t *)e->sb_rom, (const int32_t *)e->sb_prob,
-                             (const float *)e->Mc, (float *)e->Yi, e->ldk, e->ld_slots, 0, hw_sb, 1, e->ps, hw_p,
-                             (const double *)e->pg, (const double *)e->pd, (const double *)e->pr);
+                if (rows)
+                    MOS_TRY(launch_rows<float>(ctx, ks, g_rows, st, (const void *const *)e->kr32_tab, e->sb_rom, e->sb_prob,
+                                            (const float *)e->Mc, (float *)e->Yi, e->ld_slots, hw_sb, spw, e->ps, hw_p,
+                                            e->pg, e->pd, e->pr));
+                else
+                    launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm<float>, g_gemm, dim3(256), 0, st,
+                                 (const void *const *)e->kr32_tab, (const int32_t *)e->sb_rom,
+                                 (const int32_t *)e->sb_prob, (const float *)e->Mc, (float *)e->Yi, e->ldk,
+                                 e->ld_slots, 0, hw_sb, 1, e->ps, hw_p, (const double *)e->pg, (const double *)e->pd,
+                                 (const double *)e->pr);
                 launch_timed(ctx, MOS_K_PCG_UPDATE, k_bstep<float>, dim3(hw_blk), dim3(DB), 0, st,
                              (const float *)e->Yi, (const int32_t *)e->inc, (const uint8_t *)e->cmask,
                              (const float *)V[VDINV], V[VX], V[VR], V[VU], V[VW], V[VZ], V[VQ], V[VS], V[VP], V[VM],
@@ -953,10 +1054,16 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
             } else {
                 double *V[NVEC];
                 for (int i = 0; i < NVEC; ++i) V[i] = static_cast<double *>(e->v[i]);
-                launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm<double>, g_gemm, dim3(256), 0, st,
-                             (const void *const *)e->kr64_tab, (const int32_t *)e->sb_rom, (const int32_t *)e->sb_prob,
-                             (const double *)e->Mc, (double *)e->Yi, e->ldk, e->ld_slots, 0, hw_sb, 1, e->ps, hw_p,
-                             (const double *)e->pg, (const double *)e->pd, (const double *)e->pr);
+                if (rows)
+                    MOS_TRY(launch_rows<double>(ctx, ks, g_rows, st, (const void *const *)e->kr64_tab, e->sb_rom, e->sb_prob,
+                                            (const double *)e->Mc, (double *)e->Yi, e->ld_slots, hw_sb, spw, e->ps, hw_p,
+                                            e->pg, e->pd, e->pr));
+                else
+                    launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm<double>, g_gemm, dim3(256), 0, st,
+                                 (const void *const *)e->kr64_tab, (const int32_t *)e->sb_rom,
+                                 (const int32_t *)e->sb_prob, (const double *)e->Mc, (double *)e->Yi, e->ldk,
+                                 e->ld_slots, 0, hw_sb, 1, e->ps, hw_p, (const double *)e->pg, (const double *)e->pd,
+                                 (const double *)e->pr);
                 launch_timed(ctx, MOS_K_PCG_UPDATE, k_bstep<double>, dim3(hw_blk), dim3(DB), 0, st,
                              (const double *)e->Yi, (const int32_t *)e->inc, (const uint8_t *)e->cmask,
                              (const double *)V[VDINV], V[VX], V[VR], V[VU], V[VW], V[VZ], V[VQ], V[VS], V[VP], V[VM],

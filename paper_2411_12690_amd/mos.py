@@ -23,9 +23,11 @@ MOS_OUT_VM, MOS_OUT_SIGMA6 = 1, 2
 EXPORTED = ("mos_ctx_create", "mos_ctx_destroy", "mos_build_cell", "mos_reduce", "mos_solve_array",
             "mos_reconstruct", "mos_get_solution", "mos_query", "mos_cell_export", "mos_rom_export",
             "mos_array_layout", "mos_engine_create", "mos_engine_submit", "mos_engine_progress",
-            "mos_engine_result", "mos_engine_stats", "mos_engine_destroy", "mos_timing_start", "mos_timing_stop",
+            "mos_engine_result", "mos_engine_option", "mos_engine_stats", "mos_engine_destroy", "mos_timing_start", "mos_timing_stop",
             "mos_cell_free", "mos_rom_free", "mos_sol_free", "mos_last_error")
 MOS_K_CELL_GEMM, MOS_K_ASSEMBLE, MOS_K_PCG_UPDATE, MOS_K_RECON = 1, 2, 3, 4
+MOS_OPT_CELL_GEMM = 1
+GEMM_TILES, GEMM_ROWS = 1, 2
 
 
 class MosError(RuntimeError):
@@ -85,11 +87,12 @@ def _load():
         "mos_engine_progress": (ctypes.c_int, [vp, ctypes.c_int32, vp, ctypes.c_int32, P(ctypes.c_int32)]),
         "mos_engine_result": (ctypes.c_int, [vp, ctypes.c_int64, P(ctypes.c_int32), P(ctypes.c_double),
                                              P(ctypes.c_int32), P(ctypes.c_int32)]),
+        "mos_engine_option": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int64]),
         "mos_engine_stats": (ctypes.c_int, [vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64),
                                             P(ctypes.c_int64)]),
         "mos_engine_destroy": (None, [vp]),
         "mos_timing_start": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
-        "mos_timing_stop": (ctypes.c_int, [vp, P(ctypes.c_int64), P(ctypes.c_double)]),
+        "mos_timing_stop": (ctypes.c_int, [vp, P(ctypes.c_int64), P(ctypes.c_double), P(ctypes.c_int64)]),
         "mos_cell_free": (None, [vp]),
         "mos_rom_free": (None, [vp]),
         "mos_sol_free": (None, [vp]),
@@ -273,7 +276,7 @@ class Engine:
     """Batched / served global stage (mos_engine_*): submit problems, call
     progress() until their tickets complete."""
 
-    def __init__(self, ctx, roms, mixed=False, device_bytes=8 << 30):
+    def __init__(self, ctx, roms, mixed=False, device_bytes=8 << 30, gemm=None):
         self.ctx = ctx
         self.roms = list(roms)
         self.mixed = mixed
@@ -283,6 +286,8 @@ class Engine:
         _check(lib().mos_engine_create(ctx.ptr, _rom_array(roms), len(roms), MOS_MIXED if mixed else MOS_FP64,
                                        int(device_bytes), ctypes.byref(h)), "mos_engine_create")
         self.ptr = h
+        if gemm is not None:
+            self.option(MOS_OPT_CELL_GEMM, gemm)
 
     def submit(self, nx_cells, ny_cells, cell_type, delta_T, vm=None, sigma6=None, u=None, **kw):
         d, keep = array_desc(nx_cells, ny_cells, cell_type, delta_T, mixed=self.mixed, **kw)
@@ -308,6 +313,9 @@ class Engine:
         self._keep.pop(ticket, None)
         self.last_error = lib().mos_last_error().decode(errors="replace") if st.value != MOS_OK else ""
         return st.value, res.value, it.value, sw.value
+
+    def option(self, option, value):
+        _check(lib().mos_engine_option(self.ptr, option, int(value)), "mos_engine_option")
 
     def stats(self):
         a, q, cd, cs = (ctypes.c_int64() for _ in range(4))
@@ -341,6 +349,10 @@ def mos_engine_progress(engine, iterations=16):
 
 def mos_engine_result(engine, ticket):
     return engine.result(ticket)
+
+
+def mos_engine_option(engine, option, value):
+    engine.option(option, value)
 
 
 def mos_engine_stats(engine):
@@ -428,8 +440,9 @@ def mos_timing_start(ctx, kernel, every=1):
 
 
 def mos_timing_stop(ctx):
-    """Returns (launches, total milliseconds) of the timed kernel."""
+    """Returns (timed launches, their total milliseconds, launches seen)."""
     n = ctypes.c_int64()
     ms = ctypes.c_double()
-    _check(lib().mos_timing_stop(ctx.ptr, ctypes.byref(n), ctypes.byref(ms)), "mos_timing_stop")
-    return n.value, ms.value
+    seen = ctypes.c_int64()
+    _check(lib().mos_timing_stop(ctx.ptr, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(seen)), "mos_timing_stop")
+    return n.value, ms.value, seen.value

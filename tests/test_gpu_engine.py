@@ -51,9 +51,9 @@ def n_dofs_of(nx, ny):
     return 3 * (X * Y * 4 - nx * ny * 1 * 1 * 2)
 
 
-def run_engine(env, probs, mixed=False, budget=1 << 28, iterations=16, interleave=None):
+def run_engine(env, probs, mixed=False, budget=1 << 28, iterations=16, interleave=None, gemm=None):
     mos, ctx, roms, oroms, torch = env
-    eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=budget)
+    eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=budget, gemm=gemm)
     dt = torch.float32 if mixed else torch.float64
     n_elem = roms[0].query(mos.MOS_Q_CELL_ELEMS)
     outs = {}
@@ -84,10 +84,11 @@ def run_engine(env, probs, mixed=False, budget=1 << 28, iterations=16, interleav
     return [done[i] for i in range(len(probs))]
 
 
-def test_batch_of_uneven_arrays_matches_oracle(env):
+@pytest.mark.parametrize("gemm", [1, 2], ids=["tiles", "rows"])
+def test_batch_of_uneven_arrays_matches_oracle(env, gemm):
     mos, ctx, roms, oroms, torch = env
     probs = problems(1, [(3, 2), (1, 1), (5, 4), (2, 7), (4, 4)])
-    res = run_engine(env, probs)
+    res = run_engine(env, probs, gemm=gemm)
     for (nx, ny, t, dT), (st, rel, it, sw, vm, u) in zip(probs, res):
         assert st == 0 and rel <= 1e-12
         u_ref, vm_ref = oracle_solution(oroms, nx, ny, t, dT)
@@ -95,21 +96,23 @@ def test_batch_of_uneven_arrays_matches_oracle(env):
         assert np.abs(vm - vm_ref).max() <= 1e-9 * np.abs(vm_ref).max()
 
 
-@pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "mixed"])
-def test_result_is_the_same_alone_and_in_the_mix(env, mixed):
+@pytest.mark.parametrize("mixed,gemm", [(False, 1), (True, 1), (False, 2), (True, 2)],
+                         ids=["fp64-tiles", "mixed-tiles", "fp64-rows", "mixed-rows"])
+def test_result_is_the_same_alone_and_in_the_mix(env, mixed, gemm):
     probs = problems(2, [(4, 3), (2, 2), (6, 5), (3, 3)])
-    mix = run_engine(env, probs, mixed=mixed)
+    mix = run_engine(env, probs, mixed=mixed, gemm=gemm)
     for i in (0, 2):
-        alone = run_engine(env, [probs[i]], mixed=mixed)[0]
+        alone = run_engine(env, [probs[i]], mixed=mixed, gemm=gemm)[0]
         assert np.array_equal(alone[5], mix[i][5]), "reduced displacement differs"
         assert np.array_equal(alone[4], mix[i][4]), "von Mises differs"
         assert alone[2] == mix[i][2]
 
 
-def test_mixed_precision_batch_within_tolerance(env):
+@pytest.mark.parametrize("gemm", [1, 2], ids=["tiles", "rows"])
+def test_mixed_precision_batch_within_tolerance(env, gemm):
     mos, ctx, roms, oroms, torch = env
     probs = problems(3, [(5, 5), (2, 3), (7, 2)])
-    res = run_engine(env, probs, mixed=True)
+    res = run_engine(env, probs, mixed=True, gemm=gemm)
     for (nx, ny, t, dT), (st, rel, it, sw, vm, u) in zip(probs, res):
         assert st == 0 and rel <= 1e-10
         u_ref, vm_ref = oracle_solution(oroms, nx, ny, t, dT)
