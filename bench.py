@@ -33,6 +33,7 @@ TIME_EVERY = 16
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
 
 
 def per_iteration_work(kernel, mos, n, n_cells, n_dofs_pad, n_nodes, mixed):
@@ -50,7 +51,8 @@ def per_iteration_work(kernel, mos, n, n_cells, n_dofs_pad, n_nodes, mixed):
 KERNEL_INFO = {  # kernel id -> (name, bound, unit, note)
     1: ("k_bgemm", "mfma", "TFLOP/s", "2 n^2 flops per cell and iteration (K_r GEMM of the PCG matvec)"),
     3: ("k_bstep", "hbm", "GB/s", "2 n w per cell + (19 w + 1) per DoF + 16 per node and iteration"),
-    4: ("k_brecon", "mfma", "TFLOP/s", "2*6*n_elem*n flops per cell (stress GEMM)"),
+    4: ("k_brecon", "mfma", "TFLOP/s", "2*6*n_elem*n flops per cell (stress GEMM; the BF16 form issues 3x "
+        "these on MFMA for its hi/lo split)"),
 }
 
 
@@ -84,6 +86,7 @@ def cpu_baseline(case):
 
 def batch_mode(args, mos, torch, np, W):
     B = args.batch
+    mixed = args.precision == "mixed"
     cases = [W.case_c2(args.seed + i) for i in range(B)]
     diam = [4.0, 5.0, 6.0]
     spec0 = cases[0].specs[0]
@@ -101,9 +104,10 @@ def batch_mode(args, mos, torch, np, W):
     n_nodes = X * X * 4 - n_cells * 2 * 2 * 2
     n_dofs = 3 * n_nodes
     n_dofs_pad = -(-n_dofs // 768) * 768
-    eng = mos.Engine(ctx, roms, mixed=False, device_bytes=int(B * (n_dofs_pad * 140 + n_cells * 16 * 176 * 34)
+    eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=int(B * (n_dofs_pad * 140 + n_cells * 16 * 176 * 34)
                                                              * 1.3) + (64 << 20))
-    vms = [torch.empty((n_cells, n_elem), dtype=torch.float64, device="cuda") for _ in range(B)]
+    vms = [torch.empty((n_cells, n_elem), dtype=torch.float32 if mixed else torch.float64, device="cuda")
+           for _ in range(B)]
     types = [np.full(n_cells, diam.index(c.specs[0].tsv_diameter), dtype=np.uint8) for c in cases]
 
     def step(record=None):
@@ -156,11 +160,14 @@ def batch_mode(args, mos, torch, np, W):
     name, bound, unit, note = KERNEL_INFO[dominant]
     if dominant == mos.MOS_K_RECON:
         work = 2.0 * 6 * n_elem * n * n_cells * B * args.steps
-        peak = PEAK_FP64_TFLOPS
+        peak = PEAK_BF16_TFLOPS if mixed else PEAK_FP64_TFLOPS
     else:
-        per_it = per_iteration_work(dominant, mos, n, n_cells, n_dofs_pad, n_nodes, False)
+        per_it = per_iteration_work(dominant, mos, n, n_cells, n_dofs_pad, n_nodes, mixed)
         work = per_it * sum(iters)
-        peak = PEAK_FP64_TFLOPS if bound == "mfma" else PEAK_HBM_GBS
+        if bound == "mfma":
+            peak = PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS
+        else:
+            peak = PEAK_HBM_GBS
     avg_s = k_ms / max(launches, 1) / 1e3
     work_per_launch = work / max(seen, 1)
     achieved = work_per_launch / avg_s / (1e12 if unit == "TFLOP/s" else 1e9)
@@ -188,7 +195,7 @@ def batch_mode(args, mos, torch, np, W):
     if not args.no_cpu_baseline:
         cpu, vm_ref = cpu_baseline(cases[0])
         step()
-        err = float(np.abs(vms[0].cpu().numpy() - vm_ref).max() / np.abs(vm_ref).max())
+        err = float(np.abs(vms[0].double().cpu().numpy() - vm_ref).max() / np.abs(vm_ref).max())
 
     out = {
         "metric": METRIC,
@@ -201,14 +208,14 @@ def batch_mode(args, mos, torch, np, W):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+bf16+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": f"batch of {B} independent 16x16 TSV arrays (one C2-shaped run per seed)",
                    "arrays_per_step": B, "cells_per_step": B * n_cells, "array": "16x16",
                    "cell_um": [spec0.pitch_x, spec0.pitch_y, spec0.height], "cell_mesh": list(spec0.mesh),
                    "tsv_diameter_um": "per array from {4,5,6}", "interp": list(spec0.interp), "n": n,
                    "reduced_dofs_per_array": int(n_dofs), "delta_T": -250.0, "bc": "bottom clamped",
-                   "precision": "fp64", "seed": args.seed, "pcg_chunk": args.chunk},
+                   "precision": args.precision, "seed": args.seed, "pcg_chunk": args.chunk},
         "p50_ms": round(float(np.percentile(lat, 50)), 4),
         "p99_ms": round(float(np.percentile(lat, 99)), 4),
         "latency_is": "per array, submission to completion of solve + reconstruction",
@@ -324,6 +331,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--mode", choices=["batch", "serve"], default="batch")
     ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--chunk", type=int, default=16)
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--budget-gb", type=float, default=32.0)

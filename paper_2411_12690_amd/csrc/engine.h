@@ -67,6 +67,7 @@ struct mos_engine_s {
     double *scale_host = nullptr;             // pinned staging of `scale`
     void **kr64_tab = nullptr, **kr32_tab = nullptr;
     double **br_tab = nullptr, **psi_tab = nullptr, **sigt_tab = nullptr;
+    void *ub = nullptr;  // BF16 split of a finished problem's cell block (mixed reconstruction)
     // host state
     mos::RangeAlloc blk, sbs, pids;
     int64_t next_ticket = 0;

@@ -40,6 +40,9 @@ enum : uint32_t { KIND_CELL = 0x4c4c4543u, KIND_ROM = 0x214d4f52u, KIND_SOL = 0x
 
 // Tile edge of the banded Cholesky factor (64 x 64 FP64 tiles).
 constexpr int NB = 64;
+// Largest number of 32-wide k-steps (basis size <= 384) for which the BF16
+// reconstruction keeps one element block of Psi (hi and lo) in LDS.
+constexpr int RECON_BF16_MAX_KS = 12;
 
 // A set of device allocations released together.
 struct DeviceArena {
@@ -130,8 +133,9 @@ struct mos_rom_s {
     float *kr32_pad = nullptr;    // FP32 copy of kr_pad
     double *psi = nullptr;        // [n_eblk][6][ldk][16] centroid stress basis
     double *sig_t = nullptr;      // [n_elem][6] unit-dT thermal stress at centroids
-    uint16_t *psi_hi = nullptr;   // bf16 split of psi, MFMA operand layout
-    uint16_t *psi_lo = nullptr;
+    int nks = 0;                  // 32-wide k-steps of the BF16 reconstruction GEMM
+    uint16_t *psi_hi = nullptr;   // BF16 split of psi in MFMA A-operand order
+    uint16_t *psi_lo = nullptr;   //   [n_eblk][6][nks][64][8]; null if nks > RECON_BF16_MAX_KS
 };
 
 struct mos_sol_s {
@@ -168,6 +172,14 @@ mos_status band_solve(mos_cell c, const double *dinv, double *rhs, int ldr, int 
 mos_status reduce_cell(mos_cell c, mos_rom r);
 // recon.hip
 mos_status reconstruct(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void *sigma6);
+// BF16-split MFMA reconstruction (FP32 outputs) of the slot blocks
+// [sb_begin, sb_begin + tseg[n_types]) of the FP64 cell-major block U
+// ([ldk][ld]); type t owns [sb_begin + tseg[t], sb_begin + tseg[t + 1]).
+// Needs roms with psi_hi (nks <= RECON_BF16_MAX_KS), else MOS_EINVAL, and a
+// device scratch of recon_bf16_scratch(rom, tseg[n_types]) bytes.
+int64_t recon_bf16_scratch(const mos_rom r, int n_sb);
+mos_status recon_bf16(mos_ctx ctx, const mos_rom *roms, int n_types, const int *tseg, const double *U, int ld,
+                      const int32_t *perm, int sb_begin, double dT, float *vm, float *sig6, void *scratch);
 
 // ---- host helpers (api.cpp) ----
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }

@@ -10,6 +10,7 @@
 // D[l/16 + 4q][l%16] in register q.
 #include <cmath>
 
+#include "bf16.h"
 #include "mesh.h"
 #include "mos_internal.h"
 
@@ -84,7 +85,173 @@ __global__ __launch_bounds__(256) void k_recon_f64(ReconTable tt, const double *
     }
 }
 
+// Reduced-precision form of the same GEMM: BF16 operands, FP32 accumulation
+// on the 16x16x32 MFMA.  Plain BF16 rounding of Psi and u loses too much to
+// the cancellation inside Psi u, so both operands are split into hi + lo
+// BF16 halves and three products are kept (hi*hi + hi*lo + lo*hi).
+// Lane l supplies A[l%16][8(l/16)+v] and B[8(l/16)+v][l%16] (v = 0..7) and
+// receives D[4(l/16)+q][l%16] in register q, so each lane ends with all six
+// components of four consecutive elements of one cell.
+
+// B fragments of a problem's slot blocks: Ub[sb][ks][lane] holds cell
+// 16 sb + l%16, DoFs 32 ks + 8 (l/16) + 0..7, split into hi and lo.
+__global__ void k_split_u(const double *U, int ld, int sb_begin, int n_sb, int ldk, int nks, bf16x8 *ub_hi,
+                          bf16x8 *ub_lo) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_sb * nks * 64) return;
+    const int lane = (int)(i % 64), ks = (int)((i / 64) % nks);
+    const int64_t sb = i / (64 * nks);
+    const size_t slot = (size_t)(sb_begin + sb) * 16 + lane % 16;
+    u16x8 h, l;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const int k = ks * 32 + 8 * (lane / 16) + v;
+        const double x = k < ldk ? U[(size_t)k * ld + slot] : 0.0;
+        uint16_t xh, xl;
+        bf16_split(x, xh, xl);
+        h[v] = xh;
+        l[v] = xl;
+    }
+    ub_hi[i] = __builtin_bit_cast(bf16x8, h);
+    ub_lo[i] = __builtin_bit_cast(bf16x8, l);
+}
+
+// One workgroup per (element block of 16, slice of one type's slot blocks).
+// The workgroup stages its element block of Psi_hi and Psi_lo (6 components
+// x nks k-steps x 1 KB each) in LDS once; its four waves then stream the
+// slice CB slot blocks at a time, each LDS fragment feeding 3 CB MFMAs.
+template <int KSMAX, int CB>
+__global__ __launch_bounds__(256, KSMAX <= 6 ? 2 : 1) void k_recon_bf16(const bf16x8 *psi_hi, const bf16x8 *psi_lo,
+                                                       const double *sig_t, const bf16x8 *ub_hi,
+                                                       const bf16x8 *ub_lo, const int32_t *perm, int sb_first,
+                                                       int ub_first, int n_sb, int chunk, int nks, int n_elem,
+                                                       double dT, float *vm, float *sig6) {
+    __shared__ bf16x8 lds[2][6][KSMAX][64];
+    const int eb = blockIdx.x;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int y0 = blockIdx.y * chunk, y1 = min(y0 + chunk, n_sb);
+    {
+        const bf16x8 *gh = psi_hi + (size_t)eb * 6 * nks * 64;
+        const bf16x8 *gl = psi_lo + (size_t)eb * 6 * nks * 64;
+        for (int i = threadIdx.x; i < 6 * nks * 64; i += 256) {
+            const int c = i / (nks * 64), r = i % (nks * 64);
+            lds[0][c][r / 64][r % 64] = gh[i];
+            lds[1][c][r / 64][r % 64] = gl[i];
+        }
+    }
+    __syncthreads();
+    for (int base = y0 + wave * CB; base < y1; base += 4 * CB) {
+        f32x4 acc[CB][6];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) acc[cb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KSMAX; ++ks) {
+            if (ks < nks) {
+                bf16x8 bh[CB], bl[CB];
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    // Past the slice end: reread the last valid block, results unused.
+                    const size_t f = ((size_t)(ub_first + min(base + cb, y1 - 1)) * nks + ks) * 64 + lane;
+                    bh[cb] = ub_hi[f];
+                    bl[cb] = ub_lo[f];
+                }
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    const bf16x8 ah = lds[0][c][ks][lane], al = lds[1][c][ks][lane];
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) {
+                        acc[cb][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[cb], acc[cb][c], 0, 0, 0);
+                        acc[cb][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[cb], acc[cb][c], 0, 0, 0);
+                        acc[cb][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[cb], acc[cb][c], 0, 0, 0);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            if (base + cb >= y1) continue;
+            const int cell = perm[(size_t)(sb_first + base + cb) * 16 + lane % 16];
+            if (cell < 0) continue;
+            const int e0 = eb * 16 + 4 * (lane / 16);
+            float vq[4], sq[4][6];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = min(e0 + q, n_elem - 1);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) sq[q][c] = acc[cb][c][q] + (float)(dT * sig_t[(size_t)e * 6 + c]);
+                const float a = sq[q][0] - sq[q][1], b = sq[q][1] - sq[q][2], d = sq[q][2] - sq[q][0];
+                vq[q] = sqrtf(0.5f * (a * a + b * b + d * d) +
+                              3.0f * (sq[q][3] * sq[q][3] + sq[q][4] * sq[q][4] + sq[q][5] * sq[q][5]));
+            }
+            const size_t o = (size_t)cell * n_elem + e0;
+            const bool whole = e0 + 3 < n_elem && o % 4 == 0;
+            if (vm) {
+                if (whole) {
+                    *(f32x4 *)(vm + o) = f32x4{vq[0], vq[1], vq[2], vq[3]};
+                } else {
+                    for (int q = 0; q < 4; ++q)
+                        if (e0 + q < n_elem) vm[o + q] = vq[q];
+                }
+            }
+            if (sig6) {
+                if (whole) {
+#pragma unroll
+                    for (int j = 0; j < 6; ++j)
+                        *(f32x4 *)(sig6 + o * 6 + 4 * j) =
+                            f32x4{sq[(4 * j) / 6][(4 * j) % 6], sq[(4 * j + 1) / 6][(4 * j + 1) % 6],
+                                  sq[(4 * j + 2) / 6][(4 * j + 2) % 6], sq[(4 * j + 3) / 6][(4 * j + 3) % 6]};
+                } else {
+                    for (int q = 0; q < 4; ++q)
+                        if (e0 + q < n_elem)
+                            for (int c = 0; c < 6; ++c) sig6[(o + q) * 6 + c] = sq[q][c];
+                }
+            }
+        }
+    }
+}
+
 }  // namespace
+
+int64_t recon_bf16_scratch(const mos_rom r, int n_sb) { return (int64_t)n_sb * r->nks * 64 * 2 * 16; }
+
+mos_status recon_bf16(mos_ctx ctx, const mos_rom *roms, int n_types, const int *tseg, const double *U, int ld,
+                      const int32_t *perm, int sb_begin, double dT, float *vm, float *sig6, void *scratch) {
+    if (n_types < 1 || n_types > MAX_TYPES) return MOS_EINVAL;
+    const mos_rom r = roms[0];
+    for (int t = 0; t < n_types; ++t)
+        if (!roms[t]->psi_hi || roms[t]->nks != r->nks || roms[t]->n_eblk != r->n_eblk) return MOS_EINVAL;
+    const int total = tseg[n_types];
+    if (total <= 0) return MOS_OK;
+    hipStream_t st = ctx->stream;
+    bf16x8 *ub_hi = (bf16x8 *)scratch, *ub_lo = ub_hi + (size_t)total * r->nks * 64;
+    const int64_t nfrag = (int64_t)total * r->nks * 64;
+    hipLaunchKernelGGL(k_split_u, dim3(ceil_div(nfrag, 256)), dim3(256), 0, st, U, ld, sb_begin, total, r->ldk,
+                       r->nks, ub_hi, ub_lo);
+    MOS_LAUNCH_CHECK();
+    for (int t = 0; t < n_types; ++t) {
+        const int n_sb = tseg[t + 1] - tseg[t];
+        if (n_sb <= 0) continue;
+        // Slices of the slot range give >= ~2048 workgroups for large
+        // problems while each slice still streams >= 32 slot blocks per
+        // staged block of Psi.
+        const int ny = std::max(1, std::min(n_sb / 32, ceil_div(2048, r->n_eblk)));
+        const int chunk = ceil_div(n_sb, ny);
+        const dim3 grid(r->n_eblk, ceil_div(n_sb, chunk));
+        const bf16x8 *ph = (const bf16x8 *)roms[t]->psi_hi, *pl = (const bf16x8 *)roms[t]->psi_lo;
+        if (r->nks <= 6)
+            launch_timed(ctx, MOS_K_RECON, k_recon_bf16<6, 4>, grid, dim3(256), 0, st, ph, pl,
+                         (const double *)roms[t]->sig_t, (const bf16x8 *)ub_hi, (const bf16x8 *)ub_lo, perm,
+                         sb_begin + tseg[t], tseg[t], n_sb, chunk, r->nks, r->n_elem, dT, vm, sig6);
+        else
+            launch_timed(ctx, MOS_K_RECON, k_recon_bf16<RECON_BF16_MAX_KS, 2>, grid, dim3(256), 0, st, ph, pl,
+                         (const double *)roms[t]->sig_t, (const bf16x8 *)ub_hi, (const bf16x8 *)ub_lo, perm,
+                         sb_begin + tseg[t], tseg[t], n_sb, chunk, r->nks, r->n_elem, dT, vm, sig6);
+        MOS_LAUNCH_CHECK();
+    }
+    return MOS_OK;
+}
 
 mos_status reconstruct(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void *sigma6) {
     hipStream_t st = ctx->stream;
@@ -109,7 +276,14 @@ mos_status reconstruct(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void 
     dim3 grid(s->n_eblk, ceil_div(s->n_pc / 16, 4));
     void *v = (outputs & MOS_OUT_VM) ? vm : nullptr;
     void *g = (outputs & MOS_OUT_SIGMA6) ? sigma6 : nullptr;
-    if (s->precision == MOS_FP64)
+    if (s->precision == MOS_MIXED && s->roms[0]->psi_hi) {
+        std::vector<int> tseg(s->n_types + 1);
+        for (int t = 0; t <= s->n_types; ++t) tseg[t] = s->seg[t] / 16;
+        void *scratch = nullptr;
+        MOS_TRY(tmp.alloc((size_t)recon_bf16_scratch(s->roms[0], s->n_pc / 16), &scratch));
+        MOS_TRY(recon_bf16(ctx, s->roms.data(), s->n_types, tseg.data(), U, s->n_pc, s->perm, 0, s->delta_T,
+                           (float *)v, (float *)g, scratch));
+    } else if (s->precision == MOS_FP64)
         launch_timed(ctx, MOS_K_RECON, k_recon_f64<double>, grid, dim3(256), 0, st, tt, (const double *)U,
                      (const int32_t *)s->perm, s->n_pc, s->ldk, s->n_elem, s->delta_T, (double *)v, (double *)g);
     else

@@ -9,6 +9,7 @@
 //   4. the centroid stress basis Psi = D B0 Phi and the unit-dT thermal
 //      stress sigma_T = D B0 f_T - beta 1 (eq. 1 at element centroids), laid
 //      out as the A operand of the reconstruction GEMM.
+#include "bf16.h"
 #include "mos_internal.h"
 
 #include <algorithm>
@@ -213,6 +214,22 @@ __global__ void k_stress_basis(const double *phi, int ldp, const uint8_t *mat, c
     }
 }
 
+// BF16 hi/lo split of Psi in the A-operand order of the 16x16x32 MFMA:
+// [n_eblk][6][nks][64 lanes][8], lane l of k-step ks holding element
+// 16 eb + l % 16 and columns 32 ks + 8 (l / 16) + 0..7 (zero past ldk).
+__global__ void k_psi_split(const double *psi, int ldk, int nks, int64_t total, uint16_t *hi, uint16_t *lo) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int v = (int)(idx % 8), lane = (int)((idx / 8) % 64), ks = (int)((idx / 512) % nks);
+    const int64_t ebc = idx / (512 * (int64_t)nks);  // eb * 6 + component
+    const int k = ks * 32 + 8 * (lane / 16) + v;
+    const double x = k < ldk ? psi[((size_t)ebc * ldk + k) * 16 + lane % 16] : 0.0;
+    uint16_t h, l;
+    bf16_split(x, h, l);
+    hi[idx] = h;
+    lo[idx] = l;
+}
+
 }  // namespace
 
 mos_status band_cholesky(mos_cell c, double *dinv, int *status_dev, int *not_spd);
@@ -321,6 +338,15 @@ mos_status reduce_cell(mos_cell c, mos_rom r) {
                        st, r->phi, ldp, c->mat, c->mprop, r->psi, r->sig_t, c->mx, c->my, c->mz,
                        d.pitch_x / c->mx, d.pitch_y / c->my, d.height / c->mz, n, ldk, r->n_eblk);
     MOS_LAUNCH_CHECK();
+    r->nks = ceil_div(ldk, 32);
+    if (r->nks <= RECON_BF16_MAX_KS) {
+        const int64_t total = (int64_t)r->n_eblk * 6 * r->nks * 512;
+        MOS_TRY(m.alloc_n(total, &r->psi_hi));
+        MOS_TRY(m.alloc_n(total, &r->psi_lo));
+        hipLaunchKernelGGL(k_psi_split, dim3(ceil_div(total, 256)), dim3(256), 0, st, (const double *)r->psi, ldk,
+                           r->nks, total, r->psi_hi, r->psi_lo);
+        MOS_LAUNCH_CHECK();
+    }
 
     // Health check of the projection: f_T^T K Phi should vanish (Phi^T K f_T = 0).
     std::vector<double> Ph((size_t)(n + 1) * (n + 1));
