@@ -110,14 +110,21 @@ def batch_mode(args, mos, torch, np, W):
            for _ in range(B)]
     types = [np.full(n_cells, diam.index(c.specs[0].tsv_diameter), dtype=np.uint8) for c in cases]
 
+    host = {"submit_s": 0.0, "progress_calls": 0, "steps": 0}
+
     def step(record=None):
         tks = {}
         ts = time.perf_counter()
         for i, c in enumerate(cases):
             tks[eng.submit(c.nx_cells, c.ny_cells, types[i], c.delta_T, vm=vms[i])] = i
+        if record is not None:
+            host["submit_s"] += time.perf_counter() - ts
+            host["steps"] += 1
         left = set(tks)
         info = {}
         while left:
+            if record is not None:
+                host["progress_calls"] += 1
             for tk in eng.progress(args.chunk):
                 st, rel, it, sw = eng.result(tk)
                 if st != 0:
@@ -223,6 +230,8 @@ def batch_mode(args, mos, torch, np, W):
         "pcg_iters_mean": round(float(np.mean(iters)), 1),
         "refinement_sweeps_mean": round(float(np.mean(sweeps)), 2),
         "local_stage_ms_per_cell_type": round(local_ms, 2),
+        "host": {"submit_ms_per_step": round(host["submit_s"] * 1e3 / max(host["steps"], 1), 3),
+                 "progress_calls_per_step": round(host["progress_calls"] / max(host["steps"], 1), 1)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "max_rel_err_vm_vs_oracle": err,
