@@ -240,6 +240,130 @@ def batch_mode(args, mos, torch, np, W):
     print(json.dumps(out))
 
 
+def outer_prescribed(mos, ctx, rom, case, np):
+    """Prescribed reduced DoFs for a displacement field on all six outer
+    faces, evaluated at the library's own reduced-node coordinates."""
+    coords, _, _, _ = mos.mos_array_layout(ctx, case.nx_cells, case.ny_cells, rom)
+    sp = case.specs[0]
+    L = np.array([case.nx_cells * sp.pitch_x, case.ny_cells * sp.pitch_y, sp.height])
+    tol = 1e-9 * L
+    outer = np.nonzero(np.any((np.abs(coords) <= tol) | (np.abs(coords - L) <= tol), axis=1))[0]
+    vals = case.field(coords[outer])
+    dofs = (3 * outer[:, None] + np.arange(3)[None, :]).ravel()
+    return dofs.astype(np.int64), vals.ravel()
+
+
+def single_mode(args, mos, torch, np, W):
+    """One large array (C3- or C5-shaped) through the engine, plain FP64 and
+    mixed precision side by side, each with its dominant kernel's roofline."""
+    case = {"c3": W.case_c3, "c5": W.case_c5}[args.workload](args.seed)
+    ctx = mos.Context(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    roms = [mos.mos_reduce(ctx, mos.mos_build_cell(ctx, s)) for s in case.specs]
+    torch.cuda.synchronize()
+    local_ms = (time.perf_counter() - t0) * 1e3
+    n = roms[0].query(mos.MOS_Q_N)
+    n_elem = roms[0].query(mos.MOS_Q_CELL_ELEMS)
+    kw = dict(clamp_bottom=case.clamp_bottom, clamp_top=case.clamp_top)
+    if case.field is not None:
+        kw["prescribed_dofs"], kw["prescribed_values"] = outer_prescribed(mos, ctx, roms[0], case, np)
+    coords, _, _, _ = mos.mos_array_layout(ctx, case.nx_cells, case.ny_cells, roms[0])
+    n_nodes = coords.shape[0]
+    n_dofs = 3 * n_nodes
+    n_dofs_pad = -(-n_dofs // 768) * 768
+    n_cells = case.n_cells
+    paths = {}
+    vm_out = {}
+    for prec in ("fp64", "mixed"):
+        mixed = prec == "mixed"
+        w = 4 if mixed else 8
+        budget = int((n_dofs_pad * 160 + n_cells * 16 * 176 * (2 * w + 24)) * 1.3) + (256 << 20)
+        eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=budget)
+        vm = torch.empty((n_cells, n_elem), dtype=torch.float32 if mixed else torch.float64, device="cuda")
+
+        def run():
+            tk = eng.submit(case.nx_cells, case.ny_cells, case.cell_type, case.delta_T, vm=vm, **kw)
+            while tk not in eng.progress(args.chunk):
+                pass
+            return eng.result(tk)
+
+        for _ in range(args.warmup):
+            run()
+        totals = {}
+        for k in (mos.MOS_K_CELL_GEMM, mos.MOS_K_PCG_UPDATE, mos.MOS_K_RECON):
+            mos.mos_timing_start(ctx, k, 1)
+            run()
+            totals[k] = mos.mos_timing_stop(ctx)
+        dominant = max(totals, key=lambda k: totals[k][1])
+        mos.mos_timing_start(ctx, dominant, TIME_EVERY)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        res = [run() for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t1) / args.steps
+        launches, k_ms, seen = mos.mos_timing_stop(ctx)
+        st, rel, iters, sweeps = res[-1]
+        if st != 0:
+            raise RuntimeError(f"{prec} solve failed with status {st}: {eng.last_error}")
+        name, bound, unit, note = KERNEL_INFO[dominant]
+        if dominant == mos.MOS_K_RECON:
+            work = 2.0 * 6 * n_elem * n * n_cells * args.steps
+            peak = PEAK_BF16_TFLOPS if mixed else PEAK_FP64_TFLOPS
+        else:
+            work = per_iteration_work(dominant, mos, n, n_cells, n_dofs_pad, n_nodes, mixed) * \
+                sum(r[2] for r in res)
+            peak = (PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS) if bound == "mfma" else PEAK_HBM_GBS
+        avg_s = k_ms / max(launches, 1) / 1e3
+        achieved = work / max(seen, 1) / avg_s / (1e12 if unit == "TFLOP/s" else 1e9)
+        paths[prec] = {
+            "value": round(n_cells / wall, 2), "ms_per_solve": round(wall * 1e3, 3), "pcg_iters": iters,
+            "refinement_sweeps": sweeps, "rel_residual": rel,
+            "roofline": {"bound": bound, "achieved": round(achieved, 4), "peak": peak, "unit": unit,
+                         "frac": round(achieved / peak, 5), "traffic": None, "kernel": name,
+                         "avg_launch_us": round(avg_s * 1e6, 3), "timed_launches": int(launches),
+                         "launches": int(seen), "work_per_launch": round(work / max(seen, 1), 1),
+                         "work_note": note,
+                         "kernels_ms_per_solve": {KERNEL_INFO[k][0]: round(v[1], 4) for k, v in totals.items()}},
+        }
+        vm_out[prec] = vm.double().cpu().numpy()
+        eng.close()
+        del vm
+        torch.cuda.empty_cache()
+    ref = vm_out["fp64"]
+    err = float(np.abs(vm_out["mixed"] - ref).max() / np.abs(ref).max())
+    sp = case.specs[0]
+    head = paths["mixed"]
+    out = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "TSV-cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_solve"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+bf16+f64",
+        "data": "synthetic",
+        "config": {"workload": case.name, "array": f"{case.nx_cells}x{case.ny_cells}", "cells": n_cells,
+                   "cell_um": [sp.pitch_x, sp.pitch_y, sp.height], "cell_mesh": list(sp.mesh),
+                   "interp": list(sp.interp), "n": n, "reduced_dofs": int(n_dofs),
+                   "dummy_cells": int((case.cell_type != 0).sum()), "liner_um": sp.liner_thickness,
+                   "bc": "Fourier field on all outer faces" if case.field is not None else "bottom clamped",
+                   "delta_T": case.delta_T, "seed": args.seed, "pcg_chunk": args.chunk,
+                   "precision": "mixed (headline) and fp64"},
+        "mixed": paths["mixed"],
+        "fp64": paths["fp64"],
+        "max_rel_err_vm_mixed_vs_fp64": err,
+        "local_stage_ms_total": round(local_ms, 1),
+        "roofline": head["roofline"],
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def serve_mode(args, mos, torch, np, W):
     reqs = W.request_stream(seed=args.seed, n_requests=args.requests)
     pitches = [10.0, 15.0, 20.0]
@@ -338,7 +462,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--mode", choices=["batch", "serve"], default="batch")
+    ap.add_argument("--mode", choices=["batch", "serve", "single"], default="batch")
+    ap.add_argument("--workload", choices=["c3", "c5"], default="c3")
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--chunk", type=int, default=16)
@@ -357,6 +482,8 @@ def main():
     torch.cuda.set_device(0)
     if args.mode == "batch":
         batch_mode(args, mos, torch, np, W)
+    elif args.mode == "single":
+        single_mode(args, mos, torch, np, W)
     else:
         serve_mode(args, mos, torch, np, W)
 
