@@ -56,6 +56,30 @@ KERNEL_INFO = {  # kernel id -> (name, bound, unit, note)
 }
 
 
+def recorded_traffic(kernel, workload, precision):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    record (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration), or
+    None when no record matches or the kernel's source has changed since the
+    counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    for e in rec.get("entries", []):
+        if (e["kernel"], e["workload"], e["precision"]) != (kernel, workload, precision):
+            continue
+        try:
+            src = open(os.path.join(ROOT, e["source"]), "rb").read()
+        except OSError:
+            return None
+        if hashlib.sha256(src).hexdigest() != e["source_sha256"]:
+            return None
+        return e["traffic_bytes_per_launch"]
+    return None
+
+
 def cpu_baseline(case):
     """The oracle's global stage on one array of the workload (its local
     stage is run first and not timed), on the host cores."""
@@ -179,7 +203,9 @@ def batch_mode(args, mos, torch, np, W):
     work_per_launch = work / max(seen, 1)
     achieved = work_per_launch / avg_s / (1e12 if unit == "TFLOP/s" else 1e9)
     roofline = {"bound": bound, "achieved": round(achieved, 4), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 5), "traffic": None, "kernel": name,
+                "frac": round(achieved / peak, 5),
+                "traffic": recorded_traffic(name, f"batch{B}_c2", args.precision), "traffic_unit": "bytes/launch",
+                "kernel": name,
                 "avg_launch_us": round(avg_s * 1e6, 3), "timed_launches": int(launches), "launches": int(seen),
                 "timed_every": TIME_EVERY, "work_per_launch": round(work_per_launch, 1), "work_note": note,
                 "kernel_share_of_step": round(avg_s * seen * 1e3 / total_ms, 4),
@@ -364,6 +390,23 @@ def single_mode(args, mos, torch, np, W):
     print(json.dumps(out))
 
 
+def calib_mode(args, torch):
+    """A plain device copy of known size (1 GiB read, 1 GiB written per
+    launch): the reference that scales the FETCH_SIZE / WRITE_SIZE counters
+    of the profiled kernels into HBM bytes."""
+    n = 1 << 28
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    print(json.dumps({"mode": "calib", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
+                      "launches": args.steps, "copy_GBps": round(8 * n / dt / 1e9, 1)}))
+
+
 def serve_mode(args, mos, torch, np, W):
     reqs = W.request_stream(seed=args.seed, n_requests=args.requests)
     pitches = [10.0, 15.0, 20.0]
@@ -462,7 +505,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--mode", choices=["batch", "serve", "single"], default="batch")
+    ap.add_argument("--mode", choices=["batch", "serve", "single", "calib"], default="batch")
     ap.add_argument("--workload", choices=["c3", "c5"], default="c3")
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
@@ -480,7 +523,9 @@ def main():
     import workloads as W
     from paper_2411_12690_amd import mos
     torch.cuda.set_device(0)
-    if args.mode == "batch":
+    if args.mode == "calib":
+        calib_mode(args, torch)
+    elif args.mode == "batch":
         batch_mode(args, mos, torch, np, W)
     elif args.mode == "single":
         single_mode(args, mos, torch, np, W)
