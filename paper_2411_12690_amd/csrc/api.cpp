@@ -98,29 +98,20 @@ void ArrayMesh::build(int Nx_, int Ny_, int nx_, int ny_, int nz_) {
     nx = nx_;
     ny = ny_;
     nz = nz_;
-    X = (int64_t)Nx * (nx - 1) + 1;
-    Y = (int64_t)Ny * (ny - 1) + 1;
-    Z = nz;
-    node_of.assign((size_t)(X * Y * Z), -1);
-    int64_t cnt = 0;
-    for (int64_t K = 0; K < Z; ++K)
-        for (int64_t J = 0; J < Y; ++J)
-            for (int64_t I = 0; I < X; ++I)
-                if (I % (nx - 1) == 0 || J % (ny - 1) == 0 || K == 0 || K == nz - 1)
-                    node_of[(size_t)((K * Y + J) * X + I)] = (int32_t)cnt++;
-    n_nodes = cnt;
+    lat = make_lattice(Nx, Ny, nx, ny, nz);
+    X = lat.X;
+    Y = lat.Y;
+    Z = lat.Z;
+    n_nodes = lat.n_nodes;
     surface_nodes(nx, ny, nz, surf);
     S = (int)surf.size() / 3;
     conn.resize((size_t)Nx * Ny * S);
     for (int cy = 0; cy < Ny; ++cy)
         for (int cx = 0; cx < Nx; ++cx) {
             size_t c = (size_t)cy * Nx + cx;
-            for (int s = 0; s < S; ++s) {
-                int64_t I = (int64_t)cx * (nx - 1) + surf[3 * s];
-                int64_t J = (int64_t)cy * (ny - 1) + surf[3 * s + 1];
-                int64_t K = surf[3 * s + 2];
-                conn[c * S + s] = node_of[(size_t)((K * Y + J) * X + I)];
-            }
+            for (int s = 0; s < S; ++s)
+                conn[c * S + s] = (int32_t)node_id(lat, (int64_t)cx * (nx - 1) + surf[3 * s],
+                                                   (int64_t)cy * (ny - 1) + surf[3 * s + 1], surf[3 * s + 2]);
         }
 }
 
@@ -438,9 +429,8 @@ mos_status mos_solve_array(mos_ctx ctx, const mos_array_desc *d, const mos_rom *
         }
     } sg{s};
     const mos_cell_desc &cd = roms[0]->desc;
-    ArrayMesh m;
-    m.build(d->nx_cells, d->ny_cells, cd.interp[0], cd.interp[1], cd.interp[2]);
-    MOS_TRY(s->mem.alloc_n(3 * m.n_nodes, &s->u));
+    const Lattice lat = make_lattice(d->nx_cells, d->ny_cells, cd.interp[0], cd.interp[1], cd.interp[2]);
+    MOS_TRY(s->mem.alloc_n(3 * lat.n_nodes, &s->u));
     int64_t ticket = 0;
     MOS_TRY(engine_submit(e, d, nullptr, nullptr, s->u, &ticket));
     std::vector<int64_t> done;
@@ -471,20 +461,11 @@ mos_status mos_solve_array(mos_ctx ctx, const mos_array_desc *d, const mos_rom *
     s->seg.resize(n_roms + 1);
     for (int t = 0; t <= n_roms; ++t) s->seg[t] = P->seg[t] * 16;
     s->n_pc = P->n_sb * 16;
-    const int S = s->n_surf, ldk = s->ldk, n = s->n;
-    std::vector<int32_t> gidx((size_t)ldk * s->n_pc, -1);
-    for (int sl = 0; sl < s->n_pc; ++sl) {
-        int32_t c = P->perm[sl];
-        if (c < 0) continue;
-        for (int k = 0; k < n; ++k) gidx[(size_t)k * s->n_pc + sl] = 3 * P->conn[(size_t)c * S + k / 3] + k % 3;
-    }
     MOS_TRY(s->mem.alloc_n(s->n_pc, &s->perm));
-    MOS_TRY(s->mem.alloc_n(P->conn.size(), &s->conn));
-    MOS_TRY(s->mem.alloc_n(gidx.size(), &s->gidx));
+    MOS_TRY(s->mem.alloc_n((size_t)s->ldk * s->n_pc, &s->gidx));
     hipStream_t st = ctx->stream;
     MOS_HIP(hipMemcpyAsync(s->perm, P->perm.data(), P->perm.size() * 4, hipMemcpyHostToDevice, st));
-    MOS_HIP(hipMemcpyAsync(s->conn, P->conn.data(), P->conn.size() * 4, hipMemcpyHostToDevice, st));
-    MOS_HIP(hipMemcpyAsync(s->gidx, gidx.data(), gidx.size() * 4, hipMemcpyHostToDevice, st));
+    MOS_TRY(engine_gather_index(e, P, s->perm, s->gidx));
     MOS_HIP(hipStreamSynchronize(st));
     sg.keep = true;
     *out = s;
@@ -750,8 +731,8 @@ mos_status mos_array_layout(mos_ctx ctx, int32_t nx_cells, int32_t ny_cells, mos
         for (int64_t K = 0; K < m.Z; ++K)
             for (int64_t J = 0; J < m.Y; ++J)
                 for (int64_t I = 0; I < m.X; ++I) {
-                    int32_t id = m.node_of[(size_t)((K * m.Y + J) * m.X + I)];
-                    if (id < 0) continue;
+                    if (!(I % (m.nx - 1) == 0 || J % (m.ny - 1) == 0 || K == 0 || K == m.Z - 1)) continue;
+                    const int64_t id = node_id(m.lat, I, J, K);
                     coords[3 * (size_t)id + 0] = d.pitch_x * I / (m.nx - 1);
                     coords[3 * (size_t)id + 1] = d.pitch_y * J / (m.ny - 1);
                     coords[3 * (size_t)id + 2] = d.height * K / (m.nz - 1);

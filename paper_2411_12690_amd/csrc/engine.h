@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "mesh.h"
 #include "mos_internal.h"
 
 namespace mos {
@@ -68,6 +69,8 @@ struct mos_engine_s {
     void **kr64_tab = nullptr, **kr32_tab = nullptr;
     double **br_tab = nullptr, **psi_tab = nullptr, **sigt_tab = nullptr;
     void *ub = nullptr;  // BF16 split of a finished problem's cell block (mixed reconstruction)
+    int32_t *surf = nullptr;  // [S][3] surface Lagrange nodes (i, j, k) of a cell, s order
+    int S = 0;
     // host state
     mos::RangeAlloc blk, sbs, pids;
     int64_t next_ticket = 0;
@@ -89,10 +92,12 @@ struct EngineProblem {
     int sb_begin = 0, n_sb = 0;
     std::vector<int> seg;         // per ROM: first slot block within the problem (n_roms+1)
     std::vector<int32_t> perm;    // [n_sb*16] cell id per slot, -1 pad
-    std::vector<int32_t> conn;    // [n_cells][S]
-    std::vector<int32_t> inc;     // [n_blk*256/3][4], problem-local slots
-    std::vector<uint8_t> cmask;   // [n_blk*256]
-    std::vector<double> g;        // [n_blk*256]
+    std::vector<int32_t> sb_rom;  // [n_sb] ROM of each slot block
+    Lattice lat{};                // abstract-mesh numbering of the array
+    uint32_t bc_flags = 0;        // MOS_BC_CLAMP_* of the descriptor
+    std::vector<int64_t> pdof;    // prescribed (DoF, value) list as given
+    std::vector<double> pval;
+    mos::DeviceArena dev;         // device copy of the prescribed list
     double dT = 0.0, rtol = 0.0;
     int max_iters = 0, iters = 0, sweeps = 0;
     double rel = 1.0;
@@ -111,6 +116,10 @@ mos_status engine_submit(mos_engine e, const mos_array_desc *d, void *vm, void *
                          int64_t *ticket);
 mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *completed);
 void engine_free(mos_engine e);
+// Gather index [ldk][n_sb*16] (global DoF of cell DoF k in each slot, -1
+// for padding) of a retired problem, enqueued on the context stream; `perm`
+// is the device copy of the problem's slot -> cell map.
+mos_status engine_gather_index(mos_engine e, const EngineProblem *P, const int32_t *perm, int32_t *gidx);
 // Capacity (DoFs, slots) one problem needs, for sizing an engine exactly.
 mos_status engine_problem_size(mos_engine e, const mos_array_desc *d, int64_t *dofs, int64_t *slots);
 

@@ -481,6 +481,77 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
         p[i] = v;
 }
 
+// ---- problem set-up on the device (numbering contract of the abstract mesh) ----
+
+// Constrained DoFs of one problem: padding DoFs and, when clamped, the
+// bottom-plane nodes [0, bot_end) and top-plane nodes [top_begin, n_nodes)
+// (value 0); everything else free.  `last` (one int32 per DoF) is reset for
+// the prescribed list.
+__global__ void k_constraints(uint8_t *cmask, double *g, double *x64, int32_t *last, int64_t d0, int64_t nd_pad,
+                              int64_t n_dofs, int64_t bot_end, int64_t top_begin) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nd_pad) return;
+    const int64_t node = i / 3;
+    cmask[d0 + i] = (i >= n_dofs || node < bot_end || node >= top_begin) ? 1 : 0;
+    g[d0 + i] = 0.0;
+    x64[d0 + i] = 0.0;
+    last[i] = -1;
+}
+
+// Prescribed (DoF, value) list, a later entry overriding an earlier one: the
+// largest entry index per DoF wins, then only that entry is applied.
+__global__ void k_prescribe_last(const int64_t *dof, int64_t n, int32_t *last) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicMax(&last[dof[i]], (int32_t)i);
+}
+
+__global__ void k_prescribe(const int64_t *dof, const double *val, int64_t n, const int32_t *last, uint8_t *cmask,
+                            double *g, double *x64, int64_t d0) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || last[dof[i]] != (int32_t)i) return;
+    cmask[d0 + dof[i]] = 1;
+    g[d0 + dof[i]] = val[i];
+    x64[d0 + dof[i]] = val[i];
+}
+
+// Node -> (slot, surface node) incidence, entries in ascending cell id.  A
+// node on a shared vertical face or edge belongs to 2 or 4 cells; the rank of
+// cell (cx, cy) among them follows from which side of the face it lies.
+__global__ void k_incidence(int32_t *inc, const int32_t *perm, int64_t n_slots, int slot0, const int32_t *surf, int S,
+                            Lattice L) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_slots * S) return;
+    const int sl = (int)(idx / S), s = (int)(idx % S);
+    const int32_t cell = perm[sl];
+    if (cell < 0) return;
+    const int cx = cell % L.Nx, cy = cell / L.Nx;
+    const int i = surf[3 * s], j = surf[3 * s + 1], k = surf[3 * s + 2];
+    const int64_t node = node_id(L, (int64_t)cx * (L.nx - 1) + i, (int64_t)cy * (L.ny - 1) + j, k);
+    const bool shx = (i == 0 && cx > 0) || (i == L.nx - 1 && cx < L.Nx - 1);
+    const int ux = (i == 0 && cx > 0) ? 1 : 0;
+    const int uy = (j == 0 && cy > 0) ? 1 : 0;
+    inc[node * 4 + uy * (shx ? 2 : 1) + ux] = ((slot0 + sl) << INC_SHIFT) | s;
+}
+
+// Global DoF of cell DoF k in slot sl ([ldk][n_slots], -1 for padding).
+__global__ void k_gather_index(int32_t *gidx, const int32_t *perm, int64_t n_slots, int ldk, int n,
+                               const int32_t *surf, Lattice L) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)ldk * n_slots) return;
+    const int k = (int)(idx / n_slots);
+    const int64_t sl = idx % n_slots;
+    const int32_t cell = perm[sl];
+    if (cell < 0 || k >= n) {
+        gidx[idx] = -1;
+        return;
+    }
+    const int s = k / 3;
+    const int cx = cell % L.Nx, cy = cell / L.Nx;
+    const int64_t node = node_id(L, (int64_t)cx * (L.nx - 1) + surf[3 * s], (int64_t)cy * (L.ny - 1) + surf[3 * s + 1],
+                                 surf[3 * s + 2]);
+    gidx[idx] = (int32_t)(3 * node + k % 3);
+}
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
@@ -529,55 +600,37 @@ void RangeAlloc::give(int b, int n) {
 namespace {
 
 mos_status prepare_problem(mos_engine e, const mos_array_desc *d, EngineProblem *P) {
-    const mos_rom r0 = e->roms[0];
-    const mos_cell_desc &cd = r0->desc;
-    ArrayMesh m;
-    m.build(d->nx_cells, d->ny_cells, cd.interp[0], cd.interp[1], cd.interp[2]);
-    const int S = m.S;
-    P->Nx = m.Nx;
-    P->Ny = m.Ny;
-    P->n_cells = (int64_t)m.Nx * m.Ny;
-    P->n_nodes = m.n_nodes;
-    P->n_dofs = 3 * m.n_nodes;
+    const mos_cell_desc &cd = e->roms[0]->desc;
+    const Lattice L = make_lattice(d->nx_cells, d->ny_cells, cd.interp[0], cd.interp[1], cd.interp[2]);
+    P->lat = L;
+    P->Nx = d->nx_cells;
+    P->Ny = d->ny_cells;
+    P->n_cells = (int64_t)P->Nx * P->Ny;
+    P->n_nodes = L.n_nodes;
+    P->n_dofs = 3 * L.n_nodes;
     P->dT = d->delta_T;
     const bool mixed = e->precision == MOS_MIXED;
     P->rtol = d->rtol > 0 ? d->rtol : (mixed ? 1e-10 : 1e-12);
     P->max_iters = d->max_iters > 0 ? d->max_iters : 20000;
     P->n_blk = (int)(round_up(P->n_dofs, DOF_ALIGN) / DB);
-    const int64_t nd_pad = (int64_t)P->n_blk * DB;
-    P->cmask.assign(nd_pad, 1);
-    P->g.assign(nd_pad, 0.0);
-    for (int64_t i = 0; i < P->n_dofs; ++i) P->cmask[i] = 0;
-    int64_t n_con = 0;
-    for (int side = 0; side < 2; ++side) {
-        uint32_t flag = side == 0 ? MOS_BC_CLAMP_BOTTOM : MOS_BC_CLAMP_TOP;
-        if (!(d->bc_flags & flag)) continue;
-        int64_t K = side == 0 ? 0 : m.Z - 1;
-        for (int64_t J = 0; J < m.Y; ++J)
-            for (int64_t I = 0; I < m.X; ++I) {
-                int32_t id = m.node_of[(size_t)((K * m.Y + J) * m.X + I)];
-                for (int ci = 0; ci < 3; ++ci) {
-                    P->cmask[3 * (int64_t)id + ci] = 1;
-                    P->g[3 * (int64_t)id + ci] = 0.0;
-                }
-            }
+    P->bc_flags = d->bc_flags & (MOS_BC_CLAMP_BOTTOM | MOS_BC_CLAMP_TOP);
+    if (d->n_prescribed > INT32_MAX) {
+        set_error("more than 2^31-1 prescribed entries");
+        return MOS_EINVAL;
     }
-    for (int64_t i = 0; i < d->n_prescribed; ++i) {
-        int64_t dof = d->prescribed_dof[i];
-        double v = d->prescribed_value[i];
-        if (dof < 0 || dof >= P->n_dofs || !std::isfinite(v)) {
+    P->pdof.assign(d->prescribed_dof, d->prescribed_dof + d->n_prescribed);
+    P->pval.assign(d->prescribed_value, d->prescribed_value + d->n_prescribed);
+    for (int64_t i = 0; i < d->n_prescribed; ++i)
+        if (P->pdof[i] < 0 || P->pdof[i] >= P->n_dofs || !std::isfinite(P->pval[i])) {
             set_error("prescribed entry %lld: DoF %lld outside [0, %lld) or value not finite", (long long)i,
-                      (long long)dof, (long long)P->n_dofs);
+                      (long long)P->pdof[i], (long long)P->n_dofs);
             return MOS_EINVAL;
         }
-        P->cmask[dof] = 1;
-        P->g[dof] = v;
-    }
-    for (int64_t i = 0; i < P->n_dofs; ++i) n_con += P->cmask[i];
-    if (n_con == 0) {
+    if (P->bc_flags == 0 && d->n_prescribed == 0) {
         set_error("array has no constrained DoF: the reduced stiffness is singular (rigid motions)");
         return MOS_ESINGULAR;
     }
+    // Cells grouped by type, each type padded to 16 slots.
     const int n_roms = (int)e->roms.size();
     std::vector<int> count(n_roms, 0);
     for (int64_t c = 0; c < P->n_cells; ++c) count[d->cell_type[c]]++;
@@ -585,25 +638,12 @@ mos_status prepare_problem(mos_engine e, const mos_array_desc *d, EngineProblem 
     for (int t = 0; t < n_roms; ++t) P->seg[t + 1] = P->seg[t] + ceil_div(count[t], 16);
     P->n_sb = std::max(P->seg[n_roms], 1);
     P->perm.assign((size_t)P->n_sb * 16, -1);
-    std::vector<int32_t> slot_of((size_t)P->n_cells);
-    {
-        std::vector<int> next(n_roms);
-        for (int t = 0; t < n_roms; ++t) next[t] = P->seg[t] * 16;
-        for (int64_t c = 0; c < P->n_cells; ++c) {
-            int sl = next[d->cell_type[c]]++;
-            P->perm[sl] = (int32_t)c;
-            slot_of[c] = sl;
-        }
-    }
-    P->conn = m.conn;
-    // Incidence with problem-local slot indices; made global at placement.
-    P->inc.assign((size_t)nd_pad / 3 * 4, -1);
-    std::vector<uint8_t> cnt((size_t)m.n_nodes, 0);
-    for (int64_t c = 0; c < P->n_cells; ++c)
-        for (int s = 0; s < S; ++s) {
-            int32_t node = m.conn[(size_t)c * S + s];
-            P->inc[(size_t)node * 4 + cnt[node]++] = (slot_of[c] << INC_SHIFT) | s;
-        }
+    std::vector<int> next(n_roms);
+    for (int t = 0; t < n_roms; ++t) next[t] = P->seg[t] * 16;
+    for (int64_t c = 0; c < P->n_cells; ++c) P->perm[next[d->cell_type[c]]++] = (int32_t)c;
+    P->sb_rom.assign(P->n_sb, -1);
+    for (int t = 0; t < n_roms; ++t)
+        for (int b = P->seg[t]; b < P->seg[t + 1]; ++b) P->sb_rom[b] = t;
     return MOS_OK;
 }
 
@@ -664,23 +704,42 @@ mos_status setup_problem(mos_engine e, EngineProblem *P) {
     hipStream_t st = e->ctx->stream;
     const int64_t d0 = (int64_t)P->blk_begin * DB, d1 = d0 + (int64_t)P->n_blk * DB;
     const int64_t nd_pad = (int64_t)P->n_blk * DB;
-    // Tables: problem-local slot indices become global.
+    // Tables and constraints, all built on the device from the numbering
+    // contract; the host sources (P->perm, P->sb_rom, P->pdof, P->pval) live
+    // until the problem is released.
     const int slot0 = P->sb_begin * 16;
-    std::vector<int32_t> inc(P->inc);
-    for (auto &v : inc)
-        if (v >= 0) v = (((v >> INC_SHIFT) + slot0) << INC_SHIFT) | (v & MAX_SURF);
-    std::vector<int32_t> sb_rom(P->n_sb, -1), sb_prob(P->n_sb, P->pid), blk_prob(P->n_blk, P->pid);
-    const int n_roms = (int)e->roms.size();
-    for (int t = 0; t < n_roms; ++t)
-        for (int b = P->seg[t]; b < P->seg[t + 1]; ++b) sb_rom[b] = t;
-    MOS_HIP(hipMemcpyAsync(e->inc + d0 / 3 * 4, inc.data(), inc.size() * 4, hipMemcpyHostToDevice, st));
-    MOS_HIP(hipMemcpyAsync(e->cmask + d0, P->cmask.data(), nd_pad, hipMemcpyHostToDevice, st));
-    MOS_HIP(hipMemcpyAsync(e->g + d0, P->g.data(), nd_pad * 8, hipMemcpyHostToDevice, st));
-    MOS_HIP(hipMemcpyAsync(e->x64 + d0, P->g.data(), nd_pad * 8, hipMemcpyHostToDevice, st));
-    MOS_HIP(hipMemcpyAsync(e->sb_rom + P->sb_begin, sb_rom.data(), sb_rom.size() * 4, hipMemcpyHostToDevice, st));
-    MOS_HIP(hipMemcpyAsync(e->sb_prob + P->sb_begin, sb_prob.data(), sb_prob.size() * 4, hipMemcpyHostToDevice, st));
+    int32_t *inc_p = e->inc + d0 / 3 * 4;
+    auto fill32 = [&](void *p, int64_t n, uint32_t v) {
+        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>(ceil_div(n, 256), 4096)), dim3(256), 0, st,
+                           (uint32_t *)p, n, v);
+    };
+    fill32(e->blk_prob + P->blk_begin, P->n_blk, (uint32_t)P->pid);
+    fill32(e->sb_prob + P->sb_begin, P->n_sb, (uint32_t)P->pid);
+    MOS_HIP(hipMemcpyAsync(e->sb_rom + P->sb_begin, P->sb_rom.data(), P->n_sb * 4, hipMemcpyHostToDevice, st));
     MOS_HIP(hipMemcpyAsync(e->perm + slot0, P->perm.data(), P->perm.size() * 4, hipMemcpyHostToDevice, st));
-    MOS_HIP(hipStreamSynchronize(st));  // the staged host tables are locals
+    const Lattice &L = P->lat;
+    const int64_t bot_end = (P->bc_flags & MOS_BC_CLAMP_BOTTOM) ? L.plane_full : 0;
+    const int64_t top_begin = (P->bc_flags & MOS_BC_CLAMP_TOP) ? L.n_nodes - L.plane_full : INT64_MAX;
+    hipLaunchKernelGGL(k_constraints, dim3(P->n_blk), dim3(DB), 0, st, e->cmask, e->g, e->x64, inc_p, d0, nd_pad,
+                       P->n_dofs, bot_end, top_begin);
+    const int64_t np = (int64_t)P->pdof.size();
+    if (np > 0) {
+        P->dev.ctx = e->ctx;
+        int64_t *pdof = nullptr;
+        double *pval = nullptr;
+        MOS_TRY(P->dev.alloc_n(np, &pdof));
+        MOS_TRY(P->dev.alloc_n(np, &pval));
+        MOS_HIP(hipMemcpyAsync(pdof, P->pdof.data(), np * 8, hipMemcpyHostToDevice, st));
+        MOS_HIP(hipMemcpyAsync(pval, P->pval.data(), np * 8, hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(k_prescribe_last, dim3(ceil_div(np, 256)), dim3(256), 0, st, (const int64_t *)pdof, np, inc_p);
+        hipLaunchKernelGGL(k_prescribe, dim3(ceil_div(np, 256)), dim3(256), 0, st, (const int64_t *)pdof,
+                           (const double *)pval, np, (const int32_t *)inc_p, e->cmask, e->g, e->x64, d0);
+    }
+    fill32(inc_p, nd_pad / 3 * 4, 0xffffffffu);
+    const int64_t n_slots = (int64_t)P->n_sb * 16;
+    hipLaunchKernelGGL(k_incidence, dim3(ceil_div(n_slots * e->S, 256)), dim3(256), 0, st, inc_p,
+                       (const int32_t *)(e->perm + slot0), n_slots, slot0, (const int32_t *)e->surf, e->S, L);
+    MOS_LAUNCH_CHECK();
     // b_raw, A g, ||b_l||^2, Jacobi diagonal.
     hipLaunchKernelGGL(k_brhs, dim3(P->n_blk), dim3(DB), 0, st, (const double *const *)e->br_tab, e->sb_rom, e->inc,
                        P->dT, e->b_raw, d0, d1);
@@ -840,6 +899,10 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     }
     if (e->precision == MOS_MIXED && e->roms[0]->psi_hi)
         MOS_TRY(m.alloc((size_t)recon_bf16_scratch(e->roms[0], e->cap_sb), &e->ub));
+    std::vector<int> surf;
+    surface_nodes(e->roms[0]->desc.interp[0], e->roms[0]->desc.interp[1], e->roms[0]->desc.interp[2], surf);
+    e->S = (int)surf.size() / 3;
+    MOS_TRY(m.alloc_n(surf.size(), &e->surf));
     MOS_TRY(m.alloc_n(MAX_TYPES, &e->kr64_tab));
     MOS_TRY(m.alloc_n(MAX_TYPES, &e->kr32_tab));
     MOS_TRY(m.alloc_n(MAX_TYPES, &e->br_tab));
@@ -872,6 +935,7 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     MOS_HIP(hipMemcpyAsync(e->br_tab, tb.data(), MAX_TYPES * 8, hipMemcpyHostToDevice, st));
     MOS_HIP(hipMemcpyAsync(e->psi_tab, tp.data(), MAX_TYPES * 8, hipMemcpyHostToDevice, st));
     MOS_HIP(hipMemcpyAsync(e->sigt_tab, ts.data(), MAX_TYPES * 8, hipMemcpyHostToDevice, st));
+    MOS_HIP(hipMemcpyAsync(e->surf, surf.data(), surf.size() * 4, hipMemcpyHostToDevice, st));
     MOS_HIP(hipStreamSynchronize(st));
     // The GEMM variant is fixed per engine (never per batch), so a problem's
     // rounding does not depend on what else is in the batch.
@@ -946,13 +1010,12 @@ mos_status reconstruct_problem(mos_engine e, EngineProblem *P);
 
 void release_problem(mos_engine e, EngineProblem *P) {
     hipStream_t st = e->ctx->stream;
-    const int one = -1;
-    std::vector<int32_t> neg(std::max(P->n_blk, P->n_sb), one);
-    (void)hipMemcpyAsync(e->blk_prob + P->blk_begin, neg.data(), P->n_blk * 4, hipMemcpyHostToDevice, st);
-    (void)hipMemcpyAsync(e->sb_rom + P->sb_begin, neg.data(), P->n_sb * 4, hipMemcpyHostToDevice, st);
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>(ceil_div(P->n_blk, 256), 4096)), dim3(256), 0, st,
+                       (uint32_t *)(e->blk_prob + P->blk_begin), (int64_t)P->n_blk, 0xffffffffu);
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>(ceil_div(P->n_sb, 256), 4096)), dim3(256), 0, st,
+                       (uint32_t *)(e->sb_rom + P->sb_begin), (int64_t)P->n_sb, 0xffffffffu);
     hipLaunchKernelGGL(k_prob_stop, dim3(1), dim3(1), 0, st, e->ps, P->pid);
-    // Copies from a host vector must finish before it goes out of scope.
-    (void)hipStreamSynchronize(st);
+    P->dev.release();  // stream-ordered: later work on this stream may reuse it
     e->blk.give(P->blk_begin, P->n_blk);
     e->sbs.give(P->sb_begin, P->n_sb);
     e->pids.give(P->pid, 1);
@@ -1009,11 +1072,7 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
         P->pid = pid;
         P->blk_begin = b;
         P->sb_begin = sb;
-        // blk_prob for the range (device)
-        std::vector<int32_t> bp(P->n_blk, pid);
-        MOS_HIP(hipMemcpyAsync(e->blk_prob + b, bp.data(), bp.size() * 4, hipMemcpyHostToDevice, st));
         MOS_TRY(setup_problem(e, P));
-        MOS_HIP(hipStreamSynchronize(st));  // host-side tables must outlive their copies
         e->queue.pop_front();
         e->active.push_back(P);
         admitted.push_back(P);
@@ -1222,6 +1281,14 @@ mos_status reconstruct_problem(mos_engine e, EngineProblem *P) {
 
 }  // namespace
 
+mos_status engine_gather_index(mos_engine e, const EngineProblem *P, const int32_t *perm, int32_t *gidx) {
+    const int64_t n_slots = (int64_t)P->n_sb * 16;
+    hipLaunchKernelGGL(k_gather_index, dim3(ceil_div((int64_t)e->ldk * n_slots, 256)), dim3(256), 0, e->ctx->stream,
+                       gidx, perm, n_slots, e->ldk, e->n, (const int32_t *)e->surf, P->lat);
+    MOS_LAUNCH_CHECK();
+    return MOS_OK;
+}
+
 mos_status engine_problem_size(mos_engine e, const mos_array_desc *d, int64_t *dofs, int64_t *slots) {
     MOS_TRY(engine_check_desc(e, d));
     const mos_cell_desc &cd = e->roms[0]->desc;
@@ -1241,7 +1308,10 @@ mos_status engine_problem_size(mos_engine e, const mos_array_desc *d, int64_t *d
 void engine_free(mos_engine e) {
     if (!e) return;
     for (EngineProblem *P : e->queue) delete P;
-    for (EngineProblem *P : e->active) delete P;
+    for (EngineProblem *P : e->active) {
+        P->dev.release();
+        delete P;
+    }
     for (auto &kv : e->finished) delete kv.second;
     e->queue.clear();
     e->active.clear();

@@ -154,7 +154,6 @@ struct mos_sol_s {
     std::vector<mos_rom> roms;               // per type, borrowed
     mos::DeviceArena mem;
     int32_t *perm = nullptr;                 // [n_pc] cell id per slot or -1
-    int32_t *conn = nullptr;                 // [n_cells][n_surf] node ids
     int32_t *gidx = nullptr;                 // [ldk][n_pc] global DoF of cell DoF k in slot, -1 pad
     double *u = nullptr;                     // [n_dofs] solution
 };
