@@ -130,6 +130,8 @@ def batch_mode(args, mos, torch, np, W):
     n_dofs_pad = -(-n_dofs // 768) * 768
     eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=int(B * (n_dofs_pad * 140 + n_cells * 16 * 176 * 34)
                                                              * 1.3) + (64 << 20))
+    if args.gemm_split is not None:
+        eng.option(mos.MOS_OPT_GEMM_SPLIT, args.gemm_split)
     vms = [torch.empty((n_cells, n_elem), dtype=torch.float32 if mixed else torch.float64, device="cuda")
            for _ in range(B)]
     types = [np.full(n_cells, diam.index(c.specs[0].tsv_diameter), dtype=np.uint8) for c in cases]
@@ -248,7 +250,8 @@ def batch_mode(args, mos, torch, np, W):
                    "cell_um": [spec0.pitch_x, spec0.pitch_y, spec0.height], "cell_mesh": list(spec0.mesh),
                    "tsv_diameter_um": "per array from {4,5,6}", "interp": list(spec0.interp), "n": n,
                    "reduced_dofs_per_array": int(n_dofs), "delta_T": -250.0, "bc": "bottom clamped",
-                   "precision": args.precision, "seed": args.seed, "pcg_chunk": args.chunk},
+                   "precision": args.precision, "seed": args.seed, "pcg_chunk": args.chunk,
+                   "gemm_split": args.gemm_split if args.gemm_split is not None else "tuned"},
         "p50_ms": round(float(np.percentile(lat, 50)), 4),
         "p99_ms": round(float(np.percentile(lat, 99)), 4),
         "latency_is": "per array, submission to completion of solve + reconstruction",
@@ -509,6 +512,8 @@ def main():
     ap.add_argument("--workload", choices=["c3", "c5"], default="c3")
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--gemm-split", type=int, default=None,
+                    help="fixed slot blocks per wave of the cell GEMM (default: tuned online)")
     ap.add_argument("--chunk", type=int, default=16)
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--budget-gb", type=float, default=32.0)

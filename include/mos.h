@@ -223,12 +223,18 @@ mos_status mos_engine_result(mos_engine e, int64_t ticket, int32_t *status, doub
  * PCG matvec (the per-type product K_r * u_cell of eq. 20 over all cells):
  * 1 = 16x16 output tiles with the contraction split over four waves (any
  * basis size); 2 = K_r-stationary rows: each wave holds 16 rows of K_r in
- * registers and streams consecutive 16-cell blocks (basis sizes padded to
- * 32, 80 or 176, i.e. interpolation orders 2-4).  The default is 2 where it
+ * registers and streams consecutive 16-cell blocks (basis sizes up to 176,
+ * i.e. interpolation up to 4 nodes per axis).  The default is 2 where it
  * applies, else 1; asking for 2 elsewhere runs 1.  Set options before the first submission; results can
  * differ in the last bits between variants, never between batch
  * compositions. */
-enum { MOS_OPT_CELL_GEMM = 1 };
+/* MOS_OPT_GEMM_SPLIT sets how many consecutive 16-cell blocks one wave of
+ * the K_r-stationary GEMM streams: 0 (default) lets the engine tune it online
+ * per batch size (each candidate in {1, 2, 4, 8} is timed three times with
+ * stream events, the fastest kept); k > 0 fixes it.  It only decides which
+ * wave computes which output tile, so results do not depend on it; it may be
+ * changed at any time. */
+enum { MOS_OPT_CELL_GEMM = 1, MOS_OPT_GEMM_SPLIT = 2 };
 mos_status mos_engine_option(mos_engine e, int option, int64_t value);
 
 /* Problems admitted and queued, and the arena capacities. */

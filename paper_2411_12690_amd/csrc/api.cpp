@@ -577,6 +577,10 @@ mos_status mos_engine_option(mos_engine e, int option, int64_t value) {
         e->gemm_rows = value == 2;
         return MOS_OK;
     }
+    if (option == MOS_OPT_GEMM_SPLIT && value >= 0 && value <= 64) {
+        e->tuner.fixed = (int)value;
+        return MOS_OK;
+    }
     set_error("unknown option %d or value %lld", option, (long long)value);
     return MOS_EINVAL;
 }

@@ -31,6 +31,35 @@ enum { VX, VR, VU, VW, VZ, VQ, VS, VP, VM, VDINV, VRHS, NVEC };
 
 struct EngineProblem;
 
+// Largest number of 4-wide k-steps (ldk <= 176, basis size <= 176) the
+// K_r-stationary GEMM keeps in registers; larger bases use the tile GEMM.
+constexpr int ROWS_MAX_KS = 44;
+
+// Online tuner of the rows GEMM's work split (slot blocks per wave).  The
+// split only decides which wave computes which output tile -- every tile is
+// still one wave's fixed-order MFMA chain -- so tuning never changes results.
+// Per bucket of active slot blocks (power of two), each candidate is timed
+// REPS times with stream events around its launch; the fastest (minimum
+// time) is then used for that bucket for the life of the engine.
+struct GemmTuner {
+    static constexpr int N_CAND = 4;
+    static constexpr int CAND[N_CAND] = {1, 2, 4, 8};
+    static constexpr int REPS = 3;
+    struct Bucket {
+        float best[N_CAND] = {1e30f, 1e30f, 1e30f, 1e30f};
+        int runs[N_CAND] = {0, 0, 0, 0};
+        int chosen = 0;  // 0 while tuning, else the chosen spw
+    };
+    int fixed = 0;       // > 0: no tuning, always this spw
+    std::map<int, Bucket> buckets;
+    struct Pending {
+        int bucket, cand;
+        hipEvent_t start, stop;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> spare;
+};
+
 // First-fit allocator of block ranges (host side).
 struct RangeAlloc {
     int cap = 0, high = 0;
@@ -50,6 +79,7 @@ struct mos_engine_s {
     int ldk = 0, n = 0, n_elem = 0, n_eblk = 0;
     int cap_blk = 0, cap_sb = 0, ld_slots = 0;
     bool gemm_rows = false;                   // cell GEMM variant (fixed per engine)
+    mos::GemmTuner tuner;                     // work split of the rows variant
     mos::DeviceArena mem;
     // device arrays
     void *v[mos::NVEC] = {};                  // inner vectors (double or float)

@@ -203,18 +203,22 @@ __global__ __launch_bounds__(256) void k_bgemm(const void *const *kr_tab, const 
 // each slot block issues all KS operand loads before its chain of KS MFMAs.
 // Each 16x16 output is one MFMA chain in k order, so results do not depend
 // on spw.  Grid row 1 holds the per-problem scalar waves.
-template <class T, int KS>
+template <class T, int KS, bool EXACT>
 __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, const int32_t *sb_rom,
                                                     const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots,
-                                                    int sb_base, int n_sb, int spw, int gate, ProbState *ps,
-                                                    int n_probs, const double *pg, const double *pd,
-                                                    const double *pr) {
+                                                    int sb_base, int n_sb, int spw, int gate, int task_blocks,
+                                                    int ks, ProbState *ps, int n_probs, const double *pg,
+                                                    const double *pd, const double *pr) {
     typedef typename Mfma<T>::v4 v4;
-    constexpr int ldk = 4 * KS;
-    constexpr int nrb = ldk / 16;
+    // KS bounds the k-steps held in registers; the basis uses ks <= KS of
+    // them (ldk = 4 ks), and steps past ks are neither loaded nor issued.
+    // EXACT instances (ks == KS) keep every operand offset an immediate.
+    if (EXACT) ks = KS;
+    const int ldk = 4 * ks;
+    const int nrb = ldk / 16;
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-    if (blockIdx.y == 1) {
-        const int p = (int)blockIdx.x * 4 + wave;
+    if ((int)blockIdx.x >= task_blocks) {
+        const int p = ((int)blockIdx.x - task_blocks) * 4 + wave;
         if (p < n_probs) problem_step(ps[p], pg, pd, pr);
         return;
     }
@@ -223,6 +227,11 @@ __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, c
     const int s_begin = run * spw;
     if (s_begin >= n_sb) return;
     const int s_end = min(s_begin + spw, n_sb);
+    // Per-type K_r bases up front, so a slot block's operand loads wait on
+    // its type only, not on a second pointer load.
+    const T *kr[MAX_TYPES];
+#pragma unroll
+    for (int t = 0; t < MAX_TYPES; ++t) kr[t] = static_cast<const T *>(kr_tab[t]);
     T a[KS], b[KS];
     int cur = -1;
     for (int sl = s_begin; sl < s_end; ++sl) {
@@ -235,16 +244,17 @@ __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, c
         }
         const T *bp = Mc + (size_t)(lane / 16) * ld_slots + sb * 16 + lane % 16;
 #pragma unroll
-        for (int k = 0; k < KS; ++k) b[k] = bp[(size_t)(4 * k) * ld_slots];
+        for (int k = 0; k < KS; ++k) b[k] = k < ks ? bp[(size_t)(4 * k) * ld_slots] : T(0);
         if (rom != cur) {
-            const T *ap = static_cast<const T *>(kr_tab[rom]) + (size_t)(lane / 16) * ldk + rb * 16 + lane % 16;
+            const T *ap = kr[rom] + (size_t)(lane / 16) * ldk + rb * 16 + lane % 16;
 #pragma unroll
-            for (int k = 0; k < KS; ++k) a[k] = ap[(size_t)(4 * k) * ldk];
+            for (int k = 0; k < KS; ++k) a[k] = k < ks ? ap[(size_t)(4 * k) * ldk] : T(0);
             cur = rom;
         }
         v4 acc = {0, 0, 0, 0};
 #pragma unroll
-        for (int k = 0; k < KS; ++k) acc = Mfma<T>::op(a[k], b[k], acc);
+        for (int k = 0; k < KS; ++k)
+            if (k < ks) acc = Mfma<T>::op(a[k], b[k], acc);
         const int col = sb * 16 + lane % 16;
 #pragma unroll
         for (int q = 0; q < 4; ++q) Y[(size_t)(rb * 16 + Mfma<T>::row(lane, q)) * ld_slots + col] = acc[q];
@@ -431,7 +441,11 @@ __global__ __launch_bounds__(256) void k_bstep(const T *Y, const int32_t *inc, c
     __shared__ int go;
     __shared__ double step[2];
     const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x;
-    const int4 iv = incidence(inc, d);  // requested before the gate is known
+    // Only the incidence is requested before the gate resolves: blocks of
+    // problems that have stopped (converged, or between refinement sweeps)
+    // must not spend bandwidth on their operands.
+    const int4 iv = incidence(inc, d);
+    const int ci = (int)(d % 3);
     if (threadIdx.x == 0) {
         const int pb = blk_prob[blockIdx.x];
         int g = 0;
@@ -446,18 +460,19 @@ __global__ __launch_bounds__(256) void k_bstep(const T *Y, const int32_t *inc, c
     __syncthreads();
     if (!go) return;
     const T a = (T)step[0], b = (T)step[1];
-    const int ci = (int)(d % 3);
+    const T zd = z[d], qd = q[d], sd = s[d], pd0 = p[d], ud = u[d], wd = w[d], md = m[d], rd = r[d], xd = x[d];
+    const T dv = dinv[d];
     const T sum = cell_sum(Y, iv, ci, ld_slots);
     const T nv = cmask[d] ? T(0) : sum;
-    const T zv = nv + b * z[d];
-    const T qv = m[d] + b * q[d];
-    const T sv = w[d] + b * s[d];
-    const T pv = u[d] + b * p[d];
-    x[d] += a * pv;
-    const T rv = r[d] - a * sv;
-    const T uv = u[d] - a * qv;
-    const T wv = w[d] - a * zv;
-    const T mv = dinv[d] * wv;
+    const T zv = nv + b * zd;
+    const T qv = md + b * qd;
+    const T sv = wd + b * sd;
+    const T pv = ud + b * pd0;
+    x[d] = xd + a * pv;
+    const T rv = rd - a * sv;
+    const T uv = ud - a * qv;
+    const T wv = wd - a * zv;
+    const T mv = dv * wv;
     z[d] = zv;
     q[d] = qv;
     s[d] = sv;
@@ -916,6 +931,10 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     // Cell layouts must hold zeros in padding slots and rows.
     fill32(e->Mc, (int64_t)ldk * slots * w / 4, 0u);
     fill32(e->Mc64, (int64_t)ldk * slots * 2, 0u);
+    // Kernels read the incidence of every block below the high-water mark
+    // before they know whether the block is active, so it never holds
+    // anything but -1 or a valid slot.
+    fill32(e->inc, dofs / 3 * 4, 0xffffffffu);
     fill32(e->blk_prob, e->cap_blk, 0xffffffffu);
     fill32(e->sb_rom, e->cap_sb, 0xffffffffu);
     fill32(e->sb_prob, e->cap_sb, 0u);
@@ -939,7 +958,7 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     MOS_HIP(hipStreamSynchronize(st));
     // The GEMM variant is fixed per engine (never per batch), so a problem's
     // rounding does not depend on what else is in the batch.
-    e->gemm_rows = ldk / 4 == 8 || ldk / 4 == 20 || ldk / 4 == 44;
+    e->gemm_rows = ldk / 4 <= ROWS_MAX_KS;
     e->blk.init(e->cap_blk);
     e->sbs.init(e->cap_sb);
     e->pids.init(MAX_PROBS);
@@ -1024,27 +1043,125 @@ void release_problem(mos_engine e, EngineProblem *P) {
 }  // namespace
 
 template <class T>
-mos_status launch_rows(mos_ctx ctx, int ks, dim3 grid, hipStream_t st, const void *const *kr_tab, const int32_t *sb_rom,
-                       const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots, int n_sb, int spw, ProbState *ps,
+mos_status launch_rows(mos_ctx ctx, int ks, int spw, hipStream_t st, const void *const *kr_tab, const int32_t *sb_rom,
+                       const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots, int n_sb, ProbState *ps,
                        int n_probs, const double *pg, const double *pd, const double *pr) {
-    switch (ks) {
-        case 8:
-            launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm_rows<T, 8>, grid, dim3(256), 0, st, kr_tab, sb_rom, sb_prob, Mc,
-                         Y, ld_slots, 0, n_sb, spw, 1, ps, n_probs, pg, pd, pr);
-            break;
-        case 20:
-            launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm_rows<T, 20>, grid, dim3(256), 0, st, kr_tab, sb_rom, sb_prob,
-                         Mc, Y, ld_slots, 0, n_sb, spw, 1, ps, n_probs, pg, pd, pr);
-            break;
-        case 44:
-            launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm_rows<T, 44>, grid, dim3(256), 0, st, kr_tab, sb_rom, sb_prob,
-                         Mc, Y, ld_slots, 0, n_sb, spw, 1, ps, n_probs, pg, pd, pr);
-            break;
-        default:
-            set_error("no rows GEMM for %d k-steps", ks);
-            return MOS_EINVAL;
+    // Task blocks: 4 waves each, one wave per (row block, run of spw slot
+    // blocks); then the blocks whose waves compute each problem's scalars.
+    const int nrb = ks / 4;
+    const int task_blocks = (int)ceil_div((int64_t)nrb * ceil_div(n_sb, spw), 4);
+    const dim3 grid((unsigned)(task_blocks + ceil_div(n_probs, 4)));
+    if (ks == 8)
+        launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm_rows<T, 8, true>, grid, dim3(256), 0, st, kr_tab, sb_rom, sb_prob,
+                     Mc, Y, ld_slots, 0, n_sb, spw, 1, task_blocks, ks, ps, n_probs, pg, pd, pr);
+    else if (ks == 20)
+        launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm_rows<T, 20, true>, grid, dim3(256), 0, st, kr_tab, sb_rom, sb_prob,
+                     Mc, Y, ld_slots, 0, n_sb, spw, 1, task_blocks, ks, ps, n_probs, pg, pd, pr);
+    else if (ks == ROWS_MAX_KS)
+        launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm_rows<T, ROWS_MAX_KS, true>, grid, dim3(256), 0, st, kr_tab, sb_rom,
+                     sb_prob, Mc, Y, ld_slots, 0, n_sb, spw, 1, task_blocks, ks, ps, n_probs, pg, pd, pr);
+    else if (ks < ROWS_MAX_KS)
+        launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm_rows<T, ROWS_MAX_KS, false>, grid, dim3(256), 0, st, kr_tab, sb_rom,
+                     sb_prob, Mc, Y, ld_slots, 0, n_sb, spw, 1, task_blocks, ks, ps, n_probs, pg, pd, pr);
+    else {
+        set_error("no rows GEMM for %d k-steps", ks);
+        return MOS_EINVAL;
     }
     MOS_LAUNCH_CHECK();
+    return MOS_OK;
+}
+
+template <class T>
+mos_status rows_step(mos_engine e, int ks, int hw_sb, int hw_p);
+
+// Pick the rows-GEMM work split for `n_sb` active slot blocks; *timed is set
+// when this launch is a tuning trial (its events are then recorded by the
+// caller around the launch).
+int tuner_pick(GemmTuner &T, int n_sb, int *cand_out) {
+    *cand_out = -1;
+    if (T.fixed > 0) return T.fixed;
+    int bucket = 0;
+    while ((1 << bucket) < n_sb) ++bucket;
+    GemmTuner::Bucket &B = T.buckets[bucket];
+    if (B.chosen > 0) return B.chosen;
+    for (int c = 0; c < GemmTuner::N_CAND; ++c) {
+        int queued = 0;
+        for (const auto &pd : T.pending) queued += pd.bucket == bucket && pd.cand == c;
+        if (B.runs[c] + queued < GemmTuner::REPS) {
+            *cand_out = c;
+            return GemmTuner::CAND[c];
+        }
+    }
+    return GemmTuner::CAND[0];  // all trials queued, results not read yet
+}
+
+// Read the tuning trials of the last chunk (the stream has been synchronised).
+void tuner_collect(GemmTuner &T) {
+    for (auto &pd : T.pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, pd.start, pd.stop) == hipSuccess) {
+            GemmTuner::Bucket &B = T.buckets[pd.bucket];
+            B.best[pd.cand] = std::min(B.best[pd.cand], ms);
+            B.runs[pd.cand]++;
+        } else {
+            (void)hipGetLastError();
+        }
+        T.spare.push_back(pd.start);
+        T.spare.push_back(pd.stop);
+    }
+    T.pending.clear();
+    for (auto &kv : T.buckets) {
+        GemmTuner::Bucket &B = kv.second;
+        if (B.chosen > 0) continue;
+        bool done = true;
+        int best = 0;
+        for (int c = 0; c < GemmTuner::N_CAND; ++c) {
+            done &= B.runs[c] >= GemmTuner::REPS;
+            if (B.best[c] < B.best[best]) best = c;
+        }
+        if (done) B.chosen = GemmTuner::CAND[best];
+    }
+}
+
+hipEvent_t tuner_event(GemmTuner &T) {
+    if (!T.spare.empty()) {
+        hipEvent_t ev = T.spare.back();
+        T.spare.pop_back();
+        return ev;
+    }
+    hipEvent_t ev = nullptr;
+    if (hipEventCreate(&ev) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return ev;
+}
+
+// One rows-GEMM launch of the iteration over [0, hw_sb) slot blocks, with
+// the work split from the tuner (timed with events while it is a trial).
+template <class T>
+mos_status rows_step(mos_engine e, int ks, int hw_sb, int hw_p) {
+    hipStream_t st = e->ctx->stream;
+    int cand = -1;
+    const int spw = tuner_pick(e->tuner, hw_sb, &cand);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (cand >= 0) {
+        ev0 = tuner_event(e->tuner);
+        ev1 = tuner_event(e->tuner);
+        if (ev0 && ev1) MOS_HIP(hipEventRecord(ev0, st));
+    }
+    const void *const *tab = (const void *const *)(sizeof(T) == 4 ? e->kr32_tab : e->kr64_tab);
+    MOS_TRY(launch_rows<T>(e->ctx, ks, spw, st, tab, e->sb_rom, e->sb_prob, (const T *)e->Mc, (T *)e->Yi,
+                           e->ld_slots, hw_sb, e->ps, hw_p, e->pg, e->pd, e->pr));
+    if (cand >= 0 && ev0 && ev1) {
+        MOS_HIP(hipEventRecord(ev1, st));
+        int bucket = 0;
+        while ((1 << bucket) < hw_sb) ++bucket;
+        e->tuner.pending.push_back({bucket, cand, ev0, ev1});
+    } else {
+        if (ev0) e->tuner.spare.push_back(ev0);
+        if (ev1) e->tuner.spare.push_back(ev1);
+    }
     return MOS_OK;
 }
 
@@ -1098,19 +1215,15 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
         // many slot blocks each wave streams from the batch size only (its
         // results do not depend on that choice).
         const int ks = e->ldk / 4;
-        const bool rows = e->gemm_rows && (ks == 8 || ks == 20 || ks == 44);
+        const bool rows = e->gemm_rows && ks <= ROWS_MAX_KS;
         const int nrb = e->ldk / 16;
-        const int spw = std::max(1, (int)((int64_t)hw_sb * nrb / 2048));
-        const int64_t tasks = (int64_t)nrb * ceil_div(hw_sb, spw);
-        const dim3 g_rows((unsigned)std::max<int64_t>(ceil_div(tasks, 4), ceil_div(hw_p, 4)), 2);
+        (void)nrb;
         for (int j = 0; j < chunk; ++j) {
             if (e->precision == MOS_MIXED) {
                 float *V[NVEC];
                 for (int i = 0; i < NVEC; ++i) V[i] = static_cast<float *>(e->v[i]);
                 if (rows)
-                    MOS_TRY(launch_rows<float>(ctx, ks, g_rows, st, (const void *const *)e->kr32_tab, e->sb_rom, e->sb_prob,
-                                            (const float *)e->Mc, (float *)e->Yi, e->ld_slots, hw_sb, spw, e->ps, hw_p,
-                                            e->pg, e->pd, e->pr));
+                    MOS_TRY(rows_step<float>(e, ks, hw_sb, hw_p));
                 else
                     launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm<float>, g_gemm, dim3(256), 0, st,
                                  (const void *const *)e->kr32_tab, (const int32_t *)e->sb_rom,
@@ -1126,9 +1239,7 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
                 double *V[NVEC];
                 for (int i = 0; i < NVEC; ++i) V[i] = static_cast<double *>(e->v[i]);
                 if (rows)
-                    MOS_TRY(launch_rows<double>(ctx, ks, g_rows, st, (const void *const *)e->kr64_tab, e->sb_rom, e->sb_prob,
-                                            (const double *)e->Mc, (double *)e->Yi, e->ld_slots, hw_sb, spw, e->ps, hw_p,
-                                            e->pg, e->pd, e->pr));
+                    MOS_TRY(rows_step<double>(e, ks, hw_sb, hw_p));
                 else
                     launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm<double>, g_gemm, dim3(256), 0, st,
                                  (const void *const *)e->kr64_tab, (const int32_t *)e->sb_rom,
@@ -1147,6 +1258,7 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
         std::vector<ProbState> hs(hw_p);
         MOS_HIP(hipMemcpyAsync(hs.data(), e->ps, hw_p * sizeof(ProbState), hipMemcpyDeviceToHost, st));
         MOS_HIP(hipStreamSynchronize(st));
+        tuner_collect(e->tuner);
         std::vector<EngineProblem *> stopped;
         for (EngineProblem *P : e->active) {
             if (P->state != 1) continue;
@@ -1316,6 +1428,13 @@ void engine_free(mos_engine e) {
     e->queue.clear();
     e->active.clear();
     e->finished.clear();
+    for (auto &pd : e->tuner.pending) {
+        (void)hipEventDestroy(pd.start);
+        (void)hipEventDestroy(pd.stop);
+    }
+    for (hipEvent_t ev : e->tuner.spare) (void)hipEventDestroy(ev);
+    e->tuner.pending.clear();
+    e->tuner.spare.clear();
     e->mem.release();
     if (e->scale_host) (void)hipHostFree(e->scale_host);
     e->scale_host = nullptr;

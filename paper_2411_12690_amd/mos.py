@@ -28,6 +28,7 @@ EXPORTED = ("mos_ctx_create", "mos_ctx_destroy", "mos_build_cell", "mos_reduce",
 MOS_K_CELL_GEMM, MOS_K_ASSEMBLE, MOS_K_PCG_UPDATE, MOS_K_RECON = 1, 2, 3, 4
 MOS_OPT_CELL_GEMM = 1
 GEMM_TILES, GEMM_ROWS = 1, 2
+MOS_OPT_GEMM_SPLIT = 2
 
 
 class MosError(RuntimeError):

@@ -51,9 +51,11 @@ def n_dofs_of(nx, ny):
     return 3 * (X * Y * 4 - nx * ny * 1 * 1 * 2)
 
 
-def run_engine(env, probs, mixed=False, budget=1 << 28, iterations=16, interleave=None, gemm=None):
+def run_engine(env, probs, mixed=False, budget=1 << 28, iterations=16, interleave=None, gemm=None, split=None):
     mos, ctx, roms, oroms, torch = env
     eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=budget, gemm=gemm)
+    if split is not None:
+        eng.option(mos.MOS_OPT_GEMM_SPLIT, split)
     dt = torch.float32 if mixed else torch.float64
     n_elem = roms[0].query(mos.MOS_Q_CELL_ELEMS)
     outs = {}
@@ -144,3 +146,17 @@ def test_admission_while_others_iterate(env):
         u_ref, vm_ref = oracle_solution(oroms, nx, ny, t, dT)
         assert np.abs(r[5] - u_ref).max() <= 1e-10 * np.abs(u_ref).max()
         assert np.abs(r[4] - vm_ref).max() <= 1e-9 * np.abs(vm_ref).max()
+
+
+@pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "mixed"])
+def test_gemm_work_split_never_changes_results(env, mixed):
+    """The rows GEMM's work split (fixed or tuned online) only decides which
+    wave computes which output tile, so results are bitwise identical."""
+    probs = problems(5, [(3, 2), (5, 4), (2, 7), (6, 6)])
+    ref = run_engine(env, probs, mixed=mixed, gemm=2, split=1)
+    for split in (4, 0):
+        res = run_engine(env, probs, mixed=mixed, gemm=2, split=split)
+        for a, b in zip(ref, res):
+            assert a[2] == b[2] and a[3] == b[3]
+            assert np.array_equal(a[5], b[5])
+            assert np.array_equal(a[4], b[4])
