@@ -99,6 +99,7 @@ struct mos_engine_s {
     void **kr64_tab = nullptr, **kr32_tab = nullptr;
     double **br_tab = nullptr, **psi_tab = nullptr, **sigt_tab = nullptr;
     void *ub = nullptr;  // BF16 split of a finished problem's cell block (mixed reconstruction)
+    mos::ReconJob *jobs = nullptr, *jobs_host = nullptr;  // batched reconstruction table (device, pinned)
     int32_t *surf = nullptr;  // [S][3] surface Lagrange nodes (i, j, k) of a cell, s order
     int S = 0;
     // host state

@@ -918,6 +918,14 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     surface_nodes(e->roms[0]->desc.interp[0], e->roms[0]->desc.interp[1], e->roms[0]->desc.interp[2], surf);
     e->S = (int)surf.size() / 3;
     MOS_TRY(m.alloc_n(surf.size(), &e->surf));
+    MOS_TRY(m.alloc_n((size_t)MAX_PROBS * MAX_TYPES, &e->jobs));
+    if (hipHostMalloc((void **)&e->jobs_host, (size_t)MAX_PROBS * MAX_TYPES * sizeof(ReconJob),
+                      hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        e->jobs_host = nullptr;
+        set_error("pinned host allocation failed");
+        return MOS_ENOMEM;
+    }
     MOS_TRY(m.alloc_n(MAX_TYPES, &e->kr64_tab));
     MOS_TRY(m.alloc_n(MAX_TYPES, &e->kr32_tab));
     MOS_TRY(m.alloc_n(MAX_TYPES, &e->br_tab));
@@ -1294,11 +1302,29 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
             }
         }
     }
-    // 4. Retire finished problems (reconstruct into their buffers first).
+    // 4. Retire finished problems (reconstruct into their buffers first).  The
+    // FP64 reconstructions of every problem retiring now share one launch per
+    // cell type, so each block of the stress basis is staged once for all.
+    const bool batch_recon = e->precision == MOS_FP64 && e->ldk / 4 <= RECON_F64_LDS_KS;
+    if (batch_recon) {
+        const int n_roms = (int)e->roms.size();
+        std::vector<std::vector<ReconJob>> jobs(n_roms);
+        for (EngineProblem *P : e->active) {
+            if (P->state != 2 || !(P->vm || P->sig6)) continue;
+            for (int t = 0; t < n_roms; ++t) {
+                const int nsb = P->seg[t + 1] - P->seg[t];
+                if (nsb <= 0) continue;
+                const int off = jobs[t].empty() ? 0 : jobs[t].back().sb_off + jobs[t].back().n_sb;
+                jobs[t].push_back(ReconJob{P->sb_begin + P->seg[t], off, nsb, 0, P->dT, P->vm, P->sig6});
+            }
+        }
+        MOS_TRY(recon_f64_jobs(ctx, e->roms.data(), n_roms, jobs.data(), e->jobs, e->jobs_host,
+                               (const double *)e->Mc64, e->ld_slots, (const int32_t *)e->perm, false));
+    }
     std::vector<EngineProblem *> keep;
     for (EngineProblem *P : e->active) {
         if (P->state == 2 || P->state == 3) {
-            if (P->state == 2 && (P->vm || P->sig6)) MOS_TRY(reconstruct_problem(e, P));
+            if (P->state == 2 && (P->vm || P->sig6) && !batch_recon) MOS_TRY(reconstruct_problem(e, P));
             if (P->state == 2 && P->u_out)
                 MOS_HIP(hipMemcpyAsync(P->u_out, e->x64 + (int64_t)P->blk_begin * DB, P->n_dofs * 8,
                                        hipMemcpyDeviceToDevice, st));
@@ -1438,6 +1464,8 @@ void engine_free(mos_engine e) {
     e->mem.release();
     if (e->scale_host) (void)hipHostFree(e->scale_host);
     e->scale_host = nullptr;
+    if (e->jobs_host) (void)hipHostFree(e->jobs_host);
+    e->jobs_host = nullptr;
 }
 
 }  // namespace mos

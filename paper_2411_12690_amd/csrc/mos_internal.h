@@ -171,6 +171,23 @@ mos_status band_solve(mos_cell c, const double *dinv, double *rhs, int ldr, int 
 mos_status reduce_cell(mos_cell c, mos_rom r);
 // recon.hip
 mos_status reconstruct(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void *sigma6);
+// FP64 MFMA reconstruction with one element block of Psi staged in LDS per
+// workgroup, for bases with ldk / 4 <= RECON_F64_LDS_KS (else MOS_EINVAL).
+// A job is one problem's run of slot blocks of one type in the cell-major
+// block U ([ldk][ld]); jobs[t] lists type t's jobs, in order, with sb_off the
+// running count of slot blocks before each.  All of a type's jobs share one
+// launch, so Psi is staged once for all of them.  The job table goes through
+// host_jobs (pinned or otherwise stable until the copy completes) to
+// dev_jobs (room for every job).  Outputs are FP32 when fp32_out.
+constexpr int RECON_F64_LDS_KS = 44;
+struct ReconJob {
+    int32_t sb_first, sb_off, n_sb, pad;
+    double dT;
+    void *vm, *sig6;
+};
+mos_status recon_f64_jobs(mos_ctx ctx, const mos_rom *roms, int n_types, const std::vector<ReconJob> *jobs,
+                          ReconJob *dev_jobs, ReconJob *host_jobs, const double *U, int ld, const int32_t *perm,
+                          bool fp32_out);
 // BF16-split MFMA reconstruction (FP32 outputs) of the slot blocks
 // [sb_begin, sb_begin + tseg[n_types]) of the FP64 cell-major block U
 // ([ldk][ld]); type t owns [sb_begin + tseg[t], sb_begin + tseg[t + 1]).

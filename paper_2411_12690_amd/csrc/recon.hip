@@ -85,6 +85,81 @@ __global__ __launch_bounds__(256) void k_recon_f64(ReconTable tt, const double *
     }
 }
 
+// LDS-staged form for bases up to ldk = 176: one workgroup of 8 waves per
+// (element block of 16, slice of one type's slot blocks) stages that element
+// block of Psi -- all six components, ldk k-rows of 16 elements, 135 KB at
+// ldk = 176 -- in LDS once; each wave then streams slot blocks, holding u of
+// 16 cells (ks MFMA k-steps) in registers and reading the A fragments from
+// LDS, so Psi is read from memory once per workgroup instead of once per
+// wave.  Same accumulation order as k_recon_f64.
+template <class OutT, int KS, bool EXACT>
+__global__ __launch_bounds__(512, 1) void k_recon_f64_lds(const double *psi, const double *sig_t, const double *U,
+                                                          const int32_t *perm, int ld, const ReconJob *jobs,
+                                                          int n_jobs, int total_sb, int chunk, int ks, int n_elem) {
+    __shared__ double lds[6 * 4 * KS * 16];
+    if (EXACT) ks = KS;
+    const int ldk = 4 * ks;
+    const int eb = blockIdx.x;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int y0 = blockIdx.y * chunk, y1 = min(y0 + chunk, total_sb);
+    {
+        const double *g = psi + (size_t)eb * 6 * ldk * 16;
+        for (int i = threadIdx.x; i < 6 * ldk * 16; i += 512) lds[i] = g[i];
+    }
+    __syncthreads();
+    int j = 0;
+    for (int f = y0 + wave; f < y1; f += 8) {
+        // Flattened slot block f of the jobs -> its job (jobs in order of sb_off).
+        while (j + 1 < n_jobs && f >= jobs[j + 1].sb_off) ++j;
+        const ReconJob &J = jobs[j];
+        const size_t pc0 = (size_t)(J.sb_first + (f - J.sb_off)) * 16;
+        const double dT = J.dT;
+        OutT *vm = static_cast<OutT *>(J.vm);
+        OutT *sig6 = static_cast<OutT *>(J.sig6);
+        const double *bp = U + (size_t)(lane / 16) * ld + pc0 + lane % 16;
+        const double *ap = lds + (lane / 16) * 16 + lane % 16;
+        d4 acc[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
+        // u is streamed one k-step at a time (a few loads in flight through
+        // the partial unroll); the six accumulators stay in registers.
+        if (EXACT) {
+#pragma unroll 4
+            for (int k = 0; k < KS; ++k) {
+                const double b = bp[(size_t)(4 * k) * ld];
+#pragma unroll
+                for (int c = 0; c < 6; ++c)
+                    acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[(c * ldk + 4 * k) * 16], b, acc[c], 0, 0, 0);
+            }
+        } else {
+            for (int k = 0; k < ks; ++k) {
+                const double b = bp[(size_t)(4 * k) * ld];
+#pragma unroll
+                for (int c = 0; c < 6; ++c)
+                    acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[(c * ldk + 4 * k) * 16], b, acc[c], 0, 0, 0);
+            }
+        }
+        const int cell = perm[pc0 + lane % 16];
+        if (cell < 0) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = eb * 16 + lane / 16 + 4 * q;  // FP64 MFMA output row
+            if (e >= n_elem) continue;
+            double sv[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) sv[c] = acc[c][q] + dT * sig_t[(size_t)e * 6 + c];
+            const size_t o = (size_t)cell * n_elem + e;
+            if (vm) {
+                double x = sv[0] - sv[1], y = sv[1] - sv[2], z = sv[2] - sv[0];
+                vm[o] = (OutT)sqrt(0.5 * (x * x + y * y + z * z) + 3.0 * (sv[3] * sv[3] + sv[4] * sv[4] + sv[5] * sv[5]));
+            }
+            if (sig6)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) sig6[o * 6 + c] = (OutT)sv[c];
+        }
+    }
+}
+
 // Reduced-precision form of the same GEMM: BF16 operands, FP32 accumulation
 // on the 16x16x32 MFMA.  Plain BF16 rounding of Psi and u loses too much to
 // the cancellation inside Psi u, so both operands are split into hi + lo
@@ -214,6 +289,49 @@ __global__ __launch_bounds__(256, KSMAX <= 6 ? 2 : 1) void k_recon_bf16(const bf
 
 }  // namespace
 
+mos_status recon_f64_jobs(mos_ctx ctx, const mos_rom *roms, int n_types, const std::vector<ReconJob> *jobs,
+                          ReconJob *dev_jobs, ReconJob *host_jobs, const double *U, int ld, const int32_t *perm,
+                          bool fp32_out) {
+    if (n_types < 1 || n_types > MAX_TYPES) return MOS_EINVAL;
+    const mos_rom r = roms[0];
+    const int ks = r->ldk / 4;
+    if (ks > RECON_F64_LDS_KS) return MOS_EINVAL;
+    hipStream_t st = ctx->stream;
+    // One table upload for all types: type t's jobs at [first[t], first[t+1]).
+    std::vector<int> first(n_types + 1, 0);
+    for (int t = 0; t < n_types; ++t) first[t + 1] = first[t] + (int)jobs[t].size();
+    if (first[n_types] == 0) return MOS_OK;
+    for (int t = 0; t < n_types; ++t)
+        for (size_t i = 0; i < jobs[t].size(); ++i) host_jobs[first[t] + i] = jobs[t][i];
+    MOS_HIP(hipMemcpyAsync(dev_jobs, host_jobs, first[n_types] * sizeof(ReconJob), hipMemcpyHostToDevice, st));
+    for (int t = 0; t < n_types; ++t) {
+        const int nj = (int)jobs[t].size();
+        if (nj == 0) continue;
+        const int total = jobs[t].back().sb_off + jobs[t].back().n_sb;
+        // Slices give >= ~512 workgroups (one per CU at a time: 135 KB of
+        // LDS) while each slice still streams >= 16 slot blocks.
+        const int ny = std::max(1, std::min(total / 16, ceil_div(512, r->n_eblk)));
+        const int chunk = ceil_div(total, ny);
+        const dim3 grid(r->n_eblk, ceil_div(total, chunk));
+        const double *psi = roms[t]->psi, *sgt = roms[t]->sig_t;
+        const ReconJob *dj = dev_jobs + first[t];
+        if (ks == RECON_F64_LDS_KS && !fp32_out)
+            launch_timed(ctx, MOS_K_RECON, k_recon_f64_lds<double, RECON_F64_LDS_KS, true>, grid, dim3(512), 0, st, psi,
+                         sgt, U, perm, ld, dj, nj, total, chunk, ks, r->n_elem);
+        else if (!fp32_out)
+            launch_timed(ctx, MOS_K_RECON, k_recon_f64_lds<double, RECON_F64_LDS_KS, false>, grid, dim3(512), 0, st,
+                         psi, sgt, U, perm, ld, dj, nj, total, chunk, ks, r->n_elem);
+        else if (ks == RECON_F64_LDS_KS)
+            launch_timed(ctx, MOS_K_RECON, k_recon_f64_lds<float, RECON_F64_LDS_KS, true>, grid, dim3(512), 0, st, psi,
+                         sgt, U, perm, ld, dj, nj, total, chunk, ks, r->n_elem);
+        else
+            launch_timed(ctx, MOS_K_RECON, k_recon_f64_lds<float, RECON_F64_LDS_KS, false>, grid, dim3(512), 0, st,
+                         psi, sgt, U, perm, ld, dj, nj, total, chunk, ks, r->n_elem);
+        MOS_LAUNCH_CHECK();
+    }
+    return MOS_OK;
+}
+
 int64_t recon_bf16_scratch(const mos_rom r, int n_sb) { return (int64_t)n_sb * r->nks * 64 * 2 * 16; }
 
 mos_status recon_bf16(mos_ctx ctx, const mos_rom *roms, int n_types, const int *tseg, const double *U, int ld,
@@ -283,6 +401,18 @@ mos_status reconstruct(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void 
         MOS_TRY(tmp.alloc((size_t)recon_bf16_scratch(s->roms[0], s->n_pc / 16), &scratch));
         MOS_TRY(recon_bf16(ctx, s->roms.data(), s->n_types, tseg.data(), U, s->n_pc, s->perm, 0, s->delta_T,
                            (float *)v, (float *)g, scratch));
+    } else if (s->ldk / 4 <= RECON_F64_LDS_KS) {
+        std::vector<std::vector<ReconJob>> jobs(s->n_types);
+        for (int t = 0; t < s->n_types; ++t) {
+            const int nsb = (s->seg[t + 1] - s->seg[t]) / 16;
+            if (nsb > 0) jobs[t].push_back(ReconJob{s->seg[t] / 16, 0, nsb, 0, s->delta_T, v, g});
+        }
+        ReconJob *dj = nullptr;
+        MOS_TRY(tmp.alloc_n(MAX_TYPES, &dj));
+        std::vector<ReconJob> hj(MAX_TYPES);
+        MOS_TRY(recon_f64_jobs(ctx, s->roms.data(), s->n_types, jobs.data(), dj, hj.data(), U, s->n_pc, s->perm,
+                               s->precision != MOS_FP64));
+        MOS_HIP(hipStreamSynchronize(st));  // the host job table is a local
     } else if (s->precision == MOS_FP64)
         launch_timed(ctx, MOS_K_RECON, k_recon_f64<double>, grid, dim3(256), 0, st, tt, (const double *)U,
                      (const int32_t *)s->perm, s->n_pc, s->ldk, s->n_elem, s->delta_T, (double *)v, (double *)g);
