@@ -31,6 +31,30 @@ enum { VX, VR, VU, VW, VZ, VQ, VS, VP, VM, VDINV, VRHS, NVEC };
 
 struct EngineProblem;
 
+// Selection of problems for a batched phase (bit p = problem id p), passed
+// by value to the kernels of that phase.
+struct ProbSel {
+    uint32_t bits[MAX_PROBS / 32];
+};
+// The selected ids in ascending order, for per-problem work (reductions,
+// state updates).
+struct PidList {
+    int32_t n;
+    int16_t pid[MAX_PROBS];
+};
+// Static parameters of an admitted problem (device table by problem id).
+struct ProbParams {
+    int64_t d0, n_dofs, nd_pad, bot_end, top_begin;
+    double dT;
+    Lattice lat;
+    int32_t blk_begin, n_blk, sb_begin, n_sb;
+};
+// Parameters of a problem's current refinement sweep (device table by id).
+struct SweepParams {
+    double scale_in, scale_out, rtol2;
+    int32_t max_iter, pad;
+};
+
 // Largest number of 4-wide k-steps (ldk <= 176, basis size <= 176) the
 // K_r-stationary GEMM keeps in registers; larger bases use the tile GEMM.
 constexpr int ROWS_MAX_KS = 44;
@@ -94,12 +118,13 @@ struct mos_engine_s {
     int32_t *perm = nullptr;                  // [ld_slots]
     mos::ProbState *ps = nullptr;             // [MAX_PROBS]
     double *res2 = nullptr, *bb2 = nullptr;   // [MAX_PROBS]
-    double *scale = nullptr;                  // [2*MAX_PROBS] inner rhs scale, correction scale
-    double *scale_host = nullptr;             // pinned staging of `scale`
+    double *host_scratch = nullptr;           // pinned: a few doubles read back from the device
     void **kr64_tab = nullptr, **kr32_tab = nullptr;
     double **br_tab = nullptr, **psi_tab = nullptr, **sigt_tab = nullptr;
     void *ub = nullptr;  // BF16 split of a finished problem's cell block (mixed reconstruction)
     mos::ReconJob *jobs = nullptr, *jobs_host = nullptr;  // batched reconstruction table (device, pinned)
+    mos::ProbParams *pp = nullptr, *pp_host = nullptr;    // per-problem parameters (device, pinned)
+    mos::SweepParams *sp = nullptr, *sp_host = nullptr;   // per-sweep parameters (device, pinned)
     int32_t *surf = nullptr;  // [S][3] surface Lagrange nodes (i, j, k) of a cell, s order
     int S = 0;
     // host state

@@ -16,6 +16,7 @@
 // FP64 inner solves for MOS_FP64, FP32 for MOS_MIXED), restarts or retires
 // them, and reconstructs finished ones.
 #include <algorithm>
+#include <cstring>
 #include <cmath>
 #include <deque>
 #include <map>
@@ -93,6 +94,10 @@ __device__ __forceinline__ void wave_sum3(const double *pa, const double *pb, co
     }
 }
 
+__device__ __forceinline__ bool selected(const ProbSel &S, int p) {
+    return p >= 0 && ((S.bits[p >> 5] >> (p & 31)) & 1u);
+}
+
 // Scalar step of iteration ps[p].it for one problem (one wave): fixed-order
 // sums of its dot-product partials, stop decision, and (alpha, beta).
 __device__ __forceinline__ void problem_step(ProbState &S, const double *pg, const double *pd, const double *pr) {
@@ -136,14 +141,15 @@ constexpr int GEMM_MAX_STEPS = 16;  // k-steps of 4 whose loads are issued toget
 
 // Y[k][slot] = sum_j K_r[j][k] Mc[j][slot] for one 16 x 16 tile per workgroup
 // (K_r symmetric), K split over four waves summed in a fixed order through
-// LDS.  Slot blocks [sb_base, sb_base + n_sb); with `gate` the tile is skipped
-// unless its problem is iterating.  Extra block rows beyond n_sb (iteration
+// LDS.  Slot blocks [sb_base, sb_base + n_sb); with gate 1 the tile is
+// skipped unless its problem is iterating, with gate 2 unless its problem is
+// in `sel`.  Extra block rows beyond n_sb (iteration
 // launches only) run one wave per problem: the step of iteration ps[p].it.
 template <class T>
 __global__ __launch_bounds__(256) void k_bgemm(const void *const *kr_tab, const int32_t *sb_rom, const int32_t *sb_prob,
                                                const T *Mc, T *Y, int ldk, int ld_slots, int sb_base, int n_sb,
                                                int gate, ProbState *ps, int n_probs, const double *pg,
-                                               const double *pd, const double *pr) {
+                                               const double *pd, const double *pr, ProbSel sel) {
     typedef typename Mfma<T>::v4 v4;
     __shared__ v4 red[GEMM_WAVES - 1][64];
     __shared__ int skip;
@@ -162,9 +168,11 @@ __global__ __launch_bounds__(256) void k_bgemm(const void *const *kr_tab, const 
     const int k_begin = wave * steps * 4;
     if (threadIdx.x == 0) {
         int sk = rom < 0;
-        if (!sk && gate) {
+        if (!sk && gate == 1) {
             const ProbState &S = ps[sb_prob[sb]];
             sk = !S.active || S.done;
+        } else if (!sk && gate == 2) {
+            sk = !selected(sel, sb_prob[sb]);
         }
         skip = sk;
     }
@@ -285,150 +293,7 @@ __device__ __forceinline__ void cell_scatter(T *Mc, int4 iv, int ci, int ld_slot
         if (e4[e] >= 0) Mc[(size_t)(3 * (e4[e] & MAX_SURF) + ci) * ld_slots + (e4[e] >> INC_SHIFT)] = v;
 }
 
-// Copy a DoF vector into the cell-major layout, DoFs [d0, d1).
-template <class S, class T>
-__global__ void k_scatter(const S *v, const int32_t *inc, T *Mc, int64_t d0, int64_t d1, int ld_slots) {
-    const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= d1) return;
-    cell_scatter(Mc, incidence(inc, d), (int)(d % 3), ld_slots, (T)v[d]);
-}
-
-// out = (raw operator applied to the scattered vector), DoFs [d0, d1).
-template <class T>
-__global__ void k_assemble_raw(const T *Y, const int32_t *inc, T *out, int64_t d0, int64_t d1, int ld_slots) {
-    const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= d1) return;
-    out[d] = cell_sum(Y, incidence(inc, d), (int)(d % 3), ld_slots);
-}
-
-// b_raw[d] = dT * sum over the cells around d of b_r(type)[3s+ci].
-__global__ void k_brhs(const double *const *br_tab, const int32_t *sb_rom, const int32_t *inc, double dT, double *b,
-                       int64_t d0, int64_t d1) {
-    const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= d1) return;
-    const int4 iv = incidence(inc, d);
-    const int e4[4] = {iv.x, iv.y, iv.z, iv.w};
-    const int ci = (int)(d % 3);
-    double s = 0.0;
-    for (int e = 0; e < 4; ++e)
-        if (e4[e] >= 0) s += br_tab[sb_rom[(e4[e] >> INC_SHIFT) / 16]][3 * (e4[e] & MAX_SURF) + ci];
-    b[d] = dT * s;
-}
-
-template <class T>
-__global__ void k_bdiag(const void *const *kr64_tab, const int32_t *sb_rom, const int32_t *inc, const uint8_t *cmask,
-                        T *dinv, int64_t d0, int64_t d1, int ldk) {
-    const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= d1) return;
-    const int4 iv = incidence(inc, d);
-    const int e4[4] = {iv.x, iv.y, iv.z, iv.w};
-    const int ci = (int)(d % 3);
-    double s = 0.0;
-    for (int e = 0; e < 4; ++e)
-        if (e4[e] >= 0) {
-            const int k = 3 * (e4[e] & MAX_SURF) + ci;
-            s += static_cast<const double *>(kr64_tab[sb_rom[(e4[e] >> INC_SHIFT) / 16]])[(size_t)k * ldk + k];
-        }
-    dinv[d] = (cmask[d] || s == 0.0) ? T(1) : T(1.0 / s);
-}
-
-// Partials of ||b_l||^2 with the lifted rhs b_l = g (constrained), b - A g (free).
-__global__ void k_blift_norm(const double *b_raw, const double *ag, const double *g, const uint8_t *cmask,
-                             double *part, int64_t d0) {
-    const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const double v = cmask[d] ? g[d] : b_raw[d] - ag[d];
-    double a = v * v, b = 0.0, c = 0.0;
-    block_sum3(a, b, c);
-    if (threadIdx.x == 0) part[d0 / DB + blockIdx.x] = a;
-}
-
-// True residual of the lifted system (0 on constrained DoFs), its partials.
-__global__ void k_bresidual(const double *b_raw, const double *ax, const uint8_t *cmask, double *r, double *part,
-                            int64_t d0) {
-    const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const double v = cmask[d] ? 0.0 : b_raw[d] - ax[d];
-    r[d] = v;
-    double a = v * v, b = 0.0, c = 0.0;
-    block_sum3(a, b, c);
-    if (threadIdx.x == 0) part[d0 / DB + blockIdx.x] = a;
-}
-
-// dst[p] = fixed-order sum of part[begin, end).
-__global__ void k_reduce_range(const double *part, int begin, int end, double *dst) {
-    double a, b, c;
-    wave_sum3(part, part, part, begin, end, a, b, c);
-    if (threadIdx.x == 0) *dst = a;
-}
-
-template <class T>
-__global__ void k_to_inner(const double *r64, T *rhs, const double *scale_of, int64_t d0) {
-    const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    rhs[d] = (T)(r64[d] * *scale_of);
-}
-
-template <class T>
-__global__ void k_add_inner(double *x, const T *dx, const double *scale_of, double sign, int64_t d0) {
-    const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    x[d] += sign * *scale_of * (double)dx[d];
-}
-
-__global__ void k_prob_start(ProbState *ps, int p, int blk_begin, int blk_end, double rtol2, int max_iter) {
-    ProbState &S = ps[p];
-    S.gamma_prev = S.alpha_prev = S.a_cur = S.b_cur = S.rr = S.tol2 = 0.0;
-    S.rtol2 = rtol2;
-    S.it = 0;
-    S.done = 0;
-    S.active = 1;
-    S.max_iter = max_iter;
-    S.blk_begin = blk_begin;
-    S.blk_end = blk_end;
-}
-
 __global__ void k_prob_stop(ProbState *ps, int p) { ps[p].active = 0; }
-
-// Inner solve start, part 1 (DoFs [d0, d0 + 256*gridDim)): r = rhs,
-// u = M^-1 r, x = z = q = s = p = 0, u copied to the cell layout.
-template <class T>
-__global__ void k_bstart(const T *rhs, const T *dinv, const int32_t *inc, T *x, T *r, T *u, T *z, T *q, T *s, T *p,
-                         T *Mc, int64_t d0, int ld_slots) {
-    const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const T rv = rhs[d];
-    const T uv = dinv[d] * rv;
-    x[d] = 0;
-    r[d] = rv;
-    u[d] = uv;
-    z[d] = 0;
-    q[d] = 0;
-    s[d] = 0;
-    p[d] = 0;
-    cell_scatter(Mc, incidence(inc, d), (int)(d % 3), ld_slots, uv);
-}
-
-// Part 2: w = A u (0 on constrained DoFs), m = M^-1 w to the cell layout,
-// partials of (r,u), (w,u), (r,r) for iteration 0.
-template <class T>
-__global__ void k_bstart2(const T *Y, const int32_t *inc, const uint8_t *cmask, const T *dinv, const T *r,
-                          const T *u, T *w, T *m, T *Mc, int64_t d0, int ld_slots, double *pg, double *pd,
-                          double *pr) {
-    const int64_t d = d0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int4 iv = incidence(inc, d);
-    const int ci = (int)(d % 3);
-    const T sum = cell_sum(Y, iv, ci, ld_slots);
-    const T wv = cmask[d] ? T(0) : sum;
-    const T mv = dinv[d] * wv;
-    w[d] = wv;
-    m[d] = mv;
-    cell_scatter(Mc, iv, ci, ld_slots, mv);
-    const double rv = (double)r[d], uv = (double)u[d];
-    double g = rv * uv, dl = (double)wv * uv, rr = rv * rv;
-    block_sum3(g, dl, rr);
-    if (threadIdx.x == 0) {
-        const int b = (int)(d0 / DB) + blockIdx.x;
-        pg[b] = g;
-        pd[b] = dl;
-        pr[b] = rr;
-    }
-}
 
 // One iteration, per DoF block of every iterating problem: n = A m from the
 // cell products, the eight recurrences with the published step, m = M^-1 w
@@ -491,27 +356,222 @@ __global__ __launch_bounds__(256) void k_bstep(const T *Y, const int32_t *inc, c
     }
 }
 
+// ---- batched per-problem phases (set-up, FP64 residual, sweep start/stop) ----
+// Kernels over DoF blocks [0, high water) act on the blocks of selected
+// problems only; per problem they do exactly what a single-problem launch
+// would, so batching never changes a problem's results.
+
+// Problem id of every DoF block and slot block of the listed problems.
+__global__ void k_fill_owner(PidList L, const ProbParams *pp, int32_t *blk_prob, int32_t *sb_prob) {
+    const int p = L.pid[blockIdx.x];
+    const ProbParams &P = pp[p];
+    for (int i = threadIdx.x; i < P.n_blk; i += blockDim.x) blk_prob[P.blk_begin + i] = p;
+    for (int i = threadIdx.x; i < P.n_sb; i += blockDim.x) sb_prob[P.sb_begin + i] = p;
+}
+
+// Constrained DoFs: padding and, when clamped, the bottom-plane nodes
+// [0, bot_end) and top-plane nodes [top_begin, n_nodes) (value 0); the
+// problem's incidence region doubles as the "last entry" table of its
+// prescribed list, reset to -1.
+__global__ void k_setup_dofs(ProbSel sel, const int32_t *blk_prob, const ProbParams *pp, uint8_t *cmask, double *g,
+                             double *x64, int32_t *inc) {
+    const int p = blk_prob[blockIdx.x];
+    if (!selected(sel, p)) return;
+    const ProbParams &P = pp[p];
+    const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x, i = d - P.d0;
+    const int64_t node = i / 3;
+    cmask[d] = (i >= P.n_dofs || node < P.bot_end || node >= P.top_begin) ? 1 : 0;
+    g[d] = 0.0;
+    x64[d] = 0.0;
+    inc[P.d0 / 3 * 4 + i] = -1;
+}
+
+// Incidence entries of the selected problems' nodes reset to -1.
+__global__ void k_clear_incidence(ProbSel sel, const int32_t *blk_prob, int32_t *inc, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (selected(sel, blk_prob[(i / 4 * 3) / DB])) inc[i] = -1;
+}
+
+// Node -> (slot, surface node) incidence of the selected problems, entries
+// in ascending cell id.  A node on a shared vertical face or edge belongs to
+// 2 or 4 cells; the rank of cell (cx, cy) among them follows from which side
+// of the face it lies.
+__global__ void k_incidence_sel(ProbSel sel, const int32_t *sb_prob, const ProbParams *pp, const int32_t *perm,
+                                int32_t *inc, const int32_t *surf, int S, int64_t n_slots) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_slots * S) return;
+    const int slot = (int)(idx / S), s = (int)(idx % S);
+    const int p = sb_prob[slot / 16];
+    if (!selected(sel, p)) return;
+    const int32_t cell = perm[slot];
+    if (cell < 0) return;
+    const Lattice &L = pp[p].lat;
+    const int cx = cell % L.Nx, cy = cell / L.Nx;
+    const int i = surf[3 * s], j = surf[3 * s + 1], k = surf[3 * s + 2];
+    const int64_t node = node_id(L, (int64_t)cx * (L.nx - 1) + i, (int64_t)cy * (L.ny - 1) + j, k);
+    const bool shx = (i == 0 && cx > 0) || (i == L.nx - 1 && cx < L.Nx - 1);
+    const int ux = (i == 0 && cx > 0) ? 1 : 0;
+    const int uy = (j == 0 && cy > 0) ? 1 : 0;
+    inc[(pp[p].d0 / 3 + node) * 4 + uy * (shx ? 2 : 1) + ux] = (slot << INC_SHIFT) | s;
+}
+
+// b_raw = dT * sum over the cells around each DoF of b_r(type), and the
+// Jacobi scaling 1 / sum of the K_r(type) diagonals (1 on constrained DoFs).
+template <class T>
+__global__ void k_rhs_diag(ProbSel sel, const int32_t *blk_prob, const ProbParams *pp,
+                           const double *const *br_tab, const void *const *kr64_tab, const int32_t *sb_rom,
+                           const int32_t *inc, const uint8_t *cmask, double *b, T *dinv, int ldk) {
+    const int p = blk_prob[blockIdx.x];
+    if (!selected(sel, p)) return;
+    const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x;
+    const int4 iv = incidence(inc, d);
+    const int e4[4] = {iv.x, iv.y, iv.z, iv.w};
+    const int ci = (int)(d % 3);
+    double sb = 0.0, sd = 0.0;
+    for (int e = 0; e < 4; ++e)
+        if (e4[e] >= 0) {
+            const int rom = sb_rom[(e4[e] >> INC_SHIFT) / 16];
+            const int k = 3 * (e4[e] & MAX_SURF) + ci;
+            sb += br_tab[rom][k];
+            sd += static_cast<const double *>(kr64_tab[rom])[(size_t)k * ldk + k];
+        }
+    b[d] = pp[p].dT * sb;
+    dinv[d] = (cmask[d] || sd == 0.0) ? T(1) : T(1.0 / sd);
+}
+
+// FP64 vector of the selected problems to the cell-major layout.
+__global__ void k_scatter_sel(ProbSel sel, const int32_t *blk_prob, const double *v, const int32_t *inc, double *Mc,
+                              int ld_slots) {
+    if (!selected(sel, blk_prob[blockIdx.x])) return;
+    const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x;
+    cell_scatter(Mc, incidence(inc, d), (int)(d % 3), ld_slots, v[d]);
+}
+
+// True residual of the lifted system r = b - A x (0 on constrained DoFs),
+// A x assembled from the FP64 cell products, and per-block partials of
+// ||r||^2 and, with `lift`, of ||b_l||^2 (b_l = g on constrained DoFs,
+// b - A g elsewhere; at set-up x = g).
+__global__ void k_residual_sel(ProbSel sel, const int32_t *blk_prob, const double *Y, const int32_t *inc,
+                               const double *b_raw, const uint8_t *cmask, const double *g, double *r, double *part_r,
+                               double *part_b, int lift, int ld_slots) {
+    if (!selected(sel, blk_prob[blockIdx.x])) return;
+    const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x;
+    const double ax = cell_sum(Y, incidence(inc, d), (int)(d % 3), ld_slots);
+    const bool c = cmask[d];
+    const double v = c ? 0.0 : b_raw[d] - ax;
+    r[d] = v;
+    double a = v * v, bl = 0.0, z = 0.0;
+    if (lift) {
+        const double w = c ? g[d] : v;
+        bl = w * w;
+    }
+    block_sum3(a, bl, z);
+    if (threadIdx.x == 0) {
+        part_r[blockIdx.x] = a;
+        if (lift) part_b[blockIdx.x] = bl;
+    }
+}
+
+// dst[p] = fixed-order sum of the partials of problem p's DoF blocks, for
+// each listed p (one block each); a second array with `part2`.
+__global__ void k_reduce_list(PidList L, const ProbParams *pp, const double *part, double *dst, const double *part2,
+                              double *dst2) {
+    if (threadIdx.x >= 64) return;
+    const int p = L.pid[blockIdx.x];
+    const int b0 = pp[p].blk_begin, b1 = b0 + pp[p].n_blk;
+    double a, b, c;
+    wave_sum3(part, part2 ? part2 : part, part, b0, b1, a, b, c);
+    if (threadIdx.x == 0) {
+        dst[p] = a;
+        if (part2) dst2[p] = b;
+    }
+}
+
+// Sweep start, per listed problem: fresh scalar state.
+__global__ void k_prob_start_list(PidList L, const ProbParams *pp, const SweepParams *sp, ProbState *ps) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L.n) return;
+    const int p = L.pid[i];
+    ProbState &S = ps[p];
+    S.gamma_prev = S.alpha_prev = S.a_cur = S.b_cur = S.rr = S.tol2 = 0.0;
+    S.rtol2 = sp[p].rtol2;
+    S.it = 0;
+    S.done = 0;
+    S.active = 1;
+    S.max_iter = sp[p].max_iter;
+    S.blk_begin = pp[p].blk_begin;
+    S.blk_end = pp[p].blk_begin + pp[p].n_blk;
+}
+
+__global__ void k_prob_stop_list(PidList L, ProbState *ps) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < L.n) ps[L.pid[i]].active = 0;
+}
+
+// Sweep start, part 1: inner right-hand side = scale_in * r (in T), r = rhs,
+// u = M^-1 r, x = z = q = s = p = 0, u to the cell layout.
+template <class T>
+__global__ void k_bstart_sel(ProbSel sel, const int32_t *blk_prob, const SweepParams *sp, const double *r64,
+                             const T *dinv, const int32_t *inc, T *x, T *r, T *u, T *z, T *q, T *s, T *p, T *Mc,
+                             int ld_slots) {
+    const int pid = blk_prob[blockIdx.x];
+    if (!selected(sel, pid)) return;
+    const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x;
+    const T rv = (T)(r64[d] * sp[pid].scale_in);
+    const T uv = dinv[d] * rv;
+    x[d] = 0;
+    r[d] = rv;
+    u[d] = uv;
+    z[d] = 0;
+    q[d] = 0;
+    s[d] = 0;
+    p[d] = 0;
+    cell_scatter(Mc, incidence(inc, d), (int)(d % 3), ld_slots, uv);
+}
+
+// Sweep start, part 2: w = A u (0 on constrained DoFs), m = M^-1 w to the
+// cell layout, partials of (r,u), (w,u), (r,r) for iteration 0.
+template <class T>
+__global__ void k_bstart2_sel(ProbSel sel, const int32_t *blk_prob, const T *Y, const int32_t *inc,
+                              const uint8_t *cmask, const T *dinv, const T *r, const T *u, T *w, T *m, T *Mc,
+                              int ld_slots, double *pg, double *pd, double *pr) {
+    if (!selected(sel, blk_prob[blockIdx.x])) return;
+    const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x;
+    const int4 iv = incidence(inc, d);
+    const int ci = (int)(d % 3);
+    const T sum = cell_sum(Y, iv, ci, ld_slots);
+    const T wv = cmask[d] ? T(0) : sum;
+    const T mv = dinv[d] * wv;
+    w[d] = wv;
+    m[d] = mv;
+    cell_scatter(Mc, iv, ci, ld_slots, mv);
+    const double rv = (double)r[d], uv = (double)u[d];
+    double g = rv * uv, dl = (double)wv * uv, rr = rv * rv;
+    block_sum3(g, dl, rr);
+    if (threadIdx.x == 0) {
+        pg[blockIdx.x] = g;
+        pd[blockIdx.x] = dl;
+        pr[blockIdx.x] = rr;
+    }
+}
+
+// x64 += sign * scale_out * dx on the selected problems (fold in a sweep's
+// correction, or take it back).
+template <class T>
+__global__ void k_add_inner_sel(ProbSel sel, const int32_t *blk_prob, const SweepParams *sp, double *x64, const T *dx,
+                                double sign) {
+    const int pid = blk_prob[blockIdx.x];
+    if (!selected(sel, pid)) return;
+    const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x;
+    x64[d] += sign * sp[pid].scale_out * (double)dx[d];
+}
+
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
 }
 
 // ---- problem set-up on the device (numbering contract of the abstract mesh) ----
-
-// Constrained DoFs of one problem: padding DoFs and, when clamped, the
-// bottom-plane nodes [0, bot_end) and top-plane nodes [top_begin, n_nodes)
-// (value 0); everything else free.  `last` (one int32 per DoF) is reset for
-// the prescribed list.
-__global__ void k_constraints(uint8_t *cmask, double *g, double *x64, int32_t *last, int64_t d0, int64_t nd_pad,
-                              int64_t n_dofs, int64_t bot_end, int64_t top_begin) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nd_pad) return;
-    const int64_t node = i / 3;
-    cmask[d0 + i] = (i >= n_dofs || node < bot_end || node >= top_begin) ? 1 : 0;
-    g[d0 + i] = 0.0;
-    x64[d0 + i] = 0.0;
-    last[i] = -1;
-}
 
 // Prescribed (DoF, value) list, a later entry overriding an earlier one: the
 // largest entry index per DoF wins, then only that entry is applied.
@@ -527,25 +587,6 @@ __global__ void k_prescribe(const int64_t *dof, const double *val, int64_t n, co
     cmask[d0 + dof[i]] = 1;
     g[d0 + dof[i]] = val[i];
     x64[d0 + dof[i]] = val[i];
-}
-
-// Node -> (slot, surface node) incidence, entries in ascending cell id.  A
-// node on a shared vertical face or edge belongs to 2 or 4 cells; the rank of
-// cell (cx, cy) among them follows from which side of the face it lies.
-__global__ void k_incidence(int32_t *inc, const int32_t *perm, int64_t n_slots, int slot0, const int32_t *surf, int S,
-                            Lattice L) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n_slots * S) return;
-    const int sl = (int)(idx / S), s = (int)(idx % S);
-    const int32_t cell = perm[sl];
-    if (cell < 0) return;
-    const int cx = cell % L.Nx, cy = cell / L.Nx;
-    const int i = surf[3 * s], j = surf[3 * s + 1], k = surf[3 * s + 2];
-    const int64_t node = node_id(L, (int64_t)cx * (L.nx - 1) + i, (int64_t)cy * (L.ny - 1) + j, k);
-    const bool shx = (i == 0 && cx > 0) || (i == L.nx - 1 && cx < L.Nx - 1);
-    const int ux = (i == 0 && cx > 0) ? 1 : 0;
-    const int uy = (j == 0 && cy > 0) ? 1 : 0;
-    inc[node * 4 + uy * (shx ? 2 : 1) + ux] = ((slot0 + sl) << INC_SHIFT) | s;
 }
 
 // Global DoF of cell DoF k in slot sl ([ldk][n_slots], -1 for padding).
@@ -672,73 +713,73 @@ namespace {
 // Smallest relative residual reduction asked of one FP32 inner solve.
 constexpr double INNER_RTOL_F32 = 5e-3;
 
-template <class T>
-mos_status start_inner(mos_engine e, EngineProblem *P, int max_iter, double rtol_in) {
+// Problems taking part in one batched phase.
+struct Batch {
+    ProbSel sel{};
+    PidList list{};
+    void add(int p) {
+        sel.bits[p >> 5] |= 1u << (p & 31);
+        list.pid[list.n++] = (int16_t)p;
+    }
+    bool empty() const { return list.n == 0; }
+};
+
+// FP64 true residual of the batch's problems into r64 and res2[p] (and, at
+// set-up, ||b_l||^2 into bb2[p]), from x64 scattered to the cell layout --
+// which is where the reconstruction later reads the solution.
+mos_status residual_batch(mos_engine e, const Batch &B, bool lift) {
     hipStream_t st = e->ctx->stream;
-    const int64_t d0 = (int64_t)P->blk_begin * DB;
-    T *V[NVEC];
-    for (int i = 0; i < NVEC; ++i) V[i] = static_cast<T *>(e->v[i]);
-    T *Mc = static_cast<T *>(e->Mc), *Y = static_cast<T *>(e->Yi);
-    hipLaunchKernelGGL(k_prob_start, dim3(1), dim3(1), 0, st, e->ps, P->pid, P->blk_begin, P->blk_begin + P->n_blk,
-                       rtol_in * rtol_in, max_iter);
-    hipLaunchKernelGGL(k_bstart<T>, dim3(P->n_blk), dim3(DB), 0, st, (const T *)V[VRHS], (const T *)V[VDINV], e->inc,
-                       V[VX], V[VR], V[VU], V[VZ], V[VQ], V[VS], V[VP], Mc, d0, e->ld_slots);
-    hipLaunchKernelGGL(k_bgemm<T>, dim3(e->ldk / 16, P->n_sb), dim3(256), 0, st,
-                       (const void *const *)(e->precision == MOS_MIXED ? e->kr32_tab : e->kr64_tab), e->sb_rom,
-                       e->sb_prob, (const T *)Mc, Y, e->ldk, e->ld_slots, P->sb_begin, P->n_sb, 0, e->ps, 0,
-                       (const double *)nullptr, (const double *)nullptr, (const double *)nullptr);
-    hipLaunchKernelGGL(k_bstart2<T>, dim3(P->n_blk), dim3(DB), 0, st, (const T *)Y, e->inc, e->cmask,
-                       (const T *)V[VDINV], (const T *)V[VR], (const T *)V[VU], V[VW], V[VM], Mc, d0, e->ld_slots,
-                       e->pg, e->pd, e->pr);
+    const int hw_blk = e->blk.high, hw_sb = e->sbs.high;
+    hipLaunchKernelGGL(k_scatter_sel, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
+                       (const double *)e->x64, (const int32_t *)e->inc, e->Mc64, e->ld_slots);
+    hipLaunchKernelGGL(k_bgemm<double>, dim3(e->ldk / 16, hw_sb), dim3(256), 0, st, (const void *const *)e->kr64_tab,
+                       e->sb_rom, e->sb_prob, (const double *)e->Mc64, e->Y64, e->ldk, e->ld_slots, 0, hw_sb, 2,
+                       e->ps, 0, (const double *)nullptr, (const double *)nullptr, (const double *)nullptr, B.sel);
+    hipLaunchKernelGGL(k_residual_sel, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
+                       (const double *)e->Y64, (const int32_t *)e->inc, (const double *)e->b_raw,
+                       (const uint8_t *)e->cmask, (const double *)e->g, e->r64, e->pr64, e->pd, lift ? 1 : 0,
+                       e->ld_slots);
+    hipLaunchKernelGGL(k_reduce_list, dim3(B.list.n), dim3(64), 0, st, B.list, (const ProbParams *)e->pp,
+                       (const double *)e->pr64, e->res2, lift ? (const double *)e->pd : (const double *)nullptr,
+                       e->bb2);
     MOS_LAUNCH_CHECK();
     return MOS_OK;
 }
 
-// r64 = b - A x (lifted, FP64) over the problem; its squared norm into res2[pid];
-// x is left scattered in the FP64 cell layout.
-mos_status residual(mos_engine e, EngineProblem *P) {
+// Device set-up of newly admitted problems (tables, constraints, incidence,
+// load, Jacobi scaling) and their first residual.  The host sources
+// (P->perm, P->sb_rom, P->pdof, P->pval, pp_host[p]) stay put until the
+// problem is released.
+mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, const Batch &B) {
     hipStream_t st = e->ctx->stream;
-    const int64_t d0 = (int64_t)P->blk_begin * DB, d1 = d0 + (int64_t)P->n_blk * DB;
-    hipLaunchKernelGGL((k_scatter<double, double>), dim3(P->n_blk), dim3(DB), 0, st, (const double *)e->x64, e->inc,
-                       e->Mc64, d0, d1, e->ld_slots);
-    hipLaunchKernelGGL(k_bgemm<double>, dim3(e->ldk / 16, P->n_sb), dim3(256), 0, st,
-                       (const void *const *)e->kr64_tab, e->sb_rom, e->sb_prob, (const double *)e->Mc64, e->Y64,
-                       e->ldk, e->ld_slots, P->sb_begin, P->n_sb, 0, e->ps, 0, (const double *)nullptr,
-                       (const double *)nullptr, (const double *)nullptr);
-    hipLaunchKernelGGL(k_assemble_raw<double>, dim3(P->n_blk), dim3(DB), 0, st, (const double *)e->Y64, e->inc, e->q64,
-                       d0, d1, e->ld_slots);
-    hipLaunchKernelGGL(k_bresidual, dim3(P->n_blk), dim3(DB), 0, st, (const double *)e->b_raw, (const double *)e->q64,
-                       e->cmask, e->r64, e->pr64, d0);
-    hipLaunchKernelGGL(k_reduce_range, dim3(1), dim3(64), 0, st, (const double *)e->pr64, P->blk_begin,
-                       P->blk_begin + P->n_blk, e->res2 + P->pid);
-    MOS_LAUNCH_CHECK();
-    return MOS_OK;
-}
-
-mos_status setup_problem(mos_engine e, EngineProblem *P) {
-    hipStream_t st = e->ctx->stream;
-    const int64_t d0 = (int64_t)P->blk_begin * DB, d1 = d0 + (int64_t)P->n_blk * DB;
-    const int64_t nd_pad = (int64_t)P->n_blk * DB;
-    // Tables and constraints, all built on the device from the numbering
-    // contract; the host sources (P->perm, P->sb_rom, P->pdof, P->pval) live
-    // until the problem is released.
-    const int slot0 = P->sb_begin * 16;
-    int32_t *inc_p = e->inc + d0 / 3 * 4;
-    auto fill32 = [&](void *p, int64_t n, uint32_t v) {
-        hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>(ceil_div(n, 256), 4096)), dim3(256), 0, st,
-                           (uint32_t *)p, n, v);
-    };
-    fill32(e->blk_prob + P->blk_begin, P->n_blk, (uint32_t)P->pid);
-    fill32(e->sb_prob + P->sb_begin, P->n_sb, (uint32_t)P->pid);
-    MOS_HIP(hipMemcpyAsync(e->sb_rom + P->sb_begin, P->sb_rom.data(), P->n_sb * 4, hipMemcpyHostToDevice, st));
-    MOS_HIP(hipMemcpyAsync(e->perm + slot0, P->perm.data(), P->perm.size() * 4, hipMemcpyHostToDevice, st));
-    const Lattice &L = P->lat;
-    const int64_t bot_end = (P->bc_flags & MOS_BC_CLAMP_BOTTOM) ? L.plane_full : 0;
-    const int64_t top_begin = (P->bc_flags & MOS_BC_CLAMP_TOP) ? L.n_nodes - L.plane_full : INT64_MAX;
-    hipLaunchKernelGGL(k_constraints, dim3(P->n_blk), dim3(DB), 0, st, e->cmask, e->g, e->x64, inc_p, d0, nd_pad,
-                       P->n_dofs, bot_end, top_begin);
-    const int64_t np = (int64_t)P->pdof.size();
-    if (np > 0) {
+    for (EngineProblem *P : adm) {
+        ProbParams &H = e->pp_host[P->pid];
+        const Lattice &L = P->lat;
+        H.d0 = (int64_t)P->blk_begin * DB;
+        H.n_dofs = P->n_dofs;
+        H.nd_pad = (int64_t)P->n_blk * DB;
+        H.bot_end = (P->bc_flags & MOS_BC_CLAMP_BOTTOM) ? L.plane_full : 0;
+        H.top_begin = (P->bc_flags & MOS_BC_CLAMP_TOP) ? L.n_nodes - L.plane_full : INT64_MAX;
+        H.dT = P->dT;
+        H.lat = L;
+        H.blk_begin = P->blk_begin;
+        H.n_blk = P->n_blk;
+        H.sb_begin = P->sb_begin;
+        H.n_sb = P->n_sb;
+        MOS_HIP(hipMemcpyAsync(e->pp + P->pid, &H, sizeof(ProbParams), hipMemcpyHostToDevice, st));
+        MOS_HIP(hipMemcpyAsync(e->sb_rom + P->sb_begin, P->sb_rom.data(), P->n_sb * 4, hipMemcpyHostToDevice, st));
+        MOS_HIP(hipMemcpyAsync(e->perm + P->sb_begin * 16, P->perm.data(), P->perm.size() * 4, hipMemcpyHostToDevice,
+                               st));
+    }
+    const int hw_blk = e->blk.high, hw_sb = e->sbs.high;
+    hipLaunchKernelGGL(k_fill_owner, dim3(B.list.n), dim3(256), 0, st, B.list, (const ProbParams *)e->pp, e->blk_prob,
+                       e->sb_prob);
+    hipLaunchKernelGGL(k_setup_dofs, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
+                       (const ProbParams *)e->pp, e->cmask, e->g, e->x64, e->inc);
+    for (EngineProblem *P : adm) {
+        const int64_t np = (int64_t)P->pdof.size();
+        if (np == 0) continue;
+        const int64_t d0 = (int64_t)P->blk_begin * DB;
         P->dev.ctx = e->ctx;
         int64_t *pdof = nullptr;
         double *pval = nullptr;
@@ -746,65 +787,94 @@ mos_status setup_problem(mos_engine e, EngineProblem *P) {
         MOS_TRY(P->dev.alloc_n(np, &pval));
         MOS_HIP(hipMemcpyAsync(pdof, P->pdof.data(), np * 8, hipMemcpyHostToDevice, st));
         MOS_HIP(hipMemcpyAsync(pval, P->pval.data(), np * 8, hipMemcpyHostToDevice, st));
-        hipLaunchKernelGGL(k_prescribe_last, dim3(ceil_div(np, 256)), dim3(256), 0, st, (const int64_t *)pdof, np, inc_p);
+        int32_t *last = e->inc + d0 / 3 * 4;
+        hipLaunchKernelGGL(k_prescribe_last, dim3(ceil_div(np, 256)), dim3(256), 0, st, (const int64_t *)pdof, np,
+                           last);
         hipLaunchKernelGGL(k_prescribe, dim3(ceil_div(np, 256)), dim3(256), 0, st, (const int64_t *)pdof,
-                           (const double *)pval, np, (const int32_t *)inc_p, e->cmask, e->g, e->x64, d0);
+                           (const double *)pval, np, (const int32_t *)last, e->cmask, e->g, e->x64, d0);
     }
-    fill32(inc_p, nd_pad / 3 * 4, 0xffffffffu);
-    const int64_t n_slots = (int64_t)P->n_sb * 16;
-    hipLaunchKernelGGL(k_incidence, dim3(ceil_div(n_slots * e->S, 256)), dim3(256), 0, st, inc_p,
-                       (const int32_t *)(e->perm + slot0), n_slots, slot0, (const int32_t *)e->surf, e->S, L);
-    MOS_LAUNCH_CHECK();
-    // b_raw, A g, ||b_l||^2, Jacobi diagonal.
-    hipLaunchKernelGGL(k_brhs, dim3(P->n_blk), dim3(DB), 0, st, (const double *const *)e->br_tab, e->sb_rom, e->inc,
-                       P->dT, e->b_raw, d0, d1);
-    hipLaunchKernelGGL((k_scatter<double, double>), dim3(P->n_blk), dim3(DB), 0, st, (const double *)e->g, e->inc,
-                       e->Mc64, d0, d1, e->ld_slots);
-    hipLaunchKernelGGL(k_bgemm<double>, dim3(e->ldk / 16, P->n_sb), dim3(256), 0, st,
-                       (const void *const *)e->kr64_tab, e->sb_rom, e->sb_prob, (const double *)e->Mc64, e->Y64,
-                       e->ldk, e->ld_slots, P->sb_begin, P->n_sb, 0, e->ps, 0, (const double *)nullptr,
-                       (const double *)nullptr, (const double *)nullptr);
-    hipLaunchKernelGGL(k_assemble_raw<double>, dim3(P->n_blk), dim3(DB), 0, st, (const double *)e->Y64, e->inc, e->q64,
-                       d0, d1, e->ld_slots);
-    hipLaunchKernelGGL(k_blift_norm, dim3(P->n_blk), dim3(DB), 0, st, (const double *)e->b_raw,
-                       (const double *)e->q64, (const double *)e->g, e->cmask, e->pr64, d0);
-    hipLaunchKernelGGL(k_reduce_range, dim3(1), dim3(64), 0, st, (const double *)e->pr64, P->blk_begin,
-                       P->blk_begin + P->n_blk, e->bb2 + P->pid);
+    const int64_t n_inc = (int64_t)hw_blk * DB / 3 * 4;
+    hipLaunchKernelGGL(k_clear_incidence, dim3((unsigned)std::min<int64_t>(ceil_div(n_inc, 256), 4096)), dim3(256),
+                       0, st, B.sel, (const int32_t *)e->blk_prob, e->inc, n_inc);
+    const int64_t n_slots = (int64_t)hw_sb * 16;
+    hipLaunchKernelGGL(k_incidence_sel, dim3(ceil_div(n_slots * e->S, 256)), dim3(256), 0, st, B.sel,
+                       (const int32_t *)e->sb_prob, (const ProbParams *)e->pp, (const int32_t *)e->perm, e->inc,
+                       (const int32_t *)e->surf, e->S, n_slots);
     if (e->precision == MOS_MIXED)
-        hipLaunchKernelGGL(k_bdiag<float>, dim3(P->n_blk), dim3(DB), 0, st, (const void *const *)e->kr64_tab,
-                           e->sb_rom, e->inc, e->cmask, (float *)e->v[VDINV], d0, d1, e->ldk);
+        hipLaunchKernelGGL(k_rhs_diag<float>, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
+                           (const ProbParams *)e->pp, (const double *const *)e->br_tab,
+                           (const void *const *)e->kr64_tab, (const int32_t *)e->sb_rom, (const int32_t *)e->inc,
+                           (const uint8_t *)e->cmask, e->b_raw, (float *)e->v[VDINV], e->ldk);
     else
-        hipLaunchKernelGGL(k_bdiag<double>, dim3(P->n_blk), dim3(DB), 0, st, (const void *const *)e->kr64_tab,
-                           e->sb_rom, e->inc, e->cmask, (double *)e->v[VDINV], d0, d1, e->ldk);
+        hipLaunchKernelGGL(k_rhs_diag<double>, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
+                           (const ProbParams *)e->pp, (const double *const *)e->br_tab,
+                           (const void *const *)e->kr64_tab, (const int32_t *)e->sb_rom, (const int32_t *)e->inc,
+                           (const uint8_t *)e->cmask, e->b_raw, (double *)e->v[VDINV], e->ldk);
     MOS_LAUNCH_CHECK();
-    // Inner right-hand side from the initial residual r = b_l.
-    MOS_TRY(residual(e, P));
+    // At set-up x = g, so one product A g gives both ||b_l|| and the residual.
+    return residual_batch(e, B, true);
+}
+
+// Inner solves of the batch's problems start from their FP64 residuals, with
+// the sweep parameters already in sp_host.
+template <class T>
+mos_status start_batch(mos_engine e, const Batch &B) {
+    hipStream_t st = e->ctx->stream;
+    const int hw_blk = e->blk.high, hw_sb = e->sbs.high, hw_p = e->pids.high;
+    T *V[NVEC];
+    for (int i = 0; i < NVEC; ++i) V[i] = static_cast<T *>(e->v[i]);
+    T *Mc = static_cast<T *>(e->Mc), *Y = static_cast<T *>(e->Yi);
+    MOS_HIP(hipMemcpyAsync(e->sp, e->sp_host, hw_p * sizeof(SweepParams), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_prob_start_list, dim3(ceil_div(B.list.n, 64)), dim3(64), 0, st, B.list,
+                       (const ProbParams *)e->pp, (const SweepParams *)e->sp, e->ps);
+    hipLaunchKernelGGL(k_bstart_sel<T>, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
+                       (const SweepParams *)e->sp, (const double *)e->r64, (const T *)V[VDINV],
+                       (const int32_t *)e->inc, V[VX], V[VR], V[VU], V[VZ], V[VQ], V[VS], V[VP], Mc, e->ld_slots);
+    hipLaunchKernelGGL(k_bgemm<T>, dim3(e->ldk / 16, hw_sb), dim3(256), 0, st,
+                       (const void *const *)(e->precision == MOS_MIXED ? e->kr32_tab : e->kr64_tab), e->sb_rom,
+                       e->sb_prob, (const T *)Mc, Y, e->ldk, e->ld_slots, 0, hw_sb, 2, e->ps, 0,
+                       (const double *)nullptr, (const double *)nullptr, (const double *)nullptr, B.sel);
+    hipLaunchKernelGGL(k_bstart2_sel<T>, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
+                       (const T *)Y, (const int32_t *)e->inc, (const uint8_t *)e->cmask, (const T *)V[VDINV],
+                       (const T *)V[VR], (const T *)V[VU], V[VW], V[VM], Mc, e->ld_slots, e->pg, e->pd, e->pr);
+    MOS_LAUNCH_CHECK();
     return MOS_OK;
 }
 
-// After residual(): the relative residual decides; restart the inner solve or
-// finish.  Refinement is kept monotone: a correction that raised the FP64
-// residual is undone and the next sweep gets half the iterations.
-mos_status after_residual(mos_engine e, EngineProblem *P, double res2, double bb2, bool *left) {
+// Fold the stopped inner solves' corrections into x64 (sign +1), or take a
+// correction back (sign -1).
+mos_status add_inner_batch(mos_engine e, const Batch &B, double sign) {
     hipStream_t st = e->ctx->stream;
-    *left = false;
+    const int hw_blk = e->blk.high;
+    if (e->precision == MOS_MIXED)
+        hipLaunchKernelGGL(k_add_inner_sel<float>, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
+                           (const SweepParams *)e->sp, e->x64, (const float *)e->v[VX], sign);
+    else
+        hipLaunchKernelGGL(k_add_inner_sel<double>, dim3(hw_blk), dim3(DB), 0, st, B.sel,
+                           (const int32_t *)e->blk_prob, (const SweepParams *)e->sp, e->x64,
+                           (const double *)e->v[VX], sign);
+    MOS_LAUNCH_CHECK();
+    return MOS_OK;
+}
+
+// After a residual: the relative residual decides; finish, fail, or set up
+// the next sweep's parameters in sp_host (*start).  Refinement is kept
+// monotone: a correction that raised the FP64 residual is taken back (one
+// residual round trip of its own) and the next sweep gets half the
+// iterations.
+mos_status decide(mos_engine e, EngineProblem *P, double res2, double bb2, bool *start) {
+    hipStream_t st = e->ctx->stream;
+    *start = false;
     const bool mixed = e->precision == MOS_MIXED;
     if (P->sweep_cap == 0) P->sweep_cap = mixed ? 256 : P->max_iters;
     if (P->last_res2 >= 0.0 && !(res2 <= P->last_res2)) {
-        const int64_t d0 = (int64_t)P->blk_begin * DB;
-        const double *sc = e->scale + 2 * P->pid + 1;
-        if (mixed)
-            hipLaunchKernelGGL(k_add_inner<float>, dim3(P->n_blk), dim3(DB), 0, st, e->x64, (const float *)e->v[VX],
-                               sc, -1.0, d0);
-        else
-            hipLaunchKernelGGL(k_add_inner<double>, dim3(P->n_blk), dim3(DB), 0, st, e->x64,
-                               (const double *)e->v[VX], sc, -1.0, d0);
-        MOS_LAUNCH_CHECK();
-        MOS_TRY(residual(e, P));
-        MOS_HIP(hipMemcpyAsync(e->scale_host + 2 * MAX_PROBS, e->res2 + P->pid, sizeof(double),
-                               hipMemcpyDeviceToHost, st));
+        Batch U;
+        U.add(P->pid);
+        MOS_TRY(add_inner_batch(e, U, -1.0));
+        MOS_TRY(residual_batch(e, U, false));
+        MOS_HIP(hipMemcpyAsync(e->host_scratch, e->res2 + P->pid, sizeof(double), hipMemcpyDeviceToHost, st));
         MOS_HIP(hipStreamSynchronize(st));
-        res2 = e->scale_host[2 * MAX_PROBS];  // scratch slot after the per-problem scales
+        res2 = e->host_scratch[0];
         P->sweep_cap = std::max(P->sweep_cap / 2, 8);
         P->undone++;
     }
@@ -815,12 +885,10 @@ mos_status after_residual(mos_engine e, EngineProblem *P, double res2, double bb
         P->state = 3;
         P->status = MOS_ENOCONV;
         P->error = "non-finite residual in the global solve";
-        *left = true;
         return MOS_OK;
     }
     if (P->rel <= P->rtol || res2 == 0.0) {
         P->state = 2;
-        *left = true;
         return MOS_OK;
     }
     const int max_refine = mixed ? 40 : 8;
@@ -831,41 +899,51 @@ mos_status after_residual(mos_engine e, EngineProblem *P, double res2, double bb
         P->error = buf;
         P->state = 3;
         P->status = MOS_ENOCONV;
-        *left = true;
         return MOS_OK;
     }
-    // Inner rhs = r / ||r|| (mixed) or r (FP64); scale kept on the device.
-    const int64_t d0 = (int64_t)P->blk_begin * DB;
-    double scale_in = e->precision == MOS_MIXED ? 1.0 / rnorm : 1.0;
-    double scale_out = e->precision == MOS_MIXED ? rnorm : 1.0;
-    double *sc = e->scale + 2 * P->pid;
-    double *hs = e->scale_host + 2 * P->pid;  // pinned; stable until the next sweep's sync
-    hs[0] = scale_in;
-    hs[1] = scale_out;
-    MOS_HIP(hipMemcpyAsync(sc, hs, 2 * sizeof(double), hipMemcpyHostToDevice, st));
-    if (e->precision == MOS_MIXED) {
-        hipLaunchKernelGGL(k_to_inner<float>, dim3(P->n_blk), dim3(DB), 0, st, (const double *)e->r64,
-                           (float *)e->v[VRHS], (const double *)sc, d0);
+    SweepParams &S = e->sp_host[P->pid];
+    // Inner rhs = r / ||r|| (mixed) or r (FP64).
+    S.scale_in = mixed ? 1.0 / rnorm : 1.0;
+    S.scale_out = mixed ? rnorm : 1.0;
+    double rtol_in;
+    if (mixed) {
         // The recurrences of pipelined CG drift from the true residual by
         // ~unit roundoff times the condition number, which in FP32 leaves
         // ~5e-3 of relative accuracy per sweep on these systems; asking the
         // inner solve for more only adds iterations.  The last sweep asks
         // for no more than the remaining factor to the final target.
-        const double rtol_in = std::min(0.5, std::max(INNER_RTOL_F32, P->rtol * bnorm / rnorm));
-        MOS_TRY(start_inner<float>(e, P, std::min(P->sweep_cap, P->max_iters - P->iters), rtol_in));
+        rtol_in = std::min(0.5, std::max(INNER_RTOL_F32, P->rtol * bnorm / rnorm));
     } else {
-        hipLaunchKernelGGL(k_to_inner<double>, dim3(P->n_blk), dim3(DB), 0, st, (const double *)e->r64,
-                           (double *)e->v[VRHS], (const double *)sc, d0);
         // FP64 inner solves aim at the final absolute target; the drift of
         // the pipelined recurrences (~2e-11 relative here) is made up by a
         // short second sweep on the true residual.
-        const double rtol_in = std::min(0.5, std::max(P->rtol * bnorm / rnorm, 1e-15));
-        MOS_TRY(start_inner<double>(e, P, std::min(P->sweep_cap, P->max_iters - P->iters), rtol_in));
+        rtol_in = std::min(0.5, std::max(P->rtol * bnorm / rnorm, 1e-15));
     }
-    MOS_LAUNCH_CHECK();
+    S.rtol2 = rtol_in * rtol_in;
+    S.max_iter = std::min(P->sweep_cap, P->max_iters - P->iters);
     P->sweeps++;
     P->state = 1;
+    *start = true;
     return MOS_OK;
+}
+
+// Decide every problem of a residual batch, then start the next sweep of
+// those that continue, all in one batched start.
+mos_status decide_and_start(mos_engine e, const std::vector<EngineProblem *> &probs) {
+    hipStream_t st = e->ctx->stream;
+    const int hw_p = e->pids.high;
+    std::vector<double> r2(hw_p), b2(hw_p);
+    MOS_HIP(hipMemcpyAsync(r2.data(), e->res2, hw_p * 8, hipMemcpyDeviceToHost, st));
+    MOS_HIP(hipMemcpyAsync(b2.data(), e->bb2, hw_p * 8, hipMemcpyDeviceToHost, st));
+    MOS_HIP(hipStreamSynchronize(st));
+    Batch S;
+    for (EngineProblem *P : probs) {
+        bool start = false;
+        MOS_TRY(decide(e, P, r2[P->pid], b2[P->pid], &start));
+        if (start) S.add(P->pid);
+    }
+    if (S.empty()) return MOS_OK;
+    return e->precision == MOS_MIXED ? start_batch<float>(e, S) : start_batch<double>(e, S);
 }
 
 }  // namespace
@@ -904,11 +982,10 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     MOS_TRY(m.alloc_n(MAX_PROBS, &e->ps));
     MOS_TRY(m.alloc_n(MAX_PROBS, &e->res2));
     MOS_TRY(m.alloc_n(MAX_PROBS, &e->bb2));
-    MOS_TRY(m.alloc_n(2 * MAX_PROBS, &e->scale));
-    if (hipHostMalloc((void **)&e->scale_host, (2 * MAX_PROBS + 8) * sizeof(double), hipHostMallocDefault) !=
+    if (hipHostMalloc((void **)&e->host_scratch, 8 * sizeof(double), hipHostMallocDefault) !=
         hipSuccess) {
         (void)hipGetLastError();
-        e->scale_host = nullptr;
+        e->host_scratch = nullptr;
         set_error("pinned host allocation failed");
         return MOS_ENOMEM;
     }
@@ -918,6 +995,15 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     surface_nodes(e->roms[0]->desc.interp[0], e->roms[0]->desc.interp[1], e->roms[0]->desc.interp[2], surf);
     e->S = (int)surf.size() / 3;
     MOS_TRY(m.alloc_n(surf.size(), &e->surf));
+    MOS_TRY(m.alloc_n(MAX_PROBS, &e->pp));
+    MOS_TRY(m.alloc_n(MAX_PROBS, &e->sp));
+    if (hipHostMalloc((void **)&e->pp_host, MAX_PROBS * sizeof(ProbParams), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&e->sp_host, MAX_PROBS * sizeof(SweepParams), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("pinned host allocation failed");
+        return MOS_ENOMEM;
+    }
+    std::memset((void *)e->sp_host, 0, MAX_PROBS * sizeof(SweepParams));
     MOS_TRY(m.alloc_n((size_t)MAX_PROBS * MAX_TYPES, &e->jobs));
     if (hipHostMalloc((void **)&e->jobs_host, (size_t)MAX_PROBS * MAX_TYPES * sizeof(ReconJob),
                       hipHostMallocDefault) != hipSuccess) {
@@ -945,7 +1031,7 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     fill32(e->inc, dofs / 3 * 4, 0xffffffffu);
     fill32(e->blk_prob, e->cap_blk, 0xffffffffu);
     fill32(e->sb_rom, e->cap_sb, 0xffffffffu);
-    fill32(e->sb_prob, e->cap_sb, 0u);
+    fill32(e->sb_prob, e->cap_sb, 0xffffffffu);  // -1: no owner (batched phases select by owner)
     fill32(e->ps, (int64_t)MAX_PROBS * sizeof(ProbState) / 4, 0u);
     MOS_LAUNCH_CHECK();
     std::vector<const void *> t64(MAX_TYPES, nullptr), t32(MAX_TYPES, nullptr), tb(MAX_TYPES, nullptr),
@@ -1041,6 +1127,8 @@ void release_problem(mos_engine e, EngineProblem *P) {
                        (uint32_t *)(e->blk_prob + P->blk_begin), (int64_t)P->n_blk, 0xffffffffu);
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>(ceil_div(P->n_sb, 256), 4096)), dim3(256), 0, st,
                        (uint32_t *)(e->sb_rom + P->sb_begin), (int64_t)P->n_sb, 0xffffffffu);
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>(ceil_div(P->n_sb, 256), 4096)), dim3(256), 0, st,
+                       (uint32_t *)(e->sb_prob + P->sb_begin), (int64_t)P->n_sb, 0xffffffffu);
     hipLaunchKernelGGL(k_prob_stop, dim3(1), dim3(1), 0, st, e->ps, P->pid);
     P->dev.release();  // stream-ordered: later work on this stream may reuse it
     e->blk.give(P->blk_begin, P->n_blk);
@@ -1197,21 +1285,17 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
         P->pid = pid;
         P->blk_begin = b;
         P->sb_begin = sb;
-        MOS_TRY(setup_problem(e, P));
         e->queue.pop_front();
         e->active.push_back(P);
         admitted.push_back(P);
     }
-    // Residual of the newly admitted problems decides their first sweep.
+    // Device set-up of everything admitted, in one batch; its residuals
+    // decide the first sweeps.
     if (!admitted.empty()) {
-        std::vector<double> r2(MAX_PROBS), b2(MAX_PROBS);
-        MOS_HIP(hipMemcpyAsync(r2.data(), e->res2, MAX_PROBS * 8, hipMemcpyDeviceToHost, st));
-        MOS_HIP(hipMemcpyAsync(b2.data(), e->bb2, MAX_PROBS * 8, hipMemcpyDeviceToHost, st));
-        MOS_HIP(hipStreamSynchronize(st));
-        for (EngineProblem *P : admitted) {
-            bool left = false;
-            MOS_TRY(after_residual(e, P, r2[P->pid], b2[P->pid], &left));
-        }
+        Batch B;
+        for (EngineProblem *P : admitted) B.add(P->pid);
+        MOS_TRY(setup_batch(e, admitted, B));
+        MOS_TRY(decide_and_start(e, admitted));
     }
     // 2. A chunk of iterations over everything that is iterating.
     bool any_iter = false;
@@ -1237,7 +1321,7 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
                                  (const void *const *)e->kr32_tab, (const int32_t *)e->sb_rom,
                                  (const int32_t *)e->sb_prob, (const float *)e->Mc, (float *)e->Yi, e->ldk,
                                  e->ld_slots, 0, hw_sb, 1, e->ps, hw_p, (const double *)e->pg, (const double *)e->pd,
-                                 (const double *)e->pr);
+                                 (const double *)e->pr, ProbSel{});
                 launch_timed(ctx, MOS_K_PCG_UPDATE, k_bstep<float>, dim3(hw_blk), dim3(DB), 0, st,
                              (const float *)e->Yi, (const int32_t *)e->inc, (const uint8_t *)e->cmask,
                              (const float *)V[VDINV], V[VX], V[VR], V[VU], V[VW], V[VZ], V[VQ], V[VS], V[VP], V[VM],
@@ -1253,7 +1337,7 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
                                  (const void *const *)e->kr64_tab, (const int32_t *)e->sb_rom,
                                  (const int32_t *)e->sb_prob, (const double *)e->Mc, (double *)e->Yi, e->ldk,
                                  e->ld_slots, 0, hw_sb, 1, e->ps, hw_p, (const double *)e->pg, (const double *)e->pd,
-                                 (const double *)e->pr);
+                                 (const double *)e->pr, ProbSel{});
                 launch_timed(ctx, MOS_K_PCG_UPDATE, k_bstep<double>, dim3(hw_blk), dim3(DB), 0, st,
                              (const double *)e->Yi, (const int32_t *)e->inc, (const uint8_t *)e->cmask,
                              (const double *)V[VDINV], V[VX], V[VR], V[VU], V[VW], V[VZ], V[VQ], V[VS], V[VP], V[VM],
@@ -1268,6 +1352,7 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
         MOS_HIP(hipStreamSynchronize(st));
         tuner_collect(e->tuner);
         std::vector<EngineProblem *> stopped;
+        Batch B;
         for (EngineProblem *P : e->active) {
             if (P->state != 1) continue;
             const ProbState &S = hs[P->pid];
@@ -1279,27 +1364,14 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
                 P->error = "PCG breakdown (p.Ap <= 0 or non-finite) at the start of a sweep";
                 continue;
             }
-            const int64_t d0 = (int64_t)P->blk_begin * DB;
-            const double *sc = e->scale + 2 * P->pid + 1;
-            if (e->precision == MOS_MIXED)
-                hipLaunchKernelGGL(k_add_inner<float>, dim3(P->n_blk), dim3(DB), 0, st, e->x64,
-                                   (const float *)e->v[VX], sc, 1.0, d0);
-            else
-                hipLaunchKernelGGL(k_add_inner<double>, dim3(P->n_blk), dim3(DB), 0, st, e->x64,
-                                   (const double *)e->v[VX], sc, 1.0, d0);
-            hipLaunchKernelGGL(k_prob_stop, dim3(1), dim3(1), 0, st, e->ps, P->pid);
-            MOS_TRY(residual(e, P));
             stopped.push_back(P);
+            B.add(P->pid);
         }
         if (!stopped.empty()) {
-            std::vector<double> r2(hw_p), b2(hw_p);
-            MOS_HIP(hipMemcpyAsync(r2.data(), e->res2, hw_p * 8, hipMemcpyDeviceToHost, st));
-            MOS_HIP(hipMemcpyAsync(b2.data(), e->bb2, hw_p * 8, hipMemcpyDeviceToHost, st));
-            MOS_HIP(hipStreamSynchronize(st));
-            for (EngineProblem *P : stopped) {
-                bool left = false;
-                MOS_TRY(after_residual(e, P, r2[P->pid], b2[P->pid], &left));
-            }
+            MOS_TRY(add_inner_batch(e, B, 1.0));
+            hipLaunchKernelGGL(k_prob_stop_list, dim3(ceil_div(B.list.n, 64)), dim3(64), 0, st, B.list, e->ps);
+            MOS_TRY(residual_batch(e, B, false));
+            MOS_TRY(decide_and_start(e, stopped));
         }
     }
     // 4. Retire finished problems (reconstruct into their buffers first).  The
@@ -1462,10 +1534,14 @@ void engine_free(mos_engine e) {
     e->tuner.pending.clear();
     e->tuner.spare.clear();
     e->mem.release();
-    if (e->scale_host) (void)hipHostFree(e->scale_host);
-    e->scale_host = nullptr;
+    if (e->host_scratch) (void)hipHostFree(e->host_scratch);
+    e->host_scratch = nullptr;
     if (e->jobs_host) (void)hipHostFree(e->jobs_host);
     e->jobs_host = nullptr;
+    if (e->pp_host) (void)hipHostFree(e->pp_host);
+    e->pp_host = nullptr;
+    if (e->sp_host) (void)hipHostFree(e->sp_host);
+    e->sp_host = nullptr;
 }
 
 }  // namespace mos
