@@ -309,6 +309,8 @@ def single_mode(args, mos, torch, np, W):
         w = 4 if mixed else 8
         budget = int((n_dofs_pad * 160 + n_cells * 16 * 176 * (2 * w + 24)) * 1.3) + (256 << 20)
         eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=budget)
+        if args.gemm_split is not None:
+            eng.option(mos.MOS_OPT_GEMM_SPLIT, args.gemm_split)
         vm = torch.empty((n_cells, n_elem), dtype=torch.float32 if mixed else torch.float64, device="cuda")
 
         def run():

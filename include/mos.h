@@ -230,10 +230,10 @@ mos_status mos_engine_result(mos_engine e, int64_t ticket, int32_t *status, doub
  * compositions. */
 /* MOS_OPT_GEMM_SPLIT sets how many consecutive 16-cell blocks one wave of
  * the K_r-stationary GEMM streams: 0 (default) lets the engine tune it online
- * per batch size (each candidate in {1, 2, 4, 8} is timed three times with
- * stream events, the fastest kept); k > 0 fixes it.  It only decides which
- * wave computes which output tile, so results do not depend on it; it may be
- * changed at any time. */
+ * per batch size (each candidate in {1, 2, 4, 8, 16, 32} is timed three times
+ * with stream events, the fastest kept); 1 <= k <= 64 fixes it.  It only
+ * decides which wave computes which output tile, so results do not depend
+ * on it; it may be changed at any time. */
 enum { MOS_OPT_CELL_GEMM = 1, MOS_OPT_GEMM_SPLIT = 2 };
 mos_status mos_engine_option(mos_engine e, int option, int64_t value);
 

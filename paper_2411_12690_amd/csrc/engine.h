@@ -66,15 +66,15 @@ constexpr int ROWS_MAX_KS = 44;
 // REPS times with stream events around its launch; the fastest (minimum
 // time) is then used for that bucket for the life of the engine.
 struct GemmTuner {
-    static constexpr int N_CAND = 4;
-    static constexpr int CAND[N_CAND] = {1, 2, 4, 8};
+    static constexpr int N_CAND = 6;
+    static constexpr int SPW[N_CAND] = {1, 2, 4, 8, 16, 32};
     static constexpr int REPS = 3;
     struct Bucket {
-        float best[N_CAND] = {1e30f, 1e30f, 1e30f, 1e30f};
-        int runs[N_CAND] = {0, 0, 0, 0};
-        int chosen = 0;  // 0 while tuning, else the chosen spw
+        float best[N_CAND] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
+        int runs[N_CAND] = {0, 0, 0, 0, 0, 0};
+        int chosen = 0;  // 0 while tuning, else 1 + the chosen candidate
     };
-    int fixed = 0;       // > 0: no tuning, always this spw
+    int fixed = 0;       // > 0: no tuning, always this split
     std::map<int, Bucket> buckets;
     struct Pending {
         int bucket, cand;

@@ -205,12 +205,15 @@ __global__ __launch_bounds__(256) void k_bgemm(const void *const *kr_tab, const 
     }
 }
 
-// K_r-stationary variant: one wave per (16-row block of K_r, run of `spw`
-// consecutive slot blocks).  The wave keeps its 16 rows of K_r (KS k-steps of
-// 4) in registers, reloading them only when the cell type changes, and for
-// each slot block issues all KS operand loads before its chain of KS MFMAs.
-// Each 16x16 output is one MFMA chain in k order, so results do not depend
-// on spw.  Grid row 1 holds the per-problem scalar waves.
+// K_r-stationary variant: one wave per (16-row block of K_r, run
+// of `spw` consecutive slot blocks).  The wave keeps its 16 rows of K_r (KS
+// k-steps of 4) in registers, reloading them only when the cell type
+// changes, and for each slot block issues all KS operand loads before its
+// chain of KS MFMAs.  Each 16x16 output is one MFMA chain in k order, so
+// results do not depend on spw.  Blocks from task_blocks on hold the
+// per-problem scalar waves.  (Staging a row block of K_r in LDS for a whole
+// workgroup was measured slower at every batch size: the extra barrier and
+// serial staging cost more than the occupancy it frees.)
 template <class T, int KS, bool EXACT>
 __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, const int32_t *sb_rom,
                                                     const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots,
@@ -1138,27 +1141,35 @@ void release_problem(mos_engine e, EngineProblem *P) {
 
 }  // namespace
 
-template <class T>
-mos_status launch_rows(mos_ctx ctx, int ks, int spw, hipStream_t st, const void *const *kr_tab, const int32_t *sb_rom,
-                       const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots, int n_sb, ProbState *ps,
-                       int n_probs, const double *pg, const double *pd, const double *pr) {
-    // Task blocks: 4 waves each, one wave per (row block, run of spw slot
-    // blocks); then the blocks whose waves compute each problem's scalars.
+template <class T, int KS, bool EXACT>
+void launch_rows_ks(mos_ctx ctx, int spw, hipStream_t st, const void *const *kr_tab, const int32_t *sb_rom,
+                    const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots, int n_sb, int ks, ProbState *ps,
+                    int n_probs, const double *pg, const double *pd, const double *pr) {
+    // One wave per (row block, run of spw slot blocks), 4 per workgroup; then
+    // the blocks whose waves compute each problem's scalars.
     const int nrb = ks / 4;
     const int task_blocks = (int)ceil_div((int64_t)nrb * ceil_div(n_sb, spw), 4);
     const dim3 grid((unsigned)(task_blocks + ceil_div(n_probs, 4)));
+    launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm_rows<T, KS, EXACT>, grid, dim3(256), 0, st, kr_tab, sb_rom, sb_prob,
+                 Mc, Y, ld_slots, 0, n_sb, spw, 1, task_blocks, ks, ps, n_probs, pg, pd, pr);
+}
+
+template <class T>
+mos_status launch_rows(mos_ctx ctx, int ks, int spw, hipStream_t st, const void *const *kr_tab,
+                       const int32_t *sb_rom, const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots, int n_sb,
+                       ProbState *ps, int n_probs, const double *pg, const double *pd, const double *pr) {
     if (ks == 8)
-        launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm_rows<T, 8, true>, grid, dim3(256), 0, st, kr_tab, sb_rom, sb_prob,
-                     Mc, Y, ld_slots, 0, n_sb, spw, 1, task_blocks, ks, ps, n_probs, pg, pd, pr);
+        launch_rows_ks<T, 8, true>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps, n_probs,
+                                   pg, pd, pr);
     else if (ks == 20)
-        launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm_rows<T, 20, true>, grid, dim3(256), 0, st, kr_tab, sb_rom, sb_prob,
-                     Mc, Y, ld_slots, 0, n_sb, spw, 1, task_blocks, ks, ps, n_probs, pg, pd, pr);
+        launch_rows_ks<T, 20, true>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps, n_probs,
+                                    pg, pd, pr);
     else if (ks == ROWS_MAX_KS)
-        launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm_rows<T, ROWS_MAX_KS, true>, grid, dim3(256), 0, st, kr_tab, sb_rom,
-                     sb_prob, Mc, Y, ld_slots, 0, n_sb, spw, 1, task_blocks, ks, ps, n_probs, pg, pd, pr);
+        launch_rows_ks<T, ROWS_MAX_KS, true>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps,
+                                             n_probs, pg, pd, pr);
     else if (ks < ROWS_MAX_KS)
-        launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm_rows<T, ROWS_MAX_KS, false>, grid, dim3(256), 0, st, kr_tab, sb_rom,
-                     sb_prob, Mc, Y, ld_slots, 0, n_sb, spw, 1, task_blocks, ks, ps, n_probs, pg, pd, pr);
+        launch_rows_ks<T, ROWS_MAX_KS, false>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks,
+                                              ps, n_probs, pg, pd, pr);
     else {
         set_error("no rows GEMM for %d k-steps", ks);
         return MOS_EINVAL;
@@ -1170,25 +1181,25 @@ mos_status launch_rows(mos_ctx ctx, int ks, int spw, hipStream_t st, const void 
 template <class T>
 mos_status rows_step(mos_engine e, int ks, int hw_sb, int hw_p);
 
-// Pick the rows-GEMM work split for `n_sb` active slot blocks; *timed is set
-// when this launch is a tuning trial (its events are then recorded by the
-// caller around the launch).
+// Pick the rows-GEMM work split for `n_sb` active slot blocks; *cand_out is
+// set to the candidate when this launch is a tuning trial (its events are
+// then recorded by the caller around the launch).
 int tuner_pick(GemmTuner &T, int n_sb, int *cand_out) {
     *cand_out = -1;
     if (T.fixed > 0) return T.fixed;
     int bucket = 0;
     while ((1 << bucket) < n_sb) ++bucket;
     GemmTuner::Bucket &B = T.buckets[bucket];
-    if (B.chosen > 0) return B.chosen;
-    for (int c = 0; c < GemmTuner::N_CAND; ++c) {
+    if (B.chosen > 0) return GemmTuner::SPW[B.chosen - 1];
+    for (int k = 0; k < GemmTuner::N_CAND; ++k) {
         int queued = 0;
-        for (const auto &pd : T.pending) queued += pd.bucket == bucket && pd.cand == c;
-        if (B.runs[c] + queued < GemmTuner::REPS) {
-            *cand_out = c;
-            return GemmTuner::CAND[c];
+        for (const auto &pd : T.pending) queued += pd.bucket == bucket && pd.cand == k;
+        if (B.runs[k] + queued < GemmTuner::REPS) {
+            *cand_out = k;
+            return GemmTuner::SPW[k];
         }
     }
-    return GemmTuner::CAND[0];  // all trials queued, results not read yet
+    return GemmTuner::SPW[0];  // all trials queued, results not read yet
 }
 
 // Read the tuning trials of the last chunk (the stream has been synchronised).
@@ -1215,7 +1226,7 @@ void tuner_collect(GemmTuner &T) {
             done &= B.runs[c] >= GemmTuner::REPS;
             if (B.best[c] < B.best[best]) best = c;
         }
-        if (done) B.chosen = GemmTuner::CAND[best];
+        if (done) B.chosen = best + 1;
     }
 }
 

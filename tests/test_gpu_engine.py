@@ -154,7 +154,7 @@ def test_gemm_work_split_never_changes_results(env, mixed):
     wave computes which output tile, so results are bitwise identical."""
     probs = problems(5, [(3, 2), (5, 4), (2, 7), (6, 6)])
     ref = run_engine(env, probs, mixed=mixed, gemm=2, split=1)
-    for split in (4, 0):
+    for split in (4, 16, 0):
         res = run_engine(env, probs, mixed=mixed, gemm=2, split=split)
         for a, b in zip(ref, res):
             assert a[2] == b[2] and a[3] == b[3]
