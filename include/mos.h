@@ -251,7 +251,7 @@ void mos_engine_destroy(mos_engine e);
  * time. */
 enum {
     MOS_K_CELL_GEMM = 1,    /* element-by-element K_r GEMM of the PCG matvec */
-    MOS_K_ASSEMBLE = 2,     /* node-centric sum of cell products (+ p.Ap) */
+    MOS_K_PCG_SCALARS = 2,  /* per-problem fixed-order reductions and CG step */
     MOS_K_PCG_UPDATE = 3,   /* PCG vector updates and reductions */
     MOS_K_RECON = 4,        /* stress reconstruction GEMM + von Mises */
     MOS_K_COUNT = 5

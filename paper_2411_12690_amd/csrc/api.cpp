@@ -492,8 +492,8 @@ mos_status mos_engine_create(mos_ctx ctx, const mos_rom *roms, int32_t n_roms, m
     }
     // Split the budget between DoF arrays and cell slots (~100 DoFs per cell).
     const double w = precision == MOS_MIXED ? 4.0 : 8.0;
-    const double per_dof = 11 * w + 5 * 8 + 1 + 16.0 / 3 + 4 * 8.0 / 256 + 4.0 / 256;
-    const double per_slot = e->ldk * (2 * w + 16) + 4 + 8.0 / 16 +
+    const double per_dof = 5 * w + 4 * 8 + 1 + 16.0 / 3 + 4 * 8.0 / 256 + 4.0 / 256;
+    const double per_slot = e->ldk * (2 * w + 16) + 4 + 8.0 / 16 + e->ldk / 16 * 8.0 / 16 +
                             (precision == MOS_MIXED ? (double)recon_bf16_scratch(roms[0], 1) / 16 : 0.0);
     const double units = (double)device_bytes / (100 * per_dof + per_slot);
     const int64_t dofs = (int64_t)(units * 100), slots = (int64_t)units;

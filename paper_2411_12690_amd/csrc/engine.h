@@ -23,11 +23,12 @@ struct ProbState {
     double rr;                      // ||r||^2 at the last check
     double tol2, rtol2;             // stop threshold and its relative form
     int it, done, active, max_iter; // iterations of this sweep; stop code; iterating; cap
-    int blk_begin, blk_end;         // the problem's DoF blocks (partial sums)
-    int pad0, pad1;
+    int blk_begin, blk_end;         // the problem's DoF blocks (partials of (r,u), (r,r))
+    int tile_begin, tile_end;       // its cell-GEMM tiles (partials of (u, A u))
 };
 
-enum { VX, VR, VU, VW, VZ, VQ, VS, VP, VM, VDINV, VRHS, NVEC };
+// Inner PCG vectors (Chronopoulos-Gear form), in the inner precision.
+enum { VX, VR, VP, VS, VDINV, NVEC };
 
 struct EngineProblem;
 
@@ -47,7 +48,7 @@ struct ProbParams {
     int64_t d0, n_dofs, nd_pad, bot_end, top_begin;
     double dT;
     Lattice lat;
-    int32_t blk_begin, n_blk, sb_begin, n_sb;
+    int32_t blk_begin, n_blk, sb_begin, n_sb, nrb, pad;
 };
 // Parameters of a problem's current refinement sweep (device table by id).
 struct SweepParams {
@@ -109,7 +110,8 @@ struct mos_engine_s {
     void *v[mos::NVEC] = {};                  // inner vectors (double or float)
     void *Mc = nullptr, *Yi = nullptr;        // inner cell layouts [ldk][ld_slots]
     double *Mc64 = nullptr, *Y64 = nullptr;   // FP64 cell layouts
-    double *x64 = nullptr, *b_raw = nullptr, *g = nullptr, *r64 = nullptr, *q64 = nullptr;
+    double *x64 = nullptr, *b_raw = nullptr, *g = nullptr, *r64 = nullptr;
+    double *pdel = nullptr;                   // [cap_sb * ldk/16] per-tile (u, A u) partials
     uint8_t *cmask = nullptr;
     int32_t *inc = nullptr;                   // [dofs/3][4]
     int32_t *blk_prob = nullptr;              // [cap_blk]

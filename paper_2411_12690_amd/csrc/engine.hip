@@ -98,16 +98,36 @@ __device__ __forceinline__ bool selected(const ProbSel &S, int p) {
     return p >= 0 && ((S.bits[p >> 5] >> (p & 31)) & 1u);
 }
 
-// Scalar step of iteration ps[p].it for one problem (one wave): fixed-order
-// sums of its dot-product partials, stop decision, and (alpha, beta).
-__device__ __forceinline__ void problem_step(ProbState &S, const double *pg, const double *pd, const double *pr) {
-    const int lane = threadIdx.x % 64;
-    if (!S.active || S.done) return;
+// Scalars of iteration ps[p].it of one problem, one workgroup per problem
+// (Chronopoulos-Gear form of PCG: one fused reduction per iteration).
+// Fixed-order sums -- each thread a fixed strided subset, then a fixed tree
+// -- of the problem's partials: gamma = (r,u) and rho = (r,r) per DoF block
+// from the last update, delta = (u, A u) per (row block, slot block) tile
+// from this iteration's cell GEMM.  Then the stop decision (1 converged,
+// 2 breakdown, 3 iteration cap) or the step (alpha, beta).
+__global__ __launch_bounds__(256) void k_cg_scalars(ProbState *ps, const double *pg, const double *pr,
+                                                    const double *pdel) {
+    __shared__ double red[3][256];
+    ProbState &S = ps[blockIdx.x];
+    if (!S.active || S.done) return;  // uniform over the workgroup
+    double g = 0.0, r = 0.0, dl = 0.0;
+    for (int i = S.blk_begin + threadIdx.x; i < S.blk_end; i += 256) {
+        g += pg[i];
+        r += pr[i];
+    }
+    for (int i = S.tile_begin + threadIdx.x; i < S.tile_end; i += 256) dl += pdel[i];
+    red[0][threadIdx.x] = g;
+    red[1][threadIdx.x] = r;
+    red[2][threadIdx.x] = dl;
+    __syncthreads();
+    for (int m = 128; m > 0; m >>= 1) {
+        if ((int)threadIdx.x < m)
+            for (int j = 0; j < 3; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + m];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double gamma = red[0][0], rr = red[1][0], delta = red[2][0];
     const int it = S.it;
-    const double g_prev = S.gamma_prev, a_prev = S.alpha_prev;
-    double gamma, delta, rr;
-    wave_sum3(pg, pd, pr, S.blk_begin, S.blk_end, gamma, delta, rr);
-    if (lane != 0) return;
     if (it == 0) S.tol2 = S.rtol2 * rr;
     int stop = 0;
     double alpha = 0.0, beta = 0.0;
@@ -119,8 +139,8 @@ __device__ __forceinline__ void problem_step(ProbState &S, const double *pg, con
         if (it == 0) {
             alpha = gamma / delta;
         } else {
-            beta = gamma / g_prev;
-            alpha = gamma / (delta - beta * gamma / a_prev);
+            beta = gamma / S.gamma_prev;
+            alpha = gamma / (delta - beta * gamma / S.alpha_prev);
         }
         if (!(alpha > 0.0) || !isfinite(alpha) || !isfinite(beta)) stop = 2;
     }
@@ -136,6 +156,19 @@ __device__ __forceinline__ void problem_step(ProbState &S, const double *pg, con
     }
 }
 
+// (u, A u) over one 16x16 output tile: the tile's products times the cell
+// operand at the same positions, summed over the wave in a fixed order
+// (padding slots hold zeros in the cell layout, so they add nothing).
+template <class T, class V4>
+__device__ __forceinline__ double tile_dot(const V4 &acc, const T *Mc, int ld_slots, int rb, int col, int lane) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        t += (double)acc[q] * (double)Mc[(size_t)(rb * 16 + Mfma<T>::row(lane, q)) * ld_slots + col];
+    for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m);
+    return t;
+}
+
 constexpr int GEMM_WAVES = 4;       // split-K ways of the cell GEMM
 constexpr int GEMM_MAX_STEPS = 16;  // k-steps of 4 whose loads are issued together
 
@@ -143,23 +176,16 @@ constexpr int GEMM_MAX_STEPS = 16;  // k-steps of 4 whose loads are issued toget
 // (K_r symmetric), K split over four waves summed in a fixed order through
 // LDS.  Slot blocks [sb_base, sb_base + n_sb); with gate 1 the tile is
 // skipped unless its problem is iterating, with gate 2 unless its problem is
-// in `sel`.  Extra block rows beyond n_sb (iteration
-// launches only) run one wave per problem: the step of iteration ps[p].it.
+// in `sel`.  With pdel, the tile's (u, A u) partial goes to
+// pdel[slot block * row blocks + row block].
 template <class T>
 __global__ __launch_bounds__(256) void k_bgemm(const void *const *kr_tab, const int32_t *sb_rom, const int32_t *sb_prob,
                                                const T *Mc, T *Y, int ldk, int ld_slots, int sb_base, int n_sb,
-                                               int gate, ProbState *ps, int n_probs, const double *pg,
-                                               const double *pd, const double *pr, ProbSel sel) {
+                                               int gate, const ProbState *ps, double *pdel, ProbSel sel) {
     typedef typename Mfma<T>::v4 v4;
     __shared__ v4 red[GEMM_WAVES - 1][64];
     __shared__ int skip;
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-    if ((int)blockIdx.y >= n_sb) {
-        if (blockIdx.x != 0) return;
-        const int p = ((int)blockIdx.y - n_sb) * GEMM_WAVES + wave;
-        if (p < n_probs) problem_step(ps[p], pg, pd, pr);
-        return;
-    }
     const int sb = sb_base + (int)blockIdx.y;
     const int rom = sb_rom[sb];
     const int rb = blockIdx.x, pc0 = sb * 16;
@@ -202,6 +228,10 @@ __global__ __launch_bounds__(256) void k_bgemm(const void *const *kr_tab, const 
         for (int w = 0; w < GEMM_WAVES - 1; ++w) acc += red[w][lane];
 #pragma unroll
         for (int q = 0; q < 4; ++q) Y[(size_t)(rb * 16 + Mfma<T>::row(lane, q)) * ld_slots + col] = acc[q];
+        if (pdel) {
+            const double t = tile_dot<T>(acc, Mc, ld_slots, rb, col, lane);
+            if (lane == 0) pdel[(size_t)sb * (ldk / 16) + rb] = t;
+        }
     }
 }
 
@@ -210,16 +240,15 @@ __global__ __launch_bounds__(256) void k_bgemm(const void *const *kr_tab, const 
 // k-steps of 4) in registers, reloading them only when the cell type
 // changes, and for each slot block issues all KS operand loads before its
 // chain of KS MFMAs.  Each 16x16 output is one MFMA chain in k order, so
-// results do not depend on spw.  Blocks from task_blocks on hold the
-// per-problem scalar waves.  (Staging a row block of K_r in LDS for a whole
+// results do not depend on spw.  With pdel, each tile's (u, A u) partial
+// goes to pdel[slot block * row blocks + row block].  (Staging a row block of K_r in LDS for a whole
 // workgroup was measured slower at every batch size: the extra barrier and
 // serial staging cost more than the occupancy it frees.)
 template <class T, int KS, bool EXACT>
 __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, const int32_t *sb_rom,
                                                     const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots,
-                                                    int sb_base, int n_sb, int spw, int gate, int task_blocks,
-                                                    int ks, ProbState *ps, int n_probs, const double *pg,
-                                                    const double *pd, const double *pr) {
+                                                    int sb_base, int n_sb, int spw, int gate, int ks,
+                                                    const ProbState *ps, double *pdel) {
     typedef typename Mfma<T>::v4 v4;
     // KS bounds the k-steps held in registers; the basis uses ks <= KS of
     // them (ldk = 4 ks), and steps past ks are neither loaded nor issued.
@@ -228,11 +257,6 @@ __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, c
     const int ldk = 4 * ks;
     const int nrb = ldk / 16;
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-    if ((int)blockIdx.x >= task_blocks) {
-        const int p = ((int)blockIdx.x - task_blocks) * 4 + wave;
-        if (p < n_probs) problem_step(ps[p], pg, pd, pr);
-        return;
-    }
     const int task = (int)blockIdx.x * 4 + wave;
     const int rb = task % nrb, run = task / nrb;
     const int s_begin = run * spw;
@@ -269,6 +293,10 @@ __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, c
         const int col = sb * 16 + lane % 16;
 #pragma unroll
         for (int q = 0; q < 4; ++q) Y[(size_t)(rb * 16 + Mfma<T>::row(lane, q)) * ld_slots + col] = acc[q];
+        if (pdel) {
+            const double t = tile_dot<T>(acc, Mc, ld_slots, rb, col, lane);
+            if (lane == 0) pdel[(size_t)sb * nrb + rb] = t;
+        }
     }
 }
 
@@ -298,14 +326,16 @@ __device__ __forceinline__ void cell_scatter(T *Mc, int4 iv, int ci, int ld_slot
 
 __global__ void k_prob_stop(ProbState *ps, int p) { ps[p].active = 0; }
 
-// One iteration, per DoF block of every iterating problem: n = A m from the
-// cell products, the eight recurrences with the published step, m = M^-1 w
-// to the cell layout, partials of the next (r,u), (w,u), (r,r).
+// One iteration, per DoF block of every iterating problem, Chronopoulos-Gear
+// form: with the published (alpha, beta) and w = A u assembled from the cell
+// products (u = M^-1 r),
+//   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,
+// then the next u = M^-1 r to the cell layout and the partials of the next
+// (r,u) and (r,r).  Only x, r, p and s are stored.
 template <class T>
-__global__ __launch_bounds__(256) void k_bstep(const T *Y, const int32_t *inc, const uint8_t *cmask, const T *dinv,
-                                               T *x, T *r, T *u, T *w, T *z, T *q, T *s, T *p, T *m, T *Mc,
-                                               int ld_slots, const int32_t *blk_prob, const ProbState *ps, double *pg,
-                                               double *pd, double *pr) {
+__global__ __launch_bounds__(256) void k_cgstep(const T *Y, const int32_t *inc, const uint8_t *cmask, const T *dinv,
+                                                T *x, T *r, T *p, T *s, T *Mc, int ld_slots, const int32_t *blk_prob,
+                                                const ProbState *ps, double *pg, double *pr) {
     __shared__ int go;
     __shared__ double step[2];
     const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x;
@@ -328,33 +358,23 @@ __global__ __launch_bounds__(256) void k_bstep(const T *Y, const int32_t *inc, c
     __syncthreads();
     if (!go) return;
     const T a = (T)step[0], b = (T)step[1];
-    const T zd = z[d], qd = q[d], sd = s[d], pd0 = p[d], ud = u[d], wd = w[d], md = m[d], rd = r[d], xd = x[d];
-    const T dv = dinv[d];
+    const T dv = dinv[d], rd = r[d], pd0 = p[d], sd = s[d], xd = x[d];
     const T sum = cell_sum(Y, iv, ci, ld_slots);
-    const T nv = cmask[d] ? T(0) : sum;
-    const T zv = nv + b * zd;
-    const T qv = md + b * qd;
-    const T sv = wd + b * sd;
-    const T pv = ud + b * pd0;
+    const T wv = cmask[d] ? T(0) : sum;
+    const T uv = dv * rd;
+    const T pv = uv + b * pd0;
+    const T sv = wv + b * sd;
     x[d] = xd + a * pv;
     const T rv = rd - a * sv;
-    const T uv = ud - a * qv;
-    const T wv = wd - a * zv;
-    const T mv = dv * wv;
-    z[d] = zv;
-    q[d] = qv;
-    s[d] = sv;
+    const T un = dv * rv;
     p[d] = pv;
+    s[d] = sv;
     r[d] = rv;
-    u[d] = uv;
-    w[d] = wv;
-    m[d] = mv;
-    cell_scatter(Mc, iv, ci, ld_slots, mv);
-    double g = (double)rv * (double)uv, dl = (double)wv * (double)uv, r2 = (double)rv * (double)rv;
-    block_sum3(g, dl, r2);
+    cell_scatter(Mc, iv, ci, ld_slots, un);
+    double g = (double)rv * (double)un, r2 = (double)rv * (double)rv, z = 0.0;
+    block_sum3(g, r2, z);
     if (threadIdx.x == 0) {
         pg[blockIdx.x] = g;
-        pd[blockIdx.x] = dl;
         pr[blockIdx.x] = r2;
     }
 }
@@ -504,6 +524,8 @@ __global__ void k_prob_start_list(PidList L, const ProbParams *pp, const SweepPa
     S.max_iter = sp[p].max_iter;
     S.blk_begin = pp[p].blk_begin;
     S.blk_end = pp[p].blk_begin + pp[p].n_blk;
+    S.tile_begin = pp[p].sb_begin * pp[p].nrb;
+    S.tile_end = (pp[p].sb_begin + pp[p].n_sb) * pp[p].nrb;
 }
 
 __global__ void k_prob_stop_list(PidList L, ProbState *ps) {
@@ -511,12 +533,13 @@ __global__ void k_prob_stop_list(PidList L, ProbState *ps) {
     if (i < L.n) ps[L.pid[i]].active = 0;
 }
 
-// Sweep start, part 1: inner right-hand side = scale_in * r (in T), r = rhs,
-// u = M^-1 r, x = z = q = s = p = 0, u to the cell layout.
+// Sweep start: inner right-hand side r = scale_in * r64 (in T), x = p = s =
+// 0, u = M^-1 r to the cell layout, partials of (r,u) and (r,r); the first
+// iteration's cell GEMM then gives w = A u and (u, A u).
 template <class T>
-__global__ void k_bstart_sel(ProbSel sel, const int32_t *blk_prob, const SweepParams *sp, const double *r64,
-                             const T *dinv, const int32_t *inc, T *x, T *r, T *u, T *z, T *q, T *s, T *p, T *Mc,
-                             int ld_slots) {
+__global__ void k_cgstart_sel(ProbSel sel, const int32_t *blk_prob, const SweepParams *sp, const double *r64,
+                              const T *dinv, const int32_t *inc, T *x, T *r, T *p, T *s, T *Mc, int ld_slots,
+                              double *pg, double *pr) {
     const int pid = blk_prob[blockIdx.x];
     if (!selected(sel, pid)) return;
     const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x;
@@ -524,38 +547,31 @@ __global__ void k_bstart_sel(ProbSel sel, const int32_t *blk_prob, const SweepPa
     const T uv = dinv[d] * rv;
     x[d] = 0;
     r[d] = rv;
-    u[d] = uv;
-    z[d] = 0;
-    q[d] = 0;
-    s[d] = 0;
     p[d] = 0;
+    s[d] = 0;
     cell_scatter(Mc, incidence(inc, d), (int)(d % 3), ld_slots, uv);
-}
-
-// Sweep start, part 2: w = A u (0 on constrained DoFs), m = M^-1 w to the
-// cell layout, partials of (r,u), (w,u), (r,r) for iteration 0.
-template <class T>
-__global__ void k_bstart2_sel(ProbSel sel, const int32_t *blk_prob, const T *Y, const int32_t *inc,
-                              const uint8_t *cmask, const T *dinv, const T *r, const T *u, T *w, T *m, T *Mc,
-                              int ld_slots, double *pg, double *pd, double *pr) {
-    if (!selected(sel, blk_prob[blockIdx.x])) return;
-    const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x;
-    const int4 iv = incidence(inc, d);
-    const int ci = (int)(d % 3);
-    const T sum = cell_sum(Y, iv, ci, ld_slots);
-    const T wv = cmask[d] ? T(0) : sum;
-    const T mv = dinv[d] * wv;
-    w[d] = wv;
-    m[d] = mv;
-    cell_scatter(Mc, iv, ci, ld_slots, mv);
-    const double rv = (double)r[d], uv = (double)u[d];
-    double g = rv * uv, dl = (double)wv * uv, rr = rv * rv;
-    block_sum3(g, dl, rr);
+    double g = (double)rv * (double)uv, r2 = (double)rv * (double)rv, z = 0.0;
+    block_sum3(g, r2, z);
     if (threadIdx.x == 0) {
         pg[blockIdx.x] = g;
-        pd[blockIdx.x] = dl;
-        pr[blockIdx.x] = rr;
+        pr[blockIdx.x] = r2;
     }
+}
+
+// Zeros in the cell-layout columns of the selected problems' padding slots
+// (no node refers to them, so nothing else ever writes them there).
+__global__ void k_zero_padding(ProbSel sel, const int32_t *sb_prob, const int32_t *perm, uint8_t *Mc, int elem,
+                               int ld_slots, int ldk, int64_t n_slots) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_slots * ldk) return;
+    const int64_t slot = idx % n_slots;
+    const int k = (int)(idx / n_slots);
+    if (!selected(sel, sb_prob[slot / 16]) || perm[slot] >= 0) return;
+    uint8_t *q = Mc + ((size_t)k * ld_slots + slot) * elem;
+    if (elem == 8)
+        *reinterpret_cast<double *>(q) = 0.0;
+    else
+        *reinterpret_cast<float *>(q) = 0.0f;
 }
 
 // x64 += sign * scale_out * dx on the selected problems (fold in a sweep's
@@ -713,8 +729,11 @@ mos_status prepare_problem(mos_engine e, const mos_array_desc *d, EngineProblem 
 // ---------------------------------------------------------------------------
 namespace {
 
-// Smallest relative residual reduction asked of one FP32 inner solve.
-constexpr double INNER_RTOL_F32 = 5e-3;
+// Relative residual reduction asked of one FP32 inner solve.  FP32 PCG in
+// this form tracks its true residual to below 1e-4 on these systems; a target
+// of 1e-2 per sweep minimised total iterations (sweeps are cheap: one batched
+// FP64 residual each).
+constexpr double INNER_RTOL_F32 = 1e-2;
 
 // Problems taking part in one batched phase.
 struct Batch {
@@ -737,7 +756,7 @@ mos_status residual_batch(mos_engine e, const Batch &B, bool lift) {
                        (const double *)e->x64, (const int32_t *)e->inc, e->Mc64, e->ld_slots);
     hipLaunchKernelGGL(k_bgemm<double>, dim3(e->ldk / 16, hw_sb), dim3(256), 0, st, (const void *const *)e->kr64_tab,
                        e->sb_rom, e->sb_prob, (const double *)e->Mc64, e->Y64, e->ldk, e->ld_slots, 0, hw_sb, 2,
-                       e->ps, 0, (const double *)nullptr, (const double *)nullptr, (const double *)nullptr, B.sel);
+                       (const ProbState *)e->ps, (double *)nullptr, B.sel);
     hipLaunchKernelGGL(k_residual_sel, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
                        (const double *)e->Y64, (const int32_t *)e->inc, (const double *)e->b_raw,
                        (const uint8_t *)e->cmask, (const double *)e->g, e->r64, e->pr64, e->pd, lift ? 1 : 0,
@@ -769,6 +788,8 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
         H.n_blk = P->n_blk;
         H.sb_begin = P->sb_begin;
         H.n_sb = P->n_sb;
+        H.nrb = e->ldk / 16;
+        H.pad = 0;
         MOS_HIP(hipMemcpyAsync(e->pp + P->pid, &H, sizeof(ProbParams), hipMemcpyHostToDevice, st));
         MOS_HIP(hipMemcpyAsync(e->sb_rom + P->sb_begin, P->sb_rom.data(), P->n_sb * 4, hipMemcpyHostToDevice, st));
         MOS_HIP(hipMemcpyAsync(e->perm + P->sb_begin * 16, P->perm.data(), P->perm.size() * 4, hipMemcpyHostToDevice,
@@ -800,6 +821,9 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
     hipLaunchKernelGGL(k_clear_incidence, dim3((unsigned)std::min<int64_t>(ceil_div(n_inc, 256), 4096)), dim3(256),
                        0, st, B.sel, (const int32_t *)e->blk_prob, e->inc, n_inc);
     const int64_t n_slots = (int64_t)hw_sb * 16;
+    hipLaunchKernelGGL(k_zero_padding, dim3(ceil_div(n_slots * e->ldk, 256)), dim3(256), 0, st, B.sel,
+                       (const int32_t *)e->sb_prob, (const int32_t *)e->perm, (uint8_t *)e->Mc,
+                       e->precision == MOS_MIXED ? 4 : 8, e->ld_slots, e->ldk, n_slots);
     hipLaunchKernelGGL(k_incidence_sel, dim3(ceil_div(n_slots * e->S, 256)), dim3(256), 0, st, B.sel,
                        (const int32_t *)e->sb_prob, (const ProbParams *)e->pp, (const int32_t *)e->perm, e->inc,
                        (const int32_t *)e->surf, e->S, n_slots);
@@ -830,17 +854,12 @@ mos_status start_batch(mos_engine e, const Batch &B) {
     MOS_HIP(hipMemcpyAsync(e->sp, e->sp_host, hw_p * sizeof(SweepParams), hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_prob_start_list, dim3(ceil_div(B.list.n, 64)), dim3(64), 0, st, B.list,
                        (const ProbParams *)e->pp, (const SweepParams *)e->sp, e->ps);
-    hipLaunchKernelGGL(k_bstart_sel<T>, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
+    hipLaunchKernelGGL(k_cgstart_sel<T>, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
                        (const SweepParams *)e->sp, (const double *)e->r64, (const T *)V[VDINV],
-                       (const int32_t *)e->inc, V[VX], V[VR], V[VU], V[VZ], V[VQ], V[VS], V[VP], Mc, e->ld_slots);
-    hipLaunchKernelGGL(k_bgemm<T>, dim3(e->ldk / 16, hw_sb), dim3(256), 0, st,
-                       (const void *const *)(e->precision == MOS_MIXED ? e->kr32_tab : e->kr64_tab), e->sb_rom,
-                       e->sb_prob, (const T *)Mc, Y, e->ldk, e->ld_slots, 0, hw_sb, 2, e->ps, 0,
-                       (const double *)nullptr, (const double *)nullptr, (const double *)nullptr, B.sel);
-    hipLaunchKernelGGL(k_bstart2_sel<T>, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
-                       (const T *)Y, (const int32_t *)e->inc, (const uint8_t *)e->cmask, (const T *)V[VDINV],
-                       (const T *)V[VR], (const T *)V[VU], V[VW], V[VM], Mc, e->ld_slots, e->pg, e->pd, e->pr);
+                       (const int32_t *)e->inc, V[VX], V[VR], V[VP], V[VS], Mc, e->ld_slots, e->pg, e->pr);
     MOS_LAUNCH_CHECK();
+    (void)hw_sb;
+    (void)Y;
     return MOS_OK;
 }
 
@@ -910,16 +929,13 @@ mos_status decide(mos_engine e, EngineProblem *P, double res2, double bb2, bool 
     S.scale_out = mixed ? rnorm : 1.0;
     double rtol_in;
     if (mixed) {
-        // The recurrences of pipelined CG drift from the true residual by
-        // ~unit roundoff times the condition number, which in FP32 leaves
-        // ~5e-3 of relative accuracy per sweep on these systems; asking the
-        // inner solve for more only adds iterations.  The last sweep asks
-        // for no more than the remaining factor to the final target.
+        // A fixed reduction per sweep; the last sweep asks for no more than
+        // the remaining factor to the final target.
         rtol_in = std::min(0.5, std::max(INNER_RTOL_F32, P->rtol * bnorm / rnorm));
     } else {
-        // FP64 inner solves aim at the final absolute target; the drift of
-        // the pipelined recurrences (~2e-11 relative here) is made up by a
-        // short second sweep on the true residual.
+        // FP64 inner solves aim at the final absolute target; the true
+        // residual follows the recurrence closely, so one sweep usually ends
+        // the solve (a short second one makes up any drift).
         rtol_in = std::min(0.5, std::max(P->rtol * bnorm / rnorm, 1e-15));
     }
     S.rtol2 = rtol_in * rtol_in;
@@ -971,7 +987,6 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     MOS_TRY(m.alloc_n(dofs, &e->b_raw));
     MOS_TRY(m.alloc_n(dofs, &e->g));
     MOS_TRY(m.alloc_n(dofs, &e->r64));
-    MOS_TRY(m.alloc_n(dofs, &e->q64));
     MOS_TRY(m.alloc_n(dofs, &e->cmask));
     MOS_TRY(m.alloc_n(dofs / 3 * 4, &e->inc));
     MOS_TRY(m.alloc_n(e->cap_blk, &e->blk_prob));
@@ -979,6 +994,7 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     MOS_TRY(m.alloc_n(e->cap_blk, &e->pd));
     MOS_TRY(m.alloc_n(e->cap_blk, &e->pr));
     MOS_TRY(m.alloc_n(e->cap_blk, &e->pr64));
+    MOS_TRY(m.alloc_n((size_t)e->cap_sb * (ldk / 16), &e->pdel));
     MOS_TRY(m.alloc_n(e->cap_sb, &e->sb_rom));
     MOS_TRY(m.alloc_n(e->cap_sb, &e->sb_prob));
     MOS_TRY(m.alloc_n(slots, &e->perm));
@@ -1143,33 +1159,29 @@ void release_problem(mos_engine e, EngineProblem *P) {
 
 template <class T, int KS, bool EXACT>
 void launch_rows_ks(mos_ctx ctx, int spw, hipStream_t st, const void *const *kr_tab, const int32_t *sb_rom,
-                    const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots, int n_sb, int ks, ProbState *ps,
-                    int n_probs, const double *pg, const double *pd, const double *pr) {
-    // One wave per (row block, run of spw slot blocks), 4 per workgroup; then
-    // the blocks whose waves compute each problem's scalars.
+                    const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots, int n_sb, int ks, const ProbState *ps,
+                    double *pdel) {
+    // One wave per (row block, run of spw slot blocks), 4 per workgroup.
     const int nrb = ks / 4;
-    const int task_blocks = (int)ceil_div((int64_t)nrb * ceil_div(n_sb, spw), 4);
-    const dim3 grid((unsigned)(task_blocks + ceil_div(n_probs, 4)));
+    const dim3 grid((unsigned)ceil_div((int64_t)nrb * ceil_div(n_sb, spw), 4));
     launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm_rows<T, KS, EXACT>, grid, dim3(256), 0, st, kr_tab, sb_rom, sb_prob,
-                 Mc, Y, ld_slots, 0, n_sb, spw, 1, task_blocks, ks, ps, n_probs, pg, pd, pr);
+                 Mc, Y, ld_slots, 0, n_sb, spw, 1, ks, ps, pdel);
 }
 
 template <class T>
 mos_status launch_rows(mos_ctx ctx, int ks, int spw, hipStream_t st, const void *const *kr_tab,
                        const int32_t *sb_rom, const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots, int n_sb,
-                       ProbState *ps, int n_probs, const double *pg, const double *pd, const double *pr) {
+                       const ProbState *ps, double *pdel) {
     if (ks == 8)
-        launch_rows_ks<T, 8, true>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps, n_probs,
-                                   pg, pd, pr);
+        launch_rows_ks<T, 8, true>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps, pdel);
     else if (ks == 20)
-        launch_rows_ks<T, 20, true>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps, n_probs,
-                                    pg, pd, pr);
+        launch_rows_ks<T, 20, true>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps, pdel);
     else if (ks == ROWS_MAX_KS)
         launch_rows_ks<T, ROWS_MAX_KS, true>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps,
-                                             n_probs, pg, pd, pr);
+                                             pdel);
     else if (ks < ROWS_MAX_KS)
-        launch_rows_ks<T, ROWS_MAX_KS, false>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks,
-                                              ps, n_probs, pg, pd, pr);
+        launch_rows_ks<T, ROWS_MAX_KS, false>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps,
+                                              pdel);
     else {
         set_error("no rows GEMM for %d k-steps", ks);
         return MOS_EINVAL;
@@ -1179,7 +1191,7 @@ mos_status launch_rows(mos_ctx ctx, int ks, int spw, hipStream_t st, const void 
 }
 
 template <class T>
-mos_status rows_step(mos_engine e, int ks, int hw_sb, int hw_p);
+mos_status rows_step(mos_engine e, int ks, int hw_sb);
 
 // Pick the rows-GEMM work split for `n_sb` active slot blocks; *cand_out is
 // set to the candidate when this launch is a tuning trial (its events are
@@ -1247,7 +1259,7 @@ hipEvent_t tuner_event(GemmTuner &T) {
 // One rows-GEMM launch of the iteration over [0, hw_sb) slot blocks, with
 // the work split from the tuner (timed with events while it is a trial).
 template <class T>
-mos_status rows_step(mos_engine e, int ks, int hw_sb, int hw_p) {
+mos_status rows_step(mos_engine e, int ks, int hw_sb) {
     hipStream_t st = e->ctx->stream;
     int cand = -1;
     const int spw = tuner_pick(e->tuner, hw_sb, &cand);
@@ -1259,7 +1271,7 @@ mos_status rows_step(mos_engine e, int ks, int hw_sb, int hw_p) {
     }
     const void *const *tab = (const void *const *)(sizeof(T) == 4 ? e->kr32_tab : e->kr64_tab);
     MOS_TRY(launch_rows<T>(e->ctx, ks, spw, st, tab, e->sb_rom, e->sb_prob, (const T *)e->Mc, (T *)e->Yi,
-                           e->ld_slots, hw_sb, e->ps, hw_p, e->pg, e->pd, e->pr));
+                           e->ld_slots, hw_sb, (const ProbState *)e->ps, e->pdel));
     if (cand >= 0 && ev0 && ev1) {
         MOS_HIP(hipEventRecord(ev1, st));
         int bucket = 0;
@@ -1313,7 +1325,7 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
     for (EngineProblem *P : e->active) any_iter |= P->state == 1;
     if (any_iter) {
         const int hw_sb = e->sbs.high, hw_blk = e->blk.high, hw_p = e->pids.high;
-        const dim3 g_gemm(e->ldk / 16, hw_sb + ceil_div(hw_p, GEMM_WAVES));
+        const dim3 g_gemm(e->ldk / 16, hw_sb);
         // Cell GEMM variant is fixed per engine; the rows variant picks how
         // many slot blocks each wave streams from the batch size only (its
         // results do not depend on that choice).
@@ -1322,38 +1334,40 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
         const int nrb = e->ldk / 16;
         (void)nrb;
         for (int j = 0; j < chunk; ++j) {
+            // Three launches per iteration: cell GEMM (w = A u, (u, A u)
+            // tile partials), per-problem scalars, vector update.
             if (e->precision == MOS_MIXED) {
                 float *V[NVEC];
                 for (int i = 0; i < NVEC; ++i) V[i] = static_cast<float *>(e->v[i]);
                 if (rows)
-                    MOS_TRY(rows_step<float>(e, ks, hw_sb, hw_p));
+                    MOS_TRY(rows_step<float>(e, ks, hw_sb));
                 else
                     launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm<float>, g_gemm, dim3(256), 0, st,
                                  (const void *const *)e->kr32_tab, (const int32_t *)e->sb_rom,
                                  (const int32_t *)e->sb_prob, (const float *)e->Mc, (float *)e->Yi, e->ldk,
-                                 e->ld_slots, 0, hw_sb, 1, e->ps, hw_p, (const double *)e->pg, (const double *)e->pd,
-                                 (const double *)e->pr, ProbSel{});
-                launch_timed(ctx, MOS_K_PCG_UPDATE, k_bstep<float>, dim3(hw_blk), dim3(DB), 0, st,
+                                 e->ld_slots, 0, hw_sb, 1, (const ProbState *)e->ps, e->pdel, ProbSel{});
+                launch_timed(ctx, MOS_K_PCG_SCALARS, k_cg_scalars, dim3(hw_p), dim3(256), 0, st, e->ps,
+                             (const double *)e->pg, (const double *)e->pr, (const double *)e->pdel);
+                launch_timed(ctx, MOS_K_PCG_UPDATE, k_cgstep<float>, dim3(hw_blk), dim3(DB), 0, st,
                              (const float *)e->Yi, (const int32_t *)e->inc, (const uint8_t *)e->cmask,
-                             (const float *)V[VDINV], V[VX], V[VR], V[VU], V[VW], V[VZ], V[VQ], V[VS], V[VP], V[VM],
-                             (float *)e->Mc, e->ld_slots, (const int32_t *)e->blk_prob, (const ProbState *)e->ps,
-                             e->pg, e->pd, e->pr);
+                             (const float *)V[VDINV], V[VX], V[VR], V[VP], V[VS], (float *)e->Mc, e->ld_slots,
+                             (const int32_t *)e->blk_prob, (const ProbState *)e->ps, e->pg, e->pr);
             } else {
                 double *V[NVEC];
                 for (int i = 0; i < NVEC; ++i) V[i] = static_cast<double *>(e->v[i]);
                 if (rows)
-                    MOS_TRY(rows_step<double>(e, ks, hw_sb, hw_p));
+                    MOS_TRY(rows_step<double>(e, ks, hw_sb));
                 else
                     launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm<double>, g_gemm, dim3(256), 0, st,
                                  (const void *const *)e->kr64_tab, (const int32_t *)e->sb_rom,
                                  (const int32_t *)e->sb_prob, (const double *)e->Mc, (double *)e->Yi, e->ldk,
-                                 e->ld_slots, 0, hw_sb, 1, e->ps, hw_p, (const double *)e->pg, (const double *)e->pd,
-                                 (const double *)e->pr, ProbSel{});
-                launch_timed(ctx, MOS_K_PCG_UPDATE, k_bstep<double>, dim3(hw_blk), dim3(DB), 0, st,
+                                 e->ld_slots, 0, hw_sb, 1, (const ProbState *)e->ps, e->pdel, ProbSel{});
+                launch_timed(ctx, MOS_K_PCG_SCALARS, k_cg_scalars, dim3(hw_p), dim3(256), 0, st, e->ps,
+                             (const double *)e->pg, (const double *)e->pr, (const double *)e->pdel);
+                launch_timed(ctx, MOS_K_PCG_UPDATE, k_cgstep<double>, dim3(hw_blk), dim3(DB), 0, st,
                              (const double *)e->Yi, (const int32_t *)e->inc, (const uint8_t *)e->cmask,
-                             (const double *)V[VDINV], V[VX], V[VR], V[VU], V[VW], V[VZ], V[VQ], V[VS], V[VP], V[VM],
-                             (double *)e->Mc, e->ld_slots, (const int32_t *)e->blk_prob, (const ProbState *)e->ps,
-                             e->pg, e->pd, e->pr);
+                             (const double *)V[VDINV], V[VX], V[VR], V[VP], V[VS], (double *)e->Mc, e->ld_slots,
+                             (const int32_t *)e->blk_prob, (const ProbState *)e->ps, e->pg, e->pr);
             }
         }
         MOS_LAUNCH_CHECK();

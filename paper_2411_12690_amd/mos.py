@@ -25,7 +25,7 @@ EXPORTED = ("mos_ctx_create", "mos_ctx_destroy", "mos_build_cell", "mos_reduce",
             "mos_array_layout", "mos_engine_create", "mos_engine_submit", "mos_engine_progress",
             "mos_engine_result", "mos_engine_option", "mos_engine_stats", "mos_engine_destroy", "mos_timing_start", "mos_timing_stop",
             "mos_cell_free", "mos_rom_free", "mos_sol_free", "mos_last_error")
-MOS_K_CELL_GEMM, MOS_K_ASSEMBLE, MOS_K_PCG_UPDATE, MOS_K_RECON = 1, 2, 3, 4
+MOS_K_CELL_GEMM, MOS_K_PCG_SCALARS, MOS_K_PCG_UPDATE, MOS_K_RECON = 1, 2, 3, 4
 MOS_OPT_CELL_GEMM = 1
 GEMM_TILES, GEMM_ROWS = 1, 2
 MOS_OPT_GEMM_SPLIT = 2
