@@ -1,8 +1,8 @@
 #!/usr/bin/env python3
 """Benchmark of the MORE-Stress hot path on one MI355X.
 
-Default (--mode batch): one step = the global stage of a batch of B
-independent 16x16 TSV arrays (cells 15x15x50 um meshed 16x16x32, cubic face
+Default (--mode batch): one step = the global stage of a batch of B (default
+32) independent 16x16 TSV arrays (cells 15x15x50 um meshed 16x16x32, cubic face
 interpolation, n = 168, dT = -250 K, bottom clamped, FP64), each array drawing
 its via diameter from {4, 5, 6} um with its own seed.  The batch is solved
 together by the engine (mos_engine_*: reduced assembly, lifting, pipelined
@@ -42,16 +42,18 @@ def per_iteration_work(kernel, mos, n, n_cells, n_dofs_pad, n_nodes, mixed):
     if kernel == mos.MOS_K_CELL_GEMM:
         return 2.0 * n * n * n_cells
     if kernel == mos.MOS_K_PCG_UPDATE:
-        # cell products gathered + next vector scattered to the cell layout,
-        # 10 vector reads + 9 vector writes + mask per DoF, incidence per node
-        return 2.0 * n * n_cells * w + n_dofs_pad * (19 * w + 1) + n_nodes * 16
+        # cell products gathered + next u scattered to the cell layout;
+        # r, p, s, x, D^-1 read and x, r, p, s written per DoF, constraint
+        # mask byte; incidence (four int32) per node
+        return 2.0 * n * n_cells * w + n_dofs_pad * (9 * w + 1) + n_nodes * 16
     raise ValueError(kernel)
 
 
 KERNEL_INFO = {  # kernel id -> (name, bound, unit, note)
     1: ("k_bgemm", "mfma", "TFLOP/s", "2 n^2 flops per cell and iteration (K_r GEMM of the PCG matvec)"),
-    3: ("k_bstep", "hbm", "GB/s", "2 n w per cell + (19 w + 1) per DoF + 16 per node and iteration"),
-    4: ("k_brecon", "mfma", "TFLOP/s", "2*6*n_elem*n flops per cell (stress GEMM; the BF16 form issues 3x "
+    2: ("k_cg_scalars", "latency", "us", "per-problem fixed-order reductions and CG step"),
+    3: ("k_cgstep", "hbm", "GB/s", "2 n w per cell + (9 w + 1) per DoF + 16 per node and iteration"),
+    4: ("k_recon", "mfma", "TFLOP/s", "2*6*n_elem*n flops per cell (stress GEMM; the BF16 form issues 3x "
         "these on MFMA for its hi/lo split)"),
 }
 
@@ -165,11 +167,11 @@ def batch_mode(args, mos, torch, np, W):
         step()
     # Kernel totals over one step pick the dominant kernel.
     totals = {}
-    for k in (mos.MOS_K_CELL_GEMM, mos.MOS_K_PCG_UPDATE, mos.MOS_K_RECON):
+    for k in (mos.MOS_K_CELL_GEMM, mos.MOS_K_PCG_SCALARS, mos.MOS_K_PCG_UPDATE, mos.MOS_K_RECON):
         mos.mos_timing_start(ctx, k, 1)
         step()
         totals[k] = mos.mos_timing_stop(ctx)[:2]
-    dominant = max(totals, key=lambda k: totals[k][1])
+    dominant = max((k for k in totals if k != mos.MOS_K_PCG_SCALARS), key=lambda k: totals[k][1])
 
     # Timed region: one launch in TIME_EVERY of the dominant kernel carries
     # dispatch-stamped HIP events on its stream (stamping every launch adds
@@ -322,11 +324,11 @@ def single_mode(args, mos, torch, np, W):
         for _ in range(args.warmup):
             run()
         totals = {}
-        for k in (mos.MOS_K_CELL_GEMM, mos.MOS_K_PCG_UPDATE, mos.MOS_K_RECON):
+        for k in (mos.MOS_K_CELL_GEMM, mos.MOS_K_PCG_SCALARS, mos.MOS_K_PCG_UPDATE, mos.MOS_K_RECON):
             mos.mos_timing_start(ctx, k, 1)
             run()
             totals[k] = mos.mos_timing_stop(ctx)
-        dominant = max(totals, key=lambda k: totals[k][1])
+        dominant = max((k for k in totals if k != mos.MOS_K_PCG_SCALARS), key=lambda k: totals[k][1])
         mos.mos_timing_start(ctx, dominant, TIME_EVERY)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -512,7 +514,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--mode", choices=["batch", "serve", "single", "calib"], default="batch")
     ap.add_argument("--workload", choices=["c3", "c5"], default="c3")
-    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--gemm-split", type=int, default=None,
                     help="fixed slot blocks per wave of the cell GEMM (default: tuned online)")
