@@ -18,13 +18,14 @@ constexpr int MAX_PROBS = 1024;  // problems resident in one engine at a time
 // wave (iteration launches) or by single-thread set-up kernels; read by the
 // batch kernels and, between chunks, by the host.
 struct ProbState {
-    double gamma_prev, alpha_prev;  // (r,u) and step of the last applied iteration
-    double a_cur, b_cur;            // step of the current iteration
+    double hist_gamma[2], hist_alpha[2];  // (r,u) and step of iteration it, in slot it & 1
+    double a_cur, b_cur;            // step of the current iteration (separate scalar launch)
     double rr;                      // ||r||^2 at the last check
     double tol2, rtol2;             // stop threshold and its relative form
     int it, done, active, max_iter; // iterations of this sweep; stop code; iterating; cap
     int blk_begin, blk_end;         // the problem's DoF blocks (partials of (r,u), (r,r))
     int tile_begin, tile_end;       // its cell-GEMM tiles (partials of (u, A u))
+    int start_epoch, fused;         // iteration launch of the sweep's iteration 0; scalars in the update
 };
 
 // Inner PCG vectors (Chronopoulos-Gear form), in the inner precision.
@@ -48,7 +49,7 @@ struct ProbParams {
     int64_t d0, n_dofs, nd_pad, bot_end, top_begin;
     double dT;
     Lattice lat;
-    int32_t blk_begin, n_blk, sb_begin, n_sb, nrb, pad;
+    int32_t blk_begin, n_blk, sb_begin, n_sb, nrb, fused;
 };
 // Parameters of a problem's current refinement sweep (device table by id).
 struct SweepParams {
@@ -126,6 +127,7 @@ struct mos_engine_s {
     void *ub = nullptr;  // BF16 split of a finished problem's cell block (mixed reconstruction)
     mos::ReconJob *jobs = nullptr, *jobs_host = nullptr;  // batched reconstruction table (device, pinned)
     mos::ProbParams *pp = nullptr, *pp_host = nullptr;    // per-problem parameters (device, pinned)
+    int epoch = 0;                                        // PCG iteration launches issued so far
     mos::SweepParams *sp = nullptr, *sp_host = nullptr;   // per-sweep parameters (device, pinned)
     int32_t *surf = nullptr;  // [S][3] surface Lagrange nodes (i, j, k) of a cell, s order
     int S = 0;

@@ -98,23 +98,28 @@ __device__ __forceinline__ bool selected(const ProbSel &S, int p) {
     return p >= 0 && ((S.bits[p >> 5] >> (p & 31)) & 1u);
 }
 
-// Scalars of iteration ps[p].it of one problem, one workgroup per problem
+// Scalars of iteration `it` of one problem, computed by one workgroup
 // (Chronopoulos-Gear form of PCG: one fused reduction per iteration).
 // Fixed-order sums -- each thread a fixed strided subset, then a fixed tree
 // -- of the problem's partials: gamma = (r,u) and rho = (r,r) per DoF block
 // from the last update, delta = (u, A u) per (row block, slot block) tile
 // from this iteration's cell GEMM.  Then the stop decision (1 converged,
-// 2 breakdown, 3 iteration cap) or the step (alpha, beta).
-__global__ __launch_bounds__(256) void k_cg_scalars(ProbState *ps, const double *pg, const double *pr,
-                                                    const double *pdel) {
-    __shared__ double red[3][256];
-    ProbState &S = ps[blockIdx.x];
-    if (!S.active || S.done) return;  // uniform over the workgroup
+// 2 breakdown, 3 iteration cap) or the step (alpha, beta).  Every workgroup
+// that evaluates it for the same problem and iteration gets the same bits.
+struct CgStep {
+    int stop;
+    double alpha, beta, gamma, rr, tol2;
+};
+
+__device__ CgStep cg_scalars_block(const ProbState &S, int it, const double *pg, const double *pr,
+                                   const double *pdel, double (*red)[256]) {
     double g = 0.0, r = 0.0, dl = 0.0;
+#pragma unroll 4
     for (int i = S.blk_begin + threadIdx.x; i < S.blk_end; i += 256) {
         g += pg[i];
         r += pr[i];
     }
+#pragma unroll 4
     for (int i = S.tile_begin + threadIdx.x; i < S.tile_end; i += 256) dl += pdel[i];
     red[0][threadIdx.x] = g;
     red[1][threadIdx.x] = r;
@@ -125,35 +130,59 @@ __global__ __launch_bounds__(256) void k_cg_scalars(ProbState *ps, const double 
             for (int j = 0; j < 3; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + m];
         __syncthreads();
     }
-    if (threadIdx.x != 0) return;
-    const double gamma = red[0][0], rr = red[1][0], delta = red[2][0];
-    const int it = S.it;
-    if (it == 0) S.tol2 = S.rtol2 * rr;
-    int stop = 0;
-    double alpha = 0.0, beta = 0.0;
-    if (rr <= S.tol2) {
-        stop = 1;
+    CgStep o;
+    o.gamma = red[0][0];
+    o.rr = red[1][0];
+    const double delta = red[2][0];
+    o.tol2 = it == 0 ? S.rtol2 * o.rr : S.tol2;
+    o.stop = 0;
+    o.alpha = o.beta = 0.0;
+    if (o.rr <= o.tol2) {
+        o.stop = 1;
     } else if (it >= S.max_iter) {
-        stop = 3;
+        o.stop = 3;
     } else {
         if (it == 0) {
-            alpha = gamma / delta;
+            o.alpha = o.gamma / delta;
         } else {
-            beta = gamma / S.gamma_prev;
-            alpha = gamma / (delta - beta * gamma / S.alpha_prev);
+            const int pv = (it - 1) & 1;
+            o.beta = o.gamma / S.hist_gamma[pv];
+            o.alpha = o.gamma / (delta - o.beta * o.gamma / S.hist_alpha[pv]);
         }
-        if (!(alpha > 0.0) || !isfinite(alpha) || !isfinite(beta)) stop = 2;
+        if (!(o.alpha > 0.0) || !isfinite(o.alpha) || !isfinite(o.beta)) o.stop = 2;
     }
-    S.rr = rr;
-    if (stop) {
-        S.done = stop;
+    return o;
+}
+
+// Publish iteration `it`'s outcome (one writer per problem and iteration).
+// Readers of the same launch only read the other history slot.
+__device__ __forceinline__ void cg_publish(ProbState &S, int it, const CgStep &o) {
+    S.rr = o.rr;
+    if (it == 0) S.tol2 = o.tol2;
+    if (o.stop) {
+        S.done = o.stop;
     } else {
-        S.a_cur = alpha;
-        S.b_cur = beta;
-        S.gamma_prev = gamma;
-        S.alpha_prev = alpha;
+        S.a_cur = o.alpha;
+        S.b_cur = o.beta;
+        S.hist_gamma[it & 1] = o.gamma;
+        S.hist_alpha[it & 1] = o.alpha;
         S.it = it + 1;
     }
+}
+
+// Separate scalar launch for problems too large to reduce in every update
+// workgroup: one workgroup per problem, iteration launch `epoch`.  The
+// per-block partials are double-buffered by iteration parity: iteration it
+// reads slot it & 1 (written by the previous update or the sweep start).
+__global__ __launch_bounds__(256) void k_cg_scalars(ProbState *ps, const double *pg, const double *pr,
+                                                    const double *pdel, int epoch, int cap_blk) {
+    __shared__ double red[3][256];
+    ProbState &S = ps[blockIdx.x];
+    if (!S.active || S.done || S.fused) return;  // uniform over the workgroup
+    const int it = epoch - S.start_epoch;
+    const size_t slot = (size_t)(it & 1) * cap_blk;
+    const CgStep o = cg_scalars_block(S, it, pg + slot, pr + slot, pdel, red);
+    if (threadIdx.x == 0) cg_publish(S, it, o);
 }
 
 // (u, A u) over one 16x16 output tile: the tile's products times the cell
@@ -335,28 +364,49 @@ __global__ void k_prob_stop(ProbState *ps, int p) { ps[p].active = 0; }
 template <class T>
 __global__ __launch_bounds__(256) void k_cgstep(const T *Y, const int32_t *inc, const uint8_t *cmask, const T *dinv,
                                                 T *x, T *r, T *p, T *s, T *Mc, int ld_slots, const int32_t *blk_prob,
-                                                const ProbState *ps, double *pg, double *pr) {
-    __shared__ int go;
+                                                ProbState *ps, double *pg, double *pr, const double *pdel,
+                                                int epoch, int cap_blk) {
+    __shared__ int go, it_sh;
     __shared__ double step[2];
+    __shared__ double red[3][256];
     const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x;
     // Only the incidence is requested before the gate resolves: blocks of
     // problems that have stopped (converged, or between refinement sweeps)
     // must not spend bandwidth on their operands.
     const int4 iv = incidence(inc, d);
     const int ci = (int)(d % 3);
+    const int pb = blk_prob[blockIdx.x];
     if (threadIdx.x == 0) {
-        const int pb = blk_prob[blockIdx.x];
         int g = 0;
         if (pb >= 0) {
             const ProbState &S = ps[pb];
-            g = S.active && !S.done;
+            g = S.active && !S.done ? (S.fused ? 2 : 1) : 0;
             step[0] = S.a_cur;
             step[1] = S.b_cur;
+            it_sh = epoch - S.start_epoch;
         }
         go = g;
     }
     __syncthreads();
     if (!go) return;
+    // Per-block partials double-buffered by iteration parity: this
+    // iteration reads slot it & 1 and writes slot (it + 1) & 1, so no block
+    // overwrites a partial another block of the launch may still read.
+    const int it = it_sh;
+    const size_t rd_slot = (size_t)(it & 1) * cap_blk, wr_slot = (size_t)((it + 1) & 1) * cap_blk;
+    if (go == 2) {
+        // Small problem: every workgroup reduces its partials itself (same
+        // bits in each); the problem's first workgroup publishes the state.
+        ProbState &S = ps[pb];
+        const CgStep o = cg_scalars_block(S, it, pg + rd_slot, pr + rd_slot, pdel, red);
+        if (threadIdx.x == 0 && (int)blockIdx.x == S.blk_begin) cg_publish(S, it, o);
+        if (o.stop) return;
+        if (threadIdx.x == 0) {
+            step[0] = o.alpha;
+            step[1] = o.beta;
+        }
+        __syncthreads();
+    }
     const T a = (T)step[0], b = (T)step[1];
     const T dv = dinv[d], rd = r[d], pd0 = p[d], sd = s[d], xd = x[d];
     const T sum = cell_sum(Y, iv, ci, ld_slots);
@@ -374,8 +424,8 @@ __global__ __launch_bounds__(256) void k_cgstep(const T *Y, const int32_t *inc, 
     double g = (double)rv * (double)un, r2 = (double)rv * (double)rv, z = 0.0;
     block_sum3(g, r2, z);
     if (threadIdx.x == 0) {
-        pg[blockIdx.x] = g;
-        pr[blockIdx.x] = r2;
+        pg[wr_slot + blockIdx.x] = g;
+        pr[wr_slot + blockIdx.x] = r2;
     }
 }
 
@@ -511,12 +561,15 @@ __global__ void k_reduce_list(PidList L, const ProbParams *pp, const double *par
 }
 
 // Sweep start, per listed problem: fresh scalar state.
-__global__ void k_prob_start_list(PidList L, const ProbParams *pp, const SweepParams *sp, ProbState *ps) {
+__global__ void k_prob_start_list(PidList L, const ProbParams *pp, const SweepParams *sp, ProbState *ps, int epoch) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= L.n) return;
     const int p = L.pid[i];
     ProbState &S = ps[p];
-    S.gamma_prev = S.alpha_prev = S.a_cur = S.b_cur = S.rr = S.tol2 = 0.0;
+    S.hist_gamma[0] = S.hist_gamma[1] = S.hist_alpha[0] = S.hist_alpha[1] = 0.0;
+    S.a_cur = S.b_cur = S.rr = S.tol2 = 0.0;
+    S.start_epoch = epoch;
+    S.fused = pp[p].fused;
     S.rtol2 = sp[p].rtol2;
     S.it = 0;
     S.done = 0;
@@ -735,6 +788,10 @@ namespace {
 // FP64 residual each).
 constexpr double INNER_RTOL_F32 = 1e-2;
 
+// Problems with at most this many partials (DoF blocks + GEMM tiles) have
+// every update workgroup reduce them itself instead of a separate launch.
+constexpr int64_t CG_FUSE_MAX = 8192;
+
 // Problems taking part in one batched phase.
 struct Batch {
     ProbSel sel{};
@@ -789,7 +846,8 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
         H.sb_begin = P->sb_begin;
         H.n_sb = P->n_sb;
         H.nrb = e->ldk / 16;
-        H.pad = 0;
+        // Small problems reduce their scalars inside every update workgroup.
+        H.fused = (int64_t)P->n_blk + (int64_t)P->n_sb * H.nrb <= CG_FUSE_MAX ? 1 : 0;
         MOS_HIP(hipMemcpyAsync(e->pp + P->pid, &H, sizeof(ProbParams), hipMemcpyHostToDevice, st));
         MOS_HIP(hipMemcpyAsync(e->sb_rom + P->sb_begin, P->sb_rom.data(), P->n_sb * 4, hipMemcpyHostToDevice, st));
         MOS_HIP(hipMemcpyAsync(e->perm + P->sb_begin * 16, P->perm.data(), P->perm.size() * 4, hipMemcpyHostToDevice,
@@ -853,7 +911,7 @@ mos_status start_batch(mos_engine e, const Batch &B) {
     T *Mc = static_cast<T *>(e->Mc), *Y = static_cast<T *>(e->Yi);
     MOS_HIP(hipMemcpyAsync(e->sp, e->sp_host, hw_p * sizeof(SweepParams), hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_prob_start_list, dim3(ceil_div(B.list.n, 64)), dim3(64), 0, st, B.list,
-                       (const ProbParams *)e->pp, (const SweepParams *)e->sp, e->ps);
+                       (const ProbParams *)e->pp, (const SweepParams *)e->sp, e->ps, e->epoch);
     hipLaunchKernelGGL(k_cgstart_sel<T>, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
                        (const SweepParams *)e->sp, (const double *)e->r64, (const T *)V[VDINV],
                        (const int32_t *)e->inc, V[VX], V[VR], V[VP], V[VS], Mc, e->ld_slots, e->pg, e->pr);
@@ -990,9 +1048,9 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     MOS_TRY(m.alloc_n(dofs, &e->cmask));
     MOS_TRY(m.alloc_n(dofs / 3 * 4, &e->inc));
     MOS_TRY(m.alloc_n(e->cap_blk, &e->blk_prob));
-    MOS_TRY(m.alloc_n(e->cap_blk, &e->pg));
+    MOS_TRY(m.alloc_n(2 * (size_t)e->cap_blk, &e->pg));  // two parity slots
     MOS_TRY(m.alloc_n(e->cap_blk, &e->pd));
-    MOS_TRY(m.alloc_n(e->cap_blk, &e->pr));
+    MOS_TRY(m.alloc_n(2 * (size_t)e->cap_blk, &e->pr));
     MOS_TRY(m.alloc_n(e->cap_blk, &e->pr64));
     MOS_TRY(m.alloc_n((size_t)e->cap_sb * (ldk / 16), &e->pdel));
     MOS_TRY(m.alloc_n(e->cap_sb, &e->sb_rom));
@@ -1333,9 +1391,13 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
         const bool rows = e->gemm_rows && ks <= ROWS_MAX_KS;
         const int nrb = e->ldk / 16;
         (void)nrb;
+        bool any_large = false;
+        for (EngineProblem *P : e->active)
+            if (P->state == 1 && !e->pp_host[P->pid].fused) any_large = true;
         for (int j = 0; j < chunk; ++j) {
-            // Three launches per iteration: cell GEMM (w = A u, (u, A u)
-            // tile partials), per-problem scalars, vector update.
+            // Per iteration: cell GEMM (w = A u, (u, A u) tile partials),
+            // the scalar launch when a large problem iterates, and the
+            // vector update (which reduces small problems' scalars itself).
             if (e->precision == MOS_MIXED) {
                 float *V[NVEC];
                 for (int i = 0; i < NVEC; ++i) V[i] = static_cast<float *>(e->v[i]);
@@ -1346,12 +1408,15 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
                                  (const void *const *)e->kr32_tab, (const int32_t *)e->sb_rom,
                                  (const int32_t *)e->sb_prob, (const float *)e->Mc, (float *)e->Yi, e->ldk,
                                  e->ld_slots, 0, hw_sb, 1, (const ProbState *)e->ps, e->pdel, ProbSel{});
-                launch_timed(ctx, MOS_K_PCG_SCALARS, k_cg_scalars, dim3(hw_p), dim3(256), 0, st, e->ps,
-                             (const double *)e->pg, (const double *)e->pr, (const double *)e->pdel);
+                if (any_large)
+                    launch_timed(ctx, MOS_K_PCG_SCALARS, k_cg_scalars, dim3(hw_p), dim3(256), 0, st, e->ps,
+                                 (const double *)e->pg, (const double *)e->pr, (const double *)e->pdel, e->epoch,
+                                 e->cap_blk);
                 launch_timed(ctx, MOS_K_PCG_UPDATE, k_cgstep<float>, dim3(hw_blk), dim3(DB), 0, st,
                              (const float *)e->Yi, (const int32_t *)e->inc, (const uint8_t *)e->cmask,
                              (const float *)V[VDINV], V[VX], V[VR], V[VP], V[VS], (float *)e->Mc, e->ld_slots,
-                             (const int32_t *)e->blk_prob, (const ProbState *)e->ps, e->pg, e->pr);
+                             (const int32_t *)e->blk_prob, e->ps, e->pg, e->pr, (const double *)e->pdel, e->epoch,
+                             e->cap_blk);
             } else {
                 double *V[NVEC];
                 for (int i = 0; i < NVEC; ++i) V[i] = static_cast<double *>(e->v[i]);
@@ -1362,13 +1427,17 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
                                  (const void *const *)e->kr64_tab, (const int32_t *)e->sb_rom,
                                  (const int32_t *)e->sb_prob, (const double *)e->Mc, (double *)e->Yi, e->ldk,
                                  e->ld_slots, 0, hw_sb, 1, (const ProbState *)e->ps, e->pdel, ProbSel{});
-                launch_timed(ctx, MOS_K_PCG_SCALARS, k_cg_scalars, dim3(hw_p), dim3(256), 0, st, e->ps,
-                             (const double *)e->pg, (const double *)e->pr, (const double *)e->pdel);
+                if (any_large)
+                    launch_timed(ctx, MOS_K_PCG_SCALARS, k_cg_scalars, dim3(hw_p), dim3(256), 0, st, e->ps,
+                                 (const double *)e->pg, (const double *)e->pr, (const double *)e->pdel, e->epoch,
+                                 e->cap_blk);
                 launch_timed(ctx, MOS_K_PCG_UPDATE, k_cgstep<double>, dim3(hw_blk), dim3(DB), 0, st,
                              (const double *)e->Yi, (const int32_t *)e->inc, (const uint8_t *)e->cmask,
                              (const double *)V[VDINV], V[VX], V[VR], V[VP], V[VS], (double *)e->Mc, e->ld_slots,
-                             (const int32_t *)e->blk_prob, (const ProbState *)e->ps, e->pg, e->pr);
+                             (const int32_t *)e->blk_prob, e->ps, e->pg, e->pr, (const double *)e->pdel, e->epoch,
+                             e->cap_blk);
             }
+            ++e->epoch;
         }
         MOS_LAUNCH_CHECK();
         // 3. Problems whose inner solve stopped: fold in the correction, FP64 residual.
