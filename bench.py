@@ -131,7 +131,7 @@ def batch_mode(args, mos, torch, np, W):
     n_dofs = 3 * n_nodes
     n_dofs_pad = -(-n_dofs // 768) * 768
     eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=int(B * (n_dofs_pad * 140 + n_cells * 16 * 176 * 34)
-                                                             * 1.3) + (64 << 20))
+                                                             * 1.3) + (64 << 20), gemm=args.cell_gemm)
     if args.gemm_split is not None:
         eng.option(mos.MOS_OPT_GEMM_SPLIT, args.gemm_split)
     vms = [torch.empty((n_cells, n_elem), dtype=torch.float32 if mixed else torch.float64, device="cuda")
@@ -256,6 +256,7 @@ def batch_mode(args, mos, torch, np, W):
                    "gemm_split": args.gemm_split if args.gemm_split is not None else "tuned"},
         "p50_ms": round(float(np.percentile(lat, 50)), 4),
         "p99_ms": round(float(np.percentile(lat, 99)), 4),
+        "step_ms": [round(ev[s].elapsed_time(ev[s + 1]), 3) for s in range(args.steps)],
         "latency_is": "per array, submission to completion of solve + reconstruction",
         "single_array_ms": round(float(np.median(single)), 4),
         "pcg_iters_mean": round(float(np.mean(iters)), 1),
@@ -310,7 +311,7 @@ def single_mode(args, mos, torch, np, W):
         mixed = prec == "mixed"
         w = 4 if mixed else 8
         budget = int((n_dofs_pad * 160 + n_cells * 16 * 176 * (2 * w + 24)) * 1.3) + (256 << 20)
-        eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=budget)
+        eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=budget, gemm=args.cell_gemm)
         if args.gemm_split is not None:
             eng.option(mos.MOS_OPT_GEMM_SPLIT, args.gemm_split)
         vm = torch.empty((n_cells, n_elem), dtype=torch.float32 if mixed else torch.float64, device="cuda")
@@ -518,6 +519,10 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--gemm-split", type=int, default=None,
                     help="fixed slot blocks per wave of the cell GEMM (default: tuned online)")
+    ap.add_argument("--cell-gemm", type=int, choices=[0, 1, 2, 3], default=None,
+                    help="cell GEMM variant (0 rows with the operand path tuned, 1 tiles, 2 K_r-stationary rows, "
+                         "3 rows with the operand tile in LDS; "
+                         "default: the engine's)")
     ap.add_argument("--chunk", type=int, default=16)
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--budget-gb", type=float, default=32.0)

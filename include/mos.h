@@ -223,17 +223,22 @@ mos_status mos_engine_result(mos_engine e, int64_t ticket, int32_t *status, doub
  * PCG matvec (the per-type product K_r * u_cell of eq. 20 over all cells):
  * 1 = 16x16 output tiles with the contraction split over four waves (any
  * basis size); 2 = K_r-stationary rows: each wave holds 16 rows of K_r in
- * registers and streams consecutive 16-cell blocks (basis sizes up to 176,
- * i.e. interpolation up to 4 nodes per axis).  The default is 2 where it
- * applies, else 1; asking for 2 elsewhere runs 1.  Set options before the first submission; results can
- * differ in the last bits between variants, never between batch
- * compositions. */
-/* MOS_OPT_GEMM_SPLIT sets how many consecutive 16-cell blocks one wave of
- * the K_r-stationary GEMM streams: 0 (default) lets the engine tune it online
- * per batch size (each candidate in {1, 2, 4, 8, 16, 32} is timed three times
- * with stream events, the fastest kept); 1 <= k <= 64 fixes it.  It only
- * decides which wave computes which output tile, so results do not depend
- * on it; it may be changed at any time. */
+ * registers and streams consecutive 16-cell blocks of the operand from
+ * global memory; 3 = the same chains, with each 16-cell operand tile read
+ * once per workgroup (one wave per row block of K_r) and staged in LDS.
+ * 2 and 3 apply to basis sizes up to 176 (interpolation up to 4 nodes per
+ * axis); elsewhere they run 1.  0 (the default) = the K_r-stationary rows
+ * where they apply, with the engine choosing between 2 and 3 online per
+ * batch size, else 1.  2, 3 and 0 give the same bits; 1 can differ from
+ * them in the last bits.  Set it before the first submission; results never
+ * depend on the batch composition. */
+/* MOS_OPT_GEMM_SPLIT sets how many consecutive 16-cell blocks one wave
+ * (variant 2) or one workgroup (variant 3) of the K_r-stationary GEMM
+ * streams: 0 (default) lets the engine tune it online per batch size (each
+ * candidate in {1, 2, 4, 8, 16, 32}, for each operand path allowed, is timed
+ * three times with stream events and the fastest kept); 1 <= k <= 64 fixes
+ * it.  It only decides which wave computes which output tile, so results do
+ * not depend on it; it may be changed at any time (tuning starts over). */
 enum { MOS_OPT_CELL_GEMM = 1, MOS_OPT_GEMM_SPLIT = 2 };
 mos_status mos_engine_option(mos_engine e, int option, int64_t value);
 

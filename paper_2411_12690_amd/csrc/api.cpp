@@ -569,16 +569,19 @@ mos_status mos_engine_option(mos_engine e, int option, int64_t value) {
         set_error("invalid engine");
         return MOS_EINVAL;
     }
-    if (option == MOS_OPT_CELL_GEMM && (value == 1 || value == 2)) {
+    if (option == MOS_OPT_CELL_GEMM && value >= 0 && value <= 3) {
         if (!e->active.empty() || !e->queue.empty()) {
             set_error("engine options must be set before the first submission");
             return MOS_EBUSY;
         }
-        e->gemm_rows = value == 2;
+        e->gemm_rows = value != 1 && e->ldk / 4 <= mos::ROWS_MAX_KS;
+        e->gemm_paths = value == 2 ? 1 : value == 3 ? 2 : 3;
+        e->tuner.configure(e->gemm_paths, e->gemm_split);
         return MOS_OK;
     }
     if (option == MOS_OPT_GEMM_SPLIT && value >= 0 && value <= 64) {
-        e->tuner.fixed = (int)value;
+        e->gemm_split = (int)value;
+        e->tuner.configure(e->gemm_paths, e->gemm_split);
         return MOS_OK;
     }
     set_error("unknown option %d or value %lld", option, (long long)value);

@@ -68,15 +68,28 @@ constexpr int ROWS_MAX_KS = 44;
 // REPS times with stream events around its launch; the fastest (minimum
 // time) is then used for that bucket for the life of the engine.
 struct GemmTuner {
-    static constexpr int N_CAND = 6;
-    static constexpr int SPW[N_CAND] = {1, 2, 4, 8, 16, 32};
+    // A candidate is an operand path of the K_r-stationary GEMM (0: operands
+    // streamed per wave from global memory, 1: operand tile staged in LDS
+    // per workgroup) and a work split (slot blocks per wave or workgroup).
+    // All candidates compute the same MFMA chains, so the choice never
+    // changes results.
+    static constexpr int N_SPW = 6;
+    static constexpr int SPW[N_SPW] = {1, 2, 4, 8, 16, 32};
+    static constexpr int MAX_CAND = 2 * N_SPW;
     static constexpr int REPS = 3;
+    int n_cand = 0;
+    int cand_path[MAX_CAND] = {}, cand_spw[MAX_CAND] = {};
     struct Bucket {
-        float best[N_CAND] = {1e30f, 1e30f, 1e30f, 1e30f, 1e30f, 1e30f};
-        int runs[N_CAND] = {0, 0, 0, 0, 0, 0};
+        float best[MAX_CAND];
+        int runs[MAX_CAND];
         int chosen = 0;  // 0 while tuning, else 1 + the chosen candidate
+        Bucket() {
+            for (int c = 0; c < MAX_CAND; ++c) {
+                best[c] = 1e30f;
+                runs[c] = 0;
+            }
+        }
     };
-    int fixed = 0;       // > 0: no tuning, always this split
     std::map<int, Bucket> buckets;
     struct Pending {
         int bucket, cand;
@@ -84,6 +97,9 @@ struct GemmTuner {
     };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> spare;
+    // Candidates from the allowed operand paths (bit 0 global, bit 1 LDS)
+    // and a fixed split (> 0) or the tuned set; tuning starts over.
+    void configure(int paths, int fixed_spw);
 };
 
 // First-fit allocator of block ranges (host side).
@@ -105,7 +121,9 @@ struct mos_engine_s {
     int ldk = 0, n = 0, n_elem = 0, n_eblk = 0;
     int cap_blk = 0, cap_sb = 0, ld_slots = 0;
     bool gemm_rows = false;                   // cell GEMM variant (fixed per engine)
-    mos::GemmTuner tuner;                     // work split of the rows variant
+    int gemm_paths = 3;                       // operand paths of the rows variant open to the tuner
+    int gemm_split = 0;                       // fixed work split (0: tuned)
+    mos::GemmTuner tuner;                     // operand path and work split of the rows variant
     mos::DeviceArena mem;
     // device arrays
     void *v[mos::NVEC] = {};                  // inner vectors (double or float)
@@ -119,7 +137,14 @@ struct mos_engine_s {
     double *pg = nullptr, *pd = nullptr, *pr = nullptr, *pr64 = nullptr;  // [cap_blk]
     int32_t *sb_rom = nullptr, *sb_prob = nullptr;  // [cap_sb]
     int32_t *perm = nullptr;                  // [ld_slots]
+    // Pinned host mirrors of sb_rom and perm: set-up writes a problem's
+    // tables here and copies one span per batch; release writes -1 back.
+    // mirror_ev marks the last span copy, which must complete before the
+    // host changes the mirrors again.
+    int32_t *sb_rom_host = nullptr, *perm_host = nullptr;
+    hipEvent_t mirror_ev = nullptr;
     mos::ProbState *ps = nullptr;             // [MAX_PROBS]
+    mos::ProbState *ps_host = nullptr;        // pinned: states read back at the end of a chunk
     double *res2 = nullptr, *bb2 = nullptr;   // [MAX_PROBS]
     double *host_scratch = nullptr;           // pinned: a few doubles read back from the device
     void **kr64_tab = nullptr, **kr32_tab = nullptr;

@@ -100,8 +100,8 @@ __device__ __forceinline__ bool selected(const ProbSel &S, int p) {
 
 // Scalars of iteration `it` of one problem, computed by one workgroup
 // (Chronopoulos-Gear form of PCG: one fused reduction per iteration).
-// Fixed-order sums -- each thread a fixed strided subset, then a fixed tree
-// -- of the problem's partials: gamma = (r,u) and rho = (r,r) per DoF block
+// Fixed-order sums -- each thread a fixed strided subset, then a fixed
+// butterfly per wave and the waves in order -- of the problem's partials: gamma = (r,u) and rho = (r,r) per DoF block
 // from the last update, delta = (u, A u) per (row block, slot block) tile
 // from this iteration's cell GEMM.  Then the stop decision (1 converged,
 // 2 breakdown, 3 iteration cap) or the step (alpha, beta).  Every workgroup
@@ -264,15 +264,30 @@ __global__ __launch_bounds__(256) void k_bgemm(const void *const *kr_tab, const 
     }
 }
 
-// K_r-stationary variant: one wave per (16-row block of K_r, run
-// of `spw` consecutive slot blocks).  The wave keeps its 16 rows of K_r (KS
-// k-steps of 4) in registers, reloading them only when the cell type
-// changes, and for each slot block issues all KS operand loads before its
-// chain of KS MFMAs.  Each 16x16 output is one MFMA chain in k order, so
-// results do not depend on spw.  With pdel, each tile's (u, A u) partial
-// goes to pdel[slot block * row blocks + row block].  (Staging a row block of K_r in LDS for a whole
-// workgroup was measured slower at every batch size: the extra barrier and
-// serial staging cost more than the occupancy it frees.)
+// (u, A u) over one 16x16 output tile from operand values already loaded
+// (t[q] = the cell operand at output position q of the lane).
+template <class T, class V4>
+__device__ __forceinline__ double tile_dot_vals(const V4 &acc, const T (&t)[4]) {
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v += (double)acc[q] * (double)t[q];
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+// K_r-stationary variant: one wave per (16-row block of K_r, run of `spw`
+// consecutive slot blocks).  The wave keeps its 16 rows of K_r (KS k-steps
+// of 4) in registers, reloading them only when the cell type changes.  In
+// FP64 the slot blocks of the run are software-pipelined: while the chain of
+// KS MFMAs of one slot block runs, each k-step's operand register is
+// refilled with the next live slot block's value right after its MFMA has
+// read it, so the next block's loads are in flight during this block's
+// arithmetic.  Each
+// 16x16 output is one MFMA chain in k order, so results do not depend on
+// spw.  With pdel, each tile's (u, A u) partial goes to
+// pdel[slot block * row blocks + row block].  (Staging a row block of K_r
+// in LDS for a whole workgroup was measured slower at every batch size: the
+// extra barrier and serial staging cost more than the occupancy it frees.)
 template <class T, int KS, bool EXACT>
 __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, const int32_t *sb_rom,
                                                     const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots,
@@ -283,6 +298,11 @@ __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, c
     // them (ldk = 4 ks), and steps past ks are neither loaded nor issued.
     // EXACT instances (ks == KS) keep every operand offset an immediate.
     if (EXACT) ks = KS;
+    // FP64 pipelines the slot blocks and requests the epilogue operands
+    // ahead of the chain.  FP32 (twice the MFMA rate, four waves per SIMD)
+    // was measured faster issuing each block's loads after the previous
+    // chain, as a plain loop.
+    constexpr bool PIPELINE = sizeof(T) == 8, PREFETCH_T = PIPELINE;
     const int ldk = 4 * ks;
     const int nrb = ldk / 16;
     const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
@@ -291,41 +311,197 @@ __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, c
     const int s_begin = run * spw;
     if (s_begin >= n_sb) return;
     const int s_end = min(s_begin + spw, n_sb);
+    // First slot block at or after sl that is in use and whose problem
+    // iterates (s_end if none).
+    auto next_live = [&](int sl) {
+        for (; sl < s_end; ++sl) {
+            const int sb = sb_base + sl;
+            if (sb_rom[sb] < 0) continue;
+            if (gate) {
+                const ProbState &S = ps[sb_prob[sb]];
+                if (!S.active || S.done) continue;
+            }
+            break;
+        }
+        return sl;
+    };
+    int sl = next_live(s_begin);
+    if (sl >= s_end) return;
     // Per-type K_r bases up front, so a slot block's operand loads wait on
     // its type only, not on a second pointer load.
     const T *kr[MAX_TYPES];
 #pragma unroll
     for (int t = 0; t < MAX_TYPES; ++t) kr[t] = static_cast<const T *>(kr_tab[t]);
+    const T *lane_b = Mc + (size_t)(lane / 16) * ld_slots + lane % 16;
     T a[KS], b[KS];
-    int cur = -1;
-    for (int sl = s_begin; sl < s_end; ++sl) {
-        const int sb = sb_base + sl;
-        const int rom = sb_rom[sb];
-        if (rom < 0) continue;
-        if (gate) {
-            const ProbState &S = ps[sb_prob[sb]];
-            if (!S.active || S.done) continue;
-        }
-        const T *bp = Mc + (size_t)(lane / 16) * ld_slots + sb * 16 + lane % 16;
+    {
+        const T *bp = lane_b + (size_t)(sb_base + sl) * 16;
 #pragma unroll
         for (int k = 0; k < KS; ++k) b[k] = k < ks ? bp[(size_t)(4 * k) * ld_slots] : T(0);
+    }
+    int cur = -1;
+    while (sl < s_end) {
+        const int sb = sb_base + sl;
+        const int rom = sb_rom[sb];
+        const int col = sb * 16 + lane % 16;
+        // The epilogue's operand values, requested before this block's
+        // chain (and before the next block's loads) so they are not waited
+        // on behind them.
+        T t[4] = {T(0), T(0), T(0), T(0)};
+        if (PREFETCH_T && pdel) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) t[q] = Mc[(size_t)(rb * 16 + Mfma<T>::row(lane, q)) * ld_slots + col];
+        }
         if (rom != cur) {
             const T *ap = kr[rom] + (size_t)(lane / 16) * ldk + rb * 16 + lane % 16;
 #pragma unroll
             for (int k = 0; k < KS; ++k) a[k] = k < ks ? ap[(size_t)(4 * k) * ldk] : T(0);
             cur = rom;
         }
+        const int nx = next_live(sl + 1);
+        v4 acc = {0, 0, 0, 0};
+        if (PIPELINE && nx < s_end) {
+            const T *bn = lane_b + (size_t)(sb_base + nx) * 16;
+#pragma unroll
+            for (int k = 0; k < KS; ++k)
+                if (k < ks) {
+                    acc = Mfma<T>::op(a[k], b[k], acc);
+                    b[k] = bn[(size_t)(4 * k) * ld_slots];
+                }
+        } else {
+#pragma unroll
+            for (int k = 0; k < KS; ++k)
+                if (k < ks) acc = Mfma<T>::op(a[k], b[k], acc);
+            if (!PIPELINE && nx < s_end) {
+                const T *bn = lane_b + (size_t)(sb_base + nx) * 16;
+#pragma unroll
+                for (int k = 0; k < KS; ++k) b[k] = k < ks ? bn[(size_t)(4 * k) * ld_slots] : T(0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Y[(size_t)(rb * 16 + Mfma<T>::row(lane, q)) * ld_slots + col] = acc[q];
+        if (pdel) {
+            const double v = PREFETCH_T ? tile_dot_vals<T>(acc, t) : tile_dot<T>(acc, Mc, ld_slots, rb, col, lane);
+            if (lane == 0) pdel[(size_t)sb * nrb + rb] = v;
+        }
+        sl = nx;
+    }
+}
+
+// Operand-tile-stationary variant: one workgroup per run of `spw`
+// consecutive slot blocks, one wave per 16-row block of K_r (64 nrb
+// threads).  Each live slot block's operand tile (ldk rows x 16 cells) is
+// read from HBM once per workgroup -- one 16-byte chunk or two per thread --
+// and staged in LDS, double-buffered so the next tile's loads are in flight
+// during this tile's MFMA chains; every row block reads it from there, and
+// each wave keeps its K_r rows in registers (reloaded when the cell type
+// changes).  The chains are the K_r-stationary variant's, in the same order,
+// and the tile partials are the same sums, so the two give the same bits.
+template <class T>
+struct Chunk16;
+template <>
+struct Chunk16<double> {
+    typedef double v __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Chunk16<float> {
+    typedef float v __attribute__((ext_vector_type(4)));
+};
+
+template <class T, int KS, bool EXACT>
+__global__ __launch_bounds__(704) void k_bgemm_wg(const void *const *kr_tab, const int32_t *sb_rom,
+                                                  const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots,
+                                                  int sb_base, int n_sb, int spw, int gate, int ks,
+                                                  const ProbState *ps, double *pdel) {
+    typedef typename Mfma<T>::v4 v4;
+    typedef typename Chunk16<T>::v c16;
+    constexpr int EPC = 16 / sizeof(T);  // elements per 16-byte chunk
+    constexpr int CPR = 16 / EPC;        // chunks per tile row of 16 cells
+    constexpr int CPT = 4 / EPC;         // chunks per thread: ldk CPR chunks over 64 nrb = 16 ks threads
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T *tiles = reinterpret_cast<T *>(lds_raw);  // [2][ldk][16]
+    if (EXACT) ks = KS;
+    const int ldk = 4 * ks;
+    const int nrb = ks / 4;
+    const int nthr = 64 * nrb;
+    const int tid = threadIdx.x, lane = tid % 64, rb = tid / 64;
+    const int s_begin = (int)blockIdx.x * spw;
+    if (s_begin >= n_sb) return;
+    const int s_end = min(s_begin + spw, n_sb);
+    // First slot block at or after sl that is in use and whose problem
+    // iterates (s_end if none); the same for every wave of the workgroup.
+    auto next_live = [&](int sl) {
+        for (; sl < s_end; ++sl) {
+            const int sb = sb_base + sl;
+            if (sb_rom[sb] < 0) continue;
+            if (gate) {
+                const ProbState &S = ps[sb_prob[sb]];
+                if (!S.active || S.done) continue;
+            }
+            break;
+        }
+        return sl;
+    };
+    int sl = next_live(s_begin);
+    if (sl >= s_end) return;
+    // Tile chunk c of this thread: row c / CPR, cells (c % CPR) * EPC.
+    c16 stage[CPT];
+    auto fetch = [&](int slot_block) {
+        const T *src = Mc + (size_t)slot_block * 16;
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) {
+            const int c = tid + i * nthr;
+            stage[i] = *reinterpret_cast<const c16 *>(src + (size_t)(c / CPR) * ld_slots + (c % CPR) * EPC);
+        }
+    };
+    auto put = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < CPT; ++i) {
+            const int c = tid + i * nthr;
+            *reinterpret_cast<c16 *>(tiles + ((size_t)buf * ldk + c / CPR) * 16 + (c % CPR) * EPC) = stage[i];
+        }
+    };
+    const T *kr[MAX_TYPES];
+#pragma unroll
+    for (int t = 0; t < MAX_TYPES; ++t) kr[t] = static_cast<const T *>(kr_tab[t]);
+    T a[KS];
+    int cur = -1;
+    fetch(sb_base + sl);
+    put(0);
+    __syncthreads();
+    int buf = 0;
+    while (sl < s_end) {
+        const int sb = sb_base + sl;
+        const int rom = sb_rom[sb];
+        if (rom != cur) {
+            const T *ap = kr[rom] + (size_t)(lane / 16) * ldk + rb * 16 + lane % 16;
+#pragma unroll
+            for (int k = 0; k < KS; ++k) a[k] = k < ks ? ap[(size_t)(4 * k) * ldk] : T(0);
+            cur = rom;
+        }
+        const int nx = next_live(sl + 1);
+        if (nx < s_end) fetch(sb_base + nx);
+        const T *tb = tiles + (size_t)buf * ldk * 16;
         v4 acc = {0, 0, 0, 0};
 #pragma unroll
         for (int k = 0; k < KS; ++k)
-            if (k < ks) acc = Mfma<T>::op(a[k], b[k], acc);
+            if (k < ks) acc = Mfma<T>::op(a[k], tb[(4 * k + lane / 16) * 16 + lane % 16], acc);
         const int col = sb * 16 + lane % 16;
 #pragma unroll
         for (int q = 0; q < 4; ++q) Y[(size_t)(rb * 16 + Mfma<T>::row(lane, q)) * ld_slots + col] = acc[q];
         if (pdel) {
-            const double t = tile_dot<T>(acc, Mc, ld_slots, rb, col, lane);
-            if (lane == 0) pdel[(size_t)sb * nrb + rb] = t;
+            T t[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) t[q] = tb[(rb * 16 + Mfma<T>::row(lane, q)) * 16 + lane % 16];
+            const double v = tile_dot_vals<T>(acc, t);
+            if (lane == 0) pdel[(size_t)sb * nrb + rb] = v;
         }
+        // The other buffer was last read before the previous barrier; this
+        // one is not written again before the next barrier.
+        if (nx < s_end) put(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+        sl = nx;
     }
 }
 
@@ -353,7 +529,20 @@ __device__ __forceinline__ void cell_scatter(T *Mc, int4 iv, int ci, int ld_slot
         if (e4[e] >= 0) Mc[(size_t)(3 * (e4[e] & MAX_SURF) + ci) * ld_slots + (e4[e] >> INC_SHIFT)] = v;
 }
 
-__global__ void k_prob_stop(ProbState *ps, int p) { ps[p].active = 0; }
+// Owner and type tables of the listed problems' blocks back to -1, problems
+// inactive; grid (any, problems).
+__global__ __launch_bounds__(256) void k_release_list(PidList L, const ProbParams *pp, int32_t *blk_prob,
+                                                      int32_t *sb_rom, int32_t *sb_prob, ProbState *ps) {
+    const int p = L.pid[blockIdx.y];
+    const ProbParams &P = pp[p];
+    const int t0 = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+    for (int i = t0; i < P.n_blk; i += stride) blk_prob[P.blk_begin + i] = -1;
+    for (int i = t0; i < P.n_sb; i += stride) {
+        sb_rom[P.sb_begin + i] = -1;
+        sb_prob[P.sb_begin + i] = -1;
+    }
+    if (t0 == 0) ps[p].active = 0;
+}
 
 // One iteration, per DoF block of every iterating problem, Chronopoulos-Gear
 // form: with the published (alpha, beta) and w = A u assembled from the cell
@@ -803,6 +992,13 @@ struct Batch {
     bool empty() const { return list.n == 0; }
 };
 
+// The host mirrors (pp_host, sb_rom_host, perm_host) may change only once
+// the last span copy out of them has run.
+mos_status mirror_wait(mos_engine e) {
+    MOS_HIP(hipEventSynchronize(e->mirror_ev));
+    return MOS_OK;
+}
+
 // FP64 true residual of the batch's problems into r64 and res2[p] (and, at
 // set-up, ||b_l||^2 into bb2[p]), from x64 scattered to the cell layout --
 // which is where the reconstruction later reads the solution.
@@ -831,6 +1027,8 @@ mos_status residual_batch(mos_engine e, const Batch &B, bool lift) {
 // problem is released.
 mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, const Batch &B) {
     hipStream_t st = e->ctx->stream;
+    MOS_TRY(mirror_wait(e));
+    int sb_lo = INT32_MAX, sb_hi = 0;
     for (EngineProblem *P : adm) {
         ProbParams &H = e->pp_host[P->pid];
         const Lattice &L = P->lat;
@@ -848,11 +1046,20 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
         H.nrb = e->ldk / 16;
         // Small problems reduce their scalars inside every update workgroup.
         H.fused = (int64_t)P->n_blk + (int64_t)P->n_sb * H.nrb <= CG_FUSE_MAX ? 1 : 0;
-        MOS_HIP(hipMemcpyAsync(e->pp + P->pid, &H, sizeof(ProbParams), hipMemcpyHostToDevice, st));
-        MOS_HIP(hipMemcpyAsync(e->sb_rom + P->sb_begin, P->sb_rom.data(), P->n_sb * 4, hipMemcpyHostToDevice, st));
-        MOS_HIP(hipMemcpyAsync(e->perm + P->sb_begin * 16, P->perm.data(), P->perm.size() * 4, hipMemcpyHostToDevice,
-                               st));
+        std::memcpy(e->sb_rom_host + P->sb_begin, P->sb_rom.data(), P->n_sb * 4);
+        std::memcpy(e->perm_host + (int64_t)P->sb_begin * 16, P->perm.data(), P->perm.size() * 4);
+        sb_lo = std::min(sb_lo, P->sb_begin);
+        sb_hi = std::max(sb_hi, P->sb_begin + P->n_sb);
     }
+    // One copy per table for the whole batch: the spans may cover other
+    // problems' ranges, whose mirror entries equal their device entries.
+    const int hw_p = e->pids.high;
+    MOS_HIP(hipMemcpyAsync(e->pp, e->pp_host, hw_p * sizeof(ProbParams), hipMemcpyHostToDevice, st));
+    MOS_HIP(hipMemcpyAsync(e->sb_rom + sb_lo, e->sb_rom_host + sb_lo, (size_t)(sb_hi - sb_lo) * 4,
+                           hipMemcpyHostToDevice, st));
+    MOS_HIP(hipMemcpyAsync(e->perm + (int64_t)sb_lo * 16, e->perm_host + (int64_t)sb_lo * 16,
+                           (size_t)(sb_hi - sb_lo) * 64, hipMemcpyHostToDevice, st));
+    MOS_HIP(hipEventRecord(e->mirror_ev, st));
     const int hw_blk = e->blk.high, hw_sb = e->sbs.high;
     hipLaunchKernelGGL(k_fill_owner, dim3(B.list.n), dim3(256), 0, st, B.list, (const ProbParams *)e->pp, e->blk_prob,
                        e->sb_prob);
@@ -1081,6 +1288,21 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
         return MOS_ENOMEM;
     }
     std::memset((void *)e->sp_host, 0, MAX_PROBS * sizeof(SweepParams));
+    if (hipHostMalloc((void **)&e->sb_rom_host, (size_t)e->cap_sb * 4, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&e->perm_host, (size_t)slots * 4, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("pinned host allocation failed");
+        return MOS_ENOMEM;
+    }
+    std::fill(e->sb_rom_host, e->sb_rom_host + e->cap_sb, -1);
+    std::fill(e->perm_host, e->perm_host + slots, -1);
+    if (hipHostMalloc((void **)&e->ps_host, MAX_PROBS * sizeof(ProbState), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("pinned host allocation failed");
+        return MOS_ENOMEM;
+    }
+    MOS_HIP(hipEventCreateWithFlags(&e->mirror_ev, hipEventDisableTiming));
+    MOS_HIP(hipEventRecord(e->mirror_ev, ctx->stream));
     MOS_TRY(m.alloc_n((size_t)MAX_PROBS * MAX_TYPES, &e->jobs));
     if (hipHostMalloc((void **)&e->jobs_host, (size_t)MAX_PROBS * MAX_TYPES * sizeof(ReconJob),
                       hipHostMallocDefault) != hipSuccess) {
@@ -1109,6 +1331,7 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     fill32(e->blk_prob, e->cap_blk, 0xffffffffu);
     fill32(e->sb_rom, e->cap_sb, 0xffffffffu);
     fill32(e->sb_prob, e->cap_sb, 0xffffffffu);  // -1: no owner (batched phases select by owner)
+    fill32(e->perm, slots, 0xffffffffu);         // as its host mirror
     fill32(e->ps, (int64_t)MAX_PROBS * sizeof(ProbState) / 4, 0u);
     MOS_LAUNCH_CHECK();
     std::vector<const void *> t64(MAX_TYPES, nullptr), t32(MAX_TYPES, nullptr), tb(MAX_TYPES, nullptr),
@@ -1130,6 +1353,7 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     // The GEMM variant is fixed per engine (never per batch), so a problem's
     // rounding does not depend on what else is in the batch.
     e->gemm_rows = ldk / 4 <= ROWS_MAX_KS;
+    e->tuner.configure(e->gemm_paths, e->gemm_split);
     e->blk.init(e->cap_blk);
     e->sbs.init(e->cap_sb);
     e->pids.init(MAX_PROBS);
@@ -1198,19 +1422,28 @@ namespace {
 
 mos_status reconstruct_problem(mos_engine e, EngineProblem *P);
 
-void release_problem(mos_engine e, EngineProblem *P) {
+// Release the listed problems: one launch returns their owner and type
+// tables to -1 and marks them inactive (their device parameters are still
+// in place when it runs); the host mirrors follow.
+mos_status release_problems(mos_engine e, const std::vector<EngineProblem *> &probs) {
+    if (probs.empty()) return MOS_OK;
     hipStream_t st = e->ctx->stream;
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>(ceil_div(P->n_blk, 256), 4096)), dim3(256), 0, st,
-                       (uint32_t *)(e->blk_prob + P->blk_begin), (int64_t)P->n_blk, 0xffffffffu);
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>(ceil_div(P->n_sb, 256), 4096)), dim3(256), 0, st,
-                       (uint32_t *)(e->sb_rom + P->sb_begin), (int64_t)P->n_sb, 0xffffffffu);
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<int64_t>(ceil_div(P->n_sb, 256), 4096)), dim3(256), 0, st,
-                       (uint32_t *)(e->sb_prob + P->sb_begin), (int64_t)P->n_sb, 0xffffffffu);
-    hipLaunchKernelGGL(k_prob_stop, dim3(1), dim3(1), 0, st, e->ps, P->pid);
-    P->dev.release();  // stream-ordered: later work on this stream may reuse it
-    e->blk.give(P->blk_begin, P->n_blk);
-    e->sbs.give(P->sb_begin, P->n_sb);
-    e->pids.give(P->pid, 1);
+    Batch B;
+    for (EngineProblem *P : probs) B.add(P->pid);
+    hipLaunchKernelGGL(k_release_list, dim3(16, B.list.n), dim3(256), 0, st, B.list, (const ProbParams *)e->pp,
+                       e->blk_prob, e->sb_rom, e->sb_prob, e->ps);
+    MOS_LAUNCH_CHECK();
+    MOS_TRY(mirror_wait(e));
+    for (EngineProblem *P : probs) {
+        std::fill(e->sb_rom_host + P->sb_begin, e->sb_rom_host + P->sb_begin + P->n_sb, -1);
+        std::fill(e->perm_host + (int64_t)P->sb_begin * 16, e->perm_host + (int64_t)(P->sb_begin + P->n_sb) * 16,
+                  -1);
+        P->dev.release();  // stream-ordered: later work on this stream may reuse it
+        e->blk.give(P->blk_begin, P->n_blk);
+        e->sbs.give(P->sb_begin, P->n_sb);
+        e->pids.give(P->pid, 1);
+    }
+    return MOS_OK;
 }
 
 }  // namespace
@@ -1248,28 +1481,63 @@ mos_status launch_rows(mos_ctx ctx, int ks, int spw, hipStream_t st, const void 
     return MOS_OK;
 }
 
+template <class T, int KS, bool EXACT>
+void launch_wg_ks(mos_ctx ctx, int spw, hipStream_t st, const void *const *kr_tab, const int32_t *sb_rom,
+                  const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots, int n_sb, int ks, const ProbState *ps,
+                  double *pdel) {
+    // One workgroup (one wave per row block) per run of spw slot blocks;
+    // two operand tiles in LDS.
+    const int nrb = ks / 4;
+    const dim3 grid((unsigned)ceil_div(n_sb, spw));
+    const size_t lds = 2 * (size_t)(4 * ks) * 16 * sizeof(T);
+    launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm_wg<T, KS, EXACT>, grid, dim3(64 * nrb), lds, st, kr_tab, sb_rom,
+                 sb_prob, Mc, Y, ld_slots, 0, n_sb, spw, 1, ks, ps, pdel);
+}
+
+template <class T>
+mos_status launch_wg(mos_ctx ctx, int ks, int spw, hipStream_t st, const void *const *kr_tab,
+                     const int32_t *sb_rom, const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots, int n_sb,
+                     const ProbState *ps, double *pdel) {
+    if (ks == 8)
+        launch_wg_ks<T, 8, true>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps, pdel);
+    else if (ks == 20)
+        launch_wg_ks<T, 20, true>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps, pdel);
+    else if (ks == ROWS_MAX_KS)
+        launch_wg_ks<T, ROWS_MAX_KS, true>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps,
+                                           pdel);
+    else if (ks < ROWS_MAX_KS)
+        launch_wg_ks<T, ROWS_MAX_KS, false>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps,
+                                            pdel);
+    else {
+        set_error("no operand-tile GEMM for %d k-steps", ks);
+        return MOS_EINVAL;
+    }
+    MOS_LAUNCH_CHECK();
+    return MOS_OK;
+}
+
 template <class T>
 mos_status rows_step(mos_engine e, int ks, int hw_sb);
 
-// Pick the rows-GEMM work split for `n_sb` active slot blocks; *cand_out is
-// set to the candidate when this launch is a tuning trial (its events are
-// then recorded by the caller around the launch).
-int tuner_pick(GemmTuner &T, int n_sb, int *cand_out) {
-    *cand_out = -1;
-    if (T.fixed > 0) return T.fixed;
+// Pick the rows-GEMM candidate (operand path, work split) for `n_sb` active
+// slot blocks; *trial is set when this launch is a tuning trial (its events
+// are then recorded by the caller around the launch).
+int tuner_pick(GemmTuner &T, int n_sb, bool *trial) {
+    *trial = false;
+    if (T.n_cand <= 1) return 0;
     int bucket = 0;
     while ((1 << bucket) < n_sb) ++bucket;
     GemmTuner::Bucket &B = T.buckets[bucket];
-    if (B.chosen > 0) return GemmTuner::SPW[B.chosen - 1];
-    for (int k = 0; k < GemmTuner::N_CAND; ++k) {
+    if (B.chosen > 0) return B.chosen - 1;
+    for (int k = 0; k < T.n_cand; ++k) {
         int queued = 0;
         for (const auto &pd : T.pending) queued += pd.bucket == bucket && pd.cand == k;
         if (B.runs[k] + queued < GemmTuner::REPS) {
-            *cand_out = k;
-            return GemmTuner::SPW[k];
+            *trial = true;
+            return k;
         }
     }
-    return GemmTuner::SPW[0];  // all trials queued, results not read yet
+    return 0;  // all trials queued, results not read yet
 }
 
 // Read the tuning trials of the last chunk (the stream has been synchronised).
@@ -1292,12 +1560,34 @@ void tuner_collect(GemmTuner &T) {
         if (B.chosen > 0) continue;
         bool done = true;
         int best = 0;
-        for (int c = 0; c < GemmTuner::N_CAND; ++c) {
+        for (int c = 0; c < T.n_cand; ++c) {
             done &= B.runs[c] >= GemmTuner::REPS;
             if (B.best[c] < B.best[best]) best = c;
         }
         if (done) B.chosen = best + 1;
     }
+}
+
+void GemmTuner::configure(int paths, int fixed_spw) {
+    n_cand = 0;
+    for (int path = 0; path < 2; ++path) {
+        if (!((paths >> path) & 1)) continue;
+        if (fixed_spw > 0) {
+            cand_path[n_cand] = path;
+            cand_spw[n_cand++] = fixed_spw;
+        } else {
+            for (int k = 0; k < N_SPW; ++k) {
+                cand_path[n_cand] = path;
+                cand_spw[n_cand++] = SPW[k];
+            }
+        }
+    }
+    buckets.clear();
+    for (const Pending &pd : pending) {
+        spare.push_back(pd.start);
+        spare.push_back(pd.stop);
+    }
+    pending.clear();
 }
 
 hipEvent_t tuner_event(GemmTuner &T) {
@@ -1319,18 +1609,23 @@ hipEvent_t tuner_event(GemmTuner &T) {
 template <class T>
 mos_status rows_step(mos_engine e, int ks, int hw_sb) {
     hipStream_t st = e->ctx->stream;
-    int cand = -1;
-    const int spw = tuner_pick(e->tuner, hw_sb, &cand);
+    bool trial = false;
+    const int cand = tuner_pick(e->tuner, hw_sb, &trial);
+    const int spw = e->tuner.cand_spw[cand];
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (cand >= 0) {
+    if (trial) {
         ev0 = tuner_event(e->tuner);
         ev1 = tuner_event(e->tuner);
         if (ev0 && ev1) MOS_HIP(hipEventRecord(ev0, st));
     }
     const void *const *tab = (const void *const *)(sizeof(T) == 4 ? e->kr32_tab : e->kr64_tab);
-    MOS_TRY(launch_rows<T>(e->ctx, ks, spw, st, tab, e->sb_rom, e->sb_prob, (const T *)e->Mc, (T *)e->Yi,
-                           e->ld_slots, hw_sb, (const ProbState *)e->ps, e->pdel));
-    if (cand >= 0 && ev0 && ev1) {
+    if (e->tuner.cand_path[cand] == 1)
+        MOS_TRY(launch_wg<T>(e->ctx, ks, spw, st, tab, e->sb_rom, e->sb_prob, (const T *)e->Mc, (T *)e->Yi,
+                             e->ld_slots, hw_sb, (const ProbState *)e->ps, e->pdel));
+    else
+        MOS_TRY(launch_rows<T>(e->ctx, ks, spw, st, tab, e->sb_rom, e->sb_prob, (const T *)e->Mc, (T *)e->Yi,
+                               e->ld_slots, hw_sb, (const ProbState *)e->ps, e->pdel));
+    if (trial && ev0 && ev1) {
         MOS_HIP(hipEventRecord(ev1, st));
         int bucket = 0;
         while ((1 << bucket) < hw_sb) ++bucket;
@@ -1441,8 +1736,8 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
         }
         MOS_LAUNCH_CHECK();
         // 3. Problems whose inner solve stopped: fold in the correction, FP64 residual.
-        std::vector<ProbState> hs(hw_p);
-        MOS_HIP(hipMemcpyAsync(hs.data(), e->ps, hw_p * sizeof(ProbState), hipMemcpyDeviceToHost, st));
+        const ProbState *hs = e->ps_host;
+        MOS_HIP(hipMemcpyAsync(e->ps_host, e->ps, hw_p * sizeof(ProbState), hipMemcpyDeviceToHost, st));
         MOS_HIP(hipStreamSynchronize(st));
         tuner_collect(e->tuner);
         std::vector<EngineProblem *> stopped;
@@ -1487,7 +1782,7 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
         MOS_TRY(recon_f64_jobs(ctx, e->roms.data(), n_roms, jobs.data(), e->jobs, e->jobs_host,
                                (const double *)e->Mc64, e->ld_slots, (const int32_t *)e->perm, false));
     }
-    std::vector<EngineProblem *> keep;
+    std::vector<EngineProblem *> keep, gone;
     for (EngineProblem *P : e->active) {
         if (P->state == 2 || P->state == 3) {
             if (P->state == 2 && (P->vm || P->sig6) && !batch_recon) MOS_TRY(reconstruct_problem(e, P));
@@ -1495,14 +1790,14 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
                 MOS_HIP(hipMemcpyAsync(P->u_out, e->x64 + (int64_t)P->blk_begin * DB, P->n_dofs * 8,
                                        hipMemcpyDeviceToDevice, st));
             e->finished[P->ticket] = P;
-            release_problem(e, P);
+            gone.push_back(P);
             if (completed) completed->push_back(P->ticket);
         } else {
             keep.push_back(P);
         }
     }
     e->active.swap(keep);
-    return MOS_OK;
+    return release_problems(e, gone);
 }
 
 // ---------------------------------------------------------------------------
@@ -1636,6 +1931,14 @@ void engine_free(mos_engine e) {
     e->pp_host = nullptr;
     if (e->sp_host) (void)hipHostFree(e->sp_host);
     e->sp_host = nullptr;
+    if (e->ps_host) (void)hipHostFree(e->ps_host);
+    e->ps_host = nullptr;
+    if (e->sb_rom_host) (void)hipHostFree(e->sb_rom_host);
+    e->sb_rom_host = nullptr;
+    if (e->perm_host) (void)hipHostFree(e->perm_host);
+    e->perm_host = nullptr;
+    if (e->mirror_ev) (void)hipEventDestroy(e->mirror_ev);
+    e->mirror_ev = nullptr;
 }
 
 }  // namespace mos

@@ -27,7 +27,7 @@ EXPORTED = ("mos_ctx_create", "mos_ctx_destroy", "mos_build_cell", "mos_reduce",
             "mos_cell_free", "mos_rom_free", "mos_sol_free", "mos_last_error")
 MOS_K_CELL_GEMM, MOS_K_PCG_SCALARS, MOS_K_PCG_UPDATE, MOS_K_RECON = 1, 2, 3, 4
 MOS_OPT_CELL_GEMM = 1
-GEMM_TILES, GEMM_ROWS = 1, 2
+GEMM_AUTO, GEMM_TILES, GEMM_ROWS, GEMM_ROWS_LDS = 0, 1, 2, 3
 MOS_OPT_GEMM_SPLIT = 2
 
 

@@ -86,7 +86,7 @@ def run_engine(env, probs, mixed=False, budget=1 << 28, iterations=16, interleav
     return [done[i] for i in range(len(probs))]
 
 
-@pytest.mark.parametrize("gemm", [1, 2], ids=["tiles", "rows"])
+@pytest.mark.parametrize("gemm", [1, 2, 3], ids=["tiles", "rows", "rows-lds"])
 def test_batch_of_uneven_arrays_matches_oracle(env, gemm):
     mos, ctx, roms, oroms, torch = env
     probs = problems(1, [(3, 2), (1, 1), (5, 4), (2, 7), (4, 4)])
@@ -98,8 +98,9 @@ def test_batch_of_uneven_arrays_matches_oracle(env, gemm):
         assert np.abs(vm - vm_ref).max() <= 1e-9 * np.abs(vm_ref).max()
 
 
-@pytest.mark.parametrize("mixed,gemm", [(False, 1), (True, 1), (False, 2), (True, 2)],
-                         ids=["fp64-tiles", "mixed-tiles", "fp64-rows", "mixed-rows"])
+@pytest.mark.parametrize("mixed,gemm", [(False, 1), (True, 1), (False, 2), (True, 2), (False, 3), (True, 3)],
+                         ids=["fp64-tiles", "mixed-tiles", "fp64-rows", "mixed-rows", "fp64-rows-lds",
+                              "mixed-rows-lds"])
 def test_result_is_the_same_alone_and_in_the_mix(env, mixed, gemm):
     probs = problems(2, [(4, 3), (2, 2), (6, 5), (3, 3)])
     mix = run_engine(env, probs, mixed=mixed, gemm=gemm)
@@ -110,7 +111,7 @@ def test_result_is_the_same_alone_and_in_the_mix(env, mixed, gemm):
         assert alone[2] == mix[i][2]
 
 
-@pytest.mark.parametrize("gemm", [1, 2], ids=["tiles", "rows"])
+@pytest.mark.parametrize("gemm", [1, 2, 3], ids=["tiles", "rows", "rows-lds"])
 def test_mixed_precision_batch_within_tolerance(env, gemm):
     mos, ctx, roms, oroms, torch = env
     probs = problems(3, [(5, 5), (2, 3), (7, 2)])
@@ -151,11 +152,13 @@ def test_admission_while_others_iterate(env):
 @pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "mixed"])
 def test_gemm_work_split_never_changes_results(env, mixed):
     """The rows GEMM's work split (fixed or tuned online) only decides which
-    wave computes which output tile, so results are bitwise identical."""
+    wave computes which output tile, and staging the operand tile in LDS only
+    changes where the same operands are read from, so results are bitwise
+    identical."""
     probs = problems(5, [(3, 2), (5, 4), (2, 7), (6, 6)])
     ref = run_engine(env, probs, mixed=mixed, gemm=2, split=1)
-    for split in (4, 16, 0):
-        res = run_engine(env, probs, mixed=mixed, gemm=2, split=split)
+    for gemm, split in ((2, 4), (2, 16), (2, 0), (3, 1), (3, 4), (3, 0), (0, 0)):
+        res = run_engine(env, probs, mixed=mixed, gemm=gemm, split=split)
         for a, b in zip(ref, res):
             assert a[2] == b[2] and a[3] == b[3]
             assert np.array_equal(a[5], b[5])
