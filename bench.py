@@ -20,6 +20,7 @@ completion minus arrival.
 Prints one JSON line.
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -34,6 +35,14 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
+
+
+def quiet_gc():
+    """Collect now and move every live object out of the collector's reach,
+    so that no full collection (tens of ms with torch loaded) lands inside a
+    timed region."""
+    gc.collect()
+    gc.freeze()
 
 
 def per_iteration_work(kernel, mos, n, n_cells, n_dofs_pad, n_nodes, mixed):
@@ -179,6 +188,7 @@ def batch_mode(args, mos, torch, np, W):
     mos.mos_timing_start(ctx, dominant, TIME_EVERY)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     recs = []
+    quiet_gc()
     torch.cuda.synchronize()
     ev[0].record(stream)
     for s in range(args.steps):
@@ -331,6 +341,7 @@ def single_mode(args, mos, torch, np, W):
             totals[k] = mos.mos_timing_stop(ctx)
         dominant = max((k for k in totals if k != mos.MOS_K_PCG_SCALARS), key=lambda k: totals[k][1])
         mos.mos_timing_start(ctx, dominant, TIME_EVERY)
+        quiet_gc()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         res = [run() for _ in range(args.steps)]
@@ -439,6 +450,7 @@ def serve_mode(args, mos, torch, np, W):
     arrival, done_t, cells = {}, {}, 0
     i = 0
     tickets = {}
+    quiet_gc()
     start = time.perf_counter()
     while len(done_t) < len(reqs):
         now = time.perf_counter() - start

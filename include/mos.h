@@ -239,7 +239,12 @@ mos_status mos_engine_result(mos_engine e, int64_t ticket, int32_t *status, doub
  * three times with stream events and the fastest kept); 1 <= k <= 64 fixes
  * it.  It only decides which wave computes which output tile, so results do
  * not depend on it; it may be changed at any time (tuning starts over). */
-enum { MOS_OPT_CELL_GEMM = 1, MOS_OPT_GEMM_SPLIT = 2 };
+/* MOS_OPT_UPDATE_WIDTH sets the threads per workgroup of the PCG vector
+ * update: 256 (one DoF each) or 128 (two DoFs each); 0 (default) takes 256
+ * while the iterating DoF blocks fit on the chip at once and 128 beyond.
+ * Both compute every sum in the same order, so results do not depend on it;
+ * it may be changed at any time. */
+enum { MOS_OPT_CELL_GEMM = 1, MOS_OPT_GEMM_SPLIT = 2, MOS_OPT_UPDATE_WIDTH = 3 };
 mos_status mos_engine_option(mos_engine e, int option, int64_t value);
 
 /* Problems admitted and queued, and the arena capacities. */

@@ -579,6 +579,10 @@ mos_status mos_engine_option(mos_engine e, int option, int64_t value) {
         e->tuner.configure(e->gemm_paths, e->gemm_split);
         return MOS_OK;
     }
+    if (option == MOS_OPT_UPDATE_WIDTH && (value == 0 || value == 128 || value == 256)) {
+        e->update_width = (int)value;
+        return MOS_OK;
+    }
     if (option == MOS_OPT_GEMM_SPLIT && value >= 0 && value <= 64) {
         e->gemm_split = (int)value;
         e->tuner.configure(e->gemm_paths, e->gemm_split);

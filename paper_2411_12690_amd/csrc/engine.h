@@ -123,6 +123,7 @@ struct mos_engine_s {
     bool gemm_rows = false;                   // cell GEMM variant (fixed per engine)
     int gemm_paths = 3;                       // operand paths of the rows variant open to the tuner
     int gemm_split = 0;                       // fixed work split (0: tuned)
+    int update_width = 0;                     // threads per update workgroup (0: by batch size)
     mos::GemmTuner tuner;                     // operand path and work split of the rows variant
     mos::DeviceArena mem;
     // device arrays

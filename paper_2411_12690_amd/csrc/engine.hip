@@ -111,21 +111,42 @@ struct CgStep {
     double alpha, beta, gamma, rr, tol2;
 };
 
+constexpr int CG_LW = 256;  // logical width of the scalar reduction
+
+template <int NT>
 __device__ CgStep cg_scalars_block(const ProbState &S, int it, const double *pg, const double *pr,
-                                   const double *pdel, double (*red)[256]) {
+                                   const double *pdel, double (*red)[NT]) {
+    static_assert(NT == CG_LW || 2 * NT == CG_LW, "one or two logical lanes per thread");
+    // Logical lane L sums the partials L, L + CG_LW, ...; a thread holding
+    // two lanes (t and t + NT) adds them as the first level of the tree
+    // would, so the result has the same bits for either workgroup size.
     double g = 0.0, r = 0.0, dl = 0.0;
+#pragma unroll
+    for (int h = 0; h < CG_LW / NT; ++h) {
+        const int L = threadIdx.x + h * NT;
+        double gh = 0.0, rh = 0.0, dh = 0.0;
 #pragma unroll 4
-    for (int i = S.blk_begin + threadIdx.x; i < S.blk_end; i += 256) {
-        g += pg[i];
-        r += pr[i];
+        for (int i = S.blk_begin + L; i < S.blk_end; i += CG_LW) {
+            gh += pg[i];
+            rh += pr[i];
+        }
+#pragma unroll 4
+        for (int i = S.tile_begin + L; i < S.tile_end; i += CG_LW) dh += pdel[i];
+        if (h == 0) {
+            g = gh;
+            r = rh;
+            dl = dh;
+        } else {
+            g += gh;
+            r += rh;
+            dl += dh;
+        }
     }
-#pragma unroll 4
-    for (int i = S.tile_begin + threadIdx.x; i < S.tile_end; i += 256) dl += pdel[i];
     red[0][threadIdx.x] = g;
     red[1][threadIdx.x] = r;
     red[2][threadIdx.x] = dl;
     __syncthreads();
-    for (int m = 128; m > 0; m >>= 1) {
+    for (int m = NT / 2; m > 0; m >>= 1) {
         if ((int)threadIdx.x < m)
             for (int j = 0; j < 3; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + m];
         __syncthreads();
@@ -176,12 +197,12 @@ __device__ __forceinline__ void cg_publish(ProbState &S, int it, const CgStep &o
 // reads slot it & 1 (written by the previous update or the sweep start).
 __global__ __launch_bounds__(256) void k_cg_scalars(ProbState *ps, const double *pg, const double *pr,
                                                     const double *pdel, int epoch, int cap_blk) {
-    __shared__ double red[3][256];
+    __shared__ double red[3][CG_LW];
     ProbState &S = ps[blockIdx.x];
     if (!S.active || S.done || S.fused) return;  // uniform over the workgroup
     const int it = epoch - S.start_epoch;
     const size_t slot = (size_t)(it & 1) * cap_blk;
-    const CgStep o = cg_scalars_block(S, it, pg + slot, pr + slot, pdel, red);
+    const CgStep o = cg_scalars_block<CG_LW>(S, it, pg + slot, pr + slot, pdel, red);
     if (threadIdx.x == 0) cg_publish(S, it, o);
 }
 
@@ -544,26 +565,64 @@ __global__ __launch_bounds__(256) void k_release_list(PidList L, const ProbParam
     if (t0 == 0) ps[p].active = 0;
 }
 
+// Per-block (r,u) and (r,r) partials of an update workgroup of NT threads,
+// DoF j NT + t of the block at thread t, slot j: each group of 64
+// consecutive DoFs is summed by a butterfly over its wave's lanes, and the
+// groups in DoF order -- the same bits for either workgroup size.
+template <int NT>
+__device__ __forceinline__ void block_partials(const double (&g)[DB / NT], const double (&r)[DB / NT], double &gs,
+                                               double &rs) {
+    constexpr int DPT = DB / NT, NG = DB / 64;
+    __shared__ double sh[2][NG];
+    const int w = threadIdx.x / 64;
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        double a = g[j], b = r[j];
+        for (int m = 32; m >= 1; m >>= 1) {
+            a += __shfl_xor(a, m);
+            b += __shfl_xor(b, m);
+        }
+        if (threadIdx.x % 64 == 0) {
+            sh[0][j * (NT / 64) + w] = a;
+            sh[1][j * (NT / 64) + w] = b;
+        }
+    }
+    __syncthreads();
+    gs = rs = 0.0;
+    for (int i = 0; i < NG; ++i) {
+        gs += sh[0][i];
+        rs += sh[1][i];
+    }
+}
+
+// Update workgroups of 256 threads (one DoF each) while every block of the
+// launch fits on the chip at once; beyond that 128 threads with two DoFs
+// each, so more blocks are resident and each thread has more loads in
+// flight.  Both give the same bits.
+constexpr int CG_WIDE_MAX_BLK = 2048;
+
 // One iteration, per DoF block of every iterating problem, Chronopoulos-Gear
 // form: with the published (alpha, beta) and w = A u assembled from the cell
 // products (u = M^-1 r),
 //   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,
 // then the next u = M^-1 r to the cell layout and the partials of the next
 // (r,u) and (r,r).  Only x, r, p and s are stored.
-template <class T>
-__global__ __launch_bounds__(256) void k_cgstep(const T *Y, const int32_t *inc, const uint8_t *cmask, const T *dinv,
-                                                T *x, T *r, T *p, T *s, T *Mc, int ld_slots, const int32_t *blk_prob,
-                                                ProbState *ps, double *pg, double *pr, const double *pdel,
-                                                int epoch, int cap_blk) {
+template <class T, int NT>
+__global__ __launch_bounds__(NT) void k_cgstep(const T *Y, const int32_t *inc, const uint8_t *cmask, const T *dinv,
+                                               T *x, T *r, T *p, T *s, T *Mc, int ld_slots, const int32_t *blk_prob,
+                                               ProbState *ps, double *pg, double *pr, const double *pdel, int epoch,
+                                               int cap_blk) {
+    constexpr int DPT = DB / NT;
     __shared__ int go, it_sh;
     __shared__ double step[2];
-    __shared__ double red[3][256];
-    const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x;
+    __shared__ double red[3][NT];
+    const int64_t d0 = (int64_t)blockIdx.x * DB + threadIdx.x;
     // Only the incidence is requested before the gate resolves: blocks of
     // problems that have stopped (converged, or between refinement sweeps)
     // must not spend bandwidth on their operands.
-    const int4 iv = incidence(inc, d);
-    const int ci = (int)(d % 3);
+    int4 iv[DPT];
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) iv[j] = incidence(inc, d0 + j * NT);
     const int pb = blk_prob[blockIdx.x];
     if (threadIdx.x == 0) {
         int g = 0;
@@ -587,7 +646,7 @@ __global__ __launch_bounds__(256) void k_cgstep(const T *Y, const int32_t *inc, 
         // Small problem: every workgroup reduces its partials itself (same
         // bits in each); the problem's first workgroup publishes the state.
         ProbState &S = ps[pb];
-        const CgStep o = cg_scalars_block(S, it, pg + rd_slot, pr + rd_slot, pdel, red);
+        const CgStep o = cg_scalars_block<NT>(S, it, pg + rd_slot, pr + rd_slot, pdel, red);
         if (threadIdx.x == 0 && (int)blockIdx.x == S.blk_begin) cg_publish(S, it, o);
         if (o.stop) return;
         if (threadIdx.x == 0) {
@@ -597,24 +656,42 @@ __global__ __launch_bounds__(256) void k_cgstep(const T *Y, const int32_t *inc, 
         __syncthreads();
     }
     const T a = (T)step[0], b = (T)step[1];
-    const T dv = dinv[d], rd = r[d], pd0 = p[d], sd = s[d], xd = x[d];
-    const T sum = cell_sum(Y, iv, ci, ld_slots);
-    const T wv = cmask[d] ? T(0) : sum;
-    const T uv = dv * rd;
-    const T pv = uv + b * pd0;
-    const T sv = wv + b * sd;
-    x[d] = xd + a * pv;
-    const T rv = rd - a * sv;
-    const T un = dv * rv;
-    p[d] = pv;
-    s[d] = sv;
-    r[d] = rv;
-    cell_scatter(Mc, iv, ci, ld_slots, un);
-    double g = (double)rv * (double)un, r2 = (double)rv * (double)rv, z = 0.0;
-    block_sum3(g, r2, z);
+    // All operands of the thread's DoFs first (the arrays may alias as far
+    // as the compiler knows, so loads are not moved past earlier stores).
+    T dv[DPT], rd[DPT], pd0[DPT], sd[DPT], xd[DPT], wv[DPT];
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        const int64_t d = d0 + j * NT;
+        dv[j] = dinv[d];
+        rd[j] = r[d];
+        pd0[j] = p[d];
+        sd[j] = s[d];
+        xd[j] = x[d];
+        const T sum = cell_sum(Y, iv[j], (int)(d % 3), ld_slots);
+        wv[j] = cmask[d] ? T(0) : sum;
+    }
+    double g[DPT], r2[DPT];
+#pragma unroll
+    for (int j = 0; j < DPT; ++j) {
+        const int64_t d = d0 + j * NT;
+        const T uv = dv[j] * rd[j];
+        const T pv = uv + b * pd0[j];
+        const T sv = wv[j] + b * sd[j];
+        x[d] = xd[j] + a * pv;
+        const T rv = rd[j] - a * sv;
+        const T un = dv[j] * rv;
+        p[d] = pv;
+        s[d] = sv;
+        r[d] = rv;
+        cell_scatter(Mc, iv[j], (int)(d % 3), ld_slots, un);
+        g[j] = (double)rv * (double)un;
+        r2[j] = (double)rv * (double)rv;
+    }
+    double gs, rs;
+    block_partials<NT>(g, r2, gs, rs);
     if (threadIdx.x == 0) {
-        pg[wr_slot + blockIdx.x] = g;
-        pr[wr_slot + blockIdx.x] = r2;
+        pg[wr_slot + blockIdx.x] = gs;
+        pr[wr_slot + blockIdx.x] = rs;
     }
 }
 
@@ -1519,6 +1596,23 @@ mos_status launch_wg(mos_ctx ctx, int ks, int spw, hipStream_t st, const void *c
 template <class T>
 mos_status rows_step(mos_engine e, int ks, int hw_sb);
 
+// The update launch of one iteration over [0, hw_blk) DoF blocks.
+template <class T>
+void cgstep_launch(mos_engine e, int hw_blk, T *const *V) {
+    hipStream_t st = e->ctx->stream;
+    const bool wide = e->update_width ? e->update_width == 256 : hw_blk <= CG_WIDE_MAX_BLK;
+    if (wide)
+        launch_timed(e->ctx, MOS_K_PCG_UPDATE, k_cgstep<T, 256>, dim3(hw_blk), dim3(256), 0, st, (const T *)e->Yi,
+                     (const int32_t *)e->inc, (const uint8_t *)e->cmask, (const T *)V[VDINV], V[VX], V[VR], V[VP],
+                     V[VS], (T *)e->Mc, e->ld_slots, (const int32_t *)e->blk_prob, e->ps, e->pg, e->pr,
+                     (const double *)e->pdel, e->epoch, e->cap_blk);
+    else
+        launch_timed(e->ctx, MOS_K_PCG_UPDATE, k_cgstep<T, 128>, dim3(hw_blk), dim3(128), 0, st, (const T *)e->Yi,
+                     (const int32_t *)e->inc, (const uint8_t *)e->cmask, (const T *)V[VDINV], V[VX], V[VR], V[VP],
+                     V[VS], (T *)e->Mc, e->ld_slots, (const int32_t *)e->blk_prob, e->ps, e->pg, e->pr,
+                     (const double *)e->pdel, e->epoch, e->cap_blk);
+}
+
 // Pick the rows-GEMM candidate (operand path, work split) for `n_sb` active
 // slot blocks; *trial is set when this launch is a tuning trial (its events
 // are then recorded by the caller around the launch).
@@ -1707,11 +1801,7 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
                     launch_timed(ctx, MOS_K_PCG_SCALARS, k_cg_scalars, dim3(hw_p), dim3(256), 0, st, e->ps,
                                  (const double *)e->pg, (const double *)e->pr, (const double *)e->pdel, e->epoch,
                                  e->cap_blk);
-                launch_timed(ctx, MOS_K_PCG_UPDATE, k_cgstep<float>, dim3(hw_blk), dim3(DB), 0, st,
-                             (const float *)e->Yi, (const int32_t *)e->inc, (const uint8_t *)e->cmask,
-                             (const float *)V[VDINV], V[VX], V[VR], V[VP], V[VS], (float *)e->Mc, e->ld_slots,
-                             (const int32_t *)e->blk_prob, e->ps, e->pg, e->pr, (const double *)e->pdel, e->epoch,
-                             e->cap_blk);
+                cgstep_launch<float>(e, hw_blk, V);
             } else {
                 double *V[NVEC];
                 for (int i = 0; i < NVEC; ++i) V[i] = static_cast<double *>(e->v[i]);
@@ -1726,11 +1816,7 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
                     launch_timed(ctx, MOS_K_PCG_SCALARS, k_cg_scalars, dim3(hw_p), dim3(256), 0, st, e->ps,
                                  (const double *)e->pg, (const double *)e->pr, (const double *)e->pdel, e->epoch,
                                  e->cap_blk);
-                launch_timed(ctx, MOS_K_PCG_UPDATE, k_cgstep<double>, dim3(hw_blk), dim3(DB), 0, st,
-                             (const double *)e->Yi, (const int32_t *)e->inc, (const uint8_t *)e->cmask,
-                             (const double *)V[VDINV], V[VX], V[VR], V[VP], V[VS], (double *)e->Mc, e->ld_slots,
-                             (const int32_t *)e->blk_prob, e->ps, e->pg, e->pr, (const double *)e->pdel, e->epoch,
-                             e->cap_blk);
+                cgstep_launch<double>(e, hw_blk, V);
             }
             ++e->epoch;
         }

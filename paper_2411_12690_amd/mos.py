@@ -29,6 +29,7 @@ MOS_K_CELL_GEMM, MOS_K_PCG_SCALARS, MOS_K_PCG_UPDATE, MOS_K_RECON = 1, 2, 3, 4
 MOS_OPT_CELL_GEMM = 1
 GEMM_AUTO, GEMM_TILES, GEMM_ROWS, GEMM_ROWS_LDS = 0, 1, 2, 3
 MOS_OPT_GEMM_SPLIT = 2
+MOS_OPT_UPDATE_WIDTH = 3
 
 
 class MosError(RuntimeError):

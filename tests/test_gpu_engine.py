@@ -51,11 +51,14 @@ def n_dofs_of(nx, ny):
     return 3 * (X * Y * 4 - nx * ny * 1 * 1 * 2)
 
 
-def run_engine(env, probs, mixed=False, budget=1 << 28, iterations=16, interleave=None, gemm=None, split=None):
+def run_engine(env, probs, mixed=False, budget=1 << 28, iterations=16, interleave=None, gemm=None, split=None,
+               width=None):
     mos, ctx, roms, oroms, torch = env
     eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=budget, gemm=gemm)
     if split is not None:
         eng.option(mos.MOS_OPT_GEMM_SPLIT, split)
+    if width is not None:
+        eng.option(mos.MOS_OPT_UPDATE_WIDTH, width)
     dt = torch.float32 if mixed else torch.float64
     n_elem = roms[0].query(mos.MOS_Q_CELL_ELEMS)
     outs = {}
@@ -163,3 +166,16 @@ def test_gemm_work_split_never_changes_results(env, mixed):
             assert a[2] == b[2] and a[3] == b[3]
             assert np.array_equal(a[5], b[5])
             assert np.array_equal(a[4], b[4])
+
+
+@pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "mixed"])
+def test_update_width_never_changes_results(env, mixed):
+    """The vector update in workgroups of 256 threads (one DoF each) or 128
+    (two each) sums the same partials in the same order."""
+    probs = problems(6, [(4, 3), (6, 5), (2, 2)])
+    ref = run_engine(env, probs, mixed=mixed, width=256)
+    res = run_engine(env, probs, mixed=mixed, width=128)
+    for a, b in zip(ref, res):
+        assert a[2] == b[2] and a[3] == b[3]
+        assert np.array_equal(a[5], b[5])
+        assert np.array_equal(a[4], b[4])
