@@ -25,7 +25,8 @@ struct ProbState {
     int it, done, active, max_iter; // iterations of this sweep; stop code; iterating; cap
     int blk_begin, blk_end;         // the problem's DoF blocks (partials of (r,u), (r,r))
     int tile_begin, tile_end;       // its cell-GEMM tiles (partials of (u, A u))
-    int start_epoch, fused;         // iteration launch of the sweep's iteration 0; scalars in the update
+    int start_epoch, fused;         // iteration launch of iteration 0; scalars in the update
+    int seg_start, pad;             // iteration at which this sweep began (tolerance and cap count from it)
 };
 
 // Inner PCG vectors (Chronopoulos-Gear form), in the inner precision.
@@ -54,7 +55,8 @@ struct ProbParams {
 // Parameters of a problem's current refinement sweep (device table by id).
 struct SweepParams {
     double scale_in, scale_out, rtol2;
-    int32_t max_iter, pad;
+    double p_scale;                 // continuing sweeps: factor on the kept p, s (new over old scale_in)
+    int32_t max_iter, cont;         // cap; 1 = keep the search direction of the previous sweep
 };
 
 // Largest number of 4-wide k-steps (ldk <= 176, basis size <= 176) the
@@ -190,6 +192,8 @@ struct EngineProblem {
     double last_res2 = -1.0;      // FP64 residual before the last correction
     int sweep_cap = 0;            // inner iterations allowed per sweep
     int undone = 0;               // corrections undone because they raised the residual
+    bool can_continue = false;    // the inner solver state belongs to the folded-in correction
+    double last_scale_in = 0.0;   // scale_in of the last sweep
     int state = 0;                // 0 queued, 1 iterating, 2 converged, 3 failed
     mos_status status = MOS_OK;
     std::string error;

@@ -155,12 +155,12 @@ __device__ CgStep cg_scalars_block(const ProbState &S, int it, const double *pg,
     o.gamma = red[0][0];
     o.rr = red[1][0];
     const double delta = red[2][0];
-    o.tol2 = it == 0 ? S.rtol2 * o.rr : S.tol2;
+    o.tol2 = it == S.seg_start ? S.rtol2 * o.rr : S.tol2;
     o.stop = 0;
     o.alpha = o.beta = 0.0;
     if (o.rr <= o.tol2) {
         o.stop = 1;
-    } else if (it >= S.max_iter) {
+    } else if (it - S.seg_start >= S.max_iter) {
         o.stop = 3;
     } else {
         if (it == 0) {
@@ -179,7 +179,7 @@ __device__ CgStep cg_scalars_block(const ProbState &S, int it, const double *pg,
 // Readers of the same launch only read the other history slot.
 __device__ __forceinline__ void cg_publish(ProbState &S, int it, const CgStep &o) {
     S.rr = o.rr;
-    if (it == 0) S.tol2 = o.tol2;
+    if (it == S.seg_start) S.tol2 = o.tol2;
     if (o.stop) {
         S.done = o.stop;
     } else {
@@ -832,12 +832,22 @@ __global__ void k_prob_start_list(PidList L, const ProbParams *pp, const SweepPa
     if (i >= L.n) return;
     const int p = L.pid[i];
     ProbState &S = ps[p];
-    S.hist_gamma[0] = S.hist_gamma[1] = S.hist_alpha[0] = S.hist_alpha[1] = 0.0;
+    if (sp[p].cont) {
+        // Reliable update: the iteration goes on from where it stopped with
+        // the true residual in place of the recursive one; the kept (r,u)
+        // history follows the new scaling (alpha is scale-free).
+        const double c2 = sp[p].p_scale * sp[p].p_scale;
+        S.hist_gamma[0] *= c2;
+        S.hist_gamma[1] *= c2;
+    } else {
+        S.hist_gamma[0] = S.hist_gamma[1] = S.hist_alpha[0] = S.hist_alpha[1] = 0.0;
+        S.it = 0;
+    }
+    S.seg_start = S.it;
+    S.start_epoch = epoch - S.it;
     S.a_cur = S.b_cur = S.rr = S.tol2 = 0.0;
-    S.start_epoch = epoch;
     S.fused = pp[p].fused;
     S.rtol2 = sp[p].rtol2;
-    S.it = 0;
     S.done = 0;
     S.active = 1;
     S.max_iter = sp[p].max_iter;
@@ -856,24 +866,33 @@ __global__ void k_prob_stop_list(PidList L, ProbState *ps) {
 // 0, u = M^-1 r to the cell layout, partials of (r,u) and (r,r); the first
 // iteration's cell GEMM then gives w = A u and (u, A u).
 template <class T>
-__global__ void k_cgstart_sel(ProbSel sel, const int32_t *blk_prob, const SweepParams *sp, const double *r64,
-                              const T *dinv, const int32_t *inc, T *x, T *r, T *p, T *s, T *Mc, int ld_slots,
-                              double *pg, double *pr) {
+__global__ void k_cgstart_sel(ProbSel sel, const int32_t *blk_prob, const SweepParams *sp, const ProbState *ps,
+                              const double *r64, const T *dinv, const int32_t *inc, T *x, T *r, T *p, T *s, T *Mc,
+                              int ld_slots, double *pg, double *pr, int cap_blk) {
     const int pid = blk_prob[blockIdx.x];
     if (!selected(sel, pid)) return;
     const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x;
-    const T rv = (T)(r64[d] * sp[pid].scale_in);
+    const SweepParams &W = sp[pid];
+    const T rv = (T)(r64[d] * W.scale_in);
     const T uv = dinv[d] * rv;
     x[d] = 0;
     r[d] = rv;
-    p[d] = 0;
-    s[d] = 0;
+    if (W.cont) {
+        const T c = (T)W.p_scale;
+        p[d] *= c;
+        s[d] *= c;
+    } else {
+        p[d] = 0;
+        s[d] = 0;
+    }
     cell_scatter(Mc, incidence(inc, d), (int)(d % 3), ld_slots, uv);
     double g = (double)rv * (double)uv, r2 = (double)rv * (double)rv, z = 0.0;
     block_sum3(g, r2, z);
     if (threadIdx.x == 0) {
-        pg[blockIdx.x] = g;
-        pr[blockIdx.x] = r2;
+        // Partials of the first iteration of the sweep, in its parity slot.
+        const size_t slot = (size_t)(ps[pid].it & 1) * cap_blk;
+        pg[slot + blockIdx.x] = g;
+        pr[slot + blockIdx.x] = r2;
     }
 }
 
@@ -1197,8 +1216,9 @@ mos_status start_batch(mos_engine e, const Batch &B) {
     hipLaunchKernelGGL(k_prob_start_list, dim3(ceil_div(B.list.n, 64)), dim3(64), 0, st, B.list,
                        (const ProbParams *)e->pp, (const SweepParams *)e->sp, e->ps, e->epoch);
     hipLaunchKernelGGL(k_cgstart_sel<T>, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
-                       (const SweepParams *)e->sp, (const double *)e->r64, (const T *)V[VDINV],
-                       (const int32_t *)e->inc, V[VX], V[VR], V[VP], V[VS], Mc, e->ld_slots, e->pg, e->pr);
+                       (const SweepParams *)e->sp, (const ProbState *)e->ps, (const double *)e->r64,
+                       (const T *)V[VDINV], (const int32_t *)e->inc, V[VX], V[VR], V[VP], V[VS], Mc, e->ld_slots,
+                       e->pg, e->pr, e->cap_blk);
     MOS_LAUNCH_CHECK();
     (void)hw_sb;
     (void)Y;
@@ -1241,6 +1261,7 @@ mos_status decide(mos_engine e, EngineProblem *P, double res2, double bb2, bool 
         res2 = e->host_scratch[0];
         P->sweep_cap = std::max(P->sweep_cap / 2, 8);
         P->undone++;
+        P->can_continue = false;  // the solver state belonged to the rejected correction
     }
     P->last_res2 = res2;
     const double bnorm = std::sqrt(bb2), rnorm = std::sqrt(res2);
@@ -1269,6 +1290,13 @@ mos_status decide(mos_engine e, EngineProblem *P, double res2, double bb2, bool 
     // Inner rhs = r / ||r|| (mixed) or r (FP64).
     S.scale_in = mixed ? 1.0 / rnorm : 1.0;
     S.scale_out = mixed ? rnorm : 1.0;
+    // After a folded-in correction the inner iteration goes on with the
+    // true residual (a reliable update) instead of starting over, keeping
+    // its search direction rescaled to the new right-hand side.
+    S.cont = P->can_continue ? 1 : 0;
+    S.p_scale = P->can_continue ? S.scale_in / P->last_scale_in : 0.0;
+    P->last_scale_in = S.scale_in;
+    P->can_continue = true;
     double rtol_in;
     if (mixed) {
         // A fixed reduction per sweep; the last sweep asks for no more than
@@ -1832,8 +1860,9 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
             if (P->state != 1) continue;
             const ProbState &S = hs[P->pid];
             if (!S.done) continue;
-            P->iters += S.it;
-            if (S.done == 2 && S.it == 0) {
+            P->iters += S.it - S.seg_start;
+            if (S.done == 2) P->can_continue = false;  // breakdown: nothing to go on from
+            if (S.done == 2 && S.it == S.seg_start) {
                 P->state = 3;
                 P->status = MOS_ENOCONV;
                 P->error = "PCG breakdown (p.Ap <= 0 or non-finite) at the start of a sweep";
