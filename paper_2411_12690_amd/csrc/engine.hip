@@ -313,7 +313,7 @@ template <class T, int KS, bool EXACT>
 __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, const int32_t *sb_rom,
                                                     const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots,
                                                     int sb_base, int n_sb, int spw, int gate, int ks,
-                                                    const ProbState *ps, double *pdel) {
+                                                    const ProbState *ps, double *pdel, ProbSel sel) {
     typedef typename Mfma<T>::v4 v4;
     // KS bounds the k-steps held in registers; the basis uses ks <= KS of
     // them (ldk = 4 ks), and steps past ks are neither loaded nor issued.
@@ -338,9 +338,11 @@ __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, c
         for (; sl < s_end; ++sl) {
             const int sb = sb_base + sl;
             if (sb_rom[sb] < 0) continue;
-            if (gate) {
+            if (gate == 1) {
                 const ProbState &S = ps[sb_prob[sb]];
                 if (!S.active || S.done) continue;
+            } else if (gate == 2 && !selected(sel, sb_prob[sb])) {
+                continue;
             }
             break;
         }
@@ -433,7 +435,7 @@ template <class T, int KS, bool EXACT>
 __global__ __launch_bounds__(704) void k_bgemm_wg(const void *const *kr_tab, const int32_t *sb_rom,
                                                   const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots,
                                                   int sb_base, int n_sb, int spw, int gate, int ks,
-                                                  const ProbState *ps, double *pdel) {
+                                                  const ProbState *ps, double *pdel, ProbSel sel) {
     typedef typename Mfma<T>::v4 v4;
     typedef typename Chunk16<T>::v c16;
     constexpr int EPC = 16 / sizeof(T);  // elements per 16-byte chunk
@@ -455,9 +457,11 @@ __global__ __launch_bounds__(704) void k_bgemm_wg(const void *const *kr_tab, con
         for (; sl < s_end; ++sl) {
             const int sb = sb_base + sl;
             if (sb_rom[sb] < 0) continue;
-            if (gate) {
+            if (gate == 1) {
                 const ProbState &S = ps[sb_prob[sb]];
                 if (!S.active || S.done) continue;
+            } else if (gate == 2 && !selected(sel, sb_prob[sb])) {
+                continue;
             }
             break;
         }
@@ -524,6 +528,55 @@ __global__ __launch_bounds__(704) void k_bgemm_wg(const void *const *kr_tab, con
         buf ^= 1;
         sl = nx;
     }
+}
+
+// One K_r-stationary cell-GEMM launch over slot blocks [0, n_sb): operand
+// path 0 streams the operand per wave from global memory (one wave per row
+// block and run of spw slot blocks, four per workgroup), path 1 stages each
+// operand tile in LDS (one workgroup of one wave per row block per run).
+// Gate 1 skips slot blocks whose problem is not iterating, gate 2 those of
+// problems not in sel.  The launch is sampled by the kernel timer under
+// timed_id (0: never).
+template <class T, int KS, bool EXACT>
+void launch_cell_gemm_ks(mos_ctx ctx, int timed_id, int path, int spw, hipStream_t st, const void *const *kr_tab,
+                         const int32_t *sb_rom, const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots, int n_sb,
+                         int ks, const ProbState *ps, double *pdel, int gate, const ProbSel &sel) {
+    const int nrb = ks / 4;
+    if (path == 1) {
+        const dim3 grid((unsigned)ceil_div(n_sb, spw));
+        const size_t lds = 2 * (size_t)(4 * ks) * 16 * sizeof(T);
+        launch_timed(ctx, timed_id, k_bgemm_wg<T, KS, EXACT>, grid, dim3(64 * nrb), (uint32_t)lds, st, kr_tab,
+                     sb_rom, sb_prob, Mc, Y, ld_slots, 0, n_sb, spw, gate, ks, ps, pdel, sel);
+    } else {
+        const dim3 grid((unsigned)ceil_div((int64_t)nrb * ceil_div(n_sb, spw), 4));
+        launch_timed(ctx, timed_id, k_bgemm_rows<T, KS, EXACT>, grid, dim3(256), 0, st, kr_tab, sb_rom, sb_prob,
+                     Mc, Y, ld_slots, 0, n_sb, spw, gate, ks, ps, pdel, sel);
+    }
+}
+
+template <class T>
+mos_status launch_cell_gemm(mos_ctx ctx, int timed_id, int path, int ks, int spw, hipStream_t st,
+                            const void *const *kr_tab, const int32_t *sb_rom, const int32_t *sb_prob, const T *Mc,
+                            T *Y, int ld_slots, int n_sb, const ProbState *ps, double *pdel, int gate,
+                            const ProbSel &sel) {
+    if (ks == 8)
+        launch_cell_gemm_ks<T, 8, true>(ctx, timed_id, path, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots,
+                                        n_sb, ks, ps, pdel, gate, sel);
+    else if (ks == 20)
+        launch_cell_gemm_ks<T, 20, true>(ctx, timed_id, path, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots,
+                                         n_sb, ks, ps, pdel, gate, sel);
+    else if (ks == ROWS_MAX_KS)
+        launch_cell_gemm_ks<T, ROWS_MAX_KS, true>(ctx, timed_id, path, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y,
+                                                  ld_slots, n_sb, ks, ps, pdel, gate, sel);
+    else if (ks < ROWS_MAX_KS)
+        launch_cell_gemm_ks<T, ROWS_MAX_KS, false>(ctx, timed_id, path, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y,
+                                                   ld_slots, n_sb, ks, ps, pdel, gate, sel);
+    else {
+        set_error("no K_r-stationary GEMM for %d k-steps", ks);
+        return MOS_EINVAL;
+    }
+    MOS_LAUNCH_CHECK();
+    return MOS_OK;
 }
 
 // Incidence of DoF d: up to four packed (slot, surface node) of the cells
@@ -1103,9 +1156,16 @@ mos_status residual_batch(mos_engine e, const Batch &B, bool lift) {
     const int hw_blk = e->blk.high, hw_sb = e->sbs.high;
     hipLaunchKernelGGL(k_scatter_sel, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
                        (const double *)e->x64, (const int32_t *)e->inc, e->Mc64, e->ld_slots);
-    hipLaunchKernelGGL(k_bgemm<double>, dim3(e->ldk / 16, hw_sb), dim3(256), 0, st, (const void *const *)e->kr64_tab,
-                       e->sb_rom, e->sb_prob, (const double *)e->Mc64, e->Y64, e->ldk, e->ld_slots, 0, hw_sb, 2,
-                       (const ProbState *)e->ps, (double *)nullptr, B.sel);
+    // The K_r-stationary variants share one FP64 product here (operand tiles
+    // in LDS), so all of them give the same residual bits.
+    if (e->gemm_rows)
+        MOS_TRY(launch_cell_gemm<double>(e->ctx, 0, 1, e->ldk / 4, 1, st, (const void *const *)e->kr64_tab, e->sb_rom,
+                                         e->sb_prob, (const double *)e->Mc64, e->Y64, e->ld_slots, hw_sb,
+                                         (const ProbState *)e->ps, (double *)nullptr, 2, B.sel));
+    else
+        hipLaunchKernelGGL(k_bgemm<double>, dim3(e->ldk / 16, hw_sb), dim3(256), 0, st,
+                           (const void *const *)e->kr64_tab, e->sb_rom, e->sb_prob, (const double *)e->Mc64, e->Y64,
+                           e->ldk, e->ld_slots, 0, hw_sb, 2, (const ProbState *)e->ps, (double *)nullptr, B.sel);
     hipLaunchKernelGGL(k_residual_sel, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
                        (const double *)e->Y64, (const int32_t *)e->inc, (const double *)e->b_raw,
                        (const uint8_t *)e->cmask, (const double *)e->g, e->r64, e->pr64, e->pd, lift ? 1 : 0,
@@ -1553,74 +1613,6 @@ mos_status release_problems(mos_engine e, const std::vector<EngineProblem *> &pr
 
 }  // namespace
 
-template <class T, int KS, bool EXACT>
-void launch_rows_ks(mos_ctx ctx, int spw, hipStream_t st, const void *const *kr_tab, const int32_t *sb_rom,
-                    const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots, int n_sb, int ks, const ProbState *ps,
-                    double *pdel) {
-    // One wave per (row block, run of spw slot blocks), 4 per workgroup.
-    const int nrb = ks / 4;
-    const dim3 grid((unsigned)ceil_div((int64_t)nrb * ceil_div(n_sb, spw), 4));
-    launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm_rows<T, KS, EXACT>, grid, dim3(256), 0, st, kr_tab, sb_rom, sb_prob,
-                 Mc, Y, ld_slots, 0, n_sb, spw, 1, ks, ps, pdel);
-}
-
-template <class T>
-mos_status launch_rows(mos_ctx ctx, int ks, int spw, hipStream_t st, const void *const *kr_tab,
-                       const int32_t *sb_rom, const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots, int n_sb,
-                       const ProbState *ps, double *pdel) {
-    if (ks == 8)
-        launch_rows_ks<T, 8, true>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps, pdel);
-    else if (ks == 20)
-        launch_rows_ks<T, 20, true>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps, pdel);
-    else if (ks == ROWS_MAX_KS)
-        launch_rows_ks<T, ROWS_MAX_KS, true>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps,
-                                             pdel);
-    else if (ks < ROWS_MAX_KS)
-        launch_rows_ks<T, ROWS_MAX_KS, false>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps,
-                                              pdel);
-    else {
-        set_error("no rows GEMM for %d k-steps", ks);
-        return MOS_EINVAL;
-    }
-    MOS_LAUNCH_CHECK();
-    return MOS_OK;
-}
-
-template <class T, int KS, bool EXACT>
-void launch_wg_ks(mos_ctx ctx, int spw, hipStream_t st, const void *const *kr_tab, const int32_t *sb_rom,
-                  const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots, int n_sb, int ks, const ProbState *ps,
-                  double *pdel) {
-    // One workgroup (one wave per row block) per run of spw slot blocks;
-    // two operand tiles in LDS.
-    const int nrb = ks / 4;
-    const dim3 grid((unsigned)ceil_div(n_sb, spw));
-    const size_t lds = 2 * (size_t)(4 * ks) * 16 * sizeof(T);
-    launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm_wg<T, KS, EXACT>, grid, dim3(64 * nrb), lds, st, kr_tab, sb_rom,
-                 sb_prob, Mc, Y, ld_slots, 0, n_sb, spw, 1, ks, ps, pdel);
-}
-
-template <class T>
-mos_status launch_wg(mos_ctx ctx, int ks, int spw, hipStream_t st, const void *const *kr_tab,
-                     const int32_t *sb_rom, const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots, int n_sb,
-                     const ProbState *ps, double *pdel) {
-    if (ks == 8)
-        launch_wg_ks<T, 8, true>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps, pdel);
-    else if (ks == 20)
-        launch_wg_ks<T, 20, true>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps, pdel);
-    else if (ks == ROWS_MAX_KS)
-        launch_wg_ks<T, ROWS_MAX_KS, true>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps,
-                                           pdel);
-    else if (ks < ROWS_MAX_KS)
-        launch_wg_ks<T, ROWS_MAX_KS, false>(ctx, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots, n_sb, ks, ps,
-                                            pdel);
-    else {
-        set_error("no operand-tile GEMM for %d k-steps", ks);
-        return MOS_EINVAL;
-    }
-    MOS_LAUNCH_CHECK();
-    return MOS_OK;
-}
-
 template <class T>
 mos_status rows_step(mos_engine e, int ks, int hw_sb);
 
@@ -1741,12 +1733,9 @@ mos_status rows_step(mos_engine e, int ks, int hw_sb) {
         if (ev0 && ev1) MOS_HIP(hipEventRecord(ev0, st));
     }
     const void *const *tab = (const void *const *)(sizeof(T) == 4 ? e->kr32_tab : e->kr64_tab);
-    if (e->tuner.cand_path[cand] == 1)
-        MOS_TRY(launch_wg<T>(e->ctx, ks, spw, st, tab, e->sb_rom, e->sb_prob, (const T *)e->Mc, (T *)e->Yi,
-                             e->ld_slots, hw_sb, (const ProbState *)e->ps, e->pdel));
-    else
-        MOS_TRY(launch_rows<T>(e->ctx, ks, spw, st, tab, e->sb_rom, e->sb_prob, (const T *)e->Mc, (T *)e->Yi,
-                               e->ld_slots, hw_sb, (const ProbState *)e->ps, e->pdel));
+    MOS_TRY(launch_cell_gemm<T>(e->ctx, MOS_K_CELL_GEMM, e->tuner.cand_path[cand], ks, spw, st, tab, e->sb_rom,
+                                e->sb_prob, (const T *)e->Mc, (T *)e->Yi, e->ld_slots, hw_sb,
+                                (const ProbState *)e->ps, e->pdel, 1, ProbSel{}));
     if (trial && ev0 && ev1) {
         MOS_HIP(hipEventRecord(ev1, st));
         int bucket = 0;
@@ -1879,9 +1868,12 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
         }
     }
     // 4. Retire finished problems (reconstruct into their buffers first).  The
-    // FP64 reconstructions of every problem retiring now share one launch per
-    // cell type, so each block of the stress basis is staged once for all.
-    const bool batch_recon = e->precision == MOS_FP64 && e->ldk / 4 <= RECON_F64_LDS_KS;
+    // reconstructions of every problem retiring now share one launch per
+    // cell type (FP64, or BF16-split in the mixed engine), so each block of
+    // the stress basis is staged once for all.
+    const bool batch_f64 = e->precision == MOS_FP64 && e->ldk / 4 <= RECON_F64_LDS_KS;
+    const bool batch_bf16 = e->precision == MOS_MIXED && e->ub;
+    const bool batch_recon = batch_f64 || batch_bf16;
     if (batch_recon) {
         const int n_roms = (int)e->roms.size();
         std::vector<std::vector<ReconJob>> jobs(n_roms);
@@ -1894,8 +1886,12 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
                 jobs[t].push_back(ReconJob{P->sb_begin + P->seg[t], off, nsb, 0, P->dT, P->vm, P->sig6});
             }
         }
-        MOS_TRY(recon_f64_jobs(ctx, e->roms.data(), n_roms, jobs.data(), e->jobs, e->jobs_host,
-                               (const double *)e->Mc64, e->ld_slots, (const int32_t *)e->perm, false));
+        if (batch_f64)
+            MOS_TRY(recon_f64_jobs(ctx, e->roms.data(), n_roms, jobs.data(), e->jobs, e->jobs_host,
+                                   (const double *)e->Mc64, e->ld_slots, (const int32_t *)e->perm, false));
+        else
+            MOS_TRY(recon_bf16_jobs(ctx, e->roms.data(), n_roms, jobs.data(), e->jobs, e->jobs_host,
+                                    (const double *)e->Mc64, e->ld_slots, (const int32_t *)e->perm, e->ub));
     }
     std::vector<EngineProblem *> keep, gone;
     for (EngineProblem *P : e->active) {
@@ -1980,10 +1976,6 @@ mos_status reconstruct_problem(mos_engine e, EngineProblem *P) {
                      (const double *const *)e->sigt_tab, (const int32_t *)e->sb_rom, (const double *)e->Mc64,
                      (const int32_t *)e->perm, P->sb_begin, P->n_sb, e->ld_slots, e->ldk, e->n_elem, P->dT,
                      (double *)P->vm, (double *)P->sig6);
-    else if (e->ub)
-        return recon_bf16(e->ctx, e->roms.data(), (int)e->roms.size(), P->seg.data(), (const double *)e->Mc64,
-                          e->ld_slots, (const int32_t *)e->perm, P->sb_begin, P->dT, (float *)P->vm, (float *)P->sig6,
-                          e->ub);
     else
         launch_timed(e->ctx, MOS_K_RECON, k_brecon<float>, grid, dim3(256), 0, st, (const double *const *)e->psi_tab,
                      (const double *const *)e->sigt_tab, (const int32_t *)e->sb_rom, (const double *)e->Mc64,

@@ -188,14 +188,16 @@ struct ReconJob {
 mos_status recon_f64_jobs(mos_ctx ctx, const mos_rom *roms, int n_types, const std::vector<ReconJob> *jobs,
                           ReconJob *dev_jobs, ReconJob *host_jobs, const double *U, int ld, const int32_t *perm,
                           bool fp32_out);
-// BF16-split MFMA reconstruction (FP32 outputs) of the slot blocks
-// [sb_begin, sb_begin + tseg[n_types]) of the FP64 cell-major block U
-// ([ldk][ld]); type t owns [sb_begin + tseg[t], sb_begin + tseg[t + 1]).
-// Needs roms with psi_hi (nks <= RECON_BF16_MAX_KS), else MOS_EINVAL, and a
-// device scratch of recon_bf16_scratch(rom, tseg[n_types]) bytes.
+// BF16-split MFMA reconstruction (FP32 outputs) of the slot blocks listed
+// by the jobs of each type (as for recon_f64_jobs: a job covers slot blocks
+// [sb_first, sb_first + n_sb) of U, its outputs and dT, at sb_off within its
+// type's flattened list).  Needs roms with psi_hi (nks <= RECON_BF16_MAX_KS),
+// else MOS_EINVAL, and a device scratch of recon_bf16_scratch(rom, total
+// slot blocks) bytes; the host table must outlive the upload.
 int64_t recon_bf16_scratch(const mos_rom r, int n_sb);
-mos_status recon_bf16(mos_ctx ctx, const mos_rom *roms, int n_types, const int *tseg, const double *U, int ld,
-                      const int32_t *perm, int sb_begin, double dT, float *vm, float *sig6, void *scratch);
+mos_status recon_bf16_jobs(mos_ctx ctx, const mos_rom *roms, int n_types, const std::vector<ReconJob> *jobs,
+                           ReconJob *dev_jobs, ReconJob *host_jobs, const double *U, int ld, const int32_t *perm,
+                           void *scratch);
 
 // ---- host helpers (api.cpp) ----
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }

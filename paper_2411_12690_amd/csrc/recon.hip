@@ -170,22 +170,38 @@ __global__ __launch_bounds__(512, 1) void k_recon_f64_lds(const double *psi, con
 
 // B fragments of a problem's slot blocks: Ub[sb][ks][lane] holds cell
 // 16 sb + l%16, DoFs 32 ks + 8 (l/16) + 0..7, split into hi and lo.
-__global__ void k_split_u(const double *U, int ld, int sb_begin, int n_sb, int ldk, int nks, bf16x8 *ub_hi,
-                          bf16x8 *ub_lo) {
+// Job of flattened slot block v (jobs in ascending order of sb_off).
+__device__ __forceinline__ const ReconJob &job_of(const ReconJob *jobs, int n_jobs, int v) {
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (jobs[mid].sb_off <= v)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return jobs[lo];
+}
+
+// BF16 hi/lo split of the cell operand of every flattened slot block of the
+// jobs, in the MFMA B-fragment order (k-step, lane, 8 values).
+__global__ void k_split_u(const double *U, int ld, const ReconJob *jobs, int n_jobs, int total, int ldk, int nks,
+                          bf16x8 *ub_hi, bf16x8 *ub_lo) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)n_sb * nks * 64) return;
+    if (i >= (int64_t)total * nks * 64) return;
     const int lane = (int)(i % 64), ks = (int)((i / 64) % nks);
-    const int64_t sb = i / (64 * nks);
-    const size_t slot = (size_t)(sb_begin + sb) * 16 + lane % 16;
+    const int v = (int)(i / (64 * nks));
+    const ReconJob &J = job_of(jobs, n_jobs, v);
+    const size_t slot = (size_t)(J.sb_first + (v - J.sb_off)) * 16 + lane % 16;
     u16x8 h, l;
 #pragma unroll
-    for (int v = 0; v < 8; ++v) {
-        const int k = ks * 32 + 8 * (lane / 16) + v;
+    for (int q = 0; q < 8; ++q) {
+        const int k = ks * 32 + 8 * (lane / 16) + q;
         const double x = k < ldk ? U[(size_t)k * ld + slot] : 0.0;
         uint16_t xh, xl;
         bf16_split(x, xh, xl);
-        h[v] = xh;
-        l[v] = xl;
+        h[q] = xh;
+        l[q] = xl;
     }
     ub_hi[i] = __builtin_bit_cast(bf16x8, h);
     ub_lo[i] = __builtin_bit_cast(bf16x8, l);
@@ -198,13 +214,13 @@ __global__ void k_split_u(const double *U, int ld, int sb_begin, int n_sb, int l
 template <int KSMAX, int CB>
 __global__ __launch_bounds__(256, KSMAX <= 6 ? 2 : 1) void k_recon_bf16(const bf16x8 *psi_hi, const bf16x8 *psi_lo,
                                                        const double *sig_t, const bf16x8 *ub_hi,
-                                                       const bf16x8 *ub_lo, const int32_t *perm, int sb_first,
-                                                       int ub_first, int n_sb, int chunk, int nks, int n_elem,
-                                                       double dT, float *vm, float *sig6) {
+                                                       const bf16x8 *ub_lo, const int32_t *perm,
+                                                       const ReconJob *jobs, int n_jobs, int v_begin, int n_v,
+                                                       int chunk, int nks, int n_elem) {
     __shared__ bf16x8 lds[2][6][KSMAX][64];
     const int eb = blockIdx.x;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-    const int y0 = blockIdx.y * chunk, y1 = min(y0 + chunk, n_sb);
+    const int y0 = v_begin + (int)blockIdx.y * chunk, y1 = min(y0 + chunk, v_begin + n_v);
     {
         const bf16x8 *gh = psi_hi + (size_t)eb * 6 * nks * 64;
         const bf16x8 *gl = psi_lo + (size_t)eb * 6 * nks * 64;
@@ -228,7 +244,7 @@ __global__ __launch_bounds__(256, KSMAX <= 6 ? 2 : 1) void k_recon_bf16(const bf
 #pragma unroll
                 for (int cb = 0; cb < CB; ++cb) {
                     // Past the slice end: reread the last valid block, results unused.
-                    const size_t f = ((size_t)(ub_first + min(base + cb, y1 - 1)) * nks + ks) * 64 + lane;
+                    const size_t f = ((size_t)min(base + cb, y1 - 1) * nks + ks) * 64 + lane;
                     bh[cb] = ub_hi[f];
                     bl[cb] = ub_lo[f];
                 }
@@ -247,7 +263,10 @@ __global__ __launch_bounds__(256, KSMAX <= 6 ? 2 : 1) void k_recon_bf16(const bf
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
             if (base + cb >= y1) continue;
-            const int cell = perm[(size_t)(sb_first + base + cb) * 16 + lane % 16];
+            const ReconJob &J = job_of(jobs, n_jobs, base + cb);
+            const double dT = J.dT;
+            float *vm = static_cast<float *>(J.vm), *sig6 = static_cast<float *>(J.sig6);
+            const int cell = perm[(size_t)(J.sb_first + (base + cb - J.sb_off)) * 16 + lane % 16];
             if (cell < 0) continue;
             const int e0 = eb * 16 + 4 * (lane / 16);
             float vq[4], sq[4][6];
@@ -334,38 +353,56 @@ mos_status recon_f64_jobs(mos_ctx ctx, const mos_rom *roms, int n_types, const s
 
 int64_t recon_bf16_scratch(const mos_rom r, int n_sb) { return (int64_t)n_sb * r->nks * 64 * 2 * 16; }
 
-mos_status recon_bf16(mos_ctx ctx, const mos_rom *roms, int n_types, const int *tseg, const double *U, int ld,
-                      const int32_t *perm, int sb_begin, double dT, float *vm, float *sig6, void *scratch) {
+mos_status recon_bf16_jobs(mos_ctx ctx, const mos_rom *roms, int n_types, const std::vector<ReconJob> *jobs,
+                           ReconJob *dev_jobs, ReconJob *host_jobs, const double *U, int ld, const int32_t *perm,
+                           void *scratch) {
     if (n_types < 1 || n_types > MAX_TYPES) return MOS_EINVAL;
     const mos_rom r = roms[0];
     for (int t = 0; t < n_types; ++t)
         if (!roms[t]->psi_hi || roms[t]->nks != r->nks || roms[t]->n_eblk != r->n_eblk) return MOS_EINVAL;
-    const int total = tseg[n_types];
-    if (total <= 0) return MOS_OK;
     hipStream_t st = ctx->stream;
+    // One table for all types, flattened slot blocks numbered type-major:
+    // type t's jobs at [first[t], first[t + 1]), its blocks at
+    // [vbase[t], vbase[t + 1]).
+    std::vector<int> first(n_types + 1, 0), vbase(n_types + 1, 0);
+    for (int t = 0; t < n_types; ++t) {
+        first[t + 1] = first[t] + (int)jobs[t].size();
+        const int nt = jobs[t].empty() ? 0 : jobs[t].back().sb_off + jobs[t].back().n_sb;
+        vbase[t + 1] = vbase[t] + nt;
+    }
+    const int total = vbase[n_types];
+    if (total == 0) return MOS_OK;
+    for (int t = 0; t < n_types; ++t)
+        for (size_t i = 0; i < jobs[t].size(); ++i) {
+            host_jobs[first[t] + i] = jobs[t][i];
+            host_jobs[first[t] + i].sb_off += vbase[t];
+        }
+    MOS_HIP(hipMemcpyAsync(dev_jobs, host_jobs, first[n_types] * sizeof(ReconJob), hipMemcpyHostToDevice, st));
     bf16x8 *ub_hi = (bf16x8 *)scratch, *ub_lo = ub_hi + (size_t)total * r->nks * 64;
     const int64_t nfrag = (int64_t)total * r->nks * 64;
-    hipLaunchKernelGGL(k_split_u, dim3(ceil_div(nfrag, 256)), dim3(256), 0, st, U, ld, sb_begin, total, r->ldk,
-                       r->nks, ub_hi, ub_lo);
+    hipLaunchKernelGGL(k_split_u, dim3(ceil_div(nfrag, 256)), dim3(256), 0, st, U, ld, (const ReconJob *)dev_jobs,
+                       first[n_types], total, r->ldk, r->nks, ub_hi, ub_lo);
     MOS_LAUNCH_CHECK();
     for (int t = 0; t < n_types; ++t) {
-        const int n_sb = tseg[t + 1] - tseg[t];
-        if (n_sb <= 0) continue;
-        // Slices of the slot range give >= ~2048 workgroups for large
-        // problems while each slice still streams >= 32 slot blocks per
+        const int n_v = vbase[t + 1] - vbase[t];
+        if (n_v <= 0) continue;
+        // Slices of the type's blocks give >= ~2048 workgroups for large
+        // batches while each slice still streams >= 32 slot blocks per
         // staged block of Psi.
-        const int ny = std::max(1, std::min(n_sb / 32, ceil_div(2048, r->n_eblk)));
-        const int chunk = ceil_div(n_sb, ny);
-        const dim3 grid(r->n_eblk, ceil_div(n_sb, chunk));
+        const int ny = std::max(1, std::min(n_v / 32, ceil_div(2048, r->n_eblk)));
+        const int chunk = ceil_div(n_v, ny);
+        const dim3 grid(r->n_eblk, ceil_div(n_v, chunk));
         const bf16x8 *ph = (const bf16x8 *)roms[t]->psi_hi, *pl = (const bf16x8 *)roms[t]->psi_lo;
+        const ReconJob *dj = dev_jobs + first[t];
+        const int nj = first[t + 1] - first[t];
         if (r->nks <= 6)
             launch_timed(ctx, MOS_K_RECON, k_recon_bf16<6, 4>, grid, dim3(256), 0, st, ph, pl,
-                         (const double *)roms[t]->sig_t, (const bf16x8 *)ub_hi, (const bf16x8 *)ub_lo, perm,
-                         sb_begin + tseg[t], tseg[t], n_sb, chunk, r->nks, r->n_elem, dT, vm, sig6);
+                         (const double *)roms[t]->sig_t, (const bf16x8 *)ub_hi, (const bf16x8 *)ub_lo, perm, dj, nj,
+                         vbase[t], n_v, chunk, r->nks, r->n_elem);
         else
             launch_timed(ctx, MOS_K_RECON, k_recon_bf16<RECON_BF16_MAX_KS, 2>, grid, dim3(256), 0, st, ph, pl,
-                         (const double *)roms[t]->sig_t, (const bf16x8 *)ub_hi, (const bf16x8 *)ub_lo, perm,
-                         sb_begin + tseg[t], tseg[t], n_sb, chunk, r->nks, r->n_elem, dT, vm, sig6);
+                         (const double *)roms[t]->sig_t, (const bf16x8 *)ub_hi, (const bf16x8 *)ub_lo, perm, dj, nj,
+                         vbase[t], n_v, chunk, r->nks, r->n_elem);
         MOS_LAUNCH_CHECK();
     }
     return MOS_OK;
@@ -395,12 +432,19 @@ mos_status reconstruct(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void 
     void *v = (outputs & MOS_OUT_VM) ? vm : nullptr;
     void *g = (outputs & MOS_OUT_SIGMA6) ? sigma6 : nullptr;
     if (s->precision == MOS_MIXED && s->roms[0]->psi_hi) {
-        std::vector<int> tseg(s->n_types + 1);
-        for (int t = 0; t <= s->n_types; ++t) tseg[t] = s->seg[t] / 16;
+        std::vector<std::vector<ReconJob>> jobs(s->n_types);
+        for (int t = 0; t < s->n_types; ++t) {
+            const int nsb = (s->seg[t + 1] - s->seg[t]) / 16;
+            if (nsb > 0) jobs[t].push_back(ReconJob{s->seg[t] / 16, 0, nsb, 0, s->delta_T, v, g});
+        }
         void *scratch = nullptr;
         MOS_TRY(tmp.alloc((size_t)recon_bf16_scratch(s->roms[0], s->n_pc / 16), &scratch));
-        MOS_TRY(recon_bf16(ctx, s->roms.data(), s->n_types, tseg.data(), U, s->n_pc, s->perm, 0, s->delta_T,
-                           (float *)v, (float *)g, scratch));
+        ReconJob *dj = nullptr;
+        MOS_TRY(tmp.alloc_n(MAX_TYPES, &dj));
+        std::vector<ReconJob> hj(MAX_TYPES);
+        MOS_TRY(recon_bf16_jobs(ctx, s->roms.data(), s->n_types, jobs.data(), dj, hj.data(), U, s->n_pc, s->perm,
+                                scratch));
+        MOS_HIP(hipStreamSynchronize(st));  // the host job table is a local
     } else if (s->ldk / 4 <= RECON_F64_LDS_KS) {
         std::vector<std::vector<ReconJob>> jobs(s->n_types);
         for (int t = 0; t < s->n_types; ++t) {
