@@ -30,6 +30,7 @@ namespace mos {
 namespace {
 
 constexpr int DB = 256;       // DoFs per DoF block
+constexpr int N_XCD = 8;      // accelerator dies that workgroups are dealt to in turn
 constexpr int DOF_ALIGN = 3 * DB;
 
 template <class T>
@@ -664,19 +665,26 @@ template <class T, int NT>
 __global__ __launch_bounds__(NT) void k_cgstep(const T *Y, const int32_t *inc, const uint8_t *cmask, const T *dinv,
                                                T *x, T *r, T *p, T *s, T *Mc, int ld_slots, const int32_t *blk_prob,
                                                ProbState *ps, double *pg, double *pr, const double *pdel, int epoch,
-                                               int cap_blk) {
+                                               int cap_blk, int n_blk) {
     constexpr int DPT = DB / NT;
     __shared__ int go, it_sh;
     __shared__ double step[2];
     __shared__ double red[3][NT];
-    const int64_t d0 = (int64_t)blockIdx.x * DB + threadIdx.x;
+    // Workgroups are dealt to the XCDs in turn; DoF block `blk` is taken so
+    // that each XCD gets one contiguous run of blocks, and the cell-layout
+    // lines that neighbouring blocks gather from and scatter to meet in one
+    // L2 instead of several.
+    const int per = (n_blk + N_XCD - 1) / N_XCD;
+    const int blk = (int)(blockIdx.x % N_XCD) * per + (int)(blockIdx.x / N_XCD);
+    if (blk >= n_blk) return;
+    const int64_t d0 = (int64_t)blk * DB + threadIdx.x;
     // Only the incidence is requested before the gate resolves: blocks of
     // problems that have stopped (converged, or between refinement sweeps)
     // must not spend bandwidth on their operands.
     int4 iv[DPT];
 #pragma unroll
     for (int j = 0; j < DPT; ++j) iv[j] = incidence(inc, d0 + j * NT);
-    const int pb = blk_prob[blockIdx.x];
+    const int pb = blk_prob[blk];
     if (threadIdx.x == 0) {
         int g = 0;
         if (pb >= 0) {
@@ -700,7 +708,7 @@ __global__ __launch_bounds__(NT) void k_cgstep(const T *Y, const int32_t *inc, c
         // bits in each); the problem's first workgroup publishes the state.
         ProbState &S = ps[pb];
         const CgStep o = cg_scalars_block<NT>(S, it, pg + rd_slot, pr + rd_slot, pdel, red);
-        if (threadIdx.x == 0 && (int)blockIdx.x == S.blk_begin) cg_publish(S, it, o);
+        if (threadIdx.x == 0 && blk == S.blk_begin) cg_publish(S, it, o);
         if (o.stop) return;
         if (threadIdx.x == 0) {
             step[0] = o.alpha;
@@ -743,8 +751,8 @@ __global__ __launch_bounds__(NT) void k_cgstep(const T *Y, const int32_t *inc, c
     double gs, rs;
     block_partials<NT>(g, r2, gs, rs);
     if (threadIdx.x == 0) {
-        pg[wr_slot + blockIdx.x] = gs;
-        pr[wr_slot + blockIdx.x] = rs;
+        pg[wr_slot + blk] = gs;
+        pr[wr_slot + blk] = rs;
     }
 }
 
@@ -1621,16 +1629,17 @@ template <class T>
 void cgstep_launch(mos_engine e, int hw_blk, T *const *V) {
     hipStream_t st = e->ctx->stream;
     const bool wide = e->update_width ? e->update_width == 256 : hw_blk <= CG_WIDE_MAX_BLK;
+    const dim3 grid((unsigned)(ceil_div(hw_blk, N_XCD) * N_XCD));
     if (wide)
-        launch_timed(e->ctx, MOS_K_PCG_UPDATE, k_cgstep<T, 256>, dim3(hw_blk), dim3(256), 0, st, (const T *)e->Yi,
+        launch_timed(e->ctx, MOS_K_PCG_UPDATE, k_cgstep<T, 256>, grid, dim3(256), 0, st, (const T *)e->Yi,
                      (const int32_t *)e->inc, (const uint8_t *)e->cmask, (const T *)V[VDINV], V[VX], V[VR], V[VP],
                      V[VS], (T *)e->Mc, e->ld_slots, (const int32_t *)e->blk_prob, e->ps, e->pg, e->pr,
-                     (const double *)e->pdel, e->epoch, e->cap_blk);
+                     (const double *)e->pdel, e->epoch, e->cap_blk, hw_blk);
     else
-        launch_timed(e->ctx, MOS_K_PCG_UPDATE, k_cgstep<T, 128>, dim3(hw_blk), dim3(128), 0, st, (const T *)e->Yi,
+        launch_timed(e->ctx, MOS_K_PCG_UPDATE, k_cgstep<T, 128>, grid, dim3(128), 0, st, (const T *)e->Yi,
                      (const int32_t *)e->inc, (const uint8_t *)e->cmask, (const T *)V[VDINV], V[VX], V[VR], V[VP],
                      V[VS], (T *)e->Mc, e->ld_slots, (const int32_t *)e->blk_prob, e->ps, e->pg, e->pr,
-                     (const double *)e->pdel, e->epoch, e->cap_blk);
+                     (const double *)e->pdel, e->epoch, e->cap_blk, hw_blk);
 }
 
 // Pick the rows-GEMM candidate (operand path, work split) for `n_sb` active
