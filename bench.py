@@ -2,15 +2,19 @@
 """Benchmark of the MORE-Stress hot path on one MI355X.
 
 Default (--mode batch): one step = the global stage of a batch of B (default
-32) independent 16x16 TSV arrays (cells 15x15x50 um meshed 16x16x32, cubic face
-interpolation, n = 168, dT = -250 K, bottom clamped, FP64), each array drawing
+128) independent 16x16 TSV arrays (cells 15x15x50 um meshed 16x16x32, cubic
+face interpolation, n = 168, dT = -250 K, bottom clamped), each array drawing
 its via diameter from {4, 5, 6} um with its own seed.  The batch is solved
-together by the engine (mos_engine_*: reduced assembly, lifting, pipelined
-PCG, FP64 refinement) and every array's per-cell centroid von Mises stress is
-reconstructed into its own device buffer.  The reduced order models of the
-three cell types are built once before the clock (the one-shot local stage,
-reported as local_stage_ms, as the paper reports it apart from the global
-stage).  Throughput counts every cell of the batch; latency is per array.
+together by the engine (mos_engine_*: reduced assembly, lifting,
+Chronopoulos-Gear PCG, FP64 refinement) and every array's per-cell centroid
+von Mises stress is reconstructed into its own device buffer.  The record is
+the plain FP64 path; the mixed-precision path (FP32 PCG, FP64 refinement,
+BF16-split reconstruction) is measured the same way and reported beside it
+(mixed_side_by_side), with its von Mises error against the oracle.  The
+reduced order models of the three cell types are built once before the clock
+(the one-shot local stage, reported as local_stage_ms, as the paper reports
+it apart from the global stage).  Throughput counts every cell of the batch;
+latency is per array.
 
 --mode serve: a Poisson stream of requests (mean 200 /s; N ~ U{4..48},
 pitch ~ U{10,15,20} um, dT ~ U[-300,-150] K, 10% dummy cells) served with
@@ -119,9 +123,11 @@ def cpu_baseline(case):
     return out, vm
 
 
-def batch_mode(args, mos, torch, np, W):
+def batch_leg(args, mos, torch, np, W, precision, with_cpu=False, vm_ref=None):
+    """One precision of the batch workload; returns its JSON record and the
+    oracle's von Mises field of the first array (when it was computed)."""
     B = args.batch
-    mixed = args.precision == "mixed"
+    mixed = precision == "mixed"
     cases = [W.case_c2(args.seed + i) for i in range(B)]
     diam = [4.0, 5.0, 6.0]
     spec0 = cases[0].specs[0]
@@ -218,7 +224,7 @@ def batch_mode(args, mos, torch, np, W):
     achieved = work_per_launch / avg_s / (1e12 if unit == "TFLOP/s" else 1e9)
     roofline = {"bound": bound, "achieved": round(achieved, 4), "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 5),
-                "traffic": recorded_traffic(name, f"batch{B}_c2", args.precision), "traffic_unit": "bytes/launch",
+                "traffic": recorded_traffic(name, f"batch{B}_c2", precision), "traffic_unit": "bytes/launch",
                 "kernel": name,
                 "avg_launch_us": round(avg_s * 1e6, 3), "timed_launches": int(launches), "launches": int(seen),
                 "timed_every": TIME_EVERY, "work_per_launch": round(work_per_launch, 1), "work_note": note,
@@ -239,8 +245,9 @@ def batch_mode(args, mos, torch, np, W):
 
     cpu = None
     err = None
-    if not args.no_cpu_baseline:
+    if with_cpu and not args.no_cpu_baseline:
         cpu, vm_ref = cpu_baseline(cases[0])
+    if vm_ref is not None:
         step()
         err = float(np.abs(vms[0].double().cpu().numpy() - vm_ref).max() / np.abs(vm_ref).max())
 
@@ -262,7 +269,7 @@ def batch_mode(args, mos, torch, np, W):
                    "cell_um": [spec0.pitch_x, spec0.pitch_y, spec0.height], "cell_mesh": list(spec0.mesh),
                    "tsv_diameter_um": "per array from {4,5,6}", "interp": list(spec0.interp), "n": n,
                    "reduced_dofs_per_array": int(n_dofs), "delta_T": -250.0, "bc": "bottom clamped",
-                   "precision": args.precision, "seed": args.seed, "pcg_chunk": args.chunk,
+                   "precision": precision, "seed": args.seed, "pcg_chunk": args.chunk,
                    "gemm_split": args.gemm_split if args.gemm_split is not None else "tuned"},
         "p50_ms": round(float(np.percentile(lat, 50)), 4),
         "p99_ms": round(float(np.percentile(lat, 99)), 4),
@@ -279,6 +286,27 @@ def batch_mode(args, mos, torch, np, W):
         "max_rel_err_vm_vs_oracle": err,
     }
     eng.close()
+    return out, vm_ref
+
+
+def batch_mode(args, mos, torch, np, W):
+    """The batch workload in one precision, or (default) the plain FP64 path
+    as the record with the mixed-precision path measured beside it."""
+    if args.precision is not None:
+        out, _ = batch_leg(args, mos, torch, np, W, args.precision, with_cpu=True)
+        print(json.dumps(out))
+        return
+    out, vm_ref = batch_leg(args, mos, torch, np, W, "fp64", with_cpu=True)
+    mx, _ = batch_leg(args, mos, torch, np, W, "mixed", vm_ref=vm_ref)
+    r = mx["roofline"] or {}
+    out["mixed_side_by_side"] = {
+        "value": mx["value"], "unit": mx["unit"], "ms_per_step": mx["ms_per_step"], "dtype": mx["dtype"],
+        "p50_ms": mx["p50_ms"], "p99_ms": mx["p99_ms"], "single_array_ms": mx["single_array_ms"],
+        "pcg_iters_mean": mx["pcg_iters_mean"], "refinement_sweeps_mean": mx["refinement_sweeps_mean"],
+        "max_rel_err_vm_vs_oracle": mx["max_rel_err_vm_vs_oracle"],
+        "roofline": {k: r.get(k) for k in ("kernel", "bound", "achieved", "peak", "unit", "frac", "traffic",
+                                           "avg_launch_us", "kernels_ms_per_step")},
+    }
     print(json.dumps(out))
 
 
@@ -527,8 +555,10 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--mode", choices=["batch", "serve", "single", "calib"], default="batch")
     ap.add_argument("--workload", choices=["c3", "c5"], default="c3")
-    ap.add_argument("--batch", type=int, default=32)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--batch", type=int, default=128)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
+                    help="batch mode: run this precision only (default: the FP64 record with the "
+                         "mixed-precision path measured beside it)")
     ap.add_argument("--gemm-split", type=int, default=None,
                     help="fixed slot blocks per wave of the cell GEMM (default: tuned online)")
     ap.add_argument("--cell-gemm", type=int, choices=[0, 1, 2, 3], default=None,
