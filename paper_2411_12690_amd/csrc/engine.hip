@@ -200,7 +200,8 @@ __global__ __launch_bounds__(256) void k_cg_scalars(ProbState *ps, const double 
                                                     const double *pdel, int epoch, int cap_blk) {
     __shared__ double red[3][CG_LW];
     ProbState &S = ps[blockIdx.x];
-    if (!S.active || S.done || S.fused) return;  // uniform over the workgroup
+    const int active = S.active, done = S.done, fused = S.fused;  // one round trip
+    if (!((active != 0) & (done == 0) & (fused == 0))) return;     // uniform over the workgroup
     const int it = epoch - S.start_epoch;
     const size_t slot = (size_t)(it & 1) * cap_blk;
     const CgStep o = cg_scalars_block<CG_LW>(S, it, pg + slot, pr + slot, pdel, red);
@@ -338,11 +339,13 @@ __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, c
     auto next_live = [&](int sl) {
         for (; sl < s_end; ++sl) {
             const int sb = sb_base + sl;
-            if (sb_rom[sb] < 0) continue;
+            const int rom = sb_rom[sb], owner = sb_prob[sb];
+            if (rom < 0) continue;
             if (gate == 1) {
-                const ProbState &S = ps[sb_prob[sb]];
-                if (!S.active || S.done) continue;
-            } else if (gate == 2 && !selected(sel, sb_prob[sb])) {
+                const ProbState &S = ps[owner];
+                const int active = S.active, done = S.done;  // one round trip
+                if (!((active != 0) & (done == 0))) continue;
+            } else if (gate == 2 && !selected(sel, owner)) {
                 continue;
             }
             break;
@@ -457,11 +460,13 @@ __global__ __launch_bounds__(704) void k_bgemm_wg(const void *const *kr_tab, con
     auto next_live = [&](int sl) {
         for (; sl < s_end; ++sl) {
             const int sb = sb_base + sl;
-            if (sb_rom[sb] < 0) continue;
+            const int rom = sb_rom[sb], owner = sb_prob[sb];
+            if (rom < 0) continue;
             if (gate == 1) {
-                const ProbState &S = ps[sb_prob[sb]];
-                if (!S.active || S.done) continue;
-            } else if (gate == 2 && !selected(sel, sb_prob[sb])) {
+                const ProbState &S = ps[owner];
+                const int active = S.active, done = S.done;  // one round trip
+                if (!((active != 0) & (done == 0))) continue;
+            } else if (gate == 2 && !selected(sel, owner)) {
                 continue;
             }
             break;
@@ -688,11 +693,15 @@ __global__ __launch_bounds__(NT) void k_cgstep(const T *Y, const int32_t *inc, c
     if (threadIdx.x == 0) {
         int g = 0;
         if (pb >= 0) {
+            // Every field read unconditionally (no short-circuit), so the
+            // state arrives in one round trip rather than one per field.
             const ProbState &S = ps[pb];
-            g = S.active && !S.done ? (S.fused ? 2 : 1) : 0;
-            step[0] = S.a_cur;
-            step[1] = S.b_cur;
-            it_sh = epoch - S.start_epoch;
+            const int active = S.active, done = S.done, fused = S.fused, start = S.start_epoch;
+            const double a_cur = S.a_cur, b_cur = S.b_cur;
+            g = ((active != 0) & (done == 0)) ? 1 + (fused != 0) : 0;
+            step[0] = a_cur;
+            step[1] = b_cur;
+            it_sh = epoch - start;
         }
         go = g;
     }

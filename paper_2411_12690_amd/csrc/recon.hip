@@ -124,12 +124,18 @@ __global__ __launch_bounds__(512, 1) void k_recon_f64_lds(const double *psi, con
         // u is streamed one k-step at a time (a few loads in flight through
         // the partial unroll); the six accumulators stay in registers.
         if (EXACT) {
-#pragma unroll 4
+            // All of the block's u requested at once (straight-line, so each
+            // MFMA waits only for its own operand); the scheduling barriers
+            // keep the LDS reads of Psi within a few k-steps of their use.
+            double b[KS];
+#pragma unroll
+            for (int k = 0; k < KS; ++k) b[k] = bp[(size_t)(4 * k) * ld];
+#pragma unroll
             for (int k = 0; k < KS; ++k) {
-                const double b = bp[(size_t)(4 * k) * ld];
 #pragma unroll
                 for (int c = 0; c < 6; ++c)
-                    acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[(c * ldk + 4 * k) * 16], b, acc[c], 0, 0, 0);
+                    acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[(c * ldk + 4 * k) * 16], b[k], acc[c], 0, 0, 0);
+                if (k % 2 == 1) __builtin_amdgcn_sched_barrier(0);
             }
         } else {
             for (int k = 0; k < ks; ++k) {
