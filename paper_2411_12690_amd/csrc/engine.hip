@@ -287,6 +287,43 @@ __global__ __launch_bounds__(256) void k_bgemm(const void *const *kr_tab, const 
     }
 }
 
+// Live slot blocks of the run [s_begin, s_end) (at most 64): each lane
+// checks one (in use, and iterating with gate 1 or selected with gate 2) and
+// the wave's ballot gives the mask, bit i for slot block s_begin + i; every
+// wave of a workgroup computes the same mask.  Lane i keeps that block's
+// cell type in *rom_lane.  Two dependent loads for the whole run, instead
+// of a chain of scalar loads before every block.
+__device__ __forceinline__ uint64_t run_mask(const int32_t *sb_rom, const int32_t *sb_prob, const ProbState *ps,
+                                            int gate, const ProbSel &sel, int sb_base, int s_begin, int s_end,
+                                            int *rom_lane) {
+    const int lane = threadIdx.x % 64;
+    const int sl = s_begin + lane;
+    bool live = false;
+    int rom = -1;
+    if (sl < s_end) {
+        rom = sb_rom[sb_base + sl];
+        const int owner = sb_prob[sb_base + sl];
+        live = rom >= 0;
+        if (live && gate == 1) {
+            const ProbState &S = ps[owner];
+            const int active = S.active, done = S.done;
+            live = (active != 0) & (done == 0);
+        } else if (live && gate == 2) {
+            live = selected(sel, owner);
+        }
+    }
+    *rom_lane = rom;
+    return __ballot(live);
+}
+
+// First live slot block at or after sl given the run's mask (s_end if none).
+__device__ __forceinline__ int next_in_mask(uint64_t mask, int s_begin, int s_end, int sl) {
+    const int off = sl - s_begin;
+    if (off >= 64) return s_end;
+    const uint64_t m = mask & (~0ull << off);
+    return m ? s_begin + __builtin_ctzll(m) : s_end;
+}
+
 // (u, A u) over one 16x16 output tile from operand values already loaded
 // (t[q] = the cell operand at output position q of the lane).
 template <class T, class V4>
@@ -334,24 +371,11 @@ __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, c
     const int s_begin = run * spw;
     if (s_begin >= n_sb) return;
     const int s_end = min(s_begin + spw, n_sb);
-    // First slot block at or after sl that is in use and whose problem
-    // iterates (s_end if none).
-    auto next_live = [&](int sl) {
-        for (; sl < s_end; ++sl) {
-            const int sb = sb_base + sl;
-            const int rom = sb_rom[sb], owner = sb_prob[sb];
-            if (rom < 0) continue;
-            if (gate == 1) {
-                const ProbState &S = ps[owner];
-                const int active = S.active, done = S.done;  // one round trip
-                if (!((active != 0) & (done == 0))) continue;
-            } else if (gate == 2 && !selected(sel, owner)) {
-                continue;
-            }
-            break;
-        }
-        return sl;
-    };
+    // Live slot blocks of the run, decided once.
+    int rom_lane;
+    const uint64_t live = run_mask(sb_rom, sb_prob, ps, gate, sel, sb_base, s_begin, s_end, &rom_lane);
+    auto next_live = [&](int sl) { return next_in_mask(live, s_begin, s_end, sl); };
+    auto rom_of = [&](int sl) { return __builtin_amdgcn_readlane(rom_lane, sl - s_begin); };
     int sl = next_live(s_begin);
     if (sl >= s_end) return;
     // Per-type K_r bases up front, so a slot block's operand loads wait on
@@ -369,7 +393,7 @@ __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, c
     int cur = -1;
     while (sl < s_end) {
         const int sb = sb_base + sl;
-        const int rom = sb_rom[sb];
+        const int rom = rom_of(sl);
         const int col = sb * 16 + lane % 16;
         // The epilogue's operand values, requested before this block's
         // chain (and before the next block's loads) so they are not waited
@@ -455,24 +479,11 @@ __global__ __launch_bounds__(704) void k_bgemm_wg(const void *const *kr_tab, con
     const int s_begin = (int)blockIdx.x * spw;
     if (s_begin >= n_sb) return;
     const int s_end = min(s_begin + spw, n_sb);
-    // First slot block at or after sl that is in use and whose problem
-    // iterates (s_end if none); the same for every wave of the workgroup.
-    auto next_live = [&](int sl) {
-        for (; sl < s_end; ++sl) {
-            const int sb = sb_base + sl;
-            const int rom = sb_rom[sb], owner = sb_prob[sb];
-            if (rom < 0) continue;
-            if (gate == 1) {
-                const ProbState &S = ps[owner];
-                const int active = S.active, done = S.done;  // one round trip
-                if (!((active != 0) & (done == 0))) continue;
-            } else if (gate == 2 && !selected(sel, owner)) {
-                continue;
-            }
-            break;
-        }
-        return sl;
-    };
+    // Live slot blocks of the run, decided once.
+    int rom_lane;
+    const uint64_t live = run_mask(sb_rom, sb_prob, ps, gate, sel, sb_base, s_begin, s_end, &rom_lane);
+    auto next_live = [&](int sl) { return next_in_mask(live, s_begin, s_end, sl); };
+    auto rom_of = [&](int sl) { return __builtin_amdgcn_readlane(rom_lane, sl - s_begin); };
     int sl = next_live(s_begin);
     if (sl >= s_end) return;
     // Tile chunk c of this thread: row c / CPR, cells (c % CPR) * EPC.
@@ -503,7 +514,7 @@ __global__ __launch_bounds__(704) void k_bgemm_wg(const void *const *kr_tab, con
     int buf = 0;
     while (sl < s_end) {
         const int sb = sb_base + sl;
-        const int rom = sb_rom[sb];
+        const int rom = rom_of(sl);
         if (rom != cur) {
             const T *ap = kr[rom] + (size_t)(lane / 16) * ldk + rb * 16 + lane % 16;
 #pragma unroll
