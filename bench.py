@@ -146,7 +146,8 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False, vm_ref=None):
     n_dofs = 3 * n_nodes
     n_dofs_pad = -(-n_dofs // 768) * 768
     eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=int(B * (n_dofs_pad * 140 + n_cells * 16 * 176 * 34)
-                                                             * 1.3) + (64 << 20), gemm=args.cell_gemm)
+                                                             * 1.3) + (64 << 20), gemm=args.cell_gemm,
+                     precond=args.precond)
     if args.gemm_split is not None:
         eng.option(mos.MOS_OPT_GEMM_SPLIT, args.gemm_split)
     vms = [torch.empty((n_cells, n_elem), dtype=torch.float32 if mixed else torch.float64, device="cuda")
@@ -349,7 +350,7 @@ def single_mode(args, mos, torch, np, W):
         mixed = prec == "mixed"
         w = 4 if mixed else 8
         budget = int((n_dofs_pad * 160 + n_cells * 16 * 176 * (2 * w + 24)) * 1.3) + (256 << 20)
-        eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=budget, gemm=args.cell_gemm)
+        eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=budget, gemm=args.cell_gemm, precond=args.precond)
         if args.gemm_split is not None:
             eng.option(mos.MOS_OPT_GEMM_SPLIT, args.gemm_split)
         vm = torch.empty((n_cells, n_elem), dtype=torch.float32 if mixed else torch.float64, device="cuda")
@@ -468,7 +469,7 @@ def serve_mode(args, mos, torch, np, W):
     torch.cuda.synchronize()
     local_ms = (time.perf_counter() - t0) * 1e3
     n_elem = roms[0].query(mos.MOS_Q_CELL_ELEMS)
-    eng = mos.Engine(ctx, roms, mixed=True, device_bytes=int(args.budget_gb * (1 << 30)))
+    eng = mos.Engine(ctx, roms, mixed=True, device_bytes=int(args.budget_gb * (1 << 30)), precond=args.precond)
     cases = [W.request_case(r) for r in reqs]
     types = []
     for r, c in zip(reqs, cases):
@@ -564,6 +565,9 @@ def main():
     ap.add_argument("--cell-gemm", type=int, choices=[0, 1, 2, 3], default=None,
                     help="cell GEMM variant (0 rows with the operand path tuned, 1 tiles, 2 K_r-stationary rows, "
                          "3 rows with the operand tile in LDS; "
+                         "default: the engine's)")
+    ap.add_argument("--precond", type=int, choices=[0, 1], default=None,
+                    help="PCG preconditioner (0 Jacobi, 1 Jacobi plus the aggregate coarse correction; "
                          "default: the engine's)")
     ap.add_argument("--chunk", type=int, default=16)
     ap.add_argument("--requests", type=int, default=2000)

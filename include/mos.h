@@ -244,7 +244,16 @@ mos_status mos_engine_result(mos_engine e, int64_t ticket, int32_t *status, doub
  * while the iterating DoF blocks fit on the chip at once and 128 beyond.
  * Both compute every sum in the same order, so results do not depend on it;
  * it may be changed at any time. */
-enum { MOS_OPT_CELL_GEMM = 1, MOS_OPT_GEMM_SPLIT = 2, MOS_OPT_UPDATE_WIDTH = 3 };
+/* MOS_OPT_PRECOND selects the PCG preconditioner of problems submitted
+ * afterwards: 1 (the default where it applies) = Jacobi plus a coarse
+ * correction on aggregates of 2x2 cells, M^-1 = D^-1 + sum_a Z_a B_a^-1 Z_a^T
+ * with Z_a the aggregate's six rigid-body modes on its free DoFs and
+ * B_a = Z_a^T A Z_a (symmetric positive definite, so PCG converges to the
+ * same solution in fewer iterations); 0 = Jacobi alone.  1 needs cells of at
+ * most 256 reduced DoFs and at most 1024 nodes in a box of 8x2 cells
+ * (MOS_EINVAL otherwise; engines whose cells exceed this start with 0).
+ * Set it before the first submission. */
+enum { MOS_OPT_CELL_GEMM = 1, MOS_OPT_GEMM_SPLIT = 2, MOS_OPT_UPDATE_WIDTH = 3, MOS_OPT_PRECOND = 4 };
 mos_status mos_engine_option(mos_engine e, int option, int64_t value);
 
 /* Problems admitted and queued, and the arena capacities. */

@@ -492,8 +492,12 @@ mos_status mos_engine_create(mos_ctx ctx, const mos_rom *roms, int32_t n_roms, m
     }
     // Split the budget between DoF arrays and cell slots (~100 DoFs per cell).
     const double w = precision == MOS_MIXED ? 4.0 : 8.0;
-    const double per_dof = 5 * w + 4 * 8 + 1 + 16.0 / 3 + 4 * 8.0 / 256 + 4.0 / 256;
-    const double per_slot = e->ldk * (2 * w + 16) + 4 + 8.0 / 16 + e->ldk / 16 * 8.0 / 16 +
+    // Per DoF: vectors, FP64 vectors, constraint mask, incidence, packed
+    // coordinates, block tables (partials, owners, coarse inverses and
+    // coefficients of up to 4 aggregates per 256 DoFs).
+    const double per_dof = 5 * w + 4 * 8 + 1 + 16.0 / 3 + 4.0 / 3 + 4 * 8.0 / 256 + 4.0 / 256 +
+                           (4 * 42 * 8.0 + 4) / 256;
+    const double per_slot = e->ldk * (2 * w + 16) + 8 + 8.0 / 16 + e->ldk / 16 * 8.0 / 16 +
                             (precision == MOS_MIXED ? (double)recon_bf16_scratch(roms[0], 1) / 16 : 0.0);
     const double units = (double)device_bytes / (100 * per_dof + per_slot);
     const int64_t dofs = (int64_t)(units * 100), slots = (int64_t)units;
@@ -578,6 +582,13 @@ mos_status mos_engine_option(mos_engine e, int option, int64_t value) {
         e->gemm_paths = value == 2 ? 1 : value == 3 ? 2 : 3;
         e->tuner.configure(e->gemm_paths, e->gemm_split);
         return MOS_OK;
+    }
+    if (option == MOS_OPT_PRECOND && (value == 0 || value == 1)) {
+        if (!e->active.empty() || !e->queue.empty()) {
+            set_error("engine options must be set before the first submission");
+            return MOS_EBUSY;
+        }
+        return engine_set_precond(e, (int)value);
     }
     if (option == MOS_OPT_UPDATE_WIDTH && (value == 0 || value == 128 || value == 256)) {
         e->update_width = (int)value;

@@ -47,10 +47,17 @@ struct PidList {
 };
 // Static parameters of an admitted problem (device table by problem id).
 struct ProbParams {
-    int64_t d0, n_dofs, nd_pad, bot_end, top_begin;
+    int64_t d0, n_dofs, nd_pad;
     double dT;
+    double h[3];                    // node spacing over pitch_x per axis (coarse-correction coordinates)
     Lattice lat;
+    AggLayout agg;                  // internal node order (boxes of cells)
     int32_t blk_begin, n_blk, sb_begin, n_sb, nrb, fused;
+    int32_t clamp;                  // MOS_BC_CLAMP_* of the descriptor
+    int32_t n_agg;                  // boxes of the internal node order
+    int32_t box_begin;              // first box id (two-level preconditioner), else -1
+    int32_t part_begin, n_part;     // the problem's (r,u), (r,r) partial slots: its boxes or DoF blocks
+    int32_t pad;
 };
 // Parameters of a problem's current refinement sweep (device table by id).
 struct SweepParams {
@@ -126,6 +133,9 @@ struct mos_engine_s {
     int gemm_paths = 3;                       // operand paths of the rows variant open to the tuner
     int gemm_split = 0;                       // fixed work split (0: tuned)
     int update_width = 0;                     // threads per update workgroup (0: by batch size)
+    int precond = 1;                          // 0 Jacobi, 1 Jacobi + aggregate coarse correction
+    int box_cells[2] = {6, 2};                // cells per box of the internal node order (x, y)
+    int box_nt = 0;                           // threads per box workgroup (two-level update)
     mos::GemmTuner tuner;                     // operand path and work split of the rows variant
     mos::DeviceArena mem;
     // device arrays
@@ -140,6 +150,13 @@ struct mos_engine_s {
     double *pg = nullptr, *pd = nullptr, *pr = nullptr, *pr64 = nullptr;  // [cap_blk]
     int32_t *sb_rom = nullptr, *sb_prob = nullptr;  // [cap_sb]
     int32_t *perm = nullptr;                  // [ld_slots]
+    // Two-level preconditioner: per node packed aggregate-local coordinates,
+    // per problem cell -> slot, per box owner, B^-1 and kept coefficients.
+    uint32_t *lc = nullptr;                   // [dofs/3]
+    int32_t *cslot = nullptr;                 // [ld_slots], at sb_begin * 16 + cell
+    int32_t *box_prob = nullptr;              // [cap_blk]
+    double *binv = nullptr;                   // [cap_blk][MAXA][36]
+    double *cc = nullptr;                     // [cap_blk][MAXA][6]
     // Pinned host mirrors of sb_rom and perm: set-up writes a problem's
     // tables here and copies one span per batch; release writes -1 back.
     // mirror_ev marks the last span copy, which must complete before the
@@ -160,7 +177,7 @@ struct mos_engine_s {
     int32_t *surf = nullptr;  // [S][3] surface Lagrange nodes (i, j, k) of a cell, s order
     int S = 0;
     // host state
-    mos::RangeAlloc blk, sbs, pids;
+    mos::RangeAlloc blk, sbs, pids, boxes;
     int64_t next_ticket = 0;
     std::deque<mos::EngineProblem *> queue;
     std::vector<mos::EngineProblem *> active;
@@ -178,10 +195,13 @@ struct EngineProblem {
     int64_t n_cells = 0, n_nodes = 0, n_dofs = 0;
     int blk_begin = 0, n_blk = 0;
     int sb_begin = 0, n_sb = 0;
+    int box_begin = -1;           // first box id (two-level preconditioner)
     std::vector<int> seg;         // per ROM: first slot block within the problem (n_roms+1)
     std::vector<int32_t> perm;    // [n_sb*16] cell id per slot, -1 pad
     std::vector<int32_t> sb_rom;  // [n_sb] ROM of each slot block
     Lattice lat{};                // abstract-mesh numbering of the array
+    AggLayout agg{};              // internal node order
+    int n_agg = 0;
     uint32_t bc_flags = 0;        // MOS_BC_CLAMP_* of the descriptor
     std::vector<int64_t> pdof;    // prescribed (DoF, value) list as given
     std::vector<double> pval;
@@ -202,6 +222,9 @@ struct EngineProblem {
 };
 
 mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots);
+// Preconditioner of problems admitted from now on (0 Jacobi, 1 Jacobi plus
+// the aggregate coarse correction) and the internal node order it needs.
+mos_status engine_set_precond(mos_engine e, int precond);
 mos_status engine_submit(mos_engine e, const mos_array_desc *d, void *vm, void *sig6, double *u_out,
                          int64_t *ticket);
 mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *completed);

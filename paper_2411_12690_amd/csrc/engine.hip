@@ -32,6 +32,11 @@ namespace {
 constexpr int DB = 256;       // DoFs per DoF block
 constexpr int N_XCD = 8;      // accelerator dies that workgroups are dealt to in turn
 constexpr int DOF_ALIGN = 3 * DB;
+// Two-level preconditioner: aggregates of AGG_C x AGG_C cells, boxes of
+// BOX_CX x AGG_C cells (at most MAXA aggregates per box).
+constexpr int AGG_C = 2;
+constexpr int BOX_CX = 6;
+constexpr int MAXA = (BOX_CX + AGG_C - 1) / AGG_C;
 
 template <class T>
 struct Mfma;
@@ -602,13 +607,22 @@ __device__ __forceinline__ int4 incidence(const int32_t *inc, int64_t d) {
     return reinterpret_cast<const int4 *>(inc)[d / 3];
 }
 
+// Sum of a DoF's entries in the cell layout over the cells around its
+// node.  Branch-free: an unused entry loads element 0 and is dropped by a
+// select, so all four loads are in flight together instead of each waiting
+// behind a branch.
 template <class T>
 __device__ __forceinline__ T cell_sum(const T *Y, int4 iv, int ci, int ld_slots) {
     const int e4[4] = {iv.x, iv.y, iv.z, iv.w};
+    T v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const size_t i = (size_t)(3 * (e4[e] & MAX_SURF) + ci) * ld_slots + (e4[e] >> INC_SHIFT);
+        v[e] = Y[e4[e] >= 0 ? i : 0];
+    }
     T s = 0;
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-        if (e4[e] >= 0) s += Y[(size_t)(3 * (e4[e] & MAX_SURF) + ci) * ld_slots + (e4[e] >> INC_SHIFT)];
+    for (int e = 0; e < 4; ++e) s += e4[e] >= 0 ? v[e] : T(0);
     return s;
 }
 
@@ -620,14 +634,55 @@ __device__ __forceinline__ void cell_scatter(T *Mc, int4 iv, int ci, int ld_slot
         if (e4[e] >= 0) Mc[(size_t)(3 * (e4[e] & MAX_SURF) + ci) * ld_slots + (e4[e] >> INC_SHIFT)] = v;
 }
 
+// Element at a 32-bit byte offset from a uniform base: lets the compiler
+// address it as scalar base + one 32-bit offset register.
+template <class T>
+__device__ __forceinline__ T &at_byte(T *base, uint32_t off) {
+    return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + off);
+}
+template <class T>
+__device__ __forceinline__ const T &at_byte(const T *base, uint32_t off) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + off);
+}
+
+// cell_sum / cell_scatter for cell layouts below 4 GiB (32-bit byte offsets).
+template <class T>
+__device__ __forceinline__ T cell_sum32(const T *Y, const int4 &iv, int ci, uint32_t ld_slots) {
+    const int e4[4] = {iv.x, iv.y, iv.z, iv.w};
+    T v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const uint32_t o =
+            ((uint32_t)(3 * (e4[e] & MAX_SURF) + ci) * ld_slots + (uint32_t)(e4[e] >> INC_SHIFT)) * (uint32_t)sizeof(T);
+        v[e] = at_byte(Y, e4[e] >= 0 ? o : 0u);
+    }
+    T s = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) s += e4[e] >= 0 ? v[e] : T(0);
+    return s;
+}
+
+template <class T>
+__device__ __forceinline__ void cell_scatter32(T *Mc, const int4 &iv, int ci, uint32_t ld_slots, T v) {
+    const int e4[4] = {iv.x, iv.y, iv.z, iv.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        if (e4[e] >= 0)
+            at_byte(Mc, ((uint32_t)(3 * (e4[e] & MAX_SURF) + ci) * ld_slots + (uint32_t)(e4[e] >> INC_SHIFT)) *
+                            (uint32_t)sizeof(T)) = v;
+}
+
 // Owner and type tables of the listed problems' blocks back to -1, problems
 // inactive; grid (any, problems).
 __global__ __launch_bounds__(256) void k_release_list(PidList L, const ProbParams *pp, int32_t *blk_prob,
-                                                      int32_t *sb_rom, int32_t *sb_prob, ProbState *ps) {
+                                                      int32_t *sb_rom, int32_t *sb_prob, int32_t *box_prob,
+                                                      ProbState *ps) {
     const int p = L.pid[blockIdx.y];
     const ProbParams &P = pp[p];
     const int t0 = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
     for (int i = t0; i < P.n_blk; i += stride) blk_prob[P.blk_begin + i] = -1;
+    if (P.box_begin >= 0)
+        for (int i = t0; i < P.n_agg; i += stride) box_prob[P.box_begin + i] = -1;
     for (int i = t0; i < P.n_sb; i += stride) {
         sb_rom[P.sb_begin + i] = -1;
         sb_prob[P.sb_begin + i] = -1;
@@ -776,31 +831,532 @@ __global__ __launch_bounds__(NT) void k_cgstep(const T *Y, const int32_t *inc, c
     }
 }
 
+// ---- two-level preconditioner: Jacobi plus a coarse correction on aggregates ----
+// M^-1 r = D^-1 r + sum over aggregates a of Z_a B_a^-1 Z_a^T r, with Z_a the
+// six rigid-body modes of aggregate a (three translations, three rotations
+// about its corner) on its free DoFs and zero elsewhere, and B_a = Z_a^T A Z_a.
+// Aggregates are AGG_C x AGG_C cells; one workgroup owns a box of
+// aggregates (the internal node order keeps a box's DoFs consecutive), so
+// the restriction Z_a^T r, the 6x6 solve and the prolongation stay inside
+// the workgroup.  Symmetric positive definite, so PCG stays valid.
+
+// Rigid-body mode values at a node (coordinates X, Y, Zc from the
+// aggregate's corner): restriction of the node's three components r, and
+// prolongation of coefficients c onto them.
+template <class T>
+__device__ __forceinline__ void node_restrict(double X, double Y, double Zc, const T (&r)[3], const bool (&f)[3],
+                                              double (&q)[6]) {
+    const double r0 = f[0] ? (double)r[0] : 0.0, r1 = f[1] ? (double)r[1] : 0.0, r2 = f[2] ? (double)r[2] : 0.0;
+    q[0] = r0;
+    q[1] = r1;
+    q[2] = r2;
+    q[3] = X * r1 - Y * r0;
+    q[4] = Y * r2 - Zc * r1;
+    q[5] = Zc * r0 - X * r2;
+}
+
+__device__ __forceinline__ void node_prolong(double X, double Y, double Zc, const double *c, double (&u)[3]) {
+    u[0] = c[0] - Y * c[3] + Zc * c[5];
+    u[1] = c[1] + X * c[3] - Zc * c[4];
+    u[2] = c[2] + Y * c[4] - X * c[5];
+}
+
+// Packed aggregate-local coordinates of a node: i | j << 8 | K << 16 |
+// a << 24 | constrained components << 28 (a = aggregate within the box).
+__device__ __forceinline__ void unpack_lc(uint32_t w, const double *h, double &X, double &Y, double &Zc, int &a,
+                                          bool (&f)[3]) {
+    X = (double)(w & 255u) * h[0];
+    Y = (double)((w >> 8) & 255u) * h[1];
+    Zc = (double)((w >> 16) & 255u) * h[2];
+    a = (int)((w >> 24) & 15u);
+    for (int ci = 0; ci < 3; ++ci) f[ci] = ((w >> (28 + ci)) & 1u) == 0;
+}
+
+// Box b of problem P: its first node (index into the global node arrays),
+// node count, and number of aggregates.
+__device__ __forceinline__ void box_geometry(const ProbParams &P, int b, int64_t &first, int &nn, int &na) {
+    const AggLayout &A = P.agg;
+    const int gx = b % A.nax, gy = b / A.nax;
+    first = P.d0 / 3 + agg_first(A, gx, gy);
+    nn = (int)sub_count(agg_box(A, gx, gy));
+    const int cells = gx == A.nax - 1 ? P.lat.Nx - A.cx * (A.nax - 1) : A.cx;
+    na = (cells + AGG_C - 1) / AGG_C;
+}
+
+// Index in the inner vectors of DoF (node, ci) of problem P (node relative
+// to the problem).  With boxes (two-level preconditioner) the inner vectors
+// are component-major within each box -- component ci of the box's t-th node
+// at 3 * first + ci * nn + t -- so a box workgroup with one node per thread
+// reads and writes them in whole lines; otherwise 3 * node + ci.
+__device__ __forceinline__ int64_t inner_index(const ProbParams &P, int64_t node, int ci) {
+    if (P.box_begin < 0) return P.d0 + 3 * node + ci;
+    const AggLayout &A = P.agg;
+    int gy = (int)(node / A.row);
+    if (gy > A.nay - 1) gy = A.nay - 1;
+    const int64_t rem = node - (int64_t)gy * A.row;
+    const int wy = gy == A.nay - 1 ? A.wyl : A.wyi;
+    const int64_t per = sub_count(make_sub(A.wxi, wy, A.Z, A.sx, A.sy));
+    int gx = (int)(rem / per);
+    if (gx > A.nax - 1) gx = A.nax - 1;
+    const int64_t first = agg_first(A, gx, gy);
+    const int64_t nn = sub_count(agg_box(A, gx, gy));
+    return P.d0 + 3 * first + ci * nn + (node - first);
+}
+
+// Scalar step computed by one workgroup of at least CG_LW threads (threads
+// beyond CG_LW idle): the same sums, in the same order, as
+// cg_scalars_block<CG_LW>.
+__device__ CgStep cg_scalars_wide(const ProbState &S, int it, const double *pg, const double *pr,
+                                  const double *pdel, double (*red)[CG_LW]) {
+    const int t = threadIdx.x;
+    if (t < CG_LW) {
+        double g = 0.0, r = 0.0, dl = 0.0;
+#pragma unroll 4
+        for (int i = S.blk_begin + t; i < S.blk_end; i += CG_LW) {
+            g += pg[i];
+            r += pr[i];
+        }
+#pragma unroll 4
+        for (int i = S.tile_begin + t; i < S.tile_end; i += CG_LW) dl += pdel[i];
+        red[0][t] = g;
+        red[1][t] = r;
+        red[2][t] = dl;
+    }
+    __syncthreads();
+    for (int m = CG_LW / 2; m > 0; m >>= 1) {
+        if (t < m)
+            for (int j = 0; j < 3; ++j) red[j][t] += red[j][t + m];
+        __syncthreads();
+    }
+    CgStep o;
+    o.gamma = red[0][0];
+    o.rr = red[1][0];
+    const double delta = red[2][0];
+    o.tol2 = it == S.seg_start ? S.rtol2 * o.rr : S.tol2;
+    o.stop = 0;
+    o.alpha = o.beta = 0.0;
+    if (o.rr <= o.tol2) {
+        o.stop = 1;
+    } else if (it - S.seg_start >= S.max_iter) {
+        o.stop = 3;
+    } else {
+        if (it == 0) {
+            o.alpha = o.gamma / delta;
+        } else {
+            const int pv = (it - 1) & 1;
+            o.beta = o.gamma / S.hist_gamma[pv];
+            o.alpha = o.gamma / (delta - o.beta * o.gamma / S.hist_alpha[pv]);
+        }
+        if (!(o.alpha > 0.0) || !isfinite(o.alpha) || !isfinite(o.beta)) o.stop = 2;
+    }
+    return o;
+}
+
+// LDS of a box workgroup (the per-node restriction terms are dynamic LDS,
+// blockDim.x x 6 doubles).
+struct BoxShared {
+    double bi[MAXA][36];         // B^-1 of the box's aggregates
+    double wsum[16][2];          // per-wave (r,D^-1 r) and (r,r)
+    double cn[MAXA][6];          // coarse coefficients B^-1 q
+    double en[MAXA];             // q . c per aggregate
+    double cold[MAXA][6];        // coefficients of the current r (start of an iteration)
+    int8_t tag[1024];            // aggregate of each thread's node, -1 if none
+};
+
+// Box data requested at the start of a box workgroup: B^-1 of its
+// aggregates (and, for an iteration, the kept coefficients).
+__device__ __forceinline__ void box_prefetch(BoxShared &sh, const double *binv, const double *cc, int bs, int na,
+                                             bool coeffs) {
+    const int t = threadIdx.x;
+    if (t < na * 36) sh.bi[t / 36][t % 36] = binv[(size_t)bs * MAXA * 36 + t];
+    if (coeffs && t < na * 6) sh.cold[t / 6][t % 6] = cc[(size_t)bs * MAXA * 6 + t];
+}
+
+// Second half of an update or sweep start, once the thread's node holds the
+// new residual rv: restriction per aggregate (fixed order), coarse solve,
+// u = D^-1 r + Z c to the cell layout, the box's (r,u) and (r,r) partials
+// into slot `pslot` and the coefficients kept for the next iteration.
+// B^-1 must be in sh.bi (box_prefetch, before a barrier).
+template <class T>
+__device__ __forceinline__ void box_coarse_finish(BoxShared &sh, double (*qn)[6], bool act, int nn, int na, int bs,
+                                                  const int4 &iv, const T (&dv)[3], const T (&rv)[3],
+                                                  const bool (&f)[3], double X, double Y, double Zc, int a, T *Mc,
+                                                  int ld_slots, double *cc, double *pg, double *pr, size_t pslot) {
+    const int t = threadIdx.x, lane = t % 64, w = t / 64, nw = blockDim.x / 64;
+    double gd = 0.0, r2 = 0.0;
+    double q[6] = {0, 0, 0, 0, 0, 0};
+    if (act) {
+        for (int ci = 0; ci < 3; ++ci) {
+            gd += (double)rv[ci] * (double)(dv[ci] * rv[ci]);
+            r2 += (double)rv[ci] * (double)rv[ci];
+        }
+        node_restrict(X, Y, Zc, rv, f, q);
+    }
+    for (int m = 0; m < 6; ++m) qn[t][m] = q[m];
+    sh.tag[t] = act ? (int8_t)a : (int8_t)-1;
+    for (int m = 32; m >= 1; m >>= 1) {
+        gd += __shfl_xor(gd, m);
+        r2 += __shfl_xor(r2, m);
+    }
+    if (lane == 0) {
+        sh.wsum[w][0] = gd;
+        sh.wsum[w][1] = r2;
+    }
+    __syncthreads();
+    // Wave k < na sums aggregate k (lane L takes nodes L, L + 64, ...; the
+    // butterfly leaves the sum in every lane) and solves its 6x6 system.
+    if (w < na) {
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        for (int l = lane; l < nn; l += 64)
+            if (sh.tag[l] == w)
+                for (int m = 0; m < 6; ++m) acc[m] += qn[l][m];
+        for (int m = 0; m < 6; ++m)
+            for (int k = 32; k >= 1; k >>= 1) acc[m] += __shfl_xor(acc[m], k);
+        if (lane == 0) {
+            double e = 0.0;
+            for (int m = 0; m < 6; ++m) {
+                double c = 0.0;
+                for (int k = 0; k < 6; ++k) c += sh.bi[w][m * 6 + k] * acc[k];
+                sh.cn[w][m] = c;
+                e += acc[m] * c;
+            }
+            sh.en[w] = e;
+        }
+    }
+    __syncthreads();
+    if (act) {
+        double uc[3];
+        node_prolong(X, Y, Zc, sh.cn[a], uc);
+        for (int ci = 0; ci < 3; ++ci) {
+            const T un = dv[ci] * rv[ci] + (f[ci] ? (T)uc[ci] : T(0));
+            cell_scatter32(Mc, iv, ci, (uint32_t)ld_slots, un);
+        }
+    }
+    if (t < na * 6) cc[(size_t)bs * MAXA * 6 + t] = sh.cn[t / 6][t % 6];
+    if (t == 0) {
+        double g = 0.0, rr = 0.0;
+        for (int i = 0; i < nw; ++i) {
+            g += sh.wsum[i][0];
+            rr += sh.wsum[i][1];
+        }
+        double e = 0.0;
+        for (int ag = 0; ag < na; ++ag) e += sh.en[ag];
+        pg[pslot + bs] = g + e;
+        pr[pslot + bs] = rr;
+    }
+}
+
+// One iteration of the two-level form, one workgroup per box (one thread
+// per node, blockDim.x >= the box's nodes and >= CG_LW): as k_cgstep, with
+// u = M^-1 r of the two-level preconditioner.  The current u is rebuilt
+// from r and the coefficients kept by the previous step.
+template <class T>
+__global__ __launch_bounds__(1024) void k_cgstep2(const T *Y, const int32_t *inc, const uint8_t *cmask,
+                                                  const T *dinv, const uint32_t *lc, T *x, T *r, T *p, T *s, T *Mc,
+                                                  int ld_slots, const int32_t *box_prob, const ProbParams *pp,
+                                                  ProbState *ps, double *pg, double *pr, const double *pdel,
+                                                  const double *binv, double *cc, int epoch, int cap_blk,
+                                                  int n_box) {
+    // Dynamic LDS: the per-node restriction terms (blockDim.x x 6 doubles),
+    // first used as the scalar step's reduction space (3 x CG_LW doubles).
+    extern __shared__ double qn_dyn[];
+    double(*qn)[6] = reinterpret_cast<double(*)[6]>(qn_dyn);
+    double(*red)[CG_LW] = reinterpret_cast<double(*)[CG_LW]>(qn_dyn);
+    __shared__ BoxShared sh;
+    __shared__ int go, it_sh;
+    __shared__ double step[2];
+    const int per = (n_box + N_XCD - 1) / N_XCD;
+    const int bs = (int)(blockIdx.x % N_XCD) * per + (int)(blockIdx.x / N_XCD);
+    if (bs >= n_box) return;
+    const int pb = box_prob[bs];
+    if (pb < 0) return;
+    const ProbParams &P = pp[pb];
+    int64_t first;
+    int nn, na;
+    box_geometry(P, bs - P.box_begin, first, nn, na);
+    const int t = threadIdx.x;
+    const bool act = t < nn;
+    // Uniform bases of the box and 32-bit lane offsets, so every vector
+    // access shares one offset register.
+    const int4 iv = act ? reinterpret_cast<const int4 *>(inc)[first + t] : make_int4(-1, -1, -1, -1);
+    box_prefetch(sh, binv, cc, bs, na, true);
+    if (t == 0) {
+        const ProbState &S = ps[pb];
+        const int active = S.active, done = S.done, fused = S.fused, start = S.start_epoch;
+        const double a_cur = S.a_cur, b_cur = S.b_cur;
+        const int g = ((active != 0) & (done == 0)) ? 1 + (fused != 0) : 0;
+        step[0] = a_cur;
+        step[1] = b_cur;
+        it_sh = epoch - start;
+        go = g;
+    }
+    __syncthreads();
+    if (!go) return;
+    const int it = it_sh;
+    const size_t rd_slot = (size_t)(it & 1) * cap_blk, wr_slot = (size_t)((it + 1) & 1) * cap_blk;
+    if (go == 2) {
+        ProbState &S = ps[pb];
+        const CgStep o = cg_scalars_wide(S, it, pg + rd_slot, pr + rd_slot, pdel, red);
+        if (t == 0 && bs == S.blk_begin) cg_publish(S, it, o);
+        if (o.stop) return;
+        if (t == 0) {
+            step[0] = o.alpha;
+            step[1] = o.beta;
+        }
+        // Also ends every read of the reduction space before it holds
+        // restriction terms.
+        __syncthreads();
+    }
+    const T al = (T)step[0], be = (T)step[1];
+    T dv[3] = {0, 0, 0}, rv[3] = {0, 0, 0};
+    bool f[3] = {false, false, false};
+    double X = 0.0, Yc = 0.0, Zc = 0.0;
+    int a = 0;
+    if (act) {
+        unpack_lc(lc[first + t], P.h, X, Yc, Zc, a, f);
+        // Component-major within the box: component ci of node t at ci * nn + t.
+        const int64_t vb = 3 * first;
+        const T *db = dinv + vb;
+        T *xb = x + vb, *rb = r + vb, *pbv = p + vb, *sb = s + vb;
+        T rd[3], pd0[3], sd[3], xd[3], wv[3];
+        for (int ci = 0; ci < 3; ++ci) {
+            const uint32_t o = (uint32_t)(ci * nn + t) * (uint32_t)sizeof(T);
+            dv[ci] = at_byte(db, o);
+            rd[ci] = at_byte(rb, o);
+            pd0[ci] = at_byte(pbv, o);
+            sd[ci] = at_byte(sb, o);
+            xd[ci] = at_byte(xb, o);
+            const T sum = cell_sum32(Y, iv, ci, (uint32_t)ld_slots);
+            wv[ci] = f[ci] ? sum : T(0);
+        }
+        double uc[3];
+        node_prolong(X, Yc, Zc, sh.cold[a], uc);
+        for (int ci = 0; ci < 3; ++ci) {
+            const uint32_t o = (uint32_t)(ci * nn + t) * (uint32_t)sizeof(T);
+            const T uv = dv[ci] * rd[ci] + (f[ci] ? (T)uc[ci] : T(0));
+            const T pv = uv + be * pd0[ci];
+            const T sv = wv[ci] + be * sd[ci];
+            at_byte(xb, o) = xd[ci] + al * pv;
+            rv[ci] = rd[ci] - al * sv;
+            at_byte(pbv, o) = pv;
+            at_byte(sb, o) = sv;
+            at_byte(rb, o) = rv[ci];
+        }
+    }
+    box_coarse_finish(sh, qn, act, nn, na, bs, iv, dv, rv, f, X, Yc, Zc, a, Mc, ld_slots, cc, pg, pr, wr_slot);
+}
+
+// Sweep start in the two-level form: r = scale_in * r64, x = 0, p and s
+// cleared or rescaled, u = M^-1 r to the cell layout and the partials of the
+// sweep's first iteration.
+template <class T>
+__global__ __launch_bounds__(1024) void k_cgstart2(ProbSel sel, const int32_t *box_prob, const ProbParams *pp,
+                                                   const SweepParams *sp, const ProbState *ps, const double *r64,
+                                                   const T *dinv, const int32_t *inc, const uint8_t *cmask,
+                                                   const uint32_t *lc, T *x, T *r, T *p, T *s, T *Mc, int ld_slots,
+                                                   double *pg, double *pr, const double *binv, double *cc,
+                                                   int cap_blk) {
+    extern __shared__ double qn_dyn[];
+    double(*qn)[6] = reinterpret_cast<double(*)[6]>(qn_dyn);
+    __shared__ BoxShared sh;
+    const int bs = blockIdx.x;
+    const int pb = box_prob[bs];
+    if (pb < 0 || !selected(sel, pb)) return;
+    const ProbParams &P = pp[pb];
+    int64_t first;
+    int nn, na;
+    box_geometry(P, bs - P.box_begin, first, nn, na);
+    const int t = threadIdx.x;
+    const bool act = t < nn;
+    const int4 iv = act ? reinterpret_cast<const int4 *>(inc)[first + t] : make_int4(-1, -1, -1, -1);
+    const SweepParams &W = sp[pb];
+    box_prefetch(sh, binv, cc, bs, na, false);
+    T dv[3] = {0, 0, 0}, rv[3] = {0, 0, 0};
+    bool f[3] = {false, false, false};
+    double X = 0.0, Yc = 0.0, Zc = 0.0;
+    int a = 0;
+    if (act) {
+        unpack_lc(lc[first + t], P.h, X, Yc, Zc, a, f);
+        const T c = (T)W.p_scale;
+        for (int ci = 0; ci < 3; ++ci) {
+            const int64_t v = 3 * first + ci * nn + t;  // component-major within the box
+            dv[ci] = dinv[v];
+            rv[ci] = (T)(r64[3 * (first + t) + ci] * W.scale_in);
+            x[v] = 0;
+            r[v] = rv[ci];
+            if (W.cont) {
+                p[v] *= c;
+                s[v] *= c;
+            } else {
+                p[v] = 0;
+                s[v] = 0;
+            }
+        }
+    }
+    box_coarse_finish(sh, qn, act, nn, na, bs, iv, dv, rv, f, X, Yc, Zc, a, Mc, ld_slots, cc, pg, pr,
+                      (size_t)(ps[pb].it & 1) * cap_blk);
+}
+
+// B_a^-1 of every aggregate of the selected problems' boxes; grid (boxes,
+// MAXA), one workgroup per aggregate.  B_a = sum over the cells touching
+// the aggregate of Z_c^T K_r(type) Z_c, Z_c the aggregate's modes on the
+// cell's DoFs that belong to it and are free.  Cells in fixed order; the
+// 6x6 inverse by Cholesky (an aggregate whose B is not numerically positive
+// definite gets no coarse correction).
+__global__ __launch_bounds__(256) void k_coarse_setup(ProbSel sel, const int32_t *box_prob, const ProbParams *pp,
+                                                      const int32_t *cslot, const int32_t *sb_rom,
+                                                      const void *const *kr64_tab, const uint8_t *cmask,
+                                                      const int32_t *surf, int n, int ldk, double *binv) {
+    const int bs = blockIdx.x, a = blockIdx.y;
+    const int pb = box_prob[bs];
+    if (pb < 0 || !selected(sel, pb)) return;
+    const ProbParams &P = pp[pb];
+    const AggLayout &A = P.agg;
+    const int b = bs - P.box_begin, gx = b % A.nax, gy = b / A.nax;
+    const int bx0 = gx * A.cx, bx1 = gx == A.nax - 1 ? P.lat.Nx : bx0 + A.cx;
+    const int by0 = gy * A.cy, by1 = gy == A.nay - 1 ? P.lat.Ny : by0 + A.cy;
+    const int na = (bx1 - bx0 + AGG_C - 1) / AGG_C;
+    double *out = binv + ((size_t)bs * MAXA + a) * 36;
+    const int t = threadIdx.x;
+    if (a >= na) {
+        if (t < 36) out[t] = 0.0;
+        return;
+    }
+    const int ax0 = bx0 + a * AGG_C, ax1 = min(ax0 + AGG_C, bx1);
+    __shared__ double zl[256][6], acc_s[256][6], G[36];
+    __shared__ uint8_t nz[256];
+    if (t < 36) G[t] = 0.0;
+    const int sx = A.sx, sy = A.sy;
+    for (int cy = max(by0 - 1, 0); cy < by1; ++cy)
+        for (int cx = max(ax0 - 1, 0); cx < ax1; ++cx) {
+            const int cell = cy * P.lat.Nx + cx;
+            const int slot = cslot[(int64_t)P.sb_begin * 16 + cell];
+            const double *K = static_cast<const double *>(kr64_tab[sb_rom[slot / 16]]);
+            __syncthreads();
+            if (t < n) {
+                const int sn = t / 3, ci = t % 3;
+                const int64_t I = (int64_t)cx * sx + surf[3 * sn], J = (int64_t)cy * sy + surf[3 * sn + 1];
+                const int Kz = surf[3 * sn + 2];
+                bool in = agg_x(A, I) == gx && agg_y(A, J) == gy;
+                const int ib = (int)(I - (int64_t)gx * A.wxi);
+                const int ag = min(ib / (AGG_C * sx), na - 1);
+                in = in && ag == a;
+                const int64_t dd = P.d0 + 3 * agg_encode(A, I, J, Kz) + ci;
+                in = in && cmask[dd] == 0;
+                double z[6] = {0, 0, 0, 0, 0, 0};
+                if (in) {
+                    const double X = (double)(ib - ag * AGG_C * sx) * P.h[0];
+                    const double Yc = (double)(J - (int64_t)gy * A.wyi) * P.h[1];
+                    const double Zc = (double)Kz * P.h[2];
+                    // Mode values at component ci (columns of Z).
+                    z[ci] = 1.0;
+                    if (ci == 0) {
+                        z[3] = -Yc;
+                        z[5] = Zc;
+                    } else if (ci == 1) {
+                        z[3] = X;
+                        z[4] = -Zc;
+                    } else {
+                        z[4] = Yc;
+                        z[5] = -X;
+                    }
+                }
+                for (int m = 0; m < 6; ++m) zl[t][m] = z[m];
+                nz[t] = in ? 1 : 0;
+            }
+            __syncthreads();
+            if (t < n) {
+                double acc[6] = {0, 0, 0, 0, 0, 0};
+                for (int l = 0; l < n; ++l) {
+                    if (!nz[l]) continue;  // the same for every thread
+                    const double kv = K[(size_t)l * ldk + t];
+                    for (int m = 0; m < 6; ++m) acc[m] += kv * zl[l][m];
+                }
+                for (int m = 0; m < 6; ++m) acc_s[t][m] = acc[m];
+            }
+            __syncthreads();
+            if (t < 36) {
+                const int m1 = t / 6, m2 = t % 6;
+                double g = 0.0;
+                for (int k = 0; k < n; ++k) g += zl[k][m1] * acc_s[k][m2];
+                G[t] += g;
+            }
+        }
+    __syncthreads();
+    if (t == 0) {
+        double B[6][6], L[6][6] = {}, Li[6][6] = {};
+        double dmax = 0.0;
+        for (int i = 0; i < 6; ++i)
+            for (int j = 0; j < 6; ++j) B[i][j] = 0.5 * (G[i * 6 + j] + G[j * 6 + i]);
+        for (int i = 0; i < 6; ++i) dmax = fmax(dmax, B[i][i]);
+        bool ok = dmax > 0.0 && isfinite(dmax);
+        for (int j = 0; j < 6 && ok; ++j) {
+            double v = B[j][j];
+            for (int k = 0; k < j; ++k) v -= L[j][k] * L[j][k];
+            if (!(v > 1e-12 * dmax)) {
+                ok = false;
+                break;
+            }
+            L[j][j] = sqrt(v);
+            for (int i = j + 1; i < 6; ++i) {
+                double w = B[i][j];
+                for (int k = 0; k < j; ++k) w -= L[i][k] * L[j][k];
+                L[i][j] = w / L[j][j];
+            }
+        }
+        if (ok) {
+            // L^-1 by forward substitution, then B^-1 = L^-T L^-1.
+            for (int c = 0; c < 6; ++c)
+                for (int i = c; i < 6; ++i) {
+                    double v = i == c ? 1.0 : 0.0;
+                    for (int k = c; k < i; ++k) v -= L[i][k] * Li[k][c];
+                    Li[i][c] = v / L[i][i];
+                }
+            for (int i = 0; i < 6; ++i)
+                for (int j = 0; j < 6; ++j) {
+                    double v = 0.0;
+                    for (int k = max(i, j); k < 6; ++k) v += Li[k][i] * Li[k][j];
+                    out[i * 6 + j] = v;
+                }
+        } else {
+            for (int i = 0; i < 36; ++i) out[i] = 0.0;
+        }
+    }
+}
+
 // ---- batched per-problem phases (set-up, FP64 residual, sweep start/stop) ----
 // Kernels over DoF blocks [0, high water) act on the blocks of selected
 // problems only; per problem they do exactly what a single-problem launch
 // would, so batching never changes a problem's results.
 
 // Problem id of every DoF block and slot block of the listed problems.
-__global__ void k_fill_owner(PidList L, const ProbParams *pp, int32_t *blk_prob, int32_t *sb_prob) {
+__global__ void k_fill_owner(PidList L, const ProbParams *pp, int32_t *blk_prob, int32_t *sb_prob,
+                             int32_t *box_prob) {
     const int p = L.pid[blockIdx.x];
     const ProbParams &P = pp[p];
     for (int i = threadIdx.x; i < P.n_blk; i += blockDim.x) blk_prob[P.blk_begin + i] = p;
     for (int i = threadIdx.x; i < P.n_sb; i += blockDim.x) sb_prob[P.sb_begin + i] = p;
+    if (P.box_begin >= 0)
+        for (int i = threadIdx.x; i < P.n_agg; i += blockDim.x) box_prob[P.box_begin + i] = p;
 }
 
-// Constrained DoFs: padding and, when clamped, the bottom-plane nodes
-// [0, bot_end) and top-plane nodes [top_begin, n_nodes) (value 0); the
-// problem's incidence region doubles as the "last entry" table of its
-// prescribed list, reset to -1.
+// Constrained DoFs: padding and, when clamped, the nodes of the bottom and
+// top planes (value 0); the problem's incidence region doubles as the "last
+// entry" table of its prescribed list, reset to -1.
 __global__ void k_setup_dofs(ProbSel sel, const int32_t *blk_prob, const ProbParams *pp, uint8_t *cmask, double *g,
                              double *x64, int32_t *inc) {
     const int p = blk_prob[blockIdx.x];
     if (!selected(sel, p)) return;
     const ProbParams &P = pp[p];
     const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x, i = d - P.d0;
-    const int64_t node = i / 3;
-    cmask[d] = (i >= P.n_dofs || node < P.bot_end || node >= P.top_begin) ? 1 : 0;
+    bool c = i >= P.n_dofs;
+    if (!c && P.clamp) {
+        int64_t I, J;
+        int K;
+        agg_decode(P.agg, i / 3, I, J, K);
+        c = ((P.clamp & MOS_BC_CLAMP_BOTTOM) && K == 0) || ((P.clamp & MOS_BC_CLAMP_TOP) && K == P.agg.Z - 1);
+    }
+    cmask[d] = c ? 1 : 0;
     g[d] = 0.0;
     x64[d] = 0.0;
     inc[P.d0 / 3 * 4 + i] = -1;
@@ -817,7 +1373,8 @@ __global__ void k_clear_incidence(ProbSel sel, const int32_t *blk_prob, int32_t 
 // 2 or 4 cells; the rank of cell (cx, cy) among them follows from which side
 // of the face it lies.
 __global__ void k_incidence_sel(ProbSel sel, const int32_t *sb_prob, const ProbParams *pp, const int32_t *perm,
-                                int32_t *inc, const int32_t *surf, int S, int64_t n_slots) {
+                                int32_t *inc, uint32_t *lc, int32_t *cslot, const uint8_t *cmask,
+                                const int32_t *surf, int S, int64_t n_slots) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n_slots * S) return;
     const int slot = (int)(idx / S), s = (int)(idx % S);
@@ -828,7 +1385,22 @@ __global__ void k_incidence_sel(ProbSel sel, const int32_t *sb_prob, const ProbP
     const Lattice &L = pp[p].lat;
     const int cx = cell % L.Nx, cy = cell / L.Nx;
     const int i = surf[3 * s], j = surf[3 * s + 1], k = surf[3 * s + 2];
-    const int64_t node = node_id(L, (int64_t)cx * (L.nx - 1) + i, (int64_t)cy * (L.ny - 1) + j, k);
+    const AggLayout &A = pp[p].agg;
+    const int64_t I = (int64_t)cx * (L.nx - 1) + i, J = (int64_t)cy * (L.ny - 1) + j;
+    const int64_t node = agg_encode(A, I, J, k);
+    if (s == 0) cslot[(int64_t)pp[p].sb_begin * 16 + cell] = slot;
+    {
+        // Aggregate-local coordinates of the node (two-level preconditioner).
+        const int gx = agg_x(A, I), gy = agg_y(A, J);
+        const int cells = gx == A.nax - 1 ? L.Nx - A.cx * (A.nax - 1) : A.cx;
+        const int na = (cells + AGG_C - 1) / AGG_C;
+        const int ib = (int)(I - (int64_t)gx * A.wxi);
+        const int ag = min(ib / (AGG_C * A.sx), na - 1);
+        const uint32_t ia = (uint32_t)(ib - ag * AGG_C * A.sx), jb = (uint32_t)(J - (int64_t)gy * A.wyi);
+        const int64_t dn = pp[p].d0 + 3 * node;
+        const uint32_t cm = (cmask[dn] ? 1u : 0u) | (cmask[dn + 1] ? 2u : 0u) | (cmask[dn + 2] ? 4u : 0u);
+        lc[pp[p].d0 / 3 + node] = ia | jb << 8 | (uint32_t)k << 16 | (uint32_t)ag << 24 | cm << 28;
+    }
     const bool shx = (i == 0 && cx > 0) || (i == L.nx - 1 && cx < L.Nx - 1);
     const int ux = (i == 0 && cx > 0) ? 1 : 0;
     const int uy = (j == 0 && cy > 0) ? 1 : 0;
@@ -856,7 +1428,11 @@ __global__ void k_rhs_diag(ProbSel sel, const int32_t *blk_prob, const ProbParam
             sd += static_cast<const double *>(kr64_tab[rom])[(size_t)k * ldk + k];
         }
     b[d] = pp[p].dT * sb;
-    dinv[d] = (cmask[d] || sd == 0.0) ? T(1) : T(1.0 / sd);
+    const int64_t i = d - pp[p].d0;
+    if (i < pp[p].n_dofs)
+        dinv[inner_index(pp[p], i / 3, (int)(i % 3))] = (cmask[d] || sd == 0.0) ? T(1) : T(1.0 / sd);
+    else if (pp[p].box_begin < 0)
+        dinv[d] = T(1);
 }
 
 // FP64 vector of the selected problems to the cell-major layout.
@@ -932,8 +1508,8 @@ __global__ void k_prob_start_list(PidList L, const ProbParams *pp, const SweepPa
     S.done = 0;
     S.active = 1;
     S.max_iter = sp[p].max_iter;
-    S.blk_begin = pp[p].blk_begin;
-    S.blk_end = pp[p].blk_begin + pp[p].n_blk;
+    S.blk_begin = pp[p].part_begin;
+    S.blk_end = pp[p].part_begin + pp[p].n_part;
     S.tile_begin = pp[p].sb_begin * pp[p].nrb;
     S.tile_end = (pp[p].sb_begin + pp[p].n_sb) * pp[p].nrb;
 }
@@ -996,12 +1572,12 @@ __global__ void k_zero_padding(ProbSel sel, const int32_t *sb_prob, const int32_
 // x64 += sign * scale_out * dx on the selected problems (fold in a sweep's
 // correction, or take it back).
 template <class T>
-__global__ void k_add_inner_sel(ProbSel sel, const int32_t *blk_prob, const SweepParams *sp, double *x64, const T *dx,
-                                double sign) {
+__global__ void k_add_inner_sel(ProbSel sel, const int32_t *blk_prob, const ProbParams *pp, const SweepParams *sp,
+                                double *x64, const T *dx, double sign) {
     const int pid = blk_prob[blockIdx.x];
     if (!selected(sel, pid)) return;
-    const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x;
-    x64[d] += sign * sp[pid].scale_out * (double)dx[d];
+    const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x, i = d - pp[pid].d0;
+    if (i < pp[pid].n_dofs) x64[d] += sign * sp[pid].scale_out * (double)dx[inner_index(pp[pid], i / 3, (int)(i % 3))];
 }
 
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
@@ -1018,13 +1594,28 @@ __global__ void k_prescribe_last(const int64_t *dof, int64_t n, int32_t *last) {
     if (i < n) atomicMax(&last[dof[i]], (int32_t)i);
 }
 
+// DoF of the internal order for a DoF of the caller's order.
+__device__ __forceinline__ int64_t internal_dof(const SubLattice &W, const AggLayout &A, int64_t dof) {
+    int i, j, K;
+    sub_decode(W, dof / 3, i, j, K);
+    return 3 * agg_encode(A, i, j, K) + dof % 3;
+}
+
+// Prescribed values applied (the list holds DoFs of the caller's order).
 __global__ void k_prescribe(const int64_t *dof, const double *val, int64_t n, const int32_t *last, uint8_t *cmask,
-                            double *g, double *x64, int64_t d0) {
+                            double *g, double *x64, int64_t d0, SubLattice W, AggLayout A) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || last[dof[i]] != (int32_t)i) return;
-    cmask[d0 + dof[i]] = 1;
-    g[d0 + dof[i]] = val[i];
-    x64[d0 + dof[i]] = val[i];
+    const int64_t d = d0 + internal_dof(W, A, dof[i]);
+    cmask[d] = 1;
+    g[d] = val[i];
+    x64[d] = val[i];
+}
+
+// Solution in the caller's DoF order from the internal order.
+__global__ void k_export_u(const double *x, double *u, int64_t n_dofs, SubLattice W, AggLayout A) {
+    const int64_t dof = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (dof < n_dofs) u[dof] = x[internal_dof(W, A, dof)];
 }
 
 // Global DoF of cell DoF k in slot sl ([ldk][n_slots], -1 for padding).
@@ -1093,6 +1684,13 @@ void RangeAlloc::give(int b, int n) {
 
 namespace {
 
+// DoF blocks of a problem: its DoFs, and at least one block per aggregate
+// (an aggregate's partials go to the slot of its block index); a multiple
+// of 3 so every problem starts on a node boundary.
+int problem_blocks(int64_t n_dofs, int n_agg) {
+    return (int)std::max(round_up(n_dofs, DOF_ALIGN) / DB, round_up(n_agg, 3));
+}
+
 mos_status prepare_problem(mos_engine e, const mos_array_desc *d, EngineProblem *P) {
     const mos_cell_desc &cd = e->roms[0]->desc;
     const Lattice L = make_lattice(d->nx_cells, d->ny_cells, cd.interp[0], cd.interp[1], cd.interp[2]);
@@ -1106,7 +1704,9 @@ mos_status prepare_problem(mos_engine e, const mos_array_desc *d, EngineProblem 
     const bool mixed = e->precision == MOS_MIXED;
     P->rtol = d->rtol > 0 ? d->rtol : (mixed ? 1e-10 : 1e-12);
     P->max_iters = d->max_iters > 0 ? d->max_iters : 20000;
-    P->n_blk = (int)(round_up(P->n_dofs, DOF_ALIGN) / DB);
+    P->agg = make_agg_layout(L, e->box_cells[0], e->box_cells[1]);
+    P->n_agg = agg_count(P->agg);
+    P->n_blk = problem_blocks(P->n_dofs, P->n_agg);
     P->bc_flags = d->bc_flags & (MOS_BC_CLAMP_BOTTOM | MOS_BC_CLAMP_TOP);
     if (d->n_prescribed > INT32_MAX) {
         set_error("more than 2^31-1 prescribed entries");
@@ -1134,7 +1734,20 @@ mos_status prepare_problem(mos_engine e, const mos_array_desc *d, EngineProblem 
     P->perm.assign((size_t)P->n_sb * 16, -1);
     std::vector<int> next(n_roms);
     for (int t = 0; t < n_roms; ++t) next[t] = P->seg[t] * 16;
-    for (int64_t c = 0; c < P->n_cells; ++c) P->perm[next[d->cell_type[c]]++] = (int32_t)c;
+    // Within a type, slots follow the aggregates (cells of one aggregate in
+    // neighbouring slots), as the DoFs do: the update's gathers and scatters
+    // for an aggregate then fall in a few cache lines per cell-layout row.
+    const AggLayout &A = P->agg;
+    for (int gy = 0; gy < A.nay; ++gy)
+        for (int gx = 0; gx < A.nax; ++gx) {
+            const int cy1 = gy == A.nay - 1 ? P->Ny : (gy + 1) * A.cy;
+            const int cx1 = gx == A.nax - 1 ? P->Nx : (gx + 1) * A.cx;
+            for (int cy = gy * A.cy; cy < cy1; ++cy)
+                for (int cx = gx * A.cx; cx < cx1; ++cx) {
+                    const int64_t c = (int64_t)cy * P->Nx + cx;
+                    P->perm[next[d->cell_type[c]]++] = (int32_t)c;
+                }
+        }
     P->sb_rom.assign(P->n_sb, -1);
     for (int t = 0; t < n_roms; ++t)
         for (int b = P->seg[t]; b < P->seg[t + 1]; ++b) P->sb_rom[b] = t;
@@ -1219,8 +1832,18 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
         H.d0 = (int64_t)P->blk_begin * DB;
         H.n_dofs = P->n_dofs;
         H.nd_pad = (int64_t)P->n_blk * DB;
-        H.bot_end = (P->bc_flags & MOS_BC_CLAMP_BOTTOM) ? L.plane_full : 0;
-        H.top_begin = (P->bc_flags & MOS_BC_CLAMP_TOP) ? L.n_nodes - L.plane_full : INT64_MAX;
+        H.clamp = (int32_t)P->bc_flags;
+        H.agg = P->agg;
+        H.n_agg = P->n_agg;
+        H.box_begin = P->box_begin;
+        H.part_begin = P->box_begin >= 0 ? P->box_begin : P->blk_begin;
+        H.n_part = P->box_begin >= 0 ? P->n_agg : P->n_blk;
+        {
+            const mos_cell_desc &cd = e->roms[0]->desc;
+            H.h[0] = 1.0 / (cd.interp[0] - 1);
+            H.h[1] = cd.pitch_y / cd.pitch_x / (cd.interp[1] - 1);
+            H.h[2] = cd.height / cd.pitch_x / (cd.interp[2] - 1);
+        }
         H.dT = P->dT;
         H.lat = L;
         H.blk_begin = P->blk_begin;
@@ -1246,7 +1869,7 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
     MOS_HIP(hipEventRecord(e->mirror_ev, st));
     const int hw_blk = e->blk.high, hw_sb = e->sbs.high;
     hipLaunchKernelGGL(k_fill_owner, dim3(B.list.n), dim3(256), 0, st, B.list, (const ProbParams *)e->pp, e->blk_prob,
-                       e->sb_prob);
+                       e->sb_prob, e->box_prob);
     hipLaunchKernelGGL(k_setup_dofs, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
                        (const ProbParams *)e->pp, e->cmask, e->g, e->x64, e->inc);
     for (EngineProblem *P : adm) {
@@ -1264,7 +1887,8 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
         hipLaunchKernelGGL(k_prescribe_last, dim3(ceil_div(np, 256)), dim3(256), 0, st, (const int64_t *)pdof, np,
                            last);
         hipLaunchKernelGGL(k_prescribe, dim3(ceil_div(np, 256)), dim3(256), 0, st, (const int64_t *)pdof,
-                           (const double *)pval, np, (const int32_t *)last, e->cmask, e->g, e->x64, d0);
+                           (const double *)pval, np, (const int32_t *)last, e->cmask, e->g, e->x64, d0,
+                           whole_lattice(P->lat), P->agg);
     }
     const int64_t n_inc = (int64_t)hw_blk * DB / 3 * 4;
     hipLaunchKernelGGL(k_clear_incidence, dim3((unsigned)std::min<int64_t>(ceil_div(n_inc, 256), 4096)), dim3(256),
@@ -1275,7 +1899,7 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
                        e->precision == MOS_MIXED ? 4 : 8, e->ld_slots, e->ldk, n_slots);
     hipLaunchKernelGGL(k_incidence_sel, dim3(ceil_div(n_slots * e->S, 256)), dim3(256), 0, st, B.sel,
                        (const int32_t *)e->sb_prob, (const ProbParams *)e->pp, (const int32_t *)e->perm, e->inc,
-                       (const int32_t *)e->surf, e->S, n_slots);
+                       e->lc, e->cslot, (const uint8_t *)e->cmask, (const int32_t *)e->surf, e->S, n_slots);
     if (e->precision == MOS_MIXED)
         hipLaunchKernelGGL(k_rhs_diag<float>, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
                            (const ProbParams *)e->pp, (const double *const *)e->br_tab,
@@ -1286,6 +1910,11 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
                            (const ProbParams *)e->pp, (const double *const *)e->br_tab,
                            (const void *const *)e->kr64_tab, (const int32_t *)e->sb_rom, (const int32_t *)e->inc,
                            (const uint8_t *)e->cmask, e->b_raw, (double *)e->v[VDINV], e->ldk);
+    if (e->precond)
+        hipLaunchKernelGGL(k_coarse_setup, dim3(e->boxes.high, MAXA), dim3(256), 0, st, B.sel,
+                           (const int32_t *)e->box_prob, (const ProbParams *)e->pp, (const int32_t *)e->cslot,
+                           (const int32_t *)e->sb_rom, (const void *const *)e->kr64_tab, (const uint8_t *)e->cmask,
+                           (const int32_t *)e->surf, e->n, e->ldk, e->binv);
     MOS_LAUNCH_CHECK();
     // At set-up x = g, so one product A g gives both ||b_l|| and the residual.
     return residual_batch(e, B, true);
@@ -1303,10 +1932,18 @@ mos_status start_batch(mos_engine e, const Batch &B) {
     MOS_HIP(hipMemcpyAsync(e->sp, e->sp_host, hw_p * sizeof(SweepParams), hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_prob_start_list, dim3(ceil_div(B.list.n, 64)), dim3(64), 0, st, B.list,
                        (const ProbParams *)e->pp, (const SweepParams *)e->sp, e->ps, e->epoch);
-    hipLaunchKernelGGL(k_cgstart_sel<T>, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
-                       (const SweepParams *)e->sp, (const ProbState *)e->ps, (const double *)e->r64,
-                       (const T *)V[VDINV], (const int32_t *)e->inc, V[VX], V[VR], V[VP], V[VS], Mc, e->ld_slots,
-                       e->pg, e->pr, e->cap_blk);
+    if (e->precond)
+        hipLaunchKernelGGL(k_cgstart2<T>, dim3(e->boxes.high), dim3(e->box_nt), e->box_nt * 6 * sizeof(double), st,
+                           B.sel, (const int32_t *)e->box_prob, (const ProbParams *)e->pp, (const SweepParams *)e->sp,
+                           (const ProbState *)e->ps, (const double *)e->r64, (const T *)V[VDINV],
+                           (const int32_t *)e->inc, (const uint8_t *)e->cmask, (const uint32_t *)e->lc, V[VX], V[VR],
+                           V[VP], V[VS], Mc, e->ld_slots, e->pg, e->pr, (const double *)e->binv, e->cc,
+                           e->cap_blk);
+    else
+        hipLaunchKernelGGL(k_cgstart_sel<T>, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
+                           (const SweepParams *)e->sp, (const ProbState *)e->ps, (const double *)e->r64,
+                           (const T *)V[VDINV], (const int32_t *)e->inc, V[VX], V[VR], V[VP], V[VS], Mc,
+                           e->ld_slots, e->pg, e->pr, e->cap_blk);
     MOS_LAUNCH_CHECK();
     (void)hw_sb;
     (void)Y;
@@ -1320,11 +1957,12 @@ mos_status add_inner_batch(mos_engine e, const Batch &B, double sign) {
     const int hw_blk = e->blk.high;
     if (e->precision == MOS_MIXED)
         hipLaunchKernelGGL(k_add_inner_sel<float>, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
-                           (const SweepParams *)e->sp, e->x64, (const float *)e->v[VX], sign);
+                           (const ProbParams *)e->pp, (const SweepParams *)e->sp, e->x64, (const float *)e->v[VX],
+                           sign);
     else
         hipLaunchKernelGGL(k_add_inner_sel<double>, dim3(hw_blk), dim3(DB), 0, st, B.sel,
-                           (const int32_t *)e->blk_prob, (const SweepParams *)e->sp, e->x64,
-                           (const double *)e->v[VX], sign);
+                           (const int32_t *)e->blk_prob, (const ProbParams *)e->pp, (const SweepParams *)e->sp,
+                           e->x64, (const double *)e->v[VX], sign);
     MOS_LAUNCH_CHECK();
     return MOS_OK;
 }
@@ -1425,6 +2063,10 @@ mos_status decide_and_start(mos_engine e, const std::vector<EngineProblem *> &pr
 
 }  // namespace
 
+namespace {
+int64_t largest_box(mos_engine e, bool *fits);
+}  // namespace
+
 mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     mos_ctx ctx = e->ctx;
     const bool mixed = e->precision == MOS_MIXED;
@@ -1456,6 +2098,11 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     MOS_TRY(m.alloc_n(e->cap_sb, &e->sb_rom));
     MOS_TRY(m.alloc_n(e->cap_sb, &e->sb_prob));
     MOS_TRY(m.alloc_n(slots, &e->perm));
+    MOS_TRY(m.alloc_n(dofs / 3, &e->lc));
+    MOS_TRY(m.alloc_n(slots, &e->cslot));
+    MOS_TRY(m.alloc_n(e->cap_blk, &e->box_prob));
+    MOS_TRY(m.alloc_n((size_t)e->cap_blk * MAXA * 36, &e->binv));
+    MOS_TRY(m.alloc_n((size_t)e->cap_blk * MAXA * 6, &e->cc));
     MOS_TRY(m.alloc_n(MAX_PROBS, &e->ps));
     MOS_TRY(m.alloc_n(MAX_PROBS, &e->res2));
     MOS_TRY(m.alloc_n(MAX_PROBS, &e->bb2));
@@ -1525,6 +2172,7 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     fill32(e->sb_rom, e->cap_sb, 0xffffffffu);
     fill32(e->sb_prob, e->cap_sb, 0xffffffffu);  // -1: no owner (batched phases select by owner)
     fill32(e->perm, slots, 0xffffffffu);         // as its host mirror
+    fill32(e->box_prob, e->cap_blk, 0xffffffffu);
     fill32(e->ps, (int64_t)MAX_PROBS * sizeof(ProbState) / 4, 0u);
     MOS_LAUNCH_CHECK();
     std::vector<const void *> t64(MAX_TYPES, nullptr), t32(MAX_TYPES, nullptr), tb(MAX_TYPES, nullptr),
@@ -1546,10 +2194,47 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     // The GEMM variant is fixed per engine (never per batch), so a problem's
     // rounding does not depend on what else is in the batch.
     e->gemm_rows = ldk / 4 <= ROWS_MAX_KS;
+    {
+        bool fits = false;
+        largest_box(e, &fits);
+        MOS_TRY(engine_set_precond(e, e->precond && fits ? 1 : 0));
+    }
     e->tuner.configure(e->gemm_paths, e->gemm_split);
     e->blk.init(e->cap_blk);
     e->sbs.init(e->cap_sb);
     e->pids.init(MAX_PROBS);
+    e->boxes.init(e->cap_blk);
+    return MOS_OK;
+}
+
+namespace {
+// Nodes of the largest box (the corner box, with the closing nodes) and
+// whether the two-level kernels take it: one thread per node, a basis of at
+// most 256 DoFs in the set-up, packed coordinates below 256.
+int64_t largest_box(mos_engine e, bool *fits) {
+    const mos_cell_desc &cd = e->roms[0]->desc;
+    const int sx = cd.interp[0] - 1, sy = cd.interp[1] - 1, nz = cd.interp[2];
+    const int64_t max_nodes = sub_count(make_sub(BOX_CX * sx + 1, AGG_C * sy + 1, nz, sx, sy));
+    // The box kernels address the cell layouts with 32-bit byte offsets.
+    const bool small_layout = e->ld_slots == 0 || (uint64_t)e->ldk * e->ld_slots * 8 < (1ull << 32);
+    *fits = max_nodes <= 1024 && e->n <= 256 && AGG_C * sx < 256 && AGG_C * sy < 256 && nz < 256 && small_layout;
+    return max_nodes;
+}
+}  // namespace
+
+mos_status engine_set_precond(mos_engine e, int precond) {
+    bool fits = false;
+    const int64_t max_nodes = largest_box(e, &fits);
+    if (precond && !fits) {
+        set_error("the two-level preconditioner needs boxes of at most 1024 nodes and a basis of at most 256");
+        return MOS_EINVAL;
+    }
+    e->precond = precond;
+    e->box_nt = (int)std::max<int64_t>(CG_LW, round_up(max_nodes, 64));
+    // Jacobi alone keeps whole rows of cells per box (long rows of nodes
+    // give the update's gathers the fewest cache lines per wave).
+    e->box_cells[0] = precond ? BOX_CX : 4096;
+    e->box_cells[1] = AGG_C;
     return MOS_OK;
 }
 
@@ -1624,7 +2309,7 @@ mos_status release_problems(mos_engine e, const std::vector<EngineProblem *> &pr
     Batch B;
     for (EngineProblem *P : probs) B.add(P->pid);
     hipLaunchKernelGGL(k_release_list, dim3(16, B.list.n), dim3(256), 0, st, B.list, (const ProbParams *)e->pp,
-                       e->blk_prob, e->sb_rom, e->sb_prob, e->ps);
+                       e->blk_prob, e->sb_rom, e->sb_prob, e->box_prob, e->ps);
     MOS_LAUNCH_CHECK();
     MOS_TRY(mirror_wait(e));
     for (EngineProblem *P : probs) {
@@ -1633,6 +2318,7 @@ mos_status release_problems(mos_engine e, const std::vector<EngineProblem *> &pr
                   -1);
         P->dev.release();  // stream-ordered: later work on this stream may reuse it
         e->blk.give(P->blk_begin, P->n_blk);
+        if (P->box_begin >= 0) e->boxes.give(P->box_begin, P->n_agg);
         e->sbs.give(P->sb_begin, P->n_sb);
         e->pids.give(P->pid, 1);
     }
@@ -1648,6 +2334,16 @@ mos_status rows_step(mos_engine e, int ks, int hw_sb);
 template <class T>
 void cgstep_launch(mos_engine e, int hw_blk, T *const *V) {
     hipStream_t st = e->ctx->stream;
+    if (e->precond) {
+        const int hw_box = e->boxes.high;
+        launch_timed(e->ctx, MOS_K_PCG_UPDATE, k_cgstep2<T>, dim3((unsigned)(ceil_div(hw_box, N_XCD) * N_XCD)),
+                     dim3(e->box_nt), e->box_nt * 6 * sizeof(double), st, (const T *)e->Yi, (const int32_t *)e->inc,
+                     (const uint8_t *)e->cmask, (const T *)V[VDINV], (const uint32_t *)e->lc, V[VX], V[VR], V[VP],
+                     V[VS], (T *)e->Mc, e->ld_slots, (const int32_t *)e->box_prob, (const ProbParams *)e->pp, e->ps,
+                     e->pg, e->pr, (const double *)e->pdel, (const double *)e->binv, e->cc, e->epoch, e->cap_blk,
+                     hw_box);
+        return;
+    }
     const bool wide = e->update_width ? e->update_width == 256 : hw_blk <= CG_WIDE_MAX_BLK;
     const dim3 grid((unsigned)(ceil_div(hw_blk, N_XCD) * N_XCD));
     if (wide)
@@ -1798,9 +2494,20 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
             e->pids.give(pid, 1);
             break;
         }
+        int bx = -1;
+        if (e->precond) {
+            bx = e->boxes.take(P->n_agg);
+            if (bx < 0) {
+                e->sbs.give(sb, P->n_sb);
+                e->blk.give(b, P->n_blk);
+                e->pids.give(pid, 1);
+                break;
+            }
+        }
         P->pid = pid;
         P->blk_begin = b;
         P->sb_begin = sb;
+        P->box_begin = bx;
         e->queue.pop_front();
         e->active.push_back(P);
         admitted.push_back(P);
@@ -1927,8 +2634,9 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
         if (P->state == 2 || P->state == 3) {
             if (P->state == 2 && (P->vm || P->sig6) && !batch_recon) MOS_TRY(reconstruct_problem(e, P));
             if (P->state == 2 && P->u_out)
-                MOS_HIP(hipMemcpyAsync(P->u_out, e->x64 + (int64_t)P->blk_begin * DB, P->n_dofs * 8,
-                                       hipMemcpyDeviceToDevice, st));
+                hipLaunchKernelGGL(k_export_u, dim3(ceil_div(P->n_dofs, 256)), dim3(256), 0, st,
+                                   (const double *)(e->x64 + (int64_t)P->blk_begin * DB), P->u_out, P->n_dofs,
+                                   whole_lattice(P->lat), P->agg);
             e->finished[P->ticket] = P;
             gone.push_back(P);
             if (completed) completed->push_back(P->ticket);
@@ -2030,7 +2738,8 @@ mos_status engine_problem_size(mos_engine e, const mos_array_desc *d, int64_t *d
     const int nx = cd.interp[0], ny = cd.interp[1], nz = cd.interp[2];
     const int64_t X = (int64_t)d->nx_cells * (nx - 1) + 1, Y = (int64_t)d->ny_cells * (ny - 1) + 1;
     const int64_t nodes = X * Y * nz - (int64_t)d->nx_cells * d->ny_cells * (nx - 2) * (ny - 2) * (nz - 2);
-    *dofs = round_up(3 * nodes, DOF_ALIGN);
+    const Lattice L = make_lattice(d->nx_cells, d->ny_cells, nx, ny, nz);
+    *dofs = (int64_t)problem_blocks(3 * nodes, agg_count(make_agg_layout(L, e->box_cells[0], e->box_cells[1]))) * DB;
     const int64_t n_cells = (int64_t)d->nx_cells * d->ny_cells;
     std::vector<int64_t> count(e->roms.size(), 0);
     for (int64_t c = 0; c < n_cells; ++c) count[d->cell_type[c]]++;

@@ -46,6 +46,146 @@ __host__ __device__ inline int64_t node_id(const Lattice &L, int64_t I, int64_t 
     return base + (J % (L.ny - 1) == 0 ? I : I / (L.nx - 1));
 }
 
+// A box of the node lattice, wx x wy points per plane over Z planes, whose
+// origin lies on a cell corner: its point (i, j, K) is a node when i is a
+// multiple of sx, j a multiple of sy, or K is the bottom or top plane.  Nodes
+// are ranked in (K, j, i) order.  The whole lattice is the box X x Y; the
+// closed form of node_id is this rank for it.
+struct SubLattice {
+    int32_t wx, wy, Z, sx, sy;
+    int32_t fc, fr;  // columns (i % sx == 0) and rows (j % sy == 0) of nodes present in every plane
+    int64_t pf, pm;  // nodes of the bottom or top plane, and of an interior plane
+};
+
+__host__ __device__ inline SubLattice make_sub(int wx, int wy, int Z, int sx, int sy) {
+    SubLattice s;
+    s.wx = wx;
+    s.wy = wy;
+    s.Z = Z;
+    s.sx = sx;
+    s.sy = sy;
+    s.fc = (wx + sx - 1) / sx;
+    s.fr = (wy + sy - 1) / sy;
+    s.pf = (int64_t)wx * wy;
+    s.pm = (int64_t)s.fr * wx + (int64_t)(wy - s.fr) * s.fc;
+    return s;
+}
+
+__host__ __device__ inline int64_t sub_count(const SubLattice &s) { return 2 * s.pf + (int64_t)(s.Z - 2) * s.pm; }
+
+__host__ __device__ inline int64_t sub_encode(const SubLattice &s, int i, int j, int K) {
+    if (K == 0) return (int64_t)j * s.wx + i;
+    if (K == s.Z - 1) return s.pf + (int64_t)(s.Z - 2) * s.pm + (int64_t)j * s.wx + i;
+    const int fb = (j + s.sy - 1) / s.sy;  // full rows below row j
+    const int64_t base = s.pf + (int64_t)(K - 1) * s.pm + (int64_t)fb * s.wx + (int64_t)(j - fb) * s.fc;
+    return base + (j % s.sy == 0 ? i : i / s.sx);
+}
+
+__host__ __device__ inline void sub_decode(const SubLattice &s, int64_t id, int &i, int &j, int &K) {
+    const int64_t top = s.pf + (int64_t)(s.Z - 2) * s.pm;
+    if (id < s.pf || id >= top) {
+        const int64_t t = id < s.pf ? id : id - top;
+        K = id < s.pf ? 0 : s.Z - 1;
+        j = (int)(t / s.wx);
+        i = (int)(t % s.wx);
+        return;
+    }
+    int64_t t = id - s.pf;
+    K = 1 + (int)(t / s.pm);
+    t %= s.pm;
+    // Rows repeat with period sy: one full row, then sy - 1 rows of fc nodes.
+    const int64_t period = s.wx + (int64_t)(s.sy - 1) * s.fc;
+    const int q = (int)(t / period);
+    const int64_t u = t % period;
+    if (u < s.wx) {
+        j = q * s.sy;
+        i = (int)u;
+    } else {
+        j = q * s.sy + 1 + (int)((u - s.wx) / s.fc);
+        i = (int)((u - s.wx) % s.fc) * s.sx;
+    }
+}
+
+__host__ __device__ inline SubLattice whole_lattice(const Lattice &L) {
+    return make_sub((int)L.X, (int)L.Y, (int)L.Z, L.nx - 1, L.ny - 1);
+}
+
+// Internal node order of an array inside the solver: the array is cut into
+// boxes of cx x cy cells (the last box of a row or column takes what is
+// left, and the closing nodes of the array), and each box's nodes form one
+// consecutive range, boxes in (gy, gx) order and nodes within a box in
+// (K, j, i) order.  A node belongs to the box that holds it: boxes start on
+// cell boundaries and end before the next box's first column or row.  One
+// workgroup owns a box's DoFs, so the coarse correction of the
+// preconditioner over the aggregates inside a box needs no other workgroup.
+struct AggLayout {
+    int32_t nax, nay, cx, cy, sx, sy, Z;
+    int32_t wxi, wxl, wyi, wyl;  // box widths of inner and last aggregates
+    int64_t row;                 // nodes of a row of aggregates of inner height
+};
+
+__host__ __device__ inline AggLayout make_agg_layout(const Lattice &L, int cx, int cy) {
+    AggLayout a;
+    a.cx = cx;
+    a.cy = cy;
+    a.sx = L.nx - 1;
+    a.sy = L.ny - 1;
+    a.Z = (int)L.Z;
+    a.nax = (L.Nx + cx - 1) / cx;
+    a.nay = (L.Ny + cy - 1) / cy;
+    a.wxi = cx * a.sx;
+    a.wyi = cy * a.sy;
+    a.wxl = (L.Nx - cx * (a.nax - 1)) * a.sx + 1;
+    a.wyl = (L.Ny - cy * (a.nay - 1)) * a.sy + 1;
+    a.row = (int64_t)(a.nax - 1) * sub_count(make_sub(a.wxi, a.wyi, a.Z, a.sx, a.sy)) +
+            sub_count(make_sub(a.wxl, a.wyi, a.Z, a.sx, a.sy));
+    return a;
+}
+
+__host__ __device__ inline int agg_count(const AggLayout &a) { return a.nax * a.nay; }
+
+// Box of aggregate (gx, gy).
+__host__ __device__ inline SubLattice agg_box(const AggLayout &a, int gx, int gy) {
+    return make_sub(gx == a.nax - 1 ? a.wxl : a.wxi, gy == a.nay - 1 ? a.wyl : a.wyi, a.Z, a.sx, a.sy);
+}
+
+// First internal node of aggregate (gx, gy).
+__host__ __device__ inline int64_t agg_first(const AggLayout &a, int gx, int gy) {
+    const int wy = gy == a.nay - 1 ? a.wyl : a.wyi;
+    return (int64_t)gy * a.row + (int64_t)gx * sub_count(make_sub(a.wxi, wy, a.Z, a.sx, a.sy));
+}
+
+__host__ __device__ inline int agg_x(const AggLayout &a, int64_t I) {
+    const int g = (int)(I / a.wxi);
+    return g < a.nax - 1 ? g : a.nax - 1;
+}
+__host__ __device__ inline int agg_y(const AggLayout &a, int64_t J) {
+    const int g = (int)(J / a.wyi);
+    return g < a.nay - 1 ? g : a.nay - 1;
+}
+
+// Internal node id of lattice node (I, J, K).
+__host__ __device__ inline int64_t agg_encode(const AggLayout &a, int64_t I, int64_t J, int K) {
+    const int gx = agg_x(a, I), gy = agg_y(a, J);
+    return agg_first(a, gx, gy) +
+           sub_encode(agg_box(a, gx, gy), (int)(I - (int64_t)gx * a.wxi), (int)(J - (int64_t)gy * a.wyi), K);
+}
+
+// Lattice point (I, J, K) of internal node id.
+__host__ __device__ inline void agg_decode(const AggLayout &a, int64_t id, int64_t &I, int64_t &J, int &K) {
+    int gy = (int)(id / a.row);
+    if (gy > a.nay - 1) gy = a.nay - 1;
+    const int64_t rem = id - (int64_t)gy * a.row;
+    const int wy = gy == a.nay - 1 ? a.wyl : a.wyi;
+    const int64_t per = sub_count(make_sub(a.wxi, wy, a.Z, a.sx, a.sy));
+    int gx = (int)(rem / per);
+    if (gx > a.nax - 1) gx = a.nax - 1;
+    int i, j;
+    sub_decode(agg_box(a, gx, gy), rem - (int64_t)gx * per, i, j, K);
+    I = (int64_t)gx * a.wxi + i;
+    J = (int64_t)gy * a.wyi + j;
+}
+
 constexpr int MAX_TYPES = 8;
 // Surface nodes per cell are bounded so a (slot, surface node) pair packs
 // into one int32 as slot << INC_SHIFT | s.

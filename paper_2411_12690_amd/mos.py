@@ -30,6 +30,7 @@ MOS_OPT_CELL_GEMM = 1
 GEMM_AUTO, GEMM_TILES, GEMM_ROWS, GEMM_ROWS_LDS = 0, 1, 2, 3
 MOS_OPT_GEMM_SPLIT = 2
 MOS_OPT_UPDATE_WIDTH = 3
+MOS_OPT_PRECOND = 4
 
 
 class MosError(RuntimeError):
@@ -278,7 +279,7 @@ class Engine:
     """Batched / served global stage (mos_engine_*): submit problems, call
     progress() until their tickets complete."""
 
-    def __init__(self, ctx, roms, mixed=False, device_bytes=8 << 30, gemm=None):
+    def __init__(self, ctx, roms, mixed=False, device_bytes=8 << 30, gemm=None, precond=None):
         self.ctx = ctx
         self.roms = list(roms)
         self.mixed = mixed
@@ -290,6 +291,8 @@ class Engine:
         self.ptr = h
         if gemm is not None:
             self.option(MOS_OPT_CELL_GEMM, gemm)
+        if precond is not None:
+            self.option(MOS_OPT_PRECOND, precond)
 
     def submit(self, nx_cells, ny_cells, cell_type, delta_T, vm=None, sigma6=None, u=None, **kw):
         d, keep = array_desc(nx_cells, ny_cells, cell_type, delta_T, mixed=self.mixed, **kw)

@@ -52,9 +52,9 @@ def n_dofs_of(nx, ny):
 
 
 def run_engine(env, probs, mixed=False, budget=1 << 28, iterations=16, interleave=None, gemm=None, split=None,
-               width=None):
+               width=None, precond=None):
     mos, ctx, roms, oroms, torch = env
-    eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=budget, gemm=gemm)
+    eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=budget, gemm=gemm, precond=precond)
     if split is not None:
         eng.option(mos.MOS_OPT_GEMM_SPLIT, split)
     if width is not None:
@@ -170,12 +170,76 @@ def test_gemm_work_split_never_changes_results(env, mixed):
 
 @pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "mixed"])
 def test_update_width_never_changes_results(env, mixed):
-    """The vector update in workgroups of 256 threads (one DoF each) or 128
-    (two each) sums the same partials in the same order."""
+    """The Jacobi vector update in workgroups of 256 threads (one DoF each)
+    or 128 (two each) sums the same partials in the same order."""
     probs = problems(6, [(4, 3), (6, 5), (2, 2)])
-    ref = run_engine(env, probs, mixed=mixed, width=256)
-    res = run_engine(env, probs, mixed=mixed, width=128)
+    ref = run_engine(env, probs, mixed=mixed, width=256, precond=0)
+    res = run_engine(env, probs, mixed=mixed, width=128, precond=0)
     for a, b in zip(ref, res):
         assert a[2] == b[2] and a[3] == b[3]
         assert np.array_equal(a[5], b[5])
         assert np.array_equal(a[4], b[4])
+
+
+# Arrays whose boxes and aggregates end ragged: 13 = 6 + 6 + 1 cells per row
+# of boxes, odd sizes leave one-cell aggregates, 1 x n and n x 1 strips.
+RAGGED = [(13, 3), (7, 5), (1, 6), (9, 1), (2, 2), (6, 4)]
+
+
+@pytest.mark.parametrize("precond", [0, 1], ids=["jacobi", "two-level"])
+@pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "mixed"])
+def test_both_preconditioners_match_oracle(env, precond, mixed):
+    """Jacobi and Jacobi plus the aggregate coarse correction converge to the
+    oracle's solution (to the FP64 tolerance, or the mixed-precision bound
+    on von Mises stress)."""
+    mos, ctx, roms, oroms, torch = env
+    probs = problems(7, RAGGED)
+    res = run_engine(env, probs, mixed=mixed, precond=precond)
+    for (nx, ny, t, dT), (st, rel, it, sw, vm, u) in zip(probs, res):
+        assert st == 0
+        u_ref, vm_ref = oracle_solution(oroms, nx, ny, t, dT)
+        if mixed:
+            assert rel <= 1e-10
+            assert np.abs(vm - vm_ref).max() <= 1e-3 * np.abs(vm_ref).max()
+        else:
+            assert rel <= 1e-12
+            assert np.abs(u - u_ref).max() <= 1e-10 * np.abs(u_ref).max()
+            assert np.abs(vm - vm_ref).max() <= 1e-9 * np.abs(vm_ref).max()
+
+
+def test_coarse_correction_cuts_iterations(env):
+    """On arrays of several aggregates the coarse correction needs clearly
+    fewer PCG iterations than Jacobi alone for the same tolerance."""
+    probs = problems(8, [(12, 10), (9, 7)])
+    jac = run_engine(env, probs, precond=0)
+    two = run_engine(env, probs, precond=1)
+    for a, b in zip(jac, two):
+        assert a[0] == 0 and b[0] == 0
+        assert b[2] < 0.85 * a[2], (a[2], b[2])
+
+
+def test_two_level_alone_and_in_the_mix(env):
+    """The coarse correction works per box, so a problem's bits do not depend
+    on what else is in the batch (ragged sizes included)."""
+    probs = problems(9, RAGGED)
+    mix = run_engine(env, probs, mixed=True, precond=1)
+    for i in (0, 1, 3):
+        alone = run_engine(env, [probs[i]], mixed=True, precond=1)[0]
+        assert np.array_equal(alone[5], mix[i][5])
+        assert np.array_equal(alone[4], mix[i][4])
+        assert alone[2] == mix[i][2]
+
+
+def test_preconditioner_option_rules(env):
+    mos, ctx, roms, oroms, torch = env
+    eng = mos.Engine(ctx, roms, device_bytes=1 << 26)
+    with pytest.raises(mos.MosError) as e:
+        eng.option(mos.MOS_OPT_PRECOND, 2)
+    assert e.value.status == mos.MOS_EINVAL
+    eng.option(mos.MOS_OPT_PRECOND, 0)
+    eng.option(mos.MOS_OPT_PRECOND, 1)
+    eng.submit(2, 2, np.zeros(4), -250.0)
+    with pytest.raises(mos.MosError) as e:
+        eng.option(mos.MOS_OPT_PRECOND, 0)
+    assert e.value.status == mos.MOS_EBUSY
+    eng.close()
