@@ -73,9 +73,11 @@ constexpr int ROWS_MAX_KS = 44;
 // Online tuner of the rows GEMM's work split (slot blocks per wave).  The
 // split only decides which wave computes which output tile -- every tile is
 // still one wave's fixed-order MFMA chain -- so tuning never changes results.
-// Per bucket of active slot blocks (power of two), each candidate is timed
-// REPS times with stream events around its launch; the fastest (minimum
-// time) is then used for that bucket for the life of the engine.
+// Per bucket of slot blocks (power of two of the high-water mark), tuning
+// rounds run every candidate back to back within one iteration, on the same
+// operands and the same set of iterating problems, each timed with stream
+// events; after REPS rounds the fastest (minimum time) is used for that
+// bucket for the life of the engine.
 struct GemmTuner {
     // A candidate is an operand path of the K_r-stationary GEMM (0: operands
     // streamed per wave from global memory, 1: operand tile staged in LDS

@@ -2358,27 +2358,6 @@ void cgstep_launch(mos_engine e, int hw_blk, T *const *V) {
                      (const double *)e->pdel, e->epoch, e->cap_blk, hw_blk);
 }
 
-// Pick the rows-GEMM candidate (operand path, work split) for `n_sb` active
-// slot blocks; *trial is set when this launch is a tuning trial (its events
-// are then recorded by the caller around the launch).
-int tuner_pick(GemmTuner &T, int n_sb, bool *trial) {
-    *trial = false;
-    if (T.n_cand <= 1) return 0;
-    int bucket = 0;
-    while ((1 << bucket) < n_sb) ++bucket;
-    GemmTuner::Bucket &B = T.buckets[bucket];
-    if (B.chosen > 0) return B.chosen - 1;
-    for (int k = 0; k < T.n_cand; ++k) {
-        int queued = 0;
-        for (const auto &pd : T.pending) queued += pd.bucket == bucket && pd.cand == k;
-        if (B.runs[k] + queued < GemmTuner::REPS) {
-            *trial = true;
-            return k;
-        }
-    }
-    return 0;  // all trials queued, results not read yet
-}
-
 // Read the tuning trials of the last chunk (the stream has been synchronised).
 void tuner_collect(GemmTuner &T) {
     for (auto &pd : T.pending) {
@@ -2448,27 +2427,37 @@ hipEvent_t tuner_event(GemmTuner &T) {
 template <class T>
 mos_status rows_step(mos_engine e, int ks, int hw_sb) {
     hipStream_t st = e->ctx->stream;
-    bool trial = false;
-    const int cand = tuner_pick(e->tuner, hw_sb, &trial);
-    const int spw = e->tuner.cand_spw[cand];
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (trial) {
-        ev0 = tuner_event(e->tuner);
-        ev1 = tuner_event(e->tuner);
-        if (ev0 && ev1) MOS_HIP(hipEventRecord(ev0, st));
-    }
+    GemmTuner &Tn = e->tuner;
     const void *const *tab = (const void *const *)(sizeof(T) == 4 ? e->kr32_tab : e->kr64_tab);
-    MOS_TRY(launch_cell_gemm<T>(e->ctx, MOS_K_CELL_GEMM, e->tuner.cand_path[cand], ks, spw, st, tab, e->sb_rom,
-                                e->sb_prob, (const T *)e->Mc, (T *)e->Yi, e->ld_slots, hw_sb,
-                                (const ProbState *)e->ps, e->pdel, 1, ProbSel{}));
-    if (trial && ev0 && ev1) {
+    auto launch = [&](int cand) {
+        return launch_cell_gemm<T>(e->ctx, MOS_K_CELL_GEMM, Tn.cand_path[cand], ks, Tn.cand_spw[cand], st, tab,
+                                   e->sb_rom, e->sb_prob, (const T *)e->Mc, (T *)e->Yi, e->ld_slots, hw_sb,
+                                   (const ProbState *)e->ps, e->pdel, 1, ProbSel{});
+    };
+    if (Tn.n_cand <= 1) return launch(0);
+    int bucket = 0;
+    while ((1 << bucket) < hw_sb) ++bucket;
+    GemmTuner::Bucket &B = Tn.buckets[bucket];
+    if (B.chosen > 0) return launch(B.chosen - 1);
+    // Tuning round: every candidate still short of its trials runs on the
+    // same operands, back to back, so all of them see the same set of
+    // iterating problems (they write identical outputs); one untimed launch
+    // first, so the first timed one does not wait for the host.
+    MOS_TRY(launch(0));
+    for (int k = 0; k < Tn.n_cand; ++k) {
+        int queued = 0;
+        for (const auto &pd : Tn.pending) queued += pd.bucket == bucket && pd.cand == k;
+        if (B.runs[k] + queued >= GemmTuner::REPS) continue;
+        hipEvent_t ev0 = tuner_event(Tn), ev1 = tuner_event(Tn);
+        if (!ev0 || !ev1) {
+            if (ev0) Tn.spare.push_back(ev0);
+            if (ev1) Tn.spare.push_back(ev1);
+            continue;
+        }
+        MOS_HIP(hipEventRecord(ev0, st));
+        MOS_TRY(launch(k));
         MOS_HIP(hipEventRecord(ev1, st));
-        int bucket = 0;
-        while ((1 << bucket) < hw_sb) ++bucket;
-        e->tuner.pending.push_back({bucket, cand, ev0, ev1});
-    } else {
-        if (ev0) e->tuner.spare.push_back(ev0);
-        if (ev1) e->tuner.spare.push_back(ev1);
+        Tn.pending.push_back({bucket, k, ev0, ev1});
     }
     return MOS_OK;
 }
