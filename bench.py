@@ -49,23 +49,41 @@ def quiet_gc():
     gc.freeze()
 
 
-def per_iteration_work(kernel, mos, n, n_cells, n_dofs_pad, n_nodes, mixed):
+def coarse_aggregates(nx, ny, box=6, agg=2):
+    """Aggregates of the two-level preconditioner in an nx x ny array: boxes
+    of box x agg cells, each cut into aggregates of agg x agg cells (the last
+    box of a row, and its last aggregate, take what is left)."""
+    nax, nay = -(-nx // box), -(-ny // agg)
+    per_row = (nax - 1) * (box // agg) + -(-(nx - box * (nax - 1)) // agg)
+    return per_row * nay
+
+
+def per_iteration_work(kernel, mos, n, n_cells, n_dofs_pad, n_nodes, mixed, precond=1, n_dofs=None, n_agg=0):
     """Algorithmic work of one PCG iteration of one problem in the kernel."""
     w = 4 if mixed else 8
     if kernel == mos.MOS_K_CELL_GEMM:
         return 2.0 * n * n * n_cells
     if kernel == mos.MOS_K_PCG_UPDATE:
-        # cell products gathered + next u scattered to the cell layout;
-        # r, p, s, x, D^-1 read and x, r, p, s written per DoF, constraint
-        # mask byte; incidence (four int32) per node
+        if precond:
+            # cell products gathered + next u scattered to the cell layout;
+            # r, p, s, x, D^-1 read and x, r, p, s written per DoF; incidence
+            # (four int32) and packed coordinates (one int32) per node;
+            # B^-1 (36 doubles) read and six coefficients read and written
+            # per aggregate
+            return 2.0 * n * n_cells * w + n_dofs * 9 * w + n_nodes * 20 + n_agg * (36 + 12) * 8
+        # Jacobi: the same without coordinates and aggregates, plus the
+        # constraint mask byte, over the padded DoF blocks
         return 2.0 * n * n_cells * w + n_dofs_pad * (9 * w + 1) + n_nodes * 16
     raise ValueError(kernel)
 
 
+UPDATE_NOTE = {1: "2 n w per cell + 9 w per DoF + 20 per node + 384 per aggregate and iteration "
+                  "(two-level update)",
+               0: "2 n w per cell + (9 w + 1) per DoF + 16 per node and iteration (Jacobi update)"}
 KERNEL_INFO = {  # kernel id -> (name, bound, unit, note)
     1: ("k_bgemm", "mfma", "TFLOP/s", "2 n^2 flops per cell and iteration (K_r GEMM of the PCG matvec)"),
     2: ("k_cg_scalars", "latency", "us", "per-problem fixed-order reductions and CG step"),
-    3: ("k_cgstep", "hbm", "GB/s", "2 n w per cell + (9 w + 1) per DoF + 16 per node and iteration"),
+    3: ("k_cgstep", "hbm", "GB/s", UPDATE_NOTE[1]),
     4: ("k_recon", "mfma", "TFLOP/s", "2*6*n_elem*n flops per cell (stress GEMM; the BF16 form issues 3x "
         "these on MFMA for its hi/lo split)"),
 }
@@ -148,6 +166,8 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False, vm_ref=None):
     eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=int(B * (n_dofs_pad * 140 + n_cells * 16 * 176 * 34)
                                                              * 1.3) + (64 << 20), gemm=args.cell_gemm,
                      precond=args.precond)
+    # The workload's cells fit the two-level kernels, so the engine's default is on.
+    precond = 1 if args.precond is None else args.precond
     if args.gemm_split is not None:
         eng.option(mos.MOS_OPT_GEMM_SPLIT, args.gemm_split)
     vms = [torch.empty((n_cells, n_elem), dtype=torch.float32 if mixed else torch.float64, device="cuda")
@@ -210,11 +230,14 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False, vm_ref=None):
     sweeps = [v[2] for r in recs for v in r.values()]
 
     name, bound, unit, note = KERNEL_INFO[dominant]
+    if dominant == mos.MOS_K_PCG_UPDATE:
+        note = UPDATE_NOTE[precond]
     if dominant == mos.MOS_K_RECON:
         work = 2.0 * 6 * n_elem * n * n_cells * B * args.steps
         peak = PEAK_BF16_TFLOPS if mixed else PEAK_FP64_TFLOPS
     else:
-        per_it = per_iteration_work(dominant, mos, n, n_cells, n_dofs_pad, n_nodes, mixed)
+        per_it = per_iteration_work(dominant, mos, n, n_cells, n_dofs_pad, n_nodes, mixed, precond, n_dofs,
+                                    coarse_aggregates(16, 16))
         work = per_it * sum(iters)
         if bound == "mfma":
             peak = PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS
@@ -271,7 +294,8 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False, vm_ref=None):
                    "tsv_diameter_um": "per array from {4,5,6}", "interp": list(spec0.interp), "n": n,
                    "reduced_dofs_per_array": int(n_dofs), "delta_T": -250.0, "bc": "bottom clamped",
                    "precision": precision, "seed": args.seed, "pcg_chunk": args.chunk,
-                   "gemm_split": args.gemm_split if args.gemm_split is not None else "tuned"},
+                   "gemm_split": args.gemm_split if args.gemm_split is not None else "tuned",
+                   "preconditioner": "jacobi" if precond == 0 else "jacobi + aggregate coarse correction"},
         "p50_ms": round(float(np.percentile(lat, 50)), 4),
         "p99_ms": round(float(np.percentile(lat, 99)), 4),
         "step_ms": [round(ev[s].elapsed_time(ev[s + 1]), 3) for s in range(args.steps)],
@@ -351,6 +375,7 @@ def single_mode(args, mos, torch, np, W):
         w = 4 if mixed else 8
         budget = int((n_dofs_pad * 160 + n_cells * 16 * 176 * (2 * w + 24)) * 1.3) + (256 << 20)
         eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=budget, gemm=args.cell_gemm, precond=args.precond)
+        precond = 1 if args.precond is None else args.precond
         if args.gemm_split is not None:
             eng.option(mos.MOS_OPT_GEMM_SPLIT, args.gemm_split)
         vm = torch.empty((n_cells, n_elem), dtype=torch.float32 if mixed else torch.float64, device="cuda")
@@ -381,11 +406,14 @@ def single_mode(args, mos, torch, np, W):
         if st != 0:
             raise RuntimeError(f"{prec} solve failed with status {st}: {eng.last_error}")
         name, bound, unit, note = KERNEL_INFO[dominant]
+        if dominant == mos.MOS_K_PCG_UPDATE:
+            note = UPDATE_NOTE[precond]
         if dominant == mos.MOS_K_RECON:
             work = 2.0 * 6 * n_elem * n * n_cells * args.steps
             peak = PEAK_BF16_TFLOPS if mixed else PEAK_FP64_TFLOPS
         else:
-            work = per_iteration_work(dominant, mos, n, n_cells, n_dofs_pad, n_nodes, mixed) * \
+            work = per_iteration_work(dominant, mos, n, n_cells, n_dofs_pad, n_nodes, mixed, precond, n_dofs,
+                                      coarse_aggregates(case.nx_cells, case.ny_cells)) * \
                 sum(r[2] for r in res)
             peak = (PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS) if bound == "mfma" else PEAK_HBM_GBS
         avg_s = k_ms / max(launches, 1) / 1e3
@@ -427,6 +455,7 @@ def single_mode(args, mos, torch, np, W):
                    "dummy_cells": int((case.cell_type != 0).sum()), "liner_um": sp.liner_thickness,
                    "bc": "Fourier field on all outer faces" if case.field is not None else "bottom clamped",
                    "delta_T": case.delta_T, "seed": args.seed, "pcg_chunk": args.chunk,
+                   "preconditioner": "jacobi" if args.precond == 0 else "jacobi + aggregate coarse correction",
                    "precision": "mixed (headline) and fp64"},
         "mixed": paths["mixed"],
         "fp64": paths["fp64"],
@@ -535,7 +564,8 @@ def serve_mode(args, mos, torch, np, W):
                    "requests": len(reqs), "rate_hz": 200, "N": "U{4..48}", "pitch_um": pitches,
                    "delta_T": "U[-300,-150]", "dummy_fraction": 0.1, "cell_mesh": [16, 16, 32],
                    "interp": [4, 4, 4], "precision": "mixed", "budget_gb": args.budget_gb,
-                   "pcg_chunk": args.chunk},
+                   "pcg_chunk": args.chunk,
+                   "preconditioner": "jacobi" if args.precond == 0 else "jacobi + aggregate coarse correction"},
         "p50_ms": round(float(np.percentile(lat, 50)), 3),
         "p99_ms": round(float(np.percentile(lat, 99)), 3),
         "offered_cells_per_s": round(sum(c.n_cells for c in cases) / (reqs[-1].arrival_s + 1e-9), 1),

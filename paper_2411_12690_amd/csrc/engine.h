@@ -156,7 +156,7 @@ struct mos_engine_s {
     // per problem cell -> slot, per box owner, B^-1 and kept coefficients.
     uint32_t *lc = nullptr;                   // [dofs/3]
     int32_t *cslot = nullptr;                 // [ld_slots], at sb_begin * 16 + cell
-    int32_t *box_prob = nullptr;              // [cap_blk]
+    int4 *box_tab = nullptr;                  // [cap_blk]: first node, nodes, aggregates, owner (-1 free)
     double *binv = nullptr;                   // [cap_blk][MAXA][36]
     double *cc = nullptr;                     // [cap_blk][MAXA][6]
     // Pinned host mirrors of sb_rom and perm: set-up writes a problem's

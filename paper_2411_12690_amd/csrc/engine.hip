@@ -675,14 +675,14 @@ __device__ __forceinline__ void cell_scatter32(T *Mc, const int4 &iv, int ci, ui
 // Owner and type tables of the listed problems' blocks back to -1, problems
 // inactive; grid (any, problems).
 __global__ __launch_bounds__(256) void k_release_list(PidList L, const ProbParams *pp, int32_t *blk_prob,
-                                                      int32_t *sb_rom, int32_t *sb_prob, int32_t *box_prob,
+                                                      int32_t *sb_rom, int32_t *sb_prob, int4 *box_tab,
                                                       ProbState *ps) {
     const int p = L.pid[blockIdx.y];
     const ProbParams &P = pp[p];
     const int t0 = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
     for (int i = t0; i < P.n_blk; i += stride) blk_prob[P.blk_begin + i] = -1;
     if (P.box_begin >= 0)
-        for (int i = t0; i < P.n_agg; i += stride) box_prob[P.box_begin + i] = -1;
+        for (int i = t0; i < P.n_agg; i += stride) box_tab[P.box_begin + i] = make_int4(-1, -1, -1, -1);
     for (int i = t0; i < P.n_sb; i += stride) {
         sb_rom[P.sb_begin + i] = -1;
         sb_prob[P.sb_begin + i] = -1;
@@ -903,13 +903,15 @@ __device__ __forceinline__ int64_t inner_index(const ProbParams &P, int64_t node
     return P.d0 + 3 * first + ci * nn + (node - first);
 }
 
-// Scalar step computed by one workgroup of at least CG_LW threads (threads
-// beyond CG_LW idle): the same sums, in the same order, as
-// cg_scalars_block<CG_LW>.
+// Scalar step computed by one box workgroup of at least CG_LW threads
+// (threads beyond CG_LW idle).  Every box workgroup of a problem sums its
+// partials in the same order, so all get the same bits.
 __device__ CgStep cg_scalars_wide(const ProbState &S, int it, const double *pg, const double *pr,
                                   const double *pdel, double (*red)[CG_LW]) {
     const int t = threadIdx.x;
     if (t < CG_LW) {
+        // Lane t sums partials t, t + CG_LW, ...; a butterfly per wave; the
+        // waves' sums in order (one barrier).
         double g = 0.0, r = 0.0, dl = 0.0;
 #pragma unroll 4
         for (int i = S.blk_begin + t; i < S.blk_end; i += CG_LW) {
@@ -918,20 +920,27 @@ __device__ CgStep cg_scalars_wide(const ProbState &S, int it, const double *pg, 
         }
 #pragma unroll 4
         for (int i = S.tile_begin + t; i < S.tile_end; i += CG_LW) dl += pdel[i];
-        red[0][t] = g;
-        red[1][t] = r;
-        red[2][t] = dl;
+        for (int m = 32; m >= 1; m >>= 1) {
+            g += __shfl_xor(g, m);
+            r += __shfl_xor(r, m);
+            dl += __shfl_xor(dl, m);
+        }
+        if (t % 64 == 0) {
+            red[0][t / 64] = g;
+            red[1][t / 64] = r;
+            red[2][t / 64] = dl;
+        }
     }
     __syncthreads();
-    for (int m = CG_LW / 2; m > 0; m >>= 1) {
-        if (t < m)
-            for (int j = 0; j < 3; ++j) red[j][t] += red[j][t + m];
-        __syncthreads();
+    double sum[3];
+    for (int j = 0; j < 3; ++j) {
+        sum[j] = red[j][0];
+        for (int w = 1; w < CG_LW / 64; ++w) sum[j] += red[j][w];
     }
     CgStep o;
-    o.gamma = red[0][0];
-    o.rr = red[1][0];
-    const double delta = red[2][0];
+    o.gamma = sum[0];
+    o.rr = sum[1];
+    const double delta = sum[2];
     o.tol2 = it == S.seg_start ? S.rtol2 * o.rr : S.tol2;
     o.stop = 0;
     o.alpha = o.beta = 0.0;
@@ -1053,7 +1062,7 @@ __device__ __forceinline__ void box_coarse_finish(BoxShared &sh, double (*qn)[6]
 template <class T>
 __global__ __launch_bounds__(1024) void k_cgstep2(const T *Y, const int32_t *inc, const uint8_t *cmask,
                                                   const T *dinv, const uint32_t *lc, T *x, T *r, T *p, T *s, T *Mc,
-                                                  int ld_slots, const int32_t *box_prob, const ProbParams *pp,
+                                                  int ld_slots, const int4 *box_tab, const ProbParams *pp,
                                                   ProbState *ps, double *pg, double *pr, const double *pdel,
                                                   const double *binv, double *cc, int epoch, int cap_blk,
                                                   int n_box) {
@@ -1068,12 +1077,13 @@ __global__ __launch_bounds__(1024) void k_cgstep2(const T *Y, const int32_t *inc
     const int per = (n_box + N_XCD - 1) / N_XCD;
     const int bs = (int)(blockIdx.x % N_XCD) * per + (int)(blockIdx.x / N_XCD);
     if (bs >= n_box) return;
-    const int pb = box_prob[bs];
+    // The box's first node, node count, aggregates and owner, in one load.
+    const int4 bt = box_tab[bs];
+    const int pb = bt.w;
     if (pb < 0) return;
     const ProbParams &P = pp[pb];
-    int64_t first;
-    int nn, na;
-    box_geometry(P, bs - P.box_begin, first, nn, na);
+    const int64_t first = bt.x;
+    const int nn = bt.y, na = bt.z;
     const int t = threadIdx.x;
     const bool act = t < nn;
     // Uniform bases of the box and 32-bit lane offsets, so every vector
@@ -1150,7 +1160,7 @@ __global__ __launch_bounds__(1024) void k_cgstep2(const T *Y, const int32_t *inc
 // cleared or rescaled, u = M^-1 r to the cell layout and the partials of the
 // sweep's first iteration.
 template <class T>
-__global__ __launch_bounds__(1024) void k_cgstart2(ProbSel sel, const int32_t *box_prob, const ProbParams *pp,
+__global__ __launch_bounds__(1024) void k_cgstart2(ProbSel sel, const int4 *box_tab, const ProbParams *pp,
                                                    const SweepParams *sp, const ProbState *ps, const double *r64,
                                                    const T *dinv, const int32_t *inc, const uint8_t *cmask,
                                                    const uint32_t *lc, T *x, T *r, T *p, T *s, T *Mc, int ld_slots,
@@ -1160,12 +1170,12 @@ __global__ __launch_bounds__(1024) void k_cgstart2(ProbSel sel, const int32_t *b
     double(*qn)[6] = reinterpret_cast<double(*)[6]>(qn_dyn);
     __shared__ BoxShared sh;
     const int bs = blockIdx.x;
-    const int pb = box_prob[bs];
+    const int4 bt = box_tab[bs];
+    const int pb = bt.w;
     if (pb < 0 || !selected(sel, pb)) return;
     const ProbParams &P = pp[pb];
-    int64_t first;
-    int nn, na;
-    box_geometry(P, bs - P.box_begin, first, nn, na);
+    const int64_t first = bt.x;
+    const int nn = bt.y, na = bt.z;
     const int t = threadIdx.x;
     const bool act = t < nn;
     const int4 iv = act ? reinterpret_cast<const int4 *>(inc)[first + t] : make_int4(-1, -1, -1, -1);
@@ -1203,12 +1213,12 @@ __global__ __launch_bounds__(1024) void k_cgstart2(ProbSel sel, const int32_t *b
 // cell's DoFs that belong to it and are free.  Cells in fixed order; the
 // 6x6 inverse by Cholesky (an aggregate whose B is not numerically positive
 // definite gets no coarse correction).
-__global__ __launch_bounds__(256) void k_coarse_setup(ProbSel sel, const int32_t *box_prob, const ProbParams *pp,
+__global__ __launch_bounds__(256) void k_coarse_setup(ProbSel sel, const int4 *box_tab, const ProbParams *pp,
                                                       const int32_t *cslot, const int32_t *sb_rom,
                                                       const void *const *kr64_tab, const uint8_t *cmask,
                                                       const int32_t *surf, int n, int ldk, double *binv) {
     const int bs = blockIdx.x, a = blockIdx.y;
-    const int pb = box_prob[bs];
+    const int pb = box_tab[bs].w;
     if (pb < 0 || !selected(sel, pb)) return;
     const ProbParams &P = pp[pb];
     const AggLayout &A = P.agg;
@@ -1331,13 +1341,18 @@ __global__ __launch_bounds__(256) void k_coarse_setup(ProbSel sel, const int32_t
 
 // Problem id of every DoF block and slot block of the listed problems.
 __global__ void k_fill_owner(PidList L, const ProbParams *pp, int32_t *blk_prob, int32_t *sb_prob,
-                             int32_t *box_prob) {
+                             int4 *box_tab) {
     const int p = L.pid[blockIdx.x];
     const ProbParams &P = pp[p];
     for (int i = threadIdx.x; i < P.n_blk; i += blockDim.x) blk_prob[P.blk_begin + i] = p;
     for (int i = threadIdx.x; i < P.n_sb; i += blockDim.x) sb_prob[P.sb_begin + i] = p;
     if (P.box_begin >= 0)
-        for (int i = threadIdx.x; i < P.n_agg; i += blockDim.x) box_prob[P.box_begin + i] = p;
+        for (int i = threadIdx.x; i < P.n_agg; i += blockDim.x) {
+            int64_t first;
+            int nn, na;
+            box_geometry(P, i, first, nn, na);
+            box_tab[P.box_begin + i] = make_int4((int)first, nn, na, p);
+        }
 }
 
 // Constrained DoFs: padding and, when clamped, the nodes of the bottom and
@@ -1869,7 +1884,7 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
     MOS_HIP(hipEventRecord(e->mirror_ev, st));
     const int hw_blk = e->blk.high, hw_sb = e->sbs.high;
     hipLaunchKernelGGL(k_fill_owner, dim3(B.list.n), dim3(256), 0, st, B.list, (const ProbParams *)e->pp, e->blk_prob,
-                       e->sb_prob, e->box_prob);
+                       e->sb_prob, e->box_tab);
     hipLaunchKernelGGL(k_setup_dofs, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
                        (const ProbParams *)e->pp, e->cmask, e->g, e->x64, e->inc);
     for (EngineProblem *P : adm) {
@@ -1912,7 +1927,7 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
                            (const uint8_t *)e->cmask, e->b_raw, (double *)e->v[VDINV], e->ldk);
     if (e->precond)
         hipLaunchKernelGGL(k_coarse_setup, dim3(e->boxes.high, MAXA), dim3(256), 0, st, B.sel,
-                           (const int32_t *)e->box_prob, (const ProbParams *)e->pp, (const int32_t *)e->cslot,
+                           (const int4 *)e->box_tab, (const ProbParams *)e->pp, (const int32_t *)e->cslot,
                            (const int32_t *)e->sb_rom, (const void *const *)e->kr64_tab, (const uint8_t *)e->cmask,
                            (const int32_t *)e->surf, e->n, e->ldk, e->binv);
     MOS_LAUNCH_CHECK();
@@ -1934,7 +1949,7 @@ mos_status start_batch(mos_engine e, const Batch &B) {
                        (const ProbParams *)e->pp, (const SweepParams *)e->sp, e->ps, e->epoch);
     if (e->precond)
         hipLaunchKernelGGL(k_cgstart2<T>, dim3(e->boxes.high), dim3(e->box_nt), e->box_nt * 6 * sizeof(double), st,
-                           B.sel, (const int32_t *)e->box_prob, (const ProbParams *)e->pp, (const SweepParams *)e->sp,
+                           B.sel, (const int4 *)e->box_tab, (const ProbParams *)e->pp, (const SweepParams *)e->sp,
                            (const ProbState *)e->ps, (const double *)e->r64, (const T *)V[VDINV],
                            (const int32_t *)e->inc, (const uint8_t *)e->cmask, (const uint32_t *)e->lc, V[VX], V[VR],
                            V[VP], V[VS], Mc, e->ld_slots, e->pg, e->pr, (const double *)e->binv, e->cc,
@@ -2100,7 +2115,7 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     MOS_TRY(m.alloc_n(slots, &e->perm));
     MOS_TRY(m.alloc_n(dofs / 3, &e->lc));
     MOS_TRY(m.alloc_n(slots, &e->cslot));
-    MOS_TRY(m.alloc_n(e->cap_blk, &e->box_prob));
+    MOS_TRY(m.alloc_n(e->cap_blk, &e->box_tab));
     MOS_TRY(m.alloc_n((size_t)e->cap_blk * MAXA * 36, &e->binv));
     MOS_TRY(m.alloc_n((size_t)e->cap_blk * MAXA * 6, &e->cc));
     MOS_TRY(m.alloc_n(MAX_PROBS, &e->ps));
@@ -2172,7 +2187,7 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     fill32(e->sb_rom, e->cap_sb, 0xffffffffu);
     fill32(e->sb_prob, e->cap_sb, 0xffffffffu);  // -1: no owner (batched phases select by owner)
     fill32(e->perm, slots, 0xffffffffu);         // as its host mirror
-    fill32(e->box_prob, e->cap_blk, 0xffffffffu);
+    fill32(e->box_tab, (int64_t)e->cap_blk * 4, 0xffffffffu);
     fill32(e->ps, (int64_t)MAX_PROBS * sizeof(ProbState) / 4, 0u);
     MOS_LAUNCH_CHECK();
     std::vector<const void *> t64(MAX_TYPES, nullptr), t32(MAX_TYPES, nullptr), tb(MAX_TYPES, nullptr),
@@ -2309,7 +2324,7 @@ mos_status release_problems(mos_engine e, const std::vector<EngineProblem *> &pr
     Batch B;
     for (EngineProblem *P : probs) B.add(P->pid);
     hipLaunchKernelGGL(k_release_list, dim3(16, B.list.n), dim3(256), 0, st, B.list, (const ProbParams *)e->pp,
-                       e->blk_prob, e->sb_rom, e->sb_prob, e->box_prob, e->ps);
+                       e->blk_prob, e->sb_rom, e->sb_prob, e->box_tab, e->ps);
     MOS_LAUNCH_CHECK();
     MOS_TRY(mirror_wait(e));
     for (EngineProblem *P : probs) {
@@ -2339,7 +2354,7 @@ void cgstep_launch(mos_engine e, int hw_blk, T *const *V) {
         launch_timed(e->ctx, MOS_K_PCG_UPDATE, k_cgstep2<T>, dim3((unsigned)(ceil_div(hw_box, N_XCD) * N_XCD)),
                      dim3(e->box_nt), e->box_nt * 6 * sizeof(double), st, (const T *)e->Yi, (const int32_t *)e->inc,
                      (const uint8_t *)e->cmask, (const T *)V[VDINV], (const uint32_t *)e->lc, V[VX], V[VR], V[VP],
-                     V[VS], (T *)e->Mc, e->ld_slots, (const int32_t *)e->box_prob, (const ProbParams *)e->pp, e->ps,
+                     V[VS], (T *)e->Mc, e->ld_slots, (const int4 *)e->box_tab, (const ProbParams *)e->pp, e->ps,
                      e->pg, e->pr, (const double *)e->pdel, (const double *)e->binv, e->cc, e->epoch, e->cap_blk,
                      hw_box);
         return;
