@@ -1207,16 +1207,48 @@ __global__ __launch_bounds__(1024) void k_cgstart2(ProbSel sel, const int4 *box_
                       (size_t)(ps[pb].it & 1) * cap_blk);
 }
 
+// Inverse of a symmetric positive definite 6x6 matrix G (row-major) into
+// out, by Gauss-Jordan elimination without pivoting on the lanes of one
+// wave (lane 6 i + j holds entry (i, j); lanes 36..63 idle along); all
+// zeros when a pivot is not numerically positive, which leaves that
+// aggregate without a coarse correction.
+__device__ void spd_inverse6_wave(const double *G, double *out) {
+    const int lane = threadIdx.x % 64;
+    const int i = min(lane / 6, 5), j = lane % 6;
+    double m = lane < 36 ? G[lane] : 0.0, v = lane < 36 && i == j ? 1.0 : 0.0;
+    double dmax = 0.0;
+    for (int k = 0; k < 6; ++k) dmax = fmax(dmax, G[k * 7]);
+    bool ok = dmax > 0.0 && isfinite(dmax);
+    for (int k = 0; k < 6; ++k) {
+        const double piv = __shfl(m, k * 7);
+        ok = ok && piv > 1e-12 * dmax;
+        const double fac = __shfl(m, i * 6 + k);
+        const double rm = __shfl(m, k * 6 + j) / piv, rv = __shfl(v, k * 6 + j) / piv;
+        if (i == k) {
+            m = rm;
+            v = rv;
+        } else {
+            m -= fac * rm;
+            v -= fac * rv;
+        }
+    }
+    if (lane < 36) out[lane] = ok ? v : 0.0;
+}
+
 // B_a^-1 of every aggregate of the selected problems' boxes; grid (boxes,
 // MAXA), one workgroup per aggregate.  B_a = sum over the cells touching
 // the aggregate of Z_c^T K_r(type) Z_c, Z_c the aggregate's modes on the
-// cell's DoFs that belong to it and are free.  Cells in fixed order; the
-// 6x6 inverse by Cholesky (an aggregate whose B is not numerically positive
-// definite gets no coarse correction).
-__global__ __launch_bounds__(256) void k_coarse_setup(ProbSel sel, const int4 *box_tab, const ProbParams *pp,
-                                                      const int32_t *cslot, const int32_t *sb_rom,
-                                                      const void *const *kr64_tab, const uint8_t *cmask,
-                                                      const int32_t *surf, int n, int ldk, double *binv) {
+// cell's DoFs that belong to it and are free.  K_r is read in FP32 (B only
+// defines the preconditioner; any symmetric positive definite B keeps PCG
+// converging to the same solution) with FP64 sums.  The touching cells (at
+// most 3 x 3) are dealt to CS_GROUPS groups of 256 threads, each summing its
+// cells in a fixed order, the groups' sums in order; then the 6x6 inverse.
+constexpr int CS_GROUPS = 1;
+__global__ __launch_bounds__(256 * CS_GROUPS) void k_coarse_setup(ProbSel sel, const int4 *box_tab,
+                                                                  const ProbParams *pp, const int32_t *cslot,
+                                                                  const int32_t *sb_rom, const void *const *kr32_tab,
+                                                                  const uint8_t *cmask, const int32_t *surf, int n,
+                                                                  int ldk, double *binv) {
     const int bs = blockIdx.x, a = blockIdx.y;
     const int pb = box_tab[bs].w;
     if (pb < 0 || !selected(sel, pb)) return;
@@ -1227,111 +1259,121 @@ __global__ __launch_bounds__(256) void k_coarse_setup(ProbSel sel, const int4 *b
     const int by0 = gy * A.cy, by1 = gy == A.nay - 1 ? P.lat.Ny : by0 + A.cy;
     const int na = (bx1 - bx0 + AGG_C - 1) / AGG_C;
     double *out = binv + ((size_t)bs * MAXA + a) * 36;
-    const int t = threadIdx.x;
+    const int tid = threadIdx.x, grp = tid / 256, t = tid % 256;
     if (a >= na) {
-        if (t < 36) out[t] = 0.0;
+        if (tid < 36) out[tid] = 0.0;
         return;
     }
     const int ax0 = bx0 + a * AGG_C, ax1 = min(ax0 + AGG_C, bx1);
-    __shared__ double zl[256][6], acc_s[256][6], G[36];
-    __shared__ uint8_t nz[256];
-    if (t < 36) G[t] = 0.0;
+    const int cx0 = max(ax0 - 1, 0), cy0 = max(by0 - 1, 0);
+    const int ncx = ax1 - cx0, ncells = ncx * (by1 - cy0);
+    __shared__ double zl[CS_GROUPS][256][6], G[CS_GROUPS][21], wpart[CS_GROUPS][4][21];
+    __shared__ int16_t list[CS_GROUPS][256];
+    __shared__ int wcnt[CS_GROUPS][4];
+    __shared__ double Bfull[36];
+    if (t < 21) G[grp][t] = 0.0;
     const int sx = A.sx, sy = A.sy;
-    for (int cy = max(by0 - 1, 0); cy < by1; ++cy)
-        for (int cx = max(ax0 - 1, 0); cx < ax1; ++cx) {
+    const int w = t / 64, lane = t % 64;
+    // Every group takes the same number of rounds (barriers are
+    // workgroup-wide); a group without a cell in the last round idles.
+    for (int c0 = 0; c0 < ncells; c0 += CS_GROUPS) {
+        const int ci_cell = c0 + grp;
+        const bool has = ci_cell < ncells;
+        const int cx = cx0 + (has ? ci_cell % ncx : 0), cy = cy0 + (has ? ci_cell / ncx : 0);
+        const float *K = nullptr;
+        if (has) {
             const int cell = cy * P.lat.Nx + cx;
             const int slot = cslot[(int64_t)P.sb_begin * 16 + cell];
-            const double *K = static_cast<const double *>(kr64_tab[sb_rom[slot / 16]]);
-            __syncthreads();
-            if (t < n) {
-                const int sn = t / 3, ci = t % 3;
-                const int64_t I = (int64_t)cx * sx + surf[3 * sn], J = (int64_t)cy * sy + surf[3 * sn + 1];
-                const int Kz = surf[3 * sn + 2];
-                bool in = agg_x(A, I) == gx && agg_y(A, J) == gy;
-                const int ib = (int)(I - (int64_t)gx * A.wxi);
-                const int ag = min(ib / (AGG_C * sx), na - 1);
-                in = in && ag == a;
-                const int64_t dd = P.d0 + 3 * agg_encode(A, I, J, Kz) + ci;
-                in = in && cmask[dd] == 0;
-                double z[6] = {0, 0, 0, 0, 0, 0};
-                if (in) {
-                    const double X = (double)(ib - ag * AGG_C * sx) * P.h[0];
-                    const double Yc = (double)(J - (int64_t)gy * A.wyi) * P.h[1];
-                    const double Zc = (double)Kz * P.h[2];
-                    // Mode values at component ci (columns of Z).
-                    z[ci] = 1.0;
-                    if (ci == 0) {
-                        z[3] = -Yc;
-                        z[5] = Zc;
-                    } else if (ci == 1) {
-                        z[3] = X;
-                        z[4] = -Zc;
-                    } else {
-                        z[4] = Yc;
-                        z[5] = -X;
+            K = static_cast<const float *>(kr32_tab[sb_rom[slot / 16]]);
+        }
+        __syncthreads();
+        bool mine = false;
+        if (has && t < n) {
+            const int sn = t / 3, ci = t % 3;
+            const int64_t I = (int64_t)cx * sx + surf[3 * sn], J = (int64_t)cy * sy + surf[3 * sn + 1];
+            const int Kz = surf[3 * sn + 2];
+            bool in = agg_x(A, I) == gx && agg_y(A, J) == gy;
+            const int ib = (int)(I - (int64_t)gx * A.wxi);
+            const int ag = min(ib / (AGG_C * sx), na - 1);
+            in = in && ag == a;
+            const int64_t dd = P.d0 + 3 * agg_encode(A, I, J, Kz) + ci;
+            in = in && cmask[dd] == 0;
+            double z[6] = {0, 0, 0, 0, 0, 0};
+            if (in) {
+                const double X = (double)(ib - ag * AGG_C * sx) * P.h[0];
+                const double Yc = (double)(J - (int64_t)gy * A.wyi) * P.h[1];
+                const double Zc = (double)Kz * P.h[2];
+                // Mode values at component ci (columns of Z).
+                z[ci] = 1.0;
+                if (ci == 0) {
+                    z[3] = -Yc;
+                    z[5] = Zc;
+                } else if (ci == 1) {
+                    z[3] = X;
+                    z[4] = -Zc;
+                } else {
+                    z[4] = Yc;
+                    z[5] = -X;
+                }
+            }
+            for (int m = 0; m < 6; ++m) zl[grp][t][m] = z[m];
+            mine = in;
+        }
+        // The cell's DoFs in the aggregate, ascending, as a list (ballot per
+        // wave, waves in order).
+        const uint64_t bal = __ballot(mine);
+        if (lane == 0) wcnt[grp][w] = __popcll(bal);
+        __syncthreads();
+        int base = 0, nl = 0;
+        for (int i = 0; i < 4; ++i) {
+            base += i < w ? wcnt[grp][i] : 0;
+            nl += wcnt[grp][i];
+        }
+        if (mine) list[grp][base + __popcll(bal & ((1ull << lane) - 1))] = (int16_t)t;
+        __syncthreads();
+        // Row t of K_r Z over the listed columns (K_r symmetric: row l read
+        // across threads), then the row's share of the symmetric Z^T K_r Z,
+        // summed over the group in a fixed order.
+        double acc[6] = {0, 0, 0, 0, 0, 0};
+        if (has && t < n) {
+            // Sixteen rows' values requested at once (one register each),
+            // then their products.
+            for (int i0 = 0; i0 < nl; i0 += 16) {
+                float kv[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int l = list[grp][min(i0 + j, nl - 1)];
+                    kv[j] = at_byte(K, (uint32_t)(l * ldk + t) * 4u);
+                }
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    if (i0 + j < nl) {
+                        const int l = list[grp][i0 + j];
+                        for (int m = 0; m < 6; ++m) acc[m] += (double)kv[j] * zl[grp][l][m];
                     }
-                }
-                for (int m = 0; m < 6; ++m) zl[t][m] = z[m];
-                nz[t] = in ? 1 : 0;
-            }
-            __syncthreads();
-            if (t < n) {
-                double acc[6] = {0, 0, 0, 0, 0, 0};
-                for (int l = 0; l < n; ++l) {
-                    if (!nz[l]) continue;  // the same for every thread
-                    const double kv = K[(size_t)l * ldk + t];
-                    for (int m = 0; m < 6; ++m) acc[m] += kv * zl[l][m];
-                }
-                for (int m = 0; m < 6; ++m) acc_s[t][m] = acc[m];
-            }
-            __syncthreads();
-            if (t < 36) {
-                const int m1 = t / 6, m2 = t % 6;
-                double g = 0.0;
-                for (int k = 0; k < n; ++k) g += zl[k][m1] * acc_s[k][m2];
-                G[t] += g;
             }
         }
-    __syncthreads();
-    if (t == 0) {
-        double B[6][6], L[6][6] = {}, Li[6][6] = {};
-        double dmax = 0.0;
-        for (int i = 0; i < 6; ++i)
-            for (int j = 0; j < 6; ++j) B[i][j] = 0.5 * (G[i * 6 + j] + G[j * 6 + i]);
-        for (int i = 0; i < 6; ++i) dmax = fmax(dmax, B[i][i]);
-        bool ok = dmax > 0.0 && isfinite(dmax);
-        for (int j = 0; j < 6 && ok; ++j) {
-            double v = B[j][j];
-            for (int k = 0; k < j; ++k) v -= L[j][k] * L[j][k];
-            if (!(v > 1e-12 * dmax)) {
-                ok = false;
-                break;
-            }
-            L[j][j] = sqrt(v);
-            for (int i = j + 1; i < 6; ++i) {
-                double w = B[i][j];
-                for (int k = 0; k < j; ++k) w -= L[i][k] * L[j][k];
-                L[i][j] = w / L[j][j];
-            }
+#pragma unroll 1
+        for (int q = 0, m1 = 0, m2 = 0; q < 21; ++q) {
+            double v = mine ? 0.5 * (zl[grp][t][m1] * acc[m2] + zl[grp][t][m2] * acc[m1]) : 0.0;
+            for (int k = 32; k >= 1; k >>= 1) v += __shfl_xor(v, k);
+            if (lane == 0) wpart[grp][w][q] = v;
+            if (++m2 == 6) m2 = ++m1;
         }
-        if (ok) {
-            // L^-1 by forward substitution, then B^-1 = L^-T L^-1.
-            for (int c = 0; c < 6; ++c)
-                for (int i = c; i < 6; ++i) {
-                    double v = i == c ? 1.0 : 0.0;
-                    for (int k = c; k < i; ++k) v -= L[i][k] * Li[k][c];
-                    Li[i][c] = v / L[i][i];
-                }
-            for (int i = 0; i < 6; ++i)
-                for (int j = 0; j < 6; ++j) {
-                    double v = 0.0;
-                    for (int k = max(i, j); k < 6; ++k) v += Li[k][i] * Li[k][j];
-                    out[i * 6 + j] = v;
-                }
-        } else {
-            for (int i = 0; i < 36; ++i) out[i] = 0.0;
-        }
+        __syncthreads();
+        if (t < 21) G[grp][t] += ((wpart[grp][0][t] + wpart[grp][1][t]) + wpart[grp][2][t]) + wpart[grp][3][t];
     }
+    __syncthreads();
+    if (tid < 36) {
+        // Full symmetric matrix from the 21 sums (groups in order).
+        const int i = tid / 6, j = tid % 6, lo = min(i, j), hi = max(i, j);
+        const int q = lo * 6 - lo * (lo - 1) / 2 + (hi - lo);
+        double g = G[0][q];
+        for (int k = 1; k < CS_GROUPS; ++k) g += G[k][q];
+        Bfull[tid] = g;
+    }
+    __syncthreads();
+    if (tid < 64) spd_inverse6_wave(Bfull, out);
 }
 
 // ---- batched per-problem phases (set-up, FP64 residual, sweep start/stop) ----
@@ -1926,9 +1968,9 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
                            (const void *const *)e->kr64_tab, (const int32_t *)e->sb_rom, (const int32_t *)e->inc,
                            (const uint8_t *)e->cmask, e->b_raw, (double *)e->v[VDINV], e->ldk);
     if (e->precond)
-        hipLaunchKernelGGL(k_coarse_setup, dim3(e->boxes.high, MAXA), dim3(256), 0, st, B.sel,
+        hipLaunchKernelGGL(k_coarse_setup, dim3(e->boxes.high, MAXA), dim3(256 * CS_GROUPS), 0, st, B.sel,
                            (const int4 *)e->box_tab, (const ProbParams *)e->pp, (const int32_t *)e->cslot,
-                           (const int32_t *)e->sb_rom, (const void *const *)e->kr64_tab, (const uint8_t *)e->cmask,
+                           (const int32_t *)e->sb_rom, (const void *const *)e->kr32_tab, (const uint8_t *)e->cmask,
                            (const int32_t *)e->surf, e->n, e->ldk, e->binv);
     MOS_LAUNCH_CHECK();
     // At set-up x = g, so one product A g gives both ||b_l|| and the residual.
