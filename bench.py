@@ -257,7 +257,7 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False, vm_ref=None):
 
     # Single-array latency (batch of one), for reference.
     single = []
-    for s in range(3):
+    for s in range(0 if args.no_single else 3):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         tk = eng.submit(16, 16, types[0], cases[0].delta_T, vm=vms[0])
@@ -300,7 +300,7 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False, vm_ref=None):
         "p99_ms": round(float(np.percentile(lat, 99)), 4),
         "step_ms": [round(ev[s].elapsed_time(ev[s + 1]), 3) for s in range(args.steps)],
         "latency_is": "per array, submission to completion of solve + reconstruction",
-        "single_array_ms": round(float(np.median(single)), 4),
+        "single_array_ms": round(float(np.median(single)), 4) if single else None,
         "pcg_iters_mean": round(float(np.mean(iters)), 1),
         "refinement_sweeps_mean": round(float(np.mean(sweeps)), 2),
         "local_stage_ms_per_cell_type": round(local_ms, 2),
@@ -599,6 +599,9 @@ def main():
     ap.add_argument("--precond", type=int, choices=[0, 1], default=None,
                     help="PCG preconditioner (0 Jacobi, 1 Jacobi plus the aggregate coarse correction; "
                          "default: the engine's)")
+    ap.add_argument("--no-single", action="store_true",
+                    help="batch mode: skip the single-array latency pass (for counter runs that average over "
+                         "every launch of the process)")
     ap.add_argument("--chunk", type=int, default=16)
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--budget-gb", type=float, default=32.0)
