@@ -1104,6 +1104,29 @@ __global__ __launch_bounds__(1024) void k_cgstep2(const T *Y, const int32_t *inc
     if (!go) return;
     const int it = it_sh;
     const size_t rd_slot = (size_t)(it & 1) * cap_blk, wr_slot = (size_t)((it + 1) & 1) * cap_blk;
+    // The node's operands are requested before the scalar step (they do not
+    // depend on alpha and beta), so their round trip overlaps the one for
+    // the problem's partials.
+    T dv[3] = {0, 0, 0}, rv[3] = {0, 0, 0};
+    T rd[3] = {0, 0, 0}, pd0[3] = {0, 0, 0}, sd[3] = {0, 0, 0}, xd[3] = {0, 0, 0}, wv[3] = {0, 0, 0};
+    bool f[3] = {false, false, false};
+    uint32_t lw = 0;
+    // Component-major within the box: component ci of node t at ci * nn + t.
+    const int64_t vb = 3 * first;
+    const T *db = dinv + vb;
+    T *xb = x + vb, *rb = r + vb, *pbv = p + vb, *sb = s + vb;
+    if (act) {
+        lw = lc[first + t];
+        for (int ci = 0; ci < 3; ++ci) {
+            const uint32_t o = (uint32_t)(ci * nn + t) * (uint32_t)sizeof(T);
+            dv[ci] = at_byte(db, o);
+            rd[ci] = at_byte(rb, o);
+            pd0[ci] = at_byte(pbv, o);
+            sd[ci] = at_byte(sb, o);
+            xd[ci] = at_byte(xb, o);
+            wv[ci] = cell_sum32(Y, iv, ci, (uint32_t)ld_slots);
+        }
+    }
     if (go == 2) {
         ProbState &S = ps[pb];
         const CgStep o = cg_scalars_wide(S, it, pg + rd_slot, pr + rd_slot, pdel, red);
@@ -1118,27 +1141,12 @@ __global__ __launch_bounds__(1024) void k_cgstep2(const T *Y, const int32_t *inc
         __syncthreads();
     }
     const T al = (T)step[0], be = (T)step[1];
-    T dv[3] = {0, 0, 0}, rv[3] = {0, 0, 0};
-    bool f[3] = {false, false, false};
     double X = 0.0, Yc = 0.0, Zc = 0.0;
     int a = 0;
     if (act) {
-        unpack_lc(lc[first + t], P.h, X, Yc, Zc, a, f);
-        // Component-major within the box: component ci of node t at ci * nn + t.
-        const int64_t vb = 3 * first;
-        const T *db = dinv + vb;
-        T *xb = x + vb, *rb = r + vb, *pbv = p + vb, *sb = s + vb;
-        T rd[3], pd0[3], sd[3], xd[3], wv[3];
-        for (int ci = 0; ci < 3; ++ci) {
-            const uint32_t o = (uint32_t)(ci * nn + t) * (uint32_t)sizeof(T);
-            dv[ci] = at_byte(db, o);
-            rd[ci] = at_byte(rb, o);
-            pd0[ci] = at_byte(pbv, o);
-            sd[ci] = at_byte(sb, o);
-            xd[ci] = at_byte(xb, o);
-            const T sum = cell_sum32(Y, iv, ci, (uint32_t)ld_slots);
-            wv[ci] = f[ci] ? sum : T(0);
-        }
+        unpack_lc(lw, P.h, X, Yc, Zc, a, f);
+        for (int ci = 0; ci < 3; ++ci)
+            if (!f[ci]) wv[ci] = T(0);
         double uc[3];
         node_prolong(X, Yc, Zc, sh.cold[a], uc);
         for (int ci = 0; ci < 3; ++ci) {
