@@ -16,6 +16,8 @@ mor     : Lagrange surface interpolation (eq. 8-10, 16), the lifted local
 array   : the global stage: abstract mesh numbering, assembly, Dirichlet
           data, solve (eq. 20) and per-cell reconstruction (Sec. 4.3-4.4);
           plus the full fine-mesh FEM of a whole array for comparison.
+plane   : the paper's evaluation (Sec. 5.1): von Mises on a grid of points
+          on each block's mid-height plane, normalised MAE and max-norm error.
 
 Every floating-point quantity is float64.  Solves use SciPy's sparse LU
 (a library primitive); no blocking, fusion or reordering is done beyond what
