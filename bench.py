@@ -16,6 +16,10 @@ reduced order models of the three cell types are built once before the clock
 it apart from the global stage).  Throughput counts every cell of the batch;
 latency is per array.
 
+--mode plane: the paper's evaluation grid (100 x 100 points on each cell's
+mid-height plane) for the 16x16 array, FP64 and mixed, with the normalised
+MAE of the mixed field against the FP64 one.
+
 --mode serve: a Poisson stream of requests (mean 200 /s; N ~ U{4..48},
 pitch ~ U{10,15,20} um, dT ~ U[-300,-150] K, 10% dummy cells) served with
 continuous batching in mixed precision; reports TSV-cells/s and p50/p99 of
@@ -467,6 +471,82 @@ def single_mode(args, mos, torch, np, W):
     print(json.dumps(out))
 
 
+def plane_mode(args, mos, torch, np, W):
+    """The paper's evaluation (Sec. 5.1): von Mises on a g x g grid (default
+    100 x 100) of points on every cell's mid-height plane, for the 16x16 array
+    of 16x16x32 cells with cubic faces, from an FP64 and a mixed-precision
+    solution.  Times the plane reconstruction (one GEMM per cell type over a
+    stress basis built at the sample points) and reports the paper's error
+    measure, the normalised MAE, of the mixed field against the FP64 one."""
+    case = W.case_c2(args.seed)
+    g = args.grid
+    ctx = mos.Context(0)
+    roms = [mos.mos_reduce(ctx, mos.mos_build_cell(ctx, s)) for s in case.specs]
+    n = roms[0].query(mos.MOS_Q_N)
+    n_cells = case.n_cells
+    paths, fields = {}, {}
+    for prec in ("fp64", "mixed"):
+        mixed = prec == "mixed"
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sol = mos.mos_solve_array(ctx, roms, case.nx_cells, case.ny_cells, case.cell_type, case.delta_T,
+                                  clamp_bottom=case.clamp_bottom, clamp_top=case.clamp_top, mixed=mixed)
+        torch.cuda.synchronize()
+        solve_ms = (time.perf_counter() - t0) * 1e3
+        vm = torch.empty((n_cells, g * g), dtype=torch.float32 if mixed else torch.float64, device="cuda")
+        t0 = time.perf_counter()
+        mos.mos_reconstruct_plane(ctx, sol, g, vm)       # first call also builds the plane basis
+        first_ms = (time.perf_counter() - t0) * 1e3
+        for _ in range(args.warmup):
+            mos.mos_reconstruct_plane(ctx, sol, g, vm)
+        mos.mos_timing_start(ctx, mos.MOS_K_RECON, 1)
+        quiet_gc()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            mos.mos_reconstruct_plane(ctx, sol, g, vm)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t1) / args.steps
+        launches, k_ms, seen = mos.mos_timing_stop(ctx)
+        work = 2.0 * 6 * g * g * n * n_cells * args.steps        # algorithmic flops of the timed calls
+        kern_s = k_ms / 1e3 / max(launches, 1) * max(seen, 1)      # kernel time of the timed calls
+        peak = PEAK_BF16_TFLOPS if mixed else PEAK_FP64_TFLOPS
+        achieved = work / kern_s / 1e12
+        paths[prec] = {
+            "cells_per_s": round(n_cells / wall, 1), "points_per_s": round(n_cells * g * g / wall, 1),
+            "ms_per_call": round(wall * 1e3, 4), "first_call_ms_with_basis": round(first_ms, 2),
+            "solve_ms": round(solve_ms, 2), "pcg_iters": sol.query(mos.MOS_Q_ITERS),
+            "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                         "frac": round(achieved / peak, 5), "kernel": "k_recon (plane basis)",
+                         "avg_launch_us": round(k_ms * 1e3 / max(launches, 1), 3),
+                         "launches_per_call": round(seen / args.steps, 2),
+                         "work_note": "2 * 6 g^2 n flops per cell"},
+        }
+        fields[prec] = vm.double().cpu().numpy()
+        del sol, vm
+    ref, mx = fields["fp64"], fields["mixed"]
+    sp = case.specs[0]
+    out = {
+        "mode": "plane",
+        "metric": "evaluation-plane cells/s (von Mises on the mid-height grid)",
+        "value": paths["fp64"]["cells_per_s"],
+        "unit": "TSV-cells/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": paths["fp64"]["ms_per_call"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": case.name, "array": f"{case.nx_cells}x{case.ny_cells}", "cells": n_cells,
+                   "cell_mesh": list(sp.mesh), "interp": list(sp.interp), "n": n, "grid": [g, g],
+                   "points_per_cell": g * g, "plane": "z = h/2", "delta_T": case.delta_T, "seed": args.seed},
+        "fp64": paths["fp64"],
+        "mixed": paths["mixed"],
+        "normalized_mae_mixed_vs_fp64": float(np.mean(np.abs(mx - ref)) / np.abs(ref).max()),
+        "max_rel_err_mixed_vs_fp64": float(np.abs(mx - ref).max() / np.abs(ref).max()),
+        "max_vm_mpa": float(ref.max()),
+    }
+    print(json.dumps(out))
+
+
 def calib_mode(args, torch):
     """A plain device copy of known size (1 GiB read, 1 GiB written per
     launch): the reference that scales the FETCH_SIZE / WRITE_SIZE counters
@@ -584,7 +664,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--mode", choices=["batch", "serve", "single", "calib"], default="batch")
+    ap.add_argument("--mode", choices=["batch", "serve", "single", "calib", "plane"], default="batch")
+    ap.add_argument("--grid", type=int, default=100, help="plane mode: sample points per cell along x and y")
     ap.add_argument("--workload", choices=["c3", "c5"], default="c3")
     ap.add_argument("--batch", type=int, default=128)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
@@ -622,6 +703,8 @@ def main():
         batch_mode(args, mos, torch, np, W)
     elif args.mode == "single":
         single_mode(args, mos, torch, np, W)
+    elif args.mode == "plane":
+        plane_mode(args, mos, torch, np, W)
     else:
         serve_mode(args, mos, torch, np, W)
 

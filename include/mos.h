@@ -7,6 +7,7 @@
  *   mos_reduce       FE system -> reduced order model      (Sec. 4.2-4.3; eq. 8-19)
  *   mos_solve_array  ROMs + array layout -> reduced u      (Sec. 4.3-4.4; eq. 20)
  *   mos_reconstruct  reduced u -> per-cell stress          (Sec. 4.3, last paragraph; eq. 1, 15)
+ *   mos_reconstruct_plane  von Mises on each cell's mid-height sample grid (Sec. 5.1)
  *
  * Conventions
  *   Units: micrometres, MPa, 1/K, K.  Stress in MPa, displacement in um.
@@ -147,6 +148,23 @@ enum { MOS_OUT_VM = 1, MOS_OUT_SIGMA6 = 2 };
  * MOS_FP64 solution and float for MOS_MIXED.  Either pointer may be NULL
  * when its flag is not set. */
 mos_status mos_reconstruct(mos_ctx ctx, mos_sol sol, uint32_t outputs, void *vm, void *sigma6);
+
+/* The paper's evaluation plane (Sec. 5.1, error metric of Tables 1-3): von
+ * Mises stress of every cell at grid x grid points of its mid-height plane,
+ * sigma = dT sigma_T(p) + Psi(p) u_c with Psi(p) = D B(p) Phi at the point
+ * (eq. 1 and 15).  Point p = j*grid + i of a cell sits at x = pitch_x (i +
+ * 1/2) / grid, y = pitch_y (j + 1/2) / grid, z = height / 2 within the cell,
+ * in the fine element whose half-open box [x_a, x_a+1) x [y_b, y_b+1) x
+ * [z_c, z_c+1) holds it (points on an element face take the +x / +y / +z
+ * element).  vm: caller-owned device array [n_cells][grid*grid], double for
+ * a MOS_FP64 solution and float for MOS_MIXED, written on the context's
+ * stream (complete when the call returns).  The first call for a ROM and
+ * grid builds that ROM's plane stress basis (6 grid^2 x n, FP64, plus its
+ * BF16 split) and keeps it with the ROM until mos_rom_free or a call with
+ * another grid; a call with another grid first waits for the stream.
+ * Errors: MOS_EINVAL for a NULL vm, a grid outside [1, 256], or a solution
+ * whose ROMs were freed; MOS_ENOMEM if the basis does not fit. */
+mos_status mos_reconstruct_plane(mos_ctx ctx, mos_sol sol, int32_t grid, void *vm);
 
 /* Copy the reduced solution (n_global_dofs doubles) to host memory and report
  * the final relative true residual and total PCG iterations (any may be NULL). */

@@ -636,6 +636,24 @@ mos_status mos_reconstruct(mos_ctx ctx, mos_sol sol, uint32_t outputs, void *vm,
     return reconstruct(ctx, sol, outputs, vm, sigma6);
 }
 
+mos_status mos_reconstruct_plane(mos_ctx ctx, mos_sol sol, int32_t grid, void *vm) {
+    if (!ctx || !sol || sol->kind != KIND_SOL || sol->ctx != ctx) {
+        set_error("invalid context or solution handle");
+        return MOS_EINVAL;
+    }
+    if (!vm || grid < 1 || grid > PLANE_MAX_GRID) {
+        set_error("mos_reconstruct_plane: need a non-NULL vm and a grid in [1, %d]", PLANE_MAX_GRID);
+        return MOS_EINVAL;
+    }
+    for (mos_rom r : sol->roms)
+        if (!r || r->kind != KIND_ROM) {
+            set_error("mos_reconstruct_plane: a ROM of this solution has been freed");
+            return MOS_EINVAL;
+        }
+    MOS_HIP(hipSetDevice(ctx->device));
+    return reconstruct_plane(ctx, sol, grid, vm);
+}
+
 mos_status mos_get_solution(mos_sol sol, double *u_host, double *rel_residual, int32_t *iters) {
     if (!sol || sol->kind != KIND_SOL) {
         set_error("invalid solution handle");
@@ -798,6 +816,11 @@ void mos_cell_free(mos_cell c) {
 
 void mos_rom_free(mos_rom r) {
     if (!r || r->kind != KIND_ROM) return;
+    if (r->plane) {
+        r->plane->mem.release();
+        delete r->plane;
+        r->plane = nullptr;
+    }
     r->mem.release();
     r->kind = 0;
     delete r;

@@ -136,6 +136,14 @@ struct mos_rom_s {
     int nks = 0;                  // 32-wide k-steps of the BF16 reconstruction GEMM
     uint16_t *psi_hi = nullptr;   // BF16 split of psi in MFMA A-operand order
     uint16_t *psi_lo = nullptr;   //   [n_eblk][6][nks][64][8]; null if nks > RECON_BF16_MAX_KS
+    uint8_t *mat = nullptr;       // [n_elem] material code per element (copy of the cell's)
+    double *mprop = nullptr;      // [3][3] (lambda, mu, beta) per material
+    // Stress basis at the sample points of the mid-height plane, built on
+    // first use: a ROM of its own whose psi / sig_t / psi_hi / psi_lo hold
+    // the points (n_elem = grid^2 points, n_eblk their blocks of 16) and
+    // whose other arrays are null.  Owned by this ROM.
+    mos_rom_s *plane = nullptr;
+    int plane_grid = 0;
 };
 
 struct mos_sol_s {
@@ -169,8 +177,14 @@ mos_status band_cholesky(mos_cell c, double *dinv, int *status_dev, int *not_spd
 mos_status band_solve(mos_cell c, const double *dinv, double *rhs, int ldr, int ncols);
 // reduce.hip
 mos_status reduce_cell(mos_cell c, mos_rom r);
+// Stress basis of r at the grid x grid sample points of the mid-height plane
+// (built once per grid size and kept in r->plane; MOS_EINVAL for a grid
+// outside [1, PLANE_MAX_GRID]).
+constexpr int PLANE_MAX_GRID = 256;
+mos_status plane_basis(mos_rom r, int grid);
 // recon.hip
 mos_status reconstruct(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void *sigma6);
+mos_status reconstruct_plane(mos_ctx ctx, mos_sol s, int grid, void *vm);
 // FP64 MFMA reconstruction with one element block of Psi staged in LDS per
 // workgroup, for bases with ldk / 4 <= RECON_F64_LDS_KS (else MOS_EINVAL).
 // A job is one problem's run of slot blocks of one type in the cell-major

@@ -414,14 +414,18 @@ mos_status recon_bf16_jobs(mos_ctx ctx, const mos_rom *roms, int n_types, const 
     return MOS_OK;
 }
 
-mos_status reconstruct(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void *sigma6) {
+// The solution's cells through the stress bases R[t] (one per cell type:
+// the centroid bases of the solution's ROMs, or their plane bases), which
+// share ldk, n_eblk and n_elem (output points per cell).
+static mos_status recon_with(mos_ctx ctx, mos_sol s, const std::vector<mos_rom> &R, void *v, void *g) {
     hipStream_t st = ctx->stream;
+    const int n_eblk = R[0]->n_eblk, n_pts = R[0]->n_elem;
     ReconTable tt{};
     tt.n_types = s->n_types;
     for (int t = 0; t <= s->n_types; ++t) tt.seg[t] = s->seg[t];
     for (int t = 0; t < s->n_types; ++t) {
-        tt.psi[t] = s->roms[t]->psi;
-        tt.sig_t[t] = s->roms[t]->sig_t;
+        tt.psi[t] = R[t]->psi;
+        tt.sig_t[t] = R[t]->sig_t;
     }
     DeviceArena tmp;
     tmp.ctx = ctx;
@@ -434,22 +438,19 @@ mos_status reconstruct(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void 
     MOS_TRY(tmp.alloc_n(total, &U));
     hipLaunchKernelGGL(k_gather_u, dim3(ceil_div(total, 256)), dim3(256), 0, st, s->u, s->gidx, U, total);
     MOS_LAUNCH_CHECK();
-    dim3 grid(s->n_eblk, ceil_div(s->n_pc / 16, 4));
-    void *v = (outputs & MOS_OUT_VM) ? vm : nullptr;
-    void *g = (outputs & MOS_OUT_SIGMA6) ? sigma6 : nullptr;
-    if (s->precision == MOS_MIXED && s->roms[0]->psi_hi) {
+    dim3 grid(n_eblk, ceil_div(s->n_pc / 16, 4));
+    if (s->precision == MOS_MIXED && R[0]->psi_hi) {
         std::vector<std::vector<ReconJob>> jobs(s->n_types);
         for (int t = 0; t < s->n_types; ++t) {
             const int nsb = (s->seg[t + 1] - s->seg[t]) / 16;
             if (nsb > 0) jobs[t].push_back(ReconJob{s->seg[t] / 16, 0, nsb, 0, s->delta_T, v, g});
         }
         void *scratch = nullptr;
-        MOS_TRY(tmp.alloc((size_t)recon_bf16_scratch(s->roms[0], s->n_pc / 16), &scratch));
+        MOS_TRY(tmp.alloc((size_t)recon_bf16_scratch(R[0], s->n_pc / 16), &scratch));
         ReconJob *dj = nullptr;
         MOS_TRY(tmp.alloc_n(MAX_TYPES, &dj));
         std::vector<ReconJob> hj(MAX_TYPES);
-        MOS_TRY(recon_bf16_jobs(ctx, s->roms.data(), s->n_types, jobs.data(), dj, hj.data(), U, s->n_pc, s->perm,
-                                scratch));
+        MOS_TRY(recon_bf16_jobs(ctx, R.data(), s->n_types, jobs.data(), dj, hj.data(), U, s->n_pc, s->perm, scratch));
         MOS_HIP(hipStreamSynchronize(st));  // the host job table is a local
     } else if (s->ldk / 4 <= RECON_F64_LDS_KS) {
         std::vector<std::vector<ReconJob>> jobs(s->n_types);
@@ -460,18 +461,32 @@ mos_status reconstruct(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void 
         ReconJob *dj = nullptr;
         MOS_TRY(tmp.alloc_n(MAX_TYPES, &dj));
         std::vector<ReconJob> hj(MAX_TYPES);
-        MOS_TRY(recon_f64_jobs(ctx, s->roms.data(), s->n_types, jobs.data(), dj, hj.data(), U, s->n_pc, s->perm,
+        MOS_TRY(recon_f64_jobs(ctx, R.data(), s->n_types, jobs.data(), dj, hj.data(), U, s->n_pc, s->perm,
                                s->precision != MOS_FP64));
         MOS_HIP(hipStreamSynchronize(st));  // the host job table is a local
     } else if (s->precision == MOS_FP64)
         launch_timed(ctx, MOS_K_RECON, k_recon_f64<double>, grid, dim3(256), 0, st, tt, (const double *)U,
-                     (const int32_t *)s->perm, s->n_pc, s->ldk, s->n_elem, s->delta_T, (double *)v, (double *)g);
+                     (const int32_t *)s->perm, s->n_pc, s->ldk, n_pts, s->delta_T, (double *)v, (double *)g);
     else
         launch_timed(ctx, MOS_K_RECON, k_recon_f64<float>, grid, dim3(256), 0, st, tt, (const double *)U,
-                     (const int32_t *)s->perm, s->n_pc, s->ldk, s->n_elem, s->delta_T, (float *)v, (float *)g);
+                     (const int32_t *)s->perm, s->n_pc, s->ldk, n_pts, s->delta_T, (float *)v, (float *)g);
     MOS_LAUNCH_CHECK();
     MOS_HIP(hipStreamSynchronize(st));
     return MOS_OK;
+}
+
+mos_status reconstruct(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void *sigma6) {
+    return recon_with(ctx, s, s->roms, (outputs & MOS_OUT_VM) ? vm : nullptr,
+                      (outputs & MOS_OUT_SIGMA6) ? sigma6 : nullptr);
+}
+
+mos_status reconstruct_plane(mos_ctx ctx, mos_sol s, int grid, void *vm) {
+    std::vector<mos_rom> R(s->n_types);
+    for (int t = 0; t < s->n_types; ++t) {
+        MOS_TRY(plane_basis(s->roms[t], grid));
+        R[t] = s->roms[t]->plane;
+    }
+    return recon_with(ctx, s, R, vm, nullptr);
 }
 
 }  // namespace mos

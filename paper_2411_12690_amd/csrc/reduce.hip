@@ -230,6 +230,66 @@ __global__ void k_psi_split(const double *psi, int ldk, int nks, int64_t total, 
     lo[idx] = l;
 }
 
+// Stress of column q of Phi (q < ldk; columns >= n are zero) or of f_T
+// (q == ldk) at the sample points of the mid-height plane (the paper's
+// evaluation grid, Sec. 5.1): point p = j g + i at x = p_x (i + 1/2) / g,
+// y = p_y (j + 1/2) / g, z = h / 2.  The point lies in the element whose
+// half-open box holds it: along x that is a = floor(m_x (2i + 1) / (2g)) in
+// integers (a point on an element face goes to the +x element) with
+// reference coordinate xi = (m_x (2i + 1) - 2g a) / g - 1; along z the plane
+// is the bottom face of layer m_z / 2 (zeta = -1) for even m_z and the
+// middle of layer (m_z - 1) / 2 (zeta = 0) for odd m_z.  D B(xi, eta, zeta)
+// of the trilinear element in closed form (eq. 1).  Same layout as the
+// centroid basis with points in place of elements.
+__global__ void k_plane_basis(const double *phi, int ldp, const uint8_t *mat, const double *mprop, double *psi,
+                              double *sig_t, int mx, int my, int mz, double hx, double hy, double hz, int g, int n,
+                              int ldk, int n_pblk) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n_pblk * 16 * (ldk + 1)) return;
+    const int q = (int)(idx % (ldk + 1)), p = (int)(idx / (ldk + 1));
+    const int pb = p / 16, p16 = p % 16;
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    const int colq = q < ldk ? q : n;
+    if (p < g * g && (q == ldk || q < n)) {
+        const int i = p % g, j = p / g;
+        const int tx = mx * (2 * i + 1), ty = my * (2 * j + 1);
+        const int ea = tx / (2 * g), eb = ty / (2 * g), ec = mz / 2;
+        const double xi = (double)(tx - 2 * g * ea) / g - 1.0;
+        const double eta = (double)(ty - 2 * g * eb) / g - 1.0;
+        const double zeta = (mz % 2) ? 0.0 : -1.0;
+        double eps[6] = {0, 0, 0, 0, 0, 0};
+        for (int l = 0; l < 8; ++l) {
+            const double sa = (l & 1) ? 1.0 : -1.0, sb = (l & 2) ? 1.0 : -1.0, sc = (l & 4) ? 1.0 : -1.0;
+            const int node = ((ec + ((l >> 2) & 1)) * (my + 1) + eb + ((l >> 1) & 1)) * (mx + 1) + ea + (l & 1);
+            // dN_l/dx = (2 / h_x) dN_l/dxi, N_l = (1 + sa xi)(1 + sb eta)(1 + sc zeta) / 8.
+            const double gx = sa * (1.0 + sb * eta) * (1.0 + sc * zeta) / (4.0 * hx);
+            const double gy = sb * (1.0 + sa * xi) * (1.0 + sc * zeta) / (4.0 * hy);
+            const double gz = sc * (1.0 + sa * xi) * (1.0 + sb * eta) / (4.0 * hz);
+            const double ux = phi[(size_t)(3 * node + 0) * ldp + colq];
+            const double uy = phi[(size_t)(3 * node + 1) * ldp + colq];
+            const double uz = phi[(size_t)(3 * node + 2) * ldp + colq];
+            eps[0] += gx * ux;
+            eps[1] += gy * uy;
+            eps[2] += gz * uz;
+            eps[3] += gy * ux + gx * uy;
+            eps[4] += gz * uy + gy * uz;
+            eps[5] += gz * ux + gx * uz;
+        }
+        const int m = mat[(ec * my + eb) * mx + ea];
+        const double lam = mprop[3 * m + 0], mu = mprop[3 * m + 1], beta = mprop[3 * m + 2];
+        const double tr = eps[0] + eps[1] + eps[2];
+        for (int k = 0; k < 3; ++k) s[k] = lam * tr + 2.0 * mu * eps[k];
+        for (int k = 3; k < 6; ++k) s[k] = mu * eps[k];
+        if (q == ldk)
+            for (int k = 0; k < 3; ++k) s[k] -= beta;
+    }
+    if (q < ldk) {
+        for (int k = 0; k < 6; ++k) psi[(((size_t)pb * 6 + k) * ldk + q) * 16 + p16] = s[k];
+    } else if (p < g * g) {
+        for (int k = 0; k < 6; ++k) sig_t[(size_t)p * 6 + k] = s[k];
+    }
+}
+
 }  // namespace
 
 mos_status band_cholesky(mos_cell c, double *dinv, int *status_dev, int *not_spd);
@@ -288,6 +348,10 @@ mos_status reduce_cell(mos_cell c, mos_rom r) {
     MOS_TRY(m.alloc_n((size_t)ldk * ldk, &r->kr32_pad));
     MOS_TRY(m.alloc_n((size_t)r->n_eblk * 6 * ldk * 16, &r->psi));
     MOS_TRY(m.alloc_n((size_t)c->n_elem * 6, &r->sig_t));
+    MOS_TRY(m.alloc_n(c->n_elem, &r->mat));
+    MOS_TRY(m.alloc_n(9, &r->mprop));
+    MOS_HIP(hipMemcpyAsync(r->mat, c->mat, c->n_elem, hipMemcpyDeviceToDevice, st));
+    MOS_HIP(hipMemcpyAsync(r->mprop, c->mprop, 9 * sizeof(double), hipMemcpyDeviceToDevice, st));
 
     MOS_HIP(hipMemcpyAsync(surf_d, surf.data(), surf.size() * 4, hipMemcpyHostToDevice, st));
     MOS_TRY(fill(ctx, r->phi, (size_t)c->n_dofs * ldp, 0.0));
@@ -357,6 +421,69 @@ mos_status reduce_cell(mos_cell c, mos_rom r) {
         for (int j = 0; j < n; ++j) kmax = std::max(kmax, std::fabs(Ph[(size_t)i * (n + 1) + j]));
     for (int j = 0; j < n; ++j) omax = std::max(omax, std::fabs(Ph[(size_t)n * (n + 1) + j]));
     r->orth = kmax > 0 ? omax / kmax : 0.0;
+    return MOS_OK;
+}
+
+mos_status plane_basis(mos_rom r, int grid) {
+    if (grid < 1 || grid > PLANE_MAX_GRID) {
+        set_error("plane grid %d outside [1, %d]", grid, PLANE_MAX_GRID);
+        return MOS_EINVAL;
+    }
+    if (r->plane && r->plane_grid == grid) return MOS_OK;
+    hipStream_t st = r->ctx->stream;
+    if (r->plane) {
+        // A different grid: the old basis may still be read by queued work.
+        MOS_HIP(hipStreamSynchronize(st));
+        r->plane->mem.release();
+        delete r->plane;
+        r->plane = nullptr;
+        r->plane_grid = 0;
+    }
+    mos_rom_s *pl = new mos_rom_s();
+    pl->ctx = r->ctx;
+    pl->mem.ctx = r->ctx;
+    pl->desc = r->desc;
+    pl->mx = r->mx;
+    pl->my = r->my;
+    pl->mz = r->mz;
+    pl->n = r->n;
+    pl->n_surf = r->n_surf;
+    pl->ldp = r->ldp;
+    pl->ldk = r->ldk;
+    pl->n_elem = grid * grid;
+    pl->n_eblk = ceil_div(pl->n_elem, 16);
+    pl->nks = r->nks;
+    const int ldk = r->ldk;
+    auto fail = [&](mos_status s) {
+        pl->mem.release();
+        delete pl;
+        return s;
+    };
+    mos_status s = pl->mem.alloc_n((size_t)pl->n_eblk * 6 * ldk * 16, &pl->psi);
+    if (s == MOS_OK) s = pl->mem.alloc_n((size_t)pl->n_elem * 6, &pl->sig_t);
+    if (s != MOS_OK) return fail(s);
+    const mos_cell_desc &d = r->desc;
+    hipLaunchKernelGGL(k_plane_basis, dim3(ceil_div((int64_t)pl->n_eblk * 16 * (ldk + 1), 256)), dim3(256), 0, st,
+                       r->phi, r->ldp, r->mat, r->mprop, pl->psi, pl->sig_t, r->mx, r->my, r->mz, d.pitch_x / r->mx,
+                       d.pitch_y / r->my, d.height / r->mz, grid, r->n, ldk, pl->n_eblk);
+    if (hipGetLastError() != hipSuccess) {
+        set_error("k_plane_basis launch failed");
+        return fail(MOS_EHIP);
+    }
+    if (pl->nks <= RECON_BF16_MAX_KS) {
+        const int64_t total = (int64_t)pl->n_eblk * 6 * pl->nks * 512;
+        s = pl->mem.alloc_n(total, &pl->psi_hi);
+        if (s == MOS_OK) s = pl->mem.alloc_n(total, &pl->psi_lo);
+        if (s != MOS_OK) return fail(s);
+        hipLaunchKernelGGL(k_psi_split, dim3(ceil_div(total, 256)), dim3(256), 0, st, (const double *)pl->psi, ldk,
+                           pl->nks, total, pl->psi_hi, pl->psi_lo);
+        if (hipGetLastError() != hipSuccess) {
+            set_error("k_psi_split launch failed");
+            return fail(MOS_EHIP);
+        }
+    }
+    r->plane = pl;
+    r->plane_grid = grid;
     return MOS_OK;
 }
 

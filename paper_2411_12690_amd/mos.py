@@ -21,7 +21,7 @@ MOS_OUT_VM, MOS_OUT_SIGMA6 = 1, 2
  MOS_Q_GLOBAL_DOFS, MOS_Q_ITERS, MOS_Q_REFINES, MOS_Q_DEVICE_BYTES) = range(1, 11)
 
 EXPORTED = ("mos_ctx_create", "mos_ctx_destroy", "mos_build_cell", "mos_reduce", "mos_solve_array",
-            "mos_reconstruct", "mos_get_solution", "mos_query", "mos_cell_export", "mos_rom_export",
+            "mos_reconstruct", "mos_reconstruct_plane", "mos_get_solution", "mos_query", "mos_cell_export", "mos_rom_export",
             "mos_array_layout", "mos_engine_create", "mos_engine_submit", "mos_engine_progress",
             "mos_engine_result", "mos_engine_option", "mos_engine_stats", "mos_engine_destroy", "mos_timing_start", "mos_timing_stop",
             "mos_cell_free", "mos_rom_free", "mos_sol_free", "mos_last_error")
@@ -79,6 +79,7 @@ def _load():
         "mos_reduce": (ctypes.c_int, [vp, vp, P(vp)]),
         "mos_solve_array": (ctypes.c_int, [vp, P(ArrayDesc), P(vp), ctypes.c_int32, P(vp)]),
         "mos_reconstruct": (ctypes.c_int, [vp, vp, ctypes.c_uint32, vp, vp]),
+        "mos_reconstruct_plane": (ctypes.c_int, [vp, vp, ctypes.c_int32, vp]),
         "mos_get_solution": (ctypes.c_int, [vp, vp, P(ctypes.c_double), P(ctypes.c_int32)]),
         "mos_query": (ctypes.c_int, [vp, ctypes.c_int, P(ctypes.c_int64)]),
         "mos_cell_export": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
@@ -385,6 +386,19 @@ def mos_reconstruct(ctx, sol, vm=None, sigma6=None):
     _check(lib().mos_reconstruct(ctx.ptr, sol.ptr, flags, ctypes.c_void_p(vm.data_ptr() if vm is not None else 0),
                                  ctypes.c_void_p(sigma6.data_ptr() if sigma6 is not None else 0)),
            "mos_reconstruct")
+
+
+def mos_reconstruct_plane(ctx, sol, grid, vm):
+    """Von Mises at grid x grid points of every cell's mid-height plane into a
+    caller-owned contiguous device tensor [n_cells, grid * grid]; float64 for
+    an FP64 solution, float32 for a mixed one."""
+    torch = ctx.torch
+    want = torch.float32 if sol.precision == MOS_MIXED else torch.float64
+    shape = (sol.n_cells, int(grid) * int(grid))
+    if vm.dtype != want or tuple(vm.shape) != shape or not vm.is_contiguous() or not vm.is_cuda:
+        raise ValueError(f"output must be a contiguous {want} device tensor of shape {shape}")
+    _check(lib().mos_reconstruct_plane(ctx.ptr, sol.ptr, int(grid), ctypes.c_void_p(vm.data_ptr())),
+           "mos_reconstruct_plane")
 
 
 def mos_get_solution(sol):
