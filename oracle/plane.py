@@ -121,3 +121,24 @@ def max_rel_error(vm, vm_ref):
     vm = np.asarray(vm, dtype=float).ravel()
     vm_ref = np.asarray(vm_ref, dtype=float).ravel()
     return float(np.max(np.abs(vm - vm_ref)) / np.max(np.abs(vm_ref)))
+
+
+def full_plane_von_mises(full, u, dT, g):
+    """Von Mises (n_cells, g*g) on the sample grid of every block of a full
+    fine-mesh solution (array.FullArray and its nodal u): each block's fine
+    nodal displacement is read from the global mesh (block (cx, cy) local
+    node (a, b, c) is global node (cx m_x + a, cy m_y + b, c)), then eq. 1 at
+    the sample points as for a reduced solution."""
+    out = np.zeros((full.Nx * full.Ny, g * g))
+    c = np.arange(full.mz + 1)[:, None, None]
+    b = np.arange(full.my + 1)[None, :, None]
+    a = np.arange(full.mx + 1)[None, None, :]
+    for cy in range(full.Ny):
+        for cx in range(full.Nx):
+            k = cy * full.Nx + cx
+            cell = full.cells[int(full.cell_type[k])]
+            # Local node ids run (c, b, a) with a fastest, as the broadcast below.
+            glob = full.node_id(cx * full.mx + a, cy * full.my + b, c).ravel()
+            nodal = u.reshape(-1, 3)[glob].ravel()
+            out[k] = fem.von_mises(block_plane_stress(cell, cell.material_map(), nodal, dT, g))
+    return out

@@ -1,0 +1,101 @@
+"""Convergence in the interpolation order (the sweep of Table 3, n = 24, 78,
+168, 294, 456 for (2,2,2) ... (6,6,6)) on the HIP path, on the 2x2 array of
+10x10x20 cells.
+
+At every order the GPU's FP64 result must match the oracle's reduced solution
+at that order (centroid and evaluation-plane von Mises within 1e-9 of the
+largest value), and its error against the oracle's full fine-mesh FEM -- the
+paper's normalised MAE on the mid-height 100 x 100 grid -- must fall at every
+step, as in Table 3.  The mixed-precision path must stay within 1e-3 of the
+oracle at every order (bases above 176 run the FP32-output FP64
+reconstruction, above 256 the Jacobi preconditioner).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import array as oarray
+from oracle import fem as ofem
+from oracle import mor as omor
+from oracle import plane as oplane
+
+pytestmark = pytest.mark.gpu
+
+ORDERS = (2, 3, 4, 5, 6)
+GRID = 100
+
+
+@pytest.fixture(scope="module")
+def mos():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2411_12690_amd import mos as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(mos):
+    return mos.Context(0)
+
+
+@pytest.fixture(scope="module")
+def full_reference():
+    case = W.case_c1()
+    full = oarray.FullArray(case.specs, case.cell_type, 2, 2)
+    uf, _ = full.solve(case.delta_T, True, False)
+    return oplane.full_plane_von_mises(full, uf, case.delta_T, GRID)
+
+
+def rel_max(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)).max() / np.abs(np.asarray(b)).max()
+
+
+def run_order(mos, ctx, k, mixed):
+    import torch
+    case = W.case_c1()
+    spec = dataclasses.replace(case.specs[0], interp=(k, k, k))
+    rom = mos.mos_reduce(ctx, mos.mos_build_cell(ctx, spec))
+    sol = mos.mos_solve_array(ctx, [rom], 2, 2, case.cell_type, case.delta_T, clamp_bottom=True, mixed=mixed)
+    dt = torch.float32 if mixed else torch.float64
+    n_elem = rom.query(mos.MOS_Q_CELL_ELEMS)
+    vm = torch.empty((4, n_elem), dtype=dt, device="cuda")
+    mos.mos_reconstruct(ctx, sol, vm=vm)
+    vp = torch.empty((4, GRID * GRID), dtype=dt, device="cuda")
+    mos.mos_reconstruct_plane(ctx, sol, GRID, vp)
+    return rom, spec, case, vm.double().cpu().numpy(), vp.double().cpu().numpy()
+
+
+def oracle_order(spec, case):
+    rom = omor.local_stage(spec)
+    m = oarray.AbstractMesh(2, 2, spec.interp, spec.pitch_x, spec.pitch_y, spec.height)
+    dofs, vals = oarray.constrained_dofs(m, True, False)
+    u = oarray.solve_mor(m, case.cell_type, [rom], case.delta_T, dofs, vals)
+    vm = ofem.von_mises(oarray.reconstruct(m, case.cell_type, [rom], u, case.delta_T))
+    vp = oplane.plane_von_mises(m, case.cell_type, [rom], u, case.delta_T, GRID)
+    return rom.n, vm, vp
+
+
+def test_error_falls_with_the_interpolation_order(mos, ctx, full_reference):
+    errs = []
+    for k in ORDERS:
+        print(f"[convergence] order {k}", flush=True)
+        rom, spec, case, vm, vp = run_order(mos, ctx, k, mixed=False)
+        n_ref, vm_ref, vp_ref = oracle_order(spec, case)
+        assert rom.query(mos.MOS_Q_N) == n_ref == omor.n_reduced(k, k, k)
+        assert rel_max(vm, vm_ref) < 1e-9
+        assert rel_max(vp, vp_ref) < 1e-9
+        errs.append(oplane.normalized_mae(vp, full_reference))
+        print(f"[convergence] n={n_ref} normalised MAE vs full FEM {errs[-1]:.4e}", flush=True)
+    assert all(a > b for a, b in zip(errs, errs[1:]))
+    assert errs[-1] < 0.1 * errs[0]
+
+
+@pytest.mark.parametrize("k", ORDERS)
+def test_mixed_precision_at_every_order(mos, ctx, k):
+    rom, spec, case, vm, vp = run_order(mos, ctx, k, mixed=True)
+    _, vm_ref, vp_ref = oracle_order(spec, case)
+    assert rel_max(vm, vm_ref) < 1e-3
+    assert rel_max(vp, vp_ref) < 1e-3

@@ -141,3 +141,20 @@ def test_error_metrics_on_a_hand_example():
     ref = np.array([1.0, 2.0, 3.0, 5.0])
     assert plane.normalized_mae(vm, ref) == pytest.approx(0.25 / 5.0)
     assert plane.max_rel_error(vm, ref) == pytest.approx(1.0 / 5.0)
+
+
+def test_full_fem_plane_agrees_with_mor_when_nodes_cover_the_boundary():
+    # Lagrange nodes on every boundary FE node: MOR is static condensation,
+    # so the reduced and the full plane fields coincide (pins the full-mesh
+    # node gather of the plane evaluation against the reduced path).
+    s = spec_small(mesh=(4, 4, 4), interp=(5, 5, 5))
+    rom = mor.local_stage(s)
+    t = np.array([0, 0, 0, 0], dtype=np.uint8)
+    m = array.AbstractMesh(2, 2, s.interp, 3.0, 3.0, 6.0)
+    dofs, vals = array.constrained_dofs(m, True, False)
+    u = array.solve_mor(m, t, [rom], -250.0, dofs, vals)
+    vm = plane.plane_von_mises(m, t, [rom], u, -250.0, 6)
+    full = array.FullArray([s], t, 2, 2)
+    uf, _ = full.solve(-250.0, True, False)
+    vmf = plane.full_plane_von_mises(full, uf, -250.0, 6)
+    assert plane.max_rel_error(vm, vmf) < 1e-9
