@@ -20,6 +20,9 @@ latency is per array.
 mid-height plane) for the 16x16 array, FP64 and mixed, with the normalised
 MAE of the mixed field against the FP64 one.
 
+--mode convergence: Table 3's sweep of interpolation orders (2..6)^3 on a
+20x20 array: local- and global-stage times, iterations, self-convergence.
+
 --mode serve: a Poisson stream of requests (mean 200 /s; N ~ U{4..48},
 pitch ~ U{10,15,20} um, dT ~ U[-300,-150] K, 10% dummy cells) served with
 continuous batching in mixed precision; reports TSV-cells/s and p50/p99 of
@@ -547,6 +550,86 @@ def plane_mode(args, mos, torch, np, W):
     print(json.dumps(out))
 
 
+def convergence_mode(args, mos, torch, np, W):
+    """The interpolation-order sweep of Table 3 on one GPU: a 20x20 array of
+    15x15x50 um cells (16x16x32 hexes, d = 5 um, dT = -250 K, bottom clamped)
+    at orders (2,2,2) ... (6,6,6).  Per order: the one-shot local stage
+    (mos_build_cell + mos_reduce), the global stage of one array call
+    (mos_solve_array + centroid reconstruction) in FP64 and mixed precision,
+    PCG iterations, and the normalised MAE of the plane von Mises (100 x 100
+    per cell) against the (6,6,6) FP64 field -- a self-convergence measure,
+    since the paper's reference (a commercial solver on its own mesh) is not
+    available."""
+    import dataclasses
+    base = W.CellSpec()
+    N = 20
+    cell_type = np.zeros(N * N, dtype=np.uint8)
+    g = args.grid
+    ctx = mos.Context(0)
+    rows, planes = [], {}
+    for k in (2, 3, 4, 5, 6):
+        spec = dataclasses.replace(base, interp=(k, k, k))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rom = mos.mos_reduce(ctx, mos.mos_build_cell(ctx, spec))
+        torch.cuda.synchronize()
+        local_ms = (time.perf_counter() - t0) * 1e3
+        n = rom.query(mos.MOS_Q_N)
+        n_elem = rom.query(mos.MOS_Q_CELL_ELEMS)
+        row = {"interp": [k, k, k], "n": n, "local_stage_ms": round(local_ms, 2)}
+        for prec in ("fp64", "mixed"):
+            mixed = prec == "mixed"
+            dt = torch.float32 if mixed else torch.float64
+            vm = torch.empty((N * N, n_elem), dtype=dt, device="cuda")
+
+            def run():
+                sol = mos.mos_solve_array(ctx, [rom], N, N, cell_type, -250.0, clamp_bottom=True, mixed=mixed)
+                mos.mos_reconstruct(ctx, sol, vm=vm)
+                return sol
+
+            for _ in range(args.warmup):
+                run()
+            quiet_gc()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.steps):
+                sol = run()
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t1) / args.steps
+            vp = torch.empty((N * N, g * g), dtype=dt, device="cuda")
+            mos.mos_reconstruct_plane(ctx, sol, g, vp)
+            planes[(k, prec)] = vp.double().cpu().numpy()
+            row[prec] = {"global_stage_ms": round(wall * 1e3, 3), "cells_per_s": round(N * N / wall, 1),
+                         "pcg_iters": sol.query(mos.MOS_Q_ITERS), "refinement_sweeps": sol.query(mos.MOS_Q_REFINES)}
+            del sol, vm, vp
+        rows.append(row)
+        del rom
+        torch.cuda.empty_cache()
+    ref = planes[(6, "fp64")]
+    for row in rows:
+        k = row["interp"][0]
+        for prec in ("fp64", "mixed"):
+            v = planes[(k, prec)]
+            row[prec]["plane_nmae_vs_order6_fp64"] = float(np.mean(np.abs(v - ref)) / np.abs(ref).max())
+    head = rows[2]["fp64"]
+    out = {
+        "mode": "convergence",
+        "metric": METRIC,
+        "value": head["cells_per_s"],
+        "unit": "TSV-cells/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": head["global_stage_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "20x20 TSV array, 16x16x32 hex cells, interpolation orders 2..6",
+                   "array": f"{N}x{N}", "cell_um": [base.pitch_x, base.pitch_y, base.height],
+                   "cell_mesh": list(base.mesh), "tsv_diameter_um": base.tsv_diameter, "delta_T": -250.0,
+                   "bc": "bottom clamped", "plane_grid": [g, g], "value_is": "order (4,4,4), FP64"},
+        "orders": rows,
+    }
+    print(json.dumps(out))
+
+
 def calib_mode(args, torch):
     """A plain device copy of known size (1 GiB read, 1 GiB written per
     launch): the reference that scales the FETCH_SIZE / WRITE_SIZE counters
@@ -664,7 +747,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--mode", choices=["batch", "serve", "single", "calib", "plane"], default="batch")
+    ap.add_argument("--mode", choices=["batch", "serve", "single", "calib", "plane", "convergence"], default="batch")
     ap.add_argument("--grid", type=int, default=100, help="plane mode: sample points per cell along x and y")
     ap.add_argument("--workload", choices=["c3", "c5"], default="c3")
     ap.add_argument("--batch", type=int, default=128)
@@ -705,6 +788,8 @@ def main():
         single_mode(args, mos, torch, np, W)
     elif args.mode == "plane":
         plane_mode(args, mos, torch, np, W)
+    elif args.mode == "convergence":
+        convergence_mode(args, mos, torch, np, W)
     else:
         serve_mode(args, mos, torch, np, W)
 
