@@ -172,7 +172,7 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False, vm_ref=None):
     n_dofs_pad = -(-n_dofs // 768) * 768
     eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=int(B * (n_dofs_pad * 140 + n_cells * 16 * 176 * 34)
                                                              * 1.3) + (64 << 20), gemm=args.cell_gemm,
-                     precond=args.precond)
+                     precond=args.precond, graph=args.graph)
     # The workload's cells fit the two-level kernels, so the engine's default is on.
     precond = 1 if args.precond is None else args.precond
     if args.gemm_split is not None:
@@ -218,8 +218,12 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False, vm_ref=None):
 
     # Timed region: one launch in TIME_EVERY of the dominant kernel carries
     # dispatch-stamped HIP events on its stream (stamping every launch adds
-    # host work to the step being measured).
-    mos.mos_timing_start(ctx, dominant, TIME_EVERY)
+    # host work to the step being measured).  With graph replay of the
+    # iteration chunks the timed region runs unsampled (a sampled kernel
+    # keeps its chunk out of the graph) and the kernel is sampled in a
+    # separate pass of the same steps afterwards.
+    if not args.graph:
+        mos.mos_timing_start(ctx, dominant, TIME_EVERY)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     recs = []
     quiet_gc()
@@ -229,23 +233,31 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False, vm_ref=None):
         step(recs)
         ev[s + 1].record(stream)
     torch.cuda.synchronize()
+    sampled = recs
+    if args.graph:
+        sampled = []
+        mos.mos_timing_start(ctx, dominant, TIME_EVERY)
+        for s in range(max(2, args.steps // 2)):
+            step(sampled)
+        torch.cuda.synchronize()
     launches, k_ms, seen = mos.mos_timing_stop(ctx)
     total_ms = ev[0].elapsed_time(ev[-1])
     ms_per_step = total_ms / args.steps
     lat = np.array([v[0] * 1e3 for r in recs for v in r.values()])
     iters = [v[1] for r in recs for v in r.values()]
     sweeps = [v[2] for r in recs for v in r.values()]
+    iters_sampled = [v[1] for r in sampled for v in r.values()]
 
     name, bound, unit, note = KERNEL_INFO[dominant]
     if dominant == mos.MOS_K_PCG_UPDATE:
         note = UPDATE_NOTE[precond]
     if dominant == mos.MOS_K_RECON:
-        work = 2.0 * 6 * n_elem * n * n_cells * B * args.steps
+        work = 2.0 * 6 * n_elem * n * n_cells * B * len(sampled)
         peak = PEAK_BF16_TFLOPS if mixed else PEAK_FP64_TFLOPS
     else:
         per_it = per_iteration_work(dominant, mos, n, n_cells, n_dofs_pad, n_nodes, mixed, precond, n_dofs,
                                     coarse_aggregates(16, 16))
-        work = per_it * sum(iters)
+        work = per_it * sum(iters_sampled)
         if bound == "mfma":
             peak = PEAK_FP32_TFLOPS if mixed else PEAK_FP64_TFLOPS
         else:
@@ -259,7 +271,7 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False, vm_ref=None):
                 "kernel": name,
                 "avg_launch_us": round(avg_s * 1e6, 3), "timed_launches": int(launches), "launches": int(seen),
                 "timed_every": TIME_EVERY, "work_per_launch": round(work_per_launch, 1), "work_note": note,
-                "kernel_share_of_step": round(avg_s * seen * 1e3 / total_ms, 4),
+                "kernel_share_of_step": round(avg_s * seen / len(sampled) * 1e3 / ms_per_step, 4),
                 "kernels_ms_per_step": {KERNEL_INFO[k][0]: round(v[1], 4) for k, v in totals.items()}}
 
     # Single-array latency (batch of one), for reference.
@@ -302,7 +314,8 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False, vm_ref=None):
                    "reduced_dofs_per_array": int(n_dofs), "delta_T": -250.0, "bc": "bottom clamped",
                    "precision": precision, "seed": args.seed, "pcg_chunk": args.chunk,
                    "gemm_split": args.gemm_split if args.gemm_split is not None else "tuned",
-                   "preconditioner": "jacobi" if precond == 0 else "jacobi + aggregate coarse correction"},
+                   "preconditioner": "jacobi" if precond == 0 else "jacobi + aggregate coarse correction",
+                   "chunk_launch": "graph replay" if args.graph else "direct"},
         "p50_ms": round(float(np.percentile(lat, 50)), 4),
         "p99_ms": round(float(np.percentile(lat, 99)), 4),
         "step_ms": [round(ev[s].elapsed_time(ev[s + 1]), 3) for s in range(args.steps)],
@@ -767,6 +780,9 @@ def main():
                     help="batch mode: skip the single-array latency pass (for counter runs that average over "
                          "every launch of the process)")
     ap.add_argument("--chunk", type=int, default=16)
+    ap.add_argument("--graph", type=int, choices=[0, 1], default=0,
+                    help="batch mode: replay each chunk of PCG iterations from a captured HIP graph (1) or launch "
+                         "its kernels directly (0, default)")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--budget-gb", type=float, default=32.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")

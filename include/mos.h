@@ -271,8 +271,21 @@ mos_status mos_engine_result(mos_engine e, int64_t ticket, int32_t *status, doub
  * most 256 reduced DoFs and at most 1024 nodes in a box of 8x2 cells
  * (MOS_EINVAL otherwise; engines whose cells exceed this start with 0).
  * Set it before the first submission. */
-enum { MOS_OPT_CELL_GEMM = 1, MOS_OPT_GEMM_SPLIT = 2, MOS_OPT_UPDATE_WIDTH = 3, MOS_OPT_PRECOND = 4 };
+/* MOS_OPT_GRAPH = 1 replays each chunk of PCG iterations (the launches of
+ * mos_engine_progress's chunk: cell GEMM, scalar and update launches of
+ * every iteration) from a HIP graph captured once per launch shape (batch
+ * extents, chunk length, chosen GEMM split) instead of launching its
+ * kernels one by one; 0 (default) launches them directly.  Chunks during a
+ * GEMM tuning trial, or while mos_timing_start samples one of the chunk's
+ * kernels, are launched directly either way.  The kernels and their
+ * arguments are the same, so results do not depend on it; it may be
+ * changed at any time. */
+enum { MOS_OPT_CELL_GEMM = 1, MOS_OPT_GEMM_SPLIT = 2, MOS_OPT_UPDATE_WIDTH = 3, MOS_OPT_PRECOND = 4,
+       MOS_OPT_GRAPH = 5 };
 mos_status mos_engine_option(mos_engine e, int option, int64_t value);
+/* Counts of iteration-chunk graph captures and replays so far (MOS_OPT_GRAPH;
+ * either pointer may be NULL). */
+mos_status mos_engine_graph_stats(mos_engine e, int64_t *captures, int64_t *replays);
 
 /* Problems admitted and queued, and the arena capacities. */
 mos_status mos_engine_stats(mos_engine e, int64_t *active, int64_t *queued, int64_t *capacity_dofs,

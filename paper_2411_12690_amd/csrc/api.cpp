@@ -594,6 +594,10 @@ mos_status mos_engine_option(mos_engine e, int option, int64_t value) {
         e->update_width = (int)value;
         return MOS_OK;
     }
+    if (option == MOS_OPT_GRAPH && (value == 0 || value == 1)) {
+        e->use_graph = (int)value;
+        return MOS_OK;
+    }
     if (option == MOS_OPT_GEMM_SPLIT && value >= 0 && value <= 64) {
         e->gemm_split = (int)value;
         e->tuner.configure(e->gemm_paths, e->gemm_split);
@@ -601,6 +605,16 @@ mos_status mos_engine_option(mos_engine e, int option, int64_t value) {
     }
     set_error("unknown option %d or value %lld", option, (long long)value);
     return MOS_EINVAL;
+}
+
+mos_status mos_engine_graph_stats(mos_engine e, int64_t *captures, int64_t *replays) {
+    if (!e) {
+        set_error("invalid engine");
+        return MOS_EINVAL;
+    }
+    if (captures) *captures = e->graph_captures;
+    if (replays) *replays = e->graph_replays;
+    return MOS_OK;
 }
 
 mos_status mos_engine_stats(mos_engine e, int64_t *active, int64_t *queued, int64_t *capacity_dofs,

@@ -69,6 +69,8 @@ struct SweepParams {
 // Largest number of 4-wide k-steps (ldk <= 176, basis size <= 176) the
 // K_r-stationary GEMM keeps in registers; larger bases use the tile GEMM.
 constexpr int ROWS_MAX_KS = 44;
+// Entries of the launch shape a captured iteration chunk is valid for.
+constexpr int GRAPH_KEY = 11;
 
 // Online tuner of the rows GEMM's work split (slot blocks per wave).  The
 // split only decides which wave computes which output tile -- every tile is
@@ -175,6 +177,15 @@ struct mos_engine_s {
     mos::ReconJob *jobs = nullptr, *jobs_host = nullptr;  // batched reconstruction table (device, pinned)
     mos::ProbParams *pp = nullptr, *pp_host = nullptr;    // per-problem parameters (device, pinned)
     int epoch = 0;                                        // PCG iteration launches issued so far
+    int *epoch_dev = nullptr;  // [1] first epoch of the chunk in flight (iteration kernels add their place)
+    // Graph replay of iteration chunks (MOS_OPT_GRAPH): the instantiated
+    // chunk, the launch shape it was captured for, the private stream it is
+    // captured on, and counts of captures and replays.
+    int use_graph = 0;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_key[mos::GRAPH_KEY] = {};
+    hipStream_t cap_stream = nullptr;
+    int64_t graph_captures = 0, graph_replays = 0;
     mos::SweepParams *sp = nullptr, *sp_host = nullptr;   // per-sweep parameters (device, pinned)
     int32_t *surf = nullptr;  // [S][3] surface Lagrange nodes (i, j, k) of a cell, s order
     int S = 0;

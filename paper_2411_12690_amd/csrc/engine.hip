@@ -198,12 +198,15 @@ __device__ __forceinline__ void cg_publish(ProbState &S, int it, const CgStep &o
 }
 
 // Separate scalar launch for problems too large to reduce in every update
-// workgroup: one workgroup per problem, iteration launch `epoch`.  The
+// workgroup: one workgroup per problem, iteration launch ep[0] + j (the
+// chunk's first epoch, set on the device, plus the launch's place in the
+// chunk, so a captured chunk replays with the epochs of its replay).  The
 // per-block partials are double-buffered by iteration parity: iteration it
 // reads slot it & 1 (written by the previous update or the sweep start).
 __global__ __launch_bounds__(256) void k_cg_scalars(ProbState *ps, const double *pg, const double *pr,
-                                                    const double *pdel, int epoch, int cap_blk) {
+                                                    const double *pdel, const int *ep, int j, int cap_blk) {
     __shared__ double red[3][CG_LW];
+    const int epoch = ep[0] + j;
     ProbState &S = ps[blockIdx.x];
     const int active = S.active, done = S.done, fused = S.fused;  // one round trip
     if (!((active != 0) & (done == 0) & (fused == 0))) return;     // uniform over the workgroup
@@ -735,8 +738,8 @@ constexpr int CG_WIDE_MAX_BLK = 2048;
 template <class T, int NT>
 __global__ __launch_bounds__(NT) void k_cgstep(const T *Y, const int32_t *inc, const uint8_t *cmask, const T *dinv,
                                                T *x, T *r, T *p, T *s, T *Mc, int ld_slots, const int32_t *blk_prob,
-                                               ProbState *ps, double *pg, double *pr, const double *pdel, int epoch,
-                                               int cap_blk, int n_blk) {
+                                               ProbState *ps, double *pg, double *pr, const double *pdel,
+                                               const int *ep, int j, int cap_blk, int n_blk) {
     constexpr int DPT = DB / NT;
     __shared__ int go, it_sh;
     __shared__ double step[2];
@@ -767,7 +770,7 @@ __global__ __launch_bounds__(NT) void k_cgstep(const T *Y, const int32_t *inc, c
             g = ((active != 0) & (done == 0)) ? 1 + (fused != 0) : 0;
             step[0] = a_cur;
             step[1] = b_cur;
-            it_sh = epoch - start;
+            it_sh = ep[0] + j - start;
         }
         go = g;
     }
@@ -1064,8 +1067,8 @@ __global__ __launch_bounds__(1024) void k_cgstep2(const T *Y, const int32_t *inc
                                                   const T *dinv, const uint32_t *lc, T *x, T *r, T *p, T *s, T *Mc,
                                                   int ld_slots, const int4 *box_tab, const ProbParams *pp,
                                                   ProbState *ps, double *pg, double *pr, const double *pdel,
-                                                  const double *binv, double *cc, int epoch, int cap_blk,
-                                                  int n_box) {
+                                                  const double *binv, double *cc, const int *ep, int j,
+                                                  int cap_blk, int n_box) {
     // Dynamic LDS: the per-node restriction terms (blockDim.x x 6 doubles),
     // first used as the scalar step's reduction space (3 x CG_LW doubles).
     extern __shared__ double qn_dyn[];
@@ -1097,7 +1100,7 @@ __global__ __launch_bounds__(1024) void k_cgstep2(const T *Y, const int32_t *inc
         const int g = ((active != 0) & (done == 0)) ? 1 + (fused != 0) : 0;
         step[0] = a_cur;
         step[1] = b_cur;
-        it_sh = epoch - start;
+        it_sh = ep[0] + j - start;
         go = g;
     }
     __syncthreads();
@@ -2169,6 +2172,7 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     MOS_TRY(m.alloc_n((size_t)e->cap_blk * MAXA * 36, &e->binv));
     MOS_TRY(m.alloc_n((size_t)e->cap_blk * MAXA * 6, &e->cc));
     MOS_TRY(m.alloc_n(MAX_PROBS, &e->ps));
+    MOS_TRY(m.alloc_n(1, &e->epoch_dev));
     MOS_TRY(m.alloc_n(MAX_PROBS, &e->res2));
     MOS_TRY(m.alloc_n(MAX_PROBS, &e->bb2));
     if (hipHostMalloc((void **)&e->host_scratch, 8 * sizeof(double), hipHostMallocDefault) !=
@@ -2395,9 +2399,9 @@ mos_status release_problems(mos_engine e, const std::vector<EngineProblem *> &pr
 template <class T>
 mos_status rows_step(mos_engine e, int ks, int hw_sb);
 
-// The update launch of one iteration over [0, hw_blk) DoF blocks.
+// The update launch of iteration j of the chunk over [0, hw_blk) DoF blocks.
 template <class T>
-void cgstep_launch(mos_engine e, int hw_blk, T *const *V) {
+void cgstep_launch(mos_engine e, int hw_blk, T *const *V, int j) {
     hipStream_t st = e->ctx->stream;
     if (e->precond) {
         const int hw_box = e->boxes.high;
@@ -2405,8 +2409,8 @@ void cgstep_launch(mos_engine e, int hw_blk, T *const *V) {
                      dim3(e->box_nt), e->box_nt * 6 * sizeof(double), st, (const T *)e->Yi, (const int32_t *)e->inc,
                      (const uint8_t *)e->cmask, (const T *)V[VDINV], (const uint32_t *)e->lc, V[VX], V[VR], V[VP],
                      V[VS], (T *)e->Mc, e->ld_slots, (const int4 *)e->box_tab, (const ProbParams *)e->pp, e->ps,
-                     e->pg, e->pr, (const double *)e->pdel, (const double *)e->binv, e->cc, e->epoch, e->cap_blk,
-                     hw_box);
+                     e->pg, e->pr, (const double *)e->pdel, (const double *)e->binv, e->cc,
+                     (const int *)e->epoch_dev, j, e->cap_blk, hw_box);
         return;
     }
     const bool wide = e->update_width ? e->update_width == 256 : hw_blk <= CG_WIDE_MAX_BLK;
@@ -2415,12 +2419,12 @@ void cgstep_launch(mos_engine e, int hw_blk, T *const *V) {
         launch_timed(e->ctx, MOS_K_PCG_UPDATE, k_cgstep<T, 256>, grid, dim3(256), 0, st, (const T *)e->Yi,
                      (const int32_t *)e->inc, (const uint8_t *)e->cmask, (const T *)V[VDINV], V[VX], V[VR], V[VP],
                      V[VS], (T *)e->Mc, e->ld_slots, (const int32_t *)e->blk_prob, e->ps, e->pg, e->pr,
-                     (const double *)e->pdel, e->epoch, e->cap_blk, hw_blk);
+                     (const double *)e->pdel, (const int *)e->epoch_dev, j, e->cap_blk, hw_blk);
     else
         launch_timed(e->ctx, MOS_K_PCG_UPDATE, k_cgstep<T, 128>, grid, dim3(128), 0, st, (const T *)e->Yi,
                      (const int32_t *)e->inc, (const uint8_t *)e->cmask, (const T *)V[VDINV], V[VX], V[VR], V[VP],
                      V[VS], (T *)e->Mc, e->ld_slots, (const int32_t *)e->blk_prob, e->ps, e->pg, e->pr,
-                     (const double *)e->pdel, e->epoch, e->cap_blk, hw_blk);
+                     (const double *)e->pdel, (const int *)e->epoch_dev, j, e->cap_blk, hw_blk);
 }
 
 // Read the tuning trials of the last chunk (the stream has been synchronised).
@@ -2527,6 +2531,124 @@ mos_status rows_step(mos_engine e, int ks, int hw_sb) {
     return MOS_OK;
 }
 
+
+namespace {
+
+// The launches of one chunk of iterations on e->ctx->stream: per iteration
+// the cell GEMM (w = A u, (u, A u) tile partials), the scalar launch when a
+// large problem iterates, and the vector update (which reduces small
+// problems' scalars itself).  Iteration j reads its epoch as
+// epoch_dev[0] + j.
+mos_status issue_chunk(mos_engine e, int chunk, int hw_sb, int hw_blk, int hw_p, bool rows, int ks, bool any_large) {
+    mos_ctx ctx = e->ctx;
+    hipStream_t st = ctx->stream;
+    const dim3 g_gemm(e->ldk / 16, hw_sb);
+    for (int j = 0; j < chunk; ++j) {
+        if (e->precision == MOS_MIXED) {
+            float *V[NVEC];
+            for (int i = 0; i < NVEC; ++i) V[i] = static_cast<float *>(e->v[i]);
+            if (rows)
+                MOS_TRY(rows_step<float>(e, ks, hw_sb));
+            else
+                launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm<float>, g_gemm, dim3(256), 0, st,
+                             (const void *const *)e->kr32_tab, (const int32_t *)e->sb_rom,
+                             (const int32_t *)e->sb_prob, (const float *)e->Mc, (float *)e->Yi, e->ldk, e->ld_slots,
+                             0, hw_sb, 1, (const ProbState *)e->ps, e->pdel, ProbSel{});
+            if (any_large)
+                launch_timed(ctx, MOS_K_PCG_SCALARS, k_cg_scalars, dim3(hw_p), dim3(256), 0, st, e->ps,
+                             (const double *)e->pg, (const double *)e->pr, (const double *)e->pdel,
+                             (const int *)e->epoch_dev, j, e->cap_blk);
+            cgstep_launch<float>(e, hw_blk, V, j);
+        } else {
+            double *V[NVEC];
+            for (int i = 0; i < NVEC; ++i) V[i] = static_cast<double *>(e->v[i]);
+            if (rows)
+                MOS_TRY(rows_step<double>(e, ks, hw_sb));
+            else
+                launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm<double>, g_gemm, dim3(256), 0, st,
+                             (const void *const *)e->kr64_tab, (const int32_t *)e->sb_rom,
+                             (const int32_t *)e->sb_prob, (const double *)e->Mc, (double *)e->Yi, e->ldk,
+                             e->ld_slots, 0, hw_sb, 1, (const ProbState *)e->ps, e->pdel, ProbSel{});
+            if (any_large)
+                launch_timed(ctx, MOS_K_PCG_SCALARS, k_cg_scalars, dim3(hw_p), dim3(256), 0, st, e->ps,
+                             (const double *)e->pg, (const double *)e->pr, (const double *)e->pdel,
+                             (const int *)e->epoch_dev, j, e->cap_blk);
+            cgstep_launch<double>(e, hw_blk, V, j);
+        }
+    }
+    MOS_LAUNCH_CHECK();
+    return MOS_OK;
+}
+
+__global__ void k_set_epoch(int *ep, int value) {
+    if (threadIdx.x == 0) ep[0] = value;
+}
+
+// One chunk: the chunk's first epoch to the device, then its launches --
+// replayed from a captured graph when the engine's graph option is on and
+// the chunk's launch sequence is fixed (no GEMM tuning trial, no kernel of
+// the chunk under the kernel timer), otherwise issued directly.  The graph
+// is captured on a private stream and launched on the context's stream; it
+// is captured again whenever anything that shapes the launches changes.
+mos_status run_chunk(mos_engine e, int chunk, int hw_sb, int hw_blk, int hw_p, bool rows, int ks, bool any_large) {
+    mos_ctx ctx = e->ctx;
+    hipStream_t st = ctx->stream;
+    hipLaunchKernelGGL(k_set_epoch, dim3(1), dim3(64), 0, st, e->epoch_dev, e->epoch);
+    MOS_LAUNCH_CHECK();
+    int cand = 0;
+    bool fixed = true;
+    if (rows && e->tuner.n_cand > 1) {
+        int bucket = 0;
+        while ((1 << bucket) < hw_sb) ++bucket;
+        auto it = e->tuner.buckets.find(bucket);
+        fixed = it != e->tuner.buckets.end() && it->second.chosen > 0;
+        cand = fixed ? it->second.chosen - 1 : -1;
+    }
+    const int tk = ctx->timed_kernel;
+    const bool timed = tk == MOS_K_CELL_GEMM || tk == MOS_K_PCG_SCALARS || tk == MOS_K_PCG_UPDATE;
+    if (!e->use_graph || !fixed || timed) {
+        MOS_TRY(issue_chunk(e, chunk, hw_sb, hw_blk, hw_p, rows, ks, any_large));
+        e->epoch += chunk;
+        return MOS_OK;
+    }
+    const int key[GRAPH_KEY] = {chunk, hw_sb, hw_blk, hw_p, e->boxes.high, rows ? 1 : 0, cand, any_large ? 1 : 0,
+                                e->precond, e->box_nt, e->update_width};
+    if (!e->graph_exec || !std::equal(key, key + GRAPH_KEY, e->graph_key)) {
+        if (e->graph_exec) {
+            MOS_HIP(hipGraphExecDestroy(e->graph_exec));
+            e->graph_exec = nullptr;
+        }
+        if (!e->cap_stream) MOS_HIP(hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        ctx->stream = e->cap_stream;
+        hipError_t be = hipStreamBeginCapture(e->cap_stream, hipStreamCaptureModeThreadLocal);
+        mos_status s = be == hipSuccess ? issue_chunk(e, chunk, hw_sb, hw_blk, hw_p, rows, ks, any_large) : MOS_EHIP;
+        hipError_t ce = be == hipSuccess ? hipStreamEndCapture(e->cap_stream, &g) : be;
+        ctx->stream = st;
+        if (s != MOS_OK || ce != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            if (s == MOS_OK) set_error("graph capture of the iteration chunk failed: %s", hipGetErrorString(ce));
+            return s != MOS_OK ? s : MOS_EHIP;
+        }
+        const hipError_t ie = hipGraphInstantiate(&e->graph_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            e->graph_exec = nullptr;
+            set_error("graph instantiation of the iteration chunk failed: %s", hipGetErrorString(ie));
+            return MOS_EHIP;
+        }
+        std::copy(key, key + GRAPH_KEY, e->graph_key);
+        ++e->graph_captures;
+    }
+    MOS_HIP(hipGraphLaunch(e->graph_exec, st));
+    ++e->graph_replays;
+    e->epoch += chunk;
+    return MOS_OK;
+}
+
+}  // namespace
+
 // One round: admit, iterate a chunk, check stopped problems, retire finished.
 mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *completed) {
     mos_ctx ctx = e->ctx;
@@ -2579,54 +2701,15 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
     for (EngineProblem *P : e->active) any_iter |= P->state == 1;
     if (any_iter) {
         const int hw_sb = e->sbs.high, hw_blk = e->blk.high, hw_p = e->pids.high;
-        const dim3 g_gemm(e->ldk / 16, hw_sb);
         // Cell GEMM variant is fixed per engine; the rows variant picks how
         // many slot blocks each wave streams from the batch size only (its
         // results do not depend on that choice).
         const int ks = e->ldk / 4;
         const bool rows = e->gemm_rows && ks <= ROWS_MAX_KS;
-        const int nrb = e->ldk / 16;
-        (void)nrb;
         bool any_large = false;
         for (EngineProblem *P : e->active)
             if (P->state == 1 && !e->pp_host[P->pid].fused) any_large = true;
-        for (int j = 0; j < chunk; ++j) {
-            // Per iteration: cell GEMM (w = A u, (u, A u) tile partials),
-            // the scalar launch when a large problem iterates, and the
-            // vector update (which reduces small problems' scalars itself).
-            if (e->precision == MOS_MIXED) {
-                float *V[NVEC];
-                for (int i = 0; i < NVEC; ++i) V[i] = static_cast<float *>(e->v[i]);
-                if (rows)
-                    MOS_TRY(rows_step<float>(e, ks, hw_sb));
-                else
-                    launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm<float>, g_gemm, dim3(256), 0, st,
-                                 (const void *const *)e->kr32_tab, (const int32_t *)e->sb_rom,
-                                 (const int32_t *)e->sb_prob, (const float *)e->Mc, (float *)e->Yi, e->ldk,
-                                 e->ld_slots, 0, hw_sb, 1, (const ProbState *)e->ps, e->pdel, ProbSel{});
-                if (any_large)
-                    launch_timed(ctx, MOS_K_PCG_SCALARS, k_cg_scalars, dim3(hw_p), dim3(256), 0, st, e->ps,
-                                 (const double *)e->pg, (const double *)e->pr, (const double *)e->pdel, e->epoch,
-                                 e->cap_blk);
-                cgstep_launch<float>(e, hw_blk, V);
-            } else {
-                double *V[NVEC];
-                for (int i = 0; i < NVEC; ++i) V[i] = static_cast<double *>(e->v[i]);
-                if (rows)
-                    MOS_TRY(rows_step<double>(e, ks, hw_sb));
-                else
-                    launch_timed(ctx, MOS_K_CELL_GEMM, k_bgemm<double>, g_gemm, dim3(256), 0, st,
-                                 (const void *const *)e->kr64_tab, (const int32_t *)e->sb_rom,
-                                 (const int32_t *)e->sb_prob, (const double *)e->Mc, (double *)e->Yi, e->ldk,
-                                 e->ld_slots, 0, hw_sb, 1, (const ProbState *)e->ps, e->pdel, ProbSel{});
-                if (any_large)
-                    launch_timed(ctx, MOS_K_PCG_SCALARS, k_cg_scalars, dim3(hw_p), dim3(256), 0, st, e->ps,
-                                 (const double *)e->pg, (const double *)e->pr, (const double *)e->pdel, e->epoch,
-                                 e->cap_blk);
-                cgstep_launch<double>(e, hw_blk, V);
-            }
-            ++e->epoch;
-        }
+        MOS_TRY(run_chunk(e, chunk, hw_sb, hw_blk, hw_p, rows, ks, any_large));
         MOS_LAUNCH_CHECK();
         // 3. Problems whose inner solve stopped: fold in the correction, FP64 residual.
         const ProbState *hs = e->ps_host;
@@ -2838,6 +2921,10 @@ void engine_free(mos_engine e) {
     e->perm_host = nullptr;
     if (e->mirror_ev) (void)hipEventDestroy(e->mirror_ev);
     e->mirror_ev = nullptr;
+    if (e->graph_exec) (void)hipGraphExecDestroy(e->graph_exec);
+    e->graph_exec = nullptr;
+    if (e->cap_stream) (void)hipStreamDestroy(e->cap_stream);
+    e->cap_stream = nullptr;
 }
 
 }  // namespace mos

@@ -79,14 +79,17 @@ namespace mos {
 // event pair the dispatch itself stamps (start and end of its execution).
 bool timer_take(mos_ctx ctx, int id, hipEvent_t *e0, hipEvent_t *e1);
 
-// Launch through hipExtLaunchKernelGGL so that sampled launches carry their
-// own execution timestamps; unsampled launches pass null events.
+// Sampled launches go through hipExtLaunchKernelGGL so that they carry their
+// own execution timestamps; the others are plain launches (which stream
+// capture records as kernel nodes).
 template <typename F, typename... Args>
 inline void launch_timed(mos_ctx ctx, int id, F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t stream,
                          Args... args) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    timer_take(ctx, id, &e0, &e1);
-    hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, e0, e1, 0, args...);
+    if (timer_take(ctx, id, &e0, &e1))
+        hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, e0, e1, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, shmem, stream, args...);
 }
 }  // namespace mos
 

@@ -23,7 +23,7 @@ MOS_OUT_VM, MOS_OUT_SIGMA6 = 1, 2
 EXPORTED = ("mos_ctx_create", "mos_ctx_destroy", "mos_build_cell", "mos_reduce", "mos_solve_array",
             "mos_reconstruct", "mos_reconstruct_plane", "mos_get_solution", "mos_query", "mos_cell_export", "mos_rom_export",
             "mos_array_layout", "mos_engine_create", "mos_engine_submit", "mos_engine_progress",
-            "mos_engine_result", "mos_engine_option", "mos_engine_stats", "mos_engine_destroy", "mos_timing_start", "mos_timing_stop",
+            "mos_engine_result", "mos_engine_option", "mos_engine_stats", "mos_engine_graph_stats", "mos_engine_destroy", "mos_timing_start", "mos_timing_stop",
             "mos_cell_free", "mos_rom_free", "mos_sol_free", "mos_last_error")
 MOS_K_CELL_GEMM, MOS_K_PCG_SCALARS, MOS_K_PCG_UPDATE, MOS_K_RECON = 1, 2, 3, 4
 MOS_OPT_CELL_GEMM = 1
@@ -31,6 +31,7 @@ GEMM_AUTO, GEMM_TILES, GEMM_ROWS, GEMM_ROWS_LDS = 0, 1, 2, 3
 MOS_OPT_GEMM_SPLIT = 2
 MOS_OPT_UPDATE_WIDTH = 3
 MOS_OPT_PRECOND = 4
+MOS_OPT_GRAPH = 5
 
 
 class MosError(RuntimeError):
@@ -94,6 +95,7 @@ def _load():
         "mos_engine_option": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int64]),
         "mos_engine_stats": (ctypes.c_int, [vp, P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64),
                                             P(ctypes.c_int64)]),
+        "mos_engine_graph_stats": (ctypes.c_int, [vp, P(ctypes.c_int64), P(ctypes.c_int64)]),
         "mos_engine_destroy": (None, [vp]),
         "mos_timing_start": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int]),
         "mos_timing_stop": (ctypes.c_int, [vp, P(ctypes.c_int64), P(ctypes.c_double), P(ctypes.c_int64)]),
@@ -280,7 +282,7 @@ class Engine:
     """Batched / served global stage (mos_engine_*): submit problems, call
     progress() until their tickets complete."""
 
-    def __init__(self, ctx, roms, mixed=False, device_bytes=8 << 30, gemm=None, precond=None):
+    def __init__(self, ctx, roms, mixed=False, device_bytes=8 << 30, gemm=None, precond=None, graph=None):
         self.ctx = ctx
         self.roms = list(roms)
         self.mixed = mixed
@@ -294,6 +296,8 @@ class Engine:
             self.option(MOS_OPT_CELL_GEMM, gemm)
         if precond is not None:
             self.option(MOS_OPT_PRECOND, precond)
+        if graph is not None:
+            self.option(MOS_OPT_GRAPH, int(graph))
 
     def submit(self, nx_cells, ny_cells, cell_type, delta_T, vm=None, sigma6=None, u=None, **kw):
         d, keep = array_desc(nx_cells, ny_cells, cell_type, delta_T, mixed=self.mixed, **kw)
@@ -322,6 +326,13 @@ class Engine:
 
     def option(self, option, value):
         _check(lib().mos_engine_option(self.ptr, option, int(value)), "mos_engine_option")
+
+    def graph_stats(self):
+        """(captures, replays) of iteration-chunk graphs so far."""
+        c = ctypes.c_int64()
+        r = ctypes.c_int64()
+        _check(lib().mos_engine_graph_stats(self.ptr, ctypes.byref(c), ctypes.byref(r)), "mos_engine_graph_stats")
+        return c.value, r.value
 
     def stats(self):
         a, q, cd, cs = (ctypes.c_int64() for _ in range(4))

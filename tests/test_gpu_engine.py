@@ -52,9 +52,9 @@ def n_dofs_of(nx, ny):
 
 
 def run_engine(env, probs, mixed=False, budget=1 << 28, iterations=16, interleave=None, gemm=None, split=None,
-               width=None, precond=None):
+               width=None, precond=None, graph=None, stats=None):
     mos, ctx, roms, oroms, torch = env
-    eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=budget, gemm=gemm, precond=precond)
+    eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=budget, gemm=gemm, precond=precond, graph=graph)
     if split is not None:
         eng.option(mos.MOS_OPT_GEMM_SPLIT, split)
     if width is not None:
@@ -85,6 +85,8 @@ def run_engine(env, probs, mixed=False, budget=1 << 28, iterations=16, interleav
         if pending and rounds % 2 == 0:
             submit(pending.pop(0))
         assert rounds < 5000
+    if stats is not None:
+        stats["graph"] = eng.graph_stats()
     eng.close()
     return [done[i] for i in range(len(probs))]
 
@@ -242,4 +244,37 @@ def test_preconditioner_option_rules(env):
     with pytest.raises(mos.MosError) as e:
         eng.option(mos.MOS_OPT_PRECOND, 0)
     assert e.value.status == mos.MOS_EBUSY
+    eng.close()
+
+
+@pytest.mark.parametrize("mixed,precond,iterations", [(False, 1, 16), (True, 1, 16), (False, 0, 16), (True, 0, 5)],
+                         ids=["fp64-2level", "mixed-2level", "fp64-jacobi", "mixed-jacobi-chunk5"])
+def test_graph_replay_matches_direct_launches(env, mixed, precond, iterations):
+    # Problems admitted while others iterate change the launch shape, so the
+    # chunk graph is captured several times and replayed many times, with the
+    # engine's own direct work (set-up, FP64 residuals, reconstruction) and a
+    # synchronisation between replays; every result must be bitwise the one
+    # of direct launches.
+    probs = problems(11, [(4, 3), (2, 2), (6, 5), (3, 3), (1, 4), (5, 2)])
+    direct = run_engine(env, probs, mixed=mixed, precond=precond, iterations=iterations, interleave=2, graph=False)
+    st = {}
+    graphed = run_engine(env, probs, mixed=mixed, precond=precond, iterations=iterations, interleave=2, graph=True,
+                         stats=st)
+    captures, replays = st["graph"]
+    assert captures >= 2 and replays > captures
+    for a, b in zip(direct, graphed):
+        assert a[0] == b[0] == 0
+        assert np.array_equal(a[5], b[5]), "reduced displacement differs"
+        assert np.array_equal(a[4], b[4]), "von Mises differs"
+        assert a[2] == b[2] and a[3] == b[3]
+
+
+def test_graph_option_rules(env):
+    mos, ctx, roms, oroms, torch = env
+    eng = mos.Engine(ctx, roms)
+    for v in (0, 1):
+        eng.option(mos.MOS_OPT_GRAPH, v)
+    with pytest.raises(mos.MosError):
+        eng.option(mos.MOS_OPT_GRAPH, 2)
+    assert eng.graph_stats() == (0, 0)
     eng.close()
