@@ -8,6 +8,7 @@
  *   mos_solve_array  ROMs + array layout -> reduced u      (Sec. 4.3-4.4; eq. 20)
  *   mos_reconstruct  reduced u -> per-cell stress          (Sec. 4.3, last paragraph; eq. 1, 15)
  *   mos_reconstruct_plane  von Mises on each cell's mid-height sample grid (Sec. 5.1)
+ *   mos_reconstruct_displacement  fine-mesh displacement of every cell (eq. 15)
  *
  * Conventions
  *   Units: micrometres, MPa, 1/K, K.  Stress in MPa, displacement in um.
@@ -148,6 +149,16 @@ enum { MOS_OUT_VM = 1, MOS_OUT_SIGMA6 = 2 };
  * MOS_FP64 solution and float for MOS_MIXED.  Either pointer may be NULL
  * when its flag is not set. */
 mos_status mos_reconstruct(mos_ctx ctx, mos_sol sol, uint32_t outputs, void *vm, void *sigma6);
+
+/* Sec. 4.3 with eq. 15: the fine-mesh displacement of every cell,
+ * u_cell = dT f_T + Phi u_r,cell over the cell's FE DoFs (DoF 3 node +
+ * component, node and component order as in the cell numbering contract).
+ * u_nodal: caller-owned device array of double [n_cells][n_fe_dofs]
+ * (n_fe_dofs = mos_query(rom, MOS_Q_CELL_DOFS)), FP64 for either precision,
+ * written on the context's stream (complete when the call returns).
+ * Errors: MOS_EINVAL for a NULL u_nodal, a basis larger than 176, or a
+ * solution whose ROMs were freed. */
+mos_status mos_reconstruct_displacement(mos_ctx ctx, mos_sol sol, void *u_nodal);
 
 /* The paper's evaluation plane (Sec. 5.1, error metric of Tables 1-3): von
  * Mises stress of every cell at grid x grid points of its mid-height plane,

@@ -650,6 +650,24 @@ mos_status mos_reconstruct(mos_ctx ctx, mos_sol sol, uint32_t outputs, void *vm,
     return reconstruct(ctx, sol, outputs, vm, sigma6);
 }
 
+mos_status mos_reconstruct_displacement(mos_ctx ctx, mos_sol sol, void *u_nodal) {
+    if (!ctx || !sol || sol->kind != KIND_SOL || sol->ctx != ctx) {
+        set_error("invalid context or solution handle");
+        return MOS_EINVAL;
+    }
+    if (!u_nodal) {
+        set_error("mos_reconstruct_displacement: u_nodal is NULL");
+        return MOS_EINVAL;
+    }
+    for (mos_rom r : sol->roms)
+        if (!r || r->kind != KIND_ROM) {
+            set_error("mos_reconstruct_displacement: a ROM of this solution has been freed");
+            return MOS_EINVAL;
+        }
+    MOS_HIP(hipSetDevice(ctx->device));
+    return reconstruct_displacement(ctx, sol, static_cast<double *>(u_nodal));
+}
+
 mos_status mos_reconstruct_plane(mos_ctx ctx, mos_sol sol, int32_t grid, void *vm) {
     if (!ctx || !sol || sol->kind != KIND_SOL || sol->ctx != ctx) {
         set_error("invalid context or solution handle");

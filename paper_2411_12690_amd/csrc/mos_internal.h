@@ -188,6 +188,7 @@ mos_status plane_basis(mos_rom r, int grid);
 // recon.hip
 mos_status reconstruct(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void *sigma6);
 mos_status reconstruct_plane(mos_ctx ctx, mos_sol s, int grid, void *vm);
+mos_status reconstruct_displacement(mos_ctx ctx, mos_sol s, double *u_nodal);
 // FP64 MFMA reconstruction with one element block of Psi staged in LDS per
 // workgroup, for bases with ldk / 4 <= RECON_F64_LDS_KS (else MOS_EINVAL).
 // A job is one problem's run of slot blocks of one type in the cell-major

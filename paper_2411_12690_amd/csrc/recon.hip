@@ -414,6 +414,47 @@ mos_status recon_bf16_jobs(mos_ctx ctx, const mos_rom *roms, int n_types, const 
     return MOS_OK;
 }
 
+// Fine-mesh displacement of every cell (eq. 15): out[cell][d] = dT f_T[d] +
+// sum_k Phi[d][k] u_cell[k] for the FE DoFs d of one cell type's block
+// (f_T is column n of the stored Phi).  FP64 MFMA 16x16x4 with the cells as
+// rows and the DoFs as columns, so the 16 lanes of a register's row hold 16
+// consecutive DoFs of one cell (128-byte segments of the output).  Each wave
+// owns a tile of 16 DoFs, keeps that tile of Phi (ldk columns, KS k-steps of
+// 4; columns n..ldk-1 meet zero rows of U) in registers, and streams up to
+// `chunk` slot blocks of the type's slots [s0, s0 + 16 n_sb).
+template <int KS>
+__global__ __launch_bounds__(256) void k_nodal_u(const double *phi, int ldp, int n, int n_dofs, int ks,
+                                                 const double *U, int n_pc, const int32_t *perm, int s0, int n_sb,
+                                                 int chunk, double dT, double *out) {
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int d0 = (blockIdx.x * 4 + wave) * 16;
+    if (d0 >= n_dofs) return;
+    const int dcol = d0 + lane % 16;
+    const bool dval = dcol < n_dofs;
+    // B[k][dof] = Phi[dof][k]: lane l holds k = 4 s + l / 16 of DoF d0 + l % 16.
+    double b[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) b[s] = (s < ks && dval) ? phi[(size_t)dcol * ldp + 4 * s + lane / 16] : 0.0;
+    const double ft = dval ? dT * phi[(size_t)dcol * ldp + n] : 0.0;
+    const int sb0 = blockIdx.y * chunk, sb1 = min(sb0 + chunk, n_sb);
+    for (int sb = sb0; sb < sb1; ++sb) {
+        const int pc0 = s0 + sb * 16;
+        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+            if (s < ks) {
+                // A[cell][k] = U[k][slot]: lane l holds slot pc0 + l % 16, k = 4 s + l / 16.
+                const double a = U[(size_t)(4 * s + lane / 16) * n_pc + pc0 + lane % 16];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[s], acc, 0, 0, 0);
+            }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int cell = perm[pc0 + lane / 16 + 4 * q];   // output row of register q
+            if (cell >= 0 && dval) out[(size_t)cell * n_dofs + dcol] = ft + acc[q];
+        }
+    }
+}
+
 // The solution's cells through the stress bases R[t] (one per cell type:
 // the centroid bases of the solution's ROMs, or their plane bases), which
 // share ldk, n_eblk and n_elem (output points per cell).
@@ -478,6 +519,41 @@ static mos_status recon_with(mos_ctx ctx, mos_sol s, const std::vector<mos_rom> 
 mos_status reconstruct(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void *sigma6) {
     return recon_with(ctx, s, s->roms, (outputs & MOS_OUT_VM) ? vm : nullptr,
                       (outputs & MOS_OUT_SIGMA6) ? sigma6 : nullptr);
+}
+
+mos_status reconstruct_displacement(mos_ctx ctx, mos_sol s, double *u_nodal) {
+    hipStream_t st = ctx->stream;
+    const int ks = s->ldk / 4;
+    if (ks > RECON_F64_LDS_KS) {
+        set_error("nodal displacement output supports bases up to %d (this one has %d)", 4 * RECON_F64_LDS_KS, s->n);
+        return MOS_EINVAL;
+    }
+    DeviceArena tmp;
+    tmp.ctx = ctx;
+    struct Guard {
+        DeviceArena &a;
+        ~Guard() { a.release(); }
+    } guard{tmp};
+    double *U = nullptr;
+    const int64_t total = (int64_t)s->ldk * s->n_pc;
+    MOS_TRY(tmp.alloc_n(total, &U));
+    hipLaunchKernelGGL(k_gather_u, dim3(ceil_div(total, 256)), dim3(256), 0, st, s->u, s->gidx, U, total);
+    MOS_LAUNCH_CHECK();
+    for (int t = 0; t < s->n_types; ++t) {
+        const mos_rom r = s->roms[t];
+        const int n_sb = (s->seg[t + 1] - s->seg[t]) / 16;
+        if (n_sb <= 0) continue;
+        // Up to 8 slot blocks per wave, enough workgroups to fill the chip.
+        const int n_dt = ceil_div(r->n_dofs, 64);
+        const int chunk = std::max(1, std::min(8, n_sb * n_dt / 2048));
+        const dim3 grid(n_dt, ceil_div(n_sb, chunk));
+        hipLaunchKernelGGL(k_nodal_u<RECON_F64_LDS_KS>, grid, dim3(256), 0, st, (const double *)r->phi, r->ldp, r->n,
+                           r->n_dofs, ks, (const double *)U, s->n_pc, (const int32_t *)s->perm, s->seg[t], n_sb,
+                           chunk, s->delta_T, u_nodal);
+        MOS_LAUNCH_CHECK();
+    }
+    MOS_HIP(hipStreamSynchronize(st));
+    return MOS_OK;
 }
 
 mos_status reconstruct_plane(mos_ctx ctx, mos_sol s, int grid, void *vm) {

@@ -21,7 +21,7 @@ MOS_OUT_VM, MOS_OUT_SIGMA6 = 1, 2
  MOS_Q_GLOBAL_DOFS, MOS_Q_ITERS, MOS_Q_REFINES, MOS_Q_DEVICE_BYTES) = range(1, 11)
 
 EXPORTED = ("mos_ctx_create", "mos_ctx_destroy", "mos_build_cell", "mos_reduce", "mos_solve_array",
-            "mos_reconstruct", "mos_reconstruct_plane", "mos_get_solution", "mos_query", "mos_cell_export", "mos_rom_export",
+            "mos_reconstruct", "mos_reconstruct_plane", "mos_reconstruct_displacement", "mos_get_solution", "mos_query", "mos_cell_export", "mos_rom_export",
             "mos_array_layout", "mos_engine_create", "mos_engine_submit", "mos_engine_progress",
             "mos_engine_result", "mos_engine_option", "mos_engine_stats", "mos_engine_graph_stats", "mos_engine_destroy", "mos_timing_start", "mos_timing_stop",
             "mos_cell_free", "mos_rom_free", "mos_sol_free", "mos_last_error")
@@ -81,6 +81,7 @@ def _load():
         "mos_solve_array": (ctypes.c_int, [vp, P(ArrayDesc), P(vp), ctypes.c_int32, P(vp)]),
         "mos_reconstruct": (ctypes.c_int, [vp, vp, ctypes.c_uint32, vp, vp]),
         "mos_reconstruct_plane": (ctypes.c_int, [vp, vp, ctypes.c_int32, vp]),
+        "mos_reconstruct_displacement": (ctypes.c_int, [vp, vp, vp]),
         "mos_get_solution": (ctypes.c_int, [vp, vp, P(ctypes.c_double), P(ctypes.c_int32)]),
         "mos_query": (ctypes.c_int, [vp, ctypes.c_int, P(ctypes.c_int64)]),
         "mos_cell_export": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
@@ -397,6 +398,18 @@ def mos_reconstruct(ctx, sol, vm=None, sigma6=None):
     _check(lib().mos_reconstruct(ctx.ptr, sol.ptr, flags, ctypes.c_void_p(vm.data_ptr() if vm is not None else 0),
                                  ctypes.c_void_p(sigma6.data_ptr() if sigma6 is not None else 0)),
            "mos_reconstruct")
+
+
+def mos_reconstruct_displacement(ctx, sol, u_nodal):
+    """Fine-mesh displacement of every cell (eq. 15) into a caller-owned
+    contiguous float64 device tensor [n_cells, n_fe_dofs]."""
+    torch = ctx.torch
+    shape = (sol.n_cells, sol.roms[0].query(MOS_Q_CELL_DOFS))
+    if u_nodal.dtype != torch.float64 or tuple(u_nodal.shape) != shape or not u_nodal.is_contiguous() \
+            or not u_nodal.is_cuda:
+        raise ValueError(f"output must be a contiguous float64 device tensor of shape {shape}")
+    _check(lib().mos_reconstruct_displacement(ctx.ptr, sol.ptr, ctypes.c_void_p(u_nodal.data_ptr())),
+           "mos_reconstruct_displacement")
 
 
 def mos_reconstruct_plane(ctx, sol, grid, vm):

@@ -204,3 +204,37 @@ def test_zero_load_gives_zero_solution(mos, ctx):
     sol = mos.mos_solve_array(ctx, [rom], 2, 3, np.zeros(6), 0.0)
     u, res, iters = mos.mos_get_solution(sol)
     assert np.all(u == 0.0) and iters == 0
+
+
+@pytest.mark.parametrize("case,mixed", [
+    (W.small_case(nx=3, ny=2, mesh=(4, 4, 6), interp=(3, 3, 4), pitch_x=3.0, pitch_y=3.0, height=6.0,
+                  tsv_diameter=1.6, liner_thickness=0.3), False),
+    (W.small_case(nx=7, ny=5, mesh=(4, 4, 6), interp=(4, 4, 3), pitch_x=3.0, pitch_y=3.0, height=6.0,
+                  tsv_diameter=1.6, seed=3), False),
+    (W.case_c1(), False),
+    (W.small_case(nx=6, ny=5, mesh=(4, 4, 6), interp=(3, 3, 4), pitch_x=3.0, pitch_y=3.0, height=6.0,
+                  tsv_diameter=1.6, liner_thickness=0.3, seed=2), True),
+], ids=["3x2_two_types", "7x5_ragged", "c1", "6x5_mixed"])
+def test_nodal_displacement(mos, ctx, case, mixed):
+    # eq. 15 per cell, dT f_T + Phi u_cell, against the oracle's; 525 FE DoFs
+    # per 4x4x6 cell leave a ragged last tile of 16 DoFs.
+    import torch
+    roms = [mos.mos_reduce(ctx, mos.mos_build_cell(ctx, s)) for s in case.specs]
+    sol = mos.mos_solve_array(ctx, roms, case.nx_cells, case.ny_cells, case.cell_type, case.delta_T,
+                              clamp_bottom=case.clamp_bottom, clamp_top=case.clamp_top, mixed=mixed)
+    n_fe = roms[0].query(mos.MOS_Q_CELL_DOFS)
+    out = torch.full((case.n_cells, n_fe), np.nan, dtype=torch.float64, device="cuda")
+    mos.mos_reconstruct_displacement(ctx, sol, out)
+    got = out.cpu().numpy()
+    oroms = [oracle_rom(s) for s in case.specs]
+    sp = case.specs[0]
+    mesh = oarray.AbstractMesh(case.nx_cells, case.ny_cells, sp.interp, sp.pitch_x, sp.pitch_y, sp.height)
+    dofs, vals = oarray.constrained_dofs(mesh, case.clamp_bottom, case.clamp_top)
+    u_ref = oarray.solve_mor(mesh, case.cell_type, oroms, case.delta_T, dofs, vals)
+    ref = np.stack([oarray.nodal_displacement(mesh, case.cell_type, oroms, u_ref, case.delta_T, c)
+                    for c in range(case.n_cells)])
+    assert np.isfinite(got).all()
+    assert rel_max(got, ref) < (1e-8 if mixed else 1e-10)
+    # The bottom face is clamped: its FE nodes carry exactly zero displacement.
+    mz1 = (sp.mesh[0] + 1) * (sp.mesh[1] + 1)
+    assert np.all(got[:, :3 * mz1] == 0.0)
