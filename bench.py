@@ -222,8 +222,10 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False, vm_ref=None):
     # iteration chunks the timed region runs unsampled (a sampled kernel
     # keeps its chunk out of the graph) and the kernel is sampled in a
     # separate pass of the same steps afterwards.
+    # Reconstruction launches once per cell type and step: every one is sampled.
+    every = 1 if dominant == mos.MOS_K_RECON else TIME_EVERY
     if not args.graph:
-        mos.mos_timing_start(ctx, dominant, TIME_EVERY)
+        mos.mos_timing_start(ctx, dominant, every)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     recs = []
     quiet_gc()
@@ -236,7 +238,7 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False, vm_ref=None):
     sampled = recs
     if args.graph:
         sampled = []
-        mos.mos_timing_start(ctx, dominant, TIME_EVERY)
+        mos.mos_timing_start(ctx, dominant, every)
         for s in range(max(2, args.steps // 2)):
             step(sampled)
         torch.cuda.synchronize()
@@ -270,7 +272,7 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False, vm_ref=None):
                 "traffic": recorded_traffic(name, f"batch{B}_c2", precision), "traffic_unit": "bytes/launch",
                 "kernel": name,
                 "avg_launch_us": round(avg_s * 1e6, 3), "timed_launches": int(launches), "launches": int(seen),
-                "timed_every": TIME_EVERY, "work_per_launch": round(work_per_launch, 1), "work_note": note,
+                "timed_every": every, "work_per_launch": round(work_per_launch, 1), "work_note": note,
                 "kernel_share_of_step": round(avg_s * seen / len(sampled) * 1e3 / ms_per_step, 4),
                 "kernels_ms_per_step": {KERNEL_INFO[k][0]: round(v[1], 4) for k, v in totals.items()}}
 

@@ -57,7 +57,7 @@ struct ProbParams {
     int32_t n_agg;                  // boxes of the internal node order
     int32_t box_begin;              // first box id (two-level preconditioner), else -1
     int32_t part_begin, n_part;     // the problem's (r,u), (r,r) partial slots: its boxes or DoF blocks
-    int32_t pad;
+    int32_t tab_coarse;             // 1: coarse matrices from the per-type table (clamped faces only)
 };
 // Parameters of a problem's current refinement sweep (device table by id).
 struct SweepParams {
@@ -161,6 +161,11 @@ struct mos_engine_s {
     int4 *box_tab = nullptr;                  // [cap_blk]: first node, nodes, aggregates, owner (-1 free)
     double *binv = nullptr;                   // [cap_blk][MAXA][36]
     double *cc = nullptr;                     // [cap_blk][MAXA][6]
+    // Per cell type, clamp flags, cell class (whether its right / top face
+    // belongs to the next aggregate) and piece: the 21 terms of Z^T K_r Z
+    // in cell-local coordinates; built per clamp-flag value on first use.
+    double *ctab = nullptr;                   // [MAX_TYPES][4][4][4][21]
+    int ctab_built = 0;                       // bit f: flags f tabulated
     // Pinned host mirrors of sb_rom and perm: set-up writes a problem's
     // tables here and copies one span per batch; release writes -1 back.
     // mirror_ev marks the last span copy, which must complete before the

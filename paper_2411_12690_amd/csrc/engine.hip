@@ -1264,6 +1264,7 @@ __global__ __launch_bounds__(256 * CS_GROUPS) void k_coarse_setup(ProbSel sel, c
     const int pb = box_tab[bs].w;
     if (pb < 0 || !selected(sel, pb)) return;
     const ProbParams &P = pp[pb];
+    if (P.tab_coarse) return;
     const AggLayout &A = P.agg;
     const int b = bs - P.box_begin, gx = b % A.nax, gy = b / A.nax;
     const int bx0 = gx * A.cx, bx1 = gx == A.nax - 1 ? P.lat.Nx : bx0 + A.cx;
@@ -1385,6 +1386,189 @@ __global__ __launch_bounds__(256 * CS_GROUPS) void k_coarse_setup(ProbSel sel, c
     }
     __syncthreads();
     if (tid < 64) spd_inverse6_wave(Bfull, out);
+}
+
+// Tabulated coarse matrices for problems whose only constraints are clamped
+// bottom / top faces.  Every cell of a type then has the same free DoFs,
+// and its DoFs split into the same pieces wherever it sits, given its class
+// (whether its right face, and its top face, belong to the next aggregate).
+// Rigid modes in aggregate coordinates are the cell-local ones times a 6x6
+// shift T (translations unchanged; the rotations about the aggregate corner
+// gain the translations times the cell's offset), so a cell's part of B_a is
+// T^T G T with G = Z^T K_r Z of the piece in cell-local coordinates.
+
+// G[type][flags][class][piece][21] for one (type, class) per workgroup and
+// clamp flags `flags`: row t of K_r Z over the cell's free DoFs of t's own
+// piece (FP32 K_r, FP64 sums, sixteen rows' values in flight), the row's
+// share of the symmetric 21 terms, then per piece the sums over the rows in
+// a fixed order (waves in order).
+struct TypeSpacing {
+    double h[MAX_TYPES][3];  // coarse-coordinate node spacing per axis (x pitch = 1) of each cell type
+};
+__global__ __launch_bounds__(256) void k_coarse_table(const void *const *kr32_tab, const int32_t *surf, int n,
+                                                      int ldk, int nx, int ny, int nz, TypeSpacing hs, int flags,
+                                                      double *ctab) {
+    const int type = blockIdx.x, cls = blockIdx.y, t = threadIdx.x, w = t / 64, lane = t % 64;
+    const float *K = static_cast<const float *>(kr32_tab[type]);
+    const double h0 = hs.h[type][0], h1 = hs.h[type][1], h2 = hs.h[type][2];
+    __shared__ double zl[256][6];
+    __shared__ int8_t pc[256];
+    __shared__ double wpart[4][4][21];
+    int piece = -1;
+    double z[6] = {0, 0, 0, 0, 0, 0};
+    if (t < n) {
+        const int sn = t / 3, ci = t % 3;
+        const int i = surf[3 * sn], j = surf[3 * sn + 1], k = surf[3 * sn + 2];
+        const bool fixed = ((flags & MOS_BC_CLAMP_BOTTOM) && k == 0) || ((flags & MOS_BC_CLAMP_TOP) && k == nz - 1);
+        if (!fixed) {
+            piece = ((cls & 1) && i == nx - 1 ? 1 : 0) + ((cls & 2) && j == ny - 1 ? 2 : 0);
+            const double X = i * h0, Y = j * h1, Zc = k * h2;
+            z[ci] = 1.0;
+            if (ci == 0) {
+                z[3] = -Y;
+                z[5] = Zc;
+            } else if (ci == 1) {
+                z[3] = X;
+                z[4] = -Zc;
+            } else {
+                z[4] = Y;
+                z[5] = -X;
+            }
+        }
+    }
+    for (int m = 0; m < 6; ++m) zl[t][m] = z[m];
+    pc[t] = (int8_t)piece;
+    __syncthreads();
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    if (piece >= 0) {
+        for (int l0 = 0; l0 < n; l0 += 16) {
+            float kv[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) kv[j] = K[(size_t)min(l0 + j, n - 1) * ldk + t];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int l = l0 + j;
+                if (l < n && pc[l] == piece)
+                    for (int m = 0; m < 6; ++m) acc[m] += (double)kv[j] * zl[l][m];
+            }
+        }
+    }
+    for (int p = 0; p < 4; ++p) {
+#pragma unroll 1
+        for (int q = 0, m1 = 0, m2 = 0; q < 21; ++q) {
+            double v = piece == p ? 0.5 * (z[m1] * acc[m2] + z[m2] * acc[m1]) : 0.0;
+            for (int k = 32; k >= 1; k >>= 1) v += __shfl_xor(v, k);
+            if (lane == 0) wpart[w][p][q] = v;
+            if (++m2 == 6) m2 = ++m1;
+        }
+    }
+    __syncthreads();
+    if (t < 84) {
+        const int p = t / 21, q = t % 21;
+        ctab[((((size_t)type * 4 + flags) * 4 + cls) * 4 + p) * 21 + t % 21] =
+            ((wpart[0][p][q] + wpart[1][p][q]) + wpart[2][p][q]) + wpart[3][p][q];
+    }
+}
+
+// Aggregate column of lattice column I: box column times MAXA plus the
+// aggregate within the box.
+__device__ __forceinline__ int agg_column(const AggLayout &A, int Nx, int64_t I) {
+    const int gx = agg_x(A, I);
+    const int cells = gx == A.nax - 1 ? Nx - A.cx * (A.nax - 1) : A.cx;
+    const int na = (cells + AGG_C - 1) / AGG_C;
+    const int ib = (int)(I - (int64_t)gx * A.wxi);
+    return gx * MAXA + min(ib / (AGG_C * A.sx), na - 1);
+}
+
+// B_a^-1 of every aggregate of the selected problems with tabulated coarse
+// matrices; grid (boxes, MAXA), one wave per aggregate.  Lane q < 21 sums
+// term q of T^T G T over the touching cells in (cy, cx) order, G the cell's
+// table entry for its type, the problem's clamps, its class and the piece
+// this aggregate holds (left / lower neighbours hold their right / top
+// face), T its shift from the cell corner to the aggregate corner.
+__global__ __launch_bounds__(64) void k_coarse_agg_tab(ProbSel sel, const int4 *box_tab, const ProbParams *pp,
+                                                       const int32_t *cslot, const int32_t *sb_rom,
+                                                       const double *ctab, double *binv) {
+    const int bs = blockIdx.x, a = blockIdx.y;
+    const int pb = box_tab[bs].w;
+    if (pb < 0 || !selected(sel, pb)) return;
+    const ProbParams &P = pp[pb];
+    if (!P.tab_coarse) return;
+    const AggLayout &A = P.agg;
+    const int b = bs - P.box_begin, gx = b % A.nax, gy = b / A.nax;
+    const int bx0 = gx * A.cx, bx1 = gx == A.nax - 1 ? P.lat.Nx : bx0 + A.cx;
+    const int by0 = gy * A.cy, by1 = gy == A.nay - 1 ? P.lat.Ny : by0 + A.cy;
+    const int na = (bx1 - bx0 + AGG_C - 1) / AGG_C;
+    double *out = binv + ((size_t)bs * MAXA + a) * 36;
+    const int t = threadIdx.x;
+    if (a >= na) {
+        if (t < 36) out[t] = 0.0;
+        return;
+    }
+    const int ax0 = bx0 + a * AGG_C, ax1 = min(ax0 + AGG_C, bx1);
+    const int Nx = P.lat.Nx, sx = A.sx, sy = A.sy;
+    const int flags = P.clamp & 3;
+    __shared__ double Bfull[36];
+    if (t < 21) {
+        // Term q = (m1, m2), m1 <= m2, of the symmetric 6x6.
+        int m1 = 0, r = t;
+        while (r >= 6 - m1) {
+            r -= 6 - m1;
+            ++m1;
+        }
+        const int m2 = m1 + r;
+        double g = 0.0;
+        for (int cy = max(by0 - 1, 0); cy < by1; ++cy)
+            for (int cx = max(ax0 - 1, 0); cx < ax1; ++cx) {
+                const int cell = cy * Nx + cx;
+                const int slot = cslot[(int64_t)P.sb_begin * 16 + cell];
+                const int type = sb_rom[slot / 16];
+                const int rx = agg_column(A, Nx, (int64_t)(cx + 1) * sx) != agg_column(A, Nx, (int64_t)cx * sx);
+                const int ry = agg_y(A, (int64_t)(cy + 1) * sy) != agg_y(A, (int64_t)cy * sy);
+                const int piece = (cx < ax0 ? 1 : 0) + (cy < by0 ? 2 : 0);
+                const double *G = ctab + ((((size_t)type * 4 + flags) * 4 + (rx + 2 * ry)) * 4 + piece) * 21;
+                // Offsets of the cell corner from the aggregate corner, in the
+                // coarse coordinates (x pitch = 1).
+                const double X0 = (double)((cx - ax0) * sx) * P.h[0], Y0 = (double)((cy - by0) * sy) * P.h[1];
+                // Column m of T: (row, coefficient) pairs.
+                int ri[2][3];
+                double rc[2][3];
+                int nr[2];
+                const int mm[2] = {m1, m2};
+                for (int u = 0; u < 2; ++u) {
+                    const int m = mm[u];
+                    ri[u][0] = m;
+                    rc[u][0] = 1.0;
+                    nr[u] = 1;
+                    if (m == 3) {
+                        ri[u][1] = 0;
+                        rc[u][1] = -Y0;
+                        ri[u][2] = 1;
+                        rc[u][2] = X0;
+                        nr[u] = 3;
+                    } else if (m == 4) {
+                        ri[u][1] = 2;
+                        rc[u][1] = Y0;
+                        nr[u] = 2;
+                    } else if (m == 5) {
+                        ri[u][1] = 2;
+                        rc[u][1] = -X0;
+                        nr[u] = 2;
+                    }
+                }
+                double v = 0.0;
+                for (int u = 0; u < nr[0]; ++u)
+                    for (int w = 0; w < nr[1]; ++w) {
+                        const int lo = min(ri[0][u], ri[1][w]), hi = max(ri[0][u], ri[1][w]);
+                        v += rc[0][u] * rc[1][w] * G[lo * 6 - lo * (lo - 1) / 2 + (hi - lo)];
+                    }
+                g += v;
+            }
+        Bfull[m1 * 6 + m2] = g;
+        Bfull[m2 * 6 + m1] = g;
+    }
+    __syncthreads();
+    spd_inverse6_wave(Bfull, out);
 }
 
 // ---- batched per-problem phases (set-up, FP64 residual, sweep start/stop) ----
@@ -1907,11 +2091,17 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
         H.part_begin = P->box_begin >= 0 ? P->box_begin : P->blk_begin;
         H.n_part = P->box_begin >= 0 ? P->n_agg : P->n_blk;
         {
-            const mos_cell_desc &cd = e->roms[0]->desc;
+            // Coordinates of the coarse modes: node spacing over the x pitch
+            // of the problem's own cells (every cell of an array shares pitch
+            // and height).
+            const mos_cell_desc &cd = e->roms[P->sb_rom[0]]->desc;
             H.h[0] = 1.0 / (cd.interp[0] - 1);
             H.h[1] = cd.pitch_y / cd.pitch_x / (cd.interp[1] - 1);
             H.h[2] = cd.height / cd.pitch_x / (cd.interp[2] - 1);
         }
+        // Clamped faces only: every cell of a type has the same free DoFs, so
+        // its coarse terms come from the per-type table.
+        H.tab_coarse = (e->precond && P->pdof.empty()) ? 1 : 0;
         H.dT = P->dT;
         H.lat = L;
         H.blk_begin = P->blk_begin;
@@ -1978,11 +2168,38 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
                            (const ProbParams *)e->pp, (const double *const *)e->br_tab,
                            (const void *const *)e->kr64_tab, (const int32_t *)e->sb_rom, (const int32_t *)e->inc,
                            (const uint8_t *)e->cmask, e->b_raw, (double *)e->v[VDINV], e->ldk);
-    if (e->precond)
-        hipLaunchKernelGGL(k_coarse_setup, dim3(e->boxes.high, MAXA), dim3(256 * CS_GROUPS), 0, st, B.sel,
-                           (const int4 *)e->box_tab, (const ProbParams *)e->pp, (const int32_t *)e->cslot,
-                           (const int32_t *)e->sb_rom, (const void *const *)e->kr32_tab, (const uint8_t *)e->cmask,
-                           (const int32_t *)e->surf, e->n, e->ldk, e->binv);
+    if (e->precond) {
+        bool any_tab = false, any_gen = false;
+        for (EngineProblem *P : adm) {
+            const ProbParams &H = e->pp_host[P->pid];
+            any_tab |= H.tab_coarse != 0;
+            any_gen |= H.tab_coarse == 0;
+            const int f = H.clamp & 3;
+            if (H.tab_coarse && !((e->ctab_built >> f) & 1)) {
+                TypeSpacing hs{};
+                for (size_t t = 0; t < e->roms.size(); ++t) {
+                    const mos_cell_desc &cd = e->roms[t]->desc;
+                    hs.h[t][0] = 1.0 / (cd.interp[0] - 1);
+                    hs.h[t][1] = cd.pitch_y / cd.pitch_x / (cd.interp[1] - 1);
+                    hs.h[t][2] = cd.height / cd.pitch_x / (cd.interp[2] - 1);
+                }
+                const mos_cell_desc &c0 = e->roms[0]->desc;
+                hipLaunchKernelGGL(k_coarse_table, dim3((unsigned)e->roms.size(), 4), dim3(256), 0, st,
+                                   (const void *const *)e->kr32_tab, (const int32_t *)e->surf, e->n, e->ldk,
+                                   c0.interp[0], c0.interp[1], c0.interp[2], hs, f, e->ctab);
+                e->ctab_built |= 1 << f;
+            }
+        }
+        if (any_gen)
+            hipLaunchKernelGGL(k_coarse_setup, dim3(e->boxes.high, MAXA), dim3(256 * CS_GROUPS), 0, st, B.sel,
+                               (const int4 *)e->box_tab, (const ProbParams *)e->pp, (const int32_t *)e->cslot,
+                               (const int32_t *)e->sb_rom, (const void *const *)e->kr32_tab,
+                               (const uint8_t *)e->cmask, (const int32_t *)e->surf, e->n, e->ldk, e->binv);
+        if (any_tab)
+            hipLaunchKernelGGL(k_coarse_agg_tab, dim3(e->boxes.high, MAXA), dim3(64), 0, st, B.sel,
+                               (const int4 *)e->box_tab, (const ProbParams *)e->pp, (const int32_t *)e->cslot,
+                               (const int32_t *)e->sb_rom, (const double *)e->ctab, e->binv);
+    }
     MOS_LAUNCH_CHECK();
     // At set-up x = g, so one product A g gives both ||b_l|| and the residual.
     return residual_batch(e, B, true);
@@ -2171,6 +2388,7 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     MOS_TRY(m.alloc_n(e->cap_blk, &e->box_tab));
     MOS_TRY(m.alloc_n((size_t)e->cap_blk * MAXA * 36, &e->binv));
     MOS_TRY(m.alloc_n((size_t)e->cap_blk * MAXA * 6, &e->cc));
+    MOS_TRY(m.alloc_n((size_t)MAX_TYPES * 4 * 4 * 4 * 21, &e->ctab));
     MOS_TRY(m.alloc_n(MAX_PROBS, &e->ps));
     MOS_TRY(m.alloc_n(1, &e->epoch_dev));
     MOS_TRY(m.alloc_n(MAX_PROBS, &e->res2));

@@ -278,3 +278,35 @@ def test_graph_option_rules(env):
         eng.option(mos.MOS_OPT_GRAPH, 2)
     assert eng.graph_stats() == (0, 0)
     eng.close()
+
+
+@pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "mixed"])
+def test_tabulated_coarse_matrices_equal_the_general_ones(env, mixed):
+    # A clamped bottom face takes the coarse matrices from the per-type table
+    # (cell-local terms shifted to each aggregate); the same constraint given
+    # as a prescribed list of zeros takes the general per-aggregate kernel.
+    # Both describe one system and one preconditioner, so the solutions and
+    # the iteration counts agree.
+    mos, ctx, roms, oroms, torch = env
+    out = []
+    for nx, ny, t, dT in problems(21, [(7, 5), (4, 4), (1, 3)]):
+        coords, _, _, _ = mos.mos_array_layout(ctx, nx, ny, roms[0])
+        bottom = np.nonzero(coords[:, 2] == 0.0)[0]
+        pd = (3 * bottom[:, None] + np.arange(3)[None, :]).ravel().astype(np.int64)
+        res = []
+        for kw in (dict(clamp_bottom=True), dict(clamp_bottom=False, prescribed_dofs=pd,
+                                                 prescribed_values=np.zeros(pd.size))):
+            eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=1 << 28, precond=1)
+            u = torch.empty((n_dofs_of(nx, ny),), dtype=torch.float64, device="cuda")
+            tk = eng.submit(nx, ny, t, dT, u=u, **kw)
+            while tk not in eng.progress(16):
+                pass
+            st, rel, it, sw = eng.result(tk)
+            assert st == 0
+            res.append((u.cpu().numpy(), it))
+            eng.close()
+        (ua, ia), (ub, ib) = res
+        assert np.abs(ua - ub).max() <= (1e-8 if mixed else 1e-10) * np.abs(ub).max()
+        assert abs(ia - ib) <= 2
+        out.append((ia, ib))
+    print("[coarse table] iterations tabulated / general:", out, flush=True)
