@@ -215,8 +215,11 @@ __global__ void k_split_u(const double *U, int ld, const ReconJob *jobs, int n_j
 
 // One workgroup per (element block of 16, slice of one type's slot blocks).
 // The workgroup stages its element block of Psi_hi and Psi_lo (6 components
-// x nks k-steps x 1 KB each) in LDS once; its four waves then stream the
-// slice CB slot blocks at a time, each LDS fragment feeding 3 CB MFMAs.
+// x nks k-steps x 1 KB each) and of sigma_T in LDS once; its four waves then
+// stream the slice CB slot blocks at a time, each LDS fragment feeding 3 CB
+// MFMAs.  A wave's blocks come in increasing order, so it finds their jobs
+// by advancing one index, and it requests their jobs and cells before the
+// MFMA chain so that those round trips overlap it.
 template <int KSMAX, int CB>
 __global__ __launch_bounds__(256, KSMAX <= 6 ? 2 : 1) void k_recon_bf16(const bf16x8 *psi_hi, const bf16x8 *psi_lo,
                                                        const double *sig_t, const bf16x8 *ub_hi,
@@ -224,6 +227,7 @@ __global__ __launch_bounds__(256, KSMAX <= 6 ? 2 : 1) void k_recon_bf16(const bf
                                                        const ReconJob *jobs, int n_jobs, int v_begin, int n_v,
                                                        int chunk, int nks, int n_elem) {
     __shared__ bf16x8 lds[2][6][KSMAX][64];
+    __shared__ double st_lds[16][6];
     const int eb = blockIdx.x;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int y0 = v_begin + (int)blockIdx.y * chunk, y1 = min(y0 + chunk, v_begin + n_v);
@@ -235,9 +239,28 @@ __global__ __launch_bounds__(256, KSMAX <= 6 ? 2 : 1) void k_recon_bf16(const bf
             lds[0][c][r / 64][r % 64] = gh[i];
             lds[1][c][r / 64][r % 64] = gl[i];
         }
+        if (threadIdx.x < 96) {
+            const int e = min(eb * 16 + (int)threadIdx.x / 6, n_elem - 1);
+            st_lds[threadIdx.x / 6][threadIdx.x % 6] = sig_t[(size_t)e * 6 + threadIdx.x % 6];
+        }
     }
     __syncthreads();
+    int j = 0;  // job of the wave's current block (blocks only move forward)
     for (int base = y0 + wave * CB; base < y1; base += 4 * CB) {
+        // Jobs, outputs and cells of the CB blocks, requested ahead of the MFMAs.
+        double dTv[CB];
+        float *vmv[CB], *s6v[CB];
+        int cellv[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int v = min(base + cb, y1 - 1);
+            while (j + 1 < n_jobs && v >= jobs[j + 1].sb_off) ++j;
+            const ReconJob &J = jobs[j];
+            dTv[cb] = J.dT;
+            vmv[cb] = static_cast<float *>(J.vm);
+            s6v[cb] = static_cast<float *>(J.sig6);
+            cellv[cb] = perm[(size_t)(J.sb_first + (v - J.sb_off)) * 16 + lane % 16];
+        }
         f32x4 acc[CB][6];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
@@ -269,18 +292,16 @@ __global__ __launch_bounds__(256, KSMAX <= 6 ? 2 : 1) void k_recon_bf16(const bf
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
             if (base + cb >= y1) continue;
-            const ReconJob &J = job_of(jobs, n_jobs, base + cb);
-            const double dT = J.dT;
-            float *vm = static_cast<float *>(J.vm), *sig6 = static_cast<float *>(J.sig6);
-            const int cell = perm[(size_t)(J.sb_first + (base + cb - J.sb_off)) * 16 + lane % 16];
+            const double dT = dTv[cb];
+            float *vm = vmv[cb], *sig6 = s6v[cb];
+            const int cell = cellv[cb];
             if (cell < 0) continue;
             const int e0 = eb * 16 + 4 * (lane / 16);
             float vq[4], sq[4][6];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int e = min(e0 + q, n_elem - 1);
 #pragma unroll
-                for (int c = 0; c < 6; ++c) sq[q][c] = acc[cb][c][q] + (float)(dT * sig_t[(size_t)e * 6 + c]);
+                for (int c = 0; c < 6; ++c) sq[q][c] = acc[cb][c][q] + (float)(dT * st_lds[4 * (lane / 16) + q][c]);
                 const float a = sq[q][0] - sq[q][1], b = sq[q][1] - sq[q][2], d = sq[q][2] - sq[q][0];
                 vq[q] = sqrtf(0.5f * (a * a + b * b + d * d) +
                               3.0f * (sq[q][3] * sq[q][3] + sq[q][4] * sq[q][4] + sq[q][5] * sq[q][5]));
@@ -298,10 +319,10 @@ __global__ __launch_bounds__(256, KSMAX <= 6 ? 2 : 1) void k_recon_bf16(const bf
             if (sig6) {
                 if (whole) {
 #pragma unroll
-                    for (int j = 0; j < 6; ++j)
-                        *(f32x4 *)(sig6 + o * 6 + 4 * j) =
-                            f32x4{sq[(4 * j) / 6][(4 * j) % 6], sq[(4 * j + 1) / 6][(4 * j + 1) % 6],
-                                  sq[(4 * j + 2) / 6][(4 * j + 2) % 6], sq[(4 * j + 3) / 6][(4 * j + 3) % 6]};
+                    for (int jj = 0; jj < 6; ++jj)
+                        *(f32x4 *)(sig6 + o * 6 + 4 * jj) =
+                            f32x4{sq[(4 * jj) / 6][(4 * jj) % 6], sq[(4 * jj + 1) / 6][(4 * jj + 1) % 6],
+                                  sq[(4 * jj + 2) / 6][(4 * jj + 2) % 6], sq[(4 * jj + 3) / 6][(4 * jj + 3) % 6]};
                 } else {
                     for (int q = 0; q < 4; ++q)
                         if (e0 + q < n_elem)
