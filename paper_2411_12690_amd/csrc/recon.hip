@@ -97,6 +97,7 @@ __global__ __launch_bounds__(512, 1) void k_recon_f64_lds(const double *psi, con
                                                           const int32_t *perm, int ld, const ReconJob *jobs,
                                                           int n_jobs, int total_sb, int chunk, int ks, int n_elem) {
     __shared__ double lds[6 * 4 * KS * 16];
+    __shared__ double st_lds[16][6];
     if (EXACT) ks = KS;
     const int ldk = 4 * ks;
     const int eb = blockIdx.x;
@@ -105,6 +106,11 @@ __global__ __launch_bounds__(512, 1) void k_recon_f64_lds(const double *psi, con
     {
         const double *g = psi + (size_t)eb * 6 * ldk * 16;
         for (int i = threadIdx.x; i < 6 * ldk * 16; i += 512) lds[i] = g[i];
+        // sigma_T of the element block (rows past n_elem repeat the last; unused).
+        if (threadIdx.x < 96) {
+            const int e = min(eb * 16 + (int)threadIdx.x / 6, n_elem - 1);
+            st_lds[threadIdx.x / 6][threadIdx.x % 6] = sig_t[(size_t)e * 6 + threadIdx.x % 6];
+        }
     }
     __syncthreads();
     int j = 0;
@@ -116,6 +122,8 @@ __global__ __launch_bounds__(512, 1) void k_recon_f64_lds(const double *psi, con
         const double dT = J.dT;
         OutT *vm = static_cast<OutT *>(J.vm);
         OutT *sig6 = static_cast<OutT *>(J.sig6);
+        // The block's cells, requested ahead of the MFMA chain.
+        const int cell = perm[pc0 + lane % 16];
         const double *bp = U + (size_t)(lane / 16) * ld + pc0 + lane % 16;
         const double *ap = lds + (lane / 16) * 16 + lane % 16;
         d4 acc[6];
@@ -145,7 +153,6 @@ __global__ __launch_bounds__(512, 1) void k_recon_f64_lds(const double *psi, con
                     acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[(c * ldk + 4 * k) * 16], b, acc[c], 0, 0, 0);
             }
         }
-        const int cell = perm[pc0 + lane % 16];
         if (cell < 0) continue;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -153,7 +160,7 @@ __global__ __launch_bounds__(512, 1) void k_recon_f64_lds(const double *psi, con
             if (e >= n_elem) continue;
             double sv[6];
 #pragma unroll
-            for (int c = 0; c < 6; ++c) sv[c] = acc[c][q] + dT * sig_t[(size_t)e * 6 + c];
+            for (int c = 0; c < 6; ++c) sv[c] = acc[c][q] + dT * st_lds[lane / 16 + 4 * q][c];
             const size_t o = (size_t)cell * n_elem + e;
             if (vm) {
                 double x = sv[0] - sv[1], y = sv[1] - sv[2], z = sv[2] - sv[0];
