@@ -156,8 +156,8 @@ mos_status mos_reconstruct(mos_ctx ctx, mos_sol sol, uint32_t outputs, void *vm,
  * u_nodal: caller-owned device array of double [n_cells][n_fe_dofs]
  * (n_fe_dofs = mos_query(rom, MOS_Q_CELL_DOFS)), FP64 for either precision,
  * written on the context's stream (complete when the call returns).
- * Errors: MOS_EINVAL for a NULL u_nodal, a basis larger than 176, or a
- * solution whose ROMs were freed. */
+ * Errors: MOS_EINVAL for a NULL u_nodal or a solution whose ROMs were
+ * freed. */
 mos_status mos_reconstruct_displacement(mos_ctx ctx, mos_sol sol, void *u_nodal);
 
 /* The paper's evaluation plane (Sec. 5.1, error metric of Tables 1-3): von

@@ -450,6 +450,8 @@ mos_status recon_bf16_jobs(mos_ctx ctx, const mos_rom *roms, int n_types, const 
 // owns a tile of 16 DoFs, keeps that tile of Phi (ldk columns, KS k-steps of
 // 4; columns n..ldk-1 meet zero rows of U) in registers, and streams up to
 // `chunk` slot blocks of the type's slots [s0, s0 + 16 n_sb).
+// KS > 0: the wave's tile of Phi stays in registers (ks <= KS k-steps);
+// KS == 0: any basis size, the tile read again for every slot block.
 template <int KS>
 __global__ __launch_bounds__(256) void k_nodal_u(const double *phi, int ldp, int n, int n_dofs, int ks,
                                                  const double *U, int n_pc, const int32_t *perm, int s0, int n_sb,
@@ -460,21 +462,32 @@ __global__ __launch_bounds__(256) void k_nodal_u(const double *phi, int ldp, int
     const int dcol = d0 + lane % 16;
     const bool dval = dcol < n_dofs;
     // B[k][dof] = Phi[dof][k]: lane l holds k = 4 s + l / 16 of DoF d0 + l % 16.
-    double b[KS];
+    constexpr int NB = KS > 0 ? KS : 1;
+    double b[NB];
 #pragma unroll
-    for (int s = 0; s < KS; ++s) b[s] = (s < ks && dval) ? phi[(size_t)dcol * ldp + 4 * s + lane / 16] : 0.0;
+    for (int s = 0; s < NB; ++s)
+        b[s] = (KS > 0 && s < ks && dval) ? phi[(size_t)dcol * ldp + 4 * s + lane / 16] : 0.0;
+    const double *prow = phi + (size_t)(dval ? dcol : 0) * ldp + lane / 16;
     const double ft = dval ? dT * phi[(size_t)dcol * ldp + n] : 0.0;
     const int sb0 = blockIdx.y * chunk, sb1 = min(sb0 + chunk, n_sb);
     for (int sb = sb0; sb < sb1; ++sb) {
         const int pc0 = s0 + sb * 16;
         d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+        if (KS > 0) {
 #pragma unroll
-        for (int s = 0; s < KS; ++s)
-            if (s < ks) {
-                // A[cell][k] = U[k][slot]: lane l holds slot pc0 + l % 16, k = 4 s + l / 16.
+            for (int s = 0; s < NB; ++s)
+                if (s < ks) {
+                    // A[cell][k] = U[k][slot]: lane l holds slot pc0 + l % 16, k = 4 s + l / 16.
+                    const double a = U[(size_t)(4 * s + lane / 16) * n_pc + pc0 + lane % 16];
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[s], acc, 0, 0, 0);
+                }
+        } else {
+            for (int s = 0; s < ks; ++s) {
                 const double a = U[(size_t)(4 * s + lane / 16) * n_pc + pc0 + lane % 16];
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[s], acc, 0, 0, 0);
+                const double bv = dval ? prow[4 * s] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
             }
+        }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int cell = perm[pc0 + lane / 16 + 4 * q];   // output row of register q
@@ -552,10 +565,6 @@ mos_status reconstruct(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void 
 mos_status reconstruct_displacement(mos_ctx ctx, mos_sol s, double *u_nodal) {
     hipStream_t st = ctx->stream;
     const int ks = s->ldk / 4;
-    if (ks > RECON_F64_LDS_KS) {
-        set_error("nodal displacement output supports bases up to %d (this one has %d)", 4 * RECON_F64_LDS_KS, s->n);
-        return MOS_EINVAL;
-    }
     DeviceArena tmp;
     tmp.ctx = ctx;
     struct Guard {
@@ -575,9 +584,14 @@ mos_status reconstruct_displacement(mos_ctx ctx, mos_sol s, double *u_nodal) {
         const int n_dt = ceil_div(r->n_dofs, 64);
         const int chunk = std::max(1, std::min(8, n_sb * n_dt / 2048));
         const dim3 grid(n_dt, ceil_div(n_sb, chunk));
-        hipLaunchKernelGGL(k_nodal_u<RECON_F64_LDS_KS>, grid, dim3(256), 0, st, (const double *)r->phi, r->ldp, r->n,
-                           r->n_dofs, ks, (const double *)U, s->n_pc, (const int32_t *)s->perm, s->seg[t], n_sb,
-                           chunk, s->delta_T, u_nodal);
+        if (ks <= RECON_F64_LDS_KS)
+            hipLaunchKernelGGL(k_nodal_u<RECON_F64_LDS_KS>, grid, dim3(256), 0, st, (const double *)r->phi, r->ldp,
+                               r->n, r->n_dofs, ks, (const double *)U, s->n_pc, (const int32_t *)s->perm, s->seg[t],
+                               n_sb, chunk, s->delta_T, u_nodal);
+        else
+            hipLaunchKernelGGL(k_nodal_u<0>, grid, dim3(256), 0, st, (const double *)r->phi, r->ldp, r->n, r->n_dofs,
+                               ks, (const double *)U, s->n_pc, (const int32_t *)s->perm, s->seg[t], n_sb, chunk,
+                               s->delta_T, u_nodal);
         MOS_LAUNCH_CHECK();
     }
     MOS_HIP(hipStreamSynchronize(st));

@@ -65,7 +65,9 @@ def run_order(mos, ctx, k, mixed):
     mos.mos_reconstruct(ctx, sol, vm=vm)
     vp = torch.empty((4, GRID * GRID), dtype=dt, device="cuda")
     mos.mos_reconstruct_plane(ctx, sol, GRID, vp)
-    return rom, spec, case, vm.double().cpu().numpy(), vp.double().cpu().numpy()
+    un = torch.empty((4, rom.query(mos.MOS_Q_CELL_DOFS)), dtype=torch.float64, device="cuda")
+    mos.mos_reconstruct_displacement(ctx, sol, un)
+    return rom, spec, case, vm.double().cpu().numpy(), vp.double().cpu().numpy(), un.cpu().numpy()
 
 
 def oracle_order(spec, case):
@@ -75,18 +77,22 @@ def oracle_order(spec, case):
     u = oarray.solve_mor(m, case.cell_type, [rom], case.delta_T, dofs, vals)
     vm = ofem.von_mises(oarray.reconstruct(m, case.cell_type, [rom], u, case.delta_T))
     vp = oplane.plane_von_mises(m, case.cell_type, [rom], u, case.delta_T, GRID)
-    return rom.n, vm, vp
+    un = np.stack([oarray.nodal_displacement(m, case.cell_type, [rom], u, case.delta_T, c) for c in range(4)])
+    return rom.n, vm, vp, un
 
 
 def test_error_falls_with_the_interpolation_order(mos, ctx, full_reference):
     errs = []
     for k in ORDERS:
         print(f"[convergence] order {k}", flush=True)
-        rom, spec, case, vm, vp = run_order(mos, ctx, k, mixed=False)
-        n_ref, vm_ref, vp_ref = oracle_order(spec, case)
+        rom, spec, case, vm, vp, un = run_order(mos, ctx, k, mixed=False)
+        n_ref, vm_ref, vp_ref, un_ref = oracle_order(spec, case)
         assert rom.query(mos.MOS_Q_N) == n_ref == omor.n_reduced(k, k, k)
         assert rel_max(vm, vm_ref) < 1e-9
         assert rel_max(vp, vp_ref) < 1e-9
+        # Fine-mesh displacement (eq. 15), both kernel forms (bases above 176
+        # stream their tile of Phi).
+        assert rel_max(un, un_ref) < 1e-10
         errs.append(oplane.normalized_mae(vp, full_reference))
         print(f"[convergence] n={n_ref} normalised MAE vs full FEM {errs[-1]:.4e}", flush=True)
     assert all(a > b for a, b in zip(errs, errs[1:]))
@@ -95,7 +101,8 @@ def test_error_falls_with_the_interpolation_order(mos, ctx, full_reference):
 
 @pytest.mark.parametrize("k", ORDERS)
 def test_mixed_precision_at_every_order(mos, ctx, k):
-    rom, spec, case, vm, vp = run_order(mos, ctx, k, mixed=True)
-    _, vm_ref, vp_ref = oracle_order(spec, case)
+    rom, spec, case, vm, vp, un = run_order(mos, ctx, k, mixed=True)
+    _, vm_ref, vp_ref, un_ref = oracle_order(spec, case)
+    assert rel_max(un, un_ref) < 1e-8
     assert rel_max(vm, vm_ref) < 1e-3
     assert rel_max(vp, vp_ref) < 1e-3

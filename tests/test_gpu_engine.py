@@ -280,8 +280,9 @@ def test_graph_option_rules(env):
     eng.close()
 
 
-@pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "mixed"])
-def test_tabulated_coarse_matrices_equal_the_general_ones(env, mixed):
+@pytest.mark.parametrize("mixed,top", [(False, False), (True, False), (False, True)],
+                         ids=["fp64", "mixed", "fp64-top-and-bottom"])
+def test_tabulated_coarse_matrices_equal_the_general_ones(env, mixed, top):
     # A clamped bottom face takes the coarse matrices from the per-type table
     # (cell-local terms shifted to each aggregate); the same constraint given
     # as a prescribed list of zeros takes the general per-aggregate kernel.
@@ -291,11 +292,12 @@ def test_tabulated_coarse_matrices_equal_the_general_ones(env, mixed):
     out = []
     for nx, ny, t, dT in problems(21, [(7, 5), (4, 4), (1, 3)]):
         coords, _, _, _ = mos.mos_array_layout(ctx, nx, ny, roms[0])
-        bottom = np.nonzero(coords[:, 2] == 0.0)[0]
-        pd = (3 * bottom[:, None] + np.arange(3)[None, :]).ravel().astype(np.int64)
+        faces = (coords[:, 2] == 0.0) | ((coords[:, 2] == coords[:, 2].max()) & top)
+        fixed = np.nonzero(faces)[0]
+        pd = (3 * fixed[:, None] + np.arange(3)[None, :]).ravel().astype(np.int64)
         res = []
-        for kw in (dict(clamp_bottom=True), dict(clamp_bottom=False, prescribed_dofs=pd,
-                                                 prescribed_values=np.zeros(pd.size))):
+        for kw in (dict(clamp_bottom=True, clamp_top=top),
+                   dict(clamp_bottom=False, prescribed_dofs=pd, prescribed_values=np.zeros(pd.size))):
             eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=1 << 28, precond=1)
             u = torch.empty((n_dofs_of(nx, ny),), dtype=torch.float64, device="cuda")
             tk = eng.submit(nx, ny, t, dT, u=u, **kw)
