@@ -790,7 +790,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on a single GPU; --gpus must be 1", file=sys.stderr)
+        print("bench.py: the hot path runs on one GPU; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

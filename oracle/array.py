@@ -1,5 +1,5 @@
 """Oracle, part 3: the global stage of MORE-Stress (Sec. 4.3-4.4) and the full
-fine-mesh FEM of a whole TSV array used to judge it.
+fine-mesh FEM of a whole TSV array to compare it with.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
