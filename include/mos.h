@@ -279,7 +279,7 @@ mos_status mos_engine_result(mos_engine e, int64_t ticket, int32_t *status, doub
  * with Z_a the aggregate's six rigid-body modes on its free DoFs and
  * B_a = Z_a^T A Z_a (symmetric positive definite, so PCG converges to the
  * same solution in fewer iterations); 0 = Jacobi alone.  1 needs cells of at
- * most 256 reduced DoFs and at most 1024 nodes in a box of 8x2 cells
+ * most 512 reduced DoFs and at most 1024 nodes in a box of 6x2 cells
  * (MOS_EINVAL otherwise; engines whose cells exceed this start with 0).
  * Set it before the first submission. */
 /* MOS_OPT_GRAPH = 1 replays each chunk of PCG iterations (the launches of

@@ -1252,14 +1252,15 @@ __device__ void spd_inverse6_wave(const double *G, double *out) {
 // cell's DoFs that belong to it and are free.  K_r is read in FP32 (B only
 // defines the preconditioner; any symmetric positive definite B keeps PCG
 // converging to the same solution) with FP64 sums.  The touching cells (at
-// most 3 x 3) are dealt to CS_GROUPS groups of 256 threads, each summing its
-// cells in a fixed order, the groups' sums in order; then the 6x6 inverse.
-constexpr int CS_GROUPS = 1;
-__global__ __launch_bounds__(256 * CS_GROUPS) void k_coarse_setup(ProbSel sel, const int4 *box_tab,
-                                                                  const ProbParams *pp, const int32_t *cslot,
-                                                                  const int32_t *sb_rom, const void *const *kr32_tab,
-                                                                  const uint8_t *cmask, const int32_t *surf, int n,
-                                                                  int ldk, double *binv) {
+// most 3 x 3) are summed in a fixed order, then the 6x6 inverse.  One thread
+// per reduced DoF of a cell: NTH >= n threads (256, or 512 for bases above
+// 256).
+template <int NTH>
+__global__ __launch_bounds__(NTH) void k_coarse_setup(ProbSel sel, const int4 *box_tab, const ProbParams *pp,
+                                                      const int32_t *cslot, const int32_t *sb_rom,
+                                                      const void *const *kr32_tab, const uint8_t *cmask,
+                                                      const int32_t *surf, int n, int ldk, double *binv) {
+    constexpr int NW = NTH / 64;
     const int bs = blockIdx.x, a = blockIdx.y;
     const int pb = box_tab[bs].w;
     if (pb < 0 || !selected(sel, pb)) return;
@@ -1271,36 +1272,32 @@ __global__ __launch_bounds__(256 * CS_GROUPS) void k_coarse_setup(ProbSel sel, c
     const int by0 = gy * A.cy, by1 = gy == A.nay - 1 ? P.lat.Ny : by0 + A.cy;
     const int na = (bx1 - bx0 + AGG_C - 1) / AGG_C;
     double *out = binv + ((size_t)bs * MAXA + a) * 36;
-    const int tid = threadIdx.x, grp = tid / 256, t = tid % 256;
+    const int t = threadIdx.x;
     if (a >= na) {
-        if (tid < 36) out[tid] = 0.0;
+        if (t < 36) out[t] = 0.0;
         return;
     }
     const int ax0 = bx0 + a * AGG_C, ax1 = min(ax0 + AGG_C, bx1);
     const int cx0 = max(ax0 - 1, 0), cy0 = max(by0 - 1, 0);
     const int ncx = ax1 - cx0, ncells = ncx * (by1 - cy0);
-    __shared__ double zl[CS_GROUPS][256][6], G[CS_GROUPS][21], wpart[CS_GROUPS][4][21];
-    __shared__ int16_t list[CS_GROUPS][256];
-    __shared__ int wcnt[CS_GROUPS][4];
+    __shared__ double zl[NTH][6], G[21], wpart[NW][21];
+    __shared__ int16_t list[NTH];
+    __shared__ int wcnt[NW];
     __shared__ double Bfull[36];
-    if (t < 21) G[grp][t] = 0.0;
+    if (t < 21) G[t] = 0.0;
     const int sx = A.sx, sy = A.sy;
     const int w = t / 64, lane = t % 64;
-    // Every group takes the same number of rounds (barriers are
-    // workgroup-wide); a group without a cell in the last round idles.
-    for (int c0 = 0; c0 < ncells; c0 += CS_GROUPS) {
-        const int ci_cell = c0 + grp;
-        const bool has = ci_cell < ncells;
-        const int cx = cx0 + (has ? ci_cell % ncx : 0), cy = cy0 + (has ? ci_cell / ncx : 0);
+    for (int ci_cell = 0; ci_cell < ncells; ++ci_cell) {
+        const int cx = cx0 + ci_cell % ncx, cy = cy0 + ci_cell / ncx;
         const float *K = nullptr;
-        if (has) {
+        {
             const int cell = cy * P.lat.Nx + cx;
             const int slot = cslot[(int64_t)P.sb_begin * 16 + cell];
             K = static_cast<const float *>(kr32_tab[sb_rom[slot / 16]]);
         }
         __syncthreads();
         bool mine = false;
-        if (has && t < n) {
+        if (t < n) {
             const int sn = t / 3, ci = t % 3;
             const int64_t I = (int64_t)cx * sx + surf[3 * sn], J = (int64_t)cy * sy + surf[3 * sn + 1];
             const int Kz = surf[3 * sn + 2];
@@ -1328,64 +1325,65 @@ __global__ __launch_bounds__(256 * CS_GROUPS) void k_coarse_setup(ProbSel sel, c
                     z[5] = -X;
                 }
             }
-            for (int m = 0; m < 6; ++m) zl[grp][t][m] = z[m];
+            for (int m = 0; m < 6; ++m) zl[t][m] = z[m];
             mine = in;
         }
         // The cell's DoFs in the aggregate, ascending, as a list (ballot per
         // wave, waves in order).
         const uint64_t bal = __ballot(mine);
-        if (lane == 0) wcnt[grp][w] = __popcll(bal);
+        if (lane == 0) wcnt[w] = __popcll(bal);
         __syncthreads();
         int base = 0, nl = 0;
-        for (int i = 0; i < 4; ++i) {
-            base += i < w ? wcnt[grp][i] : 0;
-            nl += wcnt[grp][i];
+        for (int i = 0; i < NW; ++i) {
+            base += i < w ? wcnt[i] : 0;
+            nl += wcnt[i];
         }
-        if (mine) list[grp][base + __popcll(bal & ((1ull << lane) - 1))] = (int16_t)t;
+        if (mine) list[base + __popcll(bal & ((1ull << lane) - 1))] = (int16_t)t;
         __syncthreads();
         // Row t of K_r Z over the listed columns (K_r symmetric: row l read
         // across threads), then the row's share of the symmetric Z^T K_r Z,
-        // summed over the group in a fixed order.
+        // summed over the workgroup in a fixed order.
         double acc[6] = {0, 0, 0, 0, 0, 0};
-        if (has && t < n) {
+        if (t < n) {
             // Sixteen rows' values requested at once (one register each),
             // then their products.
             for (int i0 = 0; i0 < nl; i0 += 16) {
                 float kv[16];
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
-                    const int l = list[grp][min(i0 + j, nl - 1)];
+                    const int l = list[min(i0 + j, nl - 1)];
                     kv[j] = at_byte(K, (uint32_t)(l * ldk + t) * 4u);
                 }
 #pragma unroll
                 for (int j = 0; j < 16; ++j)
                     if (i0 + j < nl) {
-                        const int l = list[grp][i0 + j];
-                        for (int m = 0; m < 6; ++m) acc[m] += (double)kv[j] * zl[grp][l][m];
+                        const int l = list[i0 + j];
+                        for (int m = 0; m < 6; ++m) acc[m] += (double)kv[j] * zl[l][m];
                     }
             }
         }
 #pragma unroll 1
         for (int q = 0, m1 = 0, m2 = 0; q < 21; ++q) {
-            double v = mine ? 0.5 * (zl[grp][t][m1] * acc[m2] + zl[grp][t][m2] * acc[m1]) : 0.0;
+            double v = mine ? 0.5 * (zl[t][m1] * acc[m2] + zl[t][m2] * acc[m1]) : 0.0;
             for (int k = 32; k >= 1; k >>= 1) v += __shfl_xor(v, k);
-            if (lane == 0) wpart[grp][w][q] = v;
+            if (lane == 0) wpart[w][q] = v;
             if (++m2 == 6) m2 = ++m1;
         }
         __syncthreads();
-        if (t < 21) G[grp][t] += ((wpart[grp][0][t] + wpart[grp][1][t]) + wpart[grp][2][t]) + wpart[grp][3][t];
+        if (t < 21) {
+            double g = wpart[0][t];
+            for (int i = 1; i < NW; ++i) g += wpart[i][t];
+            G[t] += g;
+        }
     }
     __syncthreads();
-    if (tid < 36) {
-        // Full symmetric matrix from the 21 sums (groups in order).
-        const int i = tid / 6, j = tid % 6, lo = min(i, j), hi = max(i, j);
-        const int q = lo * 6 - lo * (lo - 1) / 2 + (hi - lo);
-        double g = G[0][q];
-        for (int k = 1; k < CS_GROUPS; ++k) g += G[k][q];
-        Bfull[tid] = g;
+    if (t < 36) {
+        // Full symmetric matrix from the 21 sums.
+        const int i = t / 6, j = t % 6, lo = min(i, j), hi = max(i, j);
+        Bfull[t] = G[lo * 6 - lo * (lo - 1) / 2 + (hi - lo)];
     }
     __syncthreads();
-    if (tid < 64) spd_inverse6_wave(Bfull, out);
+    if (t < 64) spd_inverse6_wave(Bfull, out);
 }
 
 // Tabulated coarse matrices for problems whose only constraints are clamped
@@ -1401,19 +1399,21 @@ __global__ __launch_bounds__(256 * CS_GROUPS) void k_coarse_setup(ProbSel sel, c
 // clamp flags `flags`: row t of K_r Z over the cell's free DoFs of t's own
 // piece (FP32 K_r, FP64 sums, sixteen rows' values in flight), the row's
 // share of the symmetric 21 terms, then per piece the sums over the rows in
-// a fixed order (waves in order).
+// a fixed order (waves in order).  NTH >= n threads.
 struct TypeSpacing {
     double h[MAX_TYPES][3];  // coarse-coordinate node spacing per axis (x pitch = 1) of each cell type
 };
-__global__ __launch_bounds__(256) void k_coarse_table(const void *const *kr32_tab, const int32_t *surf, int n,
+template <int NTH>
+__global__ __launch_bounds__(NTH) void k_coarse_table(const void *const *kr32_tab, const int32_t *surf, int n,
                                                       int ldk, int nx, int ny, int nz, TypeSpacing hs, int flags,
                                                       double *ctab) {
+    constexpr int NW = NTH / 64;
     const int type = blockIdx.x, cls = blockIdx.y, t = threadIdx.x, w = t / 64, lane = t % 64;
     const float *K = static_cast<const float *>(kr32_tab[type]);
     const double h0 = hs.h[type][0], h1 = hs.h[type][1], h2 = hs.h[type][2];
-    __shared__ double zl[256][6];
-    __shared__ int8_t pc[256];
-    __shared__ double wpart[4][4][21];
+    __shared__ double zl[NTH][6];
+    __shared__ int8_t pc[NTH];
+    __shared__ double wpart[NW][4][21];
     int piece = -1;
     double z[6] = {0, 0, 0, 0, 0, 0};
     if (t < n) {
@@ -1465,8 +1465,9 @@ __global__ __launch_bounds__(256) void k_coarse_table(const void *const *kr32_ta
     __syncthreads();
     if (t < 84) {
         const int p = t / 21, q = t % 21;
-        ctab[((((size_t)type * 4 + flags) * 4 + cls) * 4 + p) * 21 + t % 21] =
-            ((wpart[0][p][q] + wpart[1][p][q]) + wpart[2][p][q]) + wpart[3][p][q];
+        double g = wpart[0][p][q];
+        for (int i = 1; i < NW; ++i) g += wpart[i][p][q];
+        ctab[((((size_t)type * 4 + flags) * 4 + cls) * 4 + p) * 21 + q] = g;
     }
 }
 
@@ -2185,17 +2186,29 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
                     hs.h[t][2] = cd.height / cd.pitch_x / (cd.interp[2] - 1);
                 }
                 const mos_cell_desc &c0 = e->roms[0]->desc;
-                hipLaunchKernelGGL(k_coarse_table, dim3((unsigned)e->roms.size(), 4), dim3(256), 0, st,
-                                   (const void *const *)e->kr32_tab, (const int32_t *)e->surf, e->n, e->ldk,
-                                   c0.interp[0], c0.interp[1], c0.interp[2], hs, f, e->ctab);
+                if (e->n <= 256)
+                    hipLaunchKernelGGL(k_coarse_table<256>, dim3((unsigned)e->roms.size(), 4), dim3(256), 0, st,
+                                       (const void *const *)e->kr32_tab, (const int32_t *)e->surf, e->n, e->ldk,
+                                       c0.interp[0], c0.interp[1], c0.interp[2], hs, f, e->ctab);
+                else
+                    hipLaunchKernelGGL(k_coarse_table<512>, dim3((unsigned)e->roms.size(), 4), dim3(512), 0, st,
+                                       (const void *const *)e->kr32_tab, (const int32_t *)e->surf, e->n, e->ldk,
+                                       c0.interp[0], c0.interp[1], c0.interp[2], hs, f, e->ctab);
                 e->ctab_built |= 1 << f;
             }
         }
-        if (any_gen)
-            hipLaunchKernelGGL(k_coarse_setup, dim3(e->boxes.high, MAXA), dim3(256 * CS_GROUPS), 0, st, B.sel,
-                               (const int4 *)e->box_tab, (const ProbParams *)e->pp, (const int32_t *)e->cslot,
-                               (const int32_t *)e->sb_rom, (const void *const *)e->kr32_tab,
-                               (const uint8_t *)e->cmask, (const int32_t *)e->surf, e->n, e->ldk, e->binv);
+        if (any_gen) {
+            if (e->n <= 256)
+                hipLaunchKernelGGL(k_coarse_setup<256>, dim3(e->boxes.high, MAXA), dim3(256), 0, st, B.sel,
+                                   (const int4 *)e->box_tab, (const ProbParams *)e->pp, (const int32_t *)e->cslot,
+                                   (const int32_t *)e->sb_rom, (const void *const *)e->kr32_tab,
+                                   (const uint8_t *)e->cmask, (const int32_t *)e->surf, e->n, e->ldk, e->binv);
+            else
+                hipLaunchKernelGGL(k_coarse_setup<512>, dim3(e->boxes.high, MAXA), dim3(512), 0, st, B.sel,
+                                   (const int4 *)e->box_tab, (const ProbParams *)e->pp, (const int32_t *)e->cslot,
+                                   (const int32_t *)e->sb_rom, (const void *const *)e->kr32_tab,
+                                   (const uint8_t *)e->cmask, (const int32_t *)e->surf, e->n, e->ldk, e->binv);
+        }
         if (any_tab)
             hipLaunchKernelGGL(k_coarse_agg_tab, dim3(e->boxes.high, MAXA), dim3(64), 0, st, B.sel,
                                (const int4 *)e->box_tab, (const ProbParams *)e->pp, (const int32_t *)e->cslot,
@@ -2505,7 +2518,7 @@ int64_t largest_box(mos_engine e, bool *fits) {
     const int64_t max_nodes = sub_count(make_sub(BOX_CX * sx + 1, AGG_C * sy + 1, nz, sx, sy));
     // The box kernels address the cell layouts with 32-bit byte offsets.
     const bool small_layout = e->ld_slots == 0 || (uint64_t)e->ldk * e->ld_slots * 8 < (1ull << 32);
-    *fits = max_nodes <= 1024 && e->n <= 256 && AGG_C * sx < 256 && AGG_C * sy < 256 && nz < 256 && small_layout;
+    *fits = max_nodes <= 1024 && e->n <= 512 && AGG_C * sx < 256 && AGG_C * sy < 256 && nz < 256 && small_layout;
     return max_nodes;
 }
 }  // namespace
@@ -2514,7 +2527,7 @@ mos_status engine_set_precond(mos_engine e, int precond) {
     bool fits = false;
     const int64_t max_nodes = largest_box(e, &fits);
     if (precond && !fits) {
-        set_error("the two-level preconditioner needs boxes of at most 1024 nodes and a basis of at most 256");
+        set_error("the two-level preconditioner needs boxes of at most 1024 nodes and a basis of at most 512");
         return MOS_EINVAL;
     }
     e->precond = precond;
