@@ -33,7 +33,8 @@ constexpr int DB = 256;       // DoFs per DoF block
 constexpr int N_XCD = 8;      // accelerator dies that workgroups are dealt to in turn
 constexpr int DOF_ALIGN = 3 * DB;
 // Two-level preconditioner: aggregates of AGG_C x AGG_C cells, boxes of
-// BOX_CX x AGG_C cells (at most MAXA aggregates per box).
+// at most BOX_CX x AGG_C cells (at most MAXA aggregates per box; narrower
+// when a box of BOX_CX cells would exceed one workgroup's 1024 nodes).
 constexpr int AGG_C = 2;
 constexpr int BOX_CX = 6;
 constexpr int MAXA = (BOX_CX + AGG_C - 1) / AGG_C;
@@ -2363,7 +2364,7 @@ mos_status decide_and_start(mos_engine e, const std::vector<EngineProblem *> &pr
 }  // namespace
 
 namespace {
-int64_t largest_box(mos_engine e, bool *fits);
+int64_t largest_box(mos_engine e, bool *fits, int *width = nullptr);
 }  // namespace
 
 mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
@@ -2509,13 +2510,21 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
 }
 
 namespace {
-// Nodes of the largest box (the corner box, with the closing nodes) and
-// whether the two-level kernels take it: one thread per node, a basis of at
-// most 256 DoFs in the set-up, packed coordinates below 256.
-int64_t largest_box(mos_engine e, bool *fits) {
+// Box width (cells along x, a multiple of AGG_C up to BOX_CX: the widest
+// whose corner box holds at most 1024 nodes), the nodes of that largest box
+// (with the closing nodes), and whether the two-level kernels take it: one
+// thread per node, a basis of at most 512 DoFs in the set-up, packed
+// coordinates below 256.
+int64_t largest_box(mos_engine e, bool *fits, int *width) {
     const mos_cell_desc &cd = e->roms[0]->desc;
     const int sx = cd.interp[0] - 1, sy = cd.interp[1] - 1, nz = cd.interp[2];
-    const int64_t max_nodes = sub_count(make_sub(BOX_CX * sx + 1, AGG_C * sy + 1, nz, sx, sy));
+    int w = BOX_CX;
+    int64_t max_nodes = sub_count(make_sub(w * sx + 1, AGG_C * sy + 1, nz, sx, sy));
+    while (max_nodes > 1024 && w > AGG_C) {
+        w -= AGG_C;
+        max_nodes = sub_count(make_sub(w * sx + 1, AGG_C * sy + 1, nz, sx, sy));
+    }
+    if (width) *width = w;
     // The box kernels address the cell layouts with 32-bit byte offsets.
     const bool small_layout = e->ld_slots == 0 || (uint64_t)e->ldk * e->ld_slots * 8 < (1ull << 32);
     *fits = max_nodes <= 1024 && e->n <= 512 && AGG_C * sx < 256 && AGG_C * sy < 256 && nz < 256 && small_layout;
@@ -2525,7 +2534,8 @@ int64_t largest_box(mos_engine e, bool *fits) {
 
 mos_status engine_set_precond(mos_engine e, int precond) {
     bool fits = false;
-    const int64_t max_nodes = largest_box(e, &fits);
+    int width = BOX_CX;
+    const int64_t max_nodes = largest_box(e, &fits, &width);
     if (precond && !fits) {
         set_error("the two-level preconditioner needs boxes of at most 1024 nodes and a basis of at most 512");
         return MOS_EINVAL;
@@ -2534,7 +2544,7 @@ mos_status engine_set_precond(mos_engine e, int precond) {
     e->box_nt = (int)std::max<int64_t>(CG_LW, round_up(max_nodes, 64));
     // Jacobi alone keeps whole rows of cells per box (long rows of nodes
     // give the update's gathers the fewest cache lines per wave).
-    e->box_cells[0] = precond ? BOX_CX : 4096;
+    e->box_cells[0] = precond ? width : 4096;
     e->box_cells[1] = AGG_C;
     return MOS_OK;
 }
