@@ -289,12 +289,14 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False, vm_ref=None):
         single.append((time.perf_counter() - t1) * 1e3)
 
     cpu = None
-    err = None
+    err = nmae = None
     if with_cpu and not args.no_cpu_baseline:
         cpu, vm_ref = cpu_baseline(cases[0])
     if vm_ref is not None:
         step()
-        err = float(np.abs(vms[0].double().cpu().numpy() - vm_ref).max() / np.abs(vm_ref).max())
+        d = np.abs(vms[0].double().cpu().numpy() - vm_ref)
+        err = float(d.max() / np.abs(vm_ref).max())
+        nmae = float(d.mean() / np.abs(vm_ref).max())
 
     out = {
         "metric": METRIC,
@@ -331,6 +333,7 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False, vm_ref=None):
         "roofline": roofline,
         "cpu_baseline": cpu,
         "max_rel_err_vm_vs_oracle": err,
+        "normalized_mae_vm_vs_oracle": nmae,
     }
     eng.close()
     return out, vm_ref
@@ -351,6 +354,7 @@ def batch_mode(args, mos, torch, np, W):
         "p50_ms": mx["p50_ms"], "p99_ms": mx["p99_ms"], "single_array_ms": mx["single_array_ms"],
         "pcg_iters_mean": mx["pcg_iters_mean"], "refinement_sweeps_mean": mx["refinement_sweeps_mean"],
         "max_rel_err_vm_vs_oracle": mx["max_rel_err_vm_vs_oracle"],
+        "normalized_mae_vm_vs_oracle": mx["normalized_mae_vm_vs_oracle"],
         "roofline": {k: r.get(k) for k in ("kernel", "bound", "achieved", "peak", "unit", "frac", "traffic",
                                            "avg_launch_us", "kernels_ms_per_step")},
     }
