@@ -156,7 +156,10 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False, vm_ref=None):
     cases = [W.case_c2(args.seed + i) for i in range(B)]
     diam = [4.0, 5.0, 6.0]
     spec0 = cases[0].specs[0]
+    gc.collect()
+    torch.cuda.empty_cache()
     ctx = mos.Context(0)
+    torch.cuda.reset_peak_memory_stats()
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -332,6 +335,7 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False, vm_ref=None):
                  "progress_calls_per_step": round(host["progress_calls"] / max(host["steps"], 1), 1)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "peak_hbm_gb": round(torch.cuda.max_memory_allocated() / 2**30, 3),
         "max_rel_err_vm_vs_oracle": err,
         "normalized_mae_vm_vs_oracle": nmae,
     }
@@ -355,6 +359,7 @@ def batch_mode(args, mos, torch, np, W):
         "pcg_iters_mean": mx["pcg_iters_mean"], "refinement_sweeps_mean": mx["refinement_sweeps_mean"],
         "max_rel_err_vm_vs_oracle": mx["max_rel_err_vm_vs_oracle"],
         "normalized_mae_vm_vs_oracle": mx["normalized_mae_vm_vs_oracle"],
+        "peak_hbm_gb": mx["peak_hbm_gb"],
         "roofline": {k: r.get(k) for k in ("kernel", "bound", "achieved", "peak", "unit", "frac", "traffic",
                                            "avg_launch_us", "kernels_ms_per_step")},
     }
@@ -379,6 +384,7 @@ def single_mode(args, mos, torch, np, W):
     mixed precision side by side, each with its dominant kernel's roofline."""
     case = {"c3": W.case_c3, "c5": W.case_c5}[args.workload](args.seed)
     ctx = mos.Context(0)
+    torch.cuda.reset_peak_memory_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     roms = [mos.mos_reduce(ctx, mos.mos_build_cell(ctx, s)) for s in case.specs]
@@ -487,6 +493,7 @@ def single_mode(args, mos, torch, np, W):
         "fp64": paths["fp64"],
         "max_rel_err_vm_mixed_vs_fp64": err,
         "local_stage_ms_total": round(local_ms, 1),
+        "peak_hbm_gb": round(torch.cuda.max_memory_allocated() / 2**30, 3),
         "roofline": head["roofline"],
         "cpu_baseline": None,
     }
@@ -670,6 +677,7 @@ def serve_mode(args, mos, torch, np, W):
     reqs = W.request_stream(seed=args.seed, n_requests=args.requests)
     pitches = [10.0, 15.0, 20.0]
     ctx = mos.Context(0)
+    torch.cuda.reset_peak_memory_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     specs = []
@@ -752,6 +760,7 @@ def serve_mode(args, mos, torch, np, W):
         "p99_ms": round(float(np.percentile(lat, 99)), 3),
         "offered_cells_per_s": round(sum(c.n_cells for c in cases) / (reqs[-1].arrival_s + 1e-9), 1),
         "local_stage_ms_total": round(local_ms, 1),
+        "peak_hbm_gb": round(torch.cuda.max_memory_allocated() / 2**30, 3),
         "max_rel_err_vm_vs_fp64_sampled": max(errs) if errs else None,
         "roofline": None,
         "cpu_baseline": None,
