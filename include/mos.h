@@ -172,7 +172,9 @@ mos_status mos_reconstruct_displacement(mos_ctx ctx, mos_sol sol, void *u_nodal)
  * stream (complete when the call returns).  The first call for a ROM and
  * grid builds that ROM's plane stress basis (6 grid^2 x n, FP64, plus its
  * BF16 split) and keeps it with the ROM until mos_rom_free or a call with
- * another grid; a call with another grid first waits for the stream.
+ * another grid; a call with another grid first waits for the stream.  The
+ * call modifies the ROM: calls that use the same ROM must not run
+ * concurrently with it from other threads.
  * Errors: MOS_EINVAL for a NULL vm, a grid outside [1, 256], or a solution
  * whose ROMs were freed; MOS_ENOMEM if the basis does not fit. */
 mos_status mos_reconstruct_plane(mos_ctx ctx, mos_sol sol, int32_t grid, void *vm);
