@@ -46,47 +46,79 @@ __device__ __forceinline__ void load_tile_t(double (*S)[LDS_LD], const double *T
     for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) S[idx / NB][idx % NB] = T[idx];
 }
 
+// Diagonal tile: L_JJ (Cholesky) and X = L_JJ^{-1}.  The tile lives in
+// registers during the factorisation: thread (i, w) of the 256 holds row i
+// at columns w, w + 4, ..., w + 60.  Step k: the owner of (k, k) takes the
+// square root, the owners of column k scale it and publish it in LDS, and
+// every thread updates its own elements a_ij -= l_ik l_jk (j > k, i >= j).
 __global__ __launch_bounds__(256) void k_potrf(double *tiles, double *dinv, int J, int W, int *status) {
-    __shared__ double A[NB][LDS_LD];
+    __shared__ double L[NB][LDS_LD];
     __shared__ double X[NB][LDS_LD];
+    __shared__ double col[NB];
+    __shared__ double diag;
+    __shared__ double part_sum[4][NB];
     double *T = tile_ptr(tiles, J, 0, W);
-    load_tile(A, T);
-    __syncthreads();
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, i = tid % NB, w = tid / NB;
+    double a[NB / 4];
+#pragma unroll
+    for (int m = 0; m < NB / 4; ++m) a[m] = T[(size_t)(w + 4 * m) * NB + i];
     for (int k = 0; k < NB; ++k) {
-        if (tid == 0) {
-            double dkk = A[k][k];
+        const int wk = k % 4, mk = k / 4;
+        if (w == wk && i == k) {
+            double dkk = 0.0;
+#pragma unroll
+            for (int m = 0; m < NB / 4; ++m) dkk = m == mk ? a[m] : dkk;
             if (!(dkk > 0.0)) {
                 atomicCAS(status, 0, 1 + J * NB + k);
                 dkk = 1.0;
             }
-            A[k][k] = sqrt(dkk);
+            diag = sqrt(dkk);
         }
         __syncthreads();
-        if (tid > k && tid < NB) A[tid][k] /= A[k][k];
-        __syncthreads();
-        for (int idx = tid; idx < NB * NB; idx += blockDim.x) {
-            int i = idx % NB, j = idx / NB;
-            if (j > k && i >= j) A[i][j] -= A[i][k] * A[j][k];
+        if (w == wk) {
+            const double d = diag;
+#pragma unroll
+            for (int m = 0; m < NB / 4; ++m)
+                if (m == mk) {
+                    const double v = i == k ? d : (i > k ? a[m] / d : 0.0);
+                    if (i >= k) a[m] = v;
+                    col[i] = v;
+                }
         }
         __syncthreads();
+        const double ci = col[i];
+#pragma unroll
+        for (int m = 0; m < NB / 4; ++m) {
+            const int j = w + 4 * m;
+            if (j > k && i >= j) a[m] -= ci * col[j];
+        }
     }
-    // X = L^{-1}, one column per thread (forward substitution on e_t).
-    if (tid < NB) {
-        const int t = tid;
-        for (int i = 0; i < t; ++i) X[i][t] = 0.0;
-        X[t][t] = 1.0 / A[t][t];
-        for (int i = t + 1; i < NB; ++i) {
-            double s = 0.0;
-            for (int k = t; k < i; ++k) s += A[i][k] * X[k][t];
-            X[i][t] = -s / A[i][i];
+#pragma unroll
+    for (int m = 0; m < NB / 4; ++m) L[i][w + 4 * m] = a[m];
+    // X = L^{-1} by forward substitution on the identity, one row at a time
+    // for all 64 columns at once: X[i][t] = (delta_it - sum_{k<i} L[i][k]
+    // X[k][t]) / L[i][i].  Each dot product is split over four threads per
+    // column (k = part, part + 4, ...) and the four partials summed in order.
+    {
+        const int t = i, part = w;
+        for (int idx = tid; idx < NB * NB; idx += blockDim.x) X[idx / NB][idx % NB] = 0.0;
+        __syncthreads();
+        for (int r = 0; r < NB; ++r) {
+            double sum = 0.0;
+            for (int k = part; k < r; k += 4) sum += L[r][k] * X[k][t];
+            part_sum[part][t] = sum;
+            __syncthreads();
+            if (part == 0) {
+                const double sm = ((part_sum[0][t] + part_sum[1][t]) + part_sum[2][t]) + part_sum[3][t];
+                X[r][t] = ((r == t ? 1.0 : 0.0) - sm) / L[r][r];
+            }
+            __syncthreads();
         }
     }
-    __syncthreads();
     double *D = dinv + (size_t)J * NB * NB;
     for (int idx = tid; idx < NB * NB; idx += blockDim.x) {
         int r = idx % NB, c = idx / NB;
-        T[idx] = r >= c ? A[r][c] : 0.0;
+        T[idx] = r >= c ? L[r][c] : 0.0;
         D[idx] = r >= c ? X[r][c] : 0.0;
     }
 }
