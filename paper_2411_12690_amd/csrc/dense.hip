@@ -168,73 +168,103 @@ __global__ __launch_bounds__(256) void k_syrk(double *tiles, int J, int W, int N
         for (int j = 0; j < 4; ++j) C[(ty + 16 * i) + (tx + 16 * j) * NB] -= acc[i][j];
 }
 
-// Forward substitution step J on a 64 x 16 column slab of the row-major RHS:
-// Y_J = L_JJ^{-1} (R_J - sum_d L(J, J-d) Y_{J-d}).
-__global__ __launch_bounds__(256) void k_fwd(const double *tiles, const double *dinv, double *R, int J,
-                                             int W, int ldr) {
+// Forward substitution step J, Y_J = L_JJ^{-1} (R_J - sum_d L(J, J-d) Y_{J-d}),
+// in two launches.  k_fwd_part: one workgroup per (64 x 16 column slab of
+// the row-major RHS, off-diagonal tile d = 1..W) forms L(J, J-d) Y_{J-d}
+// into P[d-1]; k_fwd_fin: one workgroup per slab subtracts the P[d-1] from
+// R_J in the order d = 1, 2, ... and applies the stored inverse of L_JJ.
+// Spreading the W tile products over workgroups keeps the step from
+// walking its tiles one after another.
+__global__ __launch_bounds__(256) void k_fwd_part(const double *tiles, const double *R, double *P, int J, int W,
+                                                  int ldr) {
+    const int d = (int)blockIdx.y + 1;
+    if (J - d < 0) return;
     __shared__ double L[NB][LDS_LD];
     __shared__ double Y[NB][17];
     const int col = threadIdx.x % 16, r0 = threadIdx.x / 16;
     const int c0 = blockIdx.x * 16;
+    load_tile(L, tiles + ((size_t)(J - d) * (W + 1) + d) * NB * NB);
+    for (int idx = threadIdx.x; idx < NB * 16; idx += blockDim.x)
+        Y[idx / 16][idx % 16] = R[(size_t)((J - d) * NB + idx / 16) * ldr + c0 + idx % 16];
+    __syncthreads();
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < NB; ++k) {
+        const double y = Y[k][col];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] += L[r0 + 16 * i][k] * y;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) P[((size_t)(d - 1) * NB + r0 + 16 * i) * ldr + c0 + col] = acc[i];
+}
+
+__global__ __launch_bounds__(256) void k_fwd_fin(const double *dinv, const double *P, double *R, int J, int W,
+                                                 int ldr) {
+    __shared__ double L[NB][LDS_LD];
+    __shared__ double Y[NB][17];
+    const int col = threadIdx.x % 16, r0 = threadIdx.x / 16;
+    const int c0 = blockIdx.x * 16;
+    load_tile(L, dinv + (size_t)J * NB * NB);
     double acc[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[i] = R[(size_t)(J * NB + r0 + 16 * i) * ldr + c0 + col];
-    for (int d = 1; d <= W && J - d >= 0; ++d) {
-        __syncthreads();
-        load_tile(L, tiles + ((size_t)(J - d) * (W + 1) + d) * NB * NB);
-        for (int idx = threadIdx.x; idx < NB * 16; idx += blockDim.x)
-            Y[idx / 16][idx % 16] = R[(size_t)((J - d) * NB + idx / 16) * ldr + c0 + idx % 16];
-        __syncthreads();
-        for (int k = 0; k < NB; ++k) {
-            double y = Y[k][col];
+    for (int d = 1; d <= W && J - d >= 0; ++d)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) acc[i] -= L[r0 + 16 * i][k] * y;
-        }
-    }
-    __syncthreads();
-    load_tile(L, dinv + (size_t)J * NB * NB);
+        for (int i = 0; i < 4; ++i) acc[i] -= P[((size_t)(d - 1) * NB + r0 + 16 * i) * ldr + c0 + col];
 #pragma unroll
     for (int i = 0; i < 4; ++i) Y[r0 + 16 * i][col] = acc[i];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        int r = r0 + 16 * i;
+        const int r = r0 + 16 * i;
         double s = 0.0;
         for (int k = 0; k <= r; ++k) s += L[r][k] * Y[k][col];
         R[(size_t)(J * NB + r) * ldr + c0 + col] = s;
     }
 }
 
-// Backward substitution step J: X_J = L_JJ^{-T} (Y_J - sum_d L(J+d, J)^T X_{J+d}).
-__global__ __launch_bounds__(256) void k_bwd(const double *tiles, const double *dinv, double *R, int J,
-                                             int W, int NT, int ldr) {
+// Backward substitution step J, X_J = L_JJ^{-T} (Y_J - sum_d L(J+d, J)^T
+// X_{J+d}), in the same two launches.
+__global__ __launch_bounds__(256) void k_bwd_part(const double *tiles, const double *R, double *P, int J, int W,
+                                                  int NT, int ldr) {
+    const int d = (int)blockIdx.y + 1;
+    if (J + d >= NT) return;
     __shared__ double L[NB][LDS_LD];
     __shared__ double Y[NB][17];
     const int col = threadIdx.x % 16, r0 = threadIdx.x / 16;
     const int c0 = blockIdx.x * 16;
+    load_tile_t(L, tiles + ((size_t)J * (W + 1) + d) * NB * NB);
+    for (int idx = threadIdx.x; idx < NB * 16; idx += blockDim.x)
+        Y[idx / 16][idx % 16] = R[(size_t)((J + d) * NB + idx / 16) * ldr + c0 + idx % 16];
+    __syncthreads();
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < NB; ++k) {
+        const double y = Y[k][col];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] += L[r0 + 16 * i][k] * y;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) P[((size_t)(d - 1) * NB + r0 + 16 * i) * ldr + c0 + col] = acc[i];
+}
+
+__global__ __launch_bounds__(256) void k_bwd_fin(const double *dinv, const double *P, double *R, int J, int W,
+                                                 int NT, int ldr) {
+    __shared__ double L[NB][LDS_LD];
+    __shared__ double Y[NB][17];
+    const int col = threadIdx.x % 16, r0 = threadIdx.x / 16;
+    const int c0 = blockIdx.x * 16;
+    load_tile_t(L, dinv + (size_t)J * NB * NB);
     double acc[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[i] = R[(size_t)(J * NB + r0 + 16 * i) * ldr + c0 + col];
-    for (int d = 1; d <= W && J + d < NT; ++d) {
-        __syncthreads();
-        load_tile_t(L, tiles + ((size_t)J * (W + 1) + d) * NB * NB);
-        for (int idx = threadIdx.x; idx < NB * 16; idx += blockDim.x)
-            Y[idx / 16][idx % 16] = R[(size_t)((J + d) * NB + idx / 16) * ldr + c0 + idx % 16];
-        __syncthreads();
-        for (int k = 0; k < NB; ++k) {
-            double y = Y[k][col];
+    for (int d = 1; d <= W && J + d < NT; ++d)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) acc[i] -= L[r0 + 16 * i][k] * y;
-        }
-    }
-    __syncthreads();
-    load_tile_t(L, dinv + (size_t)J * NB * NB);
+        for (int i = 0; i < 4; ++i) acc[i] -= P[((size_t)(d - 1) * NB + r0 + 16 * i) * ldr + c0 + col];
 #pragma unroll
     for (int i = 0; i < 4; ++i) Y[r0 + 16 * i][col] = acc[i];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        int r = r0 + 16 * i;
+        const int r = r0 + 16 * i;
         double s = 0.0;
         for (int k = r; k < NB; ++k) s += L[r][k] * Y[k][col];
         R[(size_t)(J * NB + r) * ldr + c0 + col] = s;
@@ -266,12 +296,33 @@ mos_status band_solve(mos_cell c, const double *dinv, double *rhs, int ldr, int 
     hipStream_t st = c->ctx->stream;
     const int W = c->W, NT = c->NT;
     const int blocks = ceil_div(ncols, 16);
-    for (int J = 0; J < NT; ++J)
-        hipLaunchKernelGGL(k_fwd, dim3(blocks), dim3(256), 0, st, c->tiles, dinv, rhs, J, W, ldr);
-    for (int J = NT - 1; J >= 0; --J)
-        hipLaunchKernelGGL(k_bwd, dim3(blocks), dim3(256), 0, st, c->tiles, dinv, rhs, J, W, NT, ldr);
+    if (blocks * 16 > ldr) {
+        set_error("band_solve: %d right-hand sides exceed the row stride %d", ncols, ldr);
+        return MOS_EINVAL;
+    }
+    // Partial products of one step: [W][NB][ldr], reused by every step.
+    DeviceArena tmp;
+    tmp.ctx = c->ctx;
+    struct Guard {
+        DeviceArena &a;
+        ~Guard() { a.release(); }
+    } guard{tmp};
+    double *P = nullptr;
+    MOS_TRY(tmp.alloc_n((size_t)std::max(W, 1) * NB * ldr, &P));
+    for (int J = 0; J < NT; ++J) {
+        if (W > 0 && J > 0)
+            hipLaunchKernelGGL(k_fwd_part, dim3(blocks, W), dim3(256), 0, st, (const double *)c->tiles,
+                               (const double *)rhs, P, J, W, ldr);
+        hipLaunchKernelGGL(k_fwd_fin, dim3(blocks), dim3(256), 0, st, dinv, (const double *)P, rhs, J, W, ldr);
+    }
+    for (int J = NT - 1; J >= 0; --J) {
+        if (W > 0 && J + 1 < NT)
+            hipLaunchKernelGGL(k_bwd_part, dim3(blocks, W), dim3(256), 0, st, (const double *)c->tiles,
+                               (const double *)rhs, P, J, W, NT, ldr);
+        hipLaunchKernelGGL(k_bwd_fin, dim3(blocks), dim3(256), 0, st, dinv, (const double *)P, rhs, J, W, NT, ldr);
+    }
     MOS_LAUNCH_CHECK();
-    return MOS_OK;
+    return MOS_OK;  // releasing the scratch waits for the stream
 }
 
 }  // namespace mos
