@@ -74,8 +74,14 @@ def test_cell_assembly(mos, ctx, spec):
     assert cell.query(mos.MOS_Q_FREE_DOFS) == 3 * (oc.mx - 1) * (oc.my - 1) * (oc.mz - 1)
 
 
-@pytest.mark.parametrize("spec", [SPEC_SMALL, W.case_c1().specs[0], SPEC_SMALL.dummy()],
-                         ids=["small_liner", "c1_cell", "small_dummy"])
+@pytest.mark.parametrize("spec", [SPEC_SMALL, W.case_c1().specs[0], SPEC_SMALL.dummy(),
+                                  # The benchmark cell: 28,611 DoFs, many band tiles, and
+                                  # n + 1 = 169 right-hand sides (a ragged 16-column slab).
+                                  W.CellSpec(mesh=(16, 16, 32), tsv_diameter=6.0),
+                                  # One interior node: a single band tile and no off-diagonal ones.
+                                  W.CellSpec(pitch_x=3.0, pitch_y=3.0, height=6.0, mesh=(2, 2, 2),
+                                             interp=(3, 3, 3), tsv_diameter=1.6)],
+                         ids=["small_liner", "c1_cell", "small_dummy", "c2_cell_d6", "one_tile"])
 def test_reduction(mos, ctx, spec):
     rom = mos.mos_reduce(ctx, mos.mos_build_cell(ctx, spec))
     phi, fT, Kr, br = mos.mos_rom_export(rom)
