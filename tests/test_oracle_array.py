@@ -216,3 +216,161 @@ def test_c1_mor_against_full_fem():
     mae = np.abs(vm - vmf).mean() / vmf.max()
     assert mae < 0.06
     assert 400.0 < vmf.max() < 700.0
+
+
+# ----------------------------------------------------------------------------
+# Branches used as references by the GPU tests: the fine-mesh displacement of
+# eq. 15, the clamped top face, and prescribed displacement on the outer faces
+# of the full fine-mesh FEM (sub-modelling, Sec. 4.4).
+# ----------------------------------------------------------------------------
+def full_nodal(full, u_full, c):
+    """Full-FEM displacement of block c at its own FE nodes, in the cell
+    numbering (node (a, b, c) of the block, DoF 3 id + component)."""
+    cx, cy = c % full.Nx, c // full.Nx
+    C, B, A = np.meshgrid(np.arange(full.mz + 1), np.arange(full.my + 1), np.arange(full.mx + 1), indexing="ij")
+    g = full.node_id(cx * full.mx + A.ravel(), cy * full.my + B.ravel(), C.ravel())
+    return u_full.reshape(-1, 3)[g].ravel()
+
+
+def test_nodal_displacement_of_free_expansion_is_alpha_dT_x():
+    # Homogeneous array, 3-2-1 support at the origin: every fine node of every
+    # block moves by alpha dT x (eq. 15 with Phi reproducing linear fields);
+    # a block gathered at the wrong reduced DoFs would carry another offset.
+    s = spec_small(d=0.0)
+    rom = mor.local_stage(s)
+    m = array.AbstractMesh(3, 2, s.interp, 3.0, 3.0, 6.0)
+    t = np.zeros(6, dtype=np.uint8)
+    n0, n1, n2 = m.node_id[0, 0, 0], m.node_id[0, 0, m.X - 1], m.node_id[0, m.Y - 1, 0]
+    dofs = np.array([3 * n0, 3 * n0 + 1, 3 * n0 + 2, 3 * n1 + 1, 3 * n1 + 2, 3 * n2 + 2])
+    dT = -250.0
+    u = array.solve_mor(m, t, [rom], dT, dofs, np.zeros(6))
+    local = fem.Cell(s).node_coords()
+    for c in range(m.n_cells):
+        origin = np.array([3.0 * (c % 3), 3.0 * (c // 3), 0.0])
+        nod = array.nodal_displacement(m, t, [rom], u, dT, c).reshape(-1, 3)
+        np.testing.assert_allclose(nod, W.SI[2] * dT * (local + origin), rtol=0, atol=1e-13)
+
+
+def test_nodal_displacement_equals_full_fem_under_static_condensation():
+    # Lagrange nodes on every boundary FE node: MOR is static condensation,
+    # so eq. 15 must give the full FEM's displacement at every fine node of
+    # every block.  Via blocks have f_T != 0, so a dropped dT f_T term fails.
+    s = spec_small(mesh=(4, 4, 4), interp=(5, 5, 5), d=1.6)
+    specs = [s, s.dummy()]
+    roms = [mor.local_stage(x) for x in specs]
+    t = np.array([0, 1, 1, 0, 0, 0], dtype=np.uint8)
+    m = array.AbstractMesh(3, 2, s.interp, 3.0, 3.0, 6.0)
+    dT = -250.0
+    dofs, vals = array.constrained_dofs(m, True, False)
+    u = array.solve_mor(m, t, roms, dT, dofs, vals)
+    full = array.FullArray(specs, t, 3, 2)
+    uf, _ = full.solve(dT, True, False)
+    scale = np.abs(uf).max()
+    assert np.abs(dT * roms[0].fT).max() > 1e-3 * scale
+    for c in range(m.n_cells):
+        nod = array.nodal_displacement(m, t, roms, u, dT, c)
+        np.testing.assert_allclose(nod, full_nodal(full, uf, c), rtol=0, atol=1e-11 * scale)
+
+
+def test_clamp_top_constrains_exactly_the_top_lattice_plane():
+    m = array.AbstractMesh(3, 2, (4, 3, 4), 3.0, 3.0, 6.0)
+    want = set()
+    for node in range(m.n_nodes):
+        I, J, K = m.lattice[node]
+        if K == m.nz - 1:
+            assert m.coords[node, 2] == 6.0
+            want.update(3 * node + k for k in range(3))
+    dofs, vals = array.constrained_dofs(m, False, True)
+    assert set(dofs.tolist()) == want and not np.any(vals)
+    bottom, _ = array.constrained_dofs(m, True, False)
+    both, _ = array.constrained_dofs(m, True, True)
+    assert set(both.tolist()) == want | set(bottom.tolist())
+    assert not want & set(bottom.tolist())
+
+
+def test_top_and_bottom_clamped_array_is_mirror_symmetric_in_z():
+    # Scenario 1 of the paper's evaluation clamps both faces: the all-TSV
+    # array is then symmetric about z = h/2 (normal and xy stresses even,
+    # yz and zx odd); with the bottom clamped alone it is not.
+    s = spec_small(interp=(3, 3, 3), mesh=(4, 4, 6))
+    rom = mor.local_stage(s)
+    m = array.AbstractMesh(2, 2, (3, 3, 3), 3.0, 3.0, 6.0)
+    t = np.zeros(4, dtype=np.uint8)
+
+    def grid(top):
+        dofs, vals = array.constrained_dofs(m, True, top)
+        u = array.solve_mor(m, t, [rom], -250.0, dofs, vals)
+        return array.reconstruct(m, t, [rom], u, -250.0).reshape(4, 6, 4, 4, 6)   # [cell, z, y, x, comp]
+
+    g = grid(True)
+    tol = 1e-9 * np.abs(g).max()
+    fz = g[:, ::-1]
+    np.testing.assert_allclose(fz[..., [0, 1, 2, 3]], g[..., [0, 1, 2, 3]], atol=tol)
+    np.testing.assert_allclose(fz[..., [4, 5]], -g[..., [4, 5]], atol=tol)
+    g1 = grid(False)
+    assert np.abs(g1[:, ::-1][..., 0] - g1[..., 0]).max() > 1e3 * tol
+
+
+def linear_field(rng):
+    a = rng.normal(size=3) * 0.05
+    G = rng.normal(size=(3, 3)) * 1e-3
+    return (lambda xyz: a[None, :] + np.asarray(xyz) @ G.T), G
+
+
+def test_full_fem_reproduces_a_linear_field_on_the_outer_faces():
+    # Patch test of the prescribed-field branch: a homogeneous array at dT = 0
+    # with u = a + G x on all six outer faces is exactly that field inside,
+    # with the constant stress D sym(G) in every element.
+    s = spec_small(d=0.0)
+    rng = np.random.default_rng(7)
+    f, G = linear_field(rng)
+    full = array.FullArray([s], np.zeros(6, dtype=np.uint8), 3, 2)
+    u, sig = full.solve(0.0, False, False, field=f)
+    np.testing.assert_allclose(u.reshape(-1, 3), f(full.node_coords()), rtol=0, atol=1e-13)
+    eps = 0.5 * (G + G.T)
+    voigt = np.array([eps[0, 0], eps[1, 1], eps[2, 2], 2 * eps[0, 1], 2 * eps[1, 2], 2 * eps[2, 0]])
+    want = fem.elasticity_matrix(*W.SI[:2]) @ voigt
+    np.testing.assert_allclose(sig, np.broadcast_to(want, sig.shape), rtol=0, atol=1e-9 * np.abs(want).max())
+
+
+def test_mor_with_a_linear_field_on_the_outer_faces_is_exact():
+    s = spec_small(d=0.0)
+    rom = mor.local_stage(s)
+    rng = np.random.default_rng(8)
+    f, _ = linear_field(rng)
+    m = array.AbstractMesh(3, 2, s.interp, 3.0, 3.0, 6.0)
+    t = np.zeros(6, dtype=np.uint8)
+    outer = np.nonzero(m.outer_node_mask())[0]
+    dofs = (3 * outer[:, None] + np.arange(3)).ravel()
+    vals = f(m.coords[outer]).ravel()
+    u = array.solve_mor(m, t, [rom], 0.0, dofs, vals)
+    np.testing.assert_allclose(u.reshape(-1, 3), f(m.coords), rtol=0, atol=1e-13)
+    local = fem.Cell(s).node_coords()
+    for c in range(m.n_cells):
+        origin = np.array([3.0 * (c % 3), 3.0 * (c // 3), 0.0])
+        nod = array.nodal_displacement(m, t, [rom], u, 0.0, c).reshape(-1, 3)
+        np.testing.assert_allclose(nod, f(local + origin), rtol=0, atol=1e-13)
+
+
+def test_prescribed_field_mor_equals_full_fem_under_static_condensation():
+    # Heterogeneous blocks, a smooth non-polynomial field on all six outer
+    # faces and a thermal load: with Lagrange nodes on every boundary FE node
+    # both sides see the same Dirichlet data, so they must agree exactly.
+    s = spec_small(mesh=(4, 4, 4), interp=(5, 5, 5), d=1.6)
+    specs = [s, s.dummy()]
+    roms = [mor.local_stage(x) for x in specs]
+    t = np.array([0, 1, 0, 0], dtype=np.uint8)
+    m = array.AbstractMesh(2, 2, s.interp, 3.0, 3.0, 6.0)
+    field = W.fourier_field(np.random.default_rng(3), (6.0, 6.0, 6.0), amplitude=0.05)
+    outer = np.nonzero(m.outer_node_mask())[0]
+    dofs = (3 * outer[:, None] + np.arange(3)).ravel()
+    vals = field(m.coords[outer]).ravel()
+    dT = -150.0
+    u = array.solve_mor(m, t, roms, dT, dofs, vals)
+    full = array.FullArray(specs, t, 2, 2)
+    uf, sf = full.solve(dT, False, False, field=field)
+    sig = array.reconstruct(m, t, roms, u, dT)
+    np.testing.assert_allclose(sig, sf, rtol=0, atol=1e-9 * np.abs(sf).max())
+    for c in range(m.n_cells):
+        np.testing.assert_allclose(array.nodal_displacement(m, t, roms, u, dT, c), full_nodal(full, uf, c),
+                                   rtol=0, atol=1e-11 * np.abs(uf).max())
