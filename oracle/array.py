@@ -37,17 +37,22 @@ from . import mor
 
 class AbstractMesh:
     """Numbering of the abstract mesh of an N_x x N_y array of blocks with
-    (n_x, n_y, n_z) interpolation nodes per block (Sec. 4.3)."""
+    (n_x, n_y, n_z) interpolation nodes per block (Sec. 4.3).  With
+    nz_cells = N_z > 1 the array holds N_z layers of blocks stacked in z that
+    share their horizontal faces (a stacked variant of the same abstract
+    mesh: block (cx, cy, cz) has id (cz N_y + cy) N_x + cx and its surface
+    node (i, j, k) sits at lattice point (cx (n_x-1) + i, cy (n_y-1) + j,
+    cz (n_z-1) + k))."""
 
-    def __init__(self, nx_cells, ny_cells, interp, pitch_x=1.0, pitch_y=1.0, height=1.0):
-        self.Nx, self.Ny = int(nx_cells), int(ny_cells)
+    def __init__(self, nx_cells, ny_cells, interp, pitch_x=1.0, pitch_y=1.0, height=1.0, nz_cells=1):
+        self.Nx, self.Ny, self.Nz = int(nx_cells), int(ny_cells), int(nz_cells)
         self.nx, self.ny, self.nz = (int(v) for v in interp)
         self.X = self.Nx * (self.nx - 1) + 1
         self.Y = self.Ny * (self.ny - 1) + 1
-        self.Z = self.nz
+        self.Z = self.Nz * (self.nz - 1) + 1
         K, J, I = np.meshgrid(np.arange(self.Z), np.arange(self.Y), np.arange(self.X), indexing="ij")
         is_node = ((I % (self.nx - 1) == 0) | (J % (self.ny - 1) == 0)
-                   | (K == 0) | (K == self.nz - 1))
+                   | (K % (self.nz - 1) == 0))
         self.node_id = np.full(is_node.shape, -1, dtype=np.int64)
         self.node_id[is_node] = np.arange(int(is_node.sum()))
         self.n_nodes = int(is_node.sum())
@@ -58,17 +63,19 @@ class AbstractMesh:
                                 height * self.lattice[:, 2] / (self.nz - 1)], axis=1)
         S = mor.surface_nodes(self.nx, self.ny, self.nz)
         self.n_local = 3 * len(S)
-        n_cells = self.Nx * self.Ny
+        n_cells = self.Nx * self.Ny * self.Nz
         self.conn = np.zeros((n_cells, len(S)), dtype=np.int64)
-        for cy in range(self.Ny):
-            for cx in range(self.Nx):
-                c = cy * self.Nx + cx
-                for s, (i, j, k) in enumerate(S):
-                    self.conn[c, s] = self.node_id[k, cy * (self.ny - 1) + j, cx * (self.nx - 1) + i]
+        for cz in range(self.Nz):
+            for cy in range(self.Ny):
+                for cx in range(self.Nx):
+                    c = (cz * self.Ny + cy) * self.Nx + cx
+                    for s, (i, j, k) in enumerate(S):
+                        self.conn[c, s] = self.node_id[cz * (self.nz - 1) + k, cy * (self.ny - 1) + j,
+                                                       cx * (self.nx - 1) + i]
 
     @property
     def n_cells(self):
-        return self.Nx * self.Ny
+        return self.Nx * self.Ny * self.Nz
 
     def cell_dofs(self):
         """(n_cells, n) global DoF of each block DoF 3 s + component."""
@@ -229,18 +236,19 @@ def solve_mor(mesh, cell_type, roms, dT, bc_dofs, bc_values, direct=True, rtol=1
 # Full fine-mesh FEM of a whole array (the reference the MOR answer approximates)
 # ----------------------------------------------------------------------------
 class FullArray:
-    """Fine hexahedral mesh of an N_x x N_y array of blocks, every block meshed
-    as in its own cell spec (all types share pitch, height and mesh)."""
+    """Fine hexahedral mesh of an N_x x N_y (x N_z stacked layers) array of
+    blocks, every block meshed as in its own cell spec (all types share
+    pitch, height and mesh)."""
 
-    def __init__(self, specs, cell_type, nx_cells, ny_cells):
+    def __init__(self, specs, cell_type, nx_cells, ny_cells, nz_cells=1):
         self.specs = specs
         self.cell_type = np.asarray(cell_type)
-        self.Nx, self.Ny = nx_cells, ny_cells
+        self.Nx, self.Ny, self.Nz = nx_cells, ny_cells, nz_cells
         self.cells = [fem.Cell(s) for s in specs]
         c0 = self.cells[0]
         self.mx, self.my, self.mz = c0.mx, c0.my, c0.mz
         self.px, self.py, self.h = c0.px, c0.py, c0.h
-        self.GX, self.GY, self.GZ = self.Nx * self.mx, self.Ny * self.my, self.mz
+        self.GX, self.GY, self.GZ = self.Nx * self.mx, self.Ny * self.my, self.Nz * self.mz
         self.n_nodes = (self.GX + 1) * (self.GY + 1) * (self.GZ + 1)
         self.n_dofs = 3 * self.n_nodes
 
@@ -261,8 +269,8 @@ class FullArray:
         nodes = np.zeros((EA.size, 8), dtype=np.int64)
         for l in range(8):
             nodes[:, l] = self.node_id(EA + (l & 1), EB + ((l >> 1) & 1), EC + ((l >> 2) & 1))
-        cell = (EB // self.my) * self.Nx + EA // self.mx
-        local = (EC * self.my + EB % self.my) * self.mx + EA % self.mx
+        cell = ((EC // self.mz) * self.Ny + EB // self.my) * self.Nx + EA // self.mx
+        local = ((EC % self.mz) * self.my + EB % self.my) * self.mx + EA % self.mx
         return nodes, cell, local
 
     def solve(self, dT, clamp_bottom, clamp_top, field=None):
@@ -316,6 +324,6 @@ class FullArray:
             beta = fem.thermal_coefficient(E, nu, alpha)
             sig[sel] = u[edofs[sel]] @ DB.T - beta * dT * fem.M_VEC
         n_elem_cell = self.mx * self.my * self.mz
-        out = np.zeros((self.Nx * self.Ny, n_elem_cell, 6))
+        out = np.zeros((self.Nx * self.Ny * self.Nz, n_elem_cell, 6))
         out[cell, local] = sig
         return u, out
