@@ -28,11 +28,13 @@
  *   Lagrange surface node (i,j,k) of a cell (i in {0,n_x-1} or j in {0,n_y-1}
  *   or k in {0,n_z-1}) has local index s = its rank in (k,j,i) lexicographic
  *   order, i fastest; the reduced cell DoF is 3*s+component (eq. 14-16).
- *   The abstract array mesh has lattice X = N_x(n_x-1)+1, Y = N_y(n_y-1)+1,
- *   Z = n_z; lattice point (I,J,K) is a node iff I%(n_x-1)==0 or
- *   J%(n_y-1)==0 or K in {0, n_z-1}; node id = rank in (K,J,I) order, I
- *   fastest; global DoF 3*id+component.  Cell (cx,cy) has id cy*N_x+cx and its
- *   surface node (i,j,k) is lattice point (cx(n_x-1)+i, cy(n_y-1)+j, k).
+ *   The abstract array mesh of N_x x N_y blocks in N_z layers (N_z = 1 for
+ *   one layer) has lattice X = N_x(n_x-1)+1, Y = N_y(n_y-1)+1,
+ *   Z = N_z(n_z-1)+1; lattice point (I,J,K) is a node iff I%(n_x-1)==0 or
+ *   J%(n_y-1)==0 or K%(n_z-1)==0; node id = rank in (K,J,I) order, I
+ *   fastest; global DoF 3*id+component.  Cell (cx,cy,cz) has id
+ *   (cz*N_y+cy)*N_x+cx and its surface node (i,j,k) is lattice point
+ *   (cx(n_x-1)+i, cy(n_y-1)+j, cz(n_z-1)+k).
  */
 #ifndef MOS_H
 #define MOS_H
@@ -79,16 +81,26 @@ typedef struct {
     int32_t interp[3];
 } mos_cell_desc;
 
-enum { MOS_BC_CLAMP_BOTTOM = 1, MOS_BC_CLAMP_TOP = 2 };
+enum { MOS_BC_CLAMP_BOTTOM = 1, MOS_BC_CLAMP_TOP = 2, MOS_BC_LIST_ON_DEVICE = 4 };
 
-/* One global-stage problem (Sec. 4.3-4.4).  cell_type[cy*nx_cells+cx] indexes
- * the roms[] array passed with it (host memory).  Constrained DoFs: the
+/* One global-stage problem (Sec. 4.3-4.4).  cell_type[(cz*ny_cells+cy)*nx_cells+cx]
+ * indexes the roms[] array passed with it (host memory).  nz_cells > 1 stacks
+ * that many layers of blocks in z, sharing their horizontal faces (0 or 1:
+ * one layer); stacked arrays take the Jacobi preconditioner
+ * (MOS_OPT_PRECOND 0; mos_solve_array selects it by itself).  Constrained DoFs: the
  * clamped faces (value 0) and then the prescribed (global DoF, value) list,
  * a later entry overriding an earlier one; the system is lifted
  * symmetrically (Sec. 4.2 eq. 13 form, same solution).  rtol bounds the
  * FP64 true residual ||b - A u||_2 / ||b||_2 (0 selects 1e-12 for MOS_FP64,
  * 1e-10 for MOS_MIXED); max_iters bounds the total PCG iterations (0 selects
- * 20000). */
+ * 20000).  The prescribed list is host memory, copied during the call,
+ * unless bc_flags has MOS_BC_LIST_ON_DEVICE: then prescribed_dof and
+ * prescribed_value are device arrays of the context's device (caller-owned,
+ * read on the context's stream when the problem is set up, so they must stay
+ * valid and unchanged until its ticket completes or mos_solve_array
+ * returns), and their entries are checked on the device: a DoF outside
+ * [0, n_dofs) or a non-finite value fails the problem with MOS_EINVAL
+ * (the ticket's status, or mos_solve_array's return). */
 typedef struct {
     int32_t nx_cells, ny_cells;
     const uint8_t *cell_type;
@@ -100,6 +112,7 @@ typedef struct {
     mos_precision precision;
     double rtol;
     int32_t max_iters;
+    int32_t nz_cells;
 } mos_array_desc;
 
 /* Optional device allocator (e.g. a framework's caching allocator).  NULL
@@ -205,13 +218,14 @@ mos_status mos_cell_export(mos_cell cell, int64_t *row_ptr, int32_t *col, double
 /* ROM: Phi row-major [n_dofs][n], f_T[n_dofs], K_r row-major [n][n], b_r[n]. */
 mos_status mos_rom_export(mos_rom rom, double *phi, double *f_T, double *K_r, double *b_r);
 
-/* Abstract array mesh of nx_cells x ny_cells blocks shaped like `rom`
- * (numbering contract above).  n_nodes receives the node count; when the
- * arrays are non-NULL: coords[n_nodes][3] (um), conn[n_cells][n/3] node ids,
+/* Abstract array mesh of nx_cells x ny_cells (x nz_cells stacked layers;
+ * 0 or 1: one layer) blocks shaped like `rom` (numbering contract above).
+ * n_nodes receives the node count; when the arrays are non-NULL:
+ * coords[n_nodes][3] (um), conn[n_cells][n/3] node ids,
  * and the sparsity pattern of the assembled global matrix over DoFs
  * (union of per-cell dense blocks, columns ascending): row_ptr[3 n_nodes + 1]
  * and col[row_ptr[3 n_nodes]].  Call with col == NULL first to size it. */
-mos_status mos_array_layout(mos_ctx ctx, int32_t nx_cells, int32_t ny_cells, mos_rom rom,
+mos_status mos_array_layout(mos_ctx ctx, int32_t nx_cells, int32_t ny_cells, int32_t nz_cells, mos_rom rom,
                             int64_t *n_nodes, double *coords, int32_t *conn, int64_t *row_ptr,
                             int32_t *col);
 
@@ -231,7 +245,10 @@ mos_status mos_array_layout(mos_ctx ctx, int32_t nx_cells, int32_t ny_cells, mos
 typedef struct mos_engine_s *mos_engine;
 
 /* device_bytes: arena budget; a problem larger than the arenas is rejected
- * with MOS_EINVAL at submission.  roms must outlive the engine. */
+ * with MOS_EINVAL at submission.  One engine addresses at most 4,194,304
+ * cell slots (each cell type of a problem takes its cells rounded up to 16),
+ * so a budget beyond that (about 45 GB in FP64) is used only up to it.
+ * roms must outlive the engine. */
 mos_status mos_engine_create(mos_ctx ctx, const mos_rom *roms, int32_t n_roms, mos_precision precision,
                              size_t device_bytes, mos_engine *out);
 /* Queue one problem (desc->precision must equal the engine's).  vm / sigma6:
@@ -242,7 +259,11 @@ mos_status mos_engine_submit(mos_engine e, const mos_array_desc *desc, void *vm,
                              int64_t *ticket);
 /* One round of admission, `iterations` PCG iterations and retirement.
  * Tickets completed since the last call are written to completed[] (up to
- * max_completed; the rest are reported by the next call). */
+ * max_completed; the rest are reported by the next call).  A ticket is
+ * reported only once the device has finished writing its outputs
+ * (reconstruction and u): a problem that retires while others still iterate
+ * is reported by a later call (at the latest after the next chunk); when
+ * nothing is left to iterate the call waits for the retirements itself. */
 mos_status mos_engine_progress(mos_engine e, int32_t iterations, int64_t *completed, int32_t max_completed,
                                int32_t *n_completed);
 /* Outcome of a completed ticket (status MOS_OK or the failure code), its
@@ -293,8 +314,17 @@ mos_status mos_engine_result(mos_engine e, int64_t ticket, int32_t *status, doub
  * kernels, are launched directly either way.  The kernels and their
  * arguments are the same, so results do not depend on it; it may be
  * changed at any time. */
+/* MOS_OPT_COARSE_TABLE (two-level preconditioner): 1 (default) builds each
+ * aggregate's B_a from per-type tables of the cell terms wherever the
+ * aggregate's constrained DoFs are whole bottom / top planes (always for
+ * clamp-only problems; for problems with a prescribed list, every aggregate
+ * whose cells carry no prescribed value off those planes), and from the
+ * cells' K_r rows elsewhere; 0 builds every aggregate of problems with a
+ * prescribed list from the K_r rows.  Both give the same B_a up to rounding
+ * (only the preconditioner, never the converged solution); it applies to
+ * problems submitted afterwards. */
 enum { MOS_OPT_CELL_GEMM = 1, MOS_OPT_GEMM_SPLIT = 2, MOS_OPT_UPDATE_WIDTH = 3, MOS_OPT_PRECOND = 4,
-       MOS_OPT_GRAPH = 5 };
+       MOS_OPT_GRAPH = 5, MOS_OPT_COARSE_TABLE = 6 };
 mos_status mos_engine_option(mos_engine e, int option, int64_t value);
 /* Counts of iteration-chunk graph captures and replays so far (MOS_OPT_GRAPH;
  * either pointer may be NULL). */

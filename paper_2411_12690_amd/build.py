@@ -40,6 +40,37 @@ def _compile(src):
     return obj, p.stderr
 
 
+HOST_DIR = os.path.join(ROOT, "tests", "host")
+HOST_SRC = os.path.join(HOST_DIR, "mesh_check.cpp")
+# Host-only flags: the harness includes the HIP runtime headers for their
+# host declarations; no device code is compiled into it.
+HOST_FLAGS = ["-std=c++17", "-O1", "-g", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", "-I", INCLUDE,
+              "-I", CSRC]
+
+
+def build_host_checks():
+    """Build the host harness of the numbering contract and ABI checks twice:
+    against libmos.so as built (g++), and with the C-ABI layer compiled into it
+    under AddressSanitizer and UndefinedBehaviorSanitizer (ROCm's clang, host
+    code only).  Returns the two executable paths."""
+    plain = os.path.join(HOST_DIR, "mesh_check")
+    san = os.path.join(HOST_DIR, "mesh_check_asan")
+    link = ["-L", PKG, "-lmos", "-Wl,-rpath," + PKG]
+    cmd = ["g++"] + HOST_FLAGS + ["-Wall", HOST_SRC, "-o", plain] + link
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError(f"host harness build failed: {' '.join(cmd)}\n{p.stderr}")
+    clang = "/opt/rocm/llvm/bin/clang++"
+    sanitize = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined",
+                "-Wno-c++20-extensions"]
+    cmd = ([clang] + HOST_FLAGS + sanitize + [HOST_SRC, os.path.join(CSRC, "api.cpp"), "-o", san] + link +
+           ["-L", "/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"])
+    p = subprocess.run(cmd, capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError(f"sanitized host harness build failed: {' '.join(cmd)}\n{p.stderr}")
+    return plain, san
+
+
 def build(verbose=False):
     """Compile every source and link libmos.so; returns the library path."""
     os.makedirs(OBJ_DIR, exist_ok=True)
@@ -56,6 +87,7 @@ def build(verbose=False):
     if p.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{p.stdout}\n{p.stderr}")
     os.replace(tmp, LIB)
+    build_host_checks()
     return LIB
 
 

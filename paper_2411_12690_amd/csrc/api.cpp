@@ -92,27 +92,30 @@ void surface_nodes(int nx, int ny, int nz, std::vector<int> &ijk) {
                 }
 }
 
-void ArrayMesh::build(int Nx_, int Ny_, int nx_, int ny_, int nz_) {
+void ArrayMesh::build(int Nx_, int Ny_, int nx_, int ny_, int nz_, int Nz_) {
     Nx = Nx_;
     Ny = Ny_;
+    Nz = Nz_;
     nx = nx_;
     ny = ny_;
     nz = nz_;
-    lat = make_lattice(Nx, Ny, nx, ny, nz);
+    lat = make_lattice(Nx, Ny, nx, ny, nz, Nz);
     X = lat.X;
     Y = lat.Y;
     Z = lat.Z;
     n_nodes = lat.n_nodes;
     surface_nodes(nx, ny, nz, surf);
     S = (int)surf.size() / 3;
-    conn.resize((size_t)Nx * Ny * S);
-    for (int cy = 0; cy < Ny; ++cy)
-        for (int cx = 0; cx < Nx; ++cx) {
-            size_t c = (size_t)cy * Nx + cx;
-            for (int s = 0; s < S; ++s)
-                conn[c * S + s] = (int32_t)node_id(lat, (int64_t)cx * (nx - 1) + surf[3 * s],
-                                                   (int64_t)cy * (ny - 1) + surf[3 * s + 1], surf[3 * s + 2]);
-        }
+    conn.resize((size_t)Nx * Ny * Nz * S);
+    for (int cz = 0; cz < Nz; ++cz)
+        for (int cy = 0; cy < Ny; ++cy)
+            for (int cx = 0; cx < Nx; ++cx) {
+                const size_t c = ((size_t)cz * Ny + cy) * Nx + cx;
+                for (int s = 0; s < S; ++s)
+                    conn[c * S + s] = (int32_t)node_id(lat, (int64_t)cx * (nx - 1) + surf[3 * s],
+                                                       (int64_t)cy * (ny - 1) + surf[3 * s + 1],
+                                                       (int64_t)cz * (nz - 1) + surf[3 * s + 2]);
+            }
 }
 
 }  // namespace mos
@@ -411,6 +414,8 @@ mos_status mos_solve_array(mos_ctx ctx, const mos_array_desc *d, const mos_rom *
             delete e;
         }
     } eg{e};
+    // Stacked arrays take the Jacobi preconditioner.
+    if (d->nz_cells > 1) MOS_TRY(engine_set_precond(e, 0));
     int64_t dofs = 0, slots = 0;
     MOS_TRY(engine_problem_size(e, d, &dofs, &slots));
     MOS_TRY(engine_alloc(e, dofs, slots));
@@ -429,7 +434,8 @@ mos_status mos_solve_array(mos_ctx ctx, const mos_array_desc *d, const mos_rom *
         }
     } sg{s};
     const mos_cell_desc &cd = roms[0]->desc;
-    const Lattice lat = make_lattice(d->nx_cells, d->ny_cells, cd.interp[0], cd.interp[1], cd.interp[2]);
+    const Lattice lat = make_lattice(d->nx_cells, d->ny_cells, cd.interp[0], cd.interp[1], cd.interp[2],
+                                     d->nz_cells < 1 ? 1 : d->nz_cells);
     MOS_TRY(s->mem.alloc_n(3 * lat.n_nodes, &s->u));
     int64_t ticket = 0;
     MOS_TRY(engine_submit(e, d, nullptr, nullptr, s->u, &ticket));
@@ -500,7 +506,10 @@ mos_status mos_engine_create(mos_ctx ctx, const mos_rom *roms, int32_t n_roms, m
     const double per_slot = e->ldk * (2 * w + 16) + 8 + 8.0 / 16 + e->ldk / 16 * 8.0 / 16 +
                             (precision == MOS_MIXED ? (double)recon_bf16_scratch(roms[0], 1) / 16 : 0.0);
     const double units = (double)device_bytes / (100 * per_dof + per_slot);
-    const int64_t dofs = (int64_t)(units * 100), slots = (int64_t)units;
+    // A budget beyond what one engine can address is used only up to the
+    // slot limit of the incidence packing (about 45 GB of FP64 arenas).
+    const double units_cap = std::min(units, (double)MAX_SLOTS);
+    const int64_t dofs = (int64_t)(units_cap * 100), slots = (int64_t)units_cap;
     if (dofs < 768 || slots < 16) {
         delete e;
         set_error("device budget of %zu bytes is too small for an engine", device_bytes);
@@ -592,6 +601,10 @@ mos_status mos_engine_option(mos_engine e, int option, int64_t value) {
     }
     if (option == MOS_OPT_UPDATE_WIDTH && (value == 0 || value == 128 || value == 256)) {
         e->update_width = (int)value;
+        return MOS_OK;
+    }
+    if (option == MOS_OPT_COARSE_TABLE && (value == 0 || value == 1)) {
+        e->coarse_table = (int)value;
         return MOS_OK;
     }
     if (option == MOS_OPT_GRAPH && (value == 0 || value == 1)) {
@@ -788,22 +801,23 @@ mos_status mos_rom_export(mos_rom r, double *phi, double *f_T, double *K_r, doub
     return MOS_OK;
 }
 
-mos_status mos_array_layout(mos_ctx ctx, int32_t nx_cells, int32_t ny_cells, mos_rom rom, int64_t *n_nodes,
-                            double *coords, int32_t *conn, int64_t *row_ptr, int32_t *col) {
+mos_status mos_array_layout(mos_ctx ctx, int32_t nx_cells, int32_t ny_cells, int32_t nz_cells, mos_rom rom,
+                            int64_t *n_nodes, double *coords, int32_t *conn, int64_t *row_ptr, int32_t *col) {
+    const int32_t nz = nz_cells < 1 ? 1 : nz_cells;
     if (!ctx || !rom || rom->kind != KIND_ROM || !n_nodes || nx_cells < 1 || ny_cells < 1 ||
-        (int64_t)nx_cells * ny_cells > (1 << 22)) {
+        (int64_t)nx_cells * ny_cells * nz > (1 << 22)) {
         set_error("invalid arguments to mos_array_layout");
         return MOS_EINVAL;
     }
     const mos_cell_desc &d = rom->desc;
     ArrayMesh m;
-    m.build(nx_cells, ny_cells, d.interp[0], d.interp[1], d.interp[2]);
+    m.build(nx_cells, ny_cells, d.interp[0], d.interp[1], d.interp[2], nz);
     *n_nodes = m.n_nodes;
     if (coords) {
         for (int64_t K = 0; K < m.Z; ++K)
             for (int64_t J = 0; J < m.Y; ++J)
                 for (int64_t I = 0; I < m.X; ++I) {
-                    if (!(I % (m.nx - 1) == 0 || J % (m.ny - 1) == 0 || K == 0 || K == m.Z - 1)) continue;
+                    if (!(I % (m.nx - 1) == 0 || J % (m.ny - 1) == 0 || K % (m.nz - 1) == 0)) continue;
                     const int64_t id = node_id(m.lat, I, J, K);
                     coords[3 * (size_t)id + 0] = d.pitch_x * I / (m.nx - 1);
                     coords[3 * (size_t)id + 1] = d.pitch_y * J / (m.ny - 1);
@@ -814,7 +828,7 @@ mos_status mos_array_layout(mos_ctx ctx, int32_t nx_cells, int32_t ny_cells, mos
     if (row_ptr) {
         // Node-level pattern: union of the node sets of the cells around each node.
         std::vector<std::vector<int32_t>> cells_of((size_t)m.n_nodes);
-        const int64_t nc = (int64_t)nx_cells * ny_cells;
+        const int64_t nc = (int64_t)nx_cells * ny_cells * nz;
         for (int64_t c = 0; c < nc; ++c)
             for (int s = 0; s < m.S; ++s) cells_of[m.conn[(size_t)c * m.S + s]].push_back((int32_t)c);
         row_ptr[0] = 0;

@@ -57,7 +57,8 @@ struct ProbParams {
     int32_t n_agg;                  // boxes of the internal node order
     int32_t box_begin;              // first box id (two-level preconditioner), else -1
     int32_t part_begin, n_part;     // the problem's (r,u), (r,r) partial slots: its boxes or DoF blocks
-    int32_t tab_coarse;             // 1: coarse matrices from the per-type table (clamped faces only)
+    int32_t tab_coarse;             // coarse matrices: 1 per-type table (clamped faces only), 2 table per
+                                    // aggregate where its constraints are whole planes, else 0 general
 };
 // Parameters of a problem's current refinement sweep (device table by id).
 struct SweepParams {
@@ -70,7 +71,7 @@ struct SweepParams {
 // K_r-stationary GEMM keeps in registers; larger bases use the tile GEMM.
 constexpr int ROWS_MAX_KS = 44;
 // Entries of the launch shape a captured iteration chunk is valid for.
-constexpr int GRAPH_KEY = 11;
+constexpr int GRAPH_KEY = 12;
 
 // Online tuner of the rows GEMM's work split (slot blocks per wave).  The
 // split only decides which wave computes which output tile -- every tile is
@@ -150,6 +151,8 @@ struct mos_engine_s {
     double *pdel = nullptr;                   // [cap_sb * ldk/16] per-tile (u, A u) partials
     uint8_t *cmask = nullptr;
     int32_t *inc = nullptr;                   // [dofs/3][4]
+    int32_t *inc2 = nullptr;                  // [dofs/3][4]: cells of the layer above (stacked arrays), else -1
+    int stacked = 0;                          // a stacked array has been admitted (Jacobi kernels read inc2)
     int32_t *blk_prob = nullptr;              // [cap_blk]
     double *pg = nullptr, *pd = nullptr, *pr = nullptr, *pr64 = nullptr;  // [cap_blk]
     int32_t *sb_rom = nullptr, *sb_prob = nullptr;  // [cap_sb]
@@ -161,6 +164,8 @@ struct mos_engine_s {
     int4 *box_tab = nullptr;                  // [cap_blk]: first node, nodes, aggregates, owner (-1 free)
     double *binv = nullptr;                   // [cap_blk][MAXA][36]
     double *cc = nullptr;                     // [cap_blk][MAXA][6]
+    int32_t *agg_gen = nullptr;               // [cap_blk][MAXA]: 1 = B_a from the general kernel (prescribed lists)
+    int coarse_table = 1;                     // problems with a prescribed list may take the table per aggregate
     // Per cell type, clamp flags, cell class (whether its right / top face
     // belongs to the next aggregate) and piece: the 21 terms of Z^T K_r Z
     // in cell-local coordinates; built per clamp-flag value on first use.
@@ -175,6 +180,7 @@ struct mos_engine_s {
     mos::ProbState *ps = nullptr;             // [MAX_PROBS]
     mos::ProbState *ps_host = nullptr;        // pinned: states read back at the end of a chunk
     double *res2 = nullptr, *bb2 = nullptr;   // [MAX_PROBS]
+    int32_t *pres_bad = nullptr;              // [MAX_PROBS]: a device-resident prescribed list held a bad entry
     double *host_scratch = nullptr;           // pinned: a few doubles read back from the device
     void **kr64_tab = nullptr, **kr32_tab = nullptr;
     double **br_tab = nullptr, **psi_tab = nullptr, **sigt_tab = nullptr;
@@ -201,6 +207,16 @@ struct mos_engine_s {
     std::vector<mos::EngineProblem *> active;
     std::map<int64_t, mos::EngineProblem *> finished;
     std::vector<int64_t> completed_unreported;
+    // Problems retired by one progress call, behind an event recorded after
+    // their reconstruction, export and release launches: they move to
+    // `finished` (and are reported) only once that event has completed, so
+    // a reported ticket's output buffers are written.
+    struct Retiring {
+        hipEvent_t ev;
+        std::vector<mos::EngineProblem *> probs;
+    };
+    std::deque<Retiring> retiring;
+    std::vector<hipEvent_t> spare_events;
 };
 
 namespace mos {
@@ -209,7 +225,7 @@ namespace mos {
 struct EngineProblem {
     int64_t ticket = 0;
     int pid = -1;
-    int Nx = 0, Ny = 0;
+    int Nx = 0, Ny = 0, Nz = 1;   // blocks along x and y, stacked layers
     int64_t n_cells = 0, n_nodes = 0, n_dofs = 0;
     int blk_begin = 0, n_blk = 0;
     int sb_begin = 0, n_sb = 0;
@@ -221,8 +237,11 @@ struct EngineProblem {
     AggLayout agg{};              // internal node order
     int n_agg = 0;
     uint32_t bc_flags = 0;        // MOS_BC_CLAMP_* of the descriptor
-    std::vector<int64_t> pdof;    // prescribed (DoF, value) list as given
+    std::vector<int64_t> pdof;    // prescribed (DoF, value) list as given (host lists)
     std::vector<double> pval;
+    int64_t n_pres = 0;           // prescribed entries
+    const int64_t *dpdof = nullptr;  // the caller's device list (MOS_BC_LIST_ON_DEVICE), else NULL
+    const double *dpval = nullptr;
     mos::DeviceArena dev;         // device copy of the prescribed list
     double dT = 0.0, rtol = 0.0;
     int max_iters = 0, iters = 0, sweeps = 0;

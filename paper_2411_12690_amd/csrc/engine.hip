@@ -120,6 +120,33 @@ struct CgStep {
 
 constexpr int CG_LW = 256;  // logical width of the scalar reduction
 
+// The step of iteration it from the sums (r,u), (r,r) and (u,A u): stop
+// when (r,r) reaches the sweep's tolerance or the iteration cap, else alpha
+// and beta of the Chronopoulos-Gear recurrence (breakdown stops with code 2).
+__device__ CgStep cg_step(const ProbState &S, int it, double gamma, double rr, double delta) {
+    CgStep o;
+    o.gamma = gamma;
+    o.rr = rr;
+    o.tol2 = it == S.seg_start ? S.rtol2 * o.rr : S.tol2;
+    o.stop = 0;
+    o.alpha = o.beta = 0.0;
+    if (o.rr <= o.tol2) {
+        o.stop = 1;
+    } else if (it - S.seg_start >= S.max_iter) {
+        o.stop = 3;
+    } else {
+        if (it == 0) {
+            o.alpha = o.gamma / delta;
+        } else {
+            const int pv = (it - 1) & 1;
+            o.beta = o.gamma / S.hist_gamma[pv];
+            o.alpha = o.gamma / (delta - o.beta * o.gamma / S.hist_alpha[pv]);
+        }
+        if (!(o.alpha > 0.0) || !isfinite(o.alpha) || !isfinite(o.beta)) o.stop = 2;
+    }
+    return o;
+}
+
 template <int NT>
 __device__ CgStep cg_scalars_block(const ProbState &S, int it, const double *pg, const double *pr,
                                    const double *pdel, double (*red)[NT]) {
@@ -204,17 +231,49 @@ __device__ __forceinline__ void cg_publish(ProbState &S, int it, const CgStep &o
 // chunk, so a captured chunk replays with the epochs of its replay).  The
 // per-block partials are double-buffered by iteration parity: iteration it
 // reads slot it & 1 (written by the previous update or the sweep start).
-__global__ __launch_bounds__(256) void k_cg_scalars(ProbState *ps, const double *pg, const double *pr,
-                                                    const double *pdel, const int *ep, int j, int cap_blk) {
-    __shared__ double red[3][CG_LW];
+// Such a problem has tens of thousands of partials, so the workgroup is
+// wide (CG_BIG lanes, each with several loads in flight); lane L sums
+// partials L, L + CG_BIG, ..., then a butterfly per wave and the waves' sums
+// in order.  Only problems above the fused size come here, so their scalars
+// always take this order.
+constexpr int CG_BIG = 1024;
+__global__ __launch_bounds__(CG_BIG) void k_cg_scalars(ProbState *ps, const double *pg, const double *pr,
+                                                       const double *pdel, const int *ep, int j, int cap_blk) {
+    __shared__ double red[3][CG_BIG / 64];
     const int epoch = ep[0] + j;
     ProbState &S = ps[blockIdx.x];
     const int active = S.active, done = S.done, fused = S.fused;  // one round trip
     if (!((active != 0) & (done == 0) & (fused == 0))) return;     // uniform over the workgroup
     const int it = epoch - S.start_epoch;
     const size_t slot = (size_t)(it & 1) * cap_blk;
-    const CgStep o = cg_scalars_block<CG_LW>(S, it, pg + slot, pr + slot, pdel, red);
-    if (threadIdx.x == 0) cg_publish(S, it, o);
+    const double *g = pg + slot, *r = pr + slot;
+    const int t = threadIdx.x;
+    double gs = 0.0, rs = 0.0, ds = 0.0;
+#pragma unroll 8
+    for (int i = S.blk_begin + t; i < S.blk_end; i += CG_BIG) {
+        gs += g[i];
+        rs += r[i];
+    }
+#pragma unroll 8
+    for (int i = S.tile_begin + t; i < S.tile_end; i += CG_BIG) ds += pdel[i];
+    for (int m = 32; m >= 1; m >>= 1) {
+        gs += __shfl_xor(gs, m);
+        rs += __shfl_xor(rs, m);
+        ds += __shfl_xor(ds, m);
+    }
+    if (t % 64 == 0) {
+        red[0][t / 64] = gs;
+        red[1][t / 64] = rs;
+        red[2][t / 64] = ds;
+    }
+    __syncthreads();
+    if (t != 0) return;
+    double sum[3];
+    for (int q = 0; q < 3; ++q) {
+        sum[q] = red[q][0];
+        for (int w = 1; w < CG_BIG / 64; ++w) sum[q] += red[q][w];
+    }
+    cg_publish(S, it, cg_step(S, it, sum[0], sum[1], sum[2]));
 }
 
 // (u, A u) over one 16x16 output tile: the tile's products times the cell
@@ -638,6 +697,13 @@ __device__ __forceinline__ void cell_scatter(T *Mc, int4 iv, int ci, int ld_slot
         if (e4[e] >= 0) Mc[(size_t)(3 * (e4[e] & MAX_SURF) + ci) * ld_slots + (e4[e] >> INC_SHIFT)] = v;
 }
 
+// The cells of a stacked array's layer above a node on a shared horizontal
+// face (inc2, after those of the node's own layer in inc: ascending cell id),
+// for the kernels that take them; -1 everywhere for one-layer arrays.
+__device__ __forceinline__ int4 incidence2(const int32_t *inc2, int64_t d) {
+    return inc2 ? reinterpret_cast<const int4 *>(inc2)[d / 3] : make_int4(-1, -1, -1, -1);
+}
+
 // Element at a 32-bit byte offset from a uniform base: lets the compiler
 // address it as scalar base + one 32-bit offset register.
 template <class T>
@@ -737,10 +803,11 @@ constexpr int CG_WIDE_MAX_BLK = 2048;
 // then the next u = M^-1 r to the cell layout and the partials of the next
 // (r,u) and (r,r).  Only x, r, p and s are stored.
 template <class T, int NT>
-__global__ __launch_bounds__(NT) void k_cgstep(const T *Y, const int32_t *inc, const uint8_t *cmask, const T *dinv,
-                                               T *x, T *r, T *p, T *s, T *Mc, int ld_slots, const int32_t *blk_prob,
-                                               ProbState *ps, double *pg, double *pr, const double *pdel,
-                                               const int *ep, int j, int cap_blk, int n_blk) {
+__global__ __launch_bounds__(NT) void k_cgstep(const T *Y, const int32_t *inc, const int32_t *inc2,
+                                               const uint8_t *cmask, const T *dinv, T *x, T *r, T *p, T *s, T *Mc,
+                                               int ld_slots, const int32_t *blk_prob, ProbState *ps, double *pg,
+                                               double *pr, const double *pdel, const int *ep, int j, int cap_blk,
+                                               int n_blk) {
     constexpr int DPT = DB / NT;
     __shared__ int go, it_sh;
     __shared__ double step[2];
@@ -756,9 +823,12 @@ __global__ __launch_bounds__(NT) void k_cgstep(const T *Y, const int32_t *inc, c
     // Only the incidence is requested before the gate resolves: blocks of
     // problems that have stopped (converged, or between refinement sweeps)
     // must not spend bandwidth on their operands.
-    int4 iv[DPT];
+    int4 iv[DPT], iv2[DPT];
 #pragma unroll
-    for (int j = 0; j < DPT; ++j) iv[j] = incidence(inc, d0 + j * NT);
+    for (int j = 0; j < DPT; ++j) {
+        iv[j] = incidence(inc, d0 + j * NT);
+        iv2[j] = incidence2(inc2, d0 + j * NT);
+    }
     const int pb = blk_prob[blk];
     if (threadIdx.x == 0) {
         int g = 0;
@@ -807,7 +877,8 @@ __global__ __launch_bounds__(NT) void k_cgstep(const T *Y, const int32_t *inc, c
         pd0[j] = p[d];
         sd[j] = s[d];
         xd[j] = x[d];
-        const T sum = cell_sum(Y, iv[j], (int)(d % 3), ld_slots);
+        T sum = cell_sum(Y, iv[j], (int)(d % 3), ld_slots);
+        if (inc2) sum += cell_sum(Y, iv2[j], (int)(d % 3), ld_slots);
         wv[j] = cmask[d] ? T(0) : sum;
     }
     double g[DPT], r2[DPT];
@@ -824,6 +895,7 @@ __global__ __launch_bounds__(NT) void k_cgstep(const T *Y, const int32_t *inc, c
         s[d] = sv;
         r[d] = rv;
         cell_scatter(Mc, iv[j], (int)(d % 3), ld_slots, un);
+        if (inc2) cell_scatter(Mc, iv2[j], (int)(d % 3), ld_slots, un);
         g[j] = (double)rv * (double)un;
         r2[j] = (double)rv * (double)rv;
     }
@@ -899,7 +971,7 @@ __device__ __forceinline__ int64_t inner_index(const ProbParams &P, int64_t node
     if (gy > A.nay - 1) gy = A.nay - 1;
     const int64_t rem = node - (int64_t)gy * A.row;
     const int wy = gy == A.nay - 1 ? A.wyl : A.wyi;
-    const int64_t per = sub_count(make_sub(A.wxi, wy, A.Z, A.sx, A.sy));
+    const int64_t per = sub_count(make_sub(A.wxi, wy, A.Z, A.sx, A.sy, A.sz));
     int gx = (int)(rem / per);
     if (gx > A.nax - 1) gx = A.nax - 1;
     const int64_t first = agg_first(A, gx, gy);
@@ -1260,13 +1332,16 @@ template <int NTH>
 __global__ __launch_bounds__(NTH) void k_coarse_setup(ProbSel sel, const int4 *box_tab, const ProbParams *pp,
                                                       const int32_t *cslot, const int32_t *sb_rom,
                                                       const void *const *kr32_tab, const uint8_t *cmask,
-                                                      const int32_t *surf, int n, int ldk, double *binv) {
+                                                      const int32_t *surf, int n, int ldk, double *binv,
+                                                      const int32_t *agg_gen) {
     constexpr int NW = NTH / 64;
     const int bs = blockIdx.x, a = blockIdx.y;
     const int pb = box_tab[bs].w;
     if (pb < 0 || !selected(sel, pb)) return;
     const ProbParams &P = pp[pb];
-    if (P.tab_coarse) return;
+    // Clamp-only problems take the table; problems with a prescribed list
+    // take it for the aggregates k_coarse_agg_tab marked tabulated.
+    if (P.tab_coarse == 1 || (P.tab_coarse == 2 && agg_gen[(size_t)bs * MAXA + a] == 0)) return;
     const AggLayout &A = P.agg;
     const int b = bs - P.box_begin, gx = b % A.nax, gy = b / A.nax;
     const int bx0 = gx * A.cx, bx1 = gx == A.nax - 1 ? P.lat.Nx : bx0 + A.cx;
@@ -1490,7 +1565,9 @@ __device__ __forceinline__ int agg_column(const AggLayout &A, int Nx, int64_t I)
 // face), T its shift from the cell corner to the aggregate corner.
 __global__ __launch_bounds__(64) void k_coarse_agg_tab(ProbSel sel, const int4 *box_tab, const ProbParams *pp,
                                                        const int32_t *cslot, const int32_t *sb_rom,
-                                                       const double *ctab, double *binv) {
+                                                       const double *ctab, const uint8_t *cmask,
+                                                       const int32_t *surf, int n, double *binv,
+                                                       int32_t *agg_gen) {
     const int bs = blockIdx.x, a = blockIdx.y;
     const int pb = box_tab[bs].w;
     if (pb < 0 || !selected(sel, pb)) return;
@@ -1505,11 +1582,48 @@ __global__ __launch_bounds__(64) void k_coarse_agg_tab(ProbSel sel, const int4 *
     const int t = threadIdx.x;
     if (a >= na) {
         if (t < 36) out[t] = 0.0;
+        if (t == 0) agg_gen[(size_t)bs * MAXA + a] = 0;
         return;
     }
     const int ax0 = bx0 + a * AGG_C, ax1 = min(ax0 + AGG_C, bx1);
     const int Nx = P.lat.Nx, sx = A.sx, sy = A.sy;
-    const int flags = P.clamp & 3;
+    int flags = P.clamp & 3;
+    if (P.tab_coarse == 2) {
+        // Problems with a prescribed list: the table applies to this
+        // aggregate when its DoFs in the touching cells are constrained
+        // exactly on whole bottom / top planes (each plane all or none) and
+        // nowhere else; otherwise the general kernel builds B_a.
+        int c0 = 0, n0 = 0, cT = 0, nT = 0, cM = 0;
+        for (int cy = max(by0 - 1, 0); cy < by1; ++cy)
+            for (int cx = max(ax0 - 1, 0); cx < ax1; ++cx)
+                for (int k = t; k < n; k += 64) {
+                    const int sn = k / 3;
+                    const int64_t I = (int64_t)cx * sx + surf[3 * sn], J = (int64_t)cy * sy + surf[3 * sn + 1];
+                    const int Kz = surf[3 * sn + 2];
+                    if (agg_column(A, Nx, I) != gx * MAXA + a || agg_y(A, J) != gy) continue;
+                    const bool con = cmask[P.d0 + 3 * agg_encode(A, I, J, Kz) + k % 3] != 0;
+                    if (Kz == 0) {
+                        ++n0;
+                        c0 += con;
+                    } else if (Kz == A.Z - 1) {
+                        ++nT;
+                        cT += con;
+                    } else {
+                        cM += con;
+                    }
+                }
+        for (int o = 32; o >= 1; o >>= 1) {
+            c0 += __shfl_xor(c0, o);
+            n0 += __shfl_xor(n0, o);
+            cT += __shfl_xor(cT, o);
+            nT += __shfl_xor(nT, o);
+            cM += __shfl_xor(cM, o);
+        }
+        const bool ok = cM == 0 && (c0 == 0 || c0 == n0) && (cT == 0 || cT == nT);
+        if (t == 0) agg_gen[(size_t)bs * MAXA + a] = ok ? 0 : 1;
+        if (!ok) return;
+        flags = (c0 > 0 ? MOS_BC_CLAMP_BOTTOM : 0) | (cT > 0 ? MOS_BC_CLAMP_TOP : 0);
+    }
     __shared__ double Bfull[36];
     if (t < 21) {
         // Term q = (m1, m2), m1 <= m2, of the symmetric 6x6.
@@ -1617,9 +1731,12 @@ __global__ void k_setup_dofs(ProbSel sel, const int32_t *blk_prob, const ProbPar
 }
 
 // Incidence entries of the selected problems' nodes reset to -1.
-__global__ void k_clear_incidence(ProbSel sel, const int32_t *blk_prob, int32_t *inc, int64_t n) {
+__global__ void k_clear_incidence(ProbSel sel, const int32_t *blk_prob, int32_t *inc, int32_t *inc2, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        if (selected(sel, blk_prob[(i / 4 * 3) / DB])) inc[i] = -1;
+        if (selected(sel, blk_prob[(i / 4 * 3) / DB])) {
+            inc[i] = -1;
+            inc2[i] = -1;
+        }
 }
 
 // Node -> (slot, surface node) incidence of the selected problems, entries
@@ -1627,7 +1744,7 @@ __global__ void k_clear_incidence(ProbSel sel, const int32_t *blk_prob, int32_t 
 // 2 or 4 cells; the rank of cell (cx, cy) among them follows from which side
 // of the face it lies.
 __global__ void k_incidence_sel(ProbSel sel, const int32_t *sb_prob, const ProbParams *pp, const int32_t *perm,
-                                int32_t *inc, uint32_t *lc, int32_t *cslot, const uint8_t *cmask,
+                                int32_t *inc, int32_t *inc2, uint32_t *lc, int32_t *cslot, const uint8_t *cmask,
                                 const int32_t *surf, int S, int64_t n_slots) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n_slots * S) return;
@@ -1637,13 +1754,14 @@ __global__ void k_incidence_sel(ProbSel sel, const int32_t *sb_prob, const ProbP
     const int32_t cell = perm[slot];
     if (cell < 0) return;
     const Lattice &L = pp[p].lat;
-    const int cx = cell % L.Nx, cy = cell / L.Nx;
+    const int cx = cell % L.Nx, cy = (cell / L.Nx) % L.Ny, cz = cell / (L.Nx * L.Ny);
     const int i = surf[3 * s], j = surf[3 * s + 1], k = surf[3 * s + 2];
     const AggLayout &A = pp[p].agg;
     const int64_t I = (int64_t)cx * (L.nx - 1) + i, J = (int64_t)cy * (L.ny - 1) + j;
-    const int64_t node = agg_encode(A, I, J, k);
+    const int K = cz * (L.nz - 1) + k;
+    const int64_t node = agg_encode(A, I, J, K);
     if (s == 0) cslot[(int64_t)pp[p].sb_begin * 16 + cell] = slot;
-    {
+    if (pp[p].box_begin >= 0) {
         // Aggregate-local coordinates of the node (two-level preconditioner).
         const int gx = agg_x(A, I), gy = agg_y(A, J);
         const int cells = gx == A.nax - 1 ? L.Nx - A.cx * (A.nax - 1) : A.cx;
@@ -1658,7 +1776,10 @@ __global__ void k_incidence_sel(ProbSel sel, const int32_t *sb_prob, const ProbP
     const bool shx = (i == 0 && cx > 0) || (i == L.nx - 1 && cx < L.Nx - 1);
     const int ux = (i == 0 && cx > 0) ? 1 : 0;
     const int uy = (j == 0 && cy > 0) ? 1 : 0;
-    inc[(pp[p].d0 / 3 + node) * 4 + uy * (shx ? 2 : 1) + ux] = (slot << INC_SHIFT) | s;
+    // The bottom face of a block above the first layer is the top face of
+    // the block below: that node's cells of this (upper) layer go to inc2.
+    int32_t *dst = (k == 0 && cz > 0) ? inc2 : inc;
+    dst[(pp[p].d0 / 3 + node) * 4 + uy * (shx ? 2 : 1) + ux] = (slot << INC_SHIFT) | s;
 }
 
 // b_raw = dT * sum over the cells around each DoF of b_r(type), and the
@@ -1666,15 +1787,16 @@ __global__ void k_incidence_sel(ProbSel sel, const int32_t *sb_prob, const ProbP
 template <class T>
 __global__ void k_rhs_diag(ProbSel sel, const int32_t *blk_prob, const ProbParams *pp,
                            const double *const *br_tab, const void *const *kr64_tab, const int32_t *sb_rom,
-                           const int32_t *inc, const uint8_t *cmask, double *b, T *dinv, int ldk) {
+                           const int32_t *inc, const int32_t *inc2, const uint8_t *cmask, double *b, T *dinv,
+                           int ldk) {
     const int p = blk_prob[blockIdx.x];
     if (!selected(sel, p)) return;
     const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x;
-    const int4 iv = incidence(inc, d);
-    const int e4[4] = {iv.x, iv.y, iv.z, iv.w};
+    const int4 iv = incidence(inc, d), iv2 = incidence2(inc2, d);
+    const int e4[8] = {iv.x, iv.y, iv.z, iv.w, iv2.x, iv2.y, iv2.z, iv2.w};
     const int ci = (int)(d % 3);
     double sb = 0.0, sd = 0.0;
-    for (int e = 0; e < 4; ++e)
+    for (int e = 0; e < 8; ++e)
         if (e4[e] >= 0) {
             const int rom = sb_rom[(e4[e] >> INC_SHIFT) / 16];
             const int k = 3 * (e4[e] & MAX_SURF) + ci;
@@ -1690,11 +1812,12 @@ __global__ void k_rhs_diag(ProbSel sel, const int32_t *blk_prob, const ProbParam
 }
 
 // FP64 vector of the selected problems to the cell-major layout.
-__global__ void k_scatter_sel(ProbSel sel, const int32_t *blk_prob, const double *v, const int32_t *inc, double *Mc,
-                              int ld_slots) {
+__global__ void k_scatter_sel(ProbSel sel, const int32_t *blk_prob, const double *v, const int32_t *inc,
+                              const int32_t *inc2, double *Mc, int ld_slots) {
     if (!selected(sel, blk_prob[blockIdx.x])) return;
     const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x;
     cell_scatter(Mc, incidence(inc, d), (int)(d % 3), ld_slots, v[d]);
+    if (inc2) cell_scatter(Mc, incidence2(inc2, d), (int)(d % 3), ld_slots, v[d]);
 }
 
 // True residual of the lifted system r = b - A x (0 on constrained DoFs),
@@ -1702,11 +1825,12 @@ __global__ void k_scatter_sel(ProbSel sel, const int32_t *blk_prob, const double
 // ||r||^2 and, with `lift`, of ||b_l||^2 (b_l = g on constrained DoFs,
 // b - A g elsewhere; at set-up x = g).
 __global__ void k_residual_sel(ProbSel sel, const int32_t *blk_prob, const double *Y, const int32_t *inc,
-                               const double *b_raw, const uint8_t *cmask, const double *g, double *r, double *part_r,
-                               double *part_b, int lift, int ld_slots) {
+                               const int32_t *inc2, const double *b_raw, const uint8_t *cmask, const double *g,
+                               double *r, double *part_r, double *part_b, int lift, int ld_slots) {
     if (!selected(sel, blk_prob[blockIdx.x])) return;
     const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x;
-    const double ax = cell_sum(Y, incidence(inc, d), (int)(d % 3), ld_slots);
+    double ax = cell_sum(Y, incidence(inc, d), (int)(d % 3), ld_slots);
+    if (inc2) ax += cell_sum(Y, incidence2(inc2, d), (int)(d % 3), ld_slots);
     const bool c = cmask[d];
     const double v = c ? 0.0 : b_raw[d] - ax;
     r[d] = v;
@@ -1778,8 +1902,8 @@ __global__ void k_prob_stop_list(PidList L, ProbState *ps) {
 // iteration's cell GEMM then gives w = A u and (u, A u).
 template <class T>
 __global__ void k_cgstart_sel(ProbSel sel, const int32_t *blk_prob, const SweepParams *sp, const ProbState *ps,
-                              const double *r64, const T *dinv, const int32_t *inc, T *x, T *r, T *p, T *s, T *Mc,
-                              int ld_slots, double *pg, double *pr, int cap_blk) {
+                              const double *r64, const T *dinv, const int32_t *inc, const int32_t *inc2, T *x, T *r,
+                              T *p, T *s, T *Mc, int ld_slots, double *pg, double *pr, int cap_blk) {
     const int pid = blk_prob[blockIdx.x];
     if (!selected(sel, pid)) return;
     const int64_t d = (int64_t)blockIdx.x * DB + threadIdx.x;
@@ -1797,6 +1921,7 @@ __global__ void k_cgstart_sel(ProbSel sel, const int32_t *blk_prob, const SweepP
         s[d] = 0;
     }
     cell_scatter(Mc, incidence(inc, d), (int)(d % 3), ld_slots, uv);
+    if (inc2) cell_scatter(Mc, incidence2(inc2, d), (int)(d % 3), ld_slots, uv);
     double g = (double)rv * (double)uv, r2 = (double)rv * (double)rv, z = 0.0;
     block_sum3(g, r2, z);
     if (threadIdx.x == 0) {
@@ -1843,9 +1968,19 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
 
 // Prescribed (DoF, value) list, a later entry overriding an earlier one: the
 // largest entry index per DoF wins, then only that entry is applied.
-__global__ void k_prescribe_last(const int64_t *dof, int64_t n, int32_t *last) {
+// Last entry of the list for each DoF (a later entry overrides an earlier
+// one).  Entries with a DoF outside [0, n_dofs) or a non-finite value are
+// left out and raise *bad (lists checked on the host never hold one).
+__global__ void k_prescribe_last(const int64_t *dof, const double *val, int64_t n, int64_t n_dofs, int32_t *last,
+                                 int32_t *bad) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) atomicMax(&last[dof[i]], (int32_t)i);
+    if (i >= n) return;
+    const int64_t d = dof[i];
+    if (d < 0 || d >= n_dofs || !isfinite(val[i])) {
+        *bad = 1;
+        return;
+    }
+    atomicMax(&last[d], (int32_t)i);
 }
 
 // DoF of the internal order for a DoF of the caller's order.
@@ -1856,10 +1991,10 @@ __device__ __forceinline__ int64_t internal_dof(const SubLattice &W, const AggLa
 }
 
 // Prescribed values applied (the list holds DoFs of the caller's order).
-__global__ void k_prescribe(const int64_t *dof, const double *val, int64_t n, const int32_t *last, uint8_t *cmask,
-                            double *g, double *x64, int64_t d0, SubLattice W, AggLayout A) {
+__global__ void k_prescribe(const int64_t *dof, const double *val, int64_t n, int64_t n_dofs, const int32_t *last,
+                            uint8_t *cmask, double *g, double *x64, int64_t d0, SubLattice W, AggLayout A) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n || last[dof[i]] != (int32_t)i) return;
+    if (i >= n || dof[i] < 0 || dof[i] >= n_dofs || last[dof[i]] != (int32_t)i) return;
     const int64_t d = d0 + internal_dof(W, A, dof[i]);
     cmask[d] = 1;
     g[d] = val[i];
@@ -1885,9 +2020,9 @@ __global__ void k_gather_index(int32_t *gidx, const int32_t *perm, int64_t n_slo
         return;
     }
     const int s = k / 3;
-    const int cx = cell % L.Nx, cy = cell / L.Nx;
+    const int cx = cell % L.Nx, cy = (cell / L.Nx) % L.Ny, cz = cell / (L.Nx * L.Ny);
     const int64_t node = node_id(L, (int64_t)cx * (L.nx - 1) + surf[3 * s], (int64_t)cy * (L.ny - 1) + surf[3 * s + 1],
-                                 surf[3 * s + 2]);
+                                 (int64_t)cz * (L.nz - 1) + surf[3 * s + 2]);
     gidx[idx] = (int32_t)(3 * node + k % 3);
 }
 
@@ -1947,11 +2082,13 @@ int problem_blocks(int64_t n_dofs, int n_agg) {
 
 mos_status prepare_problem(mos_engine e, const mos_array_desc *d, EngineProblem *P) {
     const mos_cell_desc &cd = e->roms[0]->desc;
-    const Lattice L = make_lattice(d->nx_cells, d->ny_cells, cd.interp[0], cd.interp[1], cd.interp[2]);
+    const int Nz = d->nz_cells < 1 ? 1 : d->nz_cells;
+    const Lattice L = make_lattice(d->nx_cells, d->ny_cells, cd.interp[0], cd.interp[1], cd.interp[2], Nz);
     P->lat = L;
     P->Nx = d->nx_cells;
     P->Ny = d->ny_cells;
-    P->n_cells = (int64_t)P->Nx * P->Ny;
+    P->Nz = Nz;
+    P->n_cells = (int64_t)P->Nx * P->Ny * Nz;
     P->n_nodes = L.n_nodes;
     P->n_dofs = 3 * L.n_nodes;
     P->dT = d->delta_T;
@@ -1966,14 +2103,21 @@ mos_status prepare_problem(mos_engine e, const mos_array_desc *d, EngineProblem 
         set_error("more than 2^31-1 prescribed entries");
         return MOS_EINVAL;
     }
-    P->pdof.assign(d->prescribed_dof, d->prescribed_dof + d->n_prescribed);
-    P->pval.assign(d->prescribed_value, d->prescribed_value + d->n_prescribed);
-    for (int64_t i = 0; i < d->n_prescribed; ++i)
-        if (P->pdof[i] < 0 || P->pdof[i] >= P->n_dofs || !std::isfinite(P->pval[i])) {
-            set_error("prescribed entry %lld: DoF %lld outside [0, %lld) or value not finite", (long long)i,
-                      (long long)P->pdof[i], (long long)P->n_dofs);
-            return MOS_EINVAL;
-        }
+    P->n_pres = d->n_prescribed;
+    if (d->bc_flags & MOS_BC_LIST_ON_DEVICE) {
+        // Device-resident list: read at set-up and checked there.
+        P->dpdof = d->n_prescribed ? d->prescribed_dof : nullptr;
+        P->dpval = d->n_prescribed ? d->prescribed_value : nullptr;
+    } else {
+        P->pdof.assign(d->prescribed_dof, d->prescribed_dof + d->n_prescribed);
+        P->pval.assign(d->prescribed_value, d->prescribed_value + d->n_prescribed);
+        for (int64_t i = 0; i < d->n_prescribed; ++i)
+            if (P->pdof[i] < 0 || P->pdof[i] >= P->n_dofs || !std::isfinite(P->pval[i])) {
+                set_error("prescribed entry %lld: DoF %lld outside [0, %lld) or value not finite", (long long)i,
+                          (long long)P->pdof[i], (long long)P->n_dofs);
+                return MOS_EINVAL;
+            }
+    }
     if (P->bc_flags == 0 && d->n_prescribed == 0) {
         set_error("array has no constrained DoF: the reduced stiffness is singular (rigid motions)");
         return MOS_ESINGULAR;
@@ -1989,18 +2133,20 @@ mos_status prepare_problem(mos_engine e, const mos_array_desc *d, EngineProblem 
     std::vector<int> next(n_roms);
     for (int t = 0; t < n_roms; ++t) next[t] = P->seg[t] * 16;
     // Within a type, slots follow the aggregates (cells of one aggregate in
-    // neighbouring slots), as the DoFs do: the update's gathers and scatters
-    // for an aggregate then fall in a few cache lines per cell-layout row.
+    // neighbouring slots, its layers one after another), as the DoFs do: the
+    // update's gathers and scatters for an aggregate then fall in a few cache
+    // lines per cell-layout row.
     const AggLayout &A = P->agg;
     for (int gy = 0; gy < A.nay; ++gy)
         for (int gx = 0; gx < A.nax; ++gx) {
             const int cy1 = gy == A.nay - 1 ? P->Ny : (gy + 1) * A.cy;
             const int cx1 = gx == A.nax - 1 ? P->Nx : (gx + 1) * A.cx;
-            for (int cy = gy * A.cy; cy < cy1; ++cy)
-                for (int cx = gx * A.cx; cx < cx1; ++cx) {
-                    const int64_t c = (int64_t)cy * P->Nx + cx;
-                    P->perm[next[d->cell_type[c]]++] = (int32_t)c;
-                }
+            for (int cz = 0; cz < Nz; ++cz)
+                for (int cy = gy * A.cy; cy < cy1; ++cy)
+                    for (int cx = gx * A.cx; cx < cx1; ++cx) {
+                        const int64_t c = ((int64_t)cz * P->Ny + cy) * P->Nx + cx;
+                        P->perm[next[d->cell_type[c]]++] = (int32_t)c;
+                    }
         }
     P->sb_rom.assign(P->n_sb, -1);
     for (int t = 0; t < n_roms; ++t)
@@ -2051,7 +2197,7 @@ mos_status residual_batch(mos_engine e, const Batch &B, bool lift) {
     hipStream_t st = e->ctx->stream;
     const int hw_blk = e->blk.high, hw_sb = e->sbs.high;
     hipLaunchKernelGGL(k_scatter_sel, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
-                       (const double *)e->x64, (const int32_t *)e->inc, e->Mc64, e->ld_slots);
+                       (const double *)e->x64, (const int32_t *)e->inc, (const int32_t *)(e->stacked ? e->inc2 : nullptr), e->Mc64, e->ld_slots);
     // The K_r-stationary variants share one FP64 product here (operand tiles
     // in LDS), so all of them give the same residual bits.
     if (e->gemm_rows)
@@ -2063,7 +2209,7 @@ mos_status residual_batch(mos_engine e, const Batch &B, bool lift) {
                            (const void *const *)e->kr64_tab, e->sb_rom, e->sb_prob, (const double *)e->Mc64, e->Y64,
                            e->ldk, e->ld_slots, 0, hw_sb, 2, (const ProbState *)e->ps, (double *)nullptr, B.sel);
     hipLaunchKernelGGL(k_residual_sel, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
-                       (const double *)e->Y64, (const int32_t *)e->inc, (const double *)e->b_raw,
+                       (const double *)e->Y64, (const int32_t *)e->inc, (const int32_t *)(e->stacked ? e->inc2 : nullptr), (const double *)e->b_raw,
                        (const uint8_t *)e->cmask, (const double *)e->g, e->r64, e->pr64, e->pd, lift ? 1 : 0,
                        e->ld_slots);
     hipLaunchKernelGGL(k_reduce_list, dim3(B.list.n), dim3(64), 0, st, B.list, (const ProbParams *)e->pp,
@@ -2081,6 +2227,9 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
     hipStream_t st = e->ctx->stream;
     MOS_TRY(mirror_wait(e));
     int sb_lo = INT32_MAX, sb_hi = 0;
+    // From the first stacked array on, the Jacobi kernels also read the
+    // incidence of the layer above (all -1 for one-layer arrays).
+    for (EngineProblem *P : adm) e->stacked |= P->Nz > 1 ? 1 : 0;
     for (EngineProblem *P : adm) {
         ProbParams &H = e->pp_host[P->pid];
         const Lattice &L = P->lat;
@@ -2104,7 +2253,7 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
         }
         // Clamped faces only: every cell of a type has the same free DoFs, so
         // its coarse terms come from the per-type table.
-        H.tab_coarse = (e->precond && P->pdof.empty()) ? 1 : 0;
+        H.tab_coarse = !e->precond ? 0 : P->n_pres == 0 ? 1 : e->coarse_table ? 2 : 0;
         H.dT = P->dT;
         H.lat = L;
         H.blk_begin = P->blk_begin;
@@ -2134,51 +2283,61 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
     hipLaunchKernelGGL(k_setup_dofs, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
                        (const ProbParams *)e->pp, e->cmask, e->g, e->x64, e->inc);
     for (EngineProblem *P : adm) {
-        const int64_t np = (int64_t)P->pdof.size();
+        const int64_t np = P->n_pres;
         if (np == 0) continue;
         const int64_t d0 = (int64_t)P->blk_begin * DB;
-        P->dev.ctx = e->ctx;
-        int64_t *pdof = nullptr;
-        double *pval = nullptr;
-        MOS_TRY(P->dev.alloc_n(np, &pdof));
-        MOS_TRY(P->dev.alloc_n(np, &pval));
-        MOS_HIP(hipMemcpyAsync(pdof, P->pdof.data(), np * 8, hipMemcpyHostToDevice, st));
-        MOS_HIP(hipMemcpyAsync(pval, P->pval.data(), np * 8, hipMemcpyHostToDevice, st));
+        const int64_t *pdof = P->dpdof;
+        const double *pval = P->dpval;
+        if (!pdof) {
+            // Host list: one device copy for the problem's lifetime.
+            P->dev.ctx = e->ctx;
+            int64_t *dd = nullptr;
+            double *dv = nullptr;
+            MOS_TRY(P->dev.alloc_n(np, &dd));
+            MOS_TRY(P->dev.alloc_n(np, &dv));
+            MOS_HIP(hipMemcpyAsync(dd, P->pdof.data(), np * 8, hipMemcpyHostToDevice, st));
+            MOS_HIP(hipMemcpyAsync(dv, P->pval.data(), np * 8, hipMemcpyHostToDevice, st));
+            pdof = dd;
+            pval = dv;
+        }
         int32_t *last = e->inc + d0 / 3 * 4;
-        hipLaunchKernelGGL(k_prescribe_last, dim3(ceil_div(np, 256)), dim3(256), 0, st, (const int64_t *)pdof, np,
-                           last);
-        hipLaunchKernelGGL(k_prescribe, dim3(ceil_div(np, 256)), dim3(256), 0, st, (const int64_t *)pdof,
-                           (const double *)pval, np, (const int32_t *)last, e->cmask, e->g, e->x64, d0,
-                           whole_lattice(P->lat), P->agg);
+        hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, (uint32_t *)(e->pres_bad + P->pid), (int64_t)1, 0u);
+        hipLaunchKernelGGL(k_prescribe_last, dim3(ceil_div(np, 256)), dim3(256), 0, st, pdof, pval, np, P->n_dofs,
+                           last, e->pres_bad + P->pid);
+        hipLaunchKernelGGL(k_prescribe, dim3(ceil_div(np, 256)), dim3(256), 0, st, pdof, pval, np, P->n_dofs,
+                           (const int32_t *)last, e->cmask, e->g, e->x64, d0, whole_lattice(P->lat), P->agg);
     }
     const int64_t n_inc = (int64_t)hw_blk * DB / 3 * 4;
     hipLaunchKernelGGL(k_clear_incidence, dim3((unsigned)std::min<int64_t>(ceil_div(n_inc, 256), 4096)), dim3(256),
-                       0, st, B.sel, (const int32_t *)e->blk_prob, e->inc, n_inc);
+                       0, st, B.sel, (const int32_t *)e->blk_prob, e->inc, e->inc2, n_inc);
     const int64_t n_slots = (int64_t)hw_sb * 16;
     hipLaunchKernelGGL(k_zero_padding, dim3(ceil_div(n_slots * e->ldk, 256)), dim3(256), 0, st, B.sel,
                        (const int32_t *)e->sb_prob, (const int32_t *)e->perm, (uint8_t *)e->Mc,
                        e->precision == MOS_MIXED ? 4 : 8, e->ld_slots, e->ldk, n_slots);
     hipLaunchKernelGGL(k_incidence_sel, dim3(ceil_div(n_slots * e->S, 256)), dim3(256), 0, st, B.sel,
                        (const int32_t *)e->sb_prob, (const ProbParams *)e->pp, (const int32_t *)e->perm, e->inc,
-                       e->lc, e->cslot, (const uint8_t *)e->cmask, (const int32_t *)e->surf, e->S, n_slots);
+                       e->inc2, e->lc, e->cslot, (const uint8_t *)e->cmask, (const int32_t *)e->surf, e->S, n_slots);
     if (e->precision == MOS_MIXED)
         hipLaunchKernelGGL(k_rhs_diag<float>, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
                            (const ProbParams *)e->pp, (const double *const *)e->br_tab,
                            (const void *const *)e->kr64_tab, (const int32_t *)e->sb_rom, (const int32_t *)e->inc,
-                           (const uint8_t *)e->cmask, e->b_raw, (float *)e->v[VDINV], e->ldk);
+                           (const int32_t *)(e->stacked ? e->inc2 : nullptr), (const uint8_t *)e->cmask, e->b_raw, (float *)e->v[VDINV], e->ldk);
     else
         hipLaunchKernelGGL(k_rhs_diag<double>, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
                            (const ProbParams *)e->pp, (const double *const *)e->br_tab,
                            (const void *const *)e->kr64_tab, (const int32_t *)e->sb_rom, (const int32_t *)e->inc,
-                           (const uint8_t *)e->cmask, e->b_raw, (double *)e->v[VDINV], e->ldk);
+                           (const int32_t *)(e->stacked ? e->inc2 : nullptr), (const uint8_t *)e->cmask, e->b_raw, (double *)e->v[VDINV], e->ldk);
     if (e->precond) {
         bool any_tab = false, any_gen = false;
         for (EngineProblem *P : adm) {
             const ProbParams &H = e->pp_host[P->pid];
             any_tab |= H.tab_coarse != 0;
-            any_gen |= H.tab_coarse == 0;
-            const int f = H.clamp & 3;
-            if (H.tab_coarse && !((e->ctab_built >> f) & 1)) {
+            any_gen |= H.tab_coarse != 1;
+            // Clamp-only problems need the table of their flags; problems
+            // with a prescribed list may use any of the four.
+            for (int f = 0; f < 4; ++f) {
+                const bool need = (H.tab_coarse == 1 && f == (H.clamp & 3)) || H.tab_coarse == 2;
+                if (!need || ((e->ctab_built >> f) & 1)) continue;
                 TypeSpacing hs{};
                 for (size_t t = 0; t < e->roms.size(); ++t) {
                     const mos_cell_desc &cd = e->roms[t]->desc;
@@ -2198,22 +2357,27 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
                 e->ctab_built |= 1 << f;
             }
         }
+        // The tabulated aggregates first: for problems with a prescribed list
+        // they mark which aggregates the general kernel still has to build.
+        if (any_tab)
+            hipLaunchKernelGGL(k_coarse_agg_tab, dim3(e->boxes.high, MAXA), dim3(64), 0, st, B.sel,
+                               (const int4 *)e->box_tab, (const ProbParams *)e->pp, (const int32_t *)e->cslot,
+                               (const int32_t *)e->sb_rom, (const double *)e->ctab, (const uint8_t *)e->cmask,
+                               (const int32_t *)e->surf, e->n, e->binv, e->agg_gen);
         if (any_gen) {
             if (e->n <= 256)
                 hipLaunchKernelGGL(k_coarse_setup<256>, dim3(e->boxes.high, MAXA), dim3(256), 0, st, B.sel,
                                    (const int4 *)e->box_tab, (const ProbParams *)e->pp, (const int32_t *)e->cslot,
                                    (const int32_t *)e->sb_rom, (const void *const *)e->kr32_tab,
-                                   (const uint8_t *)e->cmask, (const int32_t *)e->surf, e->n, e->ldk, e->binv);
+                                   (const uint8_t *)e->cmask, (const int32_t *)e->surf, e->n, e->ldk, e->binv,
+                                   (const int32_t *)e->agg_gen);
             else
                 hipLaunchKernelGGL(k_coarse_setup<512>, dim3(e->boxes.high, MAXA), dim3(512), 0, st, B.sel,
                                    (const int4 *)e->box_tab, (const ProbParams *)e->pp, (const int32_t *)e->cslot,
                                    (const int32_t *)e->sb_rom, (const void *const *)e->kr32_tab,
-                                   (const uint8_t *)e->cmask, (const int32_t *)e->surf, e->n, e->ldk, e->binv);
+                                   (const uint8_t *)e->cmask, (const int32_t *)e->surf, e->n, e->ldk, e->binv,
+                                   (const int32_t *)e->agg_gen);
         }
-        if (any_tab)
-            hipLaunchKernelGGL(k_coarse_agg_tab, dim3(e->boxes.high, MAXA), dim3(64), 0, st, B.sel,
-                               (const int4 *)e->box_tab, (const ProbParams *)e->pp, (const int32_t *)e->cslot,
-                               (const int32_t *)e->sb_rom, (const double *)e->ctab, e->binv);
     }
     MOS_LAUNCH_CHECK();
     // At set-up x = g, so one product A g gives both ||b_l|| and the residual.
@@ -2242,8 +2406,8 @@ mos_status start_batch(mos_engine e, const Batch &B) {
     else
         hipLaunchKernelGGL(k_cgstart_sel<T>, dim3(hw_blk), dim3(DB), 0, st, B.sel, (const int32_t *)e->blk_prob,
                            (const SweepParams *)e->sp, (const ProbState *)e->ps, (const double *)e->r64,
-                           (const T *)V[VDINV], (const int32_t *)e->inc, V[VX], V[VR], V[VP], V[VS], Mc,
-                           e->ld_slots, e->pg, e->pr, e->cap_blk);
+                           (const T *)V[VDINV], (const int32_t *)e->inc, (const int32_t *)(e->stacked ? e->inc2 : nullptr), V[VX], V[VR], V[VP], V[VS],
+                           Mc, e->ld_slots, e->pg, e->pr, e->cap_blk);
     MOS_LAUNCH_CHECK();
     (void)hw_sb;
     (void)Y;
@@ -2348,11 +2512,21 @@ mos_status decide_and_start(mos_engine e, const std::vector<EngineProblem *> &pr
     hipStream_t st = e->ctx->stream;
     const int hw_p = e->pids.high;
     std::vector<double> r2(hw_p), b2(hw_p);
+    std::vector<int32_t> bad(hw_p, 0);
+    bool any_dev_list = false;
+    for (EngineProblem *P : probs) any_dev_list |= P->dpdof != nullptr && P->last_res2 < 0.0;
     MOS_HIP(hipMemcpyAsync(r2.data(), e->res2, hw_p * 8, hipMemcpyDeviceToHost, st));
     MOS_HIP(hipMemcpyAsync(b2.data(), e->bb2, hw_p * 8, hipMemcpyDeviceToHost, st));
+    if (any_dev_list) MOS_HIP(hipMemcpyAsync(bad.data(), e->pres_bad, hw_p * 4, hipMemcpyDeviceToHost, st));
     MOS_HIP(hipStreamSynchronize(st));
     Batch S;
     for (EngineProblem *P : probs) {
+        if (P->dpdof && P->last_res2 < 0.0 && bad[P->pid]) {
+            P->state = 3;
+            P->status = MOS_EINVAL;
+            P->error = "a device-resident prescribed entry has a DoF outside [0, n_dofs) or a non-finite value";
+            continue;
+        }
         bool start = false;
         MOS_TRY(decide(e, P, r2[P->pid], b2[P->pid], &start));
         if (start) S.add(P->pid);
@@ -2374,6 +2548,11 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     const int ldk = e->ldk;
     const int64_t dofs = std::max<int64_t>(round_up(cap_dofs, DOF_ALIGN), DOF_ALIGN);
     const int64_t slots = std::max<int64_t>(round_up(cap_slots, 16), 16);
+    if (!slots_fit(slots)) {
+        set_error("%lld cell slots exceed the engine's limit of %lld (slot and surface node share one int32)",
+                  (long long)slots, (long long)MAX_SLOTS);
+        return MOS_EINVAL;
+    }
     e->cap_blk = (int)(dofs / DB);
     e->cap_sb = (int)(slots / 16);
     e->ld_slots = (int)slots;
@@ -2389,6 +2568,7 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     MOS_TRY(m.alloc_n(dofs, &e->r64));
     MOS_TRY(m.alloc_n(dofs, &e->cmask));
     MOS_TRY(m.alloc_n(dofs / 3 * 4, &e->inc));
+    MOS_TRY(m.alloc_n(dofs / 3 * 4, &e->inc2));
     MOS_TRY(m.alloc_n(e->cap_blk, &e->blk_prob));
     MOS_TRY(m.alloc_n(2 * (size_t)e->cap_blk, &e->pg));  // two parity slots
     MOS_TRY(m.alloc_n(e->cap_blk, &e->pd));
@@ -2403,11 +2583,13 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     MOS_TRY(m.alloc_n(e->cap_blk, &e->box_tab));
     MOS_TRY(m.alloc_n((size_t)e->cap_blk * MAXA * 36, &e->binv));
     MOS_TRY(m.alloc_n((size_t)e->cap_blk * MAXA * 6, &e->cc));
+    MOS_TRY(m.alloc_n((size_t)e->cap_blk * MAXA, &e->agg_gen));
     MOS_TRY(m.alloc_n((size_t)MAX_TYPES * 4 * 4 * 4 * 21, &e->ctab));
     MOS_TRY(m.alloc_n(MAX_PROBS, &e->ps));
     MOS_TRY(m.alloc_n(1, &e->epoch_dev));
     MOS_TRY(m.alloc_n(MAX_PROBS, &e->res2));
     MOS_TRY(m.alloc_n(MAX_PROBS, &e->bb2));
+    MOS_TRY(m.alloc_n(MAX_PROBS, &e->pres_bad));
     if (hipHostMalloc((void **)&e->host_scratch, 8 * sizeof(double), hipHostMallocDefault) !=
         hipSuccess) {
         (void)hipGetLastError();
@@ -2470,6 +2652,7 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
     // before they know whether the block is active, so it never holds
     // anything but -1 or a valid slot.
     fill32(e->inc, dofs / 3 * 4, 0xffffffffu);
+    fill32(e->inc2, dofs / 3 * 4, 0xffffffffu);
     fill32(e->blk_prob, e->cap_blk, 0xffffffffu);
     fill32(e->sb_rom, e->cap_sb, 0xffffffffu);
     fill32(e->sb_prob, e->cap_sb, 0xffffffffu);  // -1: no owner (batched phases select by owner)
@@ -2519,10 +2702,10 @@ int64_t largest_box(mos_engine e, bool *fits, int *width) {
     const mos_cell_desc &cd = e->roms[0]->desc;
     const int sx = cd.interp[0] - 1, sy = cd.interp[1] - 1, nz = cd.interp[2];
     int w = BOX_CX;
-    int64_t max_nodes = sub_count(make_sub(w * sx + 1, AGG_C * sy + 1, nz, sx, sy));
+    int64_t max_nodes = sub_count(make_sub(w * sx + 1, AGG_C * sy + 1, nz, sx, sy, nz - 1));
     while (max_nodes > 1024 && w > AGG_C) {
         w -= AGG_C;
-        max_nodes = sub_count(make_sub(w * sx + 1, AGG_C * sy + 1, nz, sx, sy));
+        max_nodes = sub_count(make_sub(w * sx + 1, AGG_C * sy + 1, nz, sx, sy, nz - 1));
     }
     if (width) *width = w;
     // The box kernels address the cell layouts with 32-bit byte offsets.
@@ -2550,18 +2733,24 @@ mos_status engine_set_precond(mos_engine e, int precond) {
 }
 
 mos_status engine_check_desc(mos_engine e, const mos_array_desc *d) {
-    if (!d || d->nx_cells < 1 || d->ny_cells < 1 || (int64_t)d->nx_cells * d->ny_cells > (1 << 22) || !d->cell_type) {
-        set_error("array size must be >= 1x1 and <= 4M cells, with a cell_type map");
+    if (!d || d->nx_cells < 1 || d->ny_cells < 1 || d->nz_cells < 0 ||
+        (int64_t)d->nx_cells * d->ny_cells * (d->nz_cells < 1 ? 1 : d->nz_cells) > (1 << 22) || !d->cell_type) {
+        set_error("array size must be >= 1x1 (x 1 layer) and <= 4M cells, with a cell_type map");
+        return MOS_EINVAL;
+    }
+    if (d->nz_cells > 1 && e->precond) {
+        set_error("stacked arrays take the Jacobi preconditioner: set MOS_OPT_PRECOND 0 before the first submission");
         return MOS_EINVAL;
     }
     if (!std::isfinite(d->delta_T) || d->n_prescribed < 0 ||
         (d->n_prescribed > 0 && (!d->prescribed_dof || !d->prescribed_value)) ||
-        (d->bc_flags & ~(uint32_t)(MOS_BC_CLAMP_BOTTOM | MOS_BC_CLAMP_TOP)) || d->precision != e->precision ||
+        (d->bc_flags & ~(uint32_t)(MOS_BC_CLAMP_BOTTOM | MOS_BC_CLAMP_TOP | MOS_BC_LIST_ON_DEVICE)) ||
+        d->precision != e->precision ||
         d->rtol < 0 || d->max_iters < 0) {
         set_error("invalid delta_T, constraints, precision (must match the engine), rtol or max_iters");
         return MOS_EINVAL;
     }
-    const int64_t n_cells = (int64_t)d->nx_cells * d->ny_cells;
+    const int64_t n_cells = (int64_t)d->nx_cells * d->ny_cells * (d->nz_cells < 1 ? 1 : d->nz_cells);
     int first = -1;
     for (int64_t c = 0; c < n_cells; ++c) {
         const int t = d->cell_type[c];
@@ -2659,12 +2848,12 @@ void cgstep_launch(mos_engine e, int hw_blk, T *const *V, int j) {
     const dim3 grid((unsigned)(ceil_div(hw_blk, N_XCD) * N_XCD));
     if (wide)
         launch_timed(e->ctx, MOS_K_PCG_UPDATE, k_cgstep<T, 256>, grid, dim3(256), 0, st, (const T *)e->Yi,
-                     (const int32_t *)e->inc, (const uint8_t *)e->cmask, (const T *)V[VDINV], V[VX], V[VR], V[VP],
+                     (const int32_t *)e->inc, (const int32_t *)(e->stacked ? e->inc2 : nullptr), (const uint8_t *)e->cmask, (const T *)V[VDINV], V[VX], V[VR], V[VP],
                      V[VS], (T *)e->Mc, e->ld_slots, (const int32_t *)e->blk_prob, e->ps, e->pg, e->pr,
                      (const double *)e->pdel, (const int *)e->epoch_dev, j, e->cap_blk, hw_blk);
     else
         launch_timed(e->ctx, MOS_K_PCG_UPDATE, k_cgstep<T, 128>, grid, dim3(128), 0, st, (const T *)e->Yi,
-                     (const int32_t *)e->inc, (const uint8_t *)e->cmask, (const T *)V[VDINV], V[VX], V[VR], V[VP],
+                     (const int32_t *)e->inc, (const int32_t *)(e->stacked ? e->inc2 : nullptr), (const uint8_t *)e->cmask, (const T *)V[VDINV], V[VX], V[VR], V[VP],
                      V[VS], (T *)e->Mc, e->ld_slots, (const int32_t *)e->blk_prob, e->ps, e->pg, e->pr,
                      (const double *)e->pdel, (const int *)e->epoch_dev, j, e->cap_blk, hw_blk);
 }
@@ -2797,7 +2986,7 @@ mos_status issue_chunk(mos_engine e, int chunk, int hw_sb, int hw_blk, int hw_p,
                              (const int32_t *)e->sb_prob, (const float *)e->Mc, (float *)e->Yi, e->ldk, e->ld_slots,
                              0, hw_sb, 1, (const ProbState *)e->ps, e->pdel, ProbSel{});
             if (any_large)
-                launch_timed(ctx, MOS_K_PCG_SCALARS, k_cg_scalars, dim3(hw_p), dim3(256), 0, st, e->ps,
+                launch_timed(ctx, MOS_K_PCG_SCALARS, k_cg_scalars, dim3(hw_p), dim3(CG_BIG), 0, st, e->ps,
                              (const double *)e->pg, (const double *)e->pr, (const double *)e->pdel,
                              (const int *)e->epoch_dev, j, e->cap_blk);
             cgstep_launch<float>(e, hw_blk, V, j);
@@ -2812,7 +3001,7 @@ mos_status issue_chunk(mos_engine e, int chunk, int hw_sb, int hw_blk, int hw_p,
                              (const int32_t *)e->sb_prob, (const double *)e->Mc, (double *)e->Yi, e->ldk,
                              e->ld_slots, 0, hw_sb, 1, (const ProbState *)e->ps, e->pdel, ProbSel{});
             if (any_large)
-                launch_timed(ctx, MOS_K_PCG_SCALARS, k_cg_scalars, dim3(hw_p), dim3(256), 0, st, e->ps,
+                launch_timed(ctx, MOS_K_PCG_SCALARS, k_cg_scalars, dim3(hw_p), dim3(CG_BIG), 0, st, e->ps,
                              (const double *)e->pg, (const double *)e->pr, (const double *)e->pdel,
                              (const int *)e->epoch_dev, j, e->cap_blk);
             cgstep_launch<double>(e, hw_blk, V, j);
@@ -2854,7 +3043,7 @@ mos_status run_chunk(mos_engine e, int chunk, int hw_sb, int hw_blk, int hw_p, b
         return MOS_OK;
     }
     const int key[GRAPH_KEY] = {chunk, hw_sb, hw_blk, hw_p, e->boxes.high, rows ? 1 : 0, cand, any_large ? 1 : 0,
-                                e->precond, e->box_nt, e->update_width};
+                                e->precond, e->box_nt, e->update_width, e->stacked};
     if (!e->graph_exec || !std::equal(key, key + GRAPH_KEY, e->graph_key)) {
         if (e->graph_exec) {
             MOS_HIP(hipGraphExecDestroy(e->graph_exec));
@@ -2892,9 +3081,34 @@ mos_status run_chunk(mos_engine e, int chunk, int hw_sb, int hw_blk, int hw_p, b
 }  // namespace
 
 // One round: admit, iterate a chunk, check stopped problems, retire finished.
+namespace {
+// Move retired problems whose completion event has passed (all of them when
+// `wait`) to the finished map and the completed list, in retirement order.
+mos_status collect_retired(mos_engine e, std::vector<int64_t> *completed, bool wait) {
+    while (!e->retiring.empty()) {
+        mos_engine_s::Retiring &r = e->retiring.front();
+        if (wait) {
+            MOS_HIP(hipEventSynchronize(r.ev));
+        } else {
+            const hipError_t q = hipEventQuery(r.ev);
+            if (q == hipErrorNotReady) break;
+            MOS_HIP(q);
+        }
+        for (EngineProblem *P : r.probs) {
+            e->finished[P->ticket] = P;
+            if (completed) completed->push_back(P->ticket);
+        }
+        e->spare_events.push_back(r.ev);
+        e->retiring.pop_front();
+    }
+    return MOS_OK;
+}
+}  // namespace
+
 mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *completed) {
     mos_ctx ctx = e->ctx;
     hipStream_t st = ctx->stream;
+    MOS_TRY(collect_retired(e, completed, false));
     // 1. Admission in arrival order while the arenas have room.
     std::vector<EngineProblem *> admitted;
     while (!e->queue.empty()) {
@@ -2957,6 +3171,7 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
         const ProbState *hs = e->ps_host;
         MOS_HIP(hipMemcpyAsync(e->ps_host, e->ps, hw_p * sizeof(ProbState), hipMemcpyDeviceToHost, st));
         MOS_HIP(hipStreamSynchronize(st));
+        MOS_TRY(collect_retired(e, completed, false));
         tuner_collect(e->tuner);
         std::vector<EngineProblem *> stopped;
         Batch B;
@@ -3016,15 +3231,28 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
                 hipLaunchKernelGGL(k_export_u, dim3(ceil_div(P->n_dofs, 256)), dim3(256), 0, st,
                                    (const double *)(e->x64 + (int64_t)P->blk_begin * DB), P->u_out, P->n_dofs,
                                    whole_lattice(P->lat), P->agg);
-            e->finished[P->ticket] = P;
             gone.push_back(P);
-            if (completed) completed->push_back(P->ticket);
         } else {
             keep.push_back(P);
         }
     }
     e->active.swap(keep);
-    return release_problems(e, gone);
+    MOS_TRY(release_problems(e, gone));
+    if (!gone.empty()) {
+        hipEvent_t ev = nullptr;
+        if (!e->spare_events.empty()) {
+            ev = e->spare_events.back();
+            e->spare_events.pop_back();
+        } else {
+            MOS_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        }
+        e->retiring.push_back(mos_engine_s::Retiring{ev, {}});
+        MOS_HIP(hipEventRecord(ev, st));
+        e->retiring.back().probs = gone;
+    }
+    // With nothing left to iterate there is no later chunk to overlap with:
+    // wait for the retirements here instead of on the caller's next call.
+    return collect_retired(e, completed, e->active.empty() && e->queue.empty());
 }
 
 // ---------------------------------------------------------------------------
@@ -3115,11 +3343,11 @@ mos_status engine_problem_size(mos_engine e, const mos_array_desc *d, int64_t *d
     MOS_TRY(engine_check_desc(e, d));
     const mos_cell_desc &cd = e->roms[0]->desc;
     const int nx = cd.interp[0], ny = cd.interp[1], nz = cd.interp[2];
-    const int64_t X = (int64_t)d->nx_cells * (nx - 1) + 1, Y = (int64_t)d->ny_cells * (ny - 1) + 1;
-    const int64_t nodes = X * Y * nz - (int64_t)d->nx_cells * d->ny_cells * (nx - 2) * (ny - 2) * (nz - 2);
-    const Lattice L = make_lattice(d->nx_cells, d->ny_cells, nx, ny, nz);
-    *dofs = (int64_t)problem_blocks(3 * nodes, agg_count(make_agg_layout(L, e->box_cells[0], e->box_cells[1]))) * DB;
-    const int64_t n_cells = (int64_t)d->nx_cells * d->ny_cells;
+    const int Nz = d->nz_cells < 1 ? 1 : d->nz_cells;
+    const Lattice L = make_lattice(d->nx_cells, d->ny_cells, nx, ny, nz, Nz);
+    *dofs = (int64_t)problem_blocks(3 * L.n_nodes, agg_count(make_agg_layout(L, e->box_cells[0], e->box_cells[1]))) *
+            DB;
+    const int64_t n_cells = (int64_t)d->nx_cells * d->ny_cells * Nz;
     std::vector<int64_t> count(e->roms.size(), 0);
     for (int64_t c = 0; c < n_cells; ++c) count[d->cell_type[c]]++;
     int64_t sl = 0;
@@ -3136,6 +3364,14 @@ void engine_free(mos_engine e) {
         delete P;
     }
     for (auto &kv : e->finished) delete kv.second;
+    for (auto &r : e->retiring) {
+        (void)hipEventSynchronize(r.ev);
+        (void)hipEventDestroy(r.ev);
+        for (EngineProblem *P : r.probs) delete P;
+    }
+    for (hipEvent_t ev : e->spare_events) (void)hipEventDestroy(ev);
+    e->retiring.clear();
+    e->spare_events.clear();
     e->queue.clear();
     e->active.clear();
     e->finished.clear();

@@ -9,6 +9,7 @@
 // 16x16x4: lane l supplies A[l%16][l/16], B[l/16][l%16] and receives
 // D[l/16 + 4q][l%16] in register q.
 #include <cmath>
+#include <cstdlib>
 
 #include "bf16.h"
 #include "mesh.h"
@@ -170,6 +171,111 @@ __global__ __launch_bounds__(512, 1) void k_recon_f64_lds(const double *psi, con
 #pragma unroll
                 for (int c = 0; c < 6; ++c) sig6[o * 6 + c] = (OutT)sv[c];
         }
+    }
+}
+
+// The same kernel with the cell operand streamed in chunks of KC k-steps,
+// double-buffered across chunks and across a wave's slot blocks: the next
+// chunk's loads (the next block's first chunk during the last one) are in
+// flight while the current chunk's MFMAs run, so no block starts with an
+// exposed round trip, and two chunks of u take the registers one whole
+// block took (no spills).  Same products in the same order as
+// k_recon_f64_lds, so the same bits.  Bases of exactly KS k-steps.
+template <class OutT, int KS, int KC>
+__global__ __launch_bounds__(512, 1) void k_recon_f64_pipe(const double *psi, const double *sig_t, const double *U,
+                                                           const int32_t *perm, int ld, const ReconJob *jobs,
+                                                           int n_jobs, int total_sb, int chunk, int n_elem) {
+    static_assert(KS % KC == 0, "chunks must tile the k-steps");
+    constexpr int NCH = KS / KC;
+    constexpr int ldk = 4 * KS;
+    __shared__ double lds[6 * ldk * 16];
+    __shared__ double st_lds[16][6];
+    const int eb = blockIdx.x;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int y0 = blockIdx.y * chunk, y1 = min(y0 + chunk, total_sb);
+    {
+        const double *g = psi + (size_t)eb * 6 * ldk * 16;
+        for (int i = threadIdx.x; i < 6 * ldk * 16; i += 512) lds[i] = g[i];
+        if (threadIdx.x < 96) {
+            const int e = min(eb * 16 + (int)threadIdx.x / 6, n_elem - 1);
+            st_lds[threadIdx.x / 6][threadIdx.x % 6] = sig_t[(size_t)e * 6 + threadIdx.x % 6];
+        }
+    }
+    __syncthreads();
+    int f = y0 + wave;
+    if (f >= y1) return;
+    int j = 0;
+    // Operand column of flattened slot block f for this lane (job lookup
+    // moves forward only).
+    auto column = [&](int fb, int &jj) -> size_t {
+        while (jj + 1 < n_jobs && fb >= jobs[jj + 1].sb_off) ++jj;
+        const ReconJob &J = jobs[jj];
+        return (size_t)(J.sb_first + (fb - J.sb_off)) * 16;
+    };
+    int jn = j;
+    size_t pc0 = column(f, j);
+    const double *ap = lds + (lane / 16) * 16 + lane % 16;
+    double bc[KC], bn[KC];
+    {
+        const double *bp = U + (size_t)(lane / 16) * ld + pc0 + lane % 16;
+#pragma unroll
+        for (int k = 0; k < KC; ++k) bc[k] = bp[(size_t)(4 * k) * ld];
+    }
+    while (true) {
+        const ReconJob &J = jobs[j];
+        const double dT = J.dT;
+        OutT *vm = static_cast<OutT *>(J.vm);
+        OutT *sig6 = static_cast<OutT *>(J.sig6);
+        const int cell = perm[pc0 + lane % 16];
+        const int fn = f + 8;
+        jn = j;
+        const size_t pcn = fn < y1 ? column(fn, jn) : pc0;
+        d4 acc[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            // Next chunk: this block's, or the next block's first (past the
+            // wave's last block, the first chunk again; unused).
+            const size_t col = ch + 1 < NCH ? pc0 : pcn;
+            const int k0 = ch + 1 < NCH ? (ch + 1) * KC : 0;
+            const double *bp = U + (size_t)(lane / 16) * ld + col + lane % 16;
+#pragma unroll
+            for (int k = 0; k < KC; ++k) bn[k] = bp[(size_t)(4 * (k0 + k)) * ld];
+#pragma unroll
+            for (int k = 0; k < KC; ++k) {
+#pragma unroll
+                for (int c = 0; c < 6; ++c)
+                    acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ap[(c * ldk + 4 * (ch * KC + k)) * 16], bc[k],
+                                                                 acc[c], 0, 0, 0);
+                if (k % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int k = 0; k < KC; ++k) bc[k] = bn[k];
+        }
+        if (cell >= 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = eb * 16 + lane / 16 + 4 * q;  // FP64 MFMA output row
+                if (e >= n_elem) continue;
+                double sv[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) sv[c] = acc[c][q] + dT * st_lds[lane / 16 + 4 * q][c];
+                const size_t o = (size_t)cell * n_elem + e;
+                if (vm) {
+                    double x = sv[0] - sv[1], y = sv[1] - sv[2], z = sv[2] - sv[0];
+                    vm[o] = (OutT)sqrt(0.5 * (x * x + y * y + z * z) +
+                                       3.0 * (sv[3] * sv[3] + sv[4] * sv[4] + sv[5] * sv[5]));
+                }
+                if (sig6)
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) sig6[o * 6 + c] = (OutT)sv[c];
+            }
+        }
+        if (fn >= y1) break;
+        f = fn;
+        j = jn;
+        pc0 = pcn;
     }
 }
 
@@ -340,7 +446,154 @@ __global__ __launch_bounds__(256, KSMAX <= 6 ? 2 : 1) void k_recon_bf16(const bf
     }
 }
 
+// Two element blocks per workgroup (32 elements, 144 KB of Psi hi and lo in
+// LDS, one workgroup of eight waves per CU): each B fragment a wave loads
+// feeds the MFMAs of both blocks, so the cell operand is read from L2 half
+// as often per MFMA as with one block per workgroup.  Each wave streams CB
+// slot blocks at a time, the next k-step's fragments requested while the
+// current one's MFMAs run.  Products, their order and the epilogue are
+// those of k_recon_bf16, so the results are bitwise the same.
+template <int KSMAX, int CB>
+__global__ __launch_bounds__(512, 1) void k_recon_bf16_x2(const bf16x8 *psi_hi, const bf16x8 *psi_lo,
+                                                          const double *sig_t, const bf16x8 *ub_hi,
+                                                          const bf16x8 *ub_lo, const int32_t *perm,
+                                                          const ReconJob *jobs, int n_jobs, int v_begin, int n_v,
+                                                          int chunk, int nks, int n_elem, int n_eblk) {
+    constexpr int NW = 8;
+    __shared__ bf16x8 lds[2][2][6][KSMAX][64];
+    __shared__ double st_lds[32][6];
+    const int eb0 = 2 * (int)blockIdx.x;
+    const int neb = min(2, n_eblk - eb0);
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int y0 = v_begin + (int)blockIdx.y * chunk, y1 = min(y0 + chunk, v_begin + n_v);
+    {
+        const bf16x8 *gh = psi_hi + (size_t)eb0 * 6 * nks * 64;
+        const bf16x8 *gl = psi_lo + (size_t)eb0 * 6 * nks * 64;
+        const int per = 6 * nks * 64;
+        for (int i = threadIdx.x; i < neb * per; i += 64 * NW) {
+            const int b = i / per, c = (i % per) / (nks * 64), r = i % (nks * 64);
+            lds[b][0][c][r / 64][r % 64] = gh[i];
+            lds[b][1][c][r / 64][r % 64] = gl[i];
+        }
+        if (threadIdx.x < 192) {
+            const int e = min(eb0 * 16 + (int)threadIdx.x / 6, n_elem - 1);
+            st_lds[threadIdx.x / 6][threadIdx.x % 6] = sig_t[(size_t)e * 6 + threadIdx.x % 6];
+        }
+    }
+    __syncthreads();
+    int j = 0;  // job of the wave's current block (blocks only move forward)
+    for (int base = y0 + wave * CB; base < y1; base += NW * CB) {
+        double dTv[CB];
+        float *vmv[CB], *s6v[CB];
+        int cellv[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int v = min(base + cb, y1 - 1);
+            while (j + 1 < n_jobs && v >= jobs[j + 1].sb_off) ++j;
+            const ReconJob &J = jobs[j];
+            dTv[cb] = J.dT;
+            vmv[cb] = static_cast<float *>(J.vm);
+            s6v[cb] = static_cast<float *>(J.sig6);
+            cellv[cb] = perm[(size_t)(J.sb_first + (v - J.sb_off)) * 16 + lane % 16];
+        }
+        f32x4 acc[2][CB][6];
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) acc[b][cb][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // Past the slice end a wave rereads the last valid block (results unused).
+        size_t fb[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) fb[cb] = (size_t)min(base + cb, y1 - 1) * nks * 64 + lane;
+        bf16x8 bh[CB], bl[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            bh[cb] = ub_hi[fb[cb]];
+            bl[cb] = ub_lo[fb[cb]];
+        }
+#pragma unroll
+        for (int ks = 0; ks < KSMAX; ++ks) {
+            if (ks < nks) {
+                bf16x8 nh[CB], nl[CB];
+                if (ks + 1 < nks) {
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) {
+                        nh[cb] = ub_hi[fb[cb] + (size_t)(ks + 1) * 64];
+                        nl[cb] = ub_lo[fb[cb] + (size_t)(ks + 1) * 64];
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) {
+                        const bf16x8 ah = lds[b][0][c][ks][lane], al = lds[b][1][c][ks][lane];
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb) {
+                            acc[b][cb][c] =
+                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[cb], acc[b][cb][c], 0, 0, 0);
+                            acc[b][cb][c] =
+                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[cb], acc[b][cb][c], 0, 0, 0);
+                            acc[b][cb][c] =
+                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[cb], acc[b][cb][c], 0, 0, 0);
+                        }
+                    }
+                }
+                if (ks + 1 < nks) {
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) {
+                        bh[cb] = nh[cb];
+                        bl[cb] = nl[cb];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            if (b >= neb) continue;
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                if (base + cb >= y1) continue;
+                const double dT = dTv[cb];
+                float *vm = vmv[cb], *sig6 = s6v[cb];
+                const int cell = cellv[cb];
+                if (cell < 0) continue;
+                const int e0 = (eb0 + b) * 16 + 4 * (lane / 16);
+                float vq[4], sq[4][6];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                    for (int c = 0; c < 6; ++c)
+                        sq[q][c] = acc[b][cb][c][q] + (float)(dT * st_lds[b * 16 + 4 * (lane / 16) + q][c]);
+                    const float x = sq[q][0] - sq[q][1], y = sq[q][1] - sq[q][2], d = sq[q][2] - sq[q][0];
+                    vq[q] = sqrtf(0.5f * (x * x + y * y + d * d) +
+                                  3.0f * (sq[q][3] * sq[q][3] + sq[q][4] * sq[q][4] + sq[q][5] * sq[q][5]));
+                }
+                const size_t o = (size_t)cell * n_elem + e0;
+                const bool whole = e0 + 3 < n_elem && o % 4 == 0;
+                if (vm) {
+                    if (whole) {
+                        *(f32x4 *)(vm + o) = f32x4{vq[0], vq[1], vq[2], vq[3]};
+                    } else {
+                        for (int q = 0; q < 4; ++q)
+                            if (e0 + q < n_elem) vm[o + q] = vq[q];
+                    }
+                }
+                if (sig6) {
+                    for (int q = 0; q < 4; ++q)
+                        if (e0 + q < n_elem)
+                            for (int c = 0; c < 6; ++c) sig6[(o + q) * 6 + c] = sq[q][c];
+                }
+            }
+        }
+    }
+}
+
 }  // namespace
+
+int recon_f64_variant();
+int recon_bf16_variant();
 
 mos_status recon_f64_jobs(mos_ctx ctx, const mos_rom *roms, int n_types, const std::vector<ReconJob> *jobs,
                           ReconJob *dev_jobs, ReconJob *host_jobs, const double *U, int ld, const int32_t *perm,
@@ -368,7 +621,13 @@ mos_status recon_f64_jobs(mos_ctx ctx, const mos_rom *roms, int n_types, const s
         const dim3 grid(r->n_eblk, ceil_div(total, chunk));
         const double *psi = roms[t]->psi, *sgt = roms[t]->sig_t;
         const ReconJob *dj = dev_jobs + first[t];
-        if (ks == RECON_F64_LDS_KS && !fp32_out)
+        if (ks == RECON_F64_LDS_KS && !fp32_out && recon_f64_variant() == 2)
+            launch_timed(ctx, MOS_K_RECON, k_recon_f64_pipe<double, RECON_F64_LDS_KS, 11>, grid, dim3(512), 0, st,
+                         psi, sgt, U, perm, ld, dj, nj, total, chunk, r->n_elem);
+        else if (ks == RECON_F64_LDS_KS && fp32_out && recon_f64_variant() == 2)
+            launch_timed(ctx, MOS_K_RECON, k_recon_f64_pipe<float, RECON_F64_LDS_KS, 11>, grid, dim3(512), 0, st,
+                         psi, sgt, U, perm, ld, dj, nj, total, chunk, r->n_elem);
+        else if (ks == RECON_F64_LDS_KS && !fp32_out)
             launch_timed(ctx, MOS_K_RECON, k_recon_f64_lds<double, RECON_F64_LDS_KS, true>, grid, dim3(512), 0, st, psi,
                          sgt, U, perm, ld, dj, nj, total, chunk, ks, r->n_elem);
         else if (!fp32_out)
@@ -386,6 +645,24 @@ mos_status recon_f64_jobs(mos_ctx ctx, const mos_rom *roms, int n_types, const s
 }
 
 int64_t recon_bf16_scratch(const mos_rom r, int n_sb) { return (int64_t)n_sb * r->nks * 64 * 2 * 16; }
+
+// FP64 reconstruction kernel for bases of exactly 176 (44 k-steps): 2 = the
+// chunked, double-buffered operand stream (default), 1 = the whole block's
+// operand requested at once.  Both give the same bits; MOS_RECON_F64=1 in the
+// environment at the time of the call selects the second (for comparisons).
+int recon_f64_variant() {
+    const char *e = std::getenv("MOS_RECON_F64");
+    return (e && std::atoi(e) == 1) ? 1 : 2;
+}
+
+// BF16-split reconstruction kernel for bases up to 192 (nks <= 6): 2 = two
+// element blocks per workgroup (default), 1 = one.  Both give the same bits;
+// MOS_RECON_BF16=1 in the environment at the time of the call selects the
+// second (for comparisons).
+int recon_bf16_variant() {
+    const char *e = std::getenv("MOS_RECON_BF16");
+    return (e && std::atoi(e) == 1) ? 1 : 2;
+}
 
 mos_status recon_bf16_jobs(mos_ctx ctx, const mos_rom *roms, int n_types, const std::vector<ReconJob> *jobs,
                            ReconJob *dev_jobs, ReconJob *host_jobs, const double *U, int ld, const int32_t *perm,
@@ -429,7 +706,16 @@ mos_status recon_bf16_jobs(mos_ctx ctx, const mos_rom *roms, int n_types, const 
         const bf16x8 *ph = (const bf16x8 *)roms[t]->psi_hi, *pl = (const bf16x8 *)roms[t]->psi_lo;
         const ReconJob *dj = dev_jobs + first[t];
         const int nj = first[t + 1] - first[t];
-        if (r->nks <= 6)
+        if (r->nks <= 6 && recon_bf16_variant() == 2) {
+            // Two element blocks per workgroup, one workgroup per CU: slices
+            // give >= ~512 workgroups while each still streams >= 32 blocks.
+            const int nx2 = ceil_div(r->n_eblk, 2);
+            const int ny2 = std::max(1, std::min(n_v / 32, ceil_div(512, nx2)));
+            const int chunk2 = ceil_div(n_v, ny2);
+            launch_timed(ctx, MOS_K_RECON, k_recon_bf16_x2<6, 2>, dim3(nx2, ceil_div(n_v, chunk2)), dim3(512), 0, st,
+                         ph, pl, (const double *)roms[t]->sig_t, (const bf16x8 *)ub_hi, (const bf16x8 *)ub_lo, perm, dj,
+                         nj, vbase[t], n_v, chunk2, r->nks, r->n_elem, r->n_eblk);
+        } else if (r->nks <= 6)
             launch_timed(ctx, MOS_K_RECON, k_recon_bf16<6, 4>, grid, dim3(256), 0, st, ph, pl,
                          (const double *)roms[t]->sig_t, (const bf16x8 *)ub_hi, (const bf16x8 *)ub_lo, perm, dj, nj,
                          vbase[t], n_v, chunk, r->nks, r->n_elem);

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libmos.so")
 
 MOS_OK, MOS_EINVAL, MOS_ENOMEM, MOS_ENOCONV, MOS_ESINGULAR, MOS_EHIP, MOS_EBUSY = 0, -1, -2, -3, -4, -5, -6
 MOS_FP64, MOS_MIXED = 0, 1
-MOS_BC_CLAMP_BOTTOM, MOS_BC_CLAMP_TOP = 1, 2
+MOS_BC_CLAMP_BOTTOM, MOS_BC_CLAMP_TOP, MOS_BC_LIST_ON_DEVICE = 1, 2, 4
 MOS_OUT_VM, MOS_OUT_SIGMA6 = 1, 2
 (MOS_Q_N, MOS_Q_CELL_DOFS, MOS_Q_CELL_ELEMS, MOS_Q_CELL_NNZ, MOS_Q_FREE_DOFS, MOS_Q_BANDWIDTH,
  MOS_Q_GLOBAL_DOFS, MOS_Q_ITERS, MOS_Q_REFINES, MOS_Q_DEVICE_BYTES) = range(1, 11)
@@ -32,6 +32,7 @@ MOS_OPT_GEMM_SPLIT = 2
 MOS_OPT_UPDATE_WIDTH = 3
 MOS_OPT_PRECOND = 4
 MOS_OPT_GRAPH = 5
+MOS_OPT_COARSE_TABLE = 6
 
 
 class MosError(RuntimeError):
@@ -57,7 +58,7 @@ class ArrayDesc(ctypes.Structure):
                 ("bc_flags", ctypes.c_uint32), ("n_prescribed", ctypes.c_int64),
                 ("prescribed_dof", ctypes.POINTER(ctypes.c_int64)),
                 ("prescribed_value", ctypes.POINTER(ctypes.c_double)), ("precision", ctypes.c_int),
-                ("rtol", ctypes.c_double), ("max_iters", ctypes.c_int32)]
+                ("rtol", ctypes.c_double), ("max_iters", ctypes.c_int32), ("nz_cells", ctypes.c_int32)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -86,8 +87,8 @@ def _load():
         "mos_query": (ctypes.c_int, [vp, ctypes.c_int, P(ctypes.c_int64)]),
         "mos_cell_export": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
         "mos_rom_export": (ctypes.c_int, [vp, vp, vp, vp, vp]),
-        "mos_array_layout": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, vp, P(ctypes.c_int64), vp, vp,
-                                            vp, vp]),
+        "mos_array_layout": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
+                                            P(ctypes.c_int64), vp, vp, vp, vp]),
         "mos_engine_create": (ctypes.c_int, [vp, P(vp), ctypes.c_int32, ctypes.c_int, ctypes.c_size_t, P(vp)]),
         "mos_engine_submit": (ctypes.c_int, [vp, P(ArrayDesc), vp, vp, vp, P(ctypes.c_int64)]),
         "mos_engine_progress": (ctypes.c_int, [vp, ctypes.c_int32, vp, ctypes.c_int32, P(ctypes.c_int32)]),
@@ -235,18 +236,29 @@ def mos_reduce(ctx, cell):
 
 
 def array_desc(nx_cells, ny_cells, cell_type, delta_T, clamp_bottom=True, clamp_top=False,
-               prescribed_dofs=None, prescribed_values=None, mixed=False, rtol=0.0, max_iters=0):
+               prescribed_dofs=None, prescribed_values=None, mixed=False, rtol=0.0, max_iters=0, nz_cells=1):
     """Build the C descriptor; returns (desc, keep-alive arrays)."""
     ct = np.ascontiguousarray(cell_type, dtype=np.uint8)
-    if ct.size != nx_cells * ny_cells:
-        raise ValueError("cell_type must have nx_cells * ny_cells entries")
+    if ct.size != nx_cells * ny_cells * nz_cells:
+        raise ValueError("cell_type must have nx_cells * ny_cells * nz_cells entries")
     d = ArrayDesc()
-    d.nx_cells, d.ny_cells = int(nx_cells), int(ny_cells)
+    d.nx_cells, d.ny_cells, d.nz_cells = int(nx_cells), int(ny_cells), int(nz_cells)
     d.cell_type = ct.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
     d.delta_T = float(delta_T)
     d.bc_flags = (MOS_BC_CLAMP_BOTTOM if clamp_bottom else 0) | (MOS_BC_CLAMP_TOP if clamp_top else 0)
     keep = [ct]
-    if prescribed_dofs is not None and len(prescribed_dofs):
+    if prescribed_dofs is not None and getattr(prescribed_dofs, "is_cuda", False):
+        # Device-resident list (torch tensors on the context's device).
+        pd, pv = prescribed_dofs, prescribed_values
+        if (str(pd.dtype) != "torch.int64" or str(pv.dtype) != "torch.float64" or not pv.is_cuda
+                or pd.shape != pv.shape or not pd.is_contiguous() or not pv.is_contiguous()):
+            raise ValueError("device prescribed lists must be contiguous int64 / float64 tensors of one shape")
+        d.bc_flags |= MOS_BC_LIST_ON_DEVICE
+        d.n_prescribed = pd.numel()
+        d.prescribed_dof = ctypes.cast(ctypes.c_void_p(pd.data_ptr()), ctypes.POINTER(ctypes.c_int64))
+        d.prescribed_value = ctypes.cast(ctypes.c_void_p(pv.data_ptr()), ctypes.POINTER(ctypes.c_double))
+        keep += [pd, pv]
+    elif prescribed_dofs is not None and len(prescribed_dofs):
         pd = np.ascontiguousarray(prescribed_dofs, dtype=np.int64)
         pv = np.ascontiguousarray(prescribed_values, dtype=np.float64)
         if pd.shape != pv.shape:
@@ -265,15 +277,15 @@ def _rom_array(roms):
 
 
 def mos_solve_array(ctx, roms, nx_cells, ny_cells, cell_type, delta_T, clamp_bottom=True, clamp_top=False,
-                    prescribed_dofs=None, prescribed_values=None, mixed=False, rtol=0.0, max_iters=0):
+                    prescribed_dofs=None, prescribed_values=None, mixed=False, rtol=0.0, max_iters=0, nz_cells=1):
     d, keep = array_desc(nx_cells, ny_cells, cell_type, delta_T, clamp_bottom, clamp_top, prescribed_dofs,
-                         prescribed_values, mixed, rtol, max_iters)
+                         prescribed_values, mixed, rtol, max_iters, nz_cells)
     h = ctypes.c_void_p()
     _check(lib().mos_solve_array(ctx.ptr, ctypes.byref(d), _rom_array(roms), len(roms), ctypes.byref(h)),
            "mos_solve_array")
     s = Solution(h, ctx)
     s.precision = d.precision
-    s.n_cells = nx_cells * ny_cells
+    s.n_cells = nx_cells * ny_cells * nz_cells
     s.n_elem = roms[0].query(MOS_Q_CELL_ELEMS)
     s.roms = list(roms)
     return s
@@ -459,22 +471,23 @@ def mos_rom_export(rom):
     return phi, fT, Kr, br
 
 
-def mos_array_layout(ctx, nx_cells, ny_cells, rom, pattern=False):
+def mos_array_layout(ctx, nx_cells, ny_cells, rom, pattern=False, nz_cells=1):
     n_nodes = ctypes.c_int64()
-    _check(lib().mos_array_layout(ctx.ptr, nx_cells, ny_cells, rom.ptr, ctypes.byref(n_nodes), None, None, None,
-                                  None), "mos_array_layout")
+    f = lib().mos_array_layout
+    _check(f(ctx.ptr, nx_cells, ny_cells, nz_cells, rom.ptr, ctypes.byref(n_nodes), None, None, None, None),
+           "mos_array_layout")
     nn = n_nodes.value
     S = rom.query(MOS_Q_N) // 3
     coords = np.empty((nn, 3))
-    conn = np.empty((nx_cells * ny_cells, S), dtype=np.int32)
+    conn = np.empty((nx_cells * ny_cells * nz_cells, S), dtype=np.int32)
     indptr = indices = None
     if pattern:
         indptr = np.empty(3 * nn + 1, dtype=np.int64)
-        _check(lib().mos_array_layout(ctx.ptr, nx_cells, ny_cells, rom.ptr, ctypes.byref(n_nodes), None, None,
-                                      _ptr(indptr), None), "mos_array_layout")
+        _check(f(ctx.ptr, nx_cells, ny_cells, nz_cells, rom.ptr, ctypes.byref(n_nodes), None, None, _ptr(indptr),
+                 None), "mos_array_layout")
         indices = np.empty(int(indptr[-1]), dtype=np.int32)
-    _check(lib().mos_array_layout(ctx.ptr, nx_cells, ny_cells, rom.ptr, ctypes.byref(n_nodes), _ptr(coords),
-                                  _ptr(conn), _ptr(indptr), _ptr(indices)), "mos_array_layout")
+    _check(f(ctx.ptr, nx_cells, ny_cells, nz_cells, rom.ptr, ctypes.byref(n_nodes), _ptr(coords), _ptr(conn),
+             _ptr(indptr), _ptr(indices)), "mos_array_layout")
     return coords, conn, indptr, indices
 
 

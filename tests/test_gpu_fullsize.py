@@ -9,7 +9,10 @@ that follows it):
 * the residual of the GPU's FP64 solution under the oracle's own reduced
   operator, applied cell by cell with the oracle's K_r and b_r
   (sum over cells of K_r(type) u_cell against dT sum b_r(type)), must be
-  below the FP64 target: a residual bound holds at any size;
+  below the FP64 target: a residual bound holds at any size.  It bounds the
+  error of u only through the condition number of the lifted system,
+  |u - u*| / |u*| <= kappa(A) |r| / |b|, so at these sizes u itself is pinned
+  by the element-by-element comparisons on the arrays the oracle can solve;
 * the prescribed values must be reproduced exactly;
 * the oracle's plain reconstruction (u = dT f_T + Phi u_cell, centroid
   stress) of sampled cells from the GPU solution must match the GPU's von
@@ -148,6 +151,61 @@ def test_prescribed_field_small_matches_oracle(mos, ctx):
     np.testing.assert_array_equal(u[od], ov)
     u32, _, vm32 = solve_gpu(mos, ctx, roms, case, True, prescribed_dofs=pd, prescribed_values=pv)
     assert rel_max(vm32.double().cpu().numpy(), vm_ref) < 1e-3
+
+
+def test_device_resident_prescribed_list_equals_host_list(mos, ctx):
+    """The prescribed list handed over in device memory (MOS_BC_LIST_ON_DEVICE)
+    describes the same system as the host list, so every bit of the solution
+    and the stress is the same (FP64 and mixed, through mos_solve_array and an
+    engine)."""
+    import torch
+    rng = np.random.default_rng(8)
+    case = W.small_case(nx=5, ny=4, mesh=(4, 4, 6), interp=(3, 3, 4), pitch_x=3.0, pitch_y=3.0, height=6.0,
+                        tsv_diameter=1.6, liner_thickness=0.3, seed=6)
+    case.clamp_bottom = False
+    case.field = W.fourier_field(rng, (5 * 3.0, 4 * 3.0, 6.0), amplitude=0.01)
+    roms = [mos.mos_reduce(ctx, mos.mos_build_cell(ctx, s)) for s in case.specs]
+    pd, pv = gpu_prescribed(mos, ctx, roms[0], case)
+    # Repeated entries: a later one overrides an earlier one on both paths.
+    pd = np.concatenate([pd[:7], pd])
+    pv = np.concatenate([pv[:7] + 1.0, pv])
+    dpd, dpv = torch.as_tensor(pd, device="cuda"), torch.as_tensor(pv, device="cuda")
+    for mixed in (False, True):
+        u_h, res_h, vm_h = solve_gpu(mos, ctx, roms, case, mixed, prescribed_dofs=pd, prescribed_values=pv)
+        u_d, res_d, vm_d = solve_gpu(mos, ctx, roms, case, mixed, prescribed_dofs=dpd, prescribed_values=dpv)
+        assert np.array_equal(u_h, u_d) and res_h == res_d
+        assert torch.equal(vm_h, vm_d)
+        eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=1 << 28)
+        u_e = torch.empty(u_h.size, dtype=torch.float64, device="cuda")
+        tk = eng.submit(case.nx_cells, case.ny_cells, case.cell_type, case.delta_T, u=u_e, clamp_bottom=False,
+                        prescribed_dofs=dpd, prescribed_values=dpv)
+        while tk not in eng.progress(16):
+            pass
+        assert eng.result(tk)[0] == 0
+        assert np.array_equal(u_e.cpu().numpy(), u_h)
+        eng.close()
+
+
+def test_device_resident_prescribed_list_rejects_bad_entries(mos, ctx):
+    """Entries of a device list are checked on the device: a DoF outside the
+    array or a non-finite value fails the problem with MOS_EINVAL (and writes
+    nothing out of bounds); the context keeps working."""
+    import torch
+    case = W.small_case(nx=3, ny=2, mesh=(4, 4, 6), interp=(3, 3, 3), pitch_x=3.0, pitch_y=3.0, height=6.0,
+                        tsv_diameter=1.6, seed=2)
+    roms = [mos.mos_reduce(ctx, mos.mos_build_cell(ctx, s)) for s in case.specs]
+    coords, _, _, _ = mos.mos_array_layout(ctx, case.nx_cells, case.ny_cells, roms[0])
+    n_dofs = 3 * coords.shape[0]
+    for dofs, vals in (([0, 1, n_dofs], [0.0, 0.0, 0.0]), ([0, -5, 2], [0.0, 0.0, 0.0]),
+                       ([0, 1, 2], [0.0, float("nan"), 0.0])):
+        with pytest.raises(mos.MosError) as e:
+            mos.mos_solve_array(ctx, roms, case.nx_cells, case.ny_cells, case.cell_type, case.delta_T,
+                                clamp_bottom=True,
+                                prescribed_dofs=torch.tensor(dofs, dtype=torch.int64, device="cuda"),
+                                prescribed_values=torch.tensor(vals, dtype=torch.float64, device="cuda"))
+        assert e.value.status == mos.MOS_EINVAL
+    u, res, vm = solve_gpu(mos, ctx, roms, case, False)
+    assert res <= 1e-12
 
 
 def _fullsize(mos, ctx, case, n_sample):

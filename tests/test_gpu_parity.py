@@ -244,3 +244,71 @@ def test_nodal_displacement(mos, ctx, case, mixed):
     # The bottom face is clamped: its FE nodes carry exactly zero displacement.
     mz1 = (sp.mesh[0] + 1) * (sp.mesh[1] + 1)
     assert np.all(got[:, :3 * mz1] == 0.0)
+
+
+@pytest.mark.parametrize("shape", [(5, 4), (16, 16)], ids=["5x4", "16x16"])
+def test_bf16_reconstruction_kernels_agree_bitwise(shape):
+    """The BF16-split reconstruction with two element blocks per workgroup
+    and the one-block form compute the same products in the same order, so
+    their outputs are bitwise equal (von Mises and the six components)."""
+    import os
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2411_12690_amd import mos
+    ctx = mos.Context(0)
+    spec = W.CellSpec(pitch_x=3.0, pitch_y=3.0, height=6.0, mesh=(4, 4, 7), interp=(4, 4, 4), tsv_diameter=1.6,
+                      liner_thickness=0.3)
+    roms = [mos.mos_reduce(ctx, mos.mos_build_cell(ctx, s)) for s in (spec, spec.dummy())]
+    nx, ny = shape
+    t = W.dummy_map(np.random.default_rng(4), nx * ny, 0.3)
+    sol = mos.mos_solve_array(ctx, roms, nx, ny, t, -250.0, clamp_bottom=True, mixed=True)
+    n_elem = roms[0].query(mos.MOS_Q_CELL_ELEMS)
+    outs = []
+    for v in ("1", "2"):
+        os.environ["MOS_RECON_BF16"] = v
+        try:
+            vm = torch.full((nx * ny, n_elem), float("nan"), dtype=torch.float32, device="cuda")
+            s6 = torch.full((nx * ny, n_elem, 6), float("nan"), dtype=torch.float32, device="cuda")
+            mos.mos_reconstruct(ctx, sol, vm=vm, sigma6=s6)
+            torch.cuda.synchronize()
+            outs.append((vm.cpu().numpy(), s6.cpu().numpy()))
+        finally:
+            del os.environ["MOS_RECON_BF16"]
+    assert np.isfinite(outs[0][0]).all() and np.isfinite(outs[1][1]).all()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("shape", [(5, 4), (16, 16)], ids=["5x4", "16x16"])
+def test_fp64_reconstruction_kernels_agree_bitwise(shape):
+    """The FP64 reconstruction with the cell operand streamed in
+    double-buffered chunks and the form that requests a block's whole operand
+    at once run the same MFMA chains, so their outputs are bitwise equal."""
+    import os
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2411_12690_amd import mos
+    ctx = mos.Context(0)
+    spec = W.CellSpec(pitch_x=3.0, pitch_y=3.0, height=6.0, mesh=(4, 4, 7), interp=(4, 4, 4), tsv_diameter=1.6,
+                      liner_thickness=0.3)
+    roms = [mos.mos_reduce(ctx, mos.mos_build_cell(ctx, s)) for s in (spec, spec.dummy())]
+    nx, ny = shape
+    t = W.dummy_map(np.random.default_rng(6), nx * ny, 0.3)
+    sol = mos.mos_solve_array(ctx, roms, nx, ny, t, -250.0, clamp_bottom=True)
+    n_elem = roms[0].query(mos.MOS_Q_CELL_ELEMS)
+    outs = []
+    for v in ("1", "2"):
+        os.environ["MOS_RECON_F64"] = v
+        try:
+            vm = torch.full((nx * ny, n_elem), float("nan"), dtype=torch.float64, device="cuda")
+            s6 = torch.full((nx * ny, n_elem, 6), float("nan"), dtype=torch.float64, device="cuda")
+            mos.mos_reconstruct(ctx, sol, vm=vm, sigma6=s6)
+            torch.cuda.synchronize()
+            outs.append((vm.cpu().numpy(), s6.cpu().numpy()))
+        finally:
+            del os.environ["MOS_RECON_F64"]
+    assert np.isfinite(outs[0][0]).all() and np.isfinite(outs[1][1]).all()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])

@@ -119,14 +119,15 @@ def case_c3(seed=0):
                      dummy_map(rng, 4096, 0.10), mixed=True)
 
 
-def case_c5(seed=0):
-    """200x200 array, 20x20x40 hexes with a 0.5 um liner, Fourier field on all
-    outer faces."""
+def case_c5(seed=0, n=200):
+    """n x n array (200 x 200 by default), 20x20x40 hexes with a 0.5 um
+    liner, Fourier field on all outer faces (smaller n: a sub-array of the
+    same cell with a field of the same kind over its own extent)."""
     rng = np.random.default_rng(seed)
     spec = CellSpec(mesh=(20, 20, 40), liner_thickness=0.5)
-    L = (200 * spec.pitch_x, 200 * spec.pitch_y, spec.height)
-    return ArrayCase("200x200 TSV+liner, 20x20x40 hex, cubic, Fourier boundary", [spec], 200, 200,
-                     np.zeros(40000, dtype=np.uint8), clamp_bottom=False,
+    L = (n * spec.pitch_x, n * spec.pitch_y, spec.height)
+    return ArrayCase(f"{n}x{n} TSV+liner, 20x20x40 hex, cubic, Fourier boundary", [spec], n, n,
+                     np.zeros(n * n, dtype=np.uint8), clamp_bottom=False,
                      field=fourier_field(rng, L), mixed=True)
 
 
