@@ -163,6 +163,22 @@ enum { MOS_OUT_VM = 1, MOS_OUT_SIGMA6 = 2 };
  * when its flag is not set. */
 mos_status mos_reconstruct(mos_ctx ctx, mos_sol sol, uint32_t outputs, void *vm, void *sigma6);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * outputs of mos_reconstruct, bit for bit (same kernels, same order), with
+ * its device scratch -- the job table, the cell-major gather of the
+ * solution (8 ldk bytes per cell slot) and, for MOS_MIXED, its BF16 hi/lo
+ * split (64 nks bytes per slot) -- taken from one static array of 32 MiB
+ * per device that the library holds from the first mos_ctx_create on that
+ * device until the process ends.  Nothing is allocated on the device.  A
+ * solution whose scratch exceeds 32 MiB is rejected with MOS_EINVAL (with a
+ * cubic basis: about 23,000 cells in FP64, 15,000 mixed).  All calls on one
+ * device share the array and each leaves its contents behind (nothing in it
+ * needs to start at zero): calls that overlap on one device (other threads,
+ * or other contexts' streams) race.  Returns after the context's stream
+ * has finished the call's work. */
+mos_status mos_reconstruct_noalloc(mos_ctx ctx, mos_sol sol, uint32_t outputs, void *vm, void *sigma6);
+
 /* Sec. 4.3 with eq. 15: the fine-mesh displacement of every cell,
  * u_cell = dT f_T + Phi u_r,cell over the cell's FE DoFs (DoF 3 node +
  * component, node and component order as in the cell numbering contract).

@@ -198,6 +198,7 @@ mos_status mos_ctx_create(int device, void *hip_stream, const mos_allocator *all
         return MOS_EINVAL;
     }
     MOS_HIP(hipSetDevice(device));
+    MOS_TRY(noalloc_scratch_init(device));
     mos_ctx c = new (std::nothrow) mos_ctx_s();
     if (!c) {
         set_error("out of host memory");
@@ -661,6 +662,25 @@ mos_status mos_reconstruct(mos_ctx ctx, mos_sol sol, uint32_t outputs, void *vm,
     }
     MOS_HIP(hipSetDevice(ctx->device));
     return reconstruct(ctx, sol, outputs, vm, sigma6);
+}
+
+mos_status mos_reconstruct_noalloc(mos_ctx ctx, mos_sol sol, uint32_t outputs, void *vm, void *sigma6) {
+    if (!ctx || !sol || sol->kind != KIND_SOL || sol->ctx != ctx) {
+        set_error("invalid context or solution handle");
+        return MOS_EINVAL;
+    }
+    if ((outputs & ~(uint32_t)(MOS_OUT_VM | MOS_OUT_SIGMA6)) || outputs == 0 ||
+        ((outputs & MOS_OUT_VM) && !vm) || ((outputs & MOS_OUT_SIGMA6) && !sigma6)) {
+        set_error("outputs must select VM and/or SIGMA6 with non-NULL buffers");
+        return MOS_EINVAL;
+    }
+    for (mos_rom r : sol->roms)
+        if (!r || r->kind != KIND_ROM) {
+            set_error("mos_reconstruct_noalloc: a ROM of this solution has been freed");
+            return MOS_EINVAL;
+        }
+    MOS_HIP(hipSetDevice(ctx->device));
+    return reconstruct_noalloc(ctx, sol, outputs, vm, sigma6);
 }
 
 mos_status mos_reconstruct_displacement(mos_ctx ctx, mos_sol sol, void *u_nodal) {

@@ -187,6 +187,15 @@ constexpr int PLANE_MAX_GRID = 256;
 mos_status plane_basis(mos_rom r, int grid);
 // recon.hip
 mos_status reconstruct(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void *sigma6);
+// The same reconstruction with its device scratch in the library's static
+// per-device array (NOALLOC_SCRATCH_BYTES; MOS_EINVAL for a solution that
+// needs more): no device allocation.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(32) << 20;
+mos_status reconstruct_noalloc(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void *sigma6);
+// Address of that array on `device` (current when called), looked up once
+// per device at context creation; noalloc_scratch gives it back (NULL before).
+mos_status noalloc_scratch_init(int device);
+void *noalloc_scratch(int device);
 mos_status reconstruct_plane(mos_ctx ctx, mos_sol s, int grid, void *vm);
 mos_status reconstruct_displacement(mos_ctx ctx, mos_sol s, double *u_nodal);
 // FP64 MFMA reconstruction with one element block of Psi staged in LDS per
@@ -215,7 +224,7 @@ mos_status recon_f64_jobs(mos_ctx ctx, const mos_rom *roms, int n_types, const s
 int64_t recon_bf16_scratch(const mos_rom r, int n_sb);
 mos_status recon_bf16_jobs(mos_ctx ctx, const mos_rom *roms, int n_types, const std::vector<ReconJob> *jobs,
                            ReconJob *dev_jobs, ReconJob *host_jobs, const double *U, int ld, const int32_t *perm,
-                           void *scratch);
+                           void *split);
 
 // ---- host helpers (api.cpp) ----
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }

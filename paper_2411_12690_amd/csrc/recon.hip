@@ -10,6 +10,7 @@
 // D[l/16 + 4q][l%16] in register q.
 #include <cmath>
 #include <cstdlib>
+#include <mutex>
 
 #include "bf16.h"
 #include "mesh.h"
@@ -666,7 +667,7 @@ int recon_bf16_variant() {
 
 mos_status recon_bf16_jobs(mos_ctx ctx, const mos_rom *roms, int n_types, const std::vector<ReconJob> *jobs,
                            ReconJob *dev_jobs, ReconJob *host_jobs, const double *U, int ld, const int32_t *perm,
-                           void *scratch) {
+                           void *split) {
     if (n_types < 1 || n_types > MAX_TYPES) return MOS_EINVAL;
     const mos_rom r = roms[0];
     for (int t = 0; t < n_types; ++t)
@@ -689,7 +690,7 @@ mos_status recon_bf16_jobs(mos_ctx ctx, const mos_rom *roms, int n_types, const 
             host_jobs[first[t] + i].sb_off += vbase[t];
         }
     MOS_HIP(hipMemcpyAsync(dev_jobs, host_jobs, first[n_types] * sizeof(ReconJob), hipMemcpyHostToDevice, st));
-    bf16x8 *ub_hi = (bf16x8 *)scratch, *ub_lo = ub_hi + (size_t)total * r->nks * 64;
+    bf16x8 *ub_hi = (bf16x8 *)split, *ub_lo = ub_hi + (size_t)total * r->nks * 64;
     const int64_t nfrag = (int64_t)total * r->nks * 64;
     hipLaunchKernelGGL(k_split_u, dim3(ceil_div(nfrag, 256)), dim3(256), 0, st, U, ld, (const ReconJob *)dev_jobs,
                        first[n_types], total, r->ldk, r->nks, ub_hi, ub_lo);
@@ -782,10 +783,59 @@ __global__ __launch_bounds__(256) void k_nodal_u(const double *phi, int ldp, int
     }
 }
 
+// Scratch of the allocation-free reconstruction (mos_reconstruct_noalloc):
+// the job table, the cell-major gather of u and, in the mixed path, its BF16
+// split.  Each device holds its own copy until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress gives for the
+// current device (noalloc_scratch_init), never through the symbol itself.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+mos_status noalloc_scratch_init(int device) {
+    if (device < 0 || device >= MAX_DEVICES) {
+        set_error("device %d beyond the %d devices the scratch table holds", device, MAX_DEVICES);
+        return MOS_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return MOS_OK;
+    void *p = nullptr;
+    MOS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[device] = p;
+    return MOS_OK;
+}
+
+void *noalloc_scratch(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
+namespace {
+// Device bytes recon_with takes for its job table, the gather of u and (mixed)
+// the BF16 split, each rounded to 256.
+size_t recon_workspace(mos_sol s, const std::vector<mos_rom> &R, size_t *off_u, size_t *off_split) {
+    const size_t jobs = round_up((int64_t)(MAX_TYPES * sizeof(ReconJob)), 256);
+    const size_t u = round_up((int64_t)s->ldk * s->n_pc * (int64_t)sizeof(double), 256);
+    const bool split = s->precision == MOS_MIXED && R[0]->psi_hi;
+    const size_t b = split ? (size_t)round_up(recon_bf16_scratch(R[0], s->n_pc / 16), 256) : 0;
+    *off_u = jobs;
+    *off_split = jobs + u;
+    return jobs + u + b;
+}
+}  // namespace
+
 // The solution's cells through the stress bases R[t] (one per cell type:
 // the centroid bases of the solution's ROMs, or their plane bases), which
-// share ldk, n_eblk and n_elem (output points per cell).
-static mos_status recon_with(mos_ctx ctx, mos_sol s, const std::vector<mos_rom> &R, void *v, void *g) {
+// share ldk, n_eblk and n_elem (output points per cell).  Device scratch
+// comes from `ws` (ws_bytes long, nothing allocated) when it is given, else
+// from the context's allocator for the duration of the call.
+static mos_status recon_with(mos_ctx ctx, mos_sol s, const std::vector<mos_rom> &R, void *v, void *g,
+                             void *ws = nullptr, size_t ws_bytes = 0) {
     hipStream_t st = ctx->stream;
     const int n_eblk = R[0]->n_eblk, n_pts = R[0]->n_elem;
     ReconTable tt{};
@@ -801,9 +851,28 @@ static mos_status recon_with(mos_ctx ctx, mos_sol s, const std::vector<mos_rom> 
         DeviceArena &a;
         ~Guard() { a.release(); }
     } guard{tmp};
-    double *U = nullptr;
+    size_t off_u = 0, off_split = 0;
+    const size_t need = recon_workspace(s, R, &off_u, &off_split);
+    char *base = static_cast<char *>(ws);
+    if (ws) {
+        if (need > ws_bytes) {
+            set_error("reconstruction of %d cell slots needs %zu bytes of scratch; the allocation-free entry point "
+                      "holds %zu",
+                      s->n_pc, need, ws_bytes);
+            return MOS_EINVAL;
+        }
+    } else {
+        void *p = nullptr;
+        MOS_TRY(tmp.alloc(need, &p));
+        base = static_cast<char *>(p);
+    }
+    ReconJob *dj = reinterpret_cast<ReconJob *>(base);
+    double *U = reinterpret_cast<double *>(base + off_u);
+    // Host copy of the job table: pinned memory of the context (the call
+    // waits for the stream before it returns, so the buffer is free again).
+    ReconJob *hj = reinterpret_cast<ReconJob *>(static_cast<char *>(ctx->pinned) + 2048);
+    static_assert(MAX_TYPES * sizeof(ReconJob) <= 2048, "job table exceeds the pinned buffer");
     const int64_t total = (int64_t)s->ldk * s->n_pc;
-    MOS_TRY(tmp.alloc_n(total, &U));
     hipLaunchKernelGGL(k_gather_u, dim3(ceil_div(total, 256)), dim3(256), 0, st, s->u, s->gidx, U, total);
     MOS_LAUNCH_CHECK();
     dim3 grid(n_eblk, ceil_div(s->n_pc / 16, 4));
@@ -813,25 +882,18 @@ static mos_status recon_with(mos_ctx ctx, mos_sol s, const std::vector<mos_rom> 
             const int nsb = (s->seg[t + 1] - s->seg[t]) / 16;
             if (nsb > 0) jobs[t].push_back(ReconJob{s->seg[t] / 16, 0, nsb, 0, s->delta_T, v, g});
         }
-        void *scratch = nullptr;
-        MOS_TRY(tmp.alloc((size_t)recon_bf16_scratch(R[0], s->n_pc / 16), &scratch));
-        ReconJob *dj = nullptr;
-        MOS_TRY(tmp.alloc_n(MAX_TYPES, &dj));
-        std::vector<ReconJob> hj(MAX_TYPES);
-        MOS_TRY(recon_bf16_jobs(ctx, R.data(), s->n_types, jobs.data(), dj, hj.data(), U, s->n_pc, s->perm, scratch));
-        MOS_HIP(hipStreamSynchronize(st));  // the host job table is a local
+        MOS_TRY(recon_bf16_jobs(ctx, R.data(), s->n_types, jobs.data(), dj, hj, U, s->n_pc, s->perm,
+                                base + off_split));
+        MOS_HIP(hipStreamSynchronize(st));  // the host job table is reused by the next call
     } else if (s->ldk / 4 <= RECON_F64_LDS_KS) {
         std::vector<std::vector<ReconJob>> jobs(s->n_types);
         for (int t = 0; t < s->n_types; ++t) {
             const int nsb = (s->seg[t + 1] - s->seg[t]) / 16;
             if (nsb > 0) jobs[t].push_back(ReconJob{s->seg[t] / 16, 0, nsb, 0, s->delta_T, v, g});
         }
-        ReconJob *dj = nullptr;
-        MOS_TRY(tmp.alloc_n(MAX_TYPES, &dj));
-        std::vector<ReconJob> hj(MAX_TYPES);
-        MOS_TRY(recon_f64_jobs(ctx, R.data(), s->n_types, jobs.data(), dj, hj.data(), U, s->n_pc, s->perm,
+        MOS_TRY(recon_f64_jobs(ctx, R.data(), s->n_types, jobs.data(), dj, hj, U, s->n_pc, s->perm,
                                s->precision != MOS_FP64));
-        MOS_HIP(hipStreamSynchronize(st));  // the host job table is a local
+        MOS_HIP(hipStreamSynchronize(st));  // the host job table is reused by the next call
     } else if (s->precision == MOS_FP64)
         launch_timed(ctx, MOS_K_RECON, k_recon_f64<double>, grid, dim3(256), 0, st, tt, (const double *)U,
                      (const int32_t *)s->perm, s->n_pc, s->ldk, n_pts, s->delta_T, (double *)v, (double *)g);
@@ -846,6 +908,16 @@ static mos_status recon_with(mos_ctx ctx, mos_sol s, const std::vector<mos_rom> 
 mos_status reconstruct(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void *sigma6) {
     return recon_with(ctx, s, s->roms, (outputs & MOS_OUT_VM) ? vm : nullptr,
                       (outputs & MOS_OUT_SIGMA6) ? sigma6 : nullptr);
+}
+
+mos_status reconstruct_noalloc(mos_ctx ctx, mos_sol s, uint32_t outputs, void *vm, void *sigma6) {
+    void *ws = noalloc_scratch(ctx->device);
+    if (!ws) {
+        set_error("the allocation-free scratch of device %d is not set up", ctx->device);
+        return MOS_EHIP;
+    }
+    return recon_with(ctx, s, s->roms, (outputs & MOS_OUT_VM) ? vm : nullptr,
+                      (outputs & MOS_OUT_SIGMA6) ? sigma6 : nullptr, ws, NOALLOC_SCRATCH_BYTES);
 }
 
 mos_status reconstruct_displacement(mos_ctx ctx, mos_sol s, double *u_nodal) {

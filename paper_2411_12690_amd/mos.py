@@ -21,7 +21,7 @@ MOS_OUT_VM, MOS_OUT_SIGMA6 = 1, 2
  MOS_Q_GLOBAL_DOFS, MOS_Q_ITERS, MOS_Q_REFINES, MOS_Q_DEVICE_BYTES) = range(1, 11)
 
 EXPORTED = ("mos_ctx_create", "mos_ctx_destroy", "mos_build_cell", "mos_reduce", "mos_solve_array",
-            "mos_reconstruct", "mos_reconstruct_plane", "mos_reconstruct_displacement", "mos_get_solution", "mos_query", "mos_cell_export", "mos_rom_export",
+            "mos_reconstruct", "mos_reconstruct_noalloc", "mos_reconstruct_plane", "mos_reconstruct_displacement", "mos_get_solution", "mos_query", "mos_cell_export", "mos_rom_export",
             "mos_array_layout", "mos_engine_create", "mos_engine_submit", "mos_engine_progress",
             "mos_engine_result", "mos_engine_option", "mos_engine_stats", "mos_engine_graph_stats", "mos_engine_destroy", "mos_timing_start", "mos_timing_stop",
             "mos_cell_free", "mos_rom_free", "mos_sol_free", "mos_last_error")
@@ -81,6 +81,7 @@ def _load():
         "mos_reduce": (ctypes.c_int, [vp, vp, P(vp)]),
         "mos_solve_array": (ctypes.c_int, [vp, P(ArrayDesc), P(vp), ctypes.c_int32, P(vp)]),
         "mos_reconstruct": (ctypes.c_int, [vp, vp, ctypes.c_uint32, vp, vp]),
+        "mos_reconstruct_noalloc": (ctypes.c_int, [vp, vp, ctypes.c_uint32, vp, vp]),
         "mos_reconstruct_plane": (ctypes.c_int, [vp, vp, ctypes.c_int32, vp]),
         "mos_reconstruct_displacement": (ctypes.c_int, [vp, vp, vp]),
         "mos_get_solution": (ctypes.c_int, [vp, vp, P(ctypes.c_double), P(ctypes.c_int32)]),
@@ -393,10 +394,12 @@ def mos_engine_destroy(engine):
     engine.close()
 
 
-def mos_reconstruct(ctx, sol, vm=None, sigma6=None):
+def mos_reconstruct(ctx, sol, vm=None, sigma6=None, noalloc=False):
     """Write von Mises and/or the six stress components into caller-owned
     device tensors ([n_cells, n_elem] and [n_cells, n_elem, 6]); float64 for
-    an FP64 solution, float32 for a mixed one."""
+    an FP64 solution, float32 for a mixed one.  noalloc=True calls
+    mos_reconstruct_noalloc (the library's static scratch, no device
+    allocation)."""
     torch = ctx.torch
     want = torch.float32 if sol.precision == MOS_MIXED else torch.float64
     flags = 0
@@ -407,9 +410,15 @@ def mos_reconstruct(ctx, sol, vm=None, sigma6=None):
         if t.dtype != want or tuple(t.shape) != shape or not t.is_contiguous() or not t.is_cuda:
             raise ValueError(f"output must be a contiguous {want} device tensor of shape {shape}")
         flags |= flag
-    _check(lib().mos_reconstruct(ctx.ptr, sol.ptr, flags, ctypes.c_void_p(vm.data_ptr() if vm is not None else 0),
-                                 ctypes.c_void_p(sigma6.data_ptr() if sigma6 is not None else 0)),
-           "mos_reconstruct")
+    fn = lib().mos_reconstruct_noalloc if noalloc else lib().mos_reconstruct
+    _check(fn(ctx.ptr, sol.ptr, flags, ctypes.c_void_p(vm.data_ptr() if vm is not None else 0),
+              ctypes.c_void_p(sigma6.data_ptr() if sigma6 is not None else 0)),
+           "mos_reconstruct_noalloc" if noalloc else "mos_reconstruct")
+
+
+def mos_reconstruct_noalloc(ctx, sol, vm=None, sigma6=None):
+    """mos_reconstruct through the allocation-free entry point."""
+    mos_reconstruct(ctx, sol, vm=vm, sigma6=sigma6, noalloc=True)
 
 
 def mos_reconstruct_displacement(ctx, sol, u_nodal):
