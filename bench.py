@@ -133,12 +133,15 @@ def recorded_traffic(kernel, workload, precision):
     for e in rec.get("entries", []):
         if (e["kernel"], e["workload"], e["precision"]) != (kernel, workload, precision):
             continue
-        texts = [kernel_source(os.path.join(ROOT, e["source"]), f) for f in e["functions"]]
+        funs, want = e.get("functions"), e.get("functions_sha256")
+        if not funs or not want:
+            return None
+        texts = [kernel_source(os.path.join(ROOT, e.get("source", "")), f) for f in funs]
         if any(t is None for t in texts):
             return None
-        if hashlib.sha256("\n".join(texts).encode()).hexdigest() != e["functions_sha256"]:
+        if hashlib.sha256("\n".join(texts).encode()).hexdigest() != want:
             return None
-        return e["traffic_bytes_per_launch"]
+        return e.get("traffic_bytes_per_launch")
     return None
 
 
