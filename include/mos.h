@@ -303,8 +303,9 @@ mos_status mos_engine_result(mos_engine e, int64_t ticket, int32_t *status, doub
 /* MOS_OPT_GEMM_SPLIT sets how many consecutive 16-cell blocks one wave
  * (variant 2) or one workgroup (variant 3) of the K_r-stationary GEMM
  * streams: 0 (default) lets the engine tune it online per batch size (each
- * candidate in {1, 2, 4, 8, 16, 32}, for each operand path allowed, is timed
- * three times with stream events and the fastest kept); 1 <= k <= 64 fixes
+ * candidate in {1, 2, 4, 8, 16, 32}, for each operand path allowed, and for
+ * variant 3 also ceil(blocks / compute units), one workgroup per unit, is
+ * timed three times with stream events and the fastest kept); 1 <= k <= 64 fixes
  * it.  It only decides which wave computes which output tile, so results do
  * not depend on it; it may be changed at any time (tuning starts over). */
 /* MOS_OPT_UPDATE_WIDTH sets the threads per workgroup of the PCG vector

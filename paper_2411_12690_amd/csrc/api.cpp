@@ -206,6 +206,11 @@ mos_status mos_ctx_create(int device, void *hip_stream, const mos_allocator *all
     }
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        c->n_cu = cus;
+    else
+        (void)hipGetLastError();
     if (alloc && alloc->alloc) {
         c->alloc = *alloc;
         c->user_alloc = true;

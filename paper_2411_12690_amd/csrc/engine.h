@@ -87,8 +87,12 @@ struct GemmTuner {
     // per workgroup) and a work split (slot blocks per wave or workgroup).
     // All candidates compute the same MFMA chains, so the choice never
     // changes results.
-    static constexpr int N_SPW = 6;
-    static constexpr int SPW[N_SPW] = {1, 2, 4, 8, 16, 32};
+    // A split of CHIP_SPLIT stands for the one that gives every compute
+    // unit one workgroup (the LDS path runs one per CU): ceil(slot blocks /
+    // CUs), so a launch fills the chip in a single even round.
+    static constexpr int N_SPW = 7;
+    static constexpr int CHIP_SPLIT = -1;
+    static constexpr int SPW[N_SPW] = {1, 2, 4, 8, 16, 32, CHIP_SPLIT};
     static constexpr int MAX_CAND = 2 * N_SPW;
     static constexpr int REPS = 3;
     int n_cand = 0;

@@ -384,6 +384,14 @@ __device__ __forceinline__ uint64_t run_mask(const int32_t *sb_rom, const int32_
     return __ballot(live);
 }
 
+// Wait for every outstanding memory operation of this wave (s_waitcnt
+// vmcnt(0) lgkmcnt(0): loads through a generic pointer count in both).  Used
+// at the end of a branch that loads, so that the branch leaves no load
+// pending at the join: the compiler's wait insertion otherwise merges the two
+// paths pessimistically and makes the next MFMA chain wait for loads issued
+// after the branch (the next tile's prefetch).
+__device__ __forceinline__ void vm_wait_all() { __builtin_amdgcn_s_waitcnt(0x0070); }
+
 // First live slot block at or after sl given the run's mask (s_end if none).
 __device__ __forceinline__ int next_in_mask(uint64_t mask, int s_begin, int s_end, int sl) {
     const int off = sl - s_begin;
@@ -466,8 +474,10 @@ __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, c
         // The epilogue's operand values, requested before this block's
         // chain (and before the next block's loads) so they are not waited
         // on behind them.
+        // (Loaded whether or not partials are wanted: a load on one path
+        // only would make the chain below wait for every later load.)
         T t[4] = {T(0), T(0), T(0), T(0)};
-        if (PREFETCH_T && pdel) {
+        if (PREFETCH_T) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) t[q] = Mc[(size_t)(rb * 16 + Mfma<T>::row(lane, q)) * ld_slots + col];
         }
@@ -476,11 +486,14 @@ __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, c
 #pragma unroll
             for (int k = 0; k < KS; ++k) a[k] = k < ks ? ap[(size_t)(4 * k) * ldk] : T(0);
             cur = rom;
+            vm_wait_all();
         }
         const int nx = next_live(sl + 1);
         v4 acc = {0, 0, 0, 0};
-        if (PIPELINE && nx < s_end) {
-            const T *bn = lane_b + (size_t)(sb_base + nx) * 16;
+        if (PIPELINE) {
+            // The last block's chain re-reads its own operand, so every
+            // pass takes this one path.
+            const T *bn = lane_b + (size_t)(sb_base + (nx < s_end ? nx : sl)) * 16;
 #pragma unroll
             for (int k = 0; k < KS; ++k)
                 if (k < ks) {
@@ -588,9 +601,16 @@ __global__ __launch_bounds__(704) void k_bgemm_wg(const void *const *kr_tab, con
 #pragma unroll
             for (int k = 0; k < KS; ++k) a[k] = k < ks ? ap[(size_t)(4 * k) * ldk] : T(0);
             cur = rom;
+            vm_wait_all();
         }
+        // The next tile's loads are issued on every pass (the last one
+        // re-reads this tile), so no path leaves them conditional and the
+        // chain below never waits on them.
         const int nx = next_live(sl + 1);
-        if (nx < s_end) fetch(sb_base + nx);
+        fetch(sb_base + (nx < s_end ? nx : sl));
+        // Keep the loads ahead of the chain (the scheduler would otherwise
+        // sink them next to their use in put()).
+        __builtin_amdgcn_sched_barrier(0);
         const T *tb = tiles + (size_t)buf * ldk * 16;
         v4 acc = {0, 0, 0, 0};
 #pragma unroll
@@ -2895,6 +2915,7 @@ void GemmTuner::configure(int paths, int fixed_spw) {
             cand_spw[n_cand++] = fixed_spw;
         } else {
             for (int k = 0; k < N_SPW; ++k) {
+                if (SPW[k] == CHIP_SPLIT && path != 1) continue;
                 cand_path[n_cand] = path;
                 cand_spw[n_cand++] = SPW[k];
             }
@@ -2930,7 +2951,9 @@ mos_status rows_step(mos_engine e, int ks, int hw_sb) {
     GemmTuner &Tn = e->tuner;
     const void *const *tab = (const void *const *)(sizeof(T) == 4 ? e->kr32_tab : e->kr64_tab);
     auto launch = [&](int cand) {
-        return launch_cell_gemm<T>(e->ctx, MOS_K_CELL_GEMM, Tn.cand_path[cand], ks, Tn.cand_spw[cand], st, tab,
+        int spw = Tn.cand_spw[cand];
+        if (spw == GemmTuner::CHIP_SPLIT) spw = std::min(64, std::max(1, ceil_div(hw_sb, e->ctx->n_cu)));
+        return launch_cell_gemm<T>(e->ctx, MOS_K_CELL_GEMM, Tn.cand_path[cand], ks, spw, st, tab,
                                    e->sb_rom, e->sb_prob, (const T *)e->Mc, (T *)e->Yi, e->ld_slots, hw_sb,
                                    (const ProbState *)e->ps, e->pdel, 1, ProbSel{});
     };

@@ -61,6 +61,7 @@ struct DeviceArena {
 
 struct mos_ctx_s {
     int device = 0;
+    int n_cu = 256;  // compute units of the device
     hipStream_t stream = nullptr;
     mos_allocator alloc{};
     bool user_alloc = false;

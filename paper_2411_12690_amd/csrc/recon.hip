@@ -453,14 +453,18 @@ __global__ __launch_bounds__(256, KSMAX <= 6 ? 2 : 1) void k_recon_bf16(const bf
 // as often per MFMA as with one block per workgroup.  Each wave streams CB
 // slot blocks at a time, the next k-step's fragments requested while the
 // current one's MFMAs run.  Products, their order and the epilogue are
-// those of k_recon_bf16, so the results are bitwise the same.
-template <int KSMAX, int CB>
+// those of k_recon_bf16, so the results are bitwise the same.  EXACT: the
+// basis takes all KSMAX k-steps, so no step's loads sit behind a run-time
+// test (a load on one path only makes the next MFMA wait for every load
+// issued after it, the next step's prefetch included).
+template <int KSMAX, int CB, bool EXACT>
 __global__ __launch_bounds__(512, 1) void k_recon_bf16_x2(const bf16x8 *psi_hi, const bf16x8 *psi_lo,
                                                           const double *sig_t, const bf16x8 *ub_hi,
                                                           const bf16x8 *ub_lo, const int32_t *perm,
                                                           const ReconJob *jobs, int n_jobs, int v_begin, int n_v,
                                                           int chunk, int nks, int n_elem, int n_eblk) {
     constexpr int NW = 8;
+    if (EXACT) nks = KSMAX;
     __shared__ bf16x8 lds[2][2][6][KSMAX][64];
     __shared__ double st_lds[32][6];
     const int eb0 = 2 * (int)blockIdx.x;
@@ -525,6 +529,8 @@ __global__ __launch_bounds__(512, 1) void k_recon_bf16_x2(const bf16x8 *psi_hi, 
                         nl[cb] = ub_lo[fb[cb] + (size_t)(ks + 1) * 64];
                     }
                 }
+                // The next step's loads stay ahead of this step's MFMAs.
+                if (EXACT) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
 #pragma unroll
@@ -713,9 +719,10 @@ mos_status recon_bf16_jobs(mos_ctx ctx, const mos_rom *roms, int n_types, const 
             const int nx2 = ceil_div(r->n_eblk, 2);
             const int ny2 = std::max(1, std::min(n_v / 32, ceil_div(512, nx2)));
             const int chunk2 = ceil_div(n_v, ny2);
-            launch_timed(ctx, MOS_K_RECON, k_recon_bf16_x2<6, 2>, dim3(nx2, ceil_div(n_v, chunk2)), dim3(512), 0, st,
-                         ph, pl, (const double *)roms[t]->sig_t, (const bf16x8 *)ub_hi, (const bf16x8 *)ub_lo, perm, dj,
-                         nj, vbase[t], n_v, chunk2, r->nks, r->n_elem, r->n_eblk);
+            auto kern = r->nks == 6 ? k_recon_bf16_x2<6, 2, true> : k_recon_bf16_x2<6, 2, false>;
+            launch_timed(ctx, MOS_K_RECON, kern, dim3(nx2, ceil_div(n_v, chunk2)), dim3(512), 0, st, ph, pl,
+                         (const double *)roms[t]->sig_t, (const bf16x8 *)ub_hi, (const bf16x8 *)ub_lo, perm, dj, nj,
+                         vbase[t], n_v, chunk2, r->nks, r->n_elem, r->n_eblk);
         } else if (r->nks <= 6)
             launch_timed(ctx, MOS_K_RECON, k_recon_bf16<6, 4>, grid, dim3(256), 0, st, ph, pl,
                          (const double *)roms[t]->sig_t, (const bf16x8 *)ub_hi, (const bf16x8 *)ub_lo, perm, dj, nj,
