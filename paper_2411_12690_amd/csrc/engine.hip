@@ -25,6 +25,7 @@
 #include "engine.h"
 #include "mesh.h"
 #include "mos_internal.h"
+#include "waitcnt.h"
 
 namespace mos {
 namespace {
@@ -383,14 +384,6 @@ __device__ __forceinline__ uint64_t run_mask(const int32_t *sb_rom, const int32_
     *rom_lane = rom;
     return __ballot(live);
 }
-
-// Wait for every outstanding memory operation of this wave (s_waitcnt
-// vmcnt(0) lgkmcnt(0): loads through a generic pointer count in both).  Used
-// at the end of a branch that loads, so that the branch leaves no load
-// pending at the join: the compiler's wait insertion otherwise merges the two
-// paths pessimistically and makes the next MFMA chain wait for loads issued
-// after the branch (the next tile's prefetch).
-__device__ __forceinline__ void vm_wait_all() { __builtin_amdgcn_s_waitcnt(0x0070); }
 
 // First live slot block at or after sl given the run's mask (s_end if none).
 __device__ __forceinline__ int next_in_mask(uint64_t mask, int s_begin, int s_end, int sl) {
