@@ -15,7 +15,10 @@ What is computed, with the passage it follows:
   functions into A alpha = b (eq. 6-7).
 * The unit block: a p x p x h silicon cuboid with a centred copper via of
   diameter d and an optional dielectric liner of thickness t (Sec. 4.2,
-  Fig. 2).
+  Fig. 2).  The method applies to any repeated fine structure (Sec. 4.1); a
+  micro-bump block (a solder column with metal pads at both ends, in
+  underfill) is the second structure built here, read as stated in
+  ``Cell.material_map``.
 
 Readings where the paper is silent (each listed in the design doc): the element is
 the trilinear 8-node hexahedron with 2x2x2 Gauss quadrature; the mesh is a
@@ -28,8 +31,10 @@ import math
 import numpy as np
 import scipy.sparse as sp
 
-# Material codes used by the cell material map.
+# Material codes used by the cell material map.  A micro-bump block uses the
+# same three slots: underfill (MATRIX), solder column (VIA), pads (LINER).
 MATRIX, VIA, LINER = 0, 1, 2
+PAD = LINER
 
 # Voigt order of the strain and stress vectors; shears are engineering shears.
 VOIGT = ("xx", "yy", "zz", "xy", "yz", "zx")
@@ -194,22 +199,32 @@ class Cell:
         return (3 * en[:, :, None] + np.arange(3)[None, None, :]).reshape(self.n_elem, 24)
 
     def material_map(self):
-        """Material code per element from the centroid's distance to the via
-        axis (x, y) = (p_x/2, p_y/2): via if r < d/2, liner if r < d/2 + t,
-        matrix otherwise (strict comparisons of squared distances)."""
+        """Material code per element from the centroid's distance r to the
+        block's vertical axis (x, y) = (p_x/2, p_y/2), strict comparisons of
+        squared distances.  TSV block: via if r < d/2, liner if r < d/2 + t,
+        matrix otherwise.  Micro-bump block (structure "bump"): inside the
+        column (r < d/2) a pad if the centroid height z < t_pad or
+        z > h - t_pad, solder otherwise; underfill outside."""
         d = float(self.spec.tsv_diameter)
         t = float(self.spec.liner_thickness)
+        bump = getattr(self.spec, "structure", "tsv") == "bump"
+        t_pad = float(getattr(self.spec, "pad_thickness", 0.0))
         out = np.full(self.n_elem, MATRIX, dtype=np.uint8)
         r_via2 = (d / 2.0) ** 2
         r_lin2 = (d / 2.0 + t) ** 2
         e = 0
         for ec in range(self.mz):
+            zc = (ec + 0.5) * self.h / self.mz
+            in_pad = zc < t_pad or zc > self.h - t_pad
             for eb in range(self.my):
                 dy = (eb + 0.5) * self.py / self.my - self.py / 2.0
                 for ea in range(self.mx):
                     dx = (ea + 0.5) * self.px / self.mx - self.px / 2.0
                     r2 = dx * dx + dy * dy
-                    if d > 0.0 and r2 < r_via2:
+                    if bump:
+                        if d > 0.0 and r2 < r_via2:
+                            out[e] = PAD if in_pad else VIA
+                    elif d > 0.0 and r2 < r_via2:
                         out[e] = VIA
                     elif d > 0.0 and r2 < r_lin2:
                         out[e] = LINER

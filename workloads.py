@@ -18,6 +18,9 @@ import numpy as np
 SI = (130.0e3, 0.28, 2.6e-6)      # silicon matrix
 CU = (110.0e3, 0.35, 17.0e-6)     # copper via
 SIO2 = (71.0e3, 0.16, 0.5e-6)     # dielectric liner
+# Micro-bump layer (representative values; the paper fixes none for bumps).
+UNDERFILL = (8.0e3, 0.30, 30.0e-6)
+SNAG = (50.0e3, 0.36, 22.0e-6)    # SnAg solder
 
 
 @dataclass(frozen=True)
@@ -32,9 +35,15 @@ class CellSpec:
     via: tuple = CU
     liner: tuple = SIO2
     interp: tuple = (4, 4, 4)             # Lagrange nodes per axis
+    # "tsv": a via through the block with an optional liner around it.
+    # "bump": a micro-bump block; tsv_diameter is the bump column's diameter,
+    # `via` its solder, `liner` the metal of the pads at its two ends
+    # (pad_thickness each) and `matrix` the underfill around it.
+    structure: str = "tsv"
+    pad_thickness: float = 0.0
 
     def dummy(self):
-        return replace(self, tsv_diameter=0.0, liner_thickness=0.0)
+        return replace(self, tsv_diameter=0.0, liner_thickness=0.0, pad_thickness=0.0)
 
 
 @dataclass
@@ -129,6 +138,26 @@ def case_c5(seed=0, n=200):
     return ArrayCase(f"{n}x{n} TSV+liner, 20x20x40 hex, cubic, Fourier boundary", [spec], n, n,
                      np.zeros(n * n, dtype=np.uint8), clamp_bottom=False,
                      field=fourier_field(rng, L), mixed=True)
+
+
+def bump_spec(**kw):
+    """A micro-bump block: 40 x 40 x 20 um of underfill with a 25 um SnAg
+    column and 3 um copper pads at both ends, 16 x 16 x 16 hexes, cubic faces."""
+    base = dict(pitch_x=40.0, pitch_y=40.0, height=20.0, mesh=(16, 16, 16), tsv_diameter=25.0,
+                matrix=UNDERFILL, via=SNAG, liner=CU, structure="bump", pad_thickness=3.0)
+    base.update(kw)
+    return CellSpec(**base)
+
+
+def case_bump(seed=0, n=100, missing=0.05):
+    """n x n micro-bump layer between two clamped faces (substrate below, die
+    above), cooled by 200 K after reflow; a fraction of sites without a bump
+    (pure underfill blocks) drawn from the seed."""
+    rng = np.random.default_rng(seed)
+    spec = bump_spec()
+    return ArrayCase(f"{n}x{n} micro-bump layer, 16x16x16 hex, cubic, both faces clamped", [spec, spec.dummy()],
+                     n, n, dummy_map(rng, n * n, missing), delta_T=-200.0, clamp_bottom=True, clamp_top=True,
+                     mixed=True)
 
 
 def small_case(nx=3, ny=2, mesh=(4, 4, 6), interp=(3, 3, 3), dummies=True, seed=0, **kw):
