@@ -22,7 +22,9 @@ request stream served with continuous batching.
 stage on the first arrays (at least 10 s) and every one of those arrays
 compared with the GPU's result (u and von Mises).
 
---mode single --workload c3: one 64x64 array with 10% dummy cells.
+--mode single --workload c3: one 64x64 array with 10% dummy cells;
+--workload bump: a 100x100 micro-bump layer (40x40x20 um blocks, 16^3 hexes,
+a SnAg column with Cu pads in underfill, both faces clamped, 5% empty sites).
 
 --mode plane: the paper's evaluation grid (100 x 100 points on each cell's
 mid-height plane) for the 16x16 array, FP64 and mixed, with the normalised
@@ -679,12 +681,15 @@ def batch_mode(args, mos, torch, np, W):
 
 
 def single_mode(args, mos, torch, np, W):
-    """One large array (C3- or C5-shaped) through the engine, plain FP64 and
-    mixed precision side by side, each with its dominant kernel's roofline."""
+    """One large array (C3- or C5-shaped, or a 100x100 micro-bump layer)
+    through the engine, plain FP64 and mixed precision side by side, each
+    with its dominant kernel's roofline."""
     if args.workload == "c5":
         args.no_legs = True
         return c5_mode(args, mos, torch, np, W)
-    case = W.case_c3(args.seed)
+    bump = args.workload == "bump"
+    case = W.case_bump(args.seed) if bump else W.case_c3(args.seed)
+    key = "single_bump" if bump else "single_c3"
     ctx = mos.Context(0)
     torch.cuda.reset_peak_memory_stats()
     torch.cuda.synchronize()
@@ -696,18 +701,20 @@ def single_mode(args, mos, torch, np, W):
     kw = dict(clamp_bottom=case.clamp_bottom, clamp_top=case.clamp_top)
     paths, vms = {}, {}
     for prec in ("fp64", "mixed"):
-        paths[prec], vms[prec], n_dofs = solve_leg(args, mos, torch, np, ctx, roms, case, prec, kw, "single_c3")
+        paths[prec], vms[prec], n_dofs = solve_leg(args, mos, torch, np, ctx, roms, case, prec, kw, key)
     err = rel_max(vms["mixed"], vms["fp64"])
     sp = case.specs[0]
     head = paths["fp64"]
     out = {
-        "metric": METRIC, "value": head["value"], "unit": "TSV-cells/s", "n_gpus": 1, "steps": args.steps,
+        "metric": METRIC, "value": head["value"], "unit": "bump-cells/s" if bump else "TSV-cells/s", "n_gpus": 1,
+        "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": head["ms_per_solve"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": case.name, "array": f"{case.nx_cells}x{case.ny_cells}", "cells": case.n_cells,
                    "cell_um": [sp.pitch_x, sp.pitch_y, sp.height], "cell_mesh": list(sp.mesh),
                    "interp": list(sp.interp), "n": n, "reduced_dofs": int(n_dofs),
-                   "dummy_cells": int((case.cell_type != 0).sum()), "bc": "bottom clamped",
+                   "dummy_cells": int((case.cell_type != 0).sum()),
+                   "bc": "bottom and top clamped" if case.clamp_top else "bottom clamped",
                    "delta_T": case.delta_T, "seed": args.seed, "precision": "fp64 (record); mixed beside it"},
         "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
         "roofline": head["roofline"], "kernel_classes": head["kernel_classes"],
@@ -1038,7 +1045,8 @@ def main():
     ap.add_argument("--mode", choices=["c5", "batch", "serve", "single", "calib", "plane", "convergence"],
                     default="c5")
     ap.add_argument("--grid", type=int, default=100, help="plane mode: sample points per cell along x and y")
-    ap.add_argument("--workload", choices=["c3", "c5"], default="c3")
+    ap.add_argument("--workload", choices=["c3", "c5", "bump"], default="c3",
+                    help="single mode: C3, C5, or a 100x100 micro-bump layer")
     ap.add_argument("--sub", type=int, default=20, help="c5 mode: sub-array size the oracle solves on the host")
     ap.add_argument("--no-legs", action="store_true", help="c5 mode: skip the batch and served legs")
     ap.add_argument("--batch", type=int, default=128)

@@ -66,19 +66,32 @@ typedef struct mos_sol_s *mos_sol;
 /* Isotropic linear thermo-elastic material (eq. 1-2): E [MPa], nu [-], alpha [1/K]. */
 typedef struct { double E, nu, alpha; } mos_material;
 
+/* Repeated fine structure of a unit block (the method applies to any,
+ * Sec. 4.1; TSVs and micro-bumps are the arrays Sec. 1 names). */
+enum { MOS_CELL_TSV = 0, MOS_CELL_BUMP = 1 };
+
 /* Unit block of Sec. 4.2 / Fig. 2: a pitch_x x pitch_y x height cuboid of
  * `matrix` with a centred via of diameter tsv_diameter (0 = dummy block,
  * Sec. 4.4) and a liner of liner_thickness around it, meshed as a structured
  * mesh[0] x mesh[1] x mesh[2] grid of trilinear hexahedra; an element takes
  * the via material if its centroid's distance r to the via axis satisfies
  * r < d/2, the liner if r < d/2 + t, else the matrix.  interp[] is the number
- * of equally spaced Lagrange nodes per axis (n_x, n_y, n_z) >= 2 (eq. 8-10). */
+ * of equally spaced Lagrange nodes per axis (n_x, n_y, n_z) >= 2 (eq. 8-10).
+ * structure MOS_CELL_BUMP makes it a micro-bump block instead: `matrix` is
+ * the underfill, and a centred column of diameter tsv_diameter is solder
+ * (`via`) except for pads of pad_thickness at its two ends (`liner`): an
+ * element with r < d/2 is pad if its centroid height z satisfies
+ * z < pad_thickness or z > height - pad_thickness, else solder.  A bump
+ * block needs liner_thickness = 0 and 0 <= 2 pad_thickness < height; a TSV
+ * block needs pad_thickness = 0 (MOS_EINVAL otherwise). */
 typedef struct {
     double pitch_x, pitch_y, height;
     int32_t mesh[3];
     double tsv_diameter, liner_thickness;
     mos_material matrix, via, liner;
     int32_t interp[3];
+    int32_t structure;
+    double pad_thickness;
 } mos_cell_desc;
 
 enum { MOS_BC_CLAMP_BOTTOM = 1, MOS_BC_CLAMP_TOP = 2, MOS_BC_LIST_ON_DEVICE = 4 };

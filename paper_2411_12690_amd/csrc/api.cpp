@@ -160,6 +160,22 @@ static mos_status check_cell_desc(const mos_cell_desc *d) {
         set_error("tsv_diameter and liner_thickness must be finite and >= 0");
         return MOS_EINVAL;
     }
+    if (d->structure != MOS_CELL_TSV && d->structure != MOS_CELL_BUMP) {
+        set_error("structure %d is neither MOS_CELL_TSV nor MOS_CELL_BUMP", d->structure);
+        return MOS_EINVAL;
+    }
+    if (!std::isfinite(d->pad_thickness) || !(d->pad_thickness >= 0)) {
+        set_error("pad_thickness must be finite and >= 0");
+        return MOS_EINVAL;
+    }
+    if (d->structure == MOS_CELL_TSV && d->pad_thickness != 0) {
+        set_error("a TSV block has no pads (pad_thickness must be 0)");
+        return MOS_EINVAL;
+    }
+    if (d->structure == MOS_CELL_BUMP && (d->liner_thickness != 0 || !(2 * d->pad_thickness < d->height))) {
+        set_error("a micro-bump block needs liner_thickness = 0 and 2 pad_thickness < height");
+        return MOS_EINVAL;
+    }
     if (!valid_material(d->matrix) || !valid_material(d->via) || !valid_material(d->liner)) {
         set_error("material needs E > 0, -1 < nu < 0.5 and finite alpha");
         return MOS_EINVAL;

@@ -28,23 +28,33 @@ __device__ __forceinline__ void decode_node(int node, int mx, int my, int &a, in
     c = t / (my + 1);
 }
 
-// Material code of each element from its centroid distance to the via axis.
-// The products and sums are rounded separately (no contraction) so the
-// comparison is the plain IEEE evaluation of dx*dx + dy*dy.
-__global__ void k_material_map(uint8_t *mat, BrickGeom g, double d, double t) {
+// Material code of each element from its centroid distance to the via axis
+// (and, for a micro-bump block, its centroid height: pads at both ends of the
+// column).  The products and sums are rounded separately (no contraction) so
+// the comparisons are the plain IEEE evaluation of dx*dx + dy*dy and of
+// (ec + 1/2) h / m_z.
+__global__ void k_material_map(uint8_t *mat, BrickGeom g, double d, double t, int bump, double pad) {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     int n_elem = g.mx * g.my * g.mz;
     if (e >= n_elem) return;
     int ea = e % g.mx;
     int eb = (e / g.mx) % g.my;
+    int ec = e / (g.mx * g.my);
     double dx = __dadd_rn(__ddiv_rn(__dmul_rn(ea + 0.5, g.px), (double)g.mx), -(g.px / 2.0));
     double dy = __dadd_rn(__ddiv_rn(__dmul_rn(eb + 0.5, g.py), (double)g.my), -(g.py / 2.0));
     double r2 = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
     double rv = d / 2.0;
     double rl = rv + t;
     uint8_t code = 0;
-    if (d > 0.0 && r2 < __dmul_rn(rv, rv)) code = 1;
-    else if (d > 0.0 && r2 < __dmul_rn(rl, rl)) code = 2;
+    if (bump) {
+        double zc = __ddiv_rn(__dmul_rn(ec + 0.5, g.h), (double)g.mz);
+        bool in_pad = zc < pad || zc > __dadd_rn(g.h, -pad);
+        if (d > 0.0 && r2 < __dmul_rn(rv, rv)) code = in_pad ? 2 : 1;
+    } else if (d > 0.0 && r2 < __dmul_rn(rv, rv)) {
+        code = 1;
+    } else if (d > 0.0 && r2 < __dmul_rn(rl, rl)) {
+        code = 2;
+    }
     mat[e] = code;
 }
 
@@ -298,7 +308,7 @@ mos_status launch_cell_assembly(mos_cell c) {
 
     BrickGeom g{mx, my, mz, d.pitch_x, d.pitch_y, d.height};
     hipLaunchKernelGGL(k_material_map, dim3(ceil_div(c->n_elem, 256)), dim3(256), 0, st, c->mat, g,
-                       d.tsv_diameter, d.liner_thickness);
+                       d.tsv_diameter, d.liner_thickness, d.structure == MOS_CELL_BUMP ? 1 : 0, d.pad_thickness);
     MOS_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_element_tables, dim3(3), dim3(256), 0, st, c->ke, c->fe, c->mprop,
                        d.pitch_x / mx, d.pitch_y / my, d.height / mz);

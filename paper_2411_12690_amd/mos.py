@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libmos.so")
 
 MOS_OK, MOS_EINVAL, MOS_ENOMEM, MOS_ENOCONV, MOS_ESINGULAR, MOS_EHIP, MOS_EBUSY = 0, -1, -2, -3, -4, -5, -6
 MOS_FP64, MOS_MIXED = 0, 1
+MOS_CELL_TSV, MOS_CELL_BUMP = 0, 1
 MOS_BC_CLAMP_BOTTOM, MOS_BC_CLAMP_TOP, MOS_BC_LIST_ON_DEVICE = 1, 2, 4
 MOS_OUT_VM, MOS_OUT_SIGMA6 = 1, 2
 (MOS_Q_N, MOS_Q_CELL_DOFS, MOS_Q_CELL_ELEMS, MOS_Q_CELL_NNZ, MOS_Q_FREE_DOFS, MOS_Q_BANDWIDTH,
@@ -49,7 +50,8 @@ class CellDesc(ctypes.Structure):
     _fields_ = [("pitch_x", ctypes.c_double), ("pitch_y", ctypes.c_double), ("height", ctypes.c_double),
                 ("mesh", ctypes.c_int32 * 3), ("tsv_diameter", ctypes.c_double),
                 ("liner_thickness", ctypes.c_double), ("matrix", Material), ("via", Material),
-                ("liner", Material), ("interp", ctypes.c_int32 * 3)]
+                ("liner", Material), ("interp", ctypes.c_int32 * 3), ("structure", ctypes.c_int32),
+                ("pad_thickness", ctypes.c_double)]
 
 
 class ArrayDesc(ctypes.Structure):
@@ -141,6 +143,9 @@ def cell_desc(spec):
     d.tsv_diameter, d.liner_thickness = float(spec.tsv_diameter), float(spec.liner_thickness)
     d.matrix, d.via, d.liner = (Material(*map(float, m)) for m in (spec.matrix, spec.via, spec.liner))
     d.interp[:] = [int(v) for v in spec.interp]
+    kind = getattr(spec, "structure", "tsv")
+    d.structure = {"tsv": MOS_CELL_TSV, "bump": MOS_CELL_BUMP}[kind] if isinstance(kind, str) else int(kind)
+    d.pad_thickness = float(getattr(spec, "pad_thickness", 0.0))
     return d
 
 
