@@ -44,7 +44,7 @@ class AbstractMesh:
     node (i, j, k) sits at lattice point (cx (n_x-1) + i, cy (n_y-1) + j,
     cz (n_z-1) + k))."""
 
-    def __init__(self, nx_cells, ny_cells, interp, pitch_x=1.0, pitch_y=1.0, height=1.0, nz_cells=1):
+    def __init__(self, nx_cells, ny_cells, interp, pitch_x=1.0, pitch_y=1.0, height=1.0, nz_cells=1, skew=0.0):
         self.Nx, self.Ny, self.Nz = int(nx_cells), int(ny_cells), int(nz_cells)
         self.nx, self.ny, self.nz = (int(v) for v in interp)
         self.X = self.Nx * (self.nx - 1) + 1
@@ -61,6 +61,7 @@ class AbstractMesh:
         self.coords = np.stack([pitch_x * self.lattice[:, 0] / (self.nx - 1),
                                 pitch_y * self.lattice[:, 1] / (self.ny - 1),
                                 height * self.lattice[:, 2] / (self.nz - 1)], axis=1)
+        self.coords[:, 0] = self.coords[:, 0] + skew * self.coords[:, 1]     # skewed blocks
         S = mor.surface_nodes(self.nx, self.ny, self.nz)
         self.n_local = 3 * len(S)
         n_cells = self.Nx * self.Ny * self.Nz
@@ -211,7 +212,7 @@ def reconstruct(mesh, cell_type, roms, u, dT, chunk=256):
             nodal = dT * rom.fT[:, None] + rom.Phi @ U          # eq. 15
             sig = fem.centroid_stress(nodal, edofs, rom.mats,
                                       rom.cell.px / rom.cell.mx, rom.cell.py / rom.cell.my,
-                                      rom.cell.h / rom.cell.mz, rom.cell.materials, dT)
+                                      rom.cell.h / rom.cell.mz, rom.cell.materials, dT, rom.cell.skew)
             out[cs] = np.transpose(sig, (2, 0, 1))
     return out
 
@@ -248,6 +249,7 @@ class FullArray:
         c0 = self.cells[0]
         self.mx, self.my, self.mz = c0.mx, c0.my, c0.mz
         self.px, self.py, self.h = c0.px, c0.py, c0.h
+        self.skew = c0.skew
         self.GX, self.GY, self.GZ = self.Nx * self.mx, self.Ny * self.my, self.Nz * self.mz
         self.n_nodes = (self.GX + 1) * (self.GY + 1) * (self.GZ + 1)
         self.n_dofs = 3 * self.n_nodes
@@ -258,8 +260,10 @@ class FullArray:
     def node_coords(self):
         C, B, A = np.meshgrid(np.arange(self.GZ + 1), np.arange(self.GY + 1),
                               np.arange(self.GX + 1), indexing="ij")
-        return np.stack([(self.px * A / self.mx).ravel(), (self.py * B / self.my).ravel(),
-                         (self.h * C / self.mz).ravel()], axis=1)
+        X = np.stack([(self.px * A / self.mx).ravel(), (self.py * B / self.my).ravel(),
+                      (self.h * C / self.mz).ravel()], axis=1)
+        X[:, 0] = X[:, 0] + self.skew * X[:, 1]
+        return X
 
     def elements(self):
         """Per fine element: (8 node ids, block id, element id inside the block)."""
@@ -290,7 +294,7 @@ class FullArray:
         for k in np.unique(key):
             t, code = divmod(int(k), 3)
             tri = self.cells[t].materials[code]
-            table.update({int(k): fem.brick_element_table(hx, hy, hz, {0: tri}, [0])[0]})
+            table.update({int(k): fem.brick_element_table(hx, hy, hz, {0: tri}, [0], self.skew)[0]})
             mat_list[int(k)] = tri
         edofs = (3 * nodes[:, :, None] + np.arange(3)[None, None, :]).reshape(len(nodes), 24)
         A, b = fem.assemble(self.n_dofs, edofs, key, table)
@@ -317,7 +321,7 @@ class FullArray:
         u = solve_direct(A2, b2)
         # Centroid stress, per material key.
         sig = np.zeros((len(nodes), 6))
-        B0 = fem.centroid_B((fem.HEX_CORNERS + 1.0) / 2.0 * np.array([hx, hy, hz]))
+        B0 = fem.centroid_B(fem.element_corners(hx, hy, hz, self.skew))
         for k, (E, nu, alpha) in mat_list.items():
             sel = np.nonzero(key == k)[0]
             DB = fem.elasticity_matrix(E, nu) @ B0

@@ -163,6 +163,9 @@ class Cell:
         self.px, self.py, self.h = float(spec.pitch_x), float(spec.pitch_y), float(spec.height)
         self.mx, self.my, self.mz = (int(v) for v in spec.mesh)
         self.materials = [tuple(spec.matrix), tuple(spec.via), tuple(spec.liner)]
+        # x += skew * y: a parallelepiped block (skew = 1/sqrt(3) with
+        # p_y = p sqrt(3)/2 is the rhombic block of a 120-degree array).
+        self.skew = float(getattr(spec, "skew", 0.0))
         self.n_nodes = (self.mx + 1) * (self.my + 1) * (self.mz + 1)
         self.n_dofs = 3 * self.n_nodes
         self.n_elem = self.mx * self.my * self.mz
@@ -170,8 +173,9 @@ class Cell:
     def node_id(self, a, b, c):
         return (c * (self.my + 1) + b) * (self.mx + 1) + a
 
-    def node_coords(self):
-        """(n_nodes, 3) coordinates; node (a,b,c) at (p a/m_x, p b/m_y, h c/m_z)."""
+    def ref_coords(self):
+        """(n_nodes, 3) reference coordinates; node (a,b,c) at
+        (p_x a/m_x, p_y b/m_y, h c/m_z)."""
         a = np.arange(self.mx + 1)
         b = np.arange(self.my + 1)
         c = np.arange(self.mz + 1)
@@ -180,6 +184,13 @@ class Cell:
         y = self.py * B_ / self.my
         z = self.h * C / self.mz
         return np.stack([x.ravel(), y.ravel(), z.ravel()], axis=1)
+
+    def node_coords(self):
+        """(n_nodes, 3) physical coordinates: the reference ones with
+        x += skew * y."""
+        X = self.ref_coords()
+        X[:, 0] = X[:, 0] + self.skew * X[:, 1]
+        return X
 
     def element_nodes(self):
         """(n_elem, 8) FE node ids of every element, local order la+2lb+4lc."""
@@ -200,8 +211,9 @@ class Cell:
 
     def material_map(self):
         """Material code per element from the centroid's distance r to the
-        block's vertical axis (x, y) = (p_x/2, p_y/2), strict comparisons of
-        squared distances.  TSV block: via if r < d/2, liner if r < d/2 + t,
+        block's vertical axis through its centre ((p_x/2, p_y/2), sheared like
+        every point of a skewed block), strict comparisons of squared
+        distances.  TSV block: via if r < d/2, liner if r < d/2 + t,
         matrix otherwise.  Micro-bump block (structure "bump"): inside the
         column (r < d/2) a pad if the centroid height z < t_pad or
         z > h - t_pad, solder otherwise; underfill outside."""
@@ -219,7 +231,9 @@ class Cell:
             for eb in range(self.my):
                 dy = (eb + 0.5) * self.py / self.my - self.py / 2.0
                 for ea in range(self.mx):
-                    dx = (ea + 0.5) * self.px / self.mx - self.px / 2.0
+                    # Offset from the axis through the block's centre (the
+                    # centroid and the centre both sheared by skew * y).
+                    dx = ((ea + 0.5) * self.px / self.mx - self.px / 2.0) + self.skew * dy
                     r2 = dx * dx + dy * dy
                     if bump:
                         if d > 0.0 and r2 < r_via2:
@@ -270,9 +284,19 @@ def assemble(n_dofs, elem_dofs, elem_mats, element_table):
     return K, b
 
 
-def brick_element_table(hx, hy, hz, materials, codes):
-    """(Ke, fe) for an axis-aligned hx x hy x hz brick for each material code."""
+def element_corners(hx, hy, hz, skew=0.0):
+    """Corner coordinates (local order) of one element of the structured
+    grid: an hx x hy x hz brick, sheared by x += skew * y for a skewed block
+    (a parallelepiped; skew 0 leaves the brick as it is)."""
     coords = (HEX_CORNERS + 1.0) / 2.0 * np.array([hx, hy, hz])
+    coords[:, 0] = coords[:, 0] + skew * coords[:, 1]
+    return coords
+
+
+def brick_element_table(hx, hy, hz, materials, codes, skew=0.0):
+    """(Ke, fe) for each material code of one element of the structured grid
+    (an hx x hy x hz brick, sheared by `skew`)."""
+    coords = element_corners(hx, hy, hz, skew)
     table = {}
     for code in codes:
         E, nu, alpha = materials[code]
@@ -286,16 +310,17 @@ def assemble_cell(cell):
     dT = 1).  Returns (K CSR, b, material map)."""
     mats = cell.material_map()
     table = brick_element_table(cell.px / cell.mx, cell.py / cell.my, cell.h / cell.mz,
-                                cell.materials, np.unique(mats))
+                                cell.materials, np.unique(mats), cell.skew)
     K, b = assemble(cell.n_dofs, cell.element_dofs(), mats, table)
     return K, b, mats
 
 
-def centroid_stress(u, elem_dofs, elem_mats, hx, hy, hz, materials, dT):
+def centroid_stress(u, elem_dofs, elem_mats, hx, hy, hz, materials, dT, skew=0.0):
     """sigma = D B0 u_e - alpha(3 lambda + 2 mu) dT m at the centroid of every
-    hx x hy x hz brick element (eq. 1).  u may be (n_dofs,) or (n_dofs, k) for
-    k displacement fields at once.  Returns (n_elem, 6) or (n_elem, 6, k)."""
-    coords = (HEX_CORNERS + 1.0) / 2.0 * np.array([hx, hy, hz])
+    element of the structured grid (hx x hy x hz bricks, sheared by `skew`)
+    (eq. 1).  u may be (n_dofs,) or (n_dofs, k) for k displacement fields at
+    once.  Returns (n_elem, 6) or (n_elem, 6, k)."""
+    coords = element_corners(hx, hy, hz, skew)
     B0 = centroid_B(coords)
     single = u.ndim == 1
     U = u[:, None] if single else u

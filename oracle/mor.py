@@ -81,7 +81,10 @@ def interpolation_matrix(cell):
     xs = interp_points(cell.px, nx)
     ys = interp_points(cell.py, ny)
     zs = interp_points(cell.h, nz)
-    X = cell.node_coords()
+    # Interpolation in the block's reference coordinates (those of its
+    # structured grid): for a skewed block the faces stay parameterised alike
+    # on both blocks that share them.
+    X = cell.ref_coords()
     bnodes = np.nonzero(cell.boundary_node_mask())[0]
     P = X[bnodes]
     W = np.zeros((len(bnodes), len(S)))

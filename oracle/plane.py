@@ -38,6 +38,8 @@ def plane_points(cell, g):
 
     Returns (elem (g*g,) element ids, ref (g*g, 3) reference coordinates
     (xi, eta, zeta), xyz (g*g, 3) physical coordinates)."""
+    if cell.skew != 0.0:
+        raise ValueError("the evaluation plane is defined for rectangular blocks (skew 0)")
     g = int(g)
     mx, my, mz = cell.mx, cell.my, cell.mz
     elem = np.zeros(g * g, dtype=np.int64)

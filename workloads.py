@@ -10,6 +10,7 @@ the tests and of the benchmark.
 
 Units: micrometres, MPa, 1/K, K.  Material triples are (E, nu, alpha).
 """
+import math
 from dataclasses import dataclass, field, replace
 from typing import Optional
 
@@ -41,6 +42,10 @@ class CellSpec:
     # (pad_thickness each) and `matrix` the underfill around it.
     structure: str = "tsv"
     pad_thickness: float = 0.0
+    # Shear x += skew * y of the block: 0 for a 90-degree array; 1/sqrt(3)
+    # with pitch_y = pitch_x sqrt(3)/2 for the rhombic block of a 120-degree
+    # array (TSVs on a triangular lattice of spacing pitch_x).
+    skew: float = 0.0
 
     def dummy(self):
         return replace(self, tsv_diameter=0.0, liner_thickness=0.0, pad_thickness=0.0)
@@ -147,6 +152,25 @@ def bump_spec(**kw):
                 matrix=UNDERFILL, via=SNAG, liner=CU, structure="bump", pad_thickness=3.0)
     base.update(kw)
     return CellSpec(**base)
+
+
+def hex_spec(pitch=15.0, **kw):
+    """Rhombic (60/120-degree) block of a 120-degree TSV array: TSVs on a
+    triangular lattice of spacing `pitch`, 16 x 14 x 32 hexes (near-equal
+    in-plane edges), cubic faces, the via of diameter 5 um at the centre."""
+    base = dict(pitch_x=pitch, pitch_y=pitch * math.sqrt(3.0) / 2.0, skew=1.0 / math.sqrt(3.0),
+                mesh=(16, 14, 32))
+    base.update(kw)
+    return CellSpec(**base)
+
+
+def case_hex(seed=0, n=64, dummies=0.10):
+    """n x n TSV array on a 120-degree lattice (rhombic blocks), bottom
+    clamped, dT = -250 K, with a fraction of dummy blocks drawn from the seed."""
+    rng = np.random.default_rng(seed)
+    spec = hex_spec()
+    return ArrayCase(f"{n}x{n} 120-degree TSV array, 16x14x32 hex, cubic, bottom clamped", [spec, spec.dummy()],
+                     n, n, dummy_map(rng, n * n, dummies), mixed=True)
 
 
 def case_bump(seed=0, n=100, missing=0.05):
