@@ -24,7 +24,9 @@ compared with the GPU's result (u and von Mises).
 
 --mode single --workload c3: one 64x64 array with 10% dummy cells;
 --workload bump: a 100x100 micro-bump layer (40x40x20 um blocks, 16^3 hexes,
-a SnAg column with Cu pads in underfill, both faces clamped, 5% empty sites).
+a SnAg column with Cu pads in underfill, both faces clamped, 5% empty sites);
+--workload hex120: a 64x64 TSV array on a 120-degree lattice (rhombic blocks
+of 15 um spacing, 16x14x32 hexes, 10% dummy blocks, bottom clamped).
 
 --mode plane: the paper's evaluation grid (100 x 100 points on each cell's
 mid-height plane) for the 16x16 array, FP64 and mixed, with the normalised
@@ -681,15 +683,15 @@ def batch_mode(args, mos, torch, np, W):
 
 
 def single_mode(args, mos, torch, np, W):
-    """One large array (C3- or C5-shaped, or a 100x100 micro-bump layer)
-    through the engine, plain FP64 and mixed precision side by side, each
+    """One large array (C3- or C5-shaped, a 64x64 array on a 120-degree
+    lattice, or a 100x100 micro-bump layer) through the engine, plain FP64 and mixed precision side by side, each
     with its dominant kernel's roofline."""
     if args.workload == "c5":
         args.no_legs = True
         return c5_mode(args, mos, torch, np, W)
     bump = args.workload == "bump"
-    case = W.case_bump(args.seed) if bump else W.case_c3(args.seed)
-    key = "single_bump" if bump else "single_c3"
+    case = {"bump": W.case_bump, "hex120": W.case_hex}.get(args.workload, W.case_c3)(args.seed)
+    key = "single_" + args.workload
     ctx = mos.Context(0)
     torch.cuda.reset_peak_memory_stats()
     torch.cuda.synchronize()
@@ -711,7 +713,7 @@ def single_mode(args, mos, torch, np, W):
         "warmup": args.warmup, "ms_per_step": head["ms_per_solve"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": case.name, "array": f"{case.nx_cells}x{case.ny_cells}", "cells": case.n_cells,
-                   "cell_um": [sp.pitch_x, sp.pitch_y, sp.height], "cell_mesh": list(sp.mesh),
+                   "cell_um": [sp.pitch_x, sp.pitch_y, sp.height], "skew": sp.skew, "cell_mesh": list(sp.mesh),
                    "interp": list(sp.interp), "n": n, "reduced_dofs": int(n_dofs),
                    "dummy_cells": int((case.cell_type != 0).sum()),
                    "bc": "bottom and top clamped" if case.clamp_top else "bottom clamped",
@@ -1045,8 +1047,8 @@ def main():
     ap.add_argument("--mode", choices=["c5", "batch", "serve", "single", "calib", "plane", "convergence"],
                     default="c5")
     ap.add_argument("--grid", type=int, default=100, help="plane mode: sample points per cell along x and y")
-    ap.add_argument("--workload", choices=["c3", "c5", "bump"], default="c3",
-                    help="single mode: C3, C5, or a 100x100 micro-bump layer")
+    ap.add_argument("--workload", choices=["c3", "c5", "bump", "hex120"], default="c3",
+                    help="single mode: C3, C5, a 100x100 micro-bump layer, or a 64x64 120-degree array")
     ap.add_argument("--sub", type=int, default=20, help="c5 mode: sub-array size the oracle solves on the host")
     ap.add_argument("--no-legs", action="store_true", help="c5 mode: skip the batch and served legs")
     ap.add_argument("--batch", type=int, default=128)

@@ -83,7 +83,14 @@ enum { MOS_CELL_TSV = 0, MOS_CELL_BUMP = 1 };
  * element with r < d/2 is pad if its centroid height z satisfies
  * z < pad_thickness or z > height - pad_thickness, else solder.  A bump
  * block needs liner_thickness = 0 and 0 <= 2 pad_thickness < height; a TSV
- * block needs pad_thickness = 0 (MOS_EINVAL otherwise). */
+ * block needs pad_thickness = 0 (MOS_EINVAL otherwise).  skew shears every
+ * point of the block, x += skew * y (the grid, the via axis through the
+ * block's centre, node coordinates), making it a parallelepiped: skew =
+ * 1/sqrt(3) with pitch_y = pitch_x sqrt(3)/2 is the rhombic block of a
+ * 120-degree array (Sec. 4.2), TSVs on a triangular lattice of spacing
+ * pitch_x.  Interpolation and numbering stay in the block's reference
+ * coordinates.  0 is the rectangular block; it must be finite and
+ * |skew| <= 4. */
 typedef struct {
     double pitch_x, pitch_y, height;
     int32_t mesh[3];
@@ -92,6 +99,7 @@ typedef struct {
     int32_t interp[3];
     int32_t structure;
     double pad_thickness;
+    double skew;
 } mos_cell_desc;
 
 enum { MOS_BC_CLAMP_BOTTOM = 1, MOS_BC_CLAMP_TOP = 2, MOS_BC_LIST_ON_DEVICE = 4 };
@@ -139,6 +147,12 @@ typedef struct {
 /* Create a context on HIP device `device`, enqueueing on `hip_stream`
  * (a hipStream_t; NULL = the default stream).  `alloc` may be NULL. */
 mos_status mos_ctx_create(int device, void *hip_stream, const mos_allocator *alloc, mos_ctx *out);
+/* Release the context.  Cells, ROMs, solutions and engines made from it may
+ * be freed before or after this call, in any order: each holds the context,
+ * and its stream, allocator and pinned memory are released when the last of
+ * them (or this call, if none is left) goes.  After this call the context
+ * must not be passed to any other entry point; the allocator's callbacks
+ * must stay callable until the last handle is freed. */
 void mos_ctx_destroy(mos_ctx ctx);
 
 /* Sec. 3.2 and 4.2 (eq. 1-7, 11-12): mesh the unit block, assign materials,
@@ -217,8 +231,9 @@ mos_status mos_reconstruct_displacement(mos_ctx ctx, mos_sol sol, void *u_nodal)
  * another grid; a call with another grid first waits for the stream.  The
  * call modifies the ROM: calls that use the same ROM must not run
  * concurrently with it from other threads.
- * Errors: MOS_EINVAL for a NULL vm, a grid outside [1, 256], or a solution
- * whose ROMs were freed; MOS_ENOMEM if the basis does not fit. */
+ * Errors: MOS_EINVAL for a NULL vm, a grid outside [1, 256], a solution
+ * whose ROMs were freed, or skewed blocks (the plane is defined for
+ * rectangular ones); MOS_ENOMEM if the basis does not fit. */
 mos_status mos_reconstruct_plane(mos_ctx ctx, mos_sol sol, int32_t grid, void *vm);
 
 /* Copy the reduced solution (n_global_dofs doubles) to host memory and report

@@ -160,6 +160,10 @@ static mos_status check_cell_desc(const mos_cell_desc *d) {
         set_error("tsv_diameter and liner_thickness must be finite and >= 0");
         return MOS_EINVAL;
     }
+    if (!std::isfinite(d->skew) || !(std::fabs(d->skew) <= 4.0)) {
+        set_error("skew must be finite with |skew| <= 4");
+        return MOS_EINVAL;
+    }
     if (d->structure != MOS_CELL_TSV && d->structure != MOS_CELL_BUMP) {
         set_error("structure %d is neither MOS_CELL_TSV nor MOS_CELL_BUMP", d->structure);
         return MOS_EINVAL;
@@ -186,6 +190,29 @@ static mos_status check_cell_desc(const mos_cell_desc *d) {
         return MOS_EINVAL;
     }
     return MOS_OK;
+}
+
+// Context lifetime (see mos_ctx_s::life): a handle returned to the caller
+// holds its context until it is freed.
+static void ctx_teardown(mos_ctx ctx) {
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+static void ctx_hold(mos_ctx ctx) {
+    std::lock_guard<std::mutex> g(ctx->life);
+    ++ctx->live;
+}
+
+static void ctx_drop(mos_ctx ctx) {
+    bool last;
+    {
+        std::lock_guard<std::mutex> g(ctx->life);
+        last = --ctx->live == 0 && ctx->closing;
+    }
+    if (last) ctx_teardown(ctx);
 }
 
 extern "C" {
@@ -244,10 +271,13 @@ mos_status mos_ctx_create(int device, void *hip_stream, const mos_allocator *all
 
 void mos_ctx_destroy(mos_ctx ctx) {
     if (!ctx) return;
-    (void)hipStreamSynchronize(ctx->stream);
-    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-    for (hipEvent_t e : ctx->ev) (void)hipEventDestroy(e);
-    delete ctx;
+    bool now;
+    {
+        std::lock_guard<std::mutex> g(ctx->life);
+        ctx->closing = true;
+        now = ctx->live == 0;
+    }
+    if (now) ctx_teardown(ctx);
 }
 
 mos_status mos_timing_start(mos_ctx ctx, int kernel, int every) {
@@ -317,6 +347,8 @@ mos_status mos_build_cell(mos_ctx ctx, const mos_cell_desc *desc, mos_cell *out)
         mos_cell_free(c);
         return s;
     }
+    ctx_hold(ctx);
+    c->held = true;
     *out = c;
     return MOS_OK;
 }
@@ -355,6 +387,8 @@ mos_status mos_reduce(mos_ctx ctx, mos_cell cell, mos_rom *out) {
         mos_rom_free(r);
         return s;
     }
+    ctx_hold(ctx);
+    r->held = true;
     *out = r;
     return MOS_OK;
 }
@@ -377,10 +411,12 @@ static mos_status check_roms(const mos_rom *roms, int32_t n_roms, bool same_bloc
         const mos_cell_desc &b = roms[t]->desc;
         bool same = true;
         for (int k = 0; k < 3; ++k) same = same && a.mesh[k] == b.mesh[k] && a.interp[k] == b.interp[k];
-        if (same_block) same = same && a.pitch_x == b.pitch_x && a.pitch_y == b.pitch_y && a.height == b.height;
+        if (same_block)
+            same = same && a.pitch_x == b.pitch_x && a.pitch_y == b.pitch_y && a.height == b.height &&
+                   a.skew == b.skew;
         if (!same) {
             set_error("roms[%d] differs from roms[0] in %s", t,
-                      same_block ? "pitch, height, mesh or interp" : "mesh or interp");
+                      same_block ? "pitch, height, skew, mesh or interp" : "mesh or interp");
             return MOS_EINVAL;
         }
     }
@@ -496,6 +532,8 @@ mos_status mos_solve_array(mos_ctx ctx, const mos_array_desc *d, const mos_rom *
     MOS_TRY(engine_gather_index(e, P, s->perm, s->gidx));
     MOS_HIP(hipStreamSynchronize(st));
     sg.keep = true;
+    ctx_hold(ctx);
+    s->held = true;
     *out = s;
     return MOS_OK;
 }
@@ -543,6 +581,8 @@ mos_status mos_engine_create(mos_ctx ctx, const mos_rom *roms, int32_t n_roms, m
         delete e;
         return s;
     }
+    ctx_hold(ctx);
+    e->held = true;
     *out = e;
     return MOS_OK;
 }
@@ -667,8 +707,11 @@ mos_status mos_engine_stats(mos_engine e, int64_t *active, int64_t *queued, int6
 
 void mos_engine_destroy(mos_engine e) {
     if (!e) return;
+    mos_ctx ctx = e->ctx;
+    const bool held = e->held;
     engine_free(e);
     delete e;
+    if (held) ctx_drop(ctx);
 }
 
 mos_status mos_reconstruct(mos_ctx ctx, mos_sol sol, uint32_t outputs, void *vm, void *sigma6) {
@@ -731,11 +774,16 @@ mos_status mos_reconstruct_plane(mos_ctx ctx, mos_sol sol, int32_t grid, void *v
         set_error("mos_reconstruct_plane: need a non-NULL vm and a grid in [1, %d]", PLANE_MAX_GRID);
         return MOS_EINVAL;
     }
-    for (mos_rom r : sol->roms)
+    for (mos_rom r : sol->roms) {
         if (!r || r->kind != KIND_ROM) {
             set_error("mos_reconstruct_plane: a ROM of this solution has been freed");
             return MOS_EINVAL;
         }
+        if (r->desc.skew != 0.0) {
+            set_error("mos_reconstruct_plane: the evaluation plane is defined for rectangular blocks (skew 0)");
+            return MOS_EINVAL;
+        }
+    }
     MOS_HIP(hipSetDevice(ctx->device));
     return reconstruct_plane(ctx, sol, grid, vm);
 }
@@ -860,8 +908,10 @@ mos_status mos_array_layout(mos_ctx ctx, int32_t nx_cells, int32_t ny_cells, int
                 for (int64_t I = 0; I < m.X; ++I) {
                     if (!(I % (m.nx - 1) == 0 || J % (m.ny - 1) == 0 || K % (m.nz - 1) == 0)) continue;
                     const int64_t id = node_id(m.lat, I, J, K);
-                    coords[3 * (size_t)id + 0] = d.pitch_x * I / (m.nx - 1);
-                    coords[3 * (size_t)id + 1] = d.pitch_y * J / (m.ny - 1);
+                    const double x = d.pitch_x * I / (m.nx - 1), y = d.pitch_y * J / (m.ny - 1);
+                    const double sy = d.skew * y;  // its own statement: no fused multiply-add
+                    coords[3 * (size_t)id + 0] = x + sy;
+                    coords[3 * (size_t)id + 1] = y;
                     coords[3 * (size_t)id + 2] = d.height * K / (m.nz - 1);
                 }
     }
@@ -896,9 +946,12 @@ mos_status mos_array_layout(mos_ctx ctx, int32_t nx_cells, int32_t ny_cells, int
 
 void mos_cell_free(mos_cell c) {
     if (!c || c->kind != KIND_CELL) return;
+    mos_ctx ctx = c->ctx;
+    const bool held = c->held;
     c->mem.release();
     c->kind = 0;
     delete c;
+    if (held) ctx_drop(ctx);
 }
 
 void mos_rom_free(mos_rom r) {
@@ -908,16 +961,22 @@ void mos_rom_free(mos_rom r) {
         delete r->plane;
         r->plane = nullptr;
     }
+    mos_ctx ctx = r->ctx;
+    const bool held = r->held;
     r->mem.release();
     r->kind = 0;
     delete r;
+    if (held) ctx_drop(ctx);
 }
 
 void mos_sol_free(mos_sol s) {
     if (!s || s->kind != KIND_SOL) return;
+    mos_ctx ctx = s->ctx;
+    const bool held = s->held;
     s->mem.release();
     s->kind = 0;
     delete s;
+    if (held) ctx_drop(ctx);
 }
 
 }  // extern "C"

@@ -19,6 +19,7 @@ namespace {
 struct BrickGeom {
     int mx, my, mz;
     double px, py, h;
+    double skew;  // x += skew * y (a parallelepiped block)
 };
 
 __device__ __forceinline__ void decode_node(int node, int mx, int my, int &a, int &b, int &c) {
@@ -40,8 +41,11 @@ __global__ void k_material_map(uint8_t *mat, BrickGeom g, double d, double t, in
     int ea = e % g.mx;
     int eb = (e / g.mx) % g.my;
     int ec = e / (g.mx * g.my);
-    double dx = __dadd_rn(__ddiv_rn(__dmul_rn(ea + 0.5, g.px), (double)g.mx), -(g.px / 2.0));
     double dy = __dadd_rn(__ddiv_rn(__dmul_rn(eb + 0.5, g.py), (double)g.my), -(g.py / 2.0));
+    // Offset from the axis through the block's centre; both points are
+    // sheared by skew * y, so the x offset gains skew * dy.
+    double dx = __dadd_rn(__dadd_rn(__ddiv_rn(__dmul_rn(ea + 0.5, g.px), (double)g.mx), -(g.px / 2.0)),
+                          __dmul_rn(g.skew, dy));
     double r2 = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
     double rv = d / 2.0;
     double rl = rv + t;
@@ -59,20 +63,23 @@ __global__ void k_material_map(uint8_t *mat, BrickGeom g, double d, double t, in
 }
 
 // Gradient of trilinear shape function l (corner offsets la, lb, lc) of an
-// hx x hy x hz brick at reference point (xi, eta, zeta).
+// hx x hy x hz brick sheared by x += skew * y, at reference point
+// (xi, eta, zeta).  The map is affine with a constant Jacobian, whose inverse
+// transpose leaves d/dx and d/dz as for the brick and gives
+// d/dy = (brick d/dy) - skew d/dx; the volume (det J) is the brick's.
 __device__ __forceinline__ void shape_grad(int l, double xi, double eta, double zeta, double hx,
-                                           double hy, double hz, double g[3]) {
+                                           double hy, double hz, double skew, double g[3]) {
     double sa = (l & 1) ? 1.0 : -1.0;
     double sb = (l & 2) ? 1.0 : -1.0;
     double sc = (l & 4) ? 1.0 : -1.0;
     g[0] = sa * (1.0 + sb * eta) * (1.0 + sc * zeta) * 0.125 * (2.0 / hx);
-    g[1] = sb * (1.0 + sa * xi) * (1.0 + sc * zeta) * 0.125 * (2.0 / hy);
+    g[1] = sb * (1.0 + sa * xi) * (1.0 + sc * zeta) * 0.125 * (2.0 / hy) - skew * g[0];
     g[2] = sc * (1.0 + sa * xi) * (1.0 + sb * eta) * 0.125 * (2.0 / hz);
 }
 
 // One block per material; 576 stiffness entries + 24 load entries.
 __global__ void k_element_tables(double *ke, double *fe, const double *mprop, double hx, double hy,
-                                 double hz) {
+                                 double hz, double skew) {
     int m = blockIdx.x;
     double lam = mprop[3 * m + 0], mu = mprop[3 * m + 1], beta = mprop[3 * m + 2];
     const double gp = 0.57735026918962576451;  // 1/sqrt(3)
@@ -85,8 +92,8 @@ __global__ void k_element_tables(double *ke, double *fe, const double *mprop, do
             for (int q = 0; q < 8; ++q) {
                 double xi = (q & 1) ? gp : -gp, eta = (q & 2) ? gp : -gp, zeta = (q & 4) ? gp : -gp;
                 double gl[3], gm[3];
-                shape_grad(l, xi, eta, zeta, hx, hy, hz, gl);
-                shape_grad(mm, xi, eta, zeta, hx, hy, hz, gm);
+                shape_grad(l, xi, eta, zeta, hx, hy, hz, skew, gl);
+                shape_grad(mm, xi, eta, zeta, hx, hy, hz, skew, gm);
                 double dot = gl[0] * gm[0] + gl[1] * gm[1] + gl[2] * gm[2];
                 double v = lam * gl[i] * gm[j] + mu * gl[j] * gm[i] + (i == j ? mu * dot : 0.0);
                 acc += v * detJ;
@@ -98,7 +105,7 @@ __global__ void k_element_tables(double *ke, double *fe, const double *mprop, do
             for (int q = 0; q < 8; ++q) {
                 double xi = (q & 1) ? gp : -gp, eta = (q & 2) ? gp : -gp, zeta = (q & 4) ? gp : -gp;
                 double gl[3];
-                shape_grad(l, xi, eta, zeta, hx, hy, hz, gl);
+                shape_grad(l, xi, eta, zeta, hx, hy, hz, skew, gl);
                 acc += beta * gl[i] * detJ;
             }
             fe[m * 24 + r] = acc;
@@ -306,12 +313,12 @@ mos_status launch_cell_assembly(mos_cell c) {
     MOS_HIP(hipMemcpyAsync(c->bnode, bnode.data(), bnode.size() * 4, hipMemcpyHostToDevice, st));
     MOS_HIP(hipMemcpyAsync(dof_free_d, dof_free.data(), dof_free.size() * 4, hipMemcpyHostToDevice, st));
 
-    BrickGeom g{mx, my, mz, d.pitch_x, d.pitch_y, d.height};
+    BrickGeom g{mx, my, mz, d.pitch_x, d.pitch_y, d.height, d.skew};
     hipLaunchKernelGGL(k_material_map, dim3(ceil_div(c->n_elem, 256)), dim3(256), 0, st, c->mat, g,
                        d.tsv_diameter, d.liner_thickness, d.structure == MOS_CELL_BUMP ? 1 : 0, d.pad_thickness);
     MOS_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_element_tables, dim3(3), dim3(256), 0, st, c->ke, c->fe, c->mprop,
-                       d.pitch_x / mx, d.pitch_y / my, d.height / mz);
+                       d.pitch_x / mx, d.pitch_y / my, d.height / mz, d.skew);
     MOS_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_csr_values, dim3(ceil_div(c->n_dofs, 256)), dim3(256), 0, st, c->val,
                        c->row_ptr, c->ke, c->mat, mx, my, mz, c->n_dofs);

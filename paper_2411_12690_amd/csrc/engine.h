@@ -49,7 +49,8 @@ struct PidList {
 struct ProbParams {
     int64_t d0, n_dofs, nd_pad;
     double dT;
-    double h[3];                    // node spacing over pitch_x per axis (coarse-correction coordinates)
+    double h[4];                    // node spacing over pitch_x per axis (coarse-correction coordinates),
+                                    // then the block's skew (x += skew * y)
     Lattice lat;
     AggLayout agg;                  // internal node order (boxes of cells)
     int32_t blk_begin, n_blk, sb_begin, n_sb, nrb, fused;
@@ -134,6 +135,7 @@ struct RangeAlloc {
 struct mos_engine_s {
     uint32_t kind = 0x21474e45u;
     mos_ctx ctx = nullptr;
+    bool held = false;  // holds ctx (returned to the caller)
     mos_precision precision = MOS_FP64;
     std::vector<mos_rom> roms;
     int ldk = 0, n = 0, n_elem = 0, n_eblk = 0;

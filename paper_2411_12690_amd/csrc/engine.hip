@@ -954,8 +954,9 @@ __device__ __forceinline__ void node_prolong(double X, double Y, double Zc, cons
 // a << 24 | constrained components << 28 (a = aggregate within the box).
 __device__ __forceinline__ void unpack_lc(uint32_t w, const double *h, double &X, double &Y, double &Zc, int &a,
                                           bool (&f)[3]) {
-    X = (double)(w & 255u) * h[0];
+    // Physical coordinates of a skewed block: x += skew * y (h[3] = skew).
     Y = (double)((w >> 8) & 255u) * h[1];
+    X = (double)(w & 255u) * h[0] + h[3] * Y;
     Zc = (double)((w >> 16) & 255u) * h[2];
     a = (int)((w >> 24) & 15u);
     for (int ci = 0; ci < 3; ++ci) f[ci] = ((w >> (28 + ci)) & 1u) == 0;
@@ -1398,8 +1399,8 @@ __global__ __launch_bounds__(NTH) void k_coarse_setup(ProbSel sel, const int4 *b
             in = in && cmask[dd] == 0;
             double z[6] = {0, 0, 0, 0, 0, 0};
             if (in) {
-                const double X = (double)(ib - ag * AGG_C * sx) * P.h[0];
                 const double Yc = (double)(J - (int64_t)gy * A.wyi) * P.h[1];
+                const double X = (double)(ib - ag * AGG_C * sx) * P.h[0] + P.h[3] * Yc;
                 const double Zc = (double)Kz * P.h[2];
                 // Mode values at component ci (columns of Z).
                 z[ci] = 1.0;
@@ -1490,7 +1491,7 @@ __global__ __launch_bounds__(NTH) void k_coarse_setup(ProbSel sel, const int4 *b
 // share of the symmetric 21 terms, then per piece the sums over the rows in
 // a fixed order (waves in order).  NTH >= n threads.
 struct TypeSpacing {
-    double h[MAX_TYPES][3];  // coarse-coordinate node spacing per axis (x pitch = 1) of each cell type
+    double h[MAX_TYPES][4];  // coarse-coordinate node spacing per axis (x pitch = 1) and skew of each cell type
 };
 template <int NTH>
 __global__ __launch_bounds__(NTH) void k_coarse_table(const void *const *kr32_tab, const int32_t *surf, int n,
@@ -1499,7 +1500,7 @@ __global__ __launch_bounds__(NTH) void k_coarse_table(const void *const *kr32_ta
     constexpr int NW = NTH / 64;
     const int type = blockIdx.x, cls = blockIdx.y, t = threadIdx.x, w = t / 64, lane = t % 64;
     const float *K = static_cast<const float *>(kr32_tab[type]);
-    const double h0 = hs.h[type][0], h1 = hs.h[type][1], h2 = hs.h[type][2];
+    const double h0 = hs.h[type][0], h1 = hs.h[type][1], h2 = hs.h[type][2], skew = hs.h[type][3];
     __shared__ double zl[NTH][6];
     __shared__ int8_t pc[NTH];
     __shared__ double wpart[NW][4][21];
@@ -1511,7 +1512,8 @@ __global__ __launch_bounds__(NTH) void k_coarse_table(const void *const *kr32_ta
         const bool fixed = ((flags & MOS_BC_CLAMP_BOTTOM) && k == 0) || ((flags & MOS_BC_CLAMP_TOP) && k == nz - 1);
         if (!fixed) {
             piece = ((cls & 1) && i == nx - 1 ? 1 : 0) + ((cls & 2) && j == ny - 1 ? 2 : 0);
-            const double X = i * h0, Y = j * h1, Zc = k * h2;
+            const double Y = j * h1, Zc = k * h2;
+            const double X = i * h0 + skew * Y;
             z[ci] = 1.0;
             if (ci == 0) {
                 z[3] = -Y;
@@ -1658,7 +1660,8 @@ __global__ __launch_bounds__(64) void k_coarse_agg_tab(ProbSel sel, const int4 *
                 const double *G = ctab + ((((size_t)type * 4 + flags) * 4 + (rx + 2 * ry)) * 4 + piece) * 21;
                 // Offsets of the cell corner from the aggregate corner, in the
                 // coarse coordinates (x pitch = 1).
-                const double X0 = (double)((cx - ax0) * sx) * P.h[0], Y0 = (double)((cy - by0) * sy) * P.h[1];
+                const double Y0 = (double)((cy - by0) * sy) * P.h[1];
+                const double X0 = (double)((cx - ax0) * sx) * P.h[0] + P.h[3] * Y0;
                 // Column m of T: (row, coefficient) pairs.
                 int ri[2][3];
                 double rc[2][3];
@@ -2263,6 +2266,7 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
             H.h[0] = 1.0 / (cd.interp[0] - 1);
             H.h[1] = cd.pitch_y / cd.pitch_x / (cd.interp[1] - 1);
             H.h[2] = cd.height / cd.pitch_x / (cd.interp[2] - 1);
+            H.h[3] = cd.skew;
         }
         // Clamped faces only: every cell of a type has the same free DoFs, so
         // its coarse terms come from the per-type table.
@@ -2357,6 +2361,7 @@ mos_status setup_batch(mos_engine e, const std::vector<EngineProblem *> &adm, co
                     hs.h[t][0] = 1.0 / (cd.interp[0] - 1);
                     hs.h[t][1] = cd.pitch_y / cd.pitch_x / (cd.interp[1] - 1);
                     hs.h[t][2] = cd.height / cd.pitch_x / (cd.interp[2] - 1);
+                    hs.h[t][3] = cd.skew;
                 }
                 const mos_cell_desc &c0 = e->roms[0]->desc;
                 if (e->n <= 256)
@@ -2773,7 +2778,7 @@ mos_status engine_check_desc(mos_engine e, const mos_array_desc *d) {
         }
         if (first < 0) first = t;
         const mos_cell_desc &a = e->roms[first]->desc, &b = e->roms[t]->desc;
-        if (a.pitch_x != b.pitch_x || a.pitch_y != b.pitch_y || a.height != b.height) {
+        if (a.pitch_x != b.pitch_x || a.pitch_y != b.pitch_y || a.height != b.height || a.skew != b.skew) {
             set_error("cells of one array use ROMs %d and %d of different pitch or height", first, t);
             return MOS_EINVAL;
         }

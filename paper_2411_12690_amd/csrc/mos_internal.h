@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -73,6 +74,13 @@ struct mos_ctx_s {
     int64_t timed_seen = 0;       // launches of the timed kernel so far
     std::vector<hipEvent_t> ev;   // pairs (start, stop), reused
     size_t ev_used = 0;
+    // Lifetime: handles returned to the caller (cells, ROMs, solutions,
+    // engines) each hold the context; mos_ctx_destroy marks it closing and
+    // the last of it and its handles to go releases it, so handles may be
+    // freed before or after the context.
+    std::mutex life;
+    int live = 0;
+    bool closing = false;
 };
 
 namespace mos {
@@ -97,6 +105,7 @@ inline void launch_timed(mos_ctx ctx, int id, F kernel, dim3 grid, dim3 block, u
 struct mos_cell_s {
     uint32_t kind = mos::KIND_CELL;
     mos_ctx ctx = nullptr;
+    bool held = false;  // holds ctx (returned to the caller)
     mos_cell_desc desc{};
     int mx = 0, my = 0, mz = 0;
     int n_nodes = 0, n_dofs = 0, n_elem = 0;
@@ -122,6 +131,7 @@ struct mos_cell_s {
 struct mos_rom_s {
     uint32_t kind = mos::KIND_ROM;
     mos_ctx ctx = nullptr;
+    bool held = false;  // holds ctx (returned to the caller)
     mos_cell_desc desc{};
     int mx = 0, my = 0, mz = 0, n_dofs = 0, n_elem = 0;
     int n = 0, n_surf = 0;
@@ -153,6 +163,7 @@ struct mos_rom_s {
 struct mos_sol_s {
     uint32_t kind = mos::KIND_SOL;
     mos_ctx ctx = nullptr;
+    bool held = false;  // holds ctx (returned to the caller)
     mos_precision precision = MOS_FP64;
     int Nx = 0, Ny = 0, n_cells = 0;
     int n = 0, n_surf = 0, n_elem = 0, ldk = 0, n_eblk = 0;

@@ -171,8 +171,8 @@ __global__ void k_rom_finalize(const double *P, int n, int ldk, double *kr, doub
 // Centroid stress of column q of Phi (q < ldk; columns >= n are zero) or of
 // f_T (q == ldk) for every element; D B0 applied in closed form.
 __global__ void k_stress_basis(const double *phi, int ldp, const uint8_t *mat, const double *mprop, double *psi,
-                               double *sig_t, int mx, int my, int mz, double hx, double hy, double hz, int n,
-                               int ldk, int n_eblk) {
+                               double *sig_t, int mx, int my, int mz, double hx, double hy, double hz,
+                               double skew, int n, int ldk, int n_eblk) {
     int idx = blockIdx.x * blockDim.x + threadIdx.x;
     const int n_elem = mx * my * mz;
     if (idx >= n_eblk * 16 * (ldk + 1)) return;
@@ -187,7 +187,8 @@ __global__ void k_stress_basis(const double *phi, int ldp, const uint8_t *mat, c
             int a = ea + (l & 1), b = ebb + ((l >> 1) & 1), c = ec + ((l >> 2) & 1);
             int node = (c * (my + 1) + b) * (mx + 1) + a;
             double gx = ((l & 1) ? 1.0 : -1.0) / (4.0 * hx);
-            double gy = ((l & 2) ? 1.0 : -1.0) / (4.0 * hy);
+            // Sheared block (x += skew * y): d/dy loses skew d/dx.
+            double gy = ((l & 2) ? 1.0 : -1.0) / (4.0 * hy) - skew * gx;
             double gz = ((l & 4) ? 1.0 : -1.0) / (4.0 * hz);
             double ux = phi[(size_t)(3 * node + 0) * ldp + colq];
             double uy = phi[(size_t)(3 * node + 1) * ldp + colq];
@@ -400,7 +401,7 @@ mos_status reduce_cell(mos_cell c, mos_rom r) {
     // Stress basis.
     hipLaunchKernelGGL(k_stress_basis, dim3(ceil_div((int64_t)r->n_eblk * 16 * (ldk + 1), 256)), dim3(256), 0,
                        st, r->phi, ldp, c->mat, c->mprop, r->psi, r->sig_t, c->mx, c->my, c->mz,
-                       d.pitch_x / c->mx, d.pitch_y / c->my, d.height / c->mz, n, ldk, r->n_eblk);
+                       d.pitch_x / c->mx, d.pitch_y / c->my, d.height / c->mz, d.skew, n, ldk, r->n_eblk);
     MOS_LAUNCH_CHECK();
     r->nks = ceil_div(ldk, 32);
     if (r->nks <= RECON_BF16_MAX_KS) {

@@ -51,7 +51,7 @@ class CellDesc(ctypes.Structure):
                 ("mesh", ctypes.c_int32 * 3), ("tsv_diameter", ctypes.c_double),
                 ("liner_thickness", ctypes.c_double), ("matrix", Material), ("via", Material),
                 ("liner", Material), ("interp", ctypes.c_int32 * 3), ("structure", ctypes.c_int32),
-                ("pad_thickness", ctypes.c_double)]
+                ("pad_thickness", ctypes.c_double), ("skew", ctypes.c_double)]
 
 
 class ArrayDesc(ctypes.Structure):
@@ -146,6 +146,7 @@ def cell_desc(spec):
     kind = getattr(spec, "structure", "tsv")
     d.structure = {"tsv": MOS_CELL_TSV, "bump": MOS_CELL_BUMP}[kind] if isinstance(kind, str) else int(kind)
     d.pad_thickness = float(getattr(spec, "pad_thickness", 0.0))
+    d.skew = float(getattr(spec, "skew", 0.0))
     return d
 
 

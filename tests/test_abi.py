@@ -43,9 +43,9 @@ def test_binding_covers_every_declared_function():
 def test_struct_sizes_match_the_header_layout():
     from paper_2411_12690_amd import mos
     # mos_material: 3 doubles; mos_cell_desc: 3 doubles, 3 int32 (+pad), 2 doubles,
-    # 3 materials, 3 int32 and the structure int32, the pad thickness
+    # 3 materials, 3 int32 and the structure int32, the pad thickness, the skew
     assert ctypes.sizeof(mos.Material) == 24
-    assert ctypes.sizeof(mos.CellDesc) == 3 * 8 + 16 + 2 * 8 + 3 * 24 + 16 + 8
+    assert ctypes.sizeof(mos.CellDesc) == 3 * 8 + 16 + 2 * 8 + 3 * 24 + 16 + 8 + 8
     assert ctypes.sizeof(mos.ArrayDesc) == 4 + 4 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4 + 8 + 4 + 4
 
 
