@@ -1,9 +1,10 @@
 // Unit-cell FE assembly on the device (Sec. 3.2 and 4.2; eq. 1-7, 11-12).
 //
-// The block is a structured grid of identical bricks, so each material has
-// one 24x24 element stiffness and one 24-entry unit-dT load, built by
-// k_element_tables with 2x2x2 Gauss quadrature from the closed form of
-// B_l^T D B_m for an isotropic material:
+// The block is a structured grid of identical bricks (identical
+// parallelepipeds for a skewed block), so each material has one 24x24
+// element stiffness and one 24-entry unit-dT load, built by k_element_tables
+// with 2x2x2 Gauss quadrature from the closed form of B_l^T D B_m for an
+// isotropic material:
 //   lambda g_l[i] g_m[j] + mu g_l[j] g_m[i] + mu (g_l . g_m) delta_ij.
 // Assembly is row-centric (one thread per matrix row gathers over the <= 8
 // elements around its node), so it is deterministic and needs no atomics;
