@@ -25,6 +25,7 @@
 #include "engine.h"
 #include "mesh.h"
 #include "mos_internal.h"
+#include "gmem.h"
 #include "waitcnt.h"
 
 namespace mos {
@@ -325,8 +326,8 @@ __global__ __launch_bounds__(256) void k_bgemm(const void *const *kr_tab, const 
     }
     __syncthreads();
     if (skip) return;
-    const T *kr = static_cast<const T *>(kr_tab[rom]);
-    const T *ap = kr + (size_t)(k_begin + lane / 16) * ldk + rb * 16 + lane % 16;
+    global_ptr<const T> kr = to_global(static_cast<const T *>(kr_tab[rom]));
+    global_ptr<const T> ap = kr + (size_t)(k_begin + lane / 16) * ldk + rb * 16 + lane % 16;
     const T *bp = Mc + (size_t)(k_begin + lane / 16) * ld_slots + col;
     v4 acc = {0, 0, 0, 0};
     for (int s0 = 0; s0 < steps; s0 += GEMM_MAX_STEPS) {
@@ -449,9 +450,9 @@ __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, c
     if (sl >= s_end) return;
     // Per-type K_r bases up front, so a slot block's operand loads wait on
     // its type only, not on a second pointer load.
-    const T *kr[MAX_TYPES];
+    global_ptr<const T> kr[MAX_TYPES];
 #pragma unroll
-    for (int t = 0; t < MAX_TYPES; ++t) kr[t] = static_cast<const T *>(kr_tab[t]);
+    for (int t = 0; t < MAX_TYPES; ++t) kr[t] = to_global(static_cast<const T *>(kr_tab[t]));
     const T *lane_b = Mc + (size_t)(lane / 16) * ld_slots + lane % 16;
     T a[KS], b[KS];
     {
@@ -475,7 +476,7 @@ __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, c
             for (int q = 0; q < 4; ++q) t[q] = Mc[(size_t)(rb * 16 + Mfma<T>::row(lane, q)) * ld_slots + col];
         }
         if (rom != cur) {
-            const T *ap = kr[rom] + (size_t)(lane / 16) * ldk + rb * 16 + lane % 16;
+            global_ptr<const T> ap = kr[rom] + (size_t)(lane / 16) * ldk + rb * 16 + lane % 16;
 #pragma unroll
             for (int k = 0; k < KS; ++k) a[k] = k < ks ? ap[(size_t)(4 * k) * ldk] : T(0);
             cur = rom;
@@ -577,9 +578,9 @@ __global__ __launch_bounds__(704) void k_bgemm_wg(const void *const *kr_tab, con
             *reinterpret_cast<c16 *>(tiles + ((size_t)buf * ldk + c / CPR) * 16 + (c % CPR) * EPC) = stage[i];
         }
     };
-    const T *kr[MAX_TYPES];
+    global_ptr<const T> kr[MAX_TYPES];
 #pragma unroll
-    for (int t = 0; t < MAX_TYPES; ++t) kr[t] = static_cast<const T *>(kr_tab[t]);
+    for (int t = 0; t < MAX_TYPES; ++t) kr[t] = to_global(static_cast<const T *>(kr_tab[t]));
     T a[KS];
     int cur = -1;
     fetch(sb_base + sl);
@@ -590,7 +591,7 @@ __global__ __launch_bounds__(704) void k_bgemm_wg(const void *const *kr_tab, con
         const int sb = sb_base + sl;
         const int rom = rom_of(sl);
         if (rom != cur) {
-            const T *ap = kr[rom] + (size_t)(lane / 16) * ldk + rb * 16 + lane % 16;
+            global_ptr<const T> ap = kr[rom] + (size_t)(lane / 16) * ldk + rb * 16 + lane % 16;
 #pragma unroll
             for (int k = 0; k < KS; ++k) a[k] = k < ks ? ap[(size_t)(4 * k) * ldk] : T(0);
             cur = rom;

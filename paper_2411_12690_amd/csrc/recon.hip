@@ -13,6 +13,7 @@
 #include <mutex>
 
 #include "bf16.h"
+#include "gmem.h"
 #include "mesh.h"
 #include "mos_internal.h"
 
@@ -122,8 +123,8 @@ __global__ __launch_bounds__(512, 1) void k_recon_f64_lds(const double *psi, con
         const ReconJob &J = jobs[j];
         const size_t pc0 = (size_t)(J.sb_first + (f - J.sb_off)) * 16;
         const double dT = J.dT;
-        OutT *vm = static_cast<OutT *>(J.vm);
-        OutT *sig6 = static_cast<OutT *>(J.sig6);
+        global_ptr<OutT> vm = to_global(static_cast<OutT *>(J.vm));
+        global_ptr<OutT> sig6 = to_global(static_cast<OutT *>(J.sig6));
         // The block's cells, requested ahead of the MFMA chain.
         const int cell = perm[pc0 + lane % 16];
         const double *bp = U + (size_t)(lane / 16) * ld + pc0 + lane % 16;
@@ -181,14 +182,17 @@ __global__ __launch_bounds__(512, 1) void k_recon_f64_lds(const double *psi, con
 // flight while the current chunk's MFMAs run, so no block starts with an
 // exposed round trip, and two chunks of u take the registers one whole
 // block took (no spills).  Same products in the same order as
-// k_recon_f64_lds, so the same bits.  Bases of exactly KS k-steps.
-template <class OutT, int KS, int KC>
+// k_recon_f64_lds, so the same bits.  The basis is stored with LDK columns
+// and takes KS k-steps (4 KS <= LDK): a basis of 168 in the 176-column
+// layout issues 42, not the 2 padding steps that only add zeros.
+template <class OutT, int KS, int KC, int LDK = 4 * KS>
 __global__ __launch_bounds__(512, 1) void k_recon_f64_pipe(const double *psi, const double *sig_t, const double *U,
                                                            const int32_t *perm, int ld, const ReconJob *jobs,
                                                            int n_jobs, int total_sb, int chunk, int n_elem) {
     static_assert(KS % KC == 0, "chunks must tile the k-steps");
+    static_assert(4 * KS <= LDK, "the k-steps must fit the stored columns");
     constexpr int NCH = KS / KC;
-    constexpr int ldk = 4 * KS;
+    constexpr int ldk = LDK;
     __shared__ double lds[6 * ldk * 16];
     __shared__ double st_lds[16][6];
     const int eb = blockIdx.x;
@@ -225,8 +229,8 @@ __global__ __launch_bounds__(512, 1) void k_recon_f64_pipe(const double *psi, co
     while (true) {
         const ReconJob &J = jobs[j];
         const double dT = J.dT;
-        OutT *vm = static_cast<OutT *>(J.vm);
-        OutT *sig6 = static_cast<OutT *>(J.sig6);
+        global_ptr<OutT> vm = to_global(static_cast<OutT *>(J.vm));
+        global_ptr<OutT> sig6 = to_global(static_cast<OutT *>(J.sig6));
         const int cell = perm[pc0 + lane % 16];
         const int fn = f + 8;
         jn = j;
@@ -363,7 +367,7 @@ __global__ __launch_bounds__(256, KSMAX <= 6 ? 2 : 1) void k_recon_bf16(const bf
     for (int base = y0 + wave * CB; base < y1; base += 4 * CB) {
         // Jobs, outputs and cells of the CB blocks, requested ahead of the MFMAs.
         double dTv[CB];
-        float *vmv[CB], *s6v[CB];
+        global_ptr<float> vmv[CB], s6v[CB];
         int cellv[CB];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
@@ -371,8 +375,8 @@ __global__ __launch_bounds__(256, KSMAX <= 6 ? 2 : 1) void k_recon_bf16(const bf
             while (j + 1 < n_jobs && v >= jobs[j + 1].sb_off) ++j;
             const ReconJob &J = jobs[j];
             dTv[cb] = J.dT;
-            vmv[cb] = static_cast<float *>(J.vm);
-            s6v[cb] = static_cast<float *>(J.sig6);
+            vmv[cb] = to_global(static_cast<float *>(J.vm));
+            s6v[cb] = to_global(static_cast<float *>(J.sig6));
             cellv[cb] = perm[(size_t)(J.sb_first + (v - J.sb_off)) * 16 + lane % 16];
         }
         f32x4 acc[CB][6];
@@ -407,7 +411,7 @@ __global__ __launch_bounds__(256, KSMAX <= 6 ? 2 : 1) void k_recon_bf16(const bf
         for (int cb = 0; cb < CB; ++cb) {
             if (base + cb >= y1) continue;
             const double dT = dTv[cb];
-            float *vm = vmv[cb], *sig6 = s6v[cb];
+            global_ptr<float> vm = vmv[cb], sig6 = s6v[cb];
             const int cell = cellv[cb];
             if (cell < 0) continue;
             const int e0 = eb * 16 + 4 * (lane / 16);
@@ -424,7 +428,7 @@ __global__ __launch_bounds__(256, KSMAX <= 6 ? 2 : 1) void k_recon_bf16(const bf
             const bool whole = e0 + 3 < n_elem && o % 4 == 0;
             if (vm) {
                 if (whole) {
-                    *(f32x4 *)(vm + o) = f32x4{vq[0], vq[1], vq[2], vq[3]};
+                    *(global_ptr<f32x4>)(vm + o) = f32x4{vq[0], vq[1], vq[2], vq[3]};
                 } else {
                     for (int q = 0; q < 4; ++q)
                         if (e0 + q < n_elem) vm[o + q] = vq[q];
@@ -434,7 +438,7 @@ __global__ __launch_bounds__(256, KSMAX <= 6 ? 2 : 1) void k_recon_bf16(const bf
                 if (whole) {
 #pragma unroll
                     for (int jj = 0; jj < 6; ++jj)
-                        *(f32x4 *)(sig6 + o * 6 + 4 * jj) =
+                        *(global_ptr<f32x4>)(sig6 + o * 6 + 4 * jj) =
                             f32x4{sq[(4 * jj) / 6][(4 * jj) % 6], sq[(4 * jj + 1) / 6][(4 * jj + 1) % 6],
                                   sq[(4 * jj + 2) / 6][(4 * jj + 2) % 6], sq[(4 * jj + 3) / 6][(4 * jj + 3) % 6]};
                 } else {
@@ -489,7 +493,7 @@ __global__ __launch_bounds__(512, 1) void k_recon_bf16_x2(const bf16x8 *psi_hi, 
     int j = 0;  // job of the wave's current block (blocks only move forward)
     for (int base = y0 + wave * CB; base < y1; base += NW * CB) {
         double dTv[CB];
-        float *vmv[CB], *s6v[CB];
+        global_ptr<float> vmv[CB], s6v[CB];
         int cellv[CB];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
@@ -497,8 +501,8 @@ __global__ __launch_bounds__(512, 1) void k_recon_bf16_x2(const bf16x8 *psi_hi, 
             while (j + 1 < n_jobs && v >= jobs[j + 1].sb_off) ++j;
             const ReconJob &J = jobs[j];
             dTv[cb] = J.dT;
-            vmv[cb] = static_cast<float *>(J.vm);
-            s6v[cb] = static_cast<float *>(J.sig6);
+            vmv[cb] = to_global(static_cast<float *>(J.vm));
+            s6v[cb] = to_global(static_cast<float *>(J.sig6));
             cellv[cb] = perm[(size_t)(J.sb_first + (v - J.sb_off)) * 16 + lane % 16];
         }
         f32x4 acc[2][CB][6];
@@ -563,7 +567,7 @@ __global__ __launch_bounds__(512, 1) void k_recon_bf16_x2(const bf16x8 *psi_hi, 
             for (int cb = 0; cb < CB; ++cb) {
                 if (base + cb >= y1) continue;
                 const double dT = dTv[cb];
-                float *vm = vmv[cb], *sig6 = s6v[cb];
+                global_ptr<float> vm = vmv[cb], sig6 = s6v[cb];
                 const int cell = cellv[cb];
                 if (cell < 0) continue;
                 const int e0 = (eb0 + b) * 16 + 4 * (lane / 16);
@@ -581,7 +585,7 @@ __global__ __launch_bounds__(512, 1) void k_recon_bf16_x2(const bf16x8 *psi_hi, 
                 const bool whole = e0 + 3 < n_elem && o % 4 == 0;
                 if (vm) {
                     if (whole) {
-                        *(f32x4 *)(vm + o) = f32x4{vq[0], vq[1], vq[2], vq[3]};
+                        *(global_ptr<f32x4>)(vm + o) = f32x4{vq[0], vq[1], vq[2], vq[3]};
                     } else {
                         for (int q = 0; q < 4; ++q)
                             if (e0 + q < n_elem) vm[o + q] = vq[q];
@@ -628,7 +632,12 @@ mos_status recon_f64_jobs(mos_ctx ctx, const mos_rom *roms, int n_types, const s
         const dim3 grid(r->n_eblk, ceil_div(total, chunk));
         const double *psi = roms[t]->psi, *sgt = roms[t]->sig_t;
         const ReconJob *dj = dev_jobs + first[t];
-        if (ks == RECON_F64_LDS_KS && !fp32_out && recon_f64_variant() == 2)
+        // A basis of 168 (the benchmark cells) needs 42 of the 44 k-steps.
+        const bool ks42 = ks == RECON_F64_LDS_KS && ceil_div(r->n, 4) == 42;
+        if (ks42 && !fp32_out && recon_f64_variant() == 2)
+            launch_timed(ctx, MOS_K_RECON, k_recon_f64_pipe<double, 42, 6, 4 * RECON_F64_LDS_KS>, grid, dim3(512), 0,
+                         st, psi, sgt, U, perm, ld, dj, nj, total, chunk, r->n_elem);
+        else if (ks == RECON_F64_LDS_KS && !fp32_out && recon_f64_variant() == 2)
             launch_timed(ctx, MOS_K_RECON, k_recon_f64_pipe<double, RECON_F64_LDS_KS, 11>, grid, dim3(512), 0, st,
                          psi, sgt, U, perm, ld, dj, nj, total, chunk, r->n_elem);
         else if (ks == RECON_F64_LDS_KS && fp32_out && recon_f64_variant() == 2)
