@@ -181,9 +181,10 @@ def oracle_solve(case, oroms, field_dofs=None):
 def cpu_baseline(cases, min_seconds=10.0):
     """The oracle's global stage on consecutive arrays of the workload, on
     the host cores, until at least `min_seconds` of timed work (or all of
-    them).  Each distinct cell's local stage is run first and not timed.
-    Returns the record and the oracle's (u, von Mises) of every array
-    solved."""
+    them), then the first array once more with its BLAS pools held to one
+    thread (`value_1_thread`); the host's CPU model is recorded beside.
+    Each distinct cell's local stage is run first and not timed.  Returns
+    the record and the oracle's (u, von Mises) of every array solved."""
     from oracle import mor as omor
     roms = {}
     elapsed, cells, refs = 0.0, 0, []
@@ -203,8 +204,29 @@ def cpu_baseline(cases, min_seconds=10.0):
            "kind": "oracle",
            "sample": f"full global stage of {len(refs)} {c0.nx_cells}x{c0.ny_cells} arrays of the workload's "
                      f"cell ({cells} cells, {elapsed:.2f} s; {bc}): assembly, lifting, direct solve, centroid "
-                     f"stress of every element; host has {os.cpu_count()} logical CPUs"}
+                     f"stress of every element; host has {os.cpu_count()} logical CPUs",
+           "cpu_model": cpu_model()}
+    # The first array once more with the BLAS pools held to one thread.
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            oracle_solve(c0, [roms[s] for s in c0.specs])
+            out["value_1_thread"] = round(c0.n_cells / (time.perf_counter() - t0), 3)
+    except ImportError:
+        pass
     return out, refs
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def rel_max(a, b):
