@@ -418,7 +418,7 @@ __device__ __forceinline__ double tile_dot_vals(const V4 &acc, const T (&t)[4]) 
 // pdel[slot block * row blocks + row block].  (Staging a row block of K_r
 // in LDS for a whole workgroup was measured slower at every batch size: the
 // extra barrier and serial staging cost more than the occupancy it frees.)
-template <class T, int KS, bool EXACT>
+template <class T, int KS, bool EXACT, int KK = KS>
 __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, const int32_t *sb_rom,
                                                     const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots,
                                                     int sb_base, int n_sb, int spw, int gate, int ks,
@@ -426,8 +426,11 @@ __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, c
     typedef typename Mfma<T>::v4 v4;
     // KS bounds the k-steps held in registers; the basis uses ks <= KS of
     // them (ldk = 4 ks), and steps past ks are neither loaded nor issued.
-    // EXACT instances (ks == KS) keep every operand offset an immediate.
+    // EXACT instances (ks == KS) keep every operand offset an immediate,
+    // and issue the first KK of them: a basis of 168 in the 176-row layout
+    // needs 42 of 44 (the last two multiply zero padding of K_r and u).
     if (EXACT) ks = KS;
+    const int kd = EXACT ? KK : ks;
     // FP64 pipelines the slot blocks and requests the epilogue operands
     // ahead of the chain.  FP32 (twice the MFMA rate, four waves per SIMD)
     // was measured faster issuing each block's loads after the previous
@@ -458,7 +461,7 @@ __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, c
     {
         const T *bp = lane_b + (size_t)(sb_base + sl) * 16;
 #pragma unroll
-        for (int k = 0; k < KS; ++k) b[k] = k < ks ? bp[(size_t)(4 * k) * ld_slots] : T(0);
+        for (int k = 0; k < KS; ++k) b[k] = k < kd ? bp[(size_t)(4 * k) * ld_slots] : T(0);
     }
     int cur = -1;
     while (sl < s_end) {
@@ -478,7 +481,7 @@ __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, c
         if (rom != cur) {
             global_ptr<const T> ap = kr[rom] + (size_t)(lane / 16) * ldk + rb * 16 + lane % 16;
 #pragma unroll
-            for (int k = 0; k < KS; ++k) a[k] = k < ks ? ap[(size_t)(4 * k) * ldk] : T(0);
+            for (int k = 0; k < KS; ++k) a[k] = k < kd ? ap[(size_t)(4 * k) * ldk] : T(0);
             cur = rom;
             vm_wait_all();
         }
@@ -490,18 +493,18 @@ __global__ __launch_bounds__(256) void k_bgemm_rows(const void *const *kr_tab, c
             const T *bn = lane_b + (size_t)(sb_base + (nx < s_end ? nx : sl)) * 16;
 #pragma unroll
             for (int k = 0; k < KS; ++k)
-                if (k < ks) {
+                if (k < kd) {
                     acc = Mfma<T>::op(a[k], b[k], acc);
                     b[k] = bn[(size_t)(4 * k) * ld_slots];
                 }
         } else {
 #pragma unroll
             for (int k = 0; k < KS; ++k)
-                if (k < ks) acc = Mfma<T>::op(a[k], b[k], acc);
+                if (k < kd) acc = Mfma<T>::op(a[k], b[k], acc);
             if (!PIPELINE && nx < s_end) {
                 const T *bn = lane_b + (size_t)(sb_base + nx) * 16;
 #pragma unroll
-                for (int k = 0; k < KS; ++k) b[k] = k < ks ? bn[(size_t)(4 * k) * ld_slots] : T(0);
+                for (int k = 0; k < KS; ++k) b[k] = k < kd ? bn[(size_t)(4 * k) * ld_slots] : T(0);
             }
         }
 #pragma unroll
@@ -534,7 +537,7 @@ struct Chunk16<float> {
     typedef float v __attribute__((ext_vector_type(4)));
 };
 
-template <class T, int KS, bool EXACT>
+template <class T, int KS, bool EXACT, int KK = KS>
 __global__ __launch_bounds__(704) void k_bgemm_wg(const void *const *kr_tab, const int32_t *sb_rom,
                                                   const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots,
                                                   int sb_base, int n_sb, int spw, int gate, int ks,
@@ -547,6 +550,7 @@ __global__ __launch_bounds__(704) void k_bgemm_wg(const void *const *kr_tab, con
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T *tiles = reinterpret_cast<T *>(lds_raw);  // [2][ldk][16]
     if (EXACT) ks = KS;
+    const int kd = EXACT ? KK : ks;  // k-steps that carry data (as in k_bgemm_rows)
     const int ldk = 4 * ks;
     const int nrb = ks / 4;
     const int nthr = 64 * nrb;
@@ -593,7 +597,7 @@ __global__ __launch_bounds__(704) void k_bgemm_wg(const void *const *kr_tab, con
         if (rom != cur) {
             global_ptr<const T> ap = kr[rom] + (size_t)(lane / 16) * ldk + rb * 16 + lane % 16;
 #pragma unroll
-            for (int k = 0; k < KS; ++k) a[k] = k < ks ? ap[(size_t)(4 * k) * ldk] : T(0);
+            for (int k = 0; k < KS; ++k) a[k] = k < kd ? ap[(size_t)(4 * k) * ldk] : T(0);
             cur = rom;
             vm_wait_all();
         }
@@ -609,7 +613,7 @@ __global__ __launch_bounds__(704) void k_bgemm_wg(const void *const *kr_tab, con
         v4 acc = {0, 0, 0, 0};
 #pragma unroll
         for (int k = 0; k < KS; ++k)
-            if (k < ks) acc = Mfma<T>::op(a[k], tb[(4 * k + lane / 16) * 16 + lane % 16], acc);
+            if (k < kd) acc = Mfma<T>::op(a[k], tb[(4 * k + lane / 16) * 16 + lane % 16], acc);
         const int col = sb * 16 + lane % 16;
 #pragma unroll
         for (int q = 0; q < 4; ++q) Y[(size_t)(rb * 16 + Mfma<T>::row(lane, q)) * ld_slots + col] = acc[q];
@@ -636,7 +640,7 @@ __global__ __launch_bounds__(704) void k_bgemm_wg(const void *const *kr_tab, con
 // Gate 1 skips slot blocks whose problem is not iterating, gate 2 those of
 // problems not in sel.  The launch is sampled by the kernel timer under
 // timed_id (0: never).
-template <class T, int KS, bool EXACT>
+template <class T, int KS, bool EXACT, int KK = KS>
 void launch_cell_gemm_ks(mos_ctx ctx, int timed_id, int path, int spw, hipStream_t st, const void *const *kr_tab,
                          const int32_t *sb_rom, const int32_t *sb_prob, const T *Mc, T *Y, int ld_slots, int n_sb,
                          int ks, const ProbState *ps, double *pdel, int gate, const ProbSel &sel) {
@@ -644,21 +648,26 @@ void launch_cell_gemm_ks(mos_ctx ctx, int timed_id, int path, int spw, hipStream
     if (path == 1) {
         const dim3 grid((unsigned)ceil_div(n_sb, spw));
         const size_t lds = 2 * (size_t)(4 * ks) * 16 * sizeof(T);
-        launch_timed(ctx, timed_id, k_bgemm_wg<T, KS, EXACT>, grid, dim3(64 * nrb), (uint32_t)lds, st, kr_tab,
+        launch_timed(ctx, timed_id, k_bgemm_wg<T, KS, EXACT, KK>, grid, dim3(64 * nrb), (uint32_t)lds, st, kr_tab,
                      sb_rom, sb_prob, Mc, Y, ld_slots, 0, n_sb, spw, gate, ks, ps, pdel, sel);
     } else {
         const dim3 grid((unsigned)ceil_div((int64_t)nrb * ceil_div(n_sb, spw), 4));
-        launch_timed(ctx, timed_id, k_bgemm_rows<T, KS, EXACT>, grid, dim3(256), 0, st, kr_tab, sb_rom, sb_prob,
+        launch_timed(ctx, timed_id, k_bgemm_rows<T, KS, EXACT, KK>, grid, dim3(256), 0, st, kr_tab, sb_rom, sb_prob,
                      Mc, Y, ld_slots, 0, n_sb, spw, gate, ks, ps, pdel, sel);
     }
 }
 
+// ks = ldk / 4 k-steps of the padded layout, of which the basis of n
+// columns fills ceil(n / 4).
 template <class T>
-mos_status launch_cell_gemm(mos_ctx ctx, int timed_id, int path, int ks, int spw, hipStream_t st,
+mos_status launch_cell_gemm(mos_ctx ctx, int timed_id, int path, int ks, int n, int spw, hipStream_t st,
                             const void *const *kr_tab, const int32_t *sb_rom, const int32_t *sb_prob, const T *Mc,
                             T *Y, int ld_slots, int n_sb, const ProbState *ps, double *pdel, int gate,
                             const ProbSel &sel) {
-    if (ks == 8)
+    if (ks == ROWS_MAX_KS && ceil_div(n, 4) == 42)
+        launch_cell_gemm_ks<T, ROWS_MAX_KS, true, 42>(ctx, timed_id, path, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y,
+                                                      ld_slots, n_sb, ks, ps, pdel, gate, sel);
+    else if (ks == 8)
         launch_cell_gemm_ks<T, 8, true>(ctx, timed_id, path, spw, st, kr_tab, sb_rom, sb_prob, Mc, Y, ld_slots,
                                         n_sb, ks, ps, pdel, gate, sel);
     else if (ks == 20)
@@ -2218,7 +2227,7 @@ mos_status residual_batch(mos_engine e, const Batch &B, bool lift) {
     // The K_r-stationary variants share one FP64 product here (operand tiles
     // in LDS), so all of them give the same residual bits.
     if (e->gemm_rows)
-        MOS_TRY(launch_cell_gemm<double>(e->ctx, 0, 1, e->ldk / 4, 1, st, (const void *const *)e->kr64_tab, e->sb_rom,
+        MOS_TRY(launch_cell_gemm<double>(e->ctx, 0, 1, e->ldk / 4, e->n, 1, st, (const void *const *)e->kr64_tab, e->sb_rom,
                                          e->sb_prob, (const double *)e->Mc64, e->Y64, e->ld_slots, hw_sb,
                                          (const ProbState *)e->ps, (double *)nullptr, 2, B.sel));
     else
@@ -2952,7 +2961,7 @@ mos_status rows_step(mos_engine e, int ks, int hw_sb) {
     auto launch = [&](int cand) {
         int spw = Tn.cand_spw[cand];
         if (spw == GemmTuner::CHIP_SPLIT) spw = std::min(64, std::max(1, ceil_div(hw_sb, e->ctx->n_cu)));
-        return launch_cell_gemm<T>(e->ctx, MOS_K_CELL_GEMM, Tn.cand_path[cand], ks, spw, st, tab,
+        return launch_cell_gemm<T>(e->ctx, MOS_K_CELL_GEMM, Tn.cand_path[cand], ks, e->n, spw, st, tab,
                                    e->sb_rom, e->sb_prob, (const T *)e->Mc, (T *)e->Yi, e->ld_slots, hw_sb,
                                    (const ProbState *)e->ps, e->pdel, 1, ProbSel{});
     };
