@@ -909,18 +909,25 @@ def convergence_mode(args, mos, torch, np, W):
 def calib_mode(args, torch):
     """A plain device copy of known size (1 GiB read, 1 GiB written per
     launch): the reference that scales the FETCH_SIZE / WRITE_SIZE counters
-    of the profiled kernels into HBM bytes."""
+    of the profiled kernels into HBM bytes, and the sustained copy and fill
+    rates (event-timed after a warm-up copy) that the bandwidth-bound
+    kernels are compared with."""
     n = 1 << 28
     x = torch.ones(n, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
+    y.copy_(x)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        y.copy_(x)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    rates = {}
+    for name, fn, nbytes in (("copy", lambda: y.copy_(x), 8 * n), ("fill", lambda: y.fill_(2.0), 4 * n)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        rates[name] = round(nbytes * args.steps / (e0.elapsed_time(e1) * 1e6), 1)
     print(json.dumps({"mode": "calib", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
-                      "launches": args.steps, "copy_GBps": round(8 * n / dt / 1e9, 1)}))
+                      "launches": args.steps + 1, "copy_GBps": rates["copy"], "fill_GBps": rates["fill"]}))
 
 
 
