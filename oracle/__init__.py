@@ -18,6 +18,10 @@ array   : the global stage: abstract mesh numbering, assembly, Dirichlet
           plus the full fine-mesh FEM of a whole array for comparison.
 plane   : the paper's evaluation (Sec. 5.1): von Mises on a grid of points
           on each block's mid-height plane, normalised MAE and max-norm error.
+krylov  : the condition estimate of the preconditioned system of eq. 20 a
+          CG solve yields (Ritz values on its Krylov space), and the
+          library's two preconditioners (Jacobi, two-level) written out
+          densely from their definitions.
 
 Every floating-point quantity is float64.  Solves use SciPy's sparse LU
 (a library primitive); no blocking, fusion or reordering is done beyond what
