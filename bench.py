@@ -326,6 +326,13 @@ def solve_leg(args, mos, torch, np, ctx, roms, case, prec, kw, workload_key):
     wall = (time.perf_counter() - t1) / args.steps
     launches, k_ms, seen = mos.mos_timing_stop(ctx)
     st, rel, iters, sweeps = res[-1]
+    # Condition estimate of the preconditioned reduced system, from the
+    # first sweep's PCG coefficients of one more (untimed) solve.
+    tk = eng.submit(case.nx_cells, case.ny_cells, case.cell_type, case.delta_T, vm=vm, **kw)
+    while tk not in eng.progress(args.chunk):
+        pass
+    kappa, kappa_steps = eng.cond_estimate(tk)
+    eng.result(tk)
     if st != 0:
         raise RuntimeError(f"{prec} solve failed with status {st}: {eng.last_error}")
     name, bound, unit, note = KERNEL_INFO[dominant]
@@ -341,6 +348,7 @@ def solve_leg(args, mos, torch, np, ctx, roms, case, prec, kw, workload_key):
         "value": round(n_cells / wall, 2), "ms_per_solve": round(wall * 1e3, 3),
         "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
         "pcg_iters": iters, "refinement_sweeps": sweeps, "rel_residual": rel,
+        "cond_estimate": {"kappa": round(kappa, 3), "lanczos_steps": kappa_steps},
         "roofline": {"bound": bound, "achieved": round(achieved, 4), "peak": peak, "unit": unit,
                      "frac": round(achieved / peak, 5), "traffic": recorded_traffic(name, workload_key, prec),
                      "traffic_unit": "bytes/launch", "kernel": name, "avg_launch_us": round(avg_s * 1e6, 3),
@@ -455,6 +463,7 @@ def c5_mode(args, mos, torch, np, W):
         "pcg_iters": head["pcg_iters"],
         "refinement_sweeps": head["refinement_sweeps"],
         "rel_residual": head["rel_residual"],
+        "cond_estimate": head["cond_estimate"],
         "roofline": head["roofline"],
         "kernel_classes": head["kernel_classes"],
         "kernels_ms_per_solve": head["kernels_ms_per_solve"],
@@ -463,7 +472,7 @@ def c5_mode(args, mos, torch, np, W):
             "value": mx["value"], "unit": "TSV-cells/s", "ms_per_solve": mx["ms_per_solve"],
             "dtype": "f32+bf16+f64", "p50_ms": mx["p50_ms"], "p99_ms": mx["p99_ms"], "pcg_iters": mx["pcg_iters"],
             "refinement_sweeps": mx["refinement_sweeps"], "rel_residual": mx["rel_residual"],
-            "max_rel_err_vm_vs_fp64": err, "normalized_mae_vm_vs_fp64": nmae,
+            "cond_estimate": mx["cond_estimate"], "max_rel_err_vm_vs_fp64": err, "normalized_mae_vm_vs_fp64": nmae,
             "roofline": mx["roofline"], "kernel_classes": mx["kernel_classes"],
             "kernels_ms_per_solve": mx["kernels_ms_per_solve"]},
         "accuracy_vs_oracle": check,
@@ -740,7 +749,9 @@ def single_mode(args, mos, torch, np, W):
                    "dummy_cells": int((case.cell_type != 0).sum()),
                    "bc": "bottom and top clamped" if case.clamp_top else "bottom clamped",
                    "delta_T": case.delta_T, "seed": args.seed, "precision": "fp64 (record); mixed beside it"},
-        "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"],
+        "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "pcg_iters": head["pcg_iters"],
+        "refinement_sweeps": head["refinement_sweeps"], "rel_residual": head["rel_residual"],
+        "cond_estimate": head["cond_estimate"],
         "roofline": head["roofline"], "kernel_classes": head["kernel_classes"],
         "mixed_side_by_side": paths["mixed"], "max_rel_err_vm_mixed_vs_fp64": err,
         "local_stage_ms_total": round(local_ms, 1),

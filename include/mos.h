@@ -239,6 +239,16 @@ mos_status mos_reconstruct_plane(mos_ctx ctx, mos_sol sol, int32_t grid, void *v
 /* Copy the reduced solution (n_global_dofs doubles) to host memory and report
  * the final relative true residual and total PCG iterations (any may be NULL). */
 mos_status mos_get_solution(mos_sol sol, double *u_host, double *rel_residual, int32_t *iters);
+/* Estimate of the condition number of the preconditioned operator M^-1 A
+ * of the reduced system (eq. 20) that the PCG solved, from its own step
+ * sizes: the steps alpha_j, beta_j of the first sweep (at most its first
+ * 128) define the Lanczos tridiagonal of CG, whose extreme Ritz values lie
+ * inside the spectrum of M^-1 A and approach its ends as the sweep
+ * converges, so *kappa is their ratio: a lower bound that is close once the
+ * sweep has converged; *steps = the steps used.  0 and 0 when the first
+ * sweep took fewer than two steps.  The mixed path reports its FP32 inner
+ * solve's operator.  MOS_EINVAL for an invalid handle. */
+mos_status mos_get_cond_estimate(mos_sol sol, double *kappa, int32_t *steps);
 
 enum {
     MOS_Q_N = 1,            /* rom/cell: reduced DoFs per cell, n (eq. 16) */
@@ -315,6 +325,10 @@ mos_status mos_engine_progress(mos_engine e, int32_t iterations, int64_t *comple
  * forgotten afterwards.  MOS_EBUSY if it has not completed. */
 mos_status mos_engine_result(mos_engine e, int64_t ticket, int32_t *status, double *rel_residual, int32_t *iters,
                              int32_t *sweeps);
+/* The condition estimate of mos_get_cond_estimate for a completed ticket,
+ * taken before mos_engine_result forgets the ticket (MOS_EBUSY if it has
+ * not completed or was already taken). */
+mos_status mos_engine_cond_estimate(mos_engine e, int64_t ticket, double *kappa, int32_t *steps);
 /* Engine options.  MOS_OPT_CELL_GEMM selects the cell-GEMM variant of the
  * PCG matvec (the per-type product K_r * u_cell of eq. 20 over all cells):
  * 1 = 16x16 output tiles with the contraction split over four waves (any

@@ -520,6 +520,8 @@ mos_status mos_solve_array(mos_ctx ctx, const mos_array_desc *d, const mos_rom *
     s->rel_residual = P->rel;
     s->iters = P->iters;
     s->refines = P->sweeps;
+    s->cond = P->cond;
+    s->cond_steps = P->cond_steps;
     s->n_types = n_roms;
     s->roms.assign(roms, roms + n_roms);
     s->seg.resize(n_roms + 1);
@@ -636,6 +638,21 @@ mos_status mos_engine_result(mos_engine e, int64_t ticket, int32_t *status, doub
     if (P->status != MOS_OK) set_error("%s", P->error.c_str());
     delete P;
     e->finished.erase(it);
+    return MOS_OK;
+}
+
+mos_status mos_engine_cond_estimate(mos_engine e, int64_t ticket, double *kappa, int32_t *steps) {
+    if (!e) {
+        set_error("invalid engine");
+        return MOS_EINVAL;
+    }
+    auto it = e->finished.find(ticket);
+    if (it == e->finished.end()) {
+        set_error("ticket %lld has not completed (or its result was already taken)", (long long)ticket);
+        return MOS_EBUSY;
+    }
+    if (kappa) *kappa = it->second->cond;
+    if (steps) *steps = it->second->cond_steps;
     return MOS_OK;
 }
 
@@ -801,6 +818,16 @@ mos_status mos_get_solution(mos_sol sol, double *u_host, double *rel_residual, i
     }
     if (rel_residual) *rel_residual = sol->rel_residual;
     if (iters) *iters = sol->iters;
+    return MOS_OK;
+}
+
+mos_status mos_get_cond_estimate(mos_sol sol, double *kappa, int32_t *steps) {
+    if (!sol || sol->kind != KIND_SOL) {
+        set_error("invalid solution handle");
+        return MOS_EINVAL;
+    }
+    if (kappa) *kappa = sol->cond;
+    if (steps) *steps = sol->cond_steps;
     return MOS_OK;
 }
 

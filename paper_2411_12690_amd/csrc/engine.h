@@ -13,6 +13,7 @@
 namespace mos {
 
 constexpr int MAX_PROBS = 1024;  // problems resident in one engine at a time
+constexpr int LZ_MAX = 128;      // PCG steps of a problem's first sweep kept for its Lanczos estimate
 
 // Per-problem PCG scalars in device memory.  Written by the problem's scalar
 // wave (iteration launches) or by single-thread set-up kernels; read by the
@@ -185,6 +186,8 @@ struct mos_engine_s {
     hipEvent_t mirror_ev = nullptr;
     mos::ProbState *ps = nullptr;             // [MAX_PROBS]
     mos::ProbState *ps_host = nullptr;        // pinned: states read back at the end of a chunk
+    double *lz = nullptr;                     // pinned, written by the device: (alpha, beta) of the first
+                                              // sweep's steps, [MAX_PROBS][LZ_MAX][2]
     double *res2 = nullptr, *bb2 = nullptr;   // [MAX_PROBS]
     int32_t *pres_bad = nullptr;              // [MAX_PROBS]: a device-resident prescribed list held a bad entry
     double *host_scratch = nullptr;           // pinned: a few doubles read back from the device
@@ -252,6 +255,8 @@ struct EngineProblem {
     double dT = 0.0, rtol = 0.0;
     int max_iters = 0, iters = 0, sweeps = 0;
     double rel = 1.0;
+    double cond = 0.0;   // Lanczos estimate of kappa(M^-1 A) from the first sweep (0: none)
+    int cond_steps = 0;  // PCG steps it used
     double last_res2 = -1.0;      // FP64 residual before the last correction
     int sweep_cap = 0;            // inner iterations allowed per sweep
     int undone = 0;               // corrections undone because they raised the residual

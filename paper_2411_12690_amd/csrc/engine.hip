@@ -212,8 +212,10 @@ __device__ CgStep cg_scalars_block(const ProbState &S, int it, const double *pg,
 }
 
 // Publish iteration `it`'s outcome (one writer per problem and iteration).
-// Readers of the same launch only read the other history slot.
-__device__ __forceinline__ void cg_publish(ProbState &S, int it, const CgStep &o) {
+// Readers of the same launch only read the other history slot.  The steps
+// of the problem's first sweep (up to LZ_MAX) also go to its row lz of the
+// Lanczos record, (alpha, beta) per step.
+__device__ __forceinline__ void cg_publish(ProbState &S, int it, const CgStep &o, double *lz) {
     S.rr = o.rr;
     if (it == S.seg_start) S.tol2 = o.tol2;
     if (o.stop) {
@@ -224,7 +226,16 @@ __device__ __forceinline__ void cg_publish(ProbState &S, int it, const CgStep &o
         S.hist_gamma[it & 1] = o.gamma;
         S.hist_alpha[it & 1] = o.alpha;
         S.it = it + 1;
+        if (lz && S.seg_start == 0 && it < LZ_MAX) {
+            lz[2 * it] = o.alpha;
+            lz[2 * it + 1] = o.beta;
+        }
     }
+}
+
+// Row of problem pid in the Lanczos record (null: none kept).
+__device__ __forceinline__ double *lz_row(double *lz, int pid) {
+    return lz ? lz + (size_t)pid * LZ_MAX * 2 : nullptr;
 }
 
 // Separate scalar launch for problems too large to reduce in every update
@@ -240,7 +251,8 @@ __device__ __forceinline__ void cg_publish(ProbState &S, int it, const CgStep &o
 // always take this order.
 constexpr int CG_BIG = 1024;
 __global__ __launch_bounds__(CG_BIG) void k_cg_scalars(ProbState *ps, const double *pg, const double *pr,
-                                                       const double *pdel, const int *ep, int j, int cap_blk) {
+                                                       const double *pdel, const int *ep, int j, int cap_blk,
+                                                       double *lz) {
     __shared__ double red[3][CG_BIG / 64];
     const int epoch = ep[0] + j;
     ProbState &S = ps[blockIdx.x];
@@ -275,7 +287,7 @@ __global__ __launch_bounds__(CG_BIG) void k_cg_scalars(ProbState *ps, const doub
         sum[q] = red[q][0];
         for (int w = 1; w < CG_BIG / 64; ++w) sum[q] += red[q][w];
     }
-    cg_publish(S, it, cg_step(S, it, sum[0], sum[1], sum[2]));
+    cg_publish(S, it, cg_step(S, it, sum[0], sum[1], sum[2]), lz_row(lz, (int)blockIdx.x));
 }
 
 // (u, A u) over one 16x16 output tile: the tile's products times the cell
@@ -830,7 +842,7 @@ __global__ __launch_bounds__(NT) void k_cgstep(const T *Y, const int32_t *inc, c
                                                const uint8_t *cmask, const T *dinv, T *x, T *r, T *p, T *s, T *Mc,
                                                int ld_slots, const int32_t *blk_prob, ProbState *ps, double *pg,
                                                double *pr, const double *pdel, const int *ep, int j, int cap_blk,
-                                               int n_blk) {
+                                               int n_blk, double *lz) {
     constexpr int DPT = DB / NT;
     __shared__ int go, it_sh;
     __shared__ double step[2];
@@ -880,7 +892,7 @@ __global__ __launch_bounds__(NT) void k_cgstep(const T *Y, const int32_t *inc, c
         // bits in each); the problem's first workgroup publishes the state.
         ProbState &S = ps[pb];
         const CgStep o = cg_scalars_block<NT>(S, it, pg + rd_slot, pr + rd_slot, pdel, red);
-        if (threadIdx.x == 0 && blk == S.blk_begin) cg_publish(S, it, o);
+        if (threadIdx.x == 0 && blk == S.blk_begin) cg_publish(S, it, o, lz_row(lz, pb));
         if (o.stop) return;
         if (threadIdx.x == 0) {
             step[0] = o.alpha;
@@ -1165,7 +1177,7 @@ __global__ __launch_bounds__(1024) void k_cgstep2(const T *Y, const int32_t *inc
                                                   int ld_slots, const int4 *box_tab, const ProbParams *pp,
                                                   ProbState *ps, double *pg, double *pr, const double *pdel,
                                                   const double *binv, double *cc, const int *ep, int j,
-                                                  int cap_blk, int n_box) {
+                                                  int cap_blk, int n_box, double *lz) {
     // Dynamic LDS: the per-node restriction terms (blockDim.x x 6 doubles),
     // first used as the scalar step's reduction space (3 x CG_LW doubles).
     extern __shared__ double qn_dyn[];
@@ -1230,7 +1242,7 @@ __global__ __launch_bounds__(1024) void k_cgstep2(const T *Y, const int32_t *inc
     if (go == 2) {
         ProbState &S = ps[pb];
         const CgStep o = cg_scalars_wide(S, it, pg + rd_slot, pr + rd_slot, pdel, red);
-        if (t == 0 && bs == S.blk_begin) cg_publish(S, it, o);
+        if (t == 0 && bs == S.blk_begin) cg_publish(S, it, o, lz_row(lz, pb));
         if (o.stop) return;
         if (t == 0) {
             step[0] = o.alpha;
@@ -2653,6 +2665,15 @@ mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots) {
         set_error("pinned host allocation failed");
         return MOS_ENOMEM;
     }
+    // Written by the scalar step of each iteration (one thread, 16 bytes)
+    // and read by the host once a problem's first sweep has stopped.
+    if (hipHostMalloc((void **)&e->lz, (size_t)MAX_PROBS * LZ_MAX * 2 * sizeof(double), hipHostMallocDefault) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        e->lz = nullptr;
+        set_error("pinned host allocation failed");
+        return MOS_ENOMEM;
+    }
     MOS_HIP(hipEventCreateWithFlags(&e->mirror_ev, hipEventDisableTiming));
     MOS_HIP(hipEventRecord(e->mirror_ev, ctx->stream));
     MOS_TRY(m.alloc_n((size_t)MAX_PROBS * MAX_TYPES, &e->jobs));
@@ -2869,7 +2890,7 @@ void cgstep_launch(mos_engine e, int hw_blk, T *const *V, int j) {
                      (const uint8_t *)e->cmask, (const T *)V[VDINV], (const uint32_t *)e->lc, V[VX], V[VR], V[VP],
                      V[VS], (T *)e->Mc, e->ld_slots, (const int4 *)e->box_tab, (const ProbParams *)e->pp, e->ps,
                      e->pg, e->pr, (const double *)e->pdel, (const double *)e->binv, e->cc,
-                     (const int *)e->epoch_dev, j, e->cap_blk, hw_box);
+                     (const int *)e->epoch_dev, j, e->cap_blk, hw_box, e->lz);
         return;
     }
     const bool wide = e->update_width ? e->update_width == 256 : hw_blk <= CG_WIDE_MAX_BLK;
@@ -2878,12 +2899,12 @@ void cgstep_launch(mos_engine e, int hw_blk, T *const *V, int j) {
         launch_timed(e->ctx, MOS_K_PCG_UPDATE, k_cgstep<T, 256>, grid, dim3(256), 0, st, (const T *)e->Yi,
                      (const int32_t *)e->inc, (const int32_t *)(e->stacked ? e->inc2 : nullptr), (const uint8_t *)e->cmask, (const T *)V[VDINV], V[VX], V[VR], V[VP],
                      V[VS], (T *)e->Mc, e->ld_slots, (const int32_t *)e->blk_prob, e->ps, e->pg, e->pr,
-                     (const double *)e->pdel, (const int *)e->epoch_dev, j, e->cap_blk, hw_blk);
+                     (const double *)e->pdel, (const int *)e->epoch_dev, j, e->cap_blk, hw_blk, e->lz);
     else
         launch_timed(e->ctx, MOS_K_PCG_UPDATE, k_cgstep<T, 128>, grid, dim3(128), 0, st, (const T *)e->Yi,
                      (const int32_t *)e->inc, (const int32_t *)(e->stacked ? e->inc2 : nullptr), (const uint8_t *)e->cmask, (const T *)V[VDINV], V[VX], V[VR], V[VP],
                      V[VS], (T *)e->Mc, e->ld_slots, (const int32_t *)e->blk_prob, e->ps, e->pg, e->pr,
-                     (const double *)e->pdel, (const int *)e->epoch_dev, j, e->cap_blk, hw_blk);
+                     (const double *)e->pdel, (const int *)e->epoch_dev, j, e->cap_blk, hw_blk, e->lz);
 }
 
 // Read the tuning trials of the last chunk (the stream has been synchronised).
@@ -3019,7 +3040,7 @@ mos_status issue_chunk(mos_engine e, int chunk, int hw_sb, int hw_blk, int hw_p,
             if (any_large)
                 launch_timed(ctx, MOS_K_PCG_SCALARS, k_cg_scalars, dim3(hw_p), dim3(CG_BIG), 0, st, e->ps,
                              (const double *)e->pg, (const double *)e->pr, (const double *)e->pdel,
-                             (const int *)e->epoch_dev, j, e->cap_blk);
+                             (const int *)e->epoch_dev, j, e->cap_blk, e->lz);
             cgstep_launch<float>(e, hw_blk, V, j);
         } else {
             double *V[NVEC];
@@ -3034,7 +3055,7 @@ mos_status issue_chunk(mos_engine e, int chunk, int hw_sb, int hw_blk, int hw_p,
             if (any_large)
                 launch_timed(ctx, MOS_K_PCG_SCALARS, k_cg_scalars, dim3(hw_p), dim3(CG_BIG), 0, st, e->ps,
                              (const double *)e->pg, (const double *)e->pr, (const double *)e->pdel,
-                             (const int *)e->epoch_dev, j, e->cap_blk);
+                             (const int *)e->epoch_dev, j, e->cap_blk, e->lz);
             cgstep_launch<double>(e, hw_blk, V, j);
         }
     }
@@ -3136,6 +3157,56 @@ mos_status collect_retired(mos_engine e, std::vector<int64_t> *completed, bool w
 }
 }  // namespace
 
+// Condition estimate of the preconditioned operator from k PCG steps:
+// the Lanczos tridiagonal T of CG, T_jj = 1/alpha_j + beta_j/alpha_{j-1},
+// T_{j-1,j} = sqrt(beta_j)/alpha_{j-1} (beta_0 = 0), has Ritz values inside
+// the spectrum of M^-1 A that approach its ends as the iteration goes on;
+// their ratio is returned (0 when there are fewer than two steps or the
+// record is not positive).  Both ends by bisection on the Sturm count (the
+// number of negative pivots of T - x I is the number of eigenvalues below x).
+static double lanczos_cond(const double *lz, int k, int *steps) {
+    *steps = 0;
+    if (k < 2) return 0.0;
+    std::vector<double> a(k), b(k, 0.0);  // diagonal, off-diagonal b[j] = T_{j-1,j}
+    for (int j = 0; j < k; ++j) {
+        const double al = lz[2 * j], be = lz[2 * j + 1];
+        if (!(al > 0.0) || !(be >= 0.0) || !std::isfinite(al) || !std::isfinite(be)) return 0.0;
+        a[j] = 1.0 / al + (j > 0 ? be / lz[2 * (j - 1)] : 0.0);
+        if (j > 0) b[j] = std::sqrt(be) / lz[2 * (j - 1)];
+    }
+    double lo = a[0], hi = a[0];  // Gershgorin bounds
+    for (int j = 0; j < k; ++j) {
+        const double r = b[j] + (j + 1 < k ? b[j + 1] : 0.0);
+        lo = std::min(lo, a[j] - r);
+        hi = std::max(hi, a[j] + r);
+    }
+    auto below = [&](double x) {  // eigenvalues of T below x
+        int c = 0;
+        double d = 1.0;
+        for (int j = 0; j < k; ++j) {
+            d = (a[j] - x) - (j > 0 ? b[j] * b[j] / d : 0.0);
+            if (d == 0.0) d = -1e-300;
+            if (d < 0.0) ++c;
+        }
+        return c;
+    };
+    auto bisect = [&](int target) {  // smallest x with at least `target` eigenvalues below it
+        double l = lo, h = hi;
+        for (int it = 0; it < 200 && h - l > 1e-15 * std::max(std::fabs(l), std::fabs(h)); ++it) {
+            const double m = 0.5 * (l + h);
+            if (below(m) >= target)
+                h = m;
+            else
+                l = m;
+        }
+        return 0.5 * (l + h);
+    };
+    const double lmin = bisect(1), lmax = bisect(k);
+    if (!(lmin > 0.0)) return 0.0;
+    *steps = k;
+    return lmax / lmin;
+}
+
 mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *completed) {
     mos_ctx ctx = e->ctx;
     hipStream_t st = ctx->stream;
@@ -3211,6 +3282,8 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
             const ProbState &S = hs[P->pid];
             if (!S.done) continue;
             P->iters += S.it - S.seg_start;
+            if (S.seg_start == 0 && P->cond_steps == 0 && e->lz)
+                P->cond = lanczos_cond(e->lz + (size_t)P->pid * LZ_MAX * 2, std::min(S.it, LZ_MAX), &P->cond_steps);
             if (S.done == 2) P->can_continue = false;  // breakdown: nothing to go on from
             if (S.done == 2 && S.it == S.seg_start) {
                 P->state = 3;
@@ -3418,6 +3491,8 @@ void engine_free(mos_engine e) {
     e->host_scratch = nullptr;
     if (e->jobs_host) (void)hipHostFree(e->jobs_host);
     e->jobs_host = nullptr;
+    if (e->lz) (void)hipHostFree(e->lz);
+    e->lz = nullptr;
     if (e->pp_host) (void)hipHostFree(e->pp_host);
     e->pp_host = nullptr;
     if (e->sp_host) (void)hipHostFree(e->sp_host);

@@ -22,9 +22,9 @@ MOS_OUT_VM, MOS_OUT_SIGMA6 = 1, 2
  MOS_Q_GLOBAL_DOFS, MOS_Q_ITERS, MOS_Q_REFINES, MOS_Q_DEVICE_BYTES) = range(1, 11)
 
 EXPORTED = ("mos_ctx_create", "mos_ctx_destroy", "mos_build_cell", "mos_reduce", "mos_solve_array",
-            "mos_reconstruct", "mos_reconstruct_noalloc", "mos_reconstruct_plane", "mos_reconstruct_displacement", "mos_get_solution", "mos_query", "mos_cell_export", "mos_rom_export",
+            "mos_reconstruct", "mos_reconstruct_noalloc", "mos_reconstruct_plane", "mos_reconstruct_displacement", "mos_get_solution", "mos_get_cond_estimate", "mos_query", "mos_cell_export", "mos_rom_export",
             "mos_array_layout", "mos_engine_create", "mos_engine_submit", "mos_engine_progress",
-            "mos_engine_result", "mos_engine_option", "mos_engine_stats", "mos_engine_graph_stats", "mos_engine_destroy", "mos_timing_start", "mos_timing_stop",
+            "mos_engine_result", "mos_engine_cond_estimate", "mos_engine_option", "mos_engine_stats", "mos_engine_graph_stats", "mos_engine_destroy", "mos_timing_start", "mos_timing_stop",
             "mos_cell_free", "mos_rom_free", "mos_sol_free", "mos_last_error")
 MOS_K_CELL_GEMM, MOS_K_PCG_SCALARS, MOS_K_PCG_UPDATE, MOS_K_RECON = 1, 2, 3, 4
 MOS_OPT_CELL_GEMM = 1
@@ -87,6 +87,8 @@ def _load():
         "mos_reconstruct_plane": (ctypes.c_int, [vp, vp, ctypes.c_int32, vp]),
         "mos_reconstruct_displacement": (ctypes.c_int, [vp, vp, vp]),
         "mos_get_solution": (ctypes.c_int, [vp, vp, P(ctypes.c_double), P(ctypes.c_int32)]),
+        "mos_get_cond_estimate": (ctypes.c_int, [vp, P(ctypes.c_double), P(ctypes.c_int32)]),
+        "mos_engine_cond_estimate": (ctypes.c_int, [vp, ctypes.c_int64, P(ctypes.c_double), P(ctypes.c_int32)]),
         "mos_query": (ctypes.c_int, [vp, ctypes.c_int, P(ctypes.c_int64)]),
         "mos_cell_export": (ctypes.c_int, [vp, vp, vp, vp, vp, vp]),
         "mos_rom_export": (ctypes.c_int, [vp, vp, vp, vp, vp]),
@@ -344,6 +346,14 @@ class Engine:
         self.last_error = lib().mos_last_error().decode(errors="replace") if st.value != MOS_OK else ""
         return st.value, res.value, it.value, sw.value
 
+    def cond_estimate(self, ticket):
+        """(kappa, steps): the Lanczos condition estimate of a completed
+        ticket's first PCG sweep; call it before result()."""
+        k, n = ctypes.c_double(), ctypes.c_int32()
+        _check(lib().mos_engine_cond_estimate(self.ptr, ticket, ctypes.byref(k), ctypes.byref(n)),
+               "mos_engine_cond_estimate")
+        return k.value, n.value
+
     def option(self, option, value):
         _check(lib().mos_engine_option(self.ptr, option, int(value)), "mos_engine_option")
 
@@ -459,6 +469,18 @@ def mos_get_solution(sol):
     it = ctypes.c_int32()
     _check(lib().mos_get_solution(sol.ptr, _ptr(u), ctypes.byref(res), ctypes.byref(it)), "mos_get_solution")
     return u, res.value, it.value
+
+
+def mos_get_cond_estimate(sol):
+    """(kappa, steps): Lanczos estimate of the condition number of the
+    preconditioned reduced system from the first PCG sweep's steps."""
+    k, n = ctypes.c_double(), ctypes.c_int32()
+    _check(lib().mos_get_cond_estimate(sol.ptr, ctypes.byref(k), ctypes.byref(n)), "mos_get_cond_estimate")
+    return k.value, n.value
+
+
+def mos_engine_cond_estimate(engine, ticket):
+    return engine.cond_estimate(ticket)
 
 
 def mos_cell_export(cell):

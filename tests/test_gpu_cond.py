@@ -1,0 +1,121 @@
+"""Condition estimate of the preconditioned reduced system from the PCG's
+own steps (the Lanczos tridiagonal of CG).  With the Jacobi preconditioner
+the oracle gives the value by definition: the extreme Ritz values of
+D^-1/2 A D^-1/2 on the Krylov space of the solve's first k steps, over the
+free DoFs of the reduced system (eq. 20).  CG in floating point loses
+orthogonality once Ritz values converge and then trails exact Lanczos by
+about a step (plain FP64 CG on the CPU does the same), so the estimate must
+lie between the oracle's ratio two steps earlier and at its own step count
+(Ritz extremes spread monotonically with k); on a converged run that
+bracket is ~1e-9 wide.  Those lie inside the operator's
+spectrum, so the estimate may not exceed the full-spectrum ratio either; it
+falls short of it when the load has no weight on an extreme eigenvector.
+The two-level preconditioner is written out densely by the oracle from its
+definition (2 x 2-block aggregates, rigid-body coarse spaces): the same
+Ritz ratio with C = L^T A L, M^-1 = L L^T; its coarse matrices are built
+from FP32 K_r on the GPU, which moves the ratio by < 1e-8 here.  The mixed
+path's first sweep is an FP32 PCG stopped early; rounding can make its Ritz
+values lag exact Lanczos by a few steps, and Ritz extremes spread with k, so
+its estimate must lie between the oracle's a few steps earlier and its own
+step count."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import array as oarray
+from oracle import krylov as okrylov
+from oracle import mor as omor
+
+pytestmark = pytest.mark.gpu
+
+SPEC = W.CellSpec(pitch_x=3.0, pitch_y=3.0, height=6.0, mesh=(4, 4, 6), interp=(3, 3, 4), tsv_diameter=1.6,
+                  liner_thickness=0.3)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2411_12690_amd import mos
+    ctx = mos.Context(0)
+    roms = [mos.mos_reduce(ctx, mos.mos_build_cell(ctx, s)) for s in (SPEC, SPEC.dummy())]
+    return mos, ctx, roms
+
+
+def reduced_system(nx, ny, t):
+    """The oracle's reduced system over its free DoFs (bottom clamp)."""
+    oroms = [omor.local_stage(s) for s in (SPEC, SPEC.dummy())]
+    mesh = oarray.AbstractMesh(nx, ny, SPEC.interp, SPEC.pitch_x, SPEC.pitch_y, SPEC.height)
+    A, b = oarray.assemble_global(mesh, t, oroms, -250.0)
+    dofs, _ = oarray.constrained_dofs(mesh, True, False)
+    free = np.setdiff1d(np.arange(A.shape[0]), dofs)
+    return A[free][:, free].toarray(), np.asarray(b)[free]
+
+
+def bracketed(kappa, ref, k, lag=2, rel=1e-6):
+    """kappa within [ref(k - lag), ref(k)] up to `rel`."""
+    lo, hi = ref(max(k - lag, 1)), ref(k)
+    return lo * (1 - rel) <= kappa <= hi * (1 + rel), lo, hi
+
+
+def jacobi_spectrum_cond(Aff):
+    s = 1.0 / np.sqrt(np.diag(Aff))
+    ev = np.linalg.eigvalsh(s[:, None] * Aff * s[None, :])
+    return ev[-1] / ev[0]
+
+
+@pytest.mark.parametrize("shape", [(3, 2), (5, 4)], ids=["3x2", "5x4"])
+def test_jacobi_estimate_against_oracle_spectrum(env, shape):
+    mos, ctx, roms = env
+    nx, ny = shape
+    t = W.dummy_map(np.random.default_rng(nx * ny), nx * ny, 0.3)
+    Aff, bf = reduced_system(nx, ny, t)
+    kappa_full = jacobi_spectrum_cond(Aff)
+    eng = mos.Engine(ctx, roms, device_bytes=1 << 27, precond=0)
+    tk = eng.submit(nx, ny, t, -250.0)
+    done = []
+    while tk not in done:
+        done += eng.progress(16)
+    kappa, steps = eng.cond_estimate(tk)
+    st, res, it, sw = eng.result(tk)
+    ok, lo, hi = bracketed(kappa, lambda k: okrylov.jacobi_cond(Aff, bf, k), steps)
+    print(f"[cond jacobi {nx}x{ny}] estimate {kappa:.12g} oracle [{lo:.12g}, {hi:.12g}] full spectrum "
+          f"{kappa_full:.6g} steps {steps} iters {it}", flush=True)
+    assert st == mos.MOS_OK and res <= 1e-12
+    assert steps == min(it, 128) and steps >= 2
+    assert ok
+    assert kappa <= kappa_full * (1 + 1e-8)
+    with pytest.raises(mos.MosError) as e:
+        eng.cond_estimate(tk)
+    assert e.value.status == mos.MOS_EBUSY
+    eng.close()
+
+
+@pytest.mark.parametrize("shape", [(5, 3), (6, 4)], ids=["5x3", "6x4"])
+def test_two_level_estimate_against_oracle(env, shape):
+    mos, ctx, roms = env
+    nx, ny = shape
+    t = W.dummy_map(np.random.default_rng(5 + nx), nx * ny, 0.3)
+    sol = mos.mos_solve_array(ctx, roms, nx, ny, t, -250.0, clamp_bottom=True)
+    k2, n2 = mos.mos_get_cond_estimate(sol)
+    _, res, it2 = mos.mos_get_solution(sol)
+    mixed = mos.mos_solve_array(ctx, roms, nx, ny, t, -250.0, clamp_bottom=True, mixed=True)
+    km, nm = mos.mos_get_cond_estimate(mixed)
+    Aff, bf = reduced_system(nx, ny, t)
+    mesh = oarray.AbstractMesh(nx, ny, SPEC.interp, SPEC.pitch_x, SPEC.pitch_y, SPEC.height)
+    free = np.setdiff1d(np.arange(mesh.n_dofs), oarray.constrained_dofs(mesh, True, False)[0])
+    minv = okrylov.two_level_minv(mesh, Aff, free, SPEC.pitch_x)
+    ok2, lo2, hi2 = bracketed(k2, lambda k: okrylov.preconditioned_cond(Aff, minv, bf, k), n2)
+    okm, lom, him = bracketed(km, lambda k: okrylov.preconditioned_cond(Aff, minv, bf, k), nm, lag=5, rel=1e-2)
+    L = np.linalg.cholesky(minv)
+    ev = np.linalg.eigvalsh(L.T @ Aff @ L)
+    kj = jacobi_spectrum_cond(Aff)
+    print(f"[cond two-level {nx}x{ny}] estimate {k2:.12g} oracle [{lo2:.12g}, {hi2:.12g}] ({n2} steps, "
+          f"{it2} iterations); mixed first sweep {km:.8g} oracle [{lom:.8g}, {him:.8g}] ({nm} steps); "
+          f"full spectrum {ev[-1] / ev[0]:.6g}, Jacobi {kj:.6g}", flush=True)
+    assert res <= 1e-12 and n2 == min(it2, 128) and n2 >= 2
+    assert ok2
+    assert k2 <= ev[-1] / ev[0] * (1 + 1e-6) and k2 < kj
+    assert nm >= 2 and 1.0 <= km <= ev[-1] / ev[0] * (1 + 1e-4)
+    assert okm
