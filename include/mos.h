@@ -243,10 +243,12 @@ mos_status mos_get_solution(mos_sol sol, double *u_host, double *rel_residual, i
  * of the reduced system (eq. 20) that the PCG solved, from its own step
  * sizes: the steps alpha_j, beta_j of the first sweep (at most its first
  * 128) define the Lanczos tridiagonal of CG, whose extreme Ritz values lie
- * inside the spectrum of M^-1 A and approach its ends as the sweep
- * converges, so *kappa is their ratio: a lower bound that is close once the
- * sweep has converged; *steps = the steps used.  0 and 0 when the first
- * sweep took fewer than two steps.  The mixed path reports its FP32 inner
+ * inside the spectrum of M^-1 A and approach the ends of the part of it
+ * that the right-hand side excites (a load with no weight on an extreme
+ * eigenvector never reaches that end), so *kappa is their ratio: a lower
+ * bound, close once the sweep has converged on a generic load; *steps =
+ * the steps used.  0 and 0 when the first sweep took fewer than two steps
+ * (a zero load takes none).  The mixed path reports its FP32 inner
  * solve's operator.  MOS_EINVAL for an invalid handle. */
 mos_status mos_get_cond_estimate(mos_sol sol, double *kappa, int32_t *steps);
 

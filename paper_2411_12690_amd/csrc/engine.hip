@@ -3160,7 +3160,8 @@ mos_status collect_retired(mos_engine e, std::vector<int64_t> *completed, bool w
 // Condition estimate of the preconditioned operator from k PCG steps:
 // the Lanczos tridiagonal T of CG, T_jj = 1/alpha_j + beta_j/alpha_{j-1},
 // T_{j-1,j} = sqrt(beta_j)/alpha_{j-1} (beta_0 = 0), has Ritz values inside
-// the spectrum of M^-1 A that approach its ends as the iteration goes on;
+// the spectrum of M^-1 A that approach the ends of the part of it the
+// right-hand side excites as the iteration goes on;
 // their ratio is returned (0 when there are fewer than two steps or the
 // record is not positive).  Both ends by bisection on the Sturm count (the
 // number of negative pivots of T - x I is the number of eigenvalues below x).

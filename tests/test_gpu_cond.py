@@ -119,3 +119,39 @@ def test_two_level_estimate_against_oracle(env, shape):
     assert k2 <= ev[-1] / ev[0] * (1 + 1e-6) and k2 < kj
     assert nm >= 2 and 1.0 <= km <= ev[-1] / ev[0] * (1 + 1e-4)
     assert okm
+
+
+@pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "mixed"])
+def test_batch_estimates_match_solo(env, mixed):
+    """Problems solved together in one engine share every launch, but each
+    keeps its own record: the estimates are those of the same arrays solved
+    alone, bit for bit (results never depend on the batch composition)."""
+    mos, ctx, roms = env
+    shapes = [(3, 2), (5, 4), (4, 3), (2, 2)]
+    maps = [W.dummy_map(np.random.default_rng(40 + i), nx * ny, 0.3) for i, (nx, ny) in enumerate(shapes)]
+    solo = []
+    for (nx, ny), t in zip(shapes, maps):
+        sol = mos.mos_solve_array(ctx, roms, nx, ny, t, -250.0, clamp_bottom=True, mixed=mixed)
+        solo.append(mos.mos_get_cond_estimate(sol))
+    eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=1 << 28)
+    tickets = [eng.submit(nx, ny, t, -250.0) for (nx, ny), t in zip(shapes, maps)]
+    done = []
+    while len(done) < len(tickets):
+        done += eng.progress(16)
+    batch = [eng.cond_estimate(tk) for tk in tickets]
+    for tk in tickets:
+        assert eng.result(tk)[0] == mos.MOS_OK
+    eng.close()
+    print(f"[cond batch {'mixed' if mixed else 'fp64'}] solo {solo} batch {batch}", flush=True)
+    assert batch == solo
+    assert all(k > 1.0 and n >= 2 for k, n in batch)
+
+
+def test_zero_load_gives_no_estimate(env):
+    """No load and clamped faces: the solution is zero without a PCG step,
+    so there is nothing to estimate from."""
+    mos, ctx, roms = env
+    sol = mos.mos_solve_array(ctx, roms, 3, 2, np.zeros(6, dtype=np.uint8), 0.0, clamp_bottom=True)
+    u, res, it = mos.mos_get_solution(sol)
+    assert it == 0 and not np.any(u)
+    assert mos.mos_get_cond_estimate(sol) == (0.0, 0)
