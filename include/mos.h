@@ -248,7 +248,8 @@ mos_status mos_get_solution(mos_sol sol, double *u_host, double *rel_residual, i
  * eigenvector never reaches that end), so *kappa is their ratio: a lower
  * bound, close once the sweep has converged on a generic load; *steps =
  * the steps used.  0 and 0 when the first sweep took fewer than two steps
- * (a zero load takes none).  The mixed path reports its FP32 inner
+ * (a zero load takes none), or when the engine could not allocate its
+ * 2 MiB pinned host record of the steps (the solve itself is unaffected).  The mixed path reports its FP32 inner
  * solve's operator.  MOS_EINVAL for an invalid handle. */
 mos_status mos_get_cond_estimate(mos_sol sol, double *kappa, int32_t *steps);
 
