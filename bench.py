@@ -489,7 +489,8 @@ def c5_mode(args, mos, torch, np, W):
         b64, _ = batch_leg(bargs, mos, torch, np, W, "fp64")
         bmx, _ = batch_leg(bargs, mos, torch, np, W, "mixed")
         out["batch_c2"] = {p: {k: r[k] for k in ("value", "ms_per_step", "p50_ms", "p99_ms", "pcg_iters_mean",
-                                                  "dtype", "roofline")} | {"config": r["config"]["workload"]}
+                                                  "cond_estimate", "dtype", "roofline")}
+                           | {"config": r["config"]["workload"]}
                            for p, r in (("fp64", b64), ("mixed", bmx))}
         print(f"[bench] batch legs {b64['value']} / {bmx['value']} cells/s", file=sys.stderr, flush=True)
         sv = serve_leg(args, mos, torch, np, W, args.rate)
@@ -539,7 +540,7 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False):
     types = [np.full(n_cells, diam.index(c.specs[0].tsv_diameter), dtype=np.uint8) for c in cases]
     host = {"submit_s": 0.0, "progress_calls": 0, "steps": 0}
 
-    def step(record=None):
+    def step(record=None, kappa=None):
         tks = {}
         ts = time.perf_counter()
         for i, c in enumerate(cases):
@@ -553,6 +554,8 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False):
             if record is not None:
                 host["progress_calls"] += 1
             for tk in eng.progress(args.chunk):
+                if kappa is not None:
+                    kappa.append(eng.cond_estimate(tk))
                 st, rel, it, sw = eng.result(tk)
                 if st != 0:
                     raise RuntimeError(f"array {tks[tk]} failed with status {st}: {eng.last_error}")
@@ -635,6 +638,13 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False):
         torch.cuda.synchronize()
         single.append((time.perf_counter() - t1) * 1e3)
 
+    # Condition estimates of the batch's arrays, from one more (untimed) step.
+    kappa = []
+    step(kappa=kappa)
+    kv = np.array([k for k, _ in kappa])
+    cond = {"median": round(float(np.median(kv)), 3), "min": round(float(kv.min()), 3),
+            "max": round(float(kv.max()), 3), "lanczos_steps_median": int(np.median([n for _, n in kappa]))}
+
     cpu, refs, check = None, None, None
     if with_cpu and not args.no_cpu_baseline:
         cpu, refs = cpu_baseline(cases)
@@ -677,6 +687,7 @@ def batch_leg(args, mos, torch, np, W, precision, with_cpu=False):
         "single_array_ms": round(float(np.median(single)), 4) if single else None,
         "pcg_iters_mean": round(float(np.mean(iters)), 1),
         "refinement_sweeps_mean": round(float(np.mean(sweeps)), 2),
+        "cond_estimate": cond,
         "local_stage_ms_per_cell_type": round(local_ms, 2),
         "host": {"submit_ms_per_step": round(host["submit_s"] * 1e3 / max(host["steps"], 1), 3),
                  "progress_calls_per_step": round(host["progress_calls"] / max(host["steps"], 1), 1)},
@@ -705,7 +716,7 @@ def batch_mode(args, mos, torch, np, W):
         "value": mx["value"], "unit": mx["unit"], "ms_per_step": mx["ms_per_step"], "dtype": mx["dtype"],
         "p50_ms": mx["p50_ms"], "p99_ms": mx["p99_ms"], "single_array_ms": mx["single_array_ms"],
         "pcg_iters_mean": mx["pcg_iters_mean"], "refinement_sweeps_mean": mx["refinement_sweeps_mean"],
-        "accuracy_vs_oracle": mx["accuracy_vs_oracle"],
+        "cond_estimate": mx["cond_estimate"], "accuracy_vs_oracle": mx["accuracy_vs_oracle"],
         "peak_hbm_gb": mx["peak_hbm_gb"],
         "roofline": {k: r.get(k) for k in ("kernel", "bound", "achieved", "peak", "unit", "frac", "traffic",
                                            "avg_launch_us", "kernels_ms_per_step")},
