@@ -520,8 +520,7 @@ mos_status mos_solve_array(mos_ctx ctx, const mos_array_desc *d, const mos_rom *
     s->rel_residual = P->rel;
     s->iters = P->iters;
     s->refines = P->sweeps;
-    s->cond = P->cond;
-    s->cond_steps = P->cond_steps;
+    s->lz = std::move(P->lz);
     s->n_types = n_roms;
     s->roms.assign(roms, roms + n_roms);
     s->seg.resize(n_roms + 1);
@@ -651,8 +650,11 @@ mos_status mos_engine_cond_estimate(mos_engine e, int64_t ticket, double *kappa,
         set_error("ticket %lld has not completed (or its result was already taken)", (long long)ticket);
         return MOS_EBUSY;
     }
-    if (kappa) *kappa = it->second->cond;
-    if (steps) *steps = it->second->cond_steps;
+    const std::vector<double> &lz = it->second->lz;
+    int k = 0;
+    const double kap = lanczos_cond(lz.data(), (int)(lz.size() / 2), &k);
+    if (kappa) *kappa = kap;
+    if (steps) *steps = k;
     return MOS_OK;
 }
 
@@ -826,8 +828,10 @@ mos_status mos_get_cond_estimate(mos_sol sol, double *kappa, int32_t *steps) {
         set_error("invalid solution handle");
         return MOS_EINVAL;
     }
-    if (kappa) *kappa = sol->cond;
-    if (steps) *steps = sol->cond_steps;
+    int k = 0;
+    const double kap = lanczos_cond(sol->lz.data(), (int)(sol->lz.size() / 2), &k);
+    if (kappa) *kappa = kap;
+    if (steps) *steps = k;
     return MOS_OK;
 }
 

@@ -255,8 +255,8 @@ struct EngineProblem {
     double dT = 0.0, rtol = 0.0;
     int max_iters = 0, iters = 0, sweeps = 0;
     double rel = 1.0;
-    double cond = 0.0;   // Lanczos estimate of kappa(M^-1 A) from the first sweep (0: none)
-    int cond_steps = 0;  // PCG steps it used
+    std::vector<double> lz;  // (alpha_j, beta_j) of the first sweep's steps (at most LZ_MAX), kept when it ends
+    bool lz_kept = false;
     double last_res2 = -1.0;      // FP64 residual before the last correction
     int sweep_cap = 0;            // inner iterations allowed per sweep
     int undone = 0;               // corrections undone because they raised the residual
@@ -270,6 +270,11 @@ struct EngineProblem {
 };
 
 mos_status engine_alloc(mos_engine e, int64_t cap_dofs, int64_t cap_slots);
+// Condition estimate from k recorded PCG steps (alpha_j, beta_j pairs):
+// the ratio of the extreme eigenvalues of CG's Lanczos tridiagonal, *steps
+// = k; 0 and 0 when k < 2 or the record is not positive.
+double lanczos_cond(const double *lz, int k, int *steps);
+
 // Preconditioner of problems admitted from now on (0 Jacobi, 1 Jacobi plus
 // the aggregate coarse correction) and the internal node order it needs.
 mos_status engine_set_precond(mos_engine e, int precond);

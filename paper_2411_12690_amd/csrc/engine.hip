@@ -3165,7 +3165,7 @@ mos_status collect_retired(mos_engine e, std::vector<int64_t> *completed, bool w
 // their ratio is returned (0 when there are fewer than two steps or the
 // record is not positive).  Both ends by bisection on the Sturm count (the
 // number of negative pivots of T - x I is the number of eigenvalues below x).
-static double lanczos_cond(const double *lz, int k, int *steps) {
+double lanczos_cond(const double *lz, int k, int *steps) {
     *steps = 0;
     if (k < 2) return 0.0;
     std::vector<double> a(k), b(k, 0.0);  // diagonal, off-diagonal b[j] = T_{j-1,j}
@@ -3283,8 +3283,11 @@ mos_status engine_progress(mos_engine e, int chunk, std::vector<int64_t> *comple
             const ProbState &S = hs[P->pid];
             if (!S.done) continue;
             P->iters += S.it - S.seg_start;
-            if (S.seg_start == 0 && P->cond_steps == 0 && e->lz)
-                P->cond = lanczos_cond(e->lz + (size_t)P->pid * LZ_MAX * 2, std::min(S.it, LZ_MAX), &P->cond_steps);
+            if (S.seg_start == 0 && !P->lz_kept && e->lz) {  // the estimate itself is formed on request
+                const double *row = e->lz + (size_t)P->pid * LZ_MAX * 2;
+                P->lz.assign(row, row + 2 * std::min(S.it, LZ_MAX));
+                P->lz_kept = true;
+            }
             if (S.done == 2) P->can_continue = false;  // breakdown: nothing to go on from
             if (S.done == 2 && S.it == S.seg_start) {
                 P->state = 3;

@@ -171,8 +171,7 @@ struct mos_sol_s {
     double delta_T = 0.0;
     double rel_residual = 0.0;
     int iters = 0, refines = 0;
-    double cond = 0.0;                       // Lanczos estimate of kappa(M^-1 A), first sweep (0: none)
-    int cond_steps = 0;
+    std::vector<double> lz;                  // (alpha_j, beta_j) of the first sweep's PCG steps
     int n_types = 0;
     int n_pc = 0;                            // padded permuted cell slots
     std::vector<int> seg;                    // [n_types+1] slot ranges per type (multiples of 16)
