@@ -121,11 +121,13 @@ def test_two_level_estimate_against_oracle(env, shape):
     assert okm
 
 
-@pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "mixed"])
-def test_batch_estimates_match_solo(env, mixed):
+@pytest.mark.parametrize("mixed,graph", [(False, 0), (True, 0), (False, 1), (True, 1)],
+                         ids=["fp64", "mixed", "fp64-graph", "mixed-graph"])
+def test_batch_estimates_match_solo(env, mixed, graph):
     """Problems solved together in one engine share every launch, but each
     keeps its own record: the estimates are those of the same arrays solved
-    alone, bit for bit (results never depend on the batch composition)."""
+    alone, bit for bit (results never depend on the batch composition),
+    also when the iteration chunks are replayed from captured graphs."""
     mos, ctx, roms = env
     shapes = [(3, 2), (5, 4), (4, 3), (2, 2)]
     maps = [W.dummy_map(np.random.default_rng(40 + i), nx * ny, 0.3) for i, (nx, ny) in enumerate(shapes)]
@@ -133,16 +135,18 @@ def test_batch_estimates_match_solo(env, mixed):
     for (nx, ny), t in zip(shapes, maps):
         sol = mos.mos_solve_array(ctx, roms, nx, ny, t, -250.0, clamp_bottom=True, mixed=mixed)
         solo.append(mos.mos_get_cond_estimate(sol))
-    eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=1 << 28)
+    eng = mos.Engine(ctx, roms, mixed=mixed, device_bytes=1 << 28, graph=graph)
     tickets = [eng.submit(nx, ny, t, -250.0) for (nx, ny), t in zip(shapes, maps)]
     done = []
     while len(done) < len(tickets):
         done += eng.progress(16)
     batch = [eng.cond_estimate(tk) for tk in tickets]
+    if graph:
+        assert eng.graph_stats()[1] >= 1, "no chunk was replayed from a graph"
     for tk in tickets:
         assert eng.result(tk)[0] == mos.MOS_OK
     eng.close()
-    print(f"[cond batch {'mixed' if mixed else 'fp64'}] solo {solo} batch {batch}", flush=True)
+    print(f"[cond batch {'mixed' if mixed else 'fp64'} graph {graph}] solo {solo} batch {batch}", flush=True)
     assert batch == solo
     assert all(k > 1.0 and n >= 2 for k, n in batch)
 
