@@ -17,7 +17,7 @@ Steps, in the paper's order:
 5. Per block, the displacement dT f_T + sum_i u_i f_i (eq. 15) and from it the
    strain and stress (eq. 1).
 
-Readings (listed in the design doc): the abstract-mesh node at lattice point
+Readings of the paper: the abstract-mesh node at lattice point
 (I, J, K) has id equal to its rank in (K, J, I) lexicographic order with I
 fastest; block (cx, cy) has id cy N_x + cx and its surface node (i, j, k) sits
 at (cx (n_x-1) + i, cy (n_y-1) + j, k); lifting is the symmetric form (rows

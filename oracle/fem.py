@@ -20,7 +20,7 @@ What is computed, with the passage it follows:
   underfill) is the second structure built here, read as stated in
   ``Cell.material_map``.
 
-Readings where the paper is silent (each listed in the design doc): the element is
+Readings where the paper is silent: the element is
 the trilinear 8-node hexahedron with 2x2x2 Gauss quadrature; the mesh is a
 structured m_x x m_y x m_z grid; an element belongs to the via if its
 centroid lies strictly inside radius d/2 of the via axis, to the liner if

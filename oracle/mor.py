@@ -20,7 +20,7 @@ Steps, in the paper's order and notation:
    (eq. 19, per unit dT), with Phi = [f_0 ... f_{n-1}] and the un-lifted
    A_local.
 
-Readings (listed in the design doc): node coordinates x_i = p i / (n_x - 1); the
+Readings of the paper: node coordinates x_i = p i / (n_x - 1); the
 surface node set is ordered lexicographically in (k, j, i) with i fastest and
 the reduced DoF is 3 s + component, which fixes eq. 14's vector order beyond
 its first and last entries; eq. 14's "b_{local,}f" is b_{local,f}; eq. 18-19's
