@@ -14,6 +14,10 @@
 //       calls every C entry point with NULL or invalid arguments that are
 //       rejected before any device work and prints "abi ok" when each
 //       returns the documented status; also checks the engine's slot limit.
+//   mesh_check lanczos
+//       reads k and then k pairs (alpha_j, beta_j) of recorded PCG steps from
+//       stdin and prints the library's condition estimate from them as
+//       "kappa steps" (host code of the engine, no device work).
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -23,6 +27,22 @@
 #include "mos.h"
 
 using namespace mos;
+
+namespace mos {
+double lanczos_cond(const double *lz, int k, int *steps);  // the engine's host code (engine.hip)
+}
+
+static int run_lanczos() {
+    int k = 0;
+    if (std::scanf("%d", &k) != 1 || k < 0 || k > 100000) return 2;
+    std::vector<double> lz(2 * (size_t)k + 2, 0.0);
+    for (int i = 0; i < 2 * k; ++i)
+        if (std::scanf("%lf", &lz[i]) != 1) return 2;
+    int steps = -1;
+    const double kappa = lanczos_cond(lz.data(), k, &steps);
+    std::printf("%.17g %d\n", kappa, steps);
+    return 0;
+}
 
 static int fail(const char *what) {
     std::printf("FAIL %s\n", what);
@@ -124,6 +144,7 @@ int main(int argc, char **argv) {
         return run_mesh(a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7]);
     }
     if (argc == 2 && std::strcmp(argv[1], "abi") == 0) return run_abi();
-    std::fprintf(stderr, "usage: mesh_check mesh Nx Ny Nz nx ny nz cx cy | mesh_check abi\n");
+    if (argc == 2 && std::strcmp(argv[1], "lanczos") == 0) return run_lanczos();
+    std::fprintf(stderr, "usage: mesh_check mesh Nx Ny Nz nx ny nz cx cy | mesh_check abi | mesh_check lanczos\n");
     return 2;
 }
