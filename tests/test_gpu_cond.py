@@ -121,6 +121,46 @@ def test_two_level_estimate_against_oracle(env, shape):
     assert okm
 
 
+@pytest.mark.parametrize("table", [1, 0], ids=["table", "general"])
+def test_two_level_estimate_with_prescribed_faces(env, table):
+    """All six outer faces carry prescribed displacements (a sub-model's
+    boundary, as in the 200x200 workload): the aggregates touching the
+    lateral faces take their coarse matrices from the general per-aggregate
+    kernel, the inner ones from the per-type table (or the general kernel
+    too with the table switched off).  Either way the estimate is the
+    oracle's for the two-level M over the interior DoFs, with the lifted
+    right-hand side."""
+    mos, ctx, roms = env
+    nx, ny = 7, 6                      # 4 x 3 aggregates: two inner, a one-block last column
+    t = W.dummy_map(np.random.default_rng(17), nx * ny, 0.3)
+    mesh = oarray.AbstractMesh(nx, ny, SPEC.interp, SPEC.pitch_x, SPEC.pitch_y, SPEC.height)
+    outer = np.nonzero(mesh.outer_node_mask())[0]
+    pd = (3 * outer[:, None] + np.arange(3)).ravel().astype(np.int64)
+    pv = np.random.default_rng(18).uniform(-0.01, 0.01, pd.size)
+    eng = mos.Engine(ctx, roms, device_bytes=1 << 27)
+    eng.option(mos.MOS_OPT_COARSE_TABLE, table)
+    tk = eng.submit(nx, ny, t, -250.0, clamp_bottom=False, prescribed_dofs=pd, prescribed_values=pv)
+    done = []
+    while tk not in done:
+        done += eng.progress(16)
+    k2, n2 = eng.cond_estimate(tk)
+    st, res, it, sw = eng.result(tk)
+    eng.close()
+    oroms = [omor.local_stage(s) for s in (SPEC, SPEC.dummy())]
+    A, b = oarray.assemble_global(mesh, t, oroms, -250.0)
+    free = np.setdiff1d(np.arange(mesh.n_dofs), pd)
+    g = np.zeros(mesh.n_dofs)
+    g[pd] = pv
+    bf = np.asarray(b - A @ g)[free]
+    Aff = A[free][:, free].toarray()
+    minv = okrylov.two_level_minv(mesh, Aff, free, SPEC.pitch_x)
+    ok, lo, hi = bracketed(k2, lambda k: okrylov.preconditioned_cond(Aff, minv, bf, k), n2)
+    print(f"[cond prescribed faces, table {table}] estimate {k2:.12g} oracle [{lo:.12g}, {hi:.12g}] "
+          f"({n2} steps, {it} iterations)", flush=True)
+    assert st == mos.MOS_OK and res <= 1e-12 and n2 == min(it, 128) and n2 >= 2
+    assert ok
+
+
 @pytest.mark.parametrize("mixed,graph", [(False, 0), (True, 0), (False, 1), (True, 1)],
                          ids=["fp64", "mixed", "fp64-graph", "mixed-graph"])
 def test_batch_estimates_match_solo(env, mixed, graph):
