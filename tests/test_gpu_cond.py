@@ -161,6 +161,30 @@ def test_two_level_estimate_with_prescribed_faces(env, table):
     assert ok
 
 
+@pytest.mark.parametrize("shape,top", [((3, 2, 2), True), ((2, 2, 2), False), ((2, 3, 3), True)],
+                         ids=["3x2x2-top", "2x2x2", "2x3x3-top"])
+def test_stacked_jacobi_estimate_against_oracle(env, shape, top):
+    """Stacked layers of blocks take the Jacobi preconditioner: the estimate
+    is the oracle's Ritz ratio of D^-1/2 A D^-1/2 of the stack (layers
+    sharing their horizontal faces)."""
+    mos, ctx, roms = env
+    nx, ny, nz = shape
+    t = W.dummy_map(np.random.default_rng(sum(shape)), nx * ny * nz, 0.3)
+    sol = mos.mos_solve_array(ctx, roms, nx, ny, t, -250.0, clamp_bottom=True, clamp_top=top, nz_cells=nz)
+    kappa, steps = mos.mos_get_cond_estimate(sol)
+    _, res, it = mos.mos_get_solution(sol)
+    oroms = [omor.local_stage(s) for s in (SPEC, SPEC.dummy())]
+    mesh = oarray.AbstractMesh(nx, ny, SPEC.interp, SPEC.pitch_x, SPEC.pitch_y, SPEC.height, nz_cells=nz)
+    A, b = oarray.assemble_global(mesh, t, oroms, -250.0)
+    free = np.setdiff1d(np.arange(A.shape[0]), oarray.constrained_dofs(mesh, True, top)[0])
+    Aff, bf = A[free][:, free].toarray(), np.asarray(b)[free]
+    ok, lo, hi = bracketed(kappa, lambda k: okrylov.jacobi_cond(Aff, bf, k), steps)
+    print(f"[cond stacked {'x'.join(map(str, shape))}] estimate {kappa:.12g} oracle [{lo:.12g}, {hi:.12g}] "
+          f"({steps} steps, {it} iterations)", flush=True)
+    assert res <= 1e-12 and steps == min(it, 128) and steps >= 2
+    assert ok
+
+
 @pytest.mark.parametrize("mixed,graph", [(False, 0), (True, 0), (False, 1), (True, 1)],
                          ids=["fp64", "mixed", "fp64-graph", "mixed-graph"])
 def test_batch_estimates_match_solo(env, mixed, graph):
