@@ -18,6 +18,8 @@ path's first sweep is an FP32 PCG stopped early; rounding can make its Ritz
 values lag exact Lanczos by a few steps, and Ritz extremes spread with k, so
 its estimate must lie between the oracle's a few steps earlier and its own
 step count."""
+import math
+
 import numpy as np
 import pytest
 
@@ -182,6 +184,38 @@ def test_stacked_jacobi_estimate_against_oracle(env, shape, top):
     print(f"[cond stacked {'x'.join(map(str, shape))}] estimate {kappa:.12g} oracle [{lo:.12g}, {hi:.12g}] "
           f"({steps} steps, {it} iterations)", flush=True)
     assert res <= 1e-12 and steps == min(it, 128) and steps >= 2
+    assert ok
+
+
+SKEW = W.CellSpec(pitch_x=3.0, pitch_y=3.0 * math.sqrt(3.0) / 2.0, height=6.0, mesh=(4, 4, 6), interp=(3, 3, 4),
+                  tsv_diameter=1.6, liner_thickness=0.3, skew=1.0 / math.sqrt(3.0))
+
+
+def test_two_level_estimate_on_skewed_blocks(env):
+    """A 120-degree array of rhombic blocks: the coarse space's rotations use
+    the nodes' physical (sheared) coordinates, so it holds the rigid motions
+    of the skewed aggregates.  (Unsheared coordinates would give a different
+    M: 57.45 here instead of 54.18.)"""
+    mos, ctx, _ = env
+    specs = (SKEW, SKEW.dummy())
+    roms = [mos.mos_reduce(ctx, mos.mos_build_cell(ctx, x)) for x in specs]
+    nx, ny = 5, 4
+    t = W.dummy_map(np.random.default_rng(23), nx * ny, 0.3)
+    sol = mos.mos_solve_array(ctx, roms, nx, ny, t, -250.0, clamp_bottom=True)
+    k2, n2 = mos.mos_get_cond_estimate(sol)
+    _, res, it = mos.mos_get_solution(sol)
+    oroms = [omor.local_stage(x) for x in specs]
+    meshes = [oarray.AbstractMesh(nx, ny, SKEW.interp, SKEW.pitch_x, SKEW.pitch_y, SKEW.height, skew=sk)
+              for sk in (SKEW.skew, 0.0)]
+    A, b = oarray.assemble_global(meshes[0], t, oroms, -250.0)
+    free = np.setdiff1d(np.arange(A.shape[0]), oarray.constrained_dofs(meshes[0], True, False)[0])
+    Aff, bf = A[free][:, free].toarray(), np.asarray(b)[free]
+    refs = [okrylov.two_level_minv(m, Aff, free, SKEW.pitch_x) for m in meshes]
+    ok, lo, hi = bracketed(k2, lambda k: okrylov.preconditioned_cond(Aff, refs[0], bf, k), n2)
+    unsheared = okrylov.preconditioned_cond(Aff, refs[1], bf, n2)
+    print(f"[cond skewed 5x4] estimate {k2:.12g} oracle [{lo:.12g}, {hi:.12g}] ({n2} steps, {it} iterations); "
+          f"with unsheared rotations {unsheared:.8g}", flush=True)
+    assert res <= 1e-12 and n2 == min(it, 128) and n2 >= 2
     assert ok
 
 
