@@ -219,6 +219,34 @@ def test_two_level_estimate_on_skewed_blocks(env):
     assert ok
 
 
+BUMP = W.bump_spec(pitch_x=8.0, pitch_y=8.0, height=6.0, mesh=(6, 6, 6), tsv_diameter=5.0, pad_thickness=1.2,
+                   interp=(3, 3, 4))
+
+
+def test_two_level_estimate_on_bump_blocks(env):
+    """A layer of micro-bump blocks and empty sites clamped at both faces:
+    the two-level estimate equals the oracle's for the same M."""
+    mos, ctx, _ = env
+    specs = (BUMP, BUMP.dummy())
+    roms = [mos.mos_reduce(ctx, mos.mos_build_cell(ctx, x)) for x in specs]
+    nx, ny = 5, 3
+    t = W.dummy_map(np.random.default_rng(29), nx * ny, 0.2)
+    sol = mos.mos_solve_array(ctx, roms, nx, ny, t, -250.0, clamp_bottom=True, clamp_top=True)
+    k2, n2 = mos.mos_get_cond_estimate(sol)
+    _, res, it = mos.mos_get_solution(sol)
+    oroms = [omor.local_stage(x) for x in specs]
+    mesh = oarray.AbstractMesh(nx, ny, BUMP.interp, BUMP.pitch_x, BUMP.pitch_y, BUMP.height)
+    A, b = oarray.assemble_global(mesh, t, oroms, -250.0)
+    free = np.setdiff1d(np.arange(A.shape[0]), oarray.constrained_dofs(mesh, True, True)[0])
+    Aff, bf = A[free][:, free].toarray(), np.asarray(b)[free]
+    minv = okrylov.two_level_minv(mesh, Aff, free, BUMP.pitch_x)
+    ok, lo, hi = bracketed(k2, lambda k: okrylov.preconditioned_cond(Aff, minv, bf, k), n2)
+    print(f"[cond bump 5x3] estimate {k2:.12g} oracle [{lo:.12g}, {hi:.12g}] ({n2} steps, {it} iterations)",
+          flush=True)
+    assert res <= 1e-12 and n2 == min(it, 128) and n2 >= 2
+    assert ok
+
+
 @pytest.mark.parametrize("mixed,graph", [(False, 0), (True, 0), (False, 1), (True, 1)],
                          ids=["fp64", "mixed", "fp64-graph", "mixed-graph"])
 def test_batch_estimates_match_solo(env, mixed, graph):
